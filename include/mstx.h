@@ -1,0 +1,131 @@
+/*
+ * mstx.h -- C ABI of the MI355X (gfx950) parallel Boruvka minimum spanning tree.
+ *
+ * Problem (Durbhakula, arXiv 2005.06913, Section 2.1): given an undirected
+ * graph as an edge list (src[e], dst[e], w[e]), src and dst interchangeable,
+ * find the minimum spanning tree M.  The paper assumes a connected graph with
+ * distinct weights.  This library accepts any edge list:
+ *   - equal weights are ordered by edge index: edge e precedes edge f iff
+ *     (w[e], e) < (w[f], f), so the selected tree is unique;
+ *   - self-loops and parallel edges are allowed (a self-loop is never taken);
+ *   - a disconnected graph yields the minimum spanning forest and status
+ *     MSTX_DISCONNECTED.
+ *
+ * Method (Sections 2.1 and 2.2.2): Boruvka rounds.  Each round every component
+ * selects its lightest outgoing edge (64-bit atomic minimum on the packed key
+ * (w << 32) | e), components are united along the selected edges by
+ * compare-and-swap hooking of the larger root under the smaller one, parent
+ * pointers are compressed, components are renumbered densely, and edges that
+ * became internal are dropped (the paper's "covered" edges).  Rounds repeat
+ * until no component has an outgoing edge.
+ *
+ * Conventions for every entry point below:
+ *   - Array arguments are DEVICE pointers (hipMalloc / torch CUDA memory on
+ *     the current HIP device) owned by the caller.  Inputs are never modified.
+ *     The library keeps no caller pointer after a call returns.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     All device work is ordered on it.  Calls are blocking: they synchronise
+ *     `stream` before returning, because some errors are only known on the
+ *     device.
+ *   - Vertex ids are int32 in [0, n); edge counts are int64 with
+ *     m <= 0xFFFFFFFF (the edge index must fit the key's low 32 bits).
+ *   - A negative status means the outputs are unspecified.
+ *   - Scratch memory (the workspace) is owned by the library, cached per
+ *     device and reused across calls; calls on one device are serialised by
+ *     a mutex.  MSTX_WORKSPACE_LIMIT_BYTES (environment, bytes) caps it.
+ */
+#ifndef MSTX_H
+#define MSTX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes.  >= 0: outputs valid. */
+#define MSTX_OK 0                  /* spanning tree found (or n <= 1)                 */
+#define MSTX_DISCONNECTED 1        /* graph disconnected: outputs hold the forest     */
+#define MSTX_ERR_INVALID_ARG (-1)  /* n < 0, m < 0, or NULL array with m > 0          */
+#define MSTX_ERR_VERTEX_RANGE (-2) /* some src/dst id outside [0, n)                  */
+#define MSTX_ERR_TOO_LARGE (-3)    /* m > 0xFFFFFFFF                                  */
+#define MSTX_ERR_OUT_OF_MEMORY (-4)/* workspace allocation failed or over the limit   */
+#define MSTX_ERR_DEVICE (-5)       /* a HIP call failed, or a round-count watchdog    */
+
+/*
+ * Minimum spanning tree of one graph (Section 2.1; parallel form after
+ * Section 2.2.2).
+ *   n                 number of vertices (>= 0)
+ *   m                 number of edges (>= 0)
+ *   src, dst          int32[m] edge end points, ids in [0, n)
+ *   w                 uint32[m] edge weights
+ *   out_in_mst        uint8[m], overwritten: 1 iff edge e is in the tree/forest
+ *   out_total_weight  uint64[1], overwritten: sum of w over the marked edges
+ * Returns MSTX_OK, MSTX_DISCONNECTED or a negative error.
+ * Argument checks (INVALID_ARG, TOO_LARGE) happen on the host before any HIP
+ * call.  VERTEX_RANGE is detected during the first edge scan.
+ */
+int mst_solve(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, const uint32_t* w,
+              uint8_t* out_in_mst, uint64_t* out_total_weight, void* stream);
+
+/*
+ * The first Boruvka step alone (Section 2.1, the edge loop): for every vertex
+ * v, out_best[v] = min over non-loop edges e incident to v of the key
+ * ((uint64)w[e] << 32) | e, or 0xFFFFFFFFFFFFFFFF when v has no such edge.
+ *   out_best  uint64[n], overwritten.
+ * Returns MSTX_OK or a negative error (VERTEX_RANGE as for mst_solve).
+ */
+int mst_select_min_edges(int32_t n, int64_t m, const int32_t* src, const int32_t* dst,
+                         const uint32_t* w, uint64_t* out_best, void* stream);
+
+/*
+ * Per-round statistics of the most recent mst_solve call made by the calling
+ * thread.  For round r (0-based), out[3r+0] = components with at least one
+ * outgoing edge candidate at the start of the round (all components in round
+ * 0), out[3r+1] = live edges (ends in different components at the start of
+ * the round), out[3r+2] = edges added to the tree in the round.
+ *   out        host int64[3 * max_rounds]
+ * Returns the number of rounds recorded (<= max_rounds), or
+ * MSTX_ERR_INVALID_ARG if out is NULL with max_rounds > 0.
+ */
+int mst_last_round_stats(int64_t* out, int32_t max_rounds);
+
+/*
+ * Bytes of device workspace a call of mst_solve with (n, m) uses: an upper
+ * bound, for admission control by memory budget.  Pure arithmetic, no HIP call.
+ * Returns 0 for invalid (n, m).
+ */
+size_t mst_workspace_bytes(int32_t n, int64_t m);
+
+/*
+ * Per-kernel timing (profiling aid, off by default).  While enabled, each
+ * kernel launch of mst_solve is bracketed by HIP events on the solve's
+ * stream; after each solve the elapsed times, launch counts and the
+ * algorithmic bytes of each kernel kind are accumulated.  Kernel kinds:
+ * 0 scan_first (round 0 edge scan over the caller's arrays), 1 scan_input
+ * (round 1 scan + compaction from the caller's arrays), 2 scan_records
+ * (rounds >= 2 scan + in-place compaction), 3 hook, 4 compress, 5 finalize,
+ * 6 relabel.  Algorithmic bytes are counted only for the scan kinds: the edge
+ * stream read once (12 B per input edge, 16 B per record), the previous
+ * round's label map read once (4 B per entry), the minima initialised and
+ * written once (16 B per component) and the survivors written once (16 B).
+ *   mst_profile_enable: enable != 0 starts (and zeroes) the counters, 0 stops;
+ *                       returns the previous state.
+ *   mst_profile_read:   copies min(kinds, 7) entries to host arrays; returns
+ *                       the number of kinds (7) or MSTX_ERR_INVALID_ARG.
+ *   mst_profile_kernel_name: name of a kind ("" if out of range).
+ * Intended for benchmarking; the events add a little time per launch.
+ */
+int mst_profile_enable(int enable);
+int mst_profile_read(double* out_ms, int64_t* out_launches, double* out_bytes, int32_t kinds);
+const char* mst_profile_kernel_name(int kind);
+
+/* Static description of a status code. */
+const char* mst_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MSTX_H */

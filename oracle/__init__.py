@@ -12,7 +12,9 @@ Routines (arXiv 2005.06913):
                      sequential MST algorithms);
   * ``boruvka``   -- the sequential Boruvka algorithm of Section 2.1 with the
                      "covered" optimisation, with per-round statistics;
-  * ``check_mst`` -- certificate: forest, spanning, cycle property, total.
+  * ``check_mst`` -- certificate: forest, spanning, cycle property, total;
+  * ``min_edge_keys`` -- the first round's edge loop alone: the lightest
+                     edge key at every vertex.
 
 Edges are ordered by ``(w[e], e)``; with the paper's distinct weights this is
 the order by weight.  Pins (what the oracle is checked against) are in
@@ -73,6 +75,8 @@ def _bind(path: str):
     lib.oracle_boruvka.restype = ctypes.c_int
     lib.oracle_check_mst.argtypes = [i32, i64, p, p, p, p, ctypes.c_uint64]
     lib.oracle_check_mst.restype = ctypes.c_int
+    lib.oracle_min_edge_keys.argtypes = [i32, i64, p, p, p, p]
+    lib.oracle_min_edge_keys.restype = ctypes.c_int
     lib.oracle_count_components.argtypes = [i32, i64, p, p]
     lib.oracle_count_components.restype = ctypes.c_int64
     return lib
@@ -144,6 +148,13 @@ class Oracle:
         return int(self.lib.oracle_check_mst(n, src.shape[0], _ptr(src), _ptr(dst), _ptr(w),
                                             _ptr(in_mst), int(total)))
 
+    def min_edge_keys(self, n: int, src, dst, w):
+        """(status, uint64[n]): lightest key (w << 32 | e) of the non-loop edges at each vertex."""
+        src, dst, w = _prep(src, dst, w)
+        keys = np.zeros(max(n, 1), np.uint64)
+        st = self.lib.oracle_min_edge_keys(n, src.shape[0], _ptr(src), _ptr(dst), _ptr(w), _ptr(keys))
+        return int(st), keys[:max(n, 0)]
+
     def count_components(self, n: int, src, dst) -> int:
         src = np.ascontiguousarray(src, dtype=np.int32)
         dst = np.ascontiguousarray(dst, dtype=np.int32)
@@ -170,6 +181,10 @@ def boruvka(n: int, src, dst, w, max_rounds: int = 64, labels: bool = False) -> 
 
 def check_mst(n: int, src, dst, w, in_mst, total: int) -> int:
     return default().check_mst(n, src, dst, w, in_mst, total)
+
+
+def min_edge_keys(n: int, src, dst, w):
+    return default().min_edge_keys(n, src, dst, w)
 
 
 def count_components(n: int, src, dst) -> int:

@@ -23,7 +23,7 @@
  *
  *   Output: in_mst[e] in {0,1} in input order and the exact uint64 total.
  *
- * Three independent routines:
+ * Independent routines:
  *   oracle_kruskal   -- Kruskal's algorithm (named in Section 1): edges in
  *                       increasing order, keep an edge iff it joins two
  *                       different trees of the forest built so far.
@@ -32,6 +32,8 @@
  *                       paper's step order, plus per-round statistics.
  *   oracle_check_mst -- a certificate checker: spanning-forest structure, the
  *                       cycle property under the total order, and the total.
+ *   oracle_min_edge_keys -- the first round's edge loop alone: the lightest
+ *                       edge at every vertex.
  *
  * Plain and slow on purpose: qsort, a union-find with union by size and
  * path halving, arrays indexed directly.
@@ -480,4 +482,24 @@ int64_t oracle_count_components(int32_t n, int64_t m, const int32_t* src, const 
     }
     uf_free(&u);
     return c;
+}
+
+/*
+ * The first Boruvka step on its own (Section 2.1, the edge loop with every
+ * vertex its own component): keys[v] = smallest (w[e] << 32) | e over the
+ * non-loop edges e incident to v, or UINT64_MAX when there is none.
+ */
+int oracle_min_edge_keys(int32_t n, int64_t m, const int32_t* src, const int32_t* dst,
+                         const uint32_t* w, uint64_t* keys) {
+    int rc = check_args(n, m, src, dst, w);
+    if (rc != ORACLE_OK) return rc;
+    if (n > 0 && !keys) return ORACLE_ERR_ARG;
+    for (int32_t v = 0; v < n; ++v) keys[v] = UINT64_MAX;
+    for (int64_t e = 0; e < m; ++e) {
+        if (src[e] == dst[e]) continue;
+        uint64_t k = order_key(w, e);
+        if (k < keys[src[e]]) keys[src[e]] = k;
+        if (k < keys[dst[e]]) keys[dst[e]] = k;
+    }
+    return ORACLE_OK;
 }

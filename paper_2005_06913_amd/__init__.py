@@ -1,0 +1,31 @@
+"""MI355X (gfx950) parallel Boruvka minimum spanning tree.
+
+The product is the HIP library ``libmstx.so`` behind the C ABI of
+``include/mstx.h``; this package holds its sources (``csrc/``), its build
+script and a thin ctypes binding with the same function names.  PyTorch is
+used only for device memory and streams.
+
+``graphgen`` holds the seeded synthetic input generators.
+"""
+
+from .binding import (  # noqa: F401
+    EXPORTS,
+    MSTX_DISCONNECTED,
+    MSTX_ERR_DEVICE,
+    MSTX_ERR_INVALID_ARG,
+    MSTX_ERR_OUT_OF_MEMORY,
+    MSTX_ERR_TOO_LARGE,
+    MSTX_ERR_VERTEX_RANGE,
+    MSTX_OK,
+    MstxError,
+    Solution,
+    load_library,
+    mst_last_round_stats,
+    mst_profile_enable,
+    mst_profile_read,
+    mst_select_min_edges,
+    mst_solve,
+    mst_status_string,
+    mst_workspace_bytes,
+    solve,
+)

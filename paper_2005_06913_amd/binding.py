@@ -1,0 +1,163 @@
+"""ctypes binding of the mstx C ABI (``include/mstx.h``).
+
+The functions keep the C names and only marshal arguments: torch tensors on
+the current HIP device become device pointers, the current torch stream
+becomes the ``stream`` argument.  Every step of the solve runs in the HIP
+kernels of ``libmstx.so``; if that library is missing or cannot be loaded the
+call raises -- there is no fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import NamedTuple
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libmstx.so")
+
+MSTX_OK = 0
+MSTX_DISCONNECTED = 1
+MSTX_ERR_INVALID_ARG = -1
+MSTX_ERR_VERTEX_RANGE = -2
+MSTX_ERR_TOO_LARGE = -3
+MSTX_ERR_OUT_OF_MEMORY = -4
+MSTX_ERR_DEVICE = -5
+
+EXPORTS = ("mst_solve", "mst_select_min_edges", "mst_last_round_stats", "mst_workspace_bytes",
+           "mst_status_string", "mst_profile_enable", "mst_profile_read", "mst_profile_kernel_name")
+
+_lib = None
+
+
+class MstxError(RuntimeError):
+    def __init__(self, status: int):
+        super().__init__(f"mstx status {status}: {mst_status_string(status)}")
+        self.status = status
+
+
+def load_library(path: str = LIB_PATH):
+    """Load ``libmstx.so`` (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2005_06913_amd.build` "
+                           "or __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
+    i32, i64, p = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
+    lib.mst_solve.argtypes = [i32, i64, p, p, p, p, p, p]
+    lib.mst_solve.restype = ctypes.c_int
+    lib.mst_select_min_edges.argtypes = [i32, i64, p, p, p, p, p]
+    lib.mst_select_min_edges.restype = ctypes.c_int
+    lib.mst_last_round_stats.argtypes = [p, i32]
+    lib.mst_last_round_stats.restype = ctypes.c_int
+    lib.mst_workspace_bytes.argtypes = [i32, i64]
+    lib.mst_workspace_bytes.restype = ctypes.c_size_t
+    lib.mst_status_string.argtypes = [ctypes.c_int]
+    lib.mst_status_string.restype = ctypes.c_char_p
+    lib.mst_profile_enable.argtypes = [ctypes.c_int]
+    lib.mst_profile_enable.restype = ctypes.c_int
+    lib.mst_profile_read.argtypes = [p, p, p, i32]
+    lib.mst_profile_read.restype = ctypes.c_int
+    lib.mst_profile_kernel_name.argtypes = [ctypes.c_int]
+    lib.mst_profile_kernel_name.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev_ptr(t, dtype, name, numel=None):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be on the GPU")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr() if t.numel() else 0)
+
+
+def mst_status_string(status: int) -> str:
+    return load_library().mst_status_string(int(status)).decode()
+
+
+def mst_workspace_bytes(n: int, m: int) -> int:
+    return int(load_library().mst_workspace_bytes(int(n), int(m)))
+
+
+def mst_solve(n, src, dst, w, out_in_mst, out_total_weight, stream=None) -> int:
+    """C ``mst_solve`` on torch tensors: int32 src/dst, uint32 w, uint8 out_in_mst[m],
+    uint64 out_total_weight[1] (all on the current GPU).  Returns the status."""
+    import torch
+    m = int(src.numel())
+    args = (_dev_ptr(src, torch.int32, "src", m), _dev_ptr(dst, torch.int32, "dst", m),
+            _dev_ptr(w, torch.uint32, "w", m), _dev_ptr(out_in_mst, torch.uint8, "out_in_mst", m),
+            _dev_ptr(out_total_weight, torch.uint64, "out_total_weight", 1))
+    return int(load_library().mst_solve(int(n), m, *args, _stream_handle(stream)))
+
+
+def mst_select_min_edges(n, src, dst, w, out_best, stream=None) -> int:
+    """C ``mst_select_min_edges``: out_best uint64[n] <- lightest key per vertex."""
+    import torch
+    m = int(src.numel())
+    args = (_dev_ptr(src, torch.int32, "src", m), _dev_ptr(dst, torch.int32, "dst", m),
+            _dev_ptr(w, torch.uint32, "w", m), _dev_ptr(out_best, torch.uint64, "out_best", int(n)))
+    return int(load_library().mst_select_min_edges(int(n), m, *args, _stream_handle(stream)))
+
+
+def mst_last_round_stats(max_rounds: int = 40):
+    """Per-round (components, live edges, edges added) of this thread's last mst_solve."""
+    import numpy as np
+    buf = np.zeros(3 * max_rounds, np.int64)
+    k = load_library().mst_last_round_stats(buf.ctypes.data_as(ctypes.c_void_p), max_rounds)
+    if k < 0:
+        raise MstxError(k)
+    return buf[:3 * k].reshape(k, 3)
+
+
+def mst_profile_enable(enable: bool) -> bool:
+    """Start (and zero) or stop per-kernel event timing; returns the previous state."""
+    return bool(load_library().mst_profile_enable(1 if enable else 0))
+
+
+def mst_profile_read() -> dict:
+    """{kernel kind: (total ms, launches, algorithmic bytes)} accumulated while enabled."""
+    import numpy as np
+    lib = load_library()
+    ms = np.zeros(16, np.float64)
+    n = np.zeros(16, np.int64)
+    b = np.zeros(16, np.float64)
+    k = lib.mst_profile_read(ms.ctypes.data_as(ctypes.c_void_p), n.ctypes.data_as(ctypes.c_void_p),
+                             b.ctypes.data_as(ctypes.c_void_p), 16)
+    if k < 0:
+        raise MstxError(k)
+    return {lib.mst_profile_kernel_name(i).decode(): (float(ms[i]), int(n[i]), float(b[i])) for i in range(k)}
+
+
+class Solution(NamedTuple):
+    in_mst: object  # torch.uint8 [m] on the GPU
+    total: int
+    status: int
+
+
+def solve(n, src, dst, w, stream=None) -> Solution:
+    """Allocate outputs and run ``mst_solve``; raises ``MstxError`` on a negative status."""
+    import torch
+    m = int(src.numel())
+    in_mst = torch.empty(m, dtype=torch.uint8, device=src.device)
+    total = torch.empty(1, dtype=torch.uint64, device=src.device)
+    st = mst_solve(n, src, dst, w, in_mst, total, stream)
+    if st < 0:
+        raise MstxError(st)
+    return Solution(in_mst, int(total.view(torch.int64).item()), st)

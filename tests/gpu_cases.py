@@ -1,0 +1,87 @@
+"""Graph cases for the GPU parity tests (inputs only; no method arithmetic).
+
+Small and mid-size cases run the full oracle (Kruskal for the tree, Boruvka
+for the round statistics); sizes are chosen to span several workgroup tiles
+(1024 records) and segments with ragged tails.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+from paper_2005_06913_amd import graphgen as G
+
+
+def _concat(parts, name):
+    n = 0
+    src, dst, w = [], [], []
+    for g, wshift in parts:
+        src.append(g.src + n)
+        dst.append(g.dst + n)
+        w.append(g.w + np.uint32(wshift))
+        n += g.n
+    return G.Graph(n, np.concatenate(src).astype(np.int32), np.concatenate(dst).astype(np.int32),
+                   np.concatenate(w).astype(np.uint32), name)
+
+
+def ties_multigraph(n, m, seed, wmax=4):
+    """Random multigraph with self-loops, parallel edges and heavily tied weights."""
+    rng = np.random.default_rng(seed)
+    src = rng.integers(0, n, m).astype(np.int32)
+    dst = rng.integers(0, n, m).astype(np.int32)
+    w = rng.integers(1, wmax + 1, m).astype(np.uint32)
+    # make it connected: a path through a random permutation with heavy weights
+    perm = rng.permutation(n).astype(np.int32)
+    src = np.concatenate([src, perm[:-1]])
+    dst = np.concatenate([dst, perm[1:]])
+    w = np.concatenate([w, np.full(n - 1, wmax + 1, np.uint32)])
+    order = rng.permutation(len(src))
+    return G.Graph(n, src[order], dst[order], w[order], f"ties_n{n}_m{m}_s{seed}")
+
+
+def small_cases():
+    """(graph, expect_connected) pairs that the oracle finishes in well under a second."""
+    cases = [
+        G.workload("random_n1k_m8k"),
+        G.tree_plus_extra(1000, 4097, seed=21, name="ragged_n1000_m4097"),
+        G.tree_plus_extra(3000, 3000 * 4 + 77, seed=22, name="ragged_n3000"),
+        G.paper_shape(10_000, 3, seed=100),
+        G.paper_shape(10_000, 6, seed=101),
+        G.paper_shape(10_000, 9, seed=102),
+        G.grid2d(64, 96, seed=23, name="grid_64x96"),
+        G.complete_graph(64, seed=24),
+        G.star_graph(20_000, seed=25),
+        G.cycle_graph(10_001, seed=26),
+        G.path_graph(30_000),  # increasing weights: one round, a hook chain of depth n-1
+        G.path_graph(30_000, np.arange(29_999, 0, -1, dtype=np.uint32)).with_weights(
+            np.arange(29_999, 0, -1, dtype=np.uint32), "path_decreasing_30000"),
+        ties_multigraph(2000, 12_000, seed=27),
+        ties_multigraph(5000, 9000, seed=28, wmax=1),  # every weight equal but the path
+        G.rmat(14, 120_000, seed=29),
+        G.planted_weights(G.tree_plus_extra(50_000, 400_000, seed=30)),
+        _concat([(G.tree_plus_extra(700, 3000, seed=31), 0), (G.tree_plus_extra(500, 900, seed=32), 10_000),
+                 (G.Graph(5, np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0, np.uint32)), 0)],
+                "disconnected_3parts_plus_isolated"),
+    ]
+    return cases
+
+
+def edge_cases():
+    """Degenerate inputs: (name, n, src, dst, w)."""
+    z32 = np.zeros(0, np.int32)
+    zw = np.zeros(0, np.uint32)
+    return [
+        ("n0_m0", 0, z32, z32, zw),
+        ("n1_m0", 1, z32, z32, zw),
+        ("n2_m0", 2, z32, z32, zw),
+        ("n1_loops", 1, np.zeros(3, np.int32), np.zeros(3, np.int32), np.array([5, 1, 9], np.uint32)),
+        ("n2_one_edge", 2, np.array([1], np.int32), np.array([0], np.int32), np.array([7], np.uint32)),
+        ("n2_parallel_ties", 2, np.array([0, 1, 0], np.int32), np.array([1, 0, 1], np.int32),
+         np.array([3, 3, 3], np.uint32)),
+        ("max_weight", 3, np.array([0, 1, 2], np.int32), np.array([1, 2, 0], np.int32),
+         np.array([0xFFFFFFFF, 0xFFFFFFFF, 0xFFFFFFFE], np.uint32)),
+        ("zero_weight", 3, np.array([0, 1, 2], np.int32), np.array([1, 2, 0], np.int32),
+         np.array([0, 0, 0], np.uint32)),
+        ("isolated_many", 100, np.array([5, 70], np.int32), np.array([6, 71], np.int32),
+         np.array([2, 1], np.uint32)),
+    ]

@@ -47,11 +47,13 @@ class Fixture:
     total: int
     status: int
     rounds: list  # [(components, live, added)]
+    minedge: dict  # vertex -> edge index (or None) of its lightest edge in round 0
 
 
 def load_fixture(path: str) -> Fixture:
     n = None
     src, dst, w, flag, rounds = [], [], [], [], []
+    names, minedge = {}, {}
     total = status = None
     with open(path) as f:
         for line in f:
@@ -62,6 +64,7 @@ def load_fixture(path: str) -> Fixture:
             if tok[0] == "n":
                 n = int(tok[1])
             elif tok[0] == "edge":
+                names[tok[1]] = len(src)
                 src.append(int(tok[2]))
                 dst.append(int(tok[3]))
                 w.append(int(tok[4]))
@@ -72,10 +75,12 @@ def load_fixture(path: str) -> Fixture:
                 status = int(tok[1])
             elif tok[0] == "round":
                 rounds.append(tuple(int(t) for t in tok[1:4]))
+            elif tok[0] == "minedge":
+                minedge[int(tok[1])] = None if tok[2] == "none" else names[tok[2]]
             else:
                 raise ValueError(f"{path}: unknown line {line!r}")
     return Fixture(os.path.basename(path), n, np.array(src, np.int32), np.array(dst, np.int32),
-                   np.array(w, np.uint32), np.array(flag, np.uint8), total, status, rounds)
+                   np.array(w, np.uint32), np.array(flag, np.uint8), total, status, rounds, minedge)
 
 
 def all_fixtures() -> list[Fixture]:
@@ -211,6 +216,40 @@ def pin_golden(orc):
         b = orc.boruvka(fx.n, fx.src, fx.dst, fx.w)
         _eq([tuple(r) for r in b.stats.tolist()], fx.rounds, f"{fx.name} boruvka rounds")
         _eq(orc.check_mst(fx.n, fx.src, fx.dst, fx.w, fx.in_mst, fx.total), 0, f"{fx.name} certificate")
+
+
+def expected_min_keys(fx: Fixture) -> np.ndarray:
+    """Round-0 keys (w << 32 | e) spelled out from a fixture's ``minedge`` lines."""
+    keys = np.full(fx.n, np.iinfo(np.uint64).max, np.uint64)
+    for v, e in fx.minedge.items():
+        if e is not None:
+            keys[v] = (np.uint64(fx.w[e]) << np.uint64(32)) | np.uint64(e)
+    return keys
+
+
+def numpy_min_keys(n, src, dst, w) -> np.ndarray:
+    """Round-0 minima with numpy's unbuffered ``minimum.at`` (a library reduction)."""
+    keys = np.full(n, np.iinfo(np.uint64).max, np.uint64)
+    e = np.arange(len(src), dtype=np.uint64)
+    k = (w.astype(np.uint64) << np.uint64(32)) | e
+    keep = src != dst
+    np.minimum.at(keys, src[keep], k[keep])
+    np.minimum.at(keys, dst[keep], k[keep])
+    return keys
+
+
+def pin_min_edges(orc, seed=17):
+    for fx in all_fixtures():
+        if not fx.minedge:
+            continue
+        st, keys = orc.min_edge_keys(fx.n, fx.src, fx.dst, fx.w)
+        _eq(st, 0, f"{fx.name} min-edge status")
+        _eq(keys, expected_min_keys(fx), f"{fx.name} round-0 minima")
+    rng = np.random.default_rng(seed)
+    for t in range(60):
+        n, src, dst, w = random_small_graph(rng, n_max=40, m_max=200, wmax=3 if t % 2 else 10**9)
+        st, keys = orc.min_edge_keys(n, src, dst, w)
+        _eq(keys, numpy_min_keys(n, src, dst, w), f"case {t} round-0 minima vs numpy")
 
 
 def pin_brute_force(orc, cases=250, seed=11):
@@ -422,6 +461,7 @@ def pin_matrix_tree(orc=None, cases=120, seed=13):
 PINS = {
     "golden": pin_golden,
     "brute_force": pin_brute_force,
+    "min_edges": pin_min_edges,
     "closed_forms": pin_closed_forms,
     "libraries": pin_libraries,
     "round_invariants": pin_round_invariants,

@@ -1,0 +1,162 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Integer graph work, so the bar is bit-exact: the in_mst byte array, the
+uint64 total weight, the status, and the per-round statistics (components,
+live edges, edges added) must equal the oracle's.  Where the graph is
+connected the oracle's sequential Boruvka round counts are comparable one to
+one: both remove exactly the internal edges and add one tree edge per
+distinct selected minimum.
+"""
+
+import numpy as np
+import pytest
+
+import gpu_cases
+import mst_pins
+import oracle
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2005_06913_amd as P
+    P.load_library()
+    return torch.device("cuda:0")
+
+
+def to_dev(dev, src, dst, w):
+    return (torch.from_numpy(np.ascontiguousarray(src, np.int32)).to(dev),
+            torch.from_numpy(np.ascontiguousarray(dst, np.int32)).to(dev),
+            torch.from_numpy(np.ascontiguousarray(w, np.uint32)).to(dev))
+
+
+def gpu_solve(dev, n, src, dst, w):
+    import paper_2005_06913_amd as P
+    s, d, ww = to_dev(dev, src, dst, w)
+    m = len(src)
+    in_mst = torch.full((m,), 7, dtype=torch.uint8, device=dev)  # garbage: must be overwritten
+    total = torch.full((1,), 12345, dtype=torch.int64, device=dev).view(torch.uint64)
+    st = P.mst_solve(n, s, d, ww, in_mst, total)
+    torch.cuda.synchronize()
+    stats = P.mst_last_round_stats()
+    return st, in_mst.cpu().numpy(), int(total.view(torch.int64).cpu().item()), stats
+
+
+def check_against_oracle(dev, name, n, src, dst, w, stats=True):
+    print(f"[case] {name} n={n} m={len(src)}", flush=True)
+    st, in_mst, total, gstats = gpu_solve(dev, n, src, dst, w)
+    k = oracle.kruskal(n, src, dst, w)
+    assert st == k.status, f"{name}: status {st} != oracle {k.status}"
+    assert total == k.total, f"{name}: total {total} != oracle {k.total}"
+    diff = np.flatnonzero(in_mst != k.in_mst)
+    assert diff.size == 0, f"{name}: {diff.size} edges differ, first {diff[:8]}"
+    if stats and k.status == 0 and n > 1:
+        b = oracle.boruvka(n, src, dst, w)
+        assert np.array_equal(gstats, b.stats), f"{name}: round stats\n{gstats}\n!=\n{b.stats}"
+    return gstats
+
+
+# -------------------------------------------------------- first kernel (S1)
+
+@pytest.mark.parametrize("idx", range(len(gpu_cases.small_cases())))
+def test_min_edge_keys(dev, idx):
+    import paper_2005_06913_amd as P
+    g = gpu_cases.small_cases()[idx]
+    print(f"[case] min-edge {g.name}", flush=True)
+    s, d, w = to_dev(dev, g.src, g.dst, g.w)
+    out = torch.zeros(g.n, dtype=torch.int64, device=dev).view(torch.uint64)
+    assert P.mst_select_min_edges(g.n, s, d, w, out) == 0
+    st, want = oracle.min_edge_keys(g.n, g.src, g.dst, g.w)
+    assert st == 0
+    got = out.view(torch.int64).cpu().numpy().view(np.uint64)
+    assert np.array_equal(got, want)
+
+
+def test_min_edge_keys_golden(dev):
+    import paper_2005_06913_amd as P
+    for fx in mst_pins.all_fixtures():
+        if not fx.minedge:
+            continue
+        s, d, w = to_dev(dev, fx.src, fx.dst, fx.w)
+        out = torch.zeros(fx.n, dtype=torch.int64, device=dev).view(torch.uint64)
+        assert P.mst_select_min_edges(fx.n, s, d, w, out) == 0
+        got = out.view(torch.int64).cpu().numpy().view(np.uint64)
+        assert np.array_equal(got, mst_pins.expected_min_keys(fx)), fx.name
+
+
+# ------------------------------------------------------------- full solve
+
+@pytest.mark.parametrize("idx", range(len(gpu_cases.small_cases())))
+def test_solve_small(dev, idx):
+    g = gpu_cases.small_cases()[idx]
+    check_against_oracle(dev, g.name, g.n, g.src, g.dst, g.w)
+
+
+def test_solve_golden(dev):
+    for fx in mst_pins.all_fixtures():
+        st, in_mst, total, stats = gpu_solve(dev, fx.n, fx.src, fx.dst, fx.w)
+        assert st == fx.status, fx.name
+        assert total == fx.total, fx.name
+        assert np.array_equal(in_mst, fx.in_mst), fx.name
+        if fx.status == 0:
+            assert [tuple(r) for r in stats.tolist()] == fx.rounds, fx.name
+
+
+@pytest.mark.parametrize("case", gpu_cases.edge_cases(), ids=[c[0] for c in gpu_cases.edge_cases()])
+def test_solve_edge_cases(dev, case):
+    name, n, src, dst, w = case
+    check_against_oracle(dev, name, n, src, dst, w, stats=False)
+
+
+def test_vertex_range_error(dev):
+    import paper_2005_06913_amd as P
+    for bad_src in (5, -1, 1 << 30):
+        src = np.array([0, 1, bad_src], np.int32)
+        dst = np.array([1, 2, 0], np.int32)
+        w = np.array([1, 2, 3], np.uint32)
+        st, _, _, _ = gpu_solve(dev, 5, src, dst, w)
+        assert st == P.MSTX_ERR_VERTEX_RANGE
+        s, d, ww = to_dev(dev, src, dst, w)
+        out = torch.zeros(5, dtype=torch.int64, device=dev).view(torch.uint64)
+        assert P.mst_select_min_edges(5, s, d, ww, out) == P.MSTX_ERR_VERTEX_RANGE
+    # edges but no vertices
+    st, _, _, _ = gpu_solve(dev, 0, np.array([0], np.int32), np.array([0], np.int32), np.array([1], np.uint32))
+    assert st == P.MSTX_ERR_VERTEX_RANGE
+
+
+def test_determinism_and_reuse(dev):
+    """Repeated solves give identical bytes; a smaller graph after a larger one reuses the workspace."""
+    g = gpu_cases.small_cases()[3]
+    first = gpu_solve(dev, g.n, g.src, g.dst, g.w)
+    for _ in range(4):
+        again = gpu_solve(dev, g.n, g.src, g.dst, g.w)
+        assert again[0] == first[0] and again[2] == first[2]
+        assert np.array_equal(again[1], first[1])
+        assert np.array_equal(again[3], first[3])
+    small = gpu_cases.small_cases()[0]
+    check_against_oracle(dev, small.name + "_after_larger", small.n, small.src, small.dst, small.w)
+
+
+# ----------------------------------------------- full-size configurations
+
+@pytest.mark.parametrize("name", ["random_n1M_d16", "grid_1024x1024"])
+def test_solve_full_size(dev, name):
+    from paper_2005_06913_amd import graphgen as G
+    g = G.workload(name)
+    check_against_oracle(dev, g.name, g.n, g.src, g.dst, g.w, stats=(name == "grid_1024x1024"))
+
+
+def test_solve_full_size_planted(dev):
+    """n = 2^20, degree 16, planted tree: the MST is the planted tree, weight n(n-1)/2."""
+    from paper_2005_06913_amd import graphgen as G
+    g = G.planted_weights(G.workload("random_n1M_d16"))
+    print(f"[case] {g.name}", flush=True)
+    st, in_mst, total, _ = gpu_solve(dev, g.n, g.src, g.dst, g.w)
+    assert st == 0
+    assert total == g.n * (g.n - 1) // 2
+    assert np.array_equal(in_mst, g.tree_mask.astype(np.uint8))

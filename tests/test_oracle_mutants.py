@@ -42,6 +42,9 @@ MUTANTS = [
     ("checker_lca_last_step_dropped", "uint64_t x = upmax[a], y = upmax[b];", "uint64_t x = 0, y = 0;"),
     ("checker_no_span_check", "if (marked != (int64_t)n - comps) return CHECK_NOT_SPANNING;", ""),
     ("checker_no_total_check", "if (sum != total) return CHECK_TOTAL;", ""),
+    ("min_edges_drops_second_end", "if (k < keys[dst[e]]) keys[dst[e]] = k;", ""),
+    ("min_edges_keeps_loops", "if (src[e] == dst[e]) continue;\n        uint64_t k = order_key(w, e);",
+     "uint64_t k = order_key(w, e);"),
     ("range_check_off_by_one", "src[e] >= n || dst[e] < 0 || dst[e] >= n) return ORACLE_ERR_RANGE",
      "src[e] > n || dst[e] < 0 || dst[e] >= n) return ORACLE_ERR_RANGE"),
 ]
