@@ -147,6 +147,8 @@ def main() -> int:
                    "alg_bytes_per_launch": (v[2] / v[1] if v[1] else 0.0)} for k, v in prof.items()}
     dom = max(kernels, key=lambda k: kernels[k]["ms_total"])
     scan_kinds = [k for k in kernels if k.startswith("scan") and kernels[k]["launches"]]
+    # the minima of a BUCKET / LDS-slab scan are finished by bucket_min / slab_min
+    step_kinds = scan_kinds + [k for k in ("bucket_min", "slab_min") if k in kernels and kernels[k]["launches"]]
     dk = kernels[dom]
     if dk["alg_bytes_per_launch"] > 0:
         achieved = dk["alg_bytes_per_launch"] / (dk["ms_per_launch"] * 1e-3) / 1e9
@@ -155,7 +157,7 @@ def main() -> int:
         sk = max(scan_kinds, key=lambda k: kernels[k]["ms_total"])
         achieved = kernels[sk]["alg_bytes_per_launch"] / (kernels[sk]["ms_per_launch"] * 1e-3) / 1e9
         bound_kernel = sk
-    scan_ms = sum(kernels[k]["ms_total"] for k in scan_kinds)
+    scan_ms = sum(kernels[k]["ms_total"] for k in step_kinds)
     scan_bytes = sum(prof[k][2] for k in scan_kinds)
 
     out = {

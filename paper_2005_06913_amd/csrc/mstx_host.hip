@@ -2,9 +2,15 @@
 //
 // Argument checks run on the host before any HIP call.  The workspace (all
 // device scratch) is planned from (n, m), cached per device and guarded by a
-// mutex.  The round loop enqueues the five kernels of a round on the caller's
-// stream and reads back the 1 KB round state to decide whether another round
-// is needed.
+// mutex.
+//
+// Round control is pipelined one round ahead: round r+1 is enqueued before
+// the host waits for round r's record (written by k_finalize straight into
+// pinned host memory), so the GPU never idles on the host.  When round r+1
+// is enqueued only an upper bound n_{r+1} <= n_r / 2 is known; the scan
+// modes are launched for every count the bound allows and the kernels pick
+// the one that matches the actual count on the device (the others return
+// at once).  The round after the last one finds n <= 1 and returns at once.
 
 #include <hip/hip_runtime.h>
 
@@ -21,17 +27,17 @@ namespace mstx {
 namespace {
 
 constexpr int kBlockThreads = 256;
-constexpr int kMaxGrid = 4096;        // capacity of the per-block partial arrays
-constexpr int kMaxSegments = 2048;    // segments of the record stream
-constexpr uint32_t kMinSegment = 1024;
-constexpr int32_t kLdsSlots = 8192;   // per-workgroup minima kept in LDS (64 KiB)
+constexpr int kMaxGrid = 4096;  // capacity of the per-block partial arrays (hook)
 
 struct Layout {
-  size_t best, parent, root_of, labpool, rootmask, rootcnt, rootpre, rec, seg_cnt, part_live, part_sel,
-      part_w, state, bytes;
+  size_t best, parent, root_of, labpool, rootmask, rootcnt, rootpre, rec, seg_cnt, part_sel, part_w, state,
+      upd_key, upd_cl, offT, slab, bytes;
+  int64_t slab_cap;  // u64 entries of the LDS-mode slab (0: none)
   int32_t nseg;
-  uint32_t seg_cap;
+  bool bucket;  // offer buffers present
 };
+
+constexpr int kSlabRows = 256;  // workgroup rows of the LDS-mode slab
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -40,11 +46,9 @@ Layout plan(int32_t n, int64_t m) {
   Layout L{};
   const size_t N = (size_t)std::max<int32_t>(n, 1);
   const size_t words = (N + 63) / 64 + 1;
-  int64_t nseg = (m + kMinSegment - 1) / kMinSegment;
-  nseg = std::max<int64_t>(1, std::min<int64_t>(nseg, kMaxSegments));
-  const uint64_t seg_cap = m > 0 ? (uint64_t)((m + nseg - 1) / nseg) : 1;
+  const int64_t nseg = std::max<int64_t>(1, (m + kSegCap - 1) / kSegCap);
   L.nseg = (int32_t)nseg;
-  L.seg_cap = (uint32_t)seg_cap;
+  L.bucket = n > kLdsSlots;
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t o = off;
@@ -58,12 +62,18 @@ Layout plan(int32_t n, int64_t m) {
   L.rootmask = take(8 * words);
   L.rootcnt = take(4 * words);
   L.rootpre = take(4 * words);
-  L.rec = take(16 * (size_t)nseg * seg_cap);
+  L.rec = take(16 * (size_t)nseg * kSegCap);
   L.seg_cnt = take(4 * (size_t)nseg);
-  L.part_live = take(4 * (size_t)kMaxGrid);
   L.part_sel = take(4 * (size_t)kMaxGrid);
   L.part_w = take(8 * (size_t)kMaxGrid);
   L.state = take(sizeof(DevState));
+  L.slab_cap = n > kSlabMin ? (int64_t)kSlabRows * std::min<int32_t>(n, kLdsSlots) : 0;
+  if (L.slab_cap) L.slab = take(8 * (size_t)L.slab_cap);
+  if (L.bucket) {
+    L.upd_key = take(8 * (size_t)nseg * 2 * kSegCap);
+    L.upd_cl = take(2 * (size_t)nseg * 2 * kSegCap);
+    L.offT = take(4 * (size_t)(kMaxBuckets + 1) * nseg);
+  }
   L.bytes = off;
   return L;
 }
@@ -72,101 +82,16 @@ struct DeviceCache {
   std::mutex mu;
   void* base = nullptr;
   size_t bytes = 0;
-  DevState* host_state = nullptr;  // pinned
+  HostRound* host_rounds = nullptr;  // pinned, one record per round
+  hipEvent_t round_ev[kMaxRounds + 1] = {};
   int cus = 0;
+  bool configured = false;
 };
 
 constexpr int kMaxDevices = 64;
 DeviceCache g_dev[kMaxDevices];
 
 thread_local std::vector<int64_t> t_last_stats;
-
-// ------------------------------------------------------------- profiling
-// Opt-in per-kernel timing: when enabled, every kernel launch of a solve is
-// bracketed by two hipEvents on the solve's stream.  After the solve the
-// elapsed times are accumulated per kernel kind together with the kind's
-// algorithmic bytes (bytes the method must move, computed from the round
-// statistics).
-enum Kind { kScanFirst = 0, kScanInput, kScanRecords, kHook, kCompress, kFinalize, kRelabel, kKinds };
-const char* const kKindNames[kKinds] = {"scan_first", "scan_input", "scan_records", "hook",
-                                        "compress",   "finalize",   "relabel"};
-
-struct Profile {
-  std::mutex mu;
-  bool enabled = false;
-  double ms[kKinds] = {};
-  int64_t launches[kKinds] = {};
-  double bytes[kKinds] = {};
-};
-Profile g_prof;
-
-struct PendingLaunch {
-  int kind;
-  hipEvent_t a, b;
-  double bytes;
-};
-
-// Events of one solve; reused across solves on this thread.
-struct LaunchTimer {
-  bool on = false;
-  std::vector<hipEvent_t> pool;
-  size_t used = 0;
-  std::vector<PendingLaunch> pending;
-  hipStream_t s = nullptr;
-
-  hipError_t begin(hipStream_t stream) {
-    on = false;
-    {
-      std::lock_guard<std::mutex> g(g_prof.mu);
-      on = g_prof.enabled;
-    }
-    used = 0;
-    pending.clear();
-    s = stream;
-    return hipSuccess;
-  }
-  hipError_t event(hipEvent_t* out) {
-    if (used == pool.size()) {
-      hipEvent_t e;
-      hipError_t r = hipEventCreate(&e);
-      if (r != hipSuccess) return r;
-      pool.push_back(e);
-    }
-    *out = pool[used++];
-    return hipSuccess;
-  }
-  // Records the start event; returns the pending slot (or -1 when off).
-  int start(int kind) {
-    if (!on) return -1;
-    PendingLaunch p{kind, nullptr, nullptr, 0.0};
-    if (event(&p.a) != hipSuccess || event(&p.b) != hipSuccess) return -1;
-    if (hipEventRecord(p.a, s) != hipSuccess) return -1;
-    pending.push_back(p);
-    return (int)pending.size() - 1;
-  }
-  void stop(int slot, double bytes = 0.0) {
-    if (slot < 0) return;
-    pending[slot].bytes = bytes;
-    (void)hipEventRecord(pending[slot].b, s);
-  }
-  void set_bytes(int slot, double bytes) {
-    if (slot >= 0) pending[slot].bytes = bytes;
-  }
-  // Call after the stream has been synchronised.
-  void commit() {
-    if (!on) return;
-    std::lock_guard<std::mutex> g(g_prof.mu);
-    for (const auto& p : pending) {
-      float ms = 0.f;
-      if (hipEventElapsedTime(&ms, p.a, p.b) != hipSuccess) continue;
-      g_prof.ms[p.kind] += ms;
-      g_prof.launches[p.kind] += 1;
-      g_prof.bytes[p.kind] += p.bytes;
-    }
-    pending.clear();
-  }
-};
-thread_local LaunchTimer t_timer;
 
 size_t workspace_limit() {
   const char* s = std::getenv("MSTX_WORKSPACE_LIMIT_BYTES");
@@ -189,8 +114,8 @@ int check_args(int32_t n, int64_t m, const void* src, const void* dst, const voi
   return MSTX_OK;
 }
 
-#define HIP_OK(expr)                              \
-  do {                                            \
+#define HIP_OK(expr)                                  \
+  do {                                                \
     if ((expr) != hipSuccess) return MSTX_ERR_DEVICE; \
   } while (0)
 
@@ -201,11 +126,16 @@ int acquire(DeviceCache*& dc, std::unique_lock<std::mutex>& lock, size_t bytes) 
   if (dev < 0 || dev >= kMaxDevices) return MSTX_ERR_DEVICE;
   dc = &g_dev[dev];
   lock = std::unique_lock<std::mutex>(dc->mu);
-  if (!dc->host_state) {
-    HIP_OK(hipHostMalloc((void**)&dc->host_state, sizeof(DevState), hipHostMallocDefault));
+  if (!dc->configured) {
+    HIP_OK(hipHostMalloc((void**)&dc->host_rounds, sizeof(HostRound) * (kMaxRounds + 1), hipHostMallocDefault));
+    for (int i = 0; i <= kMaxRounds; ++i) HIP_OK(hipEventCreateWithFlags(&dc->round_ev[i], hipEventDisableTiming));
     hipDeviceProp_t prop;
     HIP_OK(hipGetDeviceProperties(&prop, dev));
     dc->cus = prop.multiProcessorCount;
+    // raises the dynamic LDS limit of the scan kernels; if the runtime refuses,
+    // launches that need more LDS fail and report MSTX_ERR_DEVICE
+    if (configure_kernels() != hipSuccess) (void)hipGetLastError();
+    dc->configured = true;
   }
   if (dc->bytes < bytes) {
     if (dc->base) {
@@ -235,6 +165,226 @@ int rounds_bound(int32_t n) {
   return b + 1;
 }
 
+// ------------------------------------------------------------- profiling
+// Opt-in per-kernel timing: when enabled, every kernel launch of a solve is
+// bracketed by two hipEvents on the solve's stream.  After the solve the
+// elapsed times of the launches that did the round's work are accumulated
+// per kernel kind, with the kind's algorithmic bytes (what the method must
+// move, from the round statistics).  Launches that returned at once (a scan
+// mode not chosen for the actual count, the round after the last) are left out.
+enum Kind {
+  kScan0Global = 0, kScan0Lds, kScan0Bucket,
+  kScan1Global, kScan1Lds, kScan1Bucket,
+  kScanRGlobal, kScanRLds, kScanRBucket,
+  kBucketMin, kSlabMin_, kHook, kCompress, kFinalize, kRelabel, kKinds
+};
+const char* const kKindNames[kKinds] = {
+    "scan_r0_global", "scan_r0_lds",  "scan_r0_bucket", "scan_r1_global", "scan_r1_lds",
+    "scan_r1_bucket", "scan_rN_global", "scan_rN_lds", "scan_rN_bucket", "bucket_min",
+    "slab_min",       "hook",         "compress",       "finalize",       "relabel"};
+
+int scan_kind(int stage, int mode) {
+  const int m = mode == kModeGlobal ? 0 : (mode == kModeLds ? 1 : 2);
+  return 3 * stage + m;
+}
+
+struct Profile {
+  std::mutex mu;
+  bool enabled = false;
+  double ms[kKinds] = {};
+  int64_t launches[kKinds] = {};
+  double bytes[kKinds] = {};
+};
+Profile g_prof;
+
+struct PendingLaunch {
+  int kind, round, mode;  // mode: -1 for kernels that always run
+  hipEvent_t a, b;
+};
+
+struct LaunchTimer {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  std::vector<PendingLaunch> pending;
+  hipStream_t s = nullptr;
+
+  void begin(hipStream_t stream) {
+    {
+      std::lock_guard<std::mutex> g(g_prof.mu);
+      on = g_prof.enabled;
+    }
+    used = 0;
+    pending.clear();
+    s = stream;
+  }
+  hipEvent_t event() {
+    if (used == pool.size()) {
+      hipEvent_t e = nullptr;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+  int start(int kind, int round, int mode) {
+    if (!on) return -1;
+    PendingLaunch p{kind, round, mode, event(), event()};
+    if (!p.a || !p.b || hipEventRecord(p.a, s) != hipSuccess) return -1;
+    pending.push_back(p);
+    return (int)pending.size() - 1;
+  }
+  void stop(int slot) {
+    if (slot >= 0) (void)hipEventRecord(pending[slot].b, s);
+  }
+  // After the stream is synchronised.  chosen[r] = mode that ran in round r,
+  // bytes[r] = algorithmic bytes of round r's scan; rounds >= nrounds were idle.
+  void commit(int nrounds, const std::vector<int>& chosen, const std::vector<double>& bytes) {
+    if (!on) return;
+    std::lock_guard<std::mutex> g(g_prof.mu);
+    for (const auto& p : pending) {
+      if (p.round >= nrounds) continue;
+      if (p.mode >= 0 && p.mode != chosen[p.round]) continue;
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, p.a, p.b) != hipSuccess) continue;
+      g_prof.ms[p.kind] += ms;
+      g_prof.launches[p.kind] += 1;
+      if (p.kind <= kScanRBucket) g_prof.bytes[p.kind] += bytes[p.round];
+    }
+    pending.clear();
+  }
+};
+thread_local LaunchTimer t_timer;
+
+int host_pick_mode(int32_t nr, int launched) {
+  if ((launched & (1 << kModeLds)) && nr <= kLdsSlots) return kModeLds;
+  if ((launched & (1 << kModeBucket)) && (int64_t)nr <= kBucketMaxComponents) return kModeBucket;
+  return kModeGlobal;
+}
+
+int mode_for(int64_t nr) {
+  if (nr <= kLdsSlots) return kModeLds;
+  if (nr <= kBucketMaxComponents) return kModeBucket;
+  return kModeGlobal;
+}
+
+// Everything one solve needs to enqueue its rounds.
+struct Solve {
+  int32_t n;
+  int64_t m;
+  const int32_t* src;
+  const int32_t* dst;
+  const uint32_t* w;
+  uint8_t* in_mst;
+  unsigned long long* total;
+  hipStream_t s;
+  DeviceCache* dc;
+  Layout L;
+  unsigned long long* best;
+  int32_t* parent;
+  int32_t* root_of;
+  int32_t* labpool;
+  unsigned long long* rootmask;
+  int32_t* rootcnt;
+  int32_t* rootpre;
+  uint4* rec;
+  uint32_t* seg_cnt;
+  uint32_t* part_sel;
+  unsigned long long* part_w;
+  DevState* st;
+  unsigned long long* upd_key;
+  uint16_t* upd_cl;
+  uint32_t* offT;
+  unsigned long long* slab;
+  std::vector<int> launched;  // per round
+};
+
+// Enqueues the scan of `stage` (0: round 0, 1: round 1, 2: rounds >= 2) for a
+// round whose component count is at most `bound`.  Returns the launched mask.
+int enqueue_scan(Solve& S, int r, int stage, int64_t bound, bool exact, hipError_t& err) {
+  LaunchTimer& T = t_timer;
+  const int hi_mode = mode_for(bound);
+  int launched = 1 << hi_mode;
+  if (!exact) {
+    // the actual count may be much smaller than the bound
+    if (hi_mode != kModeLds && bound / 8 <= kLdsSlots) launched |= 1 << kModeLds;
+    if (hi_mode == kModeGlobal && bound / 8 <= kBucketMaxComponents) launched |= 1 << kModeBucket;
+  }
+  if (!S.L.bucket) launched &= ~(1 << kModeBucket), launched |= (bound > kLdsSlots ? 1 << kModeGlobal : 0);
+  ScanArgs A{r,      launched, S.src,     S.dst,    S.w,    (uint32_t)S.m, S.n,     S.labpool, S.rec,
+             S.seg_cnt, S.L.nseg, S.best, S.st, S.upd_key, S.upd_cl, S.offT, S.slab, S.L.slab_cap};
+  const int cus = S.dc->cus;
+  for (int mode : {kModeLds, kModeBucket, kModeGlobal}) {
+    if (!(launched & (1 << mode))) continue;
+    int grid;
+    size_t lds;
+    if (mode == kModeLds) {
+      const int64_t slots = std::max<int64_t>(1, std::min<int64_t>(bound, kLdsSlots));
+      lds = (size_t)slots * 8;
+      const int per_cu = (int)std::max<int64_t>(1, std::min<int64_t>(4, 65536 / ((int64_t)lds + 1024)));
+      grid = std::min(S.L.nseg, cus * per_cu);
+    } else if (mode == kModeBucket) {
+      lds = kBucketScanLds;
+      grid = std::min(S.L.nseg, cus);
+    } else {
+      lds = 0;
+      grid = std::min(S.L.nseg, 2 * cus);
+    }
+    const int k = T.start(scan_kind(stage, mode), r, mode);
+    err = launch_scan(mode, stage, A, grid, lds, S.s);
+    T.stop(k);
+    if (err != hipSuccess) return launched;
+    if (mode == kModeLds && S.slab) {
+      const int ks = T.start(kSlabMin_, r, kModeLds);
+      err = launch_slab_min(r, launched, S.slab, S.L.slab_cap, grid, S.best, S.st,
+                            grid_for(std::min<int64_t>(std::max<int64_t>(bound, 1), kLdsSlots)), S.s);
+      T.stop(ks);
+      if (err != hipSuccess) return launched;
+    }
+    if (mode == kModeBucket) {
+      int shift, nbk;
+      bucket_geometry((int32_t)std::min<int64_t>(bound, kBucketMaxComponents), &shift, &nbk);
+      // a smaller actual count can have more (narrower) buckets, but never more than 256
+      // unless the width is at its maximum
+      const int grid_b = std::max(nbk, 256);
+      const int kb = T.start(kBucketMin, r, kModeBucket);
+      err = launch_bucket_min(r, launched, S.upd_key, S.upd_cl, S.offT, S.L.nseg, S.best, S.st, grid_b,
+                              (size_t)8 << shift, S.s);
+      T.stop(kb);
+      if (err != hipSuccess) return launched;
+    }
+  }
+  return launched;
+}
+
+// Enqueues round r (component count at most `bound`, exact when r == 0).
+hipError_t enqueue_round(Solve& S, int r, int64_t bound) {
+  LaunchTimer& T = t_timer;
+  hipError_t err = hipSuccess;
+  const int stage = r == 0 ? 0 : (r == 1 ? 1 : 2);
+  S.launched[r] = enqueue_scan(S, r, stage, bound, r == 0, err);
+  if (err != hipSuccess) return err;
+  const int gh = grid_for(std::max<int64_t>(bound, 1));
+  int k = T.start(kHook, r, -1);
+  err = launch_hook(r, S.src, S.dst, S.w, S.best, S.parent, S.labpool, S.st, S.in_mst, S.part_sel, S.part_w, gh,
+                    S.s);
+  T.stop(k);
+  if (err != hipSuccess) return err;
+  k = T.start(kCompress, r, -1);
+  err = launch_compress(r, S.parent, S.root_of, S.best, S.rootmask, S.rootcnt, S.st, gh, S.s);
+  T.stop(k);
+  if (err != hipSuccess) return err;
+  k = T.start(kFinalize, r, -1);
+  err = launch_finalize(r, S.rootcnt, S.rootpre, S.seg_cnt, S.L.nseg, S.part_sel, S.part_w, gh, S.st, S.total,
+                        S.dc->host_rounds, S.s);
+  T.stop(k);
+  if (err != hipSuccess) return err;
+  k = T.start(kRelabel, r, -1);
+  err = launch_relabel(r, S.root_of, S.rootmask, S.rootpre, S.labpool, S.parent, S.best, S.st, gh, S.s);
+  T.stop(k);
+  if (err != hipSuccess) return err;
+  return hipEventRecord(S.dc->round_ev[r], S.s);
+}
+
 int solve(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, const uint32_t* w, uint8_t* in_mst,
           uint64_t* total, hipStream_t s) {
   t_last_stats.clear();
@@ -252,96 +402,95 @@ int solve(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, const ui
   int rc = acquire(dc, lock, L.bytes);
   if (rc != MSTX_OK) return rc;
   void* B = dc->base;
-  auto* best = at<unsigned long long>(B, L.best);
-  auto* parent = at<int32_t>(B, L.parent);
-  auto* root_of = at<int32_t>(B, L.root_of);
-  auto* labpool = at<int32_t>(B, L.labpool);
-  auto* rootmask = at<unsigned long long>(B, L.rootmask);
-  auto* rootcnt = at<int32_t>(B, L.rootcnt);
-  auto* rootpre = at<int32_t>(B, L.rootpre);
-  auto* rec = at<uint4>(B, L.rec);
-  auto* seg_cnt = at<uint32_t>(B, L.seg_cnt);
-  auto* part_live = at<uint32_t>(B, L.part_live);
-  auto* part_sel = at<uint32_t>(B, L.part_sel);
-  auto* part_w = at<unsigned long long>(B, L.part_w);
-  auto* st = at<DevState>(B, L.state);
-  auto* tot = reinterpret_cast<unsigned long long*>(total);
-  DevState* hs = dc->host_state;
-  const uint32_t mu = (uint32_t)m;
-
-  HIP_OK(hipMemsetAsync(in_mst, 0, (size_t)m, s));
-  HIP_OK(hipMemsetAsync(total, 0, sizeof(uint64_t), s));
-  HIP_OK(launch_init(n, mu, best, parent, st, grid_for(n), s));
-
+  Solve S;
+  S.n = n;
+  S.m = m;
+  S.src = src;
+  S.dst = dst;
+  S.w = w;
+  S.in_mst = in_mst;
+  S.total = reinterpret_cast<unsigned long long*>(total);
+  S.s = s;
+  S.dc = dc;
+  S.L = L;
+  S.best = at<unsigned long long>(B, L.best);
+  S.parent = at<int32_t>(B, L.parent);
+  S.root_of = at<int32_t>(B, L.root_of);
+  S.labpool = at<int32_t>(B, L.labpool);
+  S.rootmask = at<unsigned long long>(B, L.rootmask);
+  S.rootcnt = at<int32_t>(B, L.rootcnt);
+  S.rootpre = at<int32_t>(B, L.rootpre);
+  S.rec = at<uint4>(B, L.rec);
+  S.seg_cnt = at<uint32_t>(B, L.seg_cnt);
+  S.part_sel = at<uint32_t>(B, L.part_sel);
+  S.part_w = at<unsigned long long>(B, L.part_w);
+  S.st = at<DevState>(B, L.state);
+  S.upd_key = L.bucket ? at<unsigned long long>(B, L.upd_key) : nullptr;
+  S.upd_cl = L.bucket ? at<uint16_t>(B, L.upd_cl) : nullptr;
+  S.offT = L.bucket ? at<uint32_t>(B, L.offT) : nullptr;
+  S.slab = L.slab_cap ? at<unsigned long long>(B, L.slab) : nullptr;
   const int max_rounds = std::min(rounds_bound(n) + 1, kMaxRounds);
+  S.launched.assign(kMaxRounds + 1, 0);
+
   LaunchTimer& T = t_timer;
   T.begin(s);
-  int32_t nr = n;
-  int64_t live_prev = 0;
+  HIP_OK(hipMemsetAsync(in_mst, 0, (size_t)m, s));
+  HIP_OK(hipMemsetAsync(total, 0, sizeof(uint64_t), s));
+  HIP_OK(launch_init(n, S.best, S.parent, S.st, grid_for(n), s));
+  HIP_OK(enqueue_round(S, 0, n));
+
+  int status = MSTX_ERR_DEVICE;  // until the loop decides
   int rounds = 0;
-  bool done = false;
-  for (int r = 0; r < max_rounds && !done; ++r) {
-    int nlive;
-    const uint32_t* live_parts;
-    int scan_slot;
-    if (r == 0) {
-      const bool lds = n <= kLdsSlots;
-      const int g = lds ? std::min(grid_for(m), 2 * dc->cus) : grid_for(m);
-      scan_slot = T.start(kScanFirst);
-      HIP_OK(launch_scan_first(lds, src, dst, w, mu, n, best, part_live, st, g, s));
-      T.stop(scan_slot);
-      nlive = g;
-      live_parts = part_live;
-    } else {
-      const bool lds = nr <= kLdsSlots;
-      const int g = lds ? std::min(L.nseg, 2 * dc->cus) : L.nseg;
-      scan_slot = T.start(r == 1 ? kScanInput : kScanRecords);
-      HIP_OK(launch_scan_seg(r == 1, lds, nr, r, src, dst, w, mu, labpool, rec, seg_cnt, L.seg_cap, L.nseg,
-                             best, st, g, s));
-      T.stop(scan_slot);
-      nlive = L.nseg;
-      live_parts = seg_cnt;
+  int32_t n_known = n;  // exact component count entering round r
+  std::vector<int32_t> nr_of(kMaxRounds + 2, 0);
+  nr_of[0] = n;
+  int r_enq = 0;
+  for (int r = 0; r < max_rounds; ++r) {
+    if (r_enq == r && r + 1 <= kMaxRounds - 1) {
+      HIP_OK(enqueue_round(S, r + 1, n_known / 2));
+      r_enq = r + 1;
     }
-    const int gh = grid_for(nr);
-    int k = T.start(kHook);
-    HIP_OK(launch_hook(r, src, dst, w, best, parent, labpool, st, in_mst, part_sel, part_w, gh, s));
-    T.stop(k);
-    k = T.start(kCompress);
-    HIP_OK(launch_compress(r, parent, root_of, best, rootmask, rootcnt, st, gh, s));
-    T.stop(k);
-    k = T.start(kFinalize);
-    HIP_OK(launch_finalize(r, rootcnt, rootpre, live_parts, nlive, part_sel, part_w, gh, st, tot, s));
-    T.stop(k);
-    k = T.start(kRelabel);
-    HIP_OK(launch_relabel(r, root_of, rootmask, rootpre, labpool, parent, best, st, gh, s));
-    T.stop(k);
-    HIP_OK(hipMemcpyAsync(hs, st, sizeof(DevState), hipMemcpyDeviceToHost, s));
-    HIP_OK(hipStreamSynchronize(s));
+    HIP_OK(hipEventSynchronize(dc->round_ev[r]));
+    const HostRound M = dc->host_rounds[r];
     rounds = r + 1;
-    if (r == 0 && hs->err) return MSTX_ERR_VERTEX_RANGE;
-    if (hs->err_internal) return MSTX_ERR_DEVICE;
-    // algorithmic bytes of this round's scan: the edge stream read once, the
-    // previous label map read once, best[] initialised and written once, the
-    // compacted survivors written once
-    const double nrd = (double)nr, live_r = (double)hs->live[r];
-    double b;
-    if (r == 0) b = 12.0 * (double)m + 16.0 * nrd;
-    else if (r == 1) b = 12.0 * (double)m + 4.0 * (double)n + 16.0 * nrd + 16.0 * live_r;
-    else b = 16.0 * (double)live_prev + 4.0 * (double)hs->n[r - 1] + 16.0 * nrd + 16.0 * live_r;
-    T.set_bytes(scan_slot, b);
-    live_prev = hs->live[r];
-    nr = hs->n[r + 1];
-    if (nr <= 1) done = true;
+    if (r == 0 && M.err) {
+      status = MSTX_ERR_VERTEX_RANGE;
+      break;
+    }
+    if (M.err_internal) {
+      status = MSTX_ERR_DEVICE;
+      break;
+    }
+    n_known = M.n_next;
+    nr_of[r + 1] = n_known;
+    if (n_known <= 1) {
+      status = (n <= 1 || M.edges_added == (int64_t)n - 1) ? MSTX_OK : MSTX_DISCONNECTED;
+      break;
+    }
   }
-  T.commit();
-  if (!done) return MSTX_ERR_DEVICE;  // more rounds than the halving bound allows
+  HIP_OK(hipStreamSynchronize(s));  // drains the round enqueued after the last one
+  if (status < 0) return status;
+
   t_last_stats.resize(3 * (size_t)rounds);
+  std::vector<int> chosen(kMaxRounds + 1, -1);
+  std::vector<double> bytes(kMaxRounds + 1, 0.0);
   for (int r = 0; r < rounds; ++r) {
-    t_last_stats[3 * r + 0] = hs->n[r];
-    t_last_stats[3 * r + 1] = hs->live[r];
-    t_last_stats[3 * r + 2] = hs->sel[r];
+    const HostRound& M = dc->host_rounds[r];
+    t_last_stats[3 * r + 0] = nr_of[r];
+    t_last_stats[3 * r + 1] = M.live;
+    t_last_stats[3 * r + 2] = M.sel;
+    chosen[r] = r == 0 ? host_pick_mode(n, S.launched[0]) : host_pick_mode(nr_of[r], S.launched[r]);
+    // algorithmic bytes of this round's scan: the edge stream read once, the
+    // previous label map read once, the minima initialised and written once,
+    // the compacted survivors written once
+    const double nrd = (double)nr_of[r], live_r = (double)M.live;
+    if (r == 0) bytes[r] = 12.0 * (double)m + 16.0 * nrd;
+    else if (r == 1) bytes[r] = 12.0 * (double)m + 4.0 * (double)n + 16.0 * nrd + 16.0 * live_r;
+    else bytes[r] = 16.0 * (double)dc->host_rounds[r - 1].live + 4.0 * (double)nr_of[r - 1] + 16.0 * nrd +
+                    16.0 * live_r;
   }
-  return (n <= 1 || hs->edges_added == (int64_t)n - 1) ? MSTX_OK : MSTX_DISCONNECTED;
+  T.commit(rounds, chosen, bytes);
+  return status;
 }
 
 int select_min_edges(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, const uint32_t* w,
@@ -355,19 +504,37 @@ int select_min_edges(int32_t n, int64_t m, const int32_t* src, const int32_t* ds
   int rc = acquire(dc, lock, L.bytes);
   if (rc != MSTX_OK) return rc;
   void* B = dc->base;
-  auto* part_live = at<uint32_t>(B, L.part_live);
-  auto* st = at<DevState>(B, L.state);
-  auto* best = reinterpret_cast<unsigned long long*>(out_best);
-  HIP_OK(launch_init(0, (uint32_t)m, best, at<int32_t>(B, L.parent), st, 1, s));
-  HIP_OK(launch_fill_u64(best, n, kKeyNone, grid_for(n), s));
+  Solve S{};
+  S.n = n;
+  S.m = m;
+  S.src = src;
+  S.dst = dst;
+  S.w = w;
+  S.s = s;
+  S.dc = dc;
+  S.L = L;
+  S.best = reinterpret_cast<unsigned long long*>(out_best);
+  S.seg_cnt = at<uint32_t>(B, L.seg_cnt);
+  S.rec = at<uint4>(B, L.rec);
+  S.labpool = at<int32_t>(B, L.labpool);
+  S.st = at<DevState>(B, L.state);
+  S.upd_key = L.bucket ? at<unsigned long long>(B, L.upd_key) : nullptr;
+  S.upd_cl = L.bucket ? at<uint16_t>(B, L.upd_cl) : nullptr;
+  S.offT = L.bucket ? at<uint32_t>(B, L.offT) : nullptr;
+  S.slab = L.slab_cap ? at<unsigned long long>(B, L.slab) : nullptr;
+  S.launched.assign(1, 0);
+  t_timer.begin(s);
+  t_timer.on = false;
+  HIP_OK(launch_init(n, S.best, at<int32_t>(B, L.parent), S.st, grid_for(n), s));
   if (m > 0) {
-    const bool lds = n <= kLdsSlots;
-    const int g = lds ? std::min(grid_for(m), 2 * dc->cus) : grid_for(m);
-    HIP_OK(launch_scan_first(lds, src, dst, w, (uint32_t)m, n, best, part_live, st, g, s));
+    hipError_t err = hipSuccess;
+    enqueue_scan(S, 0, 0, n, true, err);
+    HIP_OK(err);
   }
-  HIP_OK(hipMemcpyAsync(dc->host_state, st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+  int32_t err_flag = 0;
+  HIP_OK(hipMemcpyAsync(&err_flag, &S.st->err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
-  return dc->host_state->err ? MSTX_ERR_VERTEX_RANGE : MSTX_OK;
+  return err_flag ? MSTX_ERR_VERTEX_RANGE : MSTX_OK;
 }
 
 }  // namespace

@@ -9,45 +9,117 @@ namespace mstx {
 // No edge: larger than every real key ((w << 32) | e with e <= 0xFFFFFFFE).
 static constexpr unsigned long long kKeyNone = ~0ull;
 
-// Upper bound on rounds recorded: the number of components with an outgoing
-// edge at least halves every round, so ceil(log2 n) + 1 <= 33 for int32 n.
+// Rounds recorded: components with an outgoing edge at least halve every
+// round, so ceil(log2 n) + 1 <= 33 rounds for int32 n.
 static constexpr int kMaxRounds = 40;
+
+// Scan geometry: 1024-thread workgroups, 4 records per thread, one segment of
+// the record stream = one tile = 4096 records.
+static constexpr int kScanBlock = 1024;
+static constexpr int kPerThread = 4;
+static constexpr int kSegCap = kScanBlock * kPerThread;
+
+// Ways of taking the per-component minima in the scan.
+static constexpr int kModeGlobal = 0;  // filtered atomicMin on best[] in HBM
+static constexpr int kModeLds = 1;     // per-workgroup minima in LDS, flushed once
+static constexpr int kModeBucket = 2;  // offers sorted into component buckets + k_bucket_min
+static constexpr int kNumModes = 3;
+
+// LDS: up to 160 KB of dynamic LDS per workgroup (gfx950 has 160 KB per CU).
+static constexpr int kMaxDynLds = 160000;
+static constexpr int32_t kLdsSlots = kMaxDynLds / 8;  // 20000 u64 minima
+// Buckets hold 2^shift components, 64 <= 2^shift <= 16384 (the LDS table of
+// k_bucket_min), at most 1023 buckets (one counter per scan thread + total).
+static constexpr int kMaxBuckets = 1023;
+static constexpr int kMaxBucketShift = 14;
+static constexpr int64_t kBucketMaxComponents = (int64_t)kMaxBuckets << kMaxBucketShift;
+// Bytes of dynamic LDS a BUCKET-mode scan uses: offer staging + counters.
+static constexpr int kBucketScanLds = 2 * kSegCap * (8 + 2) + (kMaxBuckets + 1) * 4;
+
+// Bucket width 2^shift >= ceil(nr / 256) (about 256 buckets, so one
+// k_bucket_min workgroup per CU) and the bucket count.
+__host__ __device__ inline void bucket_geometry(int32_t nr, int* shift, int* nbk) {
+  int s = 6;
+  while (s < kMaxBucketShift && ((int64_t)256 << s) < (int64_t)nr) ++s;
+  *shift = s;
+  *nbk = (int)(((int64_t)nr + (1 << s) - 1) >> s);
+}
 
 // Device-resident round state.  Round r's kernels read n[r] and lab_off[r];
 // the finalize kernel of round r writes n[r+1], lab_off[r+1], live[r], sel[r].
 struct DevState {
-  int32_t n[kMaxRounds + 1];        // components entering round r (isolated ones dropped)
-  int64_t lab_off[kMaxRounds + 1];  // offset of round r's label map in the label pool
-  int64_t live[kMaxRounds];         // edges between different components at round r
-  int64_t sel[kMaxRounds];          // edges added in round r
+  int32_t n[kMaxRounds + 2];        // components entering round r (isolated ones dropped)
+  int64_t lab_off[kMaxRounds + 2];  // offset of round r's label map in the label pool
+  int64_t live[kMaxRounds + 1];     // edges between different components at round r
+  int64_t sel[kMaxRounds + 1];      // edges added in round r
   int64_t edges_added;              // running total of sel[]
   int32_t err;                      // an edge end outside [0, n) was seen
   int32_t err_internal;             // a label lookup gave an impossible value
 };
 
-hipError_t launch_init(int32_t n, uint32_t m, unsigned long long* best, int32_t* parent, DevState* st,
-                       int grid, hipStream_t s);
+// What the finalize kernel of round r writes to pinned host memory.
+struct HostRound {
+  int32_t n_next;
+  int32_t err;
+  int32_t err_internal;
+  int32_t pad;
+  int64_t live;
+  int64_t sel;
+  int64_t edges_added;
+};
+
+// Arguments of the scan kernel (passed by value).
+struct ScanArgs {
+  int round;
+  int launched;  // bit mask of the modes launched for this round
+  const int32_t* src;
+  const int32_t* dst;
+  const uint32_t* w;
+  uint32_t m;
+  int32_t n;
+  const int32_t* labpool;
+  uint4* rec;
+  uint32_t* seg_cnt;
+  int32_t nseg;
+  unsigned long long* best;
+  DevState* st;
+  unsigned long long* upd_key;  // BUCKET mode offers: [nseg][2 * kSegCap]
+  uint16_t* upd_cl;
+  uint32_t* offT;               // [kMaxBuckets + 1][nseg] run starts
+  unsigned long long* slab;     // LDS mode, n_r > kSlabMin: per-workgroup minima [grid][n_r]
+  int64_t slab_cap;             // entries of slab
+};
+
+// LDS-mode minima of more than kSlabMin components are flushed through a
+// per-workgroup slab and a column minimum (k_slab_min) instead of atomics.
+static constexpr int32_t kSlabMin = 512;
+__host__ __device__ inline bool use_slab(const unsigned long long* slab, int64_t cap, int32_t nr, int nwg) {
+  return slab != nullptr && nr > kSlabMin && (int64_t)nwg * nr <= cap;
+}
+
+hipError_t configure_kernels();
+hipError_t launch_init(int32_t n, unsigned long long* best, int32_t* parent, DevState* st, int grid,
+                       hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, int64_t count, unsigned long long v, int grid,
                            hipStream_t s);
-hipError_t launch_scan_first(bool lds, const int32_t* src, const int32_t* dst, const uint32_t* w,
-                             uint32_t m, int32_t n, unsigned long long* best, uint32_t* part_live,
-                             DevState* st, int grid, hipStream_t s);
-hipError_t launch_scan_seg(bool from_input, bool lds, int32_t nr_host, int round, const int32_t* src,
-                           const int32_t* dst, const uint32_t* w, uint32_t m, const int32_t* labpool,
-                           uint4* rec, uint32_t* seg_cnt, uint32_t seg_cap, int32_t nseg,
+hipError_t launch_scan(int mode, int stage, const ScanArgs& a, int grid, size_t lds, hipStream_t s);
+hipError_t launch_bucket_min(int round, int launched, const unsigned long long* upd_key, const uint16_t* upd_cl,
+                             const uint32_t* offT, int32_t nseg, unsigned long long* best, const DevState* st,
+                             int grid, size_t lds, hipStream_t s);
+hipError_t launch_slab_min(int round, int launched, const unsigned long long* slab, int64_t slab_cap, int nwg,
                            unsigned long long* best, const DevState* st, int grid, hipStream_t s);
 hipError_t launch_hook(int round, const int32_t* src, const int32_t* dst, const uint32_t* w,
-                       const unsigned long long* best, int32_t* parent, const int32_t* labpool,
-                       DevState* st, uint8_t* in_mst, uint32_t* part_sel,
-                       unsigned long long* part_w, int grid, hipStream_t s);
+                       const unsigned long long* best, int32_t* parent, const int32_t* labpool, DevState* st,
+                       uint8_t* in_mst, uint32_t* part_sel, unsigned long long* part_w, int grid, hipStream_t s);
 hipError_t launch_compress(int round, int32_t* parent, int32_t* root_of, const unsigned long long* best,
                            unsigned long long* rootmask, int32_t* rootcnt, const DevState* st, int grid,
                            hipStream_t s);
 hipError_t launch_finalize(int round, const int32_t* rootcnt, int32_t* rootpre, const uint32_t* part_live,
                            int32_t nlive, const uint32_t* part_sel, const unsigned long long* part_w,
-                           int32_t nhook, DevState* st, unsigned long long* total, hipStream_t s);
+                           int32_t nhook, DevState* st, unsigned long long* total, HostRound* host,
+                           hipStream_t s);
 hipError_t launch_relabel(int round, const int32_t* root_of, const unsigned long long* rootmask,
-                          const int32_t* rootpre, int32_t* labpool, int32_t* parent,
-                          unsigned long long* best, const DevState* st, int grid, hipStream_t s);
+                          const int32_t* rootpre, int32_t* labpool, int32_t* parent, unsigned long long* best,
+                          const DevState* st, int grid, hipStream_t s);
 
 }  // namespace mstx

@@ -1,35 +1,44 @@
 // mstx_kernels.hip -- device kernels of the parallel Boruvka MST for CDNA4 (gfx950).
 //
 // One Boruvka round (Durbhakula, arXiv 2005.06913, Section 2.1; CAS union of
-// Section 2.2.2) is five kernels, each a global barrier for the next:
+// Section 2.2.2) is a short chain of kernels, each a global barrier for the
+// next:
 //
 //   scan      every live edge: labels of both ends at this round; drop it if
-//             internal (the paper's "covered" edge); otherwise lower the
-//             per-component minimum key of both ends.  The key packs
-//             (w << 32) | e, so the order is strict and ties cannot occur.
-//             Rounds >= 1 also compact the survivors in place.
-//   hook      every component with a minimum: unite its root with the root of
-//             the other end's component by compare-and-swap of the larger
-//             root's parent to the smaller root; the winner marks the edge.
+//             internal (the paper's "covered" edge); otherwise offer the
+//             packed key (w << 32) | e to the minima of both components --
+//             the order is strict, so ties cannot occur.  From round 1 on
+//             the survivors are also compacted in place.  Three ways to
+//             take the minima, chosen per round on the device from the
+//             actual component count n_r:
+//               LDS     n_r fits one workgroup's LDS: per-workgroup minima
+//                       with ds_min_u64, flushed once to HBM;
+//               BUCKET  components are split into <= 1024 contiguous
+//                       buckets; the scan counting-sorts its (component,
+//                       key) offers by bucket in LDS and writes them out;
+//                       k_bucket_min (one workgroup per bucket) takes the
+//                       minima in LDS and writes best[] -- no global atomics;
+//               GLOBAL  filtered 64-bit atomicMin on best[] (very large n_r).
+//   hook      every component with a minimum: CAS the larger root's parent
+//             to the smaller root; the winner marks the edge.
 //   compress  pointer jumping: every component finds its root; a wave ballot
-//             records which components are roots of non-isolated trees.
+//             records which roots still have an outgoing edge.
 //   finalize  one workgroup: exclusive scan of the root counts (dense new
-//             labels), per-round totals (live edges, edges added, weight).
+//             labels), per-round totals, a small record for the host.
 //   relabel   old label -> new label map; reset parent[] and the minima.
 //
-// Layout: vertex state is structure-of-arrays in HBM (best[] u64, parent[],
-// root_of[] i32, one label map per round in a pool).  The edge stream of
+// Layout: vertex state is structure-of-arrays in HBM.  The edge stream of
 // round 0 is the caller's src/dst/w arrays; from round 1 on it is a record
-// stream {a, b, w, e} (16 B, one dwordx4 per edge) split into fixed segments,
-// one per workgroup, compacted in place each round.
+// stream {a, b, w, e} (16 B, one dwordx4) cut into fixed segments of 4096
+// records, one segment per workgroup iteration, compacted in place.
 //
-// Atomics: device-scope 64-bit atomics on gfx950 execute at the memory side,
-// so every global atomicMin is preceded by a plain load that skips it when
-// the stored key is already smaller (values only decrease, so a stale load is
-// only ever too large and never skips a needed update).  When the current
-// component count fits in LDS, minima are kept per workgroup in LDS and
-// flushed once.  No kernel uses same-address global atomics: per-block
-// partial sums go to arrays that the single-workgroup finalize reduces.
+// Device-scope 64-bit atomics on gfx950 execute at the memory side (~27
+// Gop/s whatever the table size) and same-address atomics serialise, so the
+// hot paths avoid them: minima live in LDS, per-block partial sums go to
+// arrays reduced by the single-workgroup finalize.
+//
+// Every kernel of round r returns at once when n_r <= 1: the host enqueues
+// round r+1 before it has seen the result of round r.
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -38,24 +47,48 @@
 
 namespace mstx {
 
-static constexpr int kBlock = 256;    // threads per workgroup for the streaming kernels
-static constexpr int kPerThread = 4;  // records per thread per tile in the segmented scan
-static constexpr int kTile = kBlock * kPerThread;
-static constexpr int kWaves = kBlock / 64;
+static constexpr int kBlock = 256;  // threads per workgroup, vertex-parallel kernels
+static constexpr int kScanWaves = kScanBlock / 64;
 
 // ------------------------------------------------------------------ helpers
+
+// Streaming accesses (read or written once per round) carry the non-temporal
+// hint so they do not evict the label maps and minima that the gathers reuse.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+__device__ __forceinline__ T ld_stream(const T* p) {
+  return __builtin_nontemporal_load(p);
+}
+template <typename T>
+__device__ __forceinline__ void st_stream(T v, T* p) {
+  __builtin_nontemporal_store(v, p);
+}
+__device__ __forceinline__ uint4 ld_rec(const uint4* p) {
+  const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p));
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void st_rec(const uint4& r, uint4* p) {
+  u32x4 v;
+  v.x = r.x;
+  v.y = r.y;
+  v.z = r.z;
+  v.w = r.w;
+  __builtin_nontemporal_store(v, reinterpret_cast<u32x4*>(p));
+}
 
 __device__ __forceinline__ uint64_t make_key(uint32_t w, uint32_t e) {
   return ((uint64_t)w << 32) | (uint64_t)e;
 }
 
-// Lower best[c] to key; the plain load filters the memory-side atomic.
-__device__ __forceinline__ void lower_global(unsigned long long* best, int32_t c, uint64_t key) {
+// Lower best[c] to key; the plain load filters the memory-side atomic.  Keys
+// only decrease, so a stale load is too large and never skips a needed update.
+__device__ __forceinline__ void lower_global(unsigned long long* best, int64_t c, uint64_t key) {
   if (key < best[c]) atomicMin(best + c, (unsigned long long)key);
 }
 
-__device__ __forceinline__ void lower_lds(unsigned long long* lbest, int32_t c, uint64_t key) {
-  if (key < lbest[c]) atomicMin(lbest + c, (unsigned long long)key);
+__device__ __forceinline__ void lower_lds(unsigned long long* t, int32_t c, uint64_t key) {
+  if (key < t[c]) atomicMin(t + c, (unsigned long long)key);
 }
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
@@ -71,31 +104,31 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
-// Sum over a 256-thread block; result valid in every thread.
-template <typename T>
-__device__ __forceinline__ T block_sum(T v, T* scratch /* [kWaves] */) {
+// Sum over the block (NW waves); result valid in every thread.
+template <int NW, typename T>
+__device__ __forceinline__ T block_sum(T v, T* scratch /* [NW] */) {
   v = wave_sum(v);
   __syncthreads();
   if (lane_id() == 0) scratch[threadIdx.x >> 6] = v;
   __syncthreads();
   T s = 0;
 #pragma unroll
-  for (int i = 0; i < kWaves; ++i) s += scratch[i];
+  for (int i = 0; i < NW; ++i) s += scratch[i];
   return s;
 }
 
-__device__ __forceinline__ int32_t ld_agent(const int32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_agent(int32_t* p, int32_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Mode that handles n_r among the launched ones (bit i of `launched` = mode i).
+__device__ __forceinline__ int pick_mode(int32_t nr, int launched) {
+  if ((launched & (1 << kModeLds)) && nr <= kLdsSlots) return kModeLds;
+  if ((launched & (1 << kModeBucket)) && (int64_t)nr <= kBucketMaxComponents) return kModeBucket;
+  return kModeGlobal;
 }
 
 // --------------------------------------------------------------------- init
 
-// best[0..n) <- none, parent[c] <- c, state counters for round 0.
-__global__ void __launch_bounds__(kBlock) k_init(int32_t n, uint32_t m, unsigned long long* best,
-                                                 int32_t* parent, DevState* st) {
+// best[0..n) <- none, parent[c] <- c, state for round 0.
+__global__ void __launch_bounds__(kBlock) k_init(int32_t n, unsigned long long* best, int32_t* parent,
+                                                 DevState* st) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += stride) {
     best[c] = kKeyNone;
@@ -107,7 +140,6 @@ __global__ void __launch_bounds__(kBlock) k_init(int32_t n, uint32_t m, unsigned
     st->err = 0;
     st->err_internal = 0;
     st->edges_added = 0;
-    (void)m;
   }
 }
 
@@ -116,201 +148,357 @@ __global__ void __launch_bounds__(kBlock) k_fill_u64(unsigned long long* p, int6
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = v;
 }
 
-// ---------------------------------------------------------- round 0: scan
+// --------------------------------------------------------------------- scan
 
-// Edge loop of round 0 over the caller's arrays.  Labels are the vertex ids.
-// Out-of-range ids set st->err and the edge is skipped.  part_live[block] =
-// number of non-loop in-range edges this block saw.
-template <bool kLds>
-__global__ void __launch_bounds__(kBlock) k_scan_first(const int32_t* __restrict__ src,
-                                                       const int32_t* __restrict__ dst,
-                                                       const uint32_t* __restrict__ w, uint32_t m,
-                                                       int32_t n, unsigned long long* __restrict__ best,
-                                                       uint32_t* __restrict__ part_live,
-                                                       DevState* __restrict__ st) {
-  extern __shared__ unsigned long long lbest[];  // n entries when kLds
-  __shared__ uint32_t red[kWaves];
-  if (kLds) {
-    for (int32_t c = threadIdx.x; c < n; c += kBlock) lbest[c] = kKeyNone;
-    __syncthreads();
-  }
-  uint32_t live = 0;
-  bool bad = false;
-  const uint32_t stride = gridDim.x * kBlock;
-  for (uint32_t e = blockIdx.x * kBlock + threadIdx.x; e < m; e += stride) {
-    const int32_t a = src[e];
-    const int32_t b = dst[e];
-    const uint32_t we = w[e];
-    if ((uint32_t)a >= (uint32_t)n || (uint32_t)b >= (uint32_t)n) {
-      bad = true;
-      continue;
-    }
-    if (a == b) continue;
-    ++live;
-    const uint64_t key = make_key(we, e);
-    if (kLds) {
-      lower_lds(lbest, a, key);
-      lower_lds(lbest, b, key);
-    } else {
-      lower_global(best, a, key);
-      lower_global(best, b, key);
-    }
-  }
-  if (bad) st->err = 1;
-  if (kLds) {
-    __syncthreads();
-    for (int32_t c = threadIdx.x; c < n; c += kBlock) {
-      const unsigned long long v = lbest[c];
-      if (v != kKeyNone) lower_global(best, c, v);
-    }
-  }
-  live = block_sum(live, red);
-  if (threadIdx.x == 0) part_live[blockIdx.x] = live;
-}
+// One kernel for every round and mode.
+//   kFromInput && !kCompact : round 0, the caller's edges, labels = vertex ids,
+//                             ids checked against [0, n) (st->err on failure)
+//   kFromInput &&  kCompact : round 1, the caller's edges, labels lab_0[id]
+//   !kFromInput             : rounds >= 2, the record stream, labels lab_{r-1}
+// kMode is the way minima are taken (LDS / BUCKET / GLOBAL); a launch whose
+// mode is not the one pick_mode() selects for the actual n_r returns.
+// Dynamic LDS: LDS mode n_r (<= launch capacity) u64 minima; BUCKET mode the
+// 2 * kSegCap offer staging and the (bucket count + 1) counters.
+template <int kMode, bool kFromInput, bool kCompact>
+__global__ void __launch_bounds__(kScanBlock) k_scan(ScanArgs A) {
+  extern __shared__ unsigned long long smem[];
+  __shared__ uint32_t wave_tot[kScanWaves];
+  __shared__ uint32_t red[kScanWaves];
+  const int32_t nr = A.st->n[A.round];
+  if (nr <= 1 && A.round > 0) return;
+  // a round enqueued before the host saw an input error in round 0 does nothing
+  if (A.round > 0 && A.st->err) return;
+  if (pick_mode(nr, A.launched) != kMode) return;
+  const int32_t* __restrict__ lab = kCompact ? A.labpool + A.st->lab_off[A.round - 1] : nullptr;
 
-// ------------------------------------------------- rounds >= 1: scan+compact
-
-// Segment s holds records [s*seg_cap, s*seg_cap + seg_cnt[s]) of the record
-// stream.  In round 1 (kFromInput) segment s is instead the caller's edges
-// [s*seg_cap, min((s+1)*seg_cap, m)) with labels lab[src], lab[dst].  Every
-// surviving edge (ends in different components) lowers the minima of both
-// components and is written back compacted to the front of its segment.
-// Reads of a tile complete before the barrier that precedes its writes, and
-// writes never pass the tile being read, so compaction in place is safe.
-template <bool kFromInput, bool kLds>
-__global__ void __launch_bounds__(kBlock) k_scan_seg(
-    int round, const int32_t* __restrict__ src, const int32_t* __restrict__ dst,
-    const uint32_t* __restrict__ w, uint32_t m, const int32_t* __restrict__ labpool, uint4* rec,
-    uint32_t* __restrict__ seg_cnt, uint32_t seg_cap, int32_t nseg,
-    unsigned long long* __restrict__ best, const DevState* __restrict__ st) {
-  extern __shared__ unsigned long long lbest[];  // nr entries when kLds
-  __shared__ uint32_t wave_tot[2][kWaves];
-  const int32_t nr = st->n[round];
-  const int32_t* __restrict__ lab = labpool + st->lab_off[round - 1];  // labels of round r-1 -> r
-  if (kLds) {
-    for (int32_t c = threadIdx.x; c < nr; c += kBlock) lbest[c] = kKeyNone;
+  unsigned long long* lbest = smem;  // LDS mode
+  // BUCKET mode: geometry derived from n_r exactly as k_bucket_min does
+  int shift = 0, nbk = 0;
+  uint32_t* bcnt = nullptr;
+  unsigned long long* skey = nullptr;
+  uint16_t* scl = nullptr;
+  if (kMode == kModeBucket) {
+    bucket_geometry(nr, &shift, &nbk);
+    skey = smem;                                            // [2 * kSegCap]
+    scl = reinterpret_cast<uint16_t*>(skey + 2 * kSegCap);  // [2 * kSegCap]
+    bcnt = reinterpret_cast<uint32_t*>(scl + 2 * kSegCap);  // [nbk + 1]
+  }
+  if (kMode == kModeLds) {
+    for (int32_t c = threadIdx.x; c < nr; c += kScanBlock) lbest[c] = kKeyNone;
     __syncthreads();
   }
   const int wave = threadIdx.x >> 6;
   const uint64_t lt = lanemask_lt();
-  int parity = 0;
-  for (int32_t s = blockIdx.x; s < nseg; s += gridDim.x) {
-    const uint64_t base = (uint64_t)s * seg_cap;
+  bool bad = false;
+
+  for (int32_t s = blockIdx.x; s < A.nseg; s += gridDim.x) {
+    const uint64_t base = (uint64_t)s * kSegCap;
     uint32_t count;
     if (kFromInput) {
-      count = base >= m ? 0u : (uint32_t)min((uint64_t)seg_cap, (uint64_t)m - base);
+      count = base >= A.m ? 0u : (uint32_t)min((uint64_t)kSegCap, (uint64_t)A.m - base);
     } else {
-      count = seg_cnt[s];
+      count = A.seg_cnt[s];
     }
-    uint32_t wpos = 0;
-    for (uint32_t t = 0; t < count; t += kTile) {
-      uint4 r[kPerThread];
-      bool live[kPerThread];
+    if (kMode == kModeBucket) {
+      for (int i = threadIdx.x; i <= nbk; i += kScanBlock) bcnt[i] = 0;
+      __syncthreads();
+    }
+    uint4 r[kPerThread];
+    bool live[kPerThread];
 #pragma unroll
-      for (int k = 0; k < kPerThread; ++k) {
-        const uint32_t j = t + k * kBlock + threadIdx.x;
-        live[k] = false;
-        if (j < count) {
-          int32_t a, b;
-          uint32_t we, e;
-          if (kFromInput) {
-            e = (uint32_t)(base + j);
-            a = lab[src[e]];
-            b = lab[dst[e]];
-            we = w[e];
-          } else {
-            const uint4 x = rec[base + j];
-            a = lab[(int32_t)x.x];
-            b = lab[(int32_t)x.y];
-            we = x.z;
-            e = x.w;
-          }
-          r[k] = make_uint4((uint32_t)a, (uint32_t)b, we, e);
-          // a live record never touches an isolated (label -1) component
-          live[k] = (a != b) && ((a | b) >= 0);
-          if (live[k]) {
-            const uint64_t key = make_key(we, e);
-            if (kLds) {
-              lower_lds(lbest, a, key);
-              lower_lds(lbest, b, key);
-            } else {
-              lower_global(best, a, key);
-              lower_global(best, b, key);
+    for (int k = 0; k < kPerThread; ++k) {
+      const uint32_t j = k * kScanBlock + threadIdx.x;
+      live[k] = false;
+      r[k] = make_uint4(0, 0, 0, 0);
+      if (j < count) {
+        int32_t a, b;
+        uint32_t we, e;
+        if (kFromInput) {
+          e = (uint32_t)(base + j);
+          a = ld_stream(A.src + e);
+          b = ld_stream(A.dst + e);
+          we = ld_stream(A.w + e);
+          if (!kCompact) {
+            if ((uint32_t)a >= (uint32_t)A.n || (uint32_t)b >= (uint32_t)A.n) {
+              bad = true;
+              a = b = -1;  // dropped
             }
+          } else {
+            a = lab[a];
+            b = lab[b];
+          }
+        } else {
+          const uint4 x = ld_rec(A.rec + base + j);
+          a = lab[(int32_t)x.x];
+          b = lab[(int32_t)x.y];
+          we = x.z;
+          e = x.w;
+        }
+        r[k] = make_uint4((uint32_t)a, (uint32_t)b, we, e);
+        // a live edge never touches an isolated (label -1) component
+        live[k] = (a != b) && ((a | b) >= 0);
+        if (live[k]) {
+          const uint64_t key = make_key(we, e);
+          if (kMode == kModeLds) {
+            lower_lds(lbest, a, key);
+            lower_lds(lbest, b, key);
+          } else if (kMode == kModeGlobal) {
+            lower_global(A.best, a, key);
+            lower_global(A.best, b, key);
           }
         }
       }
-      // wave-level compaction offsets, slot-major within the wave
-      uint32_t my_off[kPerThread];
-      uint32_t run = 0;
-#pragma unroll
-      for (int k = 0; k < kPerThread; ++k) {
-        const uint64_t mask = __ballot(live[k]);
-        my_off[k] = run + (uint32_t)__popcll(mask & lt);
-        run += (uint32_t)__popcll(mask);
-      }
-      if (lane_id() == 0) wave_tot[parity][wave] = run;
-      __syncthreads();  // all reads of this tile are done past this point
-      uint32_t wave_off = 0, tile_tot = 0;
-#pragma unroll
-      for (int i = 0; i < kWaves; ++i) {
-        const uint32_t v = wave_tot[parity][i];
-        wave_off += (i < wave) ? v : 0u;
-        tile_tot += v;
-      }
-#pragma unroll
-      for (int k = 0; k < kPerThread; ++k) {
-        if (live[k]) rec[base + wpos + wave_off + my_off[k]] = r[k];
-      }
-      wpos += tile_tot;
-      parity ^= 1;
     }
-    if (threadIdx.x == 0) seg_cnt[s] = wpos;
+
+    // survivors of this segment: wave-level offsets (slot-major inside a wave)
+    uint32_t my_off[kPerThread];
+    uint32_t run = 0;
+#pragma unroll
+    for (int k = 0; k < kPerThread; ++k) {
+      const uint64_t mask = __ballot(live[k]);
+      my_off[k] = run + (uint32_t)__popcll(mask & lt);
+      run += (uint32_t)__popcll(mask);
+    }
+    if (lane_id() == 0) wave_tot[wave] = run;
+
+    // BUCKET mode: claim a slot in the offer staging for both ends
+    uint32_t slot_a[kPerThread], slot_b[kPerThread];
+    if (kMode == kModeBucket) {
+#pragma unroll
+      for (int k = 0; k < kPerThread; ++k) {
+        slot_a[k] = slot_b[k] = 0;
+        if (live[k]) {
+          slot_a[k] = atomicAdd(&bcnt[(int32_t)r[k].x >> shift], 1u);
+          slot_b[k] = atomicAdd(&bcnt[(int32_t)r[k].y >> shift], 1u);
+        }
+      }
+    }
+    __syncthreads();  // all reads of this segment are done past this point
+
+    uint32_t wave_off = 0, seg_tot = 0;
+#pragma unroll
+    for (int i = 0; i < kScanWaves; ++i) {
+      const uint32_t v = wave_tot[i];
+      wave_off += (i < wave) ? v : 0u;
+      seg_tot += v;
+    }
+    if (kCompact) {
+#pragma unroll
+      for (int k = 0; k < kPerThread; ++k) {
+        if (live[k]) st_rec(r[k], A.rec + base + wave_off + my_off[k]);
+      }
+    }
+    if (threadIdx.x == 0) A.seg_cnt[s] = seg_tot;
+
+    if (kMode == kModeBucket) {
+      // exclusive scan of the bucket counters (nbk + 1 <= kScanBlock)
+      const uint32_t v = (int)threadIdx.x < nbk ? bcnt[threadIdx.x] : 0u;
+      uint32_t x = v;
+      for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off, 64);
+        if (lane_id() >= off) x += y;
+      }
+      if (lane_id() == 63) red[wave] = x;
+      __syncthreads();
+      uint32_t wbase = 0;
+      for (int i = 0; i < wave; ++i) wbase += red[i];
+      const uint32_t excl = wbase + x - v;
+      __syncthreads();  // every thread has read its counter
+      if ((int)threadIdx.x <= nbk) {
+        bcnt[threadIdx.x] = excl;  // for threadIdx == nbk this is the total
+        A.offT[(int64_t)threadIdx.x * A.nseg + s] = excl;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < kPerThread; ++k) {
+        if (live[k]) {
+          const uint64_t key = make_key(r[k].z, r[k].w);
+          const int32_t a = (int32_t)r[k].x, b = (int32_t)r[k].y;
+          const uint32_t pa = bcnt[a >> shift] + slot_a[k];
+          const uint32_t pb = bcnt[b >> shift] + slot_b[k];
+          skey[pa] = key;
+          scl[pa] = (uint16_t)(a & ((1 << shift) - 1));
+          skey[pb] = key;
+          scl[pb] = (uint16_t)(b & ((1 << shift) - 1));
+        }
+      }
+      __syncthreads();
+      const uint32_t total = 2 * seg_tot;
+      const uint64_t obase = (uint64_t)s * (2 * kSegCap);
+      for (uint32_t i = threadIdx.x; i < total; i += kScanBlock) {
+        st_stream(skey[i], A.upd_key + obase + i);
+        st_stream(scl[i], A.upd_cl + obase + i);
+      }
+    }
+    __syncthreads();  // LDS (wave_tot, counters, staging) is reused by the next segment
   }
-  if (kLds) {
+  if (!kCompact && bad) A.st->err = 1;
+  if (kMode == kModeLds) {
     __syncthreads();
-    for (int32_t c = threadIdx.x; c < nr; c += kBlock) {
-      const unsigned long long v = lbest[c];
-      if (v != kKeyNone) lower_global(best, c, v);
+    if (use_slab(A.slab, A.slab_cap, nr, gridDim.x)) {
+      // coalesced copy of this workgroup's minima; k_slab_min takes the column minima
+      unsigned long long* row = A.slab + (int64_t)blockIdx.x * nr;
+      for (int32_t c = threadIdx.x; c < nr; c += kScanBlock) row[c] = lbest[c];
+    } else {
+      for (int32_t c = threadIdx.x; c < nr; c += kScanBlock) {
+        const unsigned long long v = lbest[c];
+        if (v != kKeyNone) lower_global(A.best, c, v);
+      }
     }
+  }
+}
+
+// best[c] = min over the nwg workgroup rows of the slab (LDS mode with more
+// than kSlabMin components; the scan that wrote the slab had nwg workgroups).
+// Block (x, y): components x*256.., rows y*kSlabRowsPerBlock..; each partial
+// minimum is merged with a filtered atomicMin (best[] was reset to "none").
+static constexpr int kSlabRowsPerBlock = 32;
+__global__ void __launch_bounds__(kBlock) k_slab_min(int round, int launched,
+                                                     const unsigned long long* __restrict__ slab,
+                                                     int64_t slab_cap, int nwg,
+                                                     unsigned long long* __restrict__ best,
+                                                     const DevState* __restrict__ st) {
+  const int32_t nr = st->n[round];
+  if (nr <= 1 && round > 0) return;
+  if (round > 0 && st->err) return;
+  if (pick_mode(nr, launched) != kModeLds || !use_slab(slab, slab_cap, nr, nwg)) return;
+  const int b0 = blockIdx.y * kSlabRowsPerBlock;
+  const int b1 = min(nwg, b0 + kSlabRowsPerBlock);
+  for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < nr; c += (int64_t)gridDim.x * kBlock) {
+    unsigned long long v = kKeyNone;
+    int b = b0;
+    for (; b + 8 <= b1; b += 8) {
+      unsigned long long x[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) x[u] = slab[(int64_t)(b + u) * nr + c];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v = min(v, x[u]);
+    }
+    for (; b < b1; ++b) v = min(v, slab[(int64_t)b * nr + c]);
+    if (v != kKeyNone) lower_global(best, c, v);
+  }
+}
+
+// One workgroup per bucket p: the minimum offer for every component of the
+// bucket, over the runs [offT[p][s], offT[p+1][s]) of every segment s, taken
+// in LDS and written to best[] (every entry of the bucket, "none" included).
+// Runs are short (about 2 * kSegCap / buckets offers), so each half-wave
+// reads kRunsInFlight runs at once, each with coalesced loads; the run bounds
+// of a chunk of segments are staged in LDS first.
+static constexpr int kChunkRuns = 2048;
+static constexpr int kRunsInFlight = 8;
+static constexpr size_t kBucketMinExtraLds = 2 * kChunkRuns * sizeof(uint32_t);
+
+__global__ void __launch_bounds__(kScanBlock) k_bucket_min(int round, int launched,
+                                                           const unsigned long long* __restrict__ upd_key,
+                                                           const uint16_t* __restrict__ upd_cl,
+                                                           const uint32_t* __restrict__ offT, int32_t nseg,
+                                                           unsigned long long* __restrict__ best,
+                                                           const DevState* __restrict__ st) {
+  extern __shared__ unsigned long long table[];  // [B] minima, then the run bounds
+  const int32_t nr = st->n[round];
+  if (nr <= 1 && round > 0) return;
+  if (round > 0 && st->err) return;  // the scan of this round did nothing either
+  if (pick_mode(nr, launched) != kModeBucket) return;
+  int shift, nbk;
+  bucket_geometry(nr, &shift, &nbk);
+  const int p = blockIdx.x;
+  if (p >= nbk) return;
+  const int B = 1 << shift;
+  uint32_t* run_lo = reinterpret_cast<uint32_t*>(table + B);
+  uint32_t* run_hi = run_lo + kChunkRuns;
+  for (int i = threadIdx.x; i < B; i += kScanBlock) table[i] = kKeyNone;
+  const uint32_t* lo_row = offT + (int64_t)p * nseg;
+  const uint32_t* hi_row = offT + (int64_t)(p + 1) * nseg;
+  const int half = threadIdx.x >> 5;  // 0 .. 2 * kScanWaves - 1
+  const int hl = threadIdx.x & 31;
+  constexpr int kHalves = 2 * kScanWaves;
+  for (int32_t c0 = 0; c0 < nseg; c0 += kChunkRuns) {
+    const int nrun = min(kChunkRuns, nseg - c0);
+    __syncthreads();  // table initialised / previous chunk's bounds consumed
+    for (int i = threadIdx.x; i < nrun; i += kScanBlock) {
+      run_lo[i] = lo_row[c0 + i];
+      run_hi[i] = hi_row[c0 + i];
+    }
+    __syncthreads();
+    for (int j0 = half * kRunsInFlight; j0 < nrun; j0 += kHalves * kRunsInFlight) {
+      uint32_t lo[kRunsInFlight], len[kRunsInFlight];
+      uint32_t maxlen = 0;
+#pragma unroll
+      for (int q = 0; q < kRunsInFlight; ++q) {
+        lo[q] = 0;
+        len[q] = 0;
+        if (j0 + q < nrun) {
+          lo[q] = run_lo[j0 + q];
+          len[q] = run_hi[j0 + q] - lo[q];
+        }
+        maxlen = max(maxlen, len[q]);
+      }
+      for (uint32_t i = hl; i < maxlen; i += 32) {
+        unsigned long long k[kRunsInFlight];
+        int c[kRunsInFlight];
+#pragma unroll
+        for (int q = 0; q < kRunsInFlight; ++q) {
+          k[q] = kKeyNone;
+          c[q] = 0;
+          if (i < len[q]) {
+            const uint64_t at = (uint64_t)(c0 + j0 + q) * (2 * kSegCap) + lo[q] + i;
+            k[q] = ld_stream(upd_key + at);
+            c[q] = ld_stream(upd_cl + at);
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < kRunsInFlight; ++q) {
+          if (k[q] != kKeyNone) lower_lds(table, c[q], k[q]);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  const int64_t base = (int64_t)p << shift;
+  for (int i = threadIdx.x; i < B; i += kScanBlock) {
+    if (base + i < nr) best[base + i] = table[i];
   }
 }
 
 // -------------------------------------------------------------------- hook
 
-// Root of x with path halving.  Loads and stores are agent-scope atomics so a
-// root changed by another workgroup's CAS is seen.  Every halving store
-// writes an ancestor, and only to a non-root, so it never undoes a union.
-__device__ __forceinline__ int32_t hook_find(int32_t* parent, int32_t x) {
-  while (true) {
-    const int32_t p = ld_agent(parent + x);
-    if (p == x) return x;
-    const int32_t gp = ld_agent(parent + p);
+// Root of x by plain loads (values may be stale, but every value ever stored
+// in parent[] is an ancestor, so the walk ends at a node that was a root;
+// the caller's CAS checks that it still is).  Path halving with plain
+// stores: only non-roots are written, always with an ancestor.
+__device__ __forceinline__ int32_t walk_root(int32_t* parent, int32_t x) {
+  int32_t p = parent[x];
+  while (p != x) {
+    const int32_t gp = parent[p];
     if (gp == p) return p;
-    st_agent(parent + x, gp);
+    parent[x] = gp;
     x = gp;
+    p = parent[x];
   }
+  return x;
 }
 
 // For each component c with a minimum edge e = low32(best[c]): d = the other
-// end's component (the labels of e's original ends are followed through the
-// label maps of earlier rounds).  If c and d chose each other (same key) only
-// the smaller id acts.  Then: repeat { rc = root(c), rd = root(d); stop if
-// equal; CAS parent[max] from max to min }.  Parents always point to smaller
-// ids, so the forest never gets a cycle; the thread whose CAS succeeds marks
-// e and counts its weight.
+// end's component (the ends' labels are followed through the label maps of
+// the earlier rounds).  If c and d chose each other only the smaller id acts,
+// so every distinct selected edge has one owner thread.  Then: repeat
+// { x = root(c), y = root(d); CAS parent[max] from max to min }.  Parents
+// always point to smaller ids, so the forest never gets a cycle.  When the
+// CAS fails, the value it returns (a fresh, strictly smaller ancestor) is
+// where that side's walk resumes, so stale loads cannot make the loop spin.
 __global__ void __launch_bounds__(kBlock) k_hook(int round, const int32_t* __restrict__ src,
                                                  const int32_t* __restrict__ dst,
                                                  const uint32_t* __restrict__ w,
                                                  const unsigned long long* __restrict__ best,
                                                  int32_t* parent, const int32_t* __restrict__ labpool,
-                                                 DevState* __restrict__ st,
-                                                 uint8_t* __restrict__ in_mst,
+                                                 DevState* __restrict__ st, uint8_t* __restrict__ in_mst,
                                                  uint32_t* __restrict__ part_sel,
                                                  unsigned long long* __restrict__ part_w) {
-  __shared__ uint32_t red32[kWaves];
-  __shared__ unsigned long long red64[kWaves];
+  __shared__ uint32_t red32[kBlock / 64];
+  __shared__ unsigned long long red64[kBlock / 64];
   const int32_t nr = st->n[round];
+  if (nr <= 1 && round > 0) return;
   uint32_t sel = 0;
   unsigned long long wsum = 0;
   const int64_t stride = (int64_t)gridDim.x * kBlock;
@@ -332,25 +520,26 @@ __global__ void __launch_bounds__(kBlock) k_hook(int round, const int32_t* __res
       continue;
     }
     if (d < c && best[d] == key) continue;  // mutual choice: d hooks it
-    int32_t rc = c, rd = d;
+    int32_t x = c, y = d;
     while (true) {
-      rc = hook_find(parent, rc);
-      rd = hook_find(parent, rd);
-      if (rc == rd) break;
-      const int32_t hi = rc > rd ? rc : rd;
-      const int32_t lo = rc > rd ? rd : rc;
-      int32_t expect = hi;
-      if (__hip_atomic_compare_exchange_strong(parent + hi, &expect, lo, __ATOMIC_RELAXED,
-                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+      const int32_t rx = walk_root(parent, x);
+      const int32_t ry = walk_root(parent, y);
+      if (rx == ry) break;
+      const int32_t hi = rx > ry ? rx : ry;
+      const int32_t lo = rx > ry ? ry : rx;
+      const int32_t old = atomicCAS(parent + hi, hi, lo);
+      if (old == hi) {
         in_mst[e] = 1;
         ++sel;
         wsum += w[e];
         break;
       }
+      if (hi == rx) x = old;
+      else y = old;
     }
   }
-  sel = block_sum(sel, red32);
-  wsum = block_sum(wsum, red64);
+  sel = block_sum<kBlock / 64>(sel, red32);
+  wsum = block_sum<kBlock / 64>(wsum, red64);
   if (threadIdx.x == 0) {
     part_sel[blockIdx.x] = sel;
     part_w[blockIdx.x] = wsum;
@@ -359,12 +548,11 @@ __global__ void __launch_bounds__(kBlock) k_hook(int round, const int32_t* __res
 
 // ---------------------------------------------------------------- compress
 
-// root_of[c] = root of c (path halving with plain accesses: parent[] only
-// changes by halving here, and every value written is an ancestor).  One wave
-// handles 64 consecutive components; its ballot of "root with an outgoing
-// edge" becomes rootmask[c / 64], its popcount rootcnt[c / 64].  A root
-// without a minimum edge is an isolated component: it is final and gets no
-// new label.
+// root_of[c] = root of c (path halving with plain accesses; every value
+// written is an ancestor).  One wave handles 64 consecutive components; its
+// ballot of "root with an outgoing edge" is rootmask[c / 64], its popcount
+// rootcnt[c / 64].  A root without a minimum edge is an isolated component:
+// it is final and gets no new label.
 __global__ void __launch_bounds__(kBlock) k_compress(int round, int32_t* parent,
                                                      int32_t* __restrict__ root_of,
                                                      const unsigned long long* __restrict__ best,
@@ -372,26 +560,16 @@ __global__ void __launch_bounds__(kBlock) k_compress(int round, int32_t* parent,
                                                      int32_t* __restrict__ rootcnt,
                                                      const DevState* __restrict__ st) {
   const int32_t nr = st->n[round];
+  if (nr <= 1 && round > 0) return;
   const int64_t stride = (int64_t)gridDim.x * kBlock;
   for (int64_t base = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63); base < nr; base += stride) {
     const int64_t ci = base + lane_id();
     bool keep = false;
     if (ci < nr) {
       const int32_t c = (int32_t)ci;
-      int32_t cur = c;
-      int32_t p = parent[cur];
-      while (p != cur) {
-        const int32_t gp = parent[p];
-        if (gp == p) {
-          cur = p;
-          break;
-        }
-        parent[cur] = gp;
-        cur = gp;
-        p = parent[cur];
-      }
-      root_of[c] = cur;
-      keep = (cur == c) && (best[c] != kKeyNone);
+      const int32_t root = walk_root(parent, c);
+      root_of[c] = root;
+      keep = (root == c) && (best[c] != kKeyNone);
     }
     const uint64_t mask = __ballot(keep);
     if (lane_id() == 0) {
@@ -404,45 +582,76 @@ __global__ void __launch_bounds__(kBlock) k_compress(int round, int32_t* parent,
 // ---------------------------------------------------------------- finalize
 
 // One workgroup of 1024 threads.  Exclusive scan of rootcnt[0..W) into
-// rootpre, W = ceil(n_r / 64); n_{r+1} = total.  Reduces the per-block
-// partials of this round: live edges (part_live[0..nlive)), edges added and
-// their weight (part_sel / part_w [0..nhook)); adds the weight to *total.
+// rootpre, W = ceil(n_r / 64); n_{r+1} = total.  Reduces this round's
+// per-block partials: live edges (part_live[0..nlive)), edges added and
+// their weight (part_sel / part_w [0..nhook)); adds the weight to *total;
+// writes the round's record for the host (pinned host memory).
 __global__ void __launch_bounds__(1024) k_finalize(int round, const int32_t* __restrict__ rootcnt,
                                                    int32_t* __restrict__ rootpre,
                                                    const uint32_t* __restrict__ part_live, int32_t nlive,
                                                    const uint32_t* __restrict__ part_sel,
                                                    const unsigned long long* __restrict__ part_w,
                                                    int32_t nhook, DevState* st,
-                                                   unsigned long long* total) {
-  __shared__ int64_t sh[1024 / 64];
-  __shared__ unsigned long long shw[1024 / 64];
+                                                   unsigned long long* total, HostRound* host) {
+  __shared__ int64_t sh[16];
+  __shared__ unsigned long long shw[16];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   const int32_t nr = st->n[round];
+  if (nr <= 1 && round > 0) {
+    if (tid == 0) {
+      st->n[round + 1] = 0;
+      st->lab_off[round + 1] = st->lab_off[round];
+      HostRound h{0, st->err, st->err_internal, 0, 0, 0, st->edges_added};
+      host[round] = h;
+      __threadfence_system();
+    }
+    return;
+  }
+  // tiles of 1024 x 4 words: one int4 per thread, block-wide exclusive scan, carry
   const int32_t W = (nr + 63) >> 6;
-  const int32_t per = (W + 1023) / 1024;
-  const int32_t lo = min(W, tid * per), hi = min(W, lo + per);
-  int64_t mine = 0;
-  for (int32_t i = lo; i < hi; ++i) mine += rootcnt[i];
-  // inclusive scan of `mine` across the block
-  int64_t x = mine;
-  for (int off = 1; off < 64; off <<= 1) {
-    const int64_t y = __shfl_up(x, off, 64);
-    if (lane >= off) x += y;
+  int64_t carry = 0;
+  for (int32_t t0 = 0; t0 < W; t0 += 4096) {
+    const int32_t g = t0 + 4 * tid;
+    int32_t v0 = 0, v1 = 0, v2 = 0, v3 = 0;
+    if (g + 3 < W) {
+      const int4 q = *reinterpret_cast<const int4*>(rootcnt + g);
+      v0 = q.x;
+      v1 = q.y;
+      v2 = q.z;
+      v3 = q.w;
+    } else {
+      if (g + 0 < W) v0 = rootcnt[g + 0];
+      if (g + 1 < W) v1 = rootcnt[g + 1];
+      if (g + 2 < W) v2 = rootcnt[g + 2];
+    }
+    const int64_t mine = (int64_t)v0 + v1 + v2 + v3;
+    int64_t x = mine;
+    for (int off = 1; off < 64; off <<= 1) {
+      const int64_t y = __shfl_up(x, off, 64);
+      if (lane >= off) x += y;
+    }
+    if (lane == 63) sh[wv] = x;
+    __syncthreads();
+    int64_t wave_base = 0, tile_tot = 0;
+    for (int i = 0; i < 16; ++i) {
+      wave_base += (i < wv) ? sh[i] : 0;
+      tile_tot += sh[i];
+    }
+    const int64_t e0 = carry + wave_base + x - mine;
+    const int32_t p0 = (int32_t)e0, p1 = (int32_t)(e0 + v0), p2 = (int32_t)(e0 + v0 + v1),
+                  p3 = (int32_t)(e0 + v0 + v1 + v2);
+    if (g + 3 < W) {
+      *reinterpret_cast<int4*>(rootpre + g) = make_int4(p0, p1, p2, p3);
+    } else {
+      if (g + 0 < W) rootpre[g + 0] = p0;
+      if (g + 1 < W) rootpre[g + 1] = p1;
+      if (g + 2 < W) rootpre[g + 2] = p2;
+    }
+    carry += tile_tot;
+    __syncthreads();  // sh[] is rewritten by the next tile
   }
-  if (lane == 63) sh[wv] = x;
-  __syncthreads();
-  int64_t wave_base = 0, total_roots = 0;
-  for (int i = 0; i < 16; ++i) {
-    wave_base += (i < wv) ? sh[i] : 0;
-    total_roots += sh[i];
-  }
-  int64_t run = wave_base + x - mine;  // exclusive prefix of this thread's span
-  for (int32_t i = lo; i < hi; ++i) {
-    rootpre[i] = (int32_t)run;
-    run += rootcnt[i];
-  }
-  // reductions of the partials
+  const int64_t total_roots = carry;
   int64_t live = 0, sel = 0;
   unsigned long long ws = 0;
   for (int32_t i = tid; i < nlive; i += 1024) live += part_live[i];
@@ -459,17 +668,11 @@ __global__ void __launch_bounds__(1024) k_finalize(int round, const int32_t* __r
     shw[wv] = ws;
   }
   __syncthreads();
-  if (tid == 0) {
-    int64_t L = 0;
-    unsigned long long S = 0;
-    for (int i = 0; i < 16; ++i) {
-      L += sh[i];
-      S += shw[i];
-    }
-    st->live[round] = L;
-    st->n[round + 1] = (int32_t)total_roots;
-    st->lab_off[round + 1] = st->lab_off[round] + nr;
-    *total += S;
+  int64_t L = 0;
+  unsigned long long S = 0;
+  for (int i = 0; i < 16; ++i) {
+    L += sh[i];
+    S += shw[i];
   }
   __syncthreads();
   if (lane == 0) sh[wv] = sel;
@@ -477,8 +680,15 @@ __global__ void __launch_bounds__(1024) k_finalize(int round, const int32_t* __r
   if (tid == 0) {
     int64_t T = 0;
     for (int i = 0; i < 16; ++i) T += sh[i];
+    st->live[round] = L;
     st->sel[round] = T;
     st->edges_added += T;
+    st->n[round + 1] = (int32_t)total_roots;
+    st->lab_off[round + 1] = st->lab_off[round] + nr;
+    *total += S;
+    HostRound h{(int32_t)total_roots, st->err, st->err_internal, 0, L, T, st->edges_added};
+    host[round] = h;
+    __threadfence_system();
   }
 }
 
@@ -495,6 +705,7 @@ __global__ void __launch_bounds__(kBlock) k_relabel(int round, const int32_t* __
                                                     unsigned long long* best,
                                                     const DevState* __restrict__ st) {
   const int32_t nr = st->n[round];
+  if (nr <= 1 && round > 0) return;
   const int32_t nn = st->n[round + 1];
   const int64_t off = st->lab_off[round];
   const int64_t stride = (int64_t)gridDim.x * kBlock;
@@ -514,15 +725,41 @@ __global__ void __launch_bounds__(kBlock) k_relabel(int round, const int32_t* __
 
 // ------------------------------------------------------------ launchers
 
-#define MSTX_LAUNCH_CHECK()                                   \
-  do {                                                        \
-    hipError_t _e = hipGetLastError();                        \
-    if (_e != hipSuccess) return _e;                          \
+#define MSTX_LAUNCH_CHECK()            \
+  do {                                 \
+    hipError_t _e = hipGetLastError(); \
+    if (_e != hipSuccess) return _e;   \
   } while (0)
 
-hipError_t launch_init(int32_t n, uint32_t m, unsigned long long* best, int32_t* parent, DevState* st,
-                       int grid, hipStream_t s) {
-  k_init<<<grid, kBlock, 0, s>>>(n, m, best, parent, st);
+template <int M, bool I, bool C>
+static hipError_t raise_lds_limit() {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_scan<M, I, C>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxDynLds);
+}
+
+hipError_t configure_kernels() {
+  hipError_t e = hipSuccess;
+#define MSTX_CFG(M, I, C)                       \
+  do {                                          \
+    hipError_t r_ = raise_lds_limit<M, I, C>(); \
+    if (r_ != hipSuccess) e = r_;               \
+  } while (0)
+  MSTX_CFG(kModeLds, true, false);
+  MSTX_CFG(kModeLds, true, true);
+  MSTX_CFG(kModeLds, false, true);
+  MSTX_CFG(kModeBucket, true, false);
+  MSTX_CFG(kModeBucket, true, true);
+  MSTX_CFG(kModeBucket, false, true);
+#undef MSTX_CFG
+  hipError_t r2 = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bucket_min),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxDynLds);
+  if (r2 != hipSuccess) e = r2;
+  return e;
+}
+
+hipError_t launch_init(int32_t n, unsigned long long* best, int32_t* parent, DevState* st, int grid,
+                       hipStream_t s) {
+  k_init<<<grid, kBlock, 0, s>>>(n, best, parent, st);
   MSTX_LAUNCH_CHECK();
   return hipSuccess;
 }
@@ -533,42 +770,42 @@ hipError_t launch_fill_u64(unsigned long long* p, int64_t count, unsigned long l
   return hipSuccess;
 }
 
-hipError_t launch_scan_first(bool lds, const int32_t* src, const int32_t* dst, const uint32_t* w, uint32_t m,
-                             int32_t n, unsigned long long* best, uint32_t* part_live, DevState* st,
-                             int grid, hipStream_t s) {
-  if (lds) {
-    k_scan_first<true><<<grid, kBlock, (size_t)n * 8, s>>>(src, dst, w, m, n, best, part_live, st);
-  } else {
-    k_scan_first<false><<<grid, kBlock, 0, s>>>(src, dst, w, m, n, best, part_live, st);
-  }
+hipError_t launch_scan(int mode, int stage, const ScanArgs& a, int grid, size_t lds, hipStream_t s) {
+  // stage 0: round 0 (input, no compaction); 1: round 1 (input, compaction); 2: records
+#define MSTX_SCAN(M)                                                             \
+  do {                                                                           \
+    if (stage == 0) k_scan<M, true, false><<<grid, kScanBlock, lds, s>>>(a);     \
+    else if (stage == 1) k_scan<M, true, true><<<grid, kScanBlock, lds, s>>>(a); \
+    else k_scan<M, false, true><<<grid, kScanBlock, lds, s>>>(a);                \
+  } while (0)
+  if (mode == kModeLds) MSTX_SCAN(kModeLds);
+  else if (mode == kModeBucket) MSTX_SCAN(kModeBucket);
+  else MSTX_SCAN(kModeGlobal);
+#undef MSTX_SCAN
   MSTX_LAUNCH_CHECK();
   return hipSuccess;
 }
 
-hipError_t launch_scan_seg(bool from_input, bool lds, int32_t nr_host, int round, const int32_t* src,
-                           const int32_t* dst, const uint32_t* w, uint32_t m, const int32_t* labpool,
-                           uint4* rec, uint32_t* seg_cnt, uint32_t seg_cap, int32_t nseg,
+hipError_t launch_bucket_min(int round, int launched, const unsigned long long* upd_key, const uint16_t* upd_cl,
+                             const uint32_t* offT, int32_t nseg, unsigned long long* best, const DevState* st,
+                             int grid, size_t lds, hipStream_t s) {
+  k_bucket_min<<<grid, kScanBlock, lds + kBucketMinExtraLds, s>>>(round, launched, upd_key, upd_cl, offT, nseg,
+                                                                  best, st);
+  MSTX_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+hipError_t launch_slab_min(int round, int launched, const unsigned long long* slab, int64_t slab_cap, int nwg,
                            unsigned long long* best, const DevState* st, int grid, hipStream_t s) {
-  const size_t sh = lds ? (size_t)nr_host * 8 : 0;
-  if (from_input) {
-    if (lds)
-      k_scan_seg<true, true><<<grid, kBlock, sh, s>>>(round, src, dst, w, m, labpool, rec, seg_cnt, seg_cap, nseg, best, st);
-    else
-      k_scan_seg<true, false><<<grid, kBlock, 0, s>>>(round, src, dst, w, m, labpool, rec, seg_cnt, seg_cap, nseg, best, st);
-  } else {
-    if (lds)
-      k_scan_seg<false, true><<<grid, kBlock, sh, s>>>(round, src, dst, w, m, labpool, rec, seg_cnt, seg_cap, nseg, best, st);
-    else
-      k_scan_seg<false, false><<<grid, kBlock, 0, s>>>(round, src, dst, w, m, labpool, rec, seg_cnt, seg_cap, nseg, best, st);
-  }
+  const dim3 g2(grid, (nwg + kSlabRowsPerBlock - 1) / kSlabRowsPerBlock);
+  k_slab_min<<<g2, kBlock, 0, s>>>(round, launched, slab, slab_cap, nwg, best, st);
   MSTX_LAUNCH_CHECK();
   return hipSuccess;
 }
 
 hipError_t launch_hook(int round, const int32_t* src, const int32_t* dst, const uint32_t* w,
-                       const unsigned long long* best, int32_t* parent, const int32_t* labpool,
-                       DevState* st, uint8_t* in_mst, uint32_t* part_sel, unsigned long long* part_w,
-                       int grid, hipStream_t s) {
+                       const unsigned long long* best, int32_t* parent, const int32_t* labpool, DevState* st,
+                       uint8_t* in_mst, uint32_t* part_sel, unsigned long long* part_w, int grid, hipStream_t s) {
   k_hook<<<grid, kBlock, 0, s>>>(round, src, dst, w, best, parent, labpool, st, in_mst, part_sel, part_w);
   MSTX_LAUNCH_CHECK();
   return hipSuccess;
@@ -584,15 +821,17 @@ hipError_t launch_compress(int round, int32_t* parent, int32_t* root_of, const u
 
 hipError_t launch_finalize(int round, const int32_t* rootcnt, int32_t* rootpre, const uint32_t* part_live,
                            int32_t nlive, const uint32_t* part_sel, const unsigned long long* part_w,
-                           int32_t nhook, DevState* st, unsigned long long* total, hipStream_t s) {
-  k_finalize<<<1, 1024, 0, s>>>(round, rootcnt, rootpre, part_live, nlive, part_sel, part_w, nhook, st, total);
+                           int32_t nhook, DevState* st, unsigned long long* total, HostRound* host,
+                           hipStream_t s) {
+  k_finalize<<<1, 1024, 0, s>>>(round, rootcnt, rootpre, part_live, nlive, part_sel, part_w, nhook, st, total,
+                                host);
   MSTX_LAUNCH_CHECK();
   return hipSuccess;
 }
 
 hipError_t launch_relabel(int round, const int32_t* root_of, const unsigned long long* rootmask,
-                          const int32_t* rootpre, int32_t* labpool, int32_t* parent,
-                          unsigned long long* best, const DevState* st, int grid, hipStream_t s) {
+                          const int32_t* rootpre, int32_t* labpool, int32_t* parent, unsigned long long* best,
+                          const DevState* st, int grid, hipStream_t s) {
   k_relabel<<<grid, kBlock, 0, s>>>(round, root_of, rootmask, rootpre, labpool, parent, best, st);
   MSTX_LAUNCH_CHECK();
   return hipSuccess;
