@@ -41,6 +41,79 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_random_n1M_d16.json")
+
+
+def kernel_source_hash() -> str:
+    """sha256 over the HIP sources; a traffic summary is valid only for the kernels it measured."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2005_06913_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()
+
+
+def _pmc_rows(d):
+    import csv
+    import glob
+    out = {}
+    for path in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        for r in csv.DictReader(open(path)):
+            name = r["Kernel_Name"].replace("void ", "").replace("mstx::", "").split("(")[0]
+            out.setdefault(name, []).append(float(r["Counter_Value"]))
+    return out
+
+
+def summarize_pmc(copy_fetch, copy_write, solve_fetch, solve_write, copy_mib, out_path):
+    """Folds four rocprofv3 --pmc runs (FETCH_SIZE / WRITE_SIZE of a plain copy and of the
+    solve) into HBM bytes per launch for every kernel, scaled by the copy calibration."""
+    cf, cw = _pmc_rows(copy_fetch), _pmc_rows(copy_write)
+    copy_name = max(cf, key=lambda k: max(cf[k]))
+    nbytes = copy_mib << 20
+    fetch_factor = nbytes / (max(cf[copy_name]) * 1024.0)
+    write_factor = nbytes / (max(cw[copy_name]) * 1024.0)
+    sf, sw = _pmc_rows(solve_fetch), _pmc_rows(solve_write)
+    kernels = {}
+    for k in sf:
+        if not k.startswith("k_") or k not in sw:
+            continue
+        fb = [v * 1024.0 * fetch_factor for v in sf[k]]
+        wb = [v * 1024.0 * write_factor for v in sw[k]]
+        kernels[k] = {"launches": len(fb), "fetch_bytes_mean": sum(fb) / len(fb),
+                      "write_bytes_mean": sum(wb) / len(wb),
+                      "traffic_bytes_mean": sum(fb) / len(fb) + sum(wb) / len(wb),
+                      "traffic_bytes_max_launch": max(a + b for a, b in zip(fb, wb))}
+    doc = {"workload": "random_n1M_d16", "source_sha256": kernel_source_hash(),
+           "copy_calibration": {"kernel": copy_name, "bytes_each_way": nbytes,
+                                "fetch_kib": max(cf[copy_name]), "write_kib": max(cw[copy_name]),
+                                "fetch_factor": fetch_factor, "write_factor": write_factor},
+           "commands": [
+               f"rocprofv3 --pmc FETCH_SIZE -f csv -d <dir> -o run -- python3 bench.py --calibrate-copy-mib {copy_mib}",
+               f"rocprofv3 --pmc WRITE_SIZE -f csv -d <dir> -o run -- python3 bench.py --calibrate-copy-mib {copy_mib}",
+               "rocprofv3 --pmc FETCH_SIZE -f csv -d <dir> -o run -- python3 bench.py --steps 2 --warmup 1 "
+               "--no-cpu-baseline --cold-reps 0",
+               "rocprofv3 --pmc WRITE_SIZE -f csv -d <dir> -o run -- python3 bench.py --steps 2 --warmup 1 "
+               "--no-cpu-baseline --cold-reps 0"],
+           "kernels": kernels}
+    with open(out_path, "w") as f:
+        json.dump(doc, f, indent=1)
+    return doc
+
+
+def traffic_for(kernel: str):
+    """Counter-measured HBM bytes per launch of `kernel`, or None if absent or stale."""
+    try:
+        doc = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if doc.get("source_sha256") != kernel_source_hash():
+        return None
+    k = doc.get("kernels", {}).get(kernel)
+    return None if k is None else k["traffic_bytes_mean"]
+
+
 def cpu_baseline(g, budget_s: float):
     """The oracle (Kruskal, plain C, one thread) timed on the host on the same graph."""
     import oracle
@@ -67,7 +140,17 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="time budget of the CPU oracle leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cold-reps", type=int, default=5, help="extra solves after a 1 GiB cache flush")
+    ap.add_argument("--summarize-pmc", nargs=4, metavar=("COPY_FETCH", "COPY_WRITE", "SOLVE_FETCH", "SOLVE_WRITE"),
+                    help="fold four rocprofv3 --pmc output directories into the traffic summary and exit")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (twice) and exit; "
+                         "the reference for scaling HBM traffic counters")
     args = ap.parse_args()
+
+    if args.summarize_pmc:
+        doc = summarize_pmc(*args.summarize_pmc, copy_mib=256, out_path=TRAFFIC_FILE)
+        print(json.dumps({k: round(v["traffic_bytes_mean"] / 1e6, 2) for k, v in doc["kernels"].items()}))
+        return 0
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -86,6 +169,15 @@ def main() -> int:
         print("bench.py needs a GPU", file=sys.stderr)
         return 2
     dev = torch.device("cuda:0")
+    if args.calibrate_copy_mib:
+        nbytes = args.calibrate_copy_mib << 20
+        a = torch.ones(nbytes // 4, dtype=torch.int32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(2):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "copy", "bytes_read": nbytes, "bytes_written": nbytes}))
+        return 0
     P.load_library()
     log(f"[bench] generating {args.workload}")
     g = G.workload(args.workload)
@@ -146,11 +238,11 @@ def main() -> int:
     kernels = {k: {"ms_total": v[0], "launches": v[1], "ms_per_launch": (v[0] / v[1] if v[1] else 0.0),
                    "alg_bytes_per_launch": (v[2] / v[1] if v[1] else 0.0)} for k, v in prof.items()}
     dom = max(kernels, key=lambda k: kernels[k]["ms_total"])
-    scan_kinds = [k for k in kernels if k.startswith("scan") and kernels[k]["launches"]]
-    # the minima of a BUCKET / LDS-slab scan are finished by bucket_min / slab_min
-    step_kinds = scan_kinds + [k for k in ("bucket_min", "slab_min") if k in kernels and kernels[k]["launches"]]
+    scan_kinds = [k for k in kernels if k.startswith("k_scan") and kernels[k]["launches"]]
+    # the minima of a bucket / LDS-slab scan are finished by k_bucket_min / k_slab_min
+    step_kinds = scan_kinds + [k for k in ("k_bucket_min", "k_slab_min") if k in kernels and kernels[k]["launches"]]
     dk = kernels[dom]
-    if dk["alg_bytes_per_launch"] > 0:
+    if dk["alg_bytes_per_launch"] > 0:  # mean bytes per launch / mean duration per launch
         achieved = dk["alg_bytes_per_launch"] / (dk["ms_per_launch"] * 1e-3) / 1e9
         bound_kernel = dom
     else:  # dominant kernel has no byte model (not a scan): report the scan family
@@ -177,11 +269,12 @@ def main() -> int:
                    "leg": "single graph", "rounds": int(len(stats)),
                    "round_stats": stats.tolist()},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": bound_kernel},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for(bound_kernel),
+                     "kernel": bound_kernel},
         "kernels": kernels,
         "scan_family": {"ms_per_step": scan_ms / args.steps, "alg_bytes_per_step": scan_bytes / args.steps,
                         "achieved_GBs": (scan_bytes / (scan_ms * 1e-3) / 1e9) if scan_ms else 0.0},
-        "cold_ms_per_step": {"median": statistics.median(cold), "all": cold},
+        "cold_ms_per_step": {"median": statistics.median(cold) if cold else None, "all": cold},
         "total_weight": res_total,
     }
     if not args.no_cpu_baseline:

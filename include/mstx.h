@@ -101,20 +101,22 @@ size_t mst_workspace_bytes(int32_t n, int64_t m);
 /*
  * Per-kernel timing (profiling aid, off by default).  While enabled, each
  * kernel launch of mst_solve is bracketed by HIP events on the solve's
- * stream; after each solve the elapsed times, launch counts and the
- * algorithmic bytes of each kernel kind are accumulated.  Kernel kinds:
- * 0 scan_first (round 0 edge scan over the caller's arrays), 1 scan_input
- * (round 1 scan + compaction from the caller's arrays), 2 scan_records
- * (rounds >= 2 scan + in-place compaction), 3 hook, 4 compress, 5 finalize,
- * 6 relabel.  Algorithmic bytes are counted only for the scan kinds: the edge
- * stream read once (12 B per input edge, 16 B per record), the previous
- * round's label map read once (4 B per entry), the minima initialised and
- * written once (16 B per component) and the survivors written once (16 B).
+ * stream; after each solve the elapsed times, launch counts and algorithmic
+ * bytes are accumulated per kernel (template instantiation, named as a
+ * profiler lists it: "k_scan<mode, input, compact>", "k_bucket_min",
+ * "k_slab_min", "k_hook", "k_compress", "k_finalize", "k_relabel").  Every
+ * launch is counted, including launches that return at once (a minima mode
+ * not chosen for the actual component count, the round enqueued after the
+ * last one).  Algorithmic bytes are credited to the scan launch that did a
+ * round's work: the edge stream read once (12 B per input edge, 16 B per
+ * record), the previous round's label map read once (4 B per entry), the
+ * minima initialised and written once (16 B per component) and the survivors
+ * written once (16 B per record).
  *   mst_profile_enable: enable != 0 starts (and zeroes) the counters, 0 stops;
  *                       returns the previous state.
- *   mst_profile_read:   copies min(kinds, 7) entries to host arrays; returns
- *                       the number of kinds (7) or MSTX_ERR_INVALID_ARG.
- *   mst_profile_kernel_name: name of a kind ("" if out of range).
+ *   mst_profile_read:   copies min(kinds, K) entries to host arrays; returns
+ *                       the number K of kernels tracked or MSTX_ERR_INVALID_ARG.
+ *   mst_profile_kernel_name: name of kernel i ("" if out of range).
  * Intended for benchmarking; the events add a little time per launch.
  */
 int mst_profile_enable(int enable);

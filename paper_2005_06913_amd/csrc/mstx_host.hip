@@ -168,20 +168,26 @@ int rounds_bound(int32_t n) {
 // ------------------------------------------------------------- profiling
 // Opt-in per-kernel timing: when enabled, every kernel launch of a solve is
 // bracketed by two hipEvents on the solve's stream.  After the solve the
-// elapsed times of the launches that did the round's work are accumulated
-// per kernel kind, with the kind's algorithmic bytes (what the method must
-// move, from the round statistics).  Launches that returned at once (a scan
-// mode not chosen for the actual count, the round after the last) are left out.
+// elapsed times are accumulated per kernel (template instantiation, as a
+// profiler lists them), every launch counted -- also those that returned at
+// once (a minima mode not chosen for the actual count, the round enqueued
+// after the last one).  The scan launch that did a round's work is credited
+// with the round's algorithmic bytes (what the method must move, from the
+// round statistics).
 enum Kind {
   kScan0Global = 0, kScan0Lds, kScan0Bucket,
   kScan1Global, kScan1Lds, kScan1Bucket,
   kScanRGlobal, kScanRLds, kScanRBucket,
   kBucketMin, kSlabMin_, kHook, kCompress, kFinalize, kRelabel, kKinds
 };
+// Names as rocprofv3 reports the kernels (template arguments: minima mode
+// 0 global / 1 LDS / 2 bucket, reads the caller's arrays, compacts).
 const char* const kKindNames[kKinds] = {
-    "scan_r0_global", "scan_r0_lds",  "scan_r0_bucket", "scan_r1_global", "scan_r1_lds",
-    "scan_r1_bucket", "scan_rN_global", "scan_rN_lds", "scan_rN_bucket", "bucket_min",
-    "slab_min",       "hook",         "compress",       "finalize",       "relabel"};
+    "k_scan<0, true, false>",  "k_scan<1, true, false>",  "k_scan<2, true, false>",
+    "k_scan<0, true, true>",   "k_scan<1, true, true>",   "k_scan<2, true, true>",
+    "k_scan<0, false, true>",  "k_scan<1, false, true>",  "k_scan<2, false, true>",
+    "k_bucket_min",            "k_slab_min",              "k_hook",
+    "k_compress",              "k_finalize",              "k_relabel"};
 
 int scan_kind(int stage, int mode) {
   const int m = mode == kModeGlobal ? 0 : (mode == kModeLds ? 1 : 2);
@@ -242,13 +248,12 @@ struct LaunchTimer {
     if (!on) return;
     std::lock_guard<std::mutex> g(g_prof.mu);
     for (const auto& p : pending) {
-      if (p.round >= nrounds) continue;
-      if (p.mode >= 0 && p.mode != chosen[p.round]) continue;
       float ms = 0.f;
       if (hipEventElapsedTime(&ms, p.a, p.b) != hipSuccess) continue;
       g_prof.ms[p.kind] += ms;
       g_prof.launches[p.kind] += 1;
-      if (p.kind <= kScanRBucket) g_prof.bytes[p.kind] += bytes[p.round];
+      if (p.kind <= kScanRBucket && p.round < nrounds && p.mode == chosen[p.round])
+        g_prof.bytes[p.kind] += bytes[p.round];
     }
     pending.clear();
   }

@@ -531,7 +531,7 @@ __global__ void __launch_bounds__(kBlock) k_hook(int round, const int32_t* __res
       if (old == hi) {
         in_mst[e] = 1;
         ++sel;
-        wsum += w[e];
+        wsum += (uint32_t)(key >> 32);  // the edge's weight
         break;
       }
       if (hi == rx) x = old;

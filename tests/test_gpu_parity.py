@@ -160,3 +160,20 @@ def test_solve_full_size_planted(dev):
     assert st == 0
     assert total == g.n * (g.n - 1) // 2
     assert np.array_equal(in_mst, g.tree_mask.astype(np.uint8))
+
+
+@pytest.mark.timeout(400)
+def test_solve_full_size_rmat(dev):
+    """R-MAT scale 22, 2^26 samples (skewed degrees, hubs): bit-exact against Kruskal."""
+    from paper_2005_06913_amd import graphgen as G
+    g = G.workload("rmat_s22_e26")
+    check_against_oracle(dev, g.name, g.n, g.src, g.dst, g.w, stats=False)
+
+
+@pytest.mark.parametrize("n,d", [(10_000, 3), (10_000, 9), (100_000, 3), (100_000, 6), (100_000, 9),
+                                 (1_000_000, 3)])
+def test_solve_paper_shapes(dev, n, d):
+    """Table 1 shapes (n vertices, average degree d): edge set, total and round statistics."""
+    from paper_2005_06913_amd import graphgen as G
+    g = G.paper_shape(n, d, seed=100 + d)
+    check_against_oracle(dev, g.name, g.n, g.src, g.dst, g.w, stats=True)
