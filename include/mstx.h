@@ -70,6 +70,39 @@ int mst_solve(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, cons
               uint8_t* out_in_mst, uint64_t* out_total_weight, void* stream);
 
 /*
+ * Minimum spanning forests of many independent graphs in one call (the
+ * disjoint union of graphs has the union of their forests as its forest, and
+ * Boruvka rounds never merge components of different graphs).
+ *   num_graphs        G >= 0
+ *   vertex_offsets    HOST int64[G+1], nondecreasing, [0] = 0: graph g has
+ *                     n_g = vertex_offsets[g+1] - vertex_offsets[g] vertices
+ *   edge_offsets      HOST int64[G+1], nondecreasing, [0] = 0: graph g owns
+ *                     edges [edge_offsets[g], edge_offsets[g+1]) of the arrays
+ *   src, dst          int32[edge_offsets[G]], vertex ids LOCAL to the graph,
+ *                     in [0, n_g)
+ *   w                 uint32[edge_offsets[G]]
+ *   out_in_mst        uint8[edge_offsets[G]], overwritten
+ *   out_total_weight  uint64[G], overwritten: forest weight per graph
+ *   out_status        int32[G], overwritten: per-graph MSTX_OK /
+ *                     MSTX_DISCONNECTED / MSTX_ERR_VERTEX_RANGE (then the
+ *                     graph's outputs are those of its in-range edges)
+ * Ties break by the edge's position inside its graph, as in mst_solve, so
+ * every graph's result equals mst_solve on that graph alone.
+ * Returns MSTX_OK when the call ran (see out_status per graph),
+ * MSTX_ERR_INVALID_ARG (bad offsets or NULL arrays), MSTX_ERR_TOO_LARGE (a
+ * graph with more than 0xFFFFFFFF edges), MSTX_ERR_OUT_OF_MEMORY or
+ * MSTX_ERR_DEVICE.  Argument checks run on the host before any HIP call.
+ */
+int mst_solve_batched(int32_t num_graphs, const int64_t* vertex_offsets, const int64_t* edge_offsets,
+                      const int32_t* src, const int32_t* dst, const uint32_t* w, uint8_t* out_in_mst,
+                      uint64_t* out_total_weight, int32_t* out_status, void* stream);
+
+/* Device workspace bytes of mst_solve_batched for these offsets (upper bound;
+ * 0 for invalid offsets).  Pure host arithmetic. */
+size_t mst_batched_workspace_bytes(int32_t num_graphs, const int64_t* vertex_offsets,
+                                   const int64_t* edge_offsets);
+
+/*
  * The first Boruvka step alone (Section 2.1, the edge loop): for every vertex
  * v, out_best[v] = min over non-loop edges e incident to v of the key
  * ((uint64)w[e] << 32) | e, or 0xFFFFFFFFFFFFFFFF when v has no such edge.

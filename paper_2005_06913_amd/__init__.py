@@ -20,11 +20,13 @@ from .binding import (  # noqa: F401
     MstxError,
     Solution,
     load_library,
+    mst_batched_workspace_bytes,
     mst_last_round_stats,
     mst_profile_enable,
     mst_profile_read,
     mst_select_min_edges,
     mst_solve,
+    mst_solve_batched,
     mst_status_string,
     mst_workspace_bytes,
     solve,

@@ -24,8 +24,9 @@ MSTX_ERR_TOO_LARGE = -3
 MSTX_ERR_OUT_OF_MEMORY = -4
 MSTX_ERR_DEVICE = -5
 
-EXPORTS = ("mst_solve", "mst_select_min_edges", "mst_last_round_stats", "mst_workspace_bytes",
-           "mst_status_string", "mst_profile_enable", "mst_profile_read", "mst_profile_kernel_name")
+EXPORTS = ("mst_solve", "mst_solve_batched", "mst_batched_workspace_bytes", "mst_select_min_edges",
+           "mst_last_round_stats", "mst_workspace_bytes", "mst_status_string", "mst_profile_enable",
+           "mst_profile_read", "mst_profile_kernel_name")
 
 _lib = None
 
@@ -48,6 +49,10 @@ def load_library(path: str = LIB_PATH):
     i32, i64, p = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
     lib.mst_solve.argtypes = [i32, i64, p, p, p, p, p, p]
     lib.mst_solve.restype = ctypes.c_int
+    lib.mst_solve_batched.argtypes = [i32, p, p, p, p, p, p, p, p, p]
+    lib.mst_solve_batched.restype = ctypes.c_int
+    lib.mst_batched_workspace_bytes.argtypes = [i32, p, p]
+    lib.mst_batched_workspace_bytes.restype = ctypes.c_size_t
     lib.mst_select_min_edges.argtypes = [i32, i64, p, p, p, p, p]
     lib.mst_select_min_edges.restype = ctypes.c_int
     lib.mst_last_round_stats.argtypes = [p, i32]
@@ -105,6 +110,41 @@ def mst_solve(n, src, dst, w, out_in_mst, out_total_weight, stream=None) -> int:
             _dev_ptr(w, torch.uint32, "w", m), _dev_ptr(out_in_mst, torch.uint8, "out_in_mst", m),
             _dev_ptr(out_total_weight, torch.uint64, "out_total_weight", 1))
     return int(load_library().mst_solve(int(n), m, *args, _stream_handle(stream)))
+
+
+def _host_offsets(a, name):
+    import numpy as np
+    a = np.ascontiguousarray(a, dtype=np.int64)
+    if a.ndim != 1 or a.shape[0] < 1:
+        raise ValueError(f"{name} must be a 1-D array of G+1 offsets")
+    return a
+
+
+def mst_solve_batched(vertex_offsets, edge_offsets, src, dst, w, out_in_mst, out_total_weight, out_status,
+                      stream=None) -> int:
+    """C ``mst_solve_batched``: offsets are host int64 arrays [G+1] (numpy); src/dst (local ids),
+    w, out_in_mst [sum m] and out_total_weight (uint64 [G]), out_status (int32 [G]) are GPU tensors."""
+    import torch
+    vo = _host_offsets(vertex_offsets, "vertex_offsets")
+    eo = _host_offsets(edge_offsets, "edge_offsets")
+    G = vo.shape[0] - 1
+    if eo.shape[0] != G + 1:
+        raise ValueError("vertex_offsets and edge_offsets must have the same length")
+    m = int(eo[-1])
+    args = (_dev_ptr(src, torch.int32, "src", m), _dev_ptr(dst, torch.int32, "dst", m),
+            _dev_ptr(w, torch.uint32, "w", m), _dev_ptr(out_in_mst, torch.uint8, "out_in_mst", m),
+            _dev_ptr(out_total_weight, torch.uint64, "out_total_weight", G),
+            _dev_ptr(out_status, torch.int32, "out_status", G))
+    return int(load_library().mst_solve_batched(G, vo.ctypes.data_as(ctypes.c_void_p),
+                                                 eo.ctypes.data_as(ctypes.c_void_p), *args,
+                                                 _stream_handle(stream)))
+
+
+def mst_batched_workspace_bytes(vertex_offsets, edge_offsets) -> int:
+    vo = _host_offsets(vertex_offsets, "vertex_offsets")
+    eo = _host_offsets(edge_offsets, "edge_offsets")
+    return int(load_library().mst_batched_workspace_bytes(vo.shape[0] - 1, vo.ctypes.data_as(ctypes.c_void_p),
+                                                          eo.ctypes.data_as(ctypes.c_void_p)))
 
 
 def mst_select_min_edges(n, src, dst, w, out_best, stream=None) -> int:

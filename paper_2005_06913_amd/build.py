@@ -13,7 +13,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libmstx.so")
-SOURCES = ["mstx_kernels.hip", "mstx_host.hip"]
+SOURCES = ["mstx_kernels.hip", "mstx_batched.hip", "mstx_host.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

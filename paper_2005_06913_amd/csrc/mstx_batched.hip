@@ -1,0 +1,303 @@
+// mstx_batched.hip -- kernels of the batched solve (many independent graphs in one call).
+//
+// The minimum spanning forest of a disjoint union of graphs is the union of
+// their forests, and Boruvka never merges components of different graphs, so
+// a batch is solved in two parts:
+//
+//   * graphs with at most kSmallN vertices: one workgroup per graph runs every
+//     Boruvka round of Section 2.1 with the vertex state in LDS (component of
+//     each vertex, union-find parents, minimum keys); rounds are separated by
+//     workgroup barriers only, so thousands of small graphs proceed
+//     independently and in parallel;
+//   * larger graphs: gathered into chunks that are solved as one disjoint
+//     union by the single-graph round kernels (k_gather renumbers vertices and
+//     edges into the union, k_graph_epilogue scatters the flags back and sums
+//     per graph).
+//
+// Edge keys are (w << 32) | local edge index, so ties break by position inside
+// the graph as in the single-graph solve.
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mstx.h"
+#include "mstx_internal.h"
+
+namespace mstx {
+
+static constexpr int kSmallBlock = 1024;
+
+__device__ __forceinline__ int32_t lds_load(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Root of x in the LDS union-find `par` (parents always point to smaller ids).
+__device__ __forceinline__ int32_t small_root(int32_t* par, int32_t x) {
+  int32_t p = lds_load(par + x);
+  while (p != x) {
+    const int32_t gp = lds_load(par + p);
+    if (gp == p) return p;
+    par[x] = gp;  // halving: gp is an ancestor of x
+    x = gp;
+    p = lds_load(par + x);
+  }
+  return x;
+}
+
+// One workgroup per graph of `glist` (graphs with n <= kSmallN).  LDS holds
+// best[n] (u64 minimum key per component root), comp[n] (round-start root of
+// each vertex) and par[n] (union-find over the roots during hooking).  Each
+// round: minima over the graph's edges (re-read from HBM / cache), CAS hooking
+// of the larger root under the smaller, compression; the loop ends when a
+// round selects no edge.  Writes in_mst for the graph's edges (zeroed by the
+// caller), total[g] and status[g].
+__global__ void __launch_bounds__(kSmallBlock) k_small_solve(const int32_t* __restrict__ glist,
+                                                             const int64_t* __restrict__ voff,
+                                                             const int64_t* __restrict__ eoff,
+                                                             const int32_t* __restrict__ src,
+                                                             const int32_t* __restrict__ dst,
+                                                             const uint32_t* __restrict__ w,
+                                                             uint8_t* __restrict__ in_mst,
+                                                             unsigned long long* __restrict__ total_out,
+                                                             int32_t* __restrict__ status_out) {
+  extern __shared__ unsigned long long sbest[];  // [kSmallN]
+  int32_t* comp = reinterpret_cast<int32_t*>(sbest + kSmallN);
+  int32_t* par = comp + kSmallN;
+  __shared__ uint32_t round_sel;
+  __shared__ uint32_t bad;
+  __shared__ unsigned long long red_w[kSmallBlock / 64];
+  __shared__ uint32_t red_c[kSmallBlock / 64];
+
+  const int g = glist[blockIdx.x];
+  const int64_t e0 = eoff[g];
+  const int64_t m = eoff[g + 1] - e0;
+  const int32_t n = (int32_t)(voff[g + 1] - voff[g]);
+  const int tid = threadIdx.x;
+
+  for (int32_t v = tid; v < n; v += kSmallBlock) comp[v] = v;
+  if (tid == 0) bad = 0;
+  unsigned long long my_w = 0;
+  uint32_t my_cnt = 0;
+  __syncthreads();
+
+  for (int round = 0; round < kMaxRounds; ++round) {
+    for (int32_t v = tid; v < n; v += kSmallBlock) {
+      sbest[v] = kKeyNone;
+      par[v] = v;
+    }
+    if (tid == 0) round_sel = 0;
+    __syncthreads();
+    // edge scan: lightest outgoing key per component root
+    for (int64_t j = tid; j < m; j += kSmallBlock) {
+      const int32_t a0 = src[e0 + j], b0 = dst[e0 + j];
+      if ((uint32_t)a0 >= (uint32_t)n || (uint32_t)b0 >= (uint32_t)n) {
+        bad = 1;
+        continue;
+      }
+      const int32_t a = comp[a0], b = comp[b0];
+      if (a == b) continue;
+      const unsigned long long key = ((unsigned long long)w[e0 + j] << 32) | (unsigned long long)j;
+      if (key < sbest[a]) atomicMin(sbest + a, key);
+      if (key < sbest[b]) atomicMin(sbest + b, key);
+    }
+    __syncthreads();
+    // hooking: every root with a minimum unites with the other end's root
+    uint32_t sel = 0;
+    for (int32_t c = tid; c < n; c += kSmallBlock) {
+      if (comp[c] != c) continue;
+      const unsigned long long key = sbest[c];
+      if (key == kKeyNone) continue;
+      const int64_t j = (int64_t)(uint32_t)key;
+      const int32_t u = comp[src[e0 + j]], v = comp[dst[e0 + j]];
+      const int32_t d = (u == c) ? v : u;
+      if (d < c && sbest[d] == key) continue;  // mutual choice: d hooks it
+      int32_t x = c, y = d;
+      while (true) {
+        const int32_t rx = small_root(par, x);
+        const int32_t ry = small_root(par, y);
+        if (rx == ry) break;
+        const int32_t hi = rx > ry ? rx : ry;
+        const int32_t lo = rx > ry ? ry : rx;
+        const int32_t old = atomicCAS(par + hi, hi, lo);
+        if (old == hi) {
+          in_mst[e0 + j] = 1;
+          my_w += (uint32_t)(key >> 32);
+          ++sel;
+          break;
+        }
+        if (hi == rx) x = old;
+        else y = old;
+      }
+    }
+    if (sel) atomicAdd(&round_sel, sel);
+    my_cnt += sel;
+    __syncthreads();
+    if (round_sel == 0) break;
+    // compression: the final root of every root of this round goes to a buffer
+    // of its own (the minima are no longer needed), so a concurrent halving
+    // store into par[] cannot replace it; then every vertex takes its root's root
+    int32_t* newroot = reinterpret_cast<int32_t*>(sbest);
+    for (int32_t c = tid; c < n; c += kSmallBlock) {
+      if (comp[c] == c) newroot[c] = small_root(par, c);
+    }
+    __syncthreads();
+    for (int32_t v = tid; v < n; v += kSmallBlock) comp[v] = newroot[comp[v]];
+    __syncthreads();
+  }
+  // per-graph totals
+  for (int off = 32; off > 0; off >>= 1) {
+    my_w += __shfl_xor(my_w, off, 64);
+    my_cnt += __shfl_xor(my_cnt, off, 64);
+  }
+  if ((tid & 63) == 0) {
+    red_w[tid >> 6] = my_w;
+    red_c[tid >> 6] = my_cnt;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    unsigned long long tw = 0;
+    uint32_t tc = 0;
+    for (int i = 0; i < kSmallBlock / 64; ++i) {
+      tw += red_w[i];
+      tc += red_c[i];
+    }
+    total_out[g] = tw;
+    int32_t st = (n <= 1 || (int64_t)tc == (int64_t)n - 1) ? MSTX_OK : MSTX_DISCONNECTED;
+    if (bad) st = MSTX_ERR_VERTEX_RANGE;
+    status_out[g] = st;
+  }
+}
+
+// Union of the chunk's graphs glist[0..ng): chunk edge p belongs to graph k with
+// cedge[k] <= p < cedge[k+1]; its ends become union ids cvert[k] + local id.
+// An end outside [0, n_g) makes the edge a self-loop at cvert[k] and flags the
+// graph.  w is copied so the union's edges are contiguous.
+__global__ void __launch_bounds__(256) k_gather(const int32_t* __restrict__ glist, int ng,
+                                                const int64_t* __restrict__ voff,
+                                                const int64_t* __restrict__ eoff,
+                                                const int64_t* __restrict__ cvert,
+                                                const int64_t* __restrict__ cedge,
+                                                const int32_t* __restrict__ src,
+                                                const int32_t* __restrict__ dst,
+                                                const uint32_t* __restrict__ w, int32_t* __restrict__ gsrc,
+                                                int32_t* __restrict__ gdst, uint32_t* __restrict__ gw,
+                                                int32_t* __restrict__ gbad) {
+  const int64_t total = cedge[ng];
+  const int64_t per_block = 4096;
+  for (int64_t b0 = (int64_t)blockIdx.x * per_block; b0 < total; b0 += (int64_t)gridDim.x * per_block) {
+    // graph of this block's first edge (binary search), then forward steps per edge
+    __shared__ int k0s;
+    if (threadIdx.x == 0) {
+      int lo = 0, hi = ng - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (cedge[mid] <= b0) lo = mid;
+        else hi = mid - 1;
+      }
+      k0s = lo;
+    }
+    __syncthreads();
+    const int k0 = k0s;
+    __syncthreads();
+    const int64_t b1 = min(total, b0 + per_block);
+    for (int64_t p = b0 + threadIdx.x; p < b1; p += blockDim.x) {
+      int k = k0;
+      while (cedge[k + 1] <= p) ++k;
+      const int g = glist[k];
+      const int64_t j = eoff[g] + (p - cedge[k]);
+      const int32_t n = (int32_t)(voff[g + 1] - voff[g]);
+      int32_t a = src[j], b = dst[j];
+      if ((uint32_t)a >= (uint32_t)n || (uint32_t)b >= (uint32_t)n) {
+        gbad[k] = 1;
+        a = b = 0;
+      }
+      gsrc[p] = (int32_t)(cvert[k] + a);
+      gdst[p] = (int32_t)(cvert[k] + b);
+      gw[p] = w[j];
+    }
+  }
+}
+
+// One workgroup per chunk graph k: copies the union's flags back to the
+// caller's in_mst range of graph glist[k], sums the weight and count of the
+// marked edges, and sets total[g], status[g].
+__global__ void __launch_bounds__(256) k_graph_epilogue(const int32_t* __restrict__ glist,
+                                                        const int64_t* __restrict__ voff,
+                                                        const int64_t* __restrict__ eoff,
+                                                        const int64_t* __restrict__ cedge,
+                                                        const uint8_t* __restrict__ cin_mst,
+                                                        const uint32_t* __restrict__ gw,
+                                                        const int32_t* __restrict__ gbad,
+                                                        uint8_t* __restrict__ in_mst,
+                                                        unsigned long long* __restrict__ total_out,
+                                                        int32_t* __restrict__ status_out) {
+  __shared__ unsigned long long rw[4];
+  __shared__ uint32_t rc[4];
+  const int k = blockIdx.x;
+  const int g = glist[k];
+  const int64_t p0 = cedge[k], p1 = cedge[k + 1];
+  const int64_t j0 = eoff[g];
+  unsigned long long sw = 0;
+  uint32_t cnt = 0;
+  for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+    const uint8_t f = cin_mst[p];
+    in_mst[j0 + (p - p0)] = f;
+    if (f) {
+      sw += gw[p];
+      ++cnt;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    sw += __shfl_xor(sw, off, 64);
+    cnt += __shfl_xor(cnt, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    rw[threadIdx.x >> 6] = sw;
+    rc[threadIdx.x >> 6] = cnt;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long tw = rw[0] + rw[1] + rw[2] + rw[3];
+    const uint32_t tc = rc[0] + rc[1] + rc[2] + rc[3];
+    const int64_t n = voff[g + 1] - voff[g];
+    total_out[g] = tw;
+    int32_t st = (n <= 1 || (int64_t)tc == n - 1) ? MSTX_OK : MSTX_DISCONNECTED;
+    if (gbad[k]) st = MSTX_ERR_VERTEX_RANGE;
+    status_out[g] = st;
+  }
+}
+
+hipError_t configure_batched_kernels() {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_small_solve),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmallSolveLds);
+}
+
+hipError_t launch_small_solve(const int32_t* glist, int num, const int64_t* voff, const int64_t* eoff,
+                              const int32_t* src, const int32_t* dst, const uint32_t* w, uint8_t* in_mst,
+                              unsigned long long* total, int32_t* status, hipStream_t s) {
+  if (num <= 0) return hipSuccess;
+  k_small_solve<<<num, kSmallBlock, kSmallSolveLds, s>>>(glist, voff, eoff, src, dst, w, in_mst, total, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather(const int32_t* glist, int ng, const int64_t* voff, const int64_t* eoff,
+                         const int64_t* cvert, const int64_t* cedge, int64_t chunk_edges, const int32_t* src,
+                         const int32_t* dst, const uint32_t* w, int32_t* gsrc, int32_t* gdst, uint32_t* gw,
+                         int32_t* gbad, hipStream_t s) {
+  if (ng <= 0 || chunk_edges <= 0) return hipSuccess;
+  const int64_t blocks = (chunk_edges + 4095) / 4096;
+  const int grid = (int)(blocks < 8192 ? blocks : 8192);
+  k_gather<<<grid, 256, 0, s>>>(glist, ng, voff, eoff, cvert, cedge, src, dst, w, gsrc, gdst, gw, gbad);
+  return hipGetLastError();
+}
+
+hipError_t launch_graph_epilogue(const int32_t* glist, int ng, const int64_t* voff, const int64_t* eoff,
+                                 const int64_t* cedge, const uint8_t* cin_mst, const uint32_t* gw,
+                                 const int32_t* gbad, uint8_t* in_mst, unsigned long long* total, int32_t* status,
+                                 hipStream_t s) {
+  if (ng <= 0) return hipSuccess;
+  k_graph_epilogue<<<ng, 256, 0, s>>>(glist, voff, eoff, cedge, cin_mst, gw, gbad, in_mst, total, status);
+  return hipGetLastError();
+}
+
+}  // namespace mstx

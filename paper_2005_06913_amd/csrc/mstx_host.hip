@@ -86,6 +86,8 @@ struct DeviceCache {
   hipEvent_t round_ev[kMaxRounds + 1] = {};
   int cus = 0;
   bool configured = false;
+  void* aux = nullptr;  // batched-call scratch
+  size_t aux_bytes = 0;
 };
 
 constexpr int kMaxDevices = 64;
@@ -135,9 +137,10 @@ int acquire(DeviceCache*& dc, std::unique_lock<std::mutex>& lock, size_t bytes) 
     // raises the dynamic LDS limit of the scan kernels; if the runtime refuses,
     // launches that need more LDS fail and report MSTX_ERR_DEVICE
     if (configure_kernels() != hipSuccess) (void)hipGetLastError();
+    if (configure_batched_kernels() != hipSuccess) (void)hipGetLastError();
     dc->configured = true;
   }
-  if (dc->bytes < bytes) {
+  if (bytes > 0 && dc->bytes < bytes) {
     if (dc->base) {
       HIP_OK(hipDeviceSynchronize());
       HIP_OK(hipFree(dc->base));
@@ -390,22 +393,10 @@ hipError_t enqueue_round(Solve& S, int r, int64_t bound) {
   return hipEventRecord(S.dc->round_ev[r], S.s);
 }
 
-int solve(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, const uint32_t* w, uint8_t* in_mst,
-          uint64_t* total, hipStream_t s) {
-  t_last_stats.clear();
-  const Layout L = plan(n, m);
-  if (L.bytes > workspace_limit()) return MSTX_ERR_OUT_OF_MEMORY;
-  if (m == 0) {
-    HIP_OK(hipMemsetAsync(total, 0, sizeof(uint64_t), s));
-    HIP_OK(hipStreamSynchronize(s));
-    return n <= 1 ? MSTX_OK : MSTX_DISCONNECTED;
-  }
-  if (n == 0) return MSTX_ERR_VERTEX_RANGE;  // m > 0 edges, no valid vertex id
-
-  DeviceCache* dc = nullptr;
-  std::unique_lock<std::mutex> lock;
-  int rc = acquire(dc, lock, L.bytes);
-  if (rc != MSTX_OK) return rc;
+// The round loop of one graph (n >= 1, m >= 1) on a workspace of at least
+// plan(n, m).bytes; the device cache is locked by the caller.
+int solve_locked(DeviceCache* dc, const Layout& L, int32_t n, int64_t m, const int32_t* src, const int32_t* dst,
+                 const uint32_t* w, uint8_t* in_mst, uint64_t* total, hipStream_t s) {
   void* B = dc->base;
   Solve S;
   S.n = n;
@@ -498,6 +489,193 @@ int solve(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, const ui
   return status;
 }
 
+int solve(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, const uint32_t* w, uint8_t* in_mst,
+          uint64_t* total, hipStream_t s) {
+  t_last_stats.clear();
+  const Layout L = plan(n, m);
+  if (L.bytes > workspace_limit()) return MSTX_ERR_OUT_OF_MEMORY;
+  if (m == 0) {
+    HIP_OK(hipMemsetAsync(total, 0, sizeof(uint64_t), s));
+    HIP_OK(hipStreamSynchronize(s));
+    return n <= 1 ? MSTX_OK : MSTX_DISCONNECTED;
+  }
+  if (n == 0) return MSTX_ERR_VERTEX_RANGE;  // m > 0 edges, no valid vertex id
+  DeviceCache* dc = nullptr;
+  std::unique_lock<std::mutex> lock;
+  int rc = acquire(dc, lock, L.bytes);
+  if (rc != MSTX_OK) return rc;
+  return solve_locked(dc, L, n, m, src, dst, w, in_mst, total, s);
+}
+
+// ----------------------------------------------------------------- batched
+
+// Device scratch of a batched call besides the solve workspace.
+struct BatchLayout {
+  size_t voff, eoff, small, large, cvert, cedge, gbad, gsrc, gdst, gw, cin, total, bytes;
+};
+
+BatchLayout plan_batch(int32_t G, int64_t nsmall, int64_t nlarge, int64_t nchunk_meta, int64_t max_chunk_m) {
+  BatchLayout B{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  };
+  B.voff = take(8 * ((size_t)G + 1));
+  B.eoff = take(8 * ((size_t)G + 1));
+  B.small = take(4 * (size_t)std::max<int64_t>(nsmall, 1));
+  B.large = take(4 * (size_t)std::max<int64_t>(nlarge, 1));
+  B.cvert = take(8 * (size_t)std::max<int64_t>(nchunk_meta, 1));
+  B.cedge = take(8 * (size_t)std::max<int64_t>(nchunk_meta, 1));
+  B.gbad = take(4 * (size_t)std::max<int64_t>(nlarge, 1));
+  B.gsrc = take(4 * (size_t)std::max<int64_t>(max_chunk_m, 1));
+  B.gdst = take(4 * (size_t)std::max<int64_t>(max_chunk_m, 1));
+  B.gw = take(4 * (size_t)std::max<int64_t>(max_chunk_m, 1));
+  B.cin = take((size_t)std::max<int64_t>(max_chunk_m, 1));
+  B.total = take(8);
+  B.bytes = off;
+  return B;
+}
+
+int grow_aux(DeviceCache* dc, size_t bytes) {
+  if (dc->aux_bytes >= bytes) return MSTX_OK;
+  if (dc->aux) {
+    HIP_OK(hipDeviceSynchronize());
+    HIP_OK(hipFree(dc->aux));
+    dc->aux = nullptr;
+    dc->aux_bytes = 0;
+  }
+  if (hipMalloc(&dc->aux, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    dc->aux = nullptr;
+    return MSTX_ERR_OUT_OF_MEMORY;
+  }
+  dc->aux_bytes = bytes;
+  return MSTX_OK;
+}
+
+int check_batch_args(int32_t G, const int64_t* voff, const int64_t* eoff, const void* src, const void* dst,
+                     const void* w, const void* in_mst, const void* total, const void* status) {
+  if (G < 0) return MSTX_ERR_INVALID_ARG;
+  if (G == 0) return MSTX_OK;
+  if (!voff || !eoff || !total || !status) return MSTX_ERR_INVALID_ARG;
+  if (voff[0] != 0 || eoff[0] != 0) return MSTX_ERR_INVALID_ARG;
+  for (int32_t g = 0; g < G; ++g) {
+    if (voff[g + 1] < voff[g] || eoff[g + 1] < eoff[g]) return MSTX_ERR_INVALID_ARG;
+    if (voff[g + 1] - voff[g] > (int64_t)INT32_MAX) return MSTX_ERR_INVALID_ARG;
+    if (eoff[g + 1] - eoff[g] > (int64_t)0xFFFFFFFFLL) return MSTX_ERR_TOO_LARGE;
+  }
+  if (eoff[G] > 0 && (!src || !dst || !w || !in_mst)) return MSTX_ERR_INVALID_ARG;
+  return MSTX_OK;
+}
+
+int solve_batched(int32_t G, const int64_t* voff, const int64_t* eoff, const int32_t* src, const int32_t* dst,
+                  const uint32_t* w, uint8_t* in_mst, uint64_t* total, int32_t* status, hipStream_t s) {
+  t_last_stats.clear();
+  if (G == 0) return MSTX_OK;
+  // graphs small enough for one workgroup, largest first; the others go in chunks
+  std::vector<int32_t> small, large;
+  for (int32_t g = 0; g < G; ++g) {
+    if (voff[g + 1] - voff[g] <= kSmallN) small.push_back(g);
+    else large.push_back(g);
+  }
+  std::stable_sort(small.begin(), small.end(), [&](int32_t a, int32_t b) {
+    return eoff[a + 1] - eoff[a] > eoff[b + 1] - eoff[b];
+  });
+  // chunks of large graphs: consecutive in `large`, union within the bucket-mode limit
+  std::vector<int32_t> chunk_begin{0};
+  std::vector<int64_t> cvert, cedge;  // per chunk: (ng + 1) offsets each, concatenated
+  std::vector<int64_t> meta_at;      // start of each chunk's offsets in cvert/cedge
+  int64_t max_chunk_n = 0, max_chunk_m = 0;
+  {
+    int64_t cn = 0, cm = 0;
+    for (size_t i = 0; i < large.size(); ++i) {
+      const int32_t g = large[i];
+      const int64_t ng = voff[g + 1] - voff[g], mg = eoff[g + 1] - eoff[g];
+      if ((int)i > chunk_begin.back() && (cn + ng > kBucketMaxComponents || cm + mg > (int64_t)0xFFFFFFFFLL)) {
+        chunk_begin.push_back((int32_t)i);
+        cn = cm = 0;
+      }
+      cn += ng;
+      cm += mg;
+      max_chunk_n = std::max(max_chunk_n, cn);
+      max_chunk_m = std::max(max_chunk_m, cm);
+    }
+    chunk_begin.push_back((int32_t)large.size());
+    for (size_t c = 0; c + 1 < chunk_begin.size(); ++c) {
+      meta_at.push_back((int64_t)cvert.size());
+      int64_t a = 0, b = 0;
+      for (int32_t i = chunk_begin[c]; i < chunk_begin[c + 1]; ++i) {
+        cvert.push_back(a);
+        cedge.push_back(b);
+        a += voff[large[i] + 1] - voff[large[i]];
+        b += eoff[large[i] + 1] - eoff[large[i]];
+      }
+      cvert.push_back(a);
+      cedge.push_back(b);
+    }
+  }
+  if (max_chunk_n > INT32_MAX) return MSTX_ERR_TOO_LARGE;
+  const Layout L = plan((int32_t)std::max<int64_t>(max_chunk_n, 1), std::max<int64_t>(max_chunk_m, 1));
+  const BatchLayout BL = plan_batch(G, (int64_t)small.size(), (int64_t)large.size(), (int64_t)cvert.size(),
+                                    max_chunk_m);
+  if (L.bytes + BL.bytes > workspace_limit()) return MSTX_ERR_OUT_OF_MEMORY;
+
+  DeviceCache* dc = nullptr;
+  std::unique_lock<std::mutex> lock;
+  int rc = acquire(dc, lock, large.empty() ? 0 : L.bytes);
+  if (rc != MSTX_OK) return rc;
+  rc = grow_aux(dc, BL.bytes);
+  if (rc != MSTX_OK) return rc;
+  void* A = dc->aux;
+  auto* d_voff = at<int64_t>(A, BL.voff);
+  auto* d_eoff = at<int64_t>(A, BL.eoff);
+  auto* d_small = at<int32_t>(A, BL.small);
+  auto* d_large = at<int32_t>(A, BL.large);
+  auto* d_cvert = at<int64_t>(A, BL.cvert);
+  auto* d_cedge = at<int64_t>(A, BL.cedge);
+  auto* d_gbad = at<int32_t>(A, BL.gbad);
+  auto* gsrc = at<int32_t>(A, BL.gsrc);
+  auto* gdst = at<int32_t>(A, BL.gdst);
+  auto* gw = at<uint32_t>(A, BL.gw);
+  auto* cin = at<uint8_t>(A, BL.cin);
+  auto* ctotal = at<uint64_t>(A, BL.total);
+  auto* tot = reinterpret_cast<unsigned long long*>(total);
+
+  HIP_OK(hipMemcpyAsync(d_voff, voff, 8 * ((size_t)G + 1), hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(d_eoff, eoff, 8 * ((size_t)G + 1), hipMemcpyHostToDevice, s));
+  if (!small.empty())
+    HIP_OK(hipMemcpyAsync(d_small, small.data(), 4 * small.size(), hipMemcpyHostToDevice, s));
+  if (!large.empty()) {
+    HIP_OK(hipMemcpyAsync(d_large, large.data(), 4 * large.size(), hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(d_cvert, cvert.data(), 8 * cvert.size(), hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(d_cedge, cedge.data(), 8 * cedge.size(), hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemsetAsync(d_gbad, 0, 4 * large.size(), s));
+  }
+  if (eoff[G] > 0) HIP_OK(hipMemsetAsync(in_mst, 0, (size_t)eoff[G], s));
+  HIP_OK(launch_small_solve(d_small, (int)small.size(), d_voff, d_eoff, src, dst, w, in_mst, tot, status, s));
+
+  for (size_t c = 0; c + 1 < chunk_begin.size(); ++c) {
+    const int32_t i0 = chunk_begin[c], ng = chunk_begin[c + 1] - i0;
+    const int64_t at_meta = meta_at[c];
+    const int64_t cn = cvert[at_meta + ng], cm = cedge[at_meta + ng];
+    HIP_OK(launch_gather(d_large + i0, ng, d_voff, d_eoff, d_cvert + at_meta, d_cedge + at_meta, cm, src, dst, w,
+                         gsrc, gdst, gw, d_gbad + i0, s));
+    if (cm > 0) {
+      const Layout Lc = plan((int32_t)cn, cm);
+      rc = solve_locked(dc, Lc, (int32_t)cn, cm, gsrc, gdst, gw, cin, ctotal, s);
+      if (rc < 0) return rc;
+    } else {
+      HIP_OK(hipMemsetAsync(cin, 0, 1, s));
+    }
+    HIP_OK(launch_graph_epilogue(d_large + i0, ng, d_voff, d_eoff, d_cedge + at_meta, cin, gw, d_gbad + i0,
+                                 in_mst, tot, status, s));
+  }
+  HIP_OK(hipStreamSynchronize(s));
+  return MSTX_OK;
+}
+
 int select_min_edges(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, const uint32_t* w,
                      uint64_t* out_best, hipStream_t s) {
   const Layout L = plan(n, m);
@@ -553,6 +731,38 @@ int mst_solve(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, cons
   if (rc != MSTX_OK) return rc;
   if (!out_total_weight || (m > 0 && !out_in_mst)) return MSTX_ERR_INVALID_ARG;
   return mstx::solve(n, m, src, dst, w, out_in_mst, out_total_weight, (hipStream_t)stream);
+}
+
+int mst_solve_batched(int32_t num_graphs, const int64_t* vertex_offsets, const int64_t* edge_offsets,
+                      const int32_t* src, const int32_t* dst, const uint32_t* w, uint8_t* out_in_mst,
+                      uint64_t* out_total_weight, int32_t* out_status, void* stream) {
+  int rc = mstx::check_batch_args(num_graphs, vertex_offsets, edge_offsets, src, dst, w, out_in_mst,
+                                  out_total_weight, out_status);
+  if (rc != MSTX_OK) return rc;
+  return mstx::solve_batched(num_graphs, vertex_offsets, edge_offsets, src, dst, w, out_in_mst, out_total_weight,
+                             out_status, (hipStream_t)stream);
+}
+
+size_t mst_batched_workspace_bytes(int32_t num_graphs, const int64_t* vertex_offsets, const int64_t* edge_offsets) {
+  if (mstx::check_batch_args(num_graphs, vertex_offsets, edge_offsets, (void*)1, (void*)1, (void*)1, (void*)1,
+                             (void*)1, (void*)1) != MSTX_OK)
+    return 0;
+  int64_t cn = 0, cm = 0, maxn = 0, maxm = 0, nsmall = 0, nlarge = 0;
+  for (int32_t g = 0; g < num_graphs; ++g) {
+    const int64_t ng = vertex_offsets[g + 1] - vertex_offsets[g], mg = edge_offsets[g + 1] - edge_offsets[g];
+    if (ng <= mstx::kSmallN) {
+      ++nsmall;
+      continue;
+    }
+    ++nlarge;
+    if (cn > 0 && (cn + ng > mstx::kBucketMaxComponents || cm + mg > (int64_t)0xFFFFFFFFLL)) cn = cm = 0;
+    cn += ng;
+    cm += mg;
+    maxn = std::max(maxn, cn);
+    maxm = std::max(maxm, cm);
+  }
+  const size_t solve_ws = nlarge ? mstx::plan((int32_t)std::min<int64_t>(maxn, INT32_MAX), maxm).bytes : 0;
+  return solve_ws + mstx::plan_batch(num_graphs, nsmall, nlarge, 2 * nlarge + 2, maxm).bytes;
 }
 
 int mst_select_min_edges(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, const uint32_t* w,

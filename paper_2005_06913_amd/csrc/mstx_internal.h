@@ -97,7 +97,24 @@ __host__ __device__ inline bool use_slab(const unsigned long long* slab, int64_t
   return slab != nullptr && nr > kSlabMin && (int64_t)nwg * nr <= cap;
 }
 
+// Batched solve: graphs with at most kSmallN vertices are solved by one
+// workgroup each with the vertex state in LDS (best u64 + comp + parents).
+static constexpr int32_t kSmallN = 8192;
+static constexpr int kSmallSolveLds = kSmallN * (8 + 4 + 4);
+
 hipError_t configure_kernels();
+hipError_t configure_batched_kernels();
+hipError_t launch_small_solve(const int32_t* glist, int num, const int64_t* voff, const int64_t* eoff,
+                              const int32_t* src, const int32_t* dst, const uint32_t* w, uint8_t* in_mst,
+                              unsigned long long* total, int32_t* status, hipStream_t s);
+hipError_t launch_gather(const int32_t* glist, int ng, const int64_t* voff, const int64_t* eoff,
+                         const int64_t* cvert, const int64_t* cedge, int64_t chunk_edges, const int32_t* src,
+                         const int32_t* dst, const uint32_t* w, int32_t* gsrc, int32_t* gdst, uint32_t* gw,
+                         int32_t* gbad, hipStream_t s);
+hipError_t launch_graph_epilogue(const int32_t* glist, int ng, const int64_t* voff, const int64_t* eoff,
+                                 const int64_t* cedge, const uint8_t* cin_mst, const uint32_t* gw,
+                                 const int32_t* gbad, uint8_t* in_mst, unsigned long long* total, int32_t* status,
+                                 hipStream_t s);
 hipError_t launch_init(int32_t n, unsigned long long* best, int32_t* parent, DevState* st, int grid,
                        hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, int64_t count, unsigned long long v, int grid,

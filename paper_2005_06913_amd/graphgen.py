@@ -41,6 +41,8 @@ __all__ = [
     "complete_graph",
     "workload",
     "WORKLOADS",
+    "Batch",
+    "batch",
 ]
 
 
@@ -301,3 +303,65 @@ def workload(name: str) -> Graph:
         raise KeyError(f"unknown workload {name!r}; known: {sorted(WORKLOADS)}")
     return WORKLOADS[name]()
 
+
+
+@dataclass
+class Batch:
+    """Independent graphs concatenated: graph g owns vertices [0, n_g) (local ids) and
+    edges [edge_offsets[g], edge_offsets[g+1]) of src/dst/w."""
+
+    vertex_offsets: np.ndarray  # int64 [G+1]
+    edge_offsets: np.ndarray  # int64 [G+1]
+    src: np.ndarray  # int32 [sum m], local ids
+    dst: np.ndarray
+    w: np.ndarray  # uint32
+    name: str = ""
+
+    @property
+    def num_graphs(self) -> int:
+        return int(self.vertex_offsets.shape[0] - 1)
+
+    def graph(self, g: int) -> Graph:
+        a, b = int(self.edge_offsets[g]), int(self.edge_offsets[g + 1])
+        n = int(self.vertex_offsets[g + 1] - self.vertex_offsets[g])
+        return Graph(n, self.src[a:b], self.dst[a:b], self.w[a:b], f"{self.name}[{g}]")
+
+
+def batch(num_graphs: int, seed: int, n_lo: int = 64, n_hi: int = 65536, d_lo: float = 4.0,
+          d_hi: float = 32.0, name: str | None = None) -> Batch:
+    """Independent connected graphs: n log-uniform in [n_lo, n_hi], average degree uniform in
+    [d_lo, d_hi], a random recursive spanning tree plus uniform random extra pairs (no
+    self-loops; parallel edges possible), weights a random permutation of 1..m per graph,
+    random edge order and orientation.  Each graph draws from its own spawned seed."""
+    ss = np.random.SeedSequence(seed)
+    kids = ss.spawn(num_graphs + 1)
+    top = np.random.default_rng(kids[-1])
+    ns = np.round(np.exp(top.uniform(np.log(n_lo), np.log(n_hi), num_graphs))).astype(np.int64)
+    ds = top.uniform(d_lo, d_hi, num_graphs)
+    ms = np.round(ns * ds / 2).astype(np.int64)
+    ms = np.clip(ms, ns - 1, ns * (ns - 1) // 2)
+    voff = np.zeros(num_graphs + 1, np.int64)
+    eoff = np.zeros(num_graphs + 1, np.int64)
+    voff[1:] = np.cumsum(ns)
+    eoff[1:] = np.cumsum(ms)
+    total = int(eoff[-1])
+    src = np.empty(total, np.int32)
+    dst = np.empty(total, np.int32)
+    w = np.empty(total, np.uint32)
+    for g in range(num_graphs):
+        rng = np.random.default_rng(kids[g])
+        n, m = int(ns[g]), int(ms[g])
+        tu, tv = random_tree_edges(n, rng)
+        k = m - (n - 1)
+        u = rng.integers(0, n, k, dtype=np.int64)
+        v = (u + 1 + rng.integers(0, n - 1, k, dtype=np.int64)) % n if n > 1 else u
+        a = np.concatenate([tu, u])
+        b = np.concatenate([tv, v])
+        order = rng.permutation(m)
+        a, b = a[order], b[order]
+        flip = rng.random(m) < 0.5
+        lo, hi = int(eoff[g]), int(eoff[g + 1])
+        src[lo:hi] = np.where(flip, b, a)
+        dst[lo:hi] = np.where(flip, a, b)
+        w[lo:hi] = rng.permutation(m) + 1
+    return Batch(voff, eoff, src, dst, w, name or f"batch_G{num_graphs}_s{seed}")
