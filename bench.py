@@ -34,7 +34,11 @@ WORKLOAD_TEXT = {
     "grid_1024x1024": "1024x1024 4-neighbour grid, n=1048576, m=2095104, distinct uint32 weights, seed 3",
     "rmat_s22_e26": "R-MAT scale 22, 2^26 samples (a,b,c,d)=(.57,.19,.19,.05), loops/duplicates removed, "
                     "made connected by a random spanning tree, distinct uint32 weights, seed 4",
+    "batched_4096": "4096 independent graphs, n log-uniform in [64, 65536], average degree uniform in [4, 32], "
+                    "random spanning tree + uniform extra pairs (no loops), weights a permutation of 1..m per "
+                    "graph, local ids, int64 offsets, seed 5",
 }
+BATCHES = {"batched_4096": dict(num_graphs=4096, seed=5)}
 
 
 def log(msg):
@@ -131,6 +135,114 @@ def cpu_baseline(g, budget_s: float):
                       f"({per * 1e3:.1f} ms each)", "ms_per_solve": per * 1e3}, res
 
 
+def cpu_baseline_batched(b, budget_s: float):
+    """The oracle (Kruskal, plain C) on a prefix of the batch's graphs, one graph per host thread."""
+    import concurrent.futures as cf
+
+    import oracle
+
+    orc = oracle.default()
+    cores = os.cpu_count() or 1
+    t0 = time.perf_counter()
+    done = 0
+    with cf.ThreadPoolExecutor(max_workers=cores) as ex:
+        while done < b.num_graphs and time.perf_counter() - t0 < budget_s:
+            chunk = list(range(done, min(b.num_graphs, done + cores)))
+            list(ex.map(lambda g: orc.kruskal(*(lambda x: (x.n, x.src, x.dst, x.w))(b.graph(g))), chunk))
+            done += len(chunk)
+    el = time.perf_counter() - t0
+    return {"value": done / el, "unit": "solves/s", "cores": cores, "kind": "oracle",
+            "sample": f"the first {done} of {b.num_graphs} graphs of the same batch, Kruskal per graph, "
+                      f"{cores} host threads ({el:.1f} s)"}
+
+
+def bench_batched(args, dev):
+    """Batched solves per second: one mst_solve_batched call per step, compared with the plain
+    per-graph path (one mst_solve call per graph) on the same GPU, bit-exact."""
+    import numpy as np
+    import torch
+
+    import paper_2005_06913_amd as P
+    from paper_2005_06913_amd import graphgen as G
+
+    P.load_library()
+    log(f"[bench] generating {args.workload}")
+    b = G.batch(**BATCHES[args.workload])
+    m = int(b.edge_offsets[-1])
+    Gn = b.num_graphs
+    src = torch.from_numpy(b.src).to(dev)
+    dst = torch.from_numpy(b.dst).to(dev)
+    w = torch.from_numpy(b.w).to(dev)
+    in_mst = torch.empty(m, dtype=torch.uint8, device=dev)
+    total = torch.empty(Gn, dtype=torch.uint64, device=dev)
+    status = torch.empty(Gn, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        rc = P.mst_solve_batched(b.vertex_offsets, b.edge_offsets, src, dst, w, in_mst, total, status, stream)
+        if rc < 0:
+            raise P.MstxError(rc)
+
+    log(f"[bench] warmup {args.warmup}")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log(f"[bench] timed {args.steps} batched steps")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ms_per_step = (time.perf_counter() - t0) * 1e3 / args.steps
+    got = in_mst.cpu().numpy()
+    got_tot = total.view(torch.int64).cpu().numpy()
+    got_st = status.cpu().numpy()
+
+    # plain path: one mst_solve per graph, same device arrays
+    log("[bench] per-graph path")
+    one_mst = torch.empty(m, dtype=torch.uint8, device=dev)
+    one_tot = torch.empty(1, dtype=torch.uint64, device=dev)
+    tots = np.zeros(Gn, np.int64)
+    sts = np.zeros(Gn, np.int32)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for g in range(Gn):
+        a, c = int(b.edge_offsets[g]), int(b.edge_offsets[g + 1])
+        n = int(b.vertex_offsets[g + 1] - b.vertex_offsets[g])
+        sts[g] = P.mst_solve(n, src[a:c], dst[a:c], w[a:c], one_mst[a:c], one_tot, stream)
+        tots[g] = int(one_tot.view(torch.int64).item())
+    torch.cuda.synchronize()
+    per_graph_s = time.perf_counter() - t0
+    same = bool(np.array_equal(one_mst.cpu().numpy(), got) and np.array_equal(tots, got_tot)
+                and np.array_equal(sts, got_st))
+    out = {
+        "metric": METRIC,
+        "value": Gn / (ms_per_step * 1e-3),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {WORKLOAD_TEXT[args.workload]}", "graphs": Gn,
+                   "sum_n": int(b.vertex_offsets[-1]), "sum_m": m, "leg": "batched solves",
+                   "edges_per_s": m / (ms_per_step * 1e-3)},
+        "roofline": None,
+        "per_graph_path": {"value": Gn / per_graph_s, "unit": "solves/s", "ms_per_batch": per_graph_s * 1e3,
+                           "bit_exact_vs_batched": same},
+        "speedup_vs_per_graph": (per_graph_s * 1e3) / ms_per_step,
+        "status_counts": {int(k): int(v) for k, v in zip(*np.unique(got_st, return_counts=True))},
+    }
+    if not args.no_cpu_baseline:
+        log(f"[bench] cpu oracle leg (~{args.cpu_seconds:.0f} s)")
+        out["cpu_baseline"] = cpu_baseline_batched(b, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -178,6 +290,8 @@ def main() -> int:
         torch.cuda.synchronize()
         print(json.dumps({"calibration": "copy", "bytes_read": nbytes, "bytes_written": nbytes}))
         return 0
+    if args.workload in BATCHES:
+        return bench_batched(args, dev)
     P.load_library()
     log(f"[bench] generating {args.workload}")
     g = G.workload(args.workload)
