@@ -39,6 +39,9 @@ WORKLOAD_TEXT = {
                     "graph, local ids, int64 offsets, seed 5",
 }
 BATCHES = {"batched_4096": dict(num_graphs=4096, seed=5)}
+WORKLOAD_TEXT["served"] = ("Poisson request stream, each request one connected random graph: n log-uniform in "
+                           "[1024, 1048576], average degree uniform in [4, 32], random spanning tree + uniform "
+                           "extra pairs, weights a permutation of 1..m, seed 6")
 
 
 def log(msg):
@@ -243,15 +246,97 @@ def bench_batched(args, dev):
     return 0
 
 
+def bench_served(args, dev):
+    """p50/p99 latency and solves/s of the continuous-batching server against the plain
+    one-request-at-a-time server, at several Poisson request rates (multiples of the plain
+    server's saturated rate), with bit-exact agreement between the two."""
+    import numpy as np
+    import torch
+
+    from paper_2005_06913_amd import graphgen as G
+    from paper_2005_06913_amd import serve
+
+    log("[bench] generating requests")
+    b = G.batch(args.requests, seed=6, n_lo=1024, n_hi=1 << 20)
+
+    def pinned(a):
+        t = torch.empty(a.shape[0], dtype=torch.from_numpy(a[:0]).dtype, pin_memory=True)
+        t.copy_(torch.from_numpy(a))
+        return t.numpy()
+
+    graphs = []
+    for g in range(b.num_graphs):
+        x = b.graph(g)
+        graphs.append((x.n, pinned(x.src), pinned(x.dst), pinned(x.w)))
+
+    def fresh():
+        return [serve.Request(i, n, s, d, w) for i, (n, s, d, w) in enumerate(graphs)]
+
+    def run(kind, qps, seed):
+        reqs = fresh()
+        if kind == "plain":
+            srv = serve.PlainServer(device=dev).start()
+        else:
+            ex = serve.GpuExecutor(slots=args.slots, device=dev)
+            srv = serve.MstServer(ex, slots=args.slots, hbm_budget_bytes=args.hbm_budget_gib << 30).start()
+        wall = serve.poisson_replay(srv, reqs, qps=qps, seed=seed)
+        srv.close()
+        return reqs, serve.latency_summary(reqs, wall)
+
+    log("[bench] warmup")
+    run("served", 1e9, 0)
+    run("plain", 1e9, 0)
+    log("[bench] saturated rates")
+    plain_reqs, plain_sat = run("plain", 1e9, 1)
+    served_reqs, served_sat = run("served", 1e9, 1)
+    same = all(a.status == b_.status and a.total == b_.total and np.array_equal(a.in_mst, b_.in_mst)
+               for a, b_ in zip(plain_reqs, served_reqs))
+    mu = plain_sat["solves_per_s"]
+    points = []
+    for f in (0.5, 0.9, 1.5, 3.0):
+        log(f"[bench] qps {f:.1f} x plain rate")
+        _, p = run("plain", f * mu, 10 + int(f * 10))
+        _, s = run("served", f * mu, 10 + int(f * 10))
+        points.append({"qps": f * mu, "x_plain_rate": f, "plain": p, "served": s})
+    m = int(b.edge_offsets[-1])
+    out = {
+        "metric": METRIC,
+        "value": served_sat["solves_per_s"],
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.requests,
+        "warmup": 1,
+        "ms_per_step": 1e3 / served_sat["solves_per_s"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": f"served: {WORKLOAD_TEXT['served']}", "requests": args.requests, "sum_m": m,
+                   "slots": args.slots, "hbm_budget_gib": args.hbm_budget_gib, "leg": "served solves",
+                   "latency_includes": "host-to-device copy of the request, solve, device-to-host of the result"},
+        "roofline": None,
+        "saturated": {"served": served_sat, "plain": plain_sat,
+                      "speedup_vs_plain": served_sat["solves_per_s"] / plain_sat["solves_per_s"]},
+        "qps_sweep": points,
+        "bit_exact_served_vs_plain": bool(same),
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="random_n1M_d16", choices=sorted(WORKLOAD_TEXT))
+    ap.add_argument("--workload", default="random_n1M_d16", choices=sorted(WORKLOAD_TEXT) + ["served"])
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="time budget of the CPU oracle leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cold-reps", type=int, default=5, help="extra solves after a 1 GiB cache flush")
+    ap.add_argument("--requests", type=int, default=160, help="served workload: requests per replay")
+    ap.add_argument("--slots", type=int, default=3, help="served workload: concurrent server slots")
+    ap.add_argument("--hbm-budget-gib", type=int, default=96, help="served workload: device memory budget")
     ap.add_argument("--summarize-pmc", nargs=4, metavar=("COPY_FETCH", "COPY_WRITE", "SOLVE_FETCH", "SOLVE_WRITE"),
                     help="fold four rocprofv3 --pmc output directories into the traffic summary and exit")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -292,6 +377,8 @@ def main() -> int:
         return 0
     if args.workload in BATCHES:
         return bench_batched(args, dev)
+    if args.workload == "served":
+        return bench_served(args, dev)
     P.load_library()
     log(f"[bench] generating {args.workload}")
     g = G.workload(args.workload)

@@ -31,8 +31,10 @@
  *     m <= 0xFFFFFFFF (the edge index must fit the key's low 32 bits).
  *   - A negative status means the outputs are unspecified.
  *   - Scratch memory (the workspace) is owned by the library, cached per
- *     device and reused across calls; calls on one device are serialised by
- *     a mutex.  MSTX_WORKSPACE_LIMIT_BYTES (environment, bytes) caps it.
+ *     (device, stream) and reused across calls: calls on the same stream are
+ *     serialised by a mutex, calls on different streams run concurrently,
+ *     each with its own workspace.  MSTX_WORKSPACE_LIMIT_BYTES (environment,
+ *     bytes) caps one call's workspace; mst_workspace_release frees it.
  */
 #ifndef MSTX_H
 #define MSTX_H
@@ -155,6 +157,13 @@ size_t mst_workspace_bytes(int32_t n, int64_t m);
 int mst_profile_enable(int enable);
 int mst_profile_read(double* out_ms, int64_t* out_launches, double* out_bytes, int32_t kinds);
 const char* mst_profile_kernel_name(int kind);
+
+/*
+ * Frees the workspace cached for (current device, stream), after the stream's
+ * work has finished.  For memory-budgeted callers (a server that retires a
+ * stream).  Returns MSTX_OK or MSTX_ERR_DEVICE.
+ */
+int mst_workspace_release(void* stream);
 
 /* Static description of a status code. */
 const char* mst_status_string(int status);

@@ -29,5 +29,6 @@ from .binding import (  # noqa: F401
     mst_solve_batched,
     mst_status_string,
     mst_workspace_bytes,
+    mst_workspace_release,
     solve,
 )

@@ -26,7 +26,7 @@ MSTX_ERR_DEVICE = -5
 
 EXPORTS = ("mst_solve", "mst_solve_batched", "mst_batched_workspace_bytes", "mst_select_min_edges",
            "mst_last_round_stats", "mst_workspace_bytes", "mst_status_string", "mst_profile_enable",
-           "mst_profile_read", "mst_profile_kernel_name")
+           "mst_profile_read", "mst_profile_kernel_name", "mst_workspace_release")
 
 _lib = None
 
@@ -65,6 +65,8 @@ def load_library(path: str = LIB_PATH):
     lib.mst_profile_enable.restype = ctypes.c_int
     lib.mst_profile_read.argtypes = [p, p, p, i32]
     lib.mst_profile_read.restype = ctypes.c_int
+    lib.mst_workspace_release.argtypes = [p]
+    lib.mst_workspace_release.restype = ctypes.c_int
     lib.mst_profile_kernel_name.argtypes = [ctypes.c_int]
     lib.mst_profile_kernel_name.restype = ctypes.c_char_p
     _lib = lib
@@ -91,6 +93,11 @@ def _dev_ptr(t, dtype, name, numel=None):
     if numel is not None and t.numel() != numel:
         raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
     return ctypes.c_void_p(t.data_ptr() if t.numel() else 0)
+
+
+def mst_workspace_release(stream=None) -> int:
+    """Free the library's workspace cached for (current device, stream)."""
+    return int(load_library().mst_workspace_release(_stream_handle(stream)))
 
 
 def mst_status_string(status: int) -> str:

@@ -17,7 +17,10 @@
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <memory>
 #include <mutex>
+#include <utility>
 #include <vector>
 
 #include "mstx.h"
@@ -90,8 +93,10 @@ struct DeviceCache {
   size_t aux_bytes = 0;
 };
 
-constexpr int kMaxDevices = 64;
-DeviceCache g_dev[kMaxDevices];
+// One cache per (device, stream): calls on different streams have their own
+// workspace and run concurrently; calls on the same stream are serialised.
+std::mutex g_caches_mu;
+std::map<std::pair<int, hipStream_t>, std::unique_ptr<DeviceCache>> g_caches;
 
 thread_local std::vector<int64_t> t_last_stats;
 
@@ -121,12 +126,16 @@ int check_args(int32_t n, int64_t m, const void* src, const void* dst, const voi
     if ((expr) != hipSuccess) return MSTX_ERR_DEVICE; \
   } while (0)
 
-// Locks the device cache, grows the workspace to `bytes`.
-int acquire(DeviceCache*& dc, std::unique_lock<std::mutex>& lock, size_t bytes) {
+// Locks the cache of (current device, stream), grows its workspace to `bytes`.
+int acquire(DeviceCache*& dc, std::unique_lock<std::mutex>& lock, size_t bytes, hipStream_t stream) {
   int dev = 0;
   HIP_OK(hipGetDevice(&dev));
-  if (dev < 0 || dev >= kMaxDevices) return MSTX_ERR_DEVICE;
-  dc = &g_dev[dev];
+  {
+    std::lock_guard<std::mutex> g(g_caches_mu);
+    auto& slot = g_caches[{dev, stream}];
+    if (!slot) slot.reset(new DeviceCache());
+    dc = slot.get();
+  }
   lock = std::unique_lock<std::mutex>(dc->mu);
   if (!dc->configured) {
     HIP_OK(hipHostMalloc((void**)&dc->host_rounds, sizeof(HostRound) * (kMaxRounds + 1), hipHostMallocDefault));
@@ -502,7 +511,7 @@ int solve(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, const ui
   if (n == 0) return MSTX_ERR_VERTEX_RANGE;  // m > 0 edges, no valid vertex id
   DeviceCache* dc = nullptr;
   std::unique_lock<std::mutex> lock;
-  int rc = acquire(dc, lock, L.bytes);
+  int rc = acquire(dc, lock, L.bytes, s);
   if (rc != MSTX_OK) return rc;
   return solve_locked(dc, L, n, m, src, dst, w, in_mst, total, s);
 }
@@ -624,7 +633,7 @@ int solve_batched(int32_t G, const int64_t* voff, const int64_t* eoff, const int
 
   DeviceCache* dc = nullptr;
   std::unique_lock<std::mutex> lock;
-  int rc = acquire(dc, lock, large.empty() ? 0 : L.bytes);
+  int rc = acquire(dc, lock, large.empty() ? 0 : L.bytes, s);
   if (rc != MSTX_OK) return rc;
   rc = grow_aux(dc, BL.bytes);
   if (rc != MSTX_OK) return rc;
@@ -684,7 +693,7 @@ int select_min_edges(int32_t n, int64_t m, const int32_t* src, const int32_t* ds
   if (n == 0) return MSTX_OK;
   DeviceCache* dc = nullptr;
   std::unique_lock<std::mutex> lock;
-  int rc = acquire(dc, lock, L.bytes);
+  int rc = acquire(dc, lock, L.bytes, s);
   if (rc != MSTX_OK) return rc;
   void* B = dc->base;
   Solve S{};
@@ -809,6 +818,27 @@ int mst_profile_read(double* out_ms, int64_t* out_launches, double* out_bytes, i
 
 const char* mst_profile_kernel_name(int kind) {
   return (kind >= 0 && kind < mstx::kKinds) ? mstx::kKindNames[kind] : "";
+}
+
+int mst_workspace_release(void* stream) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return MSTX_ERR_DEVICE;
+  std::unique_ptr<mstx::DeviceCache> victim;
+  {
+    std::lock_guard<std::mutex> g(mstx::g_caches_mu);
+    auto it = mstx::g_caches.find({dev, (hipStream_t)stream});
+    if (it == mstx::g_caches.end()) return MSTX_OK;
+    std::lock_guard<std::mutex> l(it->second->mu);  // no call of this stream is running
+    victim = std::move(it->second);
+    mstx::g_caches.erase(it);
+  }
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return MSTX_ERR_DEVICE;
+  if (victim->base && hipFree(victim->base) != hipSuccess) return MSTX_ERR_DEVICE;
+  if (victim->aux && hipFree(victim->aux) != hipSuccess) return MSTX_ERR_DEVICE;
+  if (victim->host_rounds && hipHostFree(victim->host_rounds) != hipSuccess) return MSTX_ERR_DEVICE;
+  for (auto& e : victim->round_ev)
+    if (e) (void)hipEventDestroy(e);
+  return MSTX_OK;
 }
 
 size_t mst_workspace_bytes(int32_t n, int64_t m) {

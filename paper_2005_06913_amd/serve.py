@@ -1,0 +1,332 @@
+"""Continuous-batching MST server on one GPU.
+
+Requests (one graph each) arrive over time.  The server owns `slots` workers;
+each worker has its own HIP stream, and therefore its own library workspace,
+so the work of different slots overlaps on the device.  Whenever a worker is
+free it takes work from the head of the queue, within its share of the
+device-memory budget (admission by HBM budget):
+
+* a request with at least `solo_edges` edges already fills the GPU: it is
+  solved alone with ``mst_solve``;
+* otherwise the worker takes the queued requests up to the next large one,
+  at most `batch_edges` edges and `max_batch` requests, copies them to the
+  device and solves them with one ``mst_solve_batched`` call.
+
+Requests that arrive while other batches are on the GPU are admitted by the
+next free worker: batching is continuous, not a queue in front of a single
+solver, and the caps keep several workers busy at once.
+
+Every request's result is exactly the minimum spanning forest of its graph
+(a disjoint union of graphs has the union of their forests as its forest),
+so it is the same whether solved alone or in a mix; ``tests/test_serve.py``
+and ``tests/test_gpu_serve.py`` check that.
+
+The scheduling logic is independent of the device: an executor object does
+the solving (``GpuExecutor`` here; the CPU tests use one backed by the
+oracle).  ``PlainServer`` is the baseline: one request at a time, one
+``mst_solve`` per request.
+"""
+
+from __future__ import annotations
+
+import collections
+import threading
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+MSTX_ERR_OUT_OF_MEMORY = -4
+
+
+@dataclass
+class Request:
+    """One MST query: a graph with local vertex ids [0, n)."""
+
+    rid: int
+    n: int
+    src: np.ndarray  # int32 [m]
+    dst: np.ndarray  # int32 [m]
+    w: np.ndarray  # uint32 [m]
+    arrival: float = 0.0  # time.perf_counter() when submitted
+    # filled in on completion
+    in_mst: np.ndarray | None = None
+    total: int = 0
+    status: int = 0
+    done_at: float = 0.0
+    batch_size: int = 0
+    slot: int = -1
+    done: threading.Event = field(default_factory=threading.Event)
+
+    @property
+    def m(self) -> int:
+        return int(self.src.shape[0])
+
+    @property
+    def latency(self) -> float:
+        return self.done_at - self.arrival
+
+    def data_bytes(self) -> int:
+        """Device bytes of the request's graph and outputs (src, dst, w, flags)."""
+        return 13 * self.m + 16
+
+
+def batch_offsets(reqs):
+    vo = np.zeros(len(reqs) + 1, np.int64)
+    eo = np.zeros(len(reqs) + 1, np.int64)
+    for i, r in enumerate(reqs):
+        vo[i + 1] = vo[i] + r.n
+        eo[i + 1] = eo[i] + r.m
+    return vo, eo
+
+
+class GpuExecutor:
+    """Solves batches on the GPU with ``mst_solve_batched``, one stream per slot."""
+
+    def __init__(self, slots: int, device=None):
+        import torch
+
+        from . import binding as B
+
+        self.torch = torch
+        self.B = B
+        self.dev = device or torch.device("cuda:0")
+        B.load_library()
+        # streams keep the default priority
+        self.streams = [torch.cuda.Stream(device=self.dev) for _ in range(slots)]
+
+    def batch_bytes(self, reqs, solo: bool = False) -> int:
+        if solo:
+            (r,) = reqs
+            return r.data_bytes() + self.B.mst_workspace_bytes(r.n, r.m)
+        vo, eo = batch_offsets(reqs)
+        return sum(r.data_bytes() for r in reqs) + self.B.mst_batched_workspace_bytes(vo, eo)
+
+    def execute(self, slot: int, reqs, solo: bool = False) -> None:
+        torch = self.torch
+        stream = self.streams[slot]
+        if solo:
+            (r,) = reqs
+            with torch.cuda.stream(stream):
+                src = torch.from_numpy(r.src).to(self.dev, non_blocking=True)
+                dst = torch.from_numpy(r.dst).to(self.dev, non_blocking=True)
+                w = torch.from_numpy(r.w).to(self.dev, non_blocking=True)
+                in_mst = torch.empty(r.m, dtype=torch.uint8, device=self.dev)
+                total = torch.empty(1, dtype=torch.uint64, device=self.dev)
+                r.status = self.B.mst_solve(r.n, src, dst, w, in_mst, total, stream)
+                r.in_mst = in_mst.cpu().numpy()
+                r.total = int(total.view(torch.int64).cpu().item())
+            return
+        vo, eo = batch_offsets(reqs)
+        m = int(eo[-1])
+        G = len(reqs)
+        with torch.cuda.stream(stream):
+            src = torch.empty(m, dtype=torch.int32, device=self.dev)
+            dst = torch.empty(m, dtype=torch.int32, device=self.dev)
+            w = torch.empty(m, dtype=torch.uint32, device=self.dev)
+            for r, a in zip(reqs, eo[:-1]):
+                a = int(a)
+                src[a:a + r.m].copy_(torch.from_numpy(r.src), non_blocking=True)
+                dst[a:a + r.m].copy_(torch.from_numpy(r.dst), non_blocking=True)
+                w[a:a + r.m].copy_(torch.from_numpy(r.w), non_blocking=True)
+            in_mst = torch.empty(m, dtype=torch.uint8, device=self.dev)
+            total = torch.empty(G, dtype=torch.uint64, device=self.dev)
+            status = torch.empty(G, dtype=torch.int32, device=self.dev)
+            rc = self.B.mst_solve_batched(vo, eo, src, dst, w, in_mst, total, status, stream)
+            if rc < 0:
+                for r in reqs:
+                    r.status = rc
+                return
+            flags = in_mst.cpu().numpy()
+            tot = total.view(torch.int64).cpu().numpy()
+            st = status.cpu().numpy()
+        for i, r in enumerate(reqs):
+            r.in_mst = flags[eo[i]:eo[i + 1]]
+            r.total = int(tot[i])
+            r.status = int(st[i])
+
+    def release(self):
+        for s in self.streams:
+            self.B.mst_workspace_release(s)
+
+
+class MstServer:
+    """Continuous batching over `executor` with `slots` concurrent workers.
+
+    hbm_budget_bytes is the device memory all in-flight batches may use
+    together; each worker forms its batch within an equal share.  A request
+    that does not fit a share on its own is rejected (status
+    MSTX_ERR_OUT_OF_MEMORY) instead of blocking the queue.
+    """
+
+    def __init__(self, executor, slots: int = 3, hbm_budget_bytes: int = 64 << 30, max_batch: int = 1024,
+                 solo_edges: int = 1 << 19, batch_edges: int = 1 << 22):
+        self.ex = executor
+        self.slots = slots
+        self.share = hbm_budget_bytes // slots
+        self.max_batch = max_batch
+        self.solo_edges = solo_edges
+        self.batch_edges = batch_edges
+        self.queue: collections.deque = collections.deque()
+        self.cv = threading.Condition()
+        self.stop = False
+        self.workers = []
+        self.batches = []  # (slot, sizes) log for tests
+        self.in_flight_bytes = 0
+        self.peak_in_flight_bytes = 0
+
+    def start(self):
+        for s in range(self.slots):
+            t = threading.Thread(target=self._worker, args=(s,), daemon=True)
+            t.start()
+            self.workers.append(t)
+        return self
+
+    def submit(self, req: Request) -> Request:
+        req.arrival = time.perf_counter()
+        with self.cv:
+            self.queue.append(req)
+            self.cv.notify()
+        return req
+
+    def close(self):
+        with self.cv:
+            self.stop = True
+            self.cv.notify_all()
+        for t in self.workers:
+            t.join()
+
+    def _take_batch(self):
+        """Work for one worker from the head of the queue (called with the lock held):
+        (requests, bytes, solo)."""
+        while self.queue:
+            r = self.queue[0]
+            solo = r.m >= self.solo_edges
+            need = self.ex.batch_bytes([r], solo)
+            if need <= self.share:
+                break
+            self.queue.popleft()  # can never fit: reject rather than block the queue
+            r.status = MSTX_ERR_OUT_OF_MEMORY
+            r.done_at = time.perf_counter()
+            r.done.set()
+        else:
+            return [], 0, False
+        if solo:
+            return [self.queue.popleft()], need, True
+        batch, used, edges = [self.queue.popleft()], need, r.m
+        while self.queue and len(batch) < self.max_batch:
+            r = self.queue[0]
+            if r.m >= self.solo_edges or edges + r.m > self.batch_edges:
+                break
+            need = self.ex.batch_bytes(batch + [r])
+            if need > self.share:
+                break
+            batch.append(self.queue.popleft())
+            used, edges = need, edges + r.m
+        return batch, used, False
+
+    def _worker(self, slot: int):
+        while True:
+            with self.cv:
+                while not self.queue and not self.stop:
+                    self.cv.wait()
+                if self.stop and not self.queue:
+                    return
+                batch, used, solo = self._take_batch()
+                self.in_flight_bytes += used
+                self.peak_in_flight_bytes = max(self.peak_in_flight_bytes, self.in_flight_bytes)
+            if not batch:
+                continue
+            self.ex.execute(slot, batch, solo)
+            now = time.perf_counter()
+            with self.cv:
+                self.in_flight_bytes -= used
+                self.batches.append((slot, [r.rid for r in batch]))
+            for r in batch:
+                r.done_at = now
+                r.batch_size = len(batch)
+                r.slot = slot
+                r.done.set()
+
+
+class PlainServer:
+    """Baseline: one worker, one request at a time, one ``mst_solve`` per request."""
+
+    def __init__(self, device=None):
+        import torch
+
+        from . import binding as B
+
+        self.torch = torch
+        self.B = B
+        self.dev = device or torch.device("cuda:0")
+        B.load_library()
+        self.queue: collections.deque = collections.deque()
+        self.cv = threading.Condition()
+        self.stop = False
+        self.stream = torch.cuda.Stream(device=self.dev)
+        self.worker = None
+
+    def start(self):
+        self.worker = threading.Thread(target=self._run, daemon=True)
+        self.worker.start()
+        return self
+
+    def submit(self, req: Request) -> Request:
+        req.arrival = time.perf_counter()
+        with self.cv:
+            self.queue.append(req)
+            self.cv.notify()
+        return req
+
+    def close(self):
+        with self.cv:
+            self.stop = True
+            self.cv.notify_all()
+        self.worker.join()
+
+    def _run(self):
+        torch = self.torch
+        while True:
+            with self.cv:
+                while not self.queue and not self.stop:
+                    self.cv.wait()
+                if self.stop and not self.queue:
+                    return
+                r = self.queue.popleft()
+            with torch.cuda.stream(self.stream):
+                src = torch.from_numpy(r.src).to(self.dev, non_blocking=True)
+                dst = torch.from_numpy(r.dst).to(self.dev, non_blocking=True)
+                w = torch.from_numpy(r.w).to(self.dev, non_blocking=True)
+                in_mst = torch.empty(r.m, dtype=torch.uint8, device=self.dev)
+                total = torch.empty(1, dtype=torch.uint64, device=self.dev)
+                r.status = self.B.mst_solve(r.n, src, dst, w, in_mst, total, self.stream)
+                r.in_mst = in_mst.cpu().numpy()
+                r.total = int(total.view(torch.int64).cpu().item())
+            r.done_at = time.perf_counter()
+            r.batch_size = 1
+            r.done.set()
+
+
+def poisson_replay(server, requests, qps: float, seed: int = 0):
+    """Submit `requests` with exponential inter-arrival times (rate qps) and wait for all."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / qps, len(requests))
+    t0 = time.perf_counter()
+    due = t0 + np.cumsum(gaps)
+    for r, t in zip(requests, due):
+        delay = t - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        server.submit(r)
+    for r in requests:
+        r.done.wait()
+    return time.perf_counter() - t0
+
+
+def latency_summary(requests, wall_s: float) -> dict:
+    lat = np.array([r.latency for r in requests]) * 1e3
+    return {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "mean_ms": float(lat.mean()), "max_ms": float(lat.max()),
+            "solves_per_s": len(requests) / wall_s,
+            "mean_batch": float(np.mean([r.batch_size for r in requests]))}

@@ -1,0 +1,106 @@
+"""Serving scheduler on the CPU with a fake executor backed by the oracle.
+
+Checks continuous batching (requests that arrive while batches are running
+are admitted by the next free slot), admission by memory budget, rejection
+of requests that can never fit, and that every result is the oracle's.
+"""
+
+import threading
+import time
+
+import numpy as np
+
+import oracle
+from paper_2005_06913_amd import graphgen as G
+from paper_2005_06913_amd import serve
+
+
+class FakeExecutor:
+    """Solves each request of a batch with the oracle after a short delay."""
+
+    def __init__(self, delay=0.01):
+        self.delay = delay
+        self.lock = threading.Lock()
+        self.active = 0
+        self.max_active = 0
+        self.seen = []
+
+    def batch_bytes(self, reqs, solo=False):
+        return sum(r.data_bytes() + 64 * r.m for r in reqs)
+
+    def execute(self, slot, reqs, solo=False):
+        assert not solo or len(reqs) == 1
+        with self.lock:
+            self.active += 1
+            self.max_active = max(self.max_active, self.active)
+            self.seen.append((slot, len(reqs), self.batch_bytes(reqs)))
+        time.sleep(self.delay)
+        for r in reqs:
+            k = oracle.kruskal(r.n, r.src, r.dst, r.w)
+            r.in_mst, r.total, r.status = k.in_mst, k.total, k.status
+        with self.lock:
+            self.active -= 1
+
+
+def make_requests(k, seed=0, n_hi=3000):
+    b = G.batch(k, seed=seed, n_lo=16, n_hi=n_hi)
+    return [serve.Request(i, *(lambda g: (g.n, g.src, g.dst, g.w))(b.graph(i))) for i in range(k)]
+
+
+def test_results_and_continuous_batching():
+    ex = FakeExecutor(delay=0.02)
+    srv = serve.MstServer(ex, slots=3, hbm_budget_bytes=3 << 30).start()
+    reqs = make_requests(120, seed=1)
+    wall = serve.poisson_replay(srv, reqs, qps=2000.0, seed=2)
+    srv.close()
+    for r in reqs:
+        k = oracle.kruskal(r.n, r.src, r.dst, r.w)
+        assert r.status == k.status == 0 and r.total == k.total
+        assert np.array_equal(r.in_mst, k.in_mst)
+    # arrivals outpace one 20 ms batch: later batches hold several requests, slots overlap
+    assert max(len(b[1]) for b in srv.batches) > 1
+    assert ex.max_active >= 2
+    assert len({b[0] for b in srv.batches}) >= 2
+    s = serve.latency_summary(reqs, wall)
+    assert s["p99_ms"] >= s["p50_ms"] > 0
+
+
+def test_budget_and_rejection():
+    ex = FakeExecutor(delay=0.0)
+    share_bytes = 4_000_000
+    srv = serve.MstServer(ex, slots=2, hbm_budget_bytes=2 * share_bytes).start()
+    reqs = make_requests(60, seed=3, n_hi=2000)
+    huge = serve.Request(999, 50_000, *(lambda g: (g.src, g.dst, g.w))(G.tree_plus_extra(50_000, 200_000, 4)))
+    reqs.append(huge)
+    serve.poisson_replay(srv, reqs, qps=5000.0, seed=4)
+    srv.close()
+    assert huge.status == serve.MSTX_ERR_OUT_OF_MEMORY
+    assert all(r.status == 0 for r in reqs[:-1])
+    assert all(nbytes <= share_bytes for _, _, nbytes in ex.seen)
+    assert srv.peak_in_flight_bytes <= 2 * share_bytes
+
+
+def test_fifo_order_within_slot():
+    ex = FakeExecutor(delay=0.005)
+    srv = serve.MstServer(ex, slots=1, hbm_budget_bytes=1 << 30).start()
+    reqs = make_requests(40, seed=5)
+    serve.poisson_replay(srv, reqs, qps=3000.0, seed=6)
+    srv.close()
+    order = [rid for _, ids in srv.batches for rid in ids]
+    assert order == sorted(order)
+
+
+def test_large_requests_run_alone_and_caps():
+    ex = FakeExecutor(delay=0.002)
+    srv = serve.MstServer(ex, slots=2, hbm_budget_bytes=1 << 30, solo_edges=20_000, batch_edges=30_000).start()
+    reqs = make_requests(50, seed=7, n_hi=6000)
+    serve.poisson_replay(srv, reqs, qps=5000.0, seed=8)
+    srv.close()
+    by_id = {r.rid: r for r in reqs}
+    for _, ids in srv.batches:
+        ms = [by_id[i].m for i in ids]
+        if any(m >= 20_000 for m in ms):
+            assert len(ids) == 1
+        else:
+            assert sum(ms) <= 30_000 or len(ids) == 1
+    assert all(r.status == 0 for r in reqs)
