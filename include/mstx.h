@@ -17,7 +17,9 @@
  * compare-and-swap hooking of the larger root under the smaller one, parent
  * pointers are compressed, components are renumbered densely, and edges that
  * became internal are dropped (the paper's "covered" edges).  Rounds repeat
- * until no component has an outgoing edge.
+ * until no component has an outgoing edge.  When few components remain the
+ * last round is a dense finish (contraction of the remaining graph to the
+ * lightest edge between every pair of components, see mst_set_dense_limit).
  *
  * Conventions for every entry point below:
  *   - Array arguments are DEVICE pointers (hipMalloc / torch CUDA memory on
@@ -139,14 +141,16 @@ size_t mst_workspace_bytes(int32_t n, int64_t m);
  * stream; after each solve the elapsed times, launch counts and algorithmic
  * bytes are accumulated per kernel (template instantiation, named as a
  * profiler lists it: "k_scan<mode, input, compact>", "k_bucket_min",
- * "k_slab_min", "k_hook", "k_compress", "k_finalize", "k_relabel").  Every
+ * "k_slab_min", "k_dense_finish", "k_hook", "k_compress", "k_finalize",
+ * "k_relabel").  Every
  * launch is counted, including launches that return at once (a minima mode
  * not chosen for the actual component count, the round enqueued after the
  * last one).  Algorithmic bytes are credited to the scan launch that did a
  * round's work: the edge stream read once (12 B per input edge, 16 B per
  * record), the previous round's label map read once (4 B per entry), the
  * minima initialised and written once (16 B per component) and the survivors
- * written once (16 B per record).
+ * written once (16 B per record); a dense round writes its pair table once
+ * (8 B per pair) instead of minima and survivors.
  *   mst_profile_enable: enable != 0 starts (and zeroes) the counters, 0 stops;
  *                       returns the previous state.
  *   mst_profile_read:   copies min(kinds, K) entries to host arrays; returns
@@ -161,9 +165,25 @@ const char* mst_profile_kernel_name(int kind);
 /*
  * Frees the workspace cached for (current device, stream), after the stream's
  * work has finished.  For memory-budgeted callers (a server that retires a
- * stream).  Returns MSTX_OK or MSTX_ERR_DEVICE.
+ * stream).  Must not run while another thread has a call in flight on the
+ * same stream.  Returns MSTX_OK or MSTX_ERR_DEVICE.
  */
 int mst_workspace_release(void* stream);
+
+/*
+ * Dense finish (a contraction of the graph that Section 2.1's cycle property
+ * allows: of the edges joining two components only the lightest can be in the
+ * tree).  When a round of mst_solve starts with at most `limit` components,
+ * that round keeps the lightest edge of every component pair (a table of
+ * limit * (limit - 1) / 2 keys in LDS) and one workgroup completes Boruvka on
+ * that small complete graph; it is the last round.  The tree is the same; the
+ * per-round statistics then end with that round, whose "edges added" is the
+ * sum over the rounds it replaces.  limit is clamped to [0, 198] (0: off,
+ * every round is a plain Boruvka round; the default is 198).  limit < 0 only
+ * queries.  Returns the previous limit.  Process-wide; read at the start of
+ * each call (mst_solve_batched's large graphs included).
+ */
+int32_t mst_set_dense_limit(int32_t limit);
 
 /* Static description of a status code. */
 const char* mst_status_string(int status);

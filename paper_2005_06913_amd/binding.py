@@ -26,7 +26,7 @@ MSTX_ERR_DEVICE = -5
 
 EXPORTS = ("mst_solve", "mst_solve_batched", "mst_batched_workspace_bytes", "mst_select_min_edges",
            "mst_last_round_stats", "mst_workspace_bytes", "mst_status_string", "mst_profile_enable",
-           "mst_profile_read", "mst_profile_kernel_name", "mst_workspace_release")
+           "mst_profile_read", "mst_profile_kernel_name", "mst_workspace_release", "mst_set_dense_limit")
 
 _lib = None
 
@@ -67,6 +67,8 @@ def load_library(path: str = LIB_PATH):
     lib.mst_profile_read.restype = ctypes.c_int
     lib.mst_workspace_release.argtypes = [p]
     lib.mst_workspace_release.restype = ctypes.c_int
+    lib.mst_set_dense_limit.argtypes = [ctypes.c_int32]
+    lib.mst_set_dense_limit.restype = ctypes.c_int32
     lib.mst_profile_kernel_name.argtypes = [ctypes.c_int]
     lib.mst_profile_kernel_name.restype = ctypes.c_char_p
     _lib = lib
@@ -98,6 +100,28 @@ def _dev_ptr(t, dtype, name, numel=None):
 def mst_workspace_release(stream=None) -> int:
     """Free the library's workspace cached for (current device, stream)."""
     return int(load_library().mst_workspace_release(_stream_handle(stream)))
+
+
+def mst_set_dense_limit(limit: int) -> int:
+    """Set the component count at or below which a solve ends with the dense
+    finish (0: off, clamped to 198; negative: query).  Returns the previous limit."""
+    return int(load_library().mst_set_dense_limit(int(limit)))
+
+
+class dense_limit:
+    """Context manager: ``with dense_limit(0): ...`` runs plain Boruvka rounds only."""
+
+    def __init__(self, limit: int):
+        self.limit = limit
+        self.prev = None
+
+    def __enter__(self):
+        self.prev = mst_set_dense_limit(self.limit)
+        return self
+
+    def __exit__(self, *exc):
+        mst_set_dense_limit(self.prev)
+        return False
 
 
 def mst_status_string(status: int) -> str:
@@ -182,13 +206,15 @@ def mst_profile_read() -> dict:
     """{kernel kind: (total ms, launches, algorithmic bytes)} accumulated while enabled."""
     import numpy as np
     lib = load_library()
-    ms = np.zeros(16, np.float64)
-    n = np.zeros(16, np.int64)
-    b = np.zeros(16, np.float64)
+    cap = 64
+    ms = np.zeros(cap, np.float64)
+    n = np.zeros(cap, np.int64)
+    b = np.zeros(cap, np.float64)
     k = lib.mst_profile_read(ms.ctypes.data_as(ctypes.c_void_p), n.ctypes.data_as(ctypes.c_void_p),
-                             b.ctypes.data_as(ctypes.c_void_p), 16)
+                             b.ctypes.data_as(ctypes.c_void_p), cap)
     if k < 0:
         raise MstxError(k)
+    k = min(k, cap)
     return {lib.mst_profile_kernel_name(i).decode(): (float(ms[i]), int(n[i]), float(b[i])) for i in range(k)}
 
 

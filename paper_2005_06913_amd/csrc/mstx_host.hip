@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdlib>
 #include <cstring>
 #include <map>
@@ -34,7 +35,7 @@ constexpr int kMaxGrid = 4096;  // capacity of the per-block partial arrays (hoo
 
 struct Layout {
   size_t best, parent, root_of, labpool, rootmask, rootcnt, rootpre, rec, seg_cnt, part_sel, part_w, state,
-      upd_key, upd_cl, offT, slab, bytes;
+      pbest, upd_key, upd_cl, offT, slab, bytes;
   int64_t slab_cap;  // u64 entries of the LDS-mode slab (0: none)
   int32_t nseg;
   bool bucket;  // offer buffers present
@@ -70,6 +71,7 @@ Layout plan(int32_t n, int64_t m) {
   L.part_sel = take(4 * (size_t)kMaxGrid);
   L.part_w = take(8 * (size_t)kMaxGrid);
   L.state = take(sizeof(DevState));
+  L.pbest = take(8 * (size_t)kDensePairsMax);
   L.slab_cap = n > kSlabMin ? (int64_t)kSlabRows * std::min<int32_t>(n, kLdsSlots) : 0;
   if (L.slab_cap) L.slab = take(8 * (size_t)L.slab_cap);
   if (L.bucket) {
@@ -96,6 +98,10 @@ struct DeviceCache {
 // One cache per (device, stream): calls on different streams have their own
 // workspace and run concurrently; calls on the same stream are serialised.
 std::mutex g_caches_mu;
+
+// Largest component count the dense finish takes (0: every round is a plain
+// Boruvka round); mst_set_dense_limit() changes it.
+std::atomic<int> g_dense_limit{kDenseMax};
 std::map<std::pair<int, hipStream_t>, std::unique_ptr<DeviceCache>> g_caches;
 
 thread_local std::vector<int64_t> t_last_stats;
@@ -187,24 +193,21 @@ int rounds_bound(int32_t n) {
 // with the round's algorithmic bytes (what the method must move, from the
 // round statistics).
 enum Kind {
-  kScan0Global = 0, kScan0Lds, kScan0Bucket,
-  kScan1Global, kScan1Lds, kScan1Bucket,
-  kScanRGlobal, kScanRLds, kScanRBucket,
-  kBucketMin, kSlabMin_, kHook, kCompress, kFinalize, kRelabel, kKinds
+  kScan0Global = 0, kScan0Lds, kScan0Bucket, kScan0Dense,
+  kScan1Global, kScan1Lds, kScan1Bucket, kScan1Dense,
+  kScanRGlobal, kScanRLds, kScanRBucket, kScanRDense,
+  kBucketMin, kSlabMin_, kDenseFinish, kHook, kCompress, kFinalize, kRelabel, kKinds
 };
 // Names as rocprofv3 reports the kernels (template arguments: minima mode
-// 0 global / 1 LDS / 2 bucket, reads the caller's arrays, compacts).
+// 0 global / 1 LDS / 2 bucket / 3 dense, reads the caller's arrays, compacts).
 const char* const kKindNames[kKinds] = {
-    "k_scan<0, true, false>",  "k_scan<1, true, false>",  "k_scan<2, true, false>",
-    "k_scan<0, true, true>",   "k_scan<1, true, true>",   "k_scan<2, true, true>",
-    "k_scan<0, false, true>",  "k_scan<1, false, true>",  "k_scan<2, false, true>",
-    "k_bucket_min",            "k_slab_min",              "k_hook",
+    "k_scan<0, true, false>",  "k_scan<1, true, false>",  "k_scan<2, true, false>",  "k_scan<3, true, false>",
+    "k_scan<0, true, true>",   "k_scan<1, true, true>",   "k_scan<2, true, true>",   "k_scan<3, true, true>",
+    "k_scan<0, false, true>",  "k_scan<1, false, true>",  "k_scan<2, false, true>",  "k_scan<3, false, true>",
+    "k_bucket_min",            "k_slab_min",              "k_dense_finish",          "k_hook",
     "k_compress",              "k_finalize",              "k_relabel"};
 
-int scan_kind(int stage, int mode) {
-  const int m = mode == kModeGlobal ? 0 : (mode == kModeLds ? 1 : 2);
-  return 3 * stage + m;
-}
+int scan_kind(int stage, int mode) { return kNumModes * stage + mode; }
 
 struct Profile {
   std::mutex mu;
@@ -264,7 +267,7 @@ struct LaunchTimer {
       if (hipEventElapsedTime(&ms, p.a, p.b) != hipSuccess) continue;
       g_prof.ms[p.kind] += ms;
       g_prof.launches[p.kind] += 1;
-      if (p.kind <= kScanRBucket && p.round < nrounds && p.mode == chosen[p.round])
+      if (p.kind <= kScanRDense && p.round < nrounds && p.mode == chosen[p.round])
         g_prof.bytes[p.kind] += bytes[p.round];
     }
     pending.clear();
@@ -272,13 +275,9 @@ struct LaunchTimer {
 };
 thread_local LaunchTimer t_timer;
 
-int host_pick_mode(int32_t nr, int launched) {
-  if ((launched & (1 << kModeLds)) && nr <= kLdsSlots) return kModeLds;
-  if ((launched & (1 << kModeBucket)) && (int64_t)nr <= kBucketMaxComponents) return kModeBucket;
-  return kModeGlobal;
-}
-
-int mode_for(int64_t nr) {
+// Mode that handles `bound` components when it is the exact count.
+int mode_for(int64_t nr, int dense_limit) {
+  if (nr <= dense_limit) return kModeDense;
   if (nr <= kLdsSlots) return kModeLds;
   if (nr <= kBucketMaxComponents) return kModeBucket;
   return kModeGlobal;
@@ -312,6 +311,8 @@ struct Solve {
   uint16_t* upd_cl;
   uint32_t* offT;
   unsigned long long* slab;
+  unsigned long long* pbest;
+  int dense_limit;            // 0: no dense finish
   std::vector<int> launched;  // per round
 };
 
@@ -319,22 +320,27 @@ struct Solve {
 // round whose component count is at most `bound`.  Returns the launched mask.
 int enqueue_scan(Solve& S, int r, int stage, int64_t bound, bool exact, hipError_t& err) {
   LaunchTimer& T = t_timer;
-  const int hi_mode = mode_for(bound);
+  const int hi_mode = mode_for(bound, S.dense_limit);
   int launched = 1 << hi_mode;
   if (!exact) {
     // the actual count may be much smaller than the bound
-    if (hi_mode != kModeLds && bound / 8 <= kLdsSlots) launched |= 1 << kModeLds;
+    if (hi_mode != kModeDense && S.dense_limit > 0 && bound / 8 <= S.dense_limit) launched |= 1 << kModeDense;
+    if (hi_mode != kModeLds && hi_mode != kModeDense && bound / 8 <= kLdsSlots) launched |= 1 << kModeLds;
     if (hi_mode == kModeGlobal && bound / 8 <= kBucketMaxComponents) launched |= 1 << kModeBucket;
   }
   if (!S.L.bucket) launched &= ~(1 << kModeBucket), launched |= (bound > kLdsSlots ? 1 << kModeGlobal : 0);
+  launched |= S.dense_limit << 8;
   ScanArgs A{r,      launched, S.src,     S.dst,    S.w,    (uint32_t)S.m, S.n,     S.labpool, S.rec,
-             S.seg_cnt, S.L.nseg, S.best, S.st, S.upd_key, S.upd_cl, S.offT, S.slab, S.L.slab_cap};
+             S.seg_cnt, S.L.nseg, S.best, S.st, S.upd_key, S.upd_cl, S.offT, S.slab, S.L.slab_cap, S.pbest};
   const int cus = S.dc->cus;
-  for (int mode : {kModeLds, kModeBucket, kModeGlobal}) {
+  for (int mode : {kModeDense, kModeLds, kModeBucket, kModeGlobal}) {
     if (!(launched & (1 << mode))) continue;
     int grid;
     size_t lds;
-    if (mode == kModeLds) {
+    if (mode == kModeDense) {
+      lds = (size_t)dense_pairs((int32_t)std::min<int64_t>(std::max<int64_t>(bound, 2), S.dense_limit)) * 8;
+      grid = std::min(S.L.nseg, cus);
+    } else if (mode == kModeLds) {
       const int64_t slots = std::max<int64_t>(1, std::min<int64_t>(bound, kLdsSlots));
       lds = (size_t)slots * 8;
       const int per_cu = (int)std::max<int64_t>(1, std::min<int64_t>(4, 65536 / ((int64_t)lds + 1024)));
@@ -350,11 +356,19 @@ int enqueue_scan(Solve& S, int r, int stage, int64_t bound, bool exact, hipError
     err = launch_scan(mode, stage, A, grid, lds, S.s);
     T.stop(k);
     if (err != hipSuccess) return launched;
-    if (mode == kModeLds && S.slab) {
-      const int ks = T.start(kSlabMin_, r, kModeLds);
-      err = launch_slab_min(r, launched, S.slab, S.L.slab_cap, grid, S.best, S.st,
-                            grid_for(std::min<int64_t>(std::max<int64_t>(bound, 1), kLdsSlots)), S.s);
+    if ((mode == kModeLds || mode == kModeDense) && S.slab) {
+      const int ks = T.start(kSlabMin_, r, mode);
+      const int64_t cols = mode == kModeDense ? kDensePairsMax : std::min<int64_t>(std::max<int64_t>(bound, 1), kLdsSlots);
+      err = launch_slab_min(r, launched, mode, S.slab, S.L.slab_cap, grid, S.best, S.pbest, S.st, grid_for(cols),
+                            S.s);
       T.stop(ks);
+      if (err != hipSuccess) return launched;
+    }
+    if (mode == kModeDense && S.in_mst) {
+      const int kd = T.start(kDenseFinish, r, mode);
+      err = launch_dense_finish(r, launched, S.pbest, S.seg_cnt, S.L.nseg, S.in_mst, S.total, S.st,
+                                S.dc->host_rounds, S.s);
+      T.stop(kd);
       if (err != hipSuccess) return launched;
     }
     if (mode == kModeBucket) {
@@ -434,6 +448,8 @@ int solve_locked(DeviceCache* dc, const Layout& L, int32_t n, int64_t m, const i
   S.upd_cl = L.bucket ? at<uint16_t>(B, L.upd_cl) : nullptr;
   S.offT = L.bucket ? at<uint32_t>(B, L.offT) : nullptr;
   S.slab = L.slab_cap ? at<unsigned long long>(B, L.slab) : nullptr;
+  S.pbest = at<unsigned long long>(B, L.pbest);
+  S.dense_limit = g_dense_limit.load();
   const int max_rounds = std::min(rounds_bound(n) + 1, kMaxRounds);
   S.launched.assign(kMaxRounds + 1, 0);
 
@@ -441,7 +457,7 @@ int solve_locked(DeviceCache* dc, const Layout& L, int32_t n, int64_t m, const i
   T.begin(s);
   HIP_OK(hipMemsetAsync(in_mst, 0, (size_t)m, s));
   HIP_OK(hipMemsetAsync(total, 0, sizeof(uint64_t), s));
-  HIP_OK(launch_init(n, S.best, S.parent, S.st, grid_for(n), s));
+  HIP_OK(launch_init(n, S.best, S.parent, S.dense_limit > 0 ? S.pbest : nullptr, S.st, grid_for(n), s));
   HIP_OK(enqueue_round(S, 0, n));
 
   int status = MSTX_ERR_DEVICE;  // until the loop decides
@@ -484,15 +500,16 @@ int solve_locked(DeviceCache* dc, const Layout& L, int32_t n, int64_t m, const i
     t_last_stats[3 * r + 0] = nr_of[r];
     t_last_stats[3 * r + 1] = M.live;
     t_last_stats[3 * r + 2] = M.sel;
-    chosen[r] = r == 0 ? host_pick_mode(n, S.launched[0]) : host_pick_mode(nr_of[r], S.launched[r]);
+    chosen[r] = pick_mode(nr_of[r], S.launched[r]);
     // algorithmic bytes of this round's scan: the edge stream read once, the
     // previous label map read once, the minima initialised and written once,
-    // the compacted survivors written once
-    const double nrd = (double)nr_of[r], live_r = (double)M.live;
-    if (r == 0) bytes[r] = 12.0 * (double)m + 16.0 * nrd;
-    else if (r == 1) bytes[r] = 12.0 * (double)m + 4.0 * (double)n + 16.0 * nrd + 16.0 * live_r;
-    else bytes[r] = 16.0 * (double)dc->host_rounds[r - 1].live + 4.0 * (double)nr_of[r - 1] + 16.0 * nrd +
-                    16.0 * live_r;
+    // the compacted survivors written once (a dense round instead writes its
+    // pair table once and compacts nothing)
+    const double nrd = (double)nr_of[r];
+    const double out = M.dense ? 8.0 * (double)dense_pairs(nr_of[r]) : 16.0 * nrd + 16.0 * (double)M.live;
+    if (r == 0) bytes[r] = 12.0 * (double)m + (M.dense ? out : 16.0 * nrd);
+    else if (r == 1) bytes[r] = 12.0 * (double)m + 4.0 * (double)n + out;
+    else bytes[r] = 16.0 * (double)dc->host_rounds[r - 1].live + 4.0 * (double)nr_of[r - 1] + out;
   }
   T.commit(rounds, chosen, bytes);
   return status;
@@ -714,10 +731,13 @@ int select_min_edges(int32_t n, int64_t m, const int32_t* src, const int32_t* ds
   S.upd_cl = L.bucket ? at<uint16_t>(B, L.upd_cl) : nullptr;
   S.offT = L.bucket ? at<uint32_t>(B, L.offT) : nullptr;
   S.slab = L.slab_cap ? at<unsigned long long>(B, L.slab) : nullptr;
+  S.pbest = at<unsigned long long>(B, L.pbest);
+  S.dense_limit = 0;  // per-vertex minima: never the pair table
+  S.in_mst = nullptr;
   S.launched.assign(1, 0);
   t_timer.begin(s);
   t_timer.on = false;
-  HIP_OK(launch_init(n, S.best, at<int32_t>(B, L.parent), S.st, grid_for(n), s));
+  HIP_OK(launch_init(n, S.best, at<int32_t>(B, L.parent), nullptr, S.st, grid_for(n), s));
   if (m > 0) {
     hipError_t err = hipSuccess;
     enqueue_scan(S, 0, 0, n, true, err);
@@ -844,6 +864,11 @@ int mst_workspace_release(void* stream) {
 size_t mst_workspace_bytes(int32_t n, int64_t m) {
   if (n < 0 || m < 0 || m > (int64_t)0xFFFFFFFFLL) return 0;
   return mstx::plan(n, m).bytes;
+}
+
+int32_t mst_set_dense_limit(int32_t limit) {
+  if (limit < 0) return mstx::g_dense_limit.load();
+  return mstx::g_dense_limit.exchange(std::min<int32_t>(limit, mstx::kDenseMax));
 }
 
 const char* mst_status_string(int status) {

@@ -23,7 +23,8 @@ static constexpr int kSegCap = kScanBlock * kPerThread;
 static constexpr int kModeGlobal = 0;  // filtered atomicMin on best[] in HBM
 static constexpr int kModeLds = 1;     // per-workgroup minima in LDS, flushed once
 static constexpr int kModeBucket = 2;  // offers sorted into component buckets + k_bucket_min
-static constexpr int kNumModes = 3;
+static constexpr int kModeDense = 3;   // last round: lightest edge per component pair, then finish
+static constexpr int kNumModes = 4;
 
 // LDS: up to 160 KB of dynamic LDS per workgroup (gfx950 has 160 KB per CU).
 static constexpr int kMaxDynLds = 160000;
@@ -45,6 +46,38 @@ __host__ __device__ inline void bucket_geometry(int32_t nr, int* shift, int* nbk
   *nbk = (int)(((int64_t)nr + (1 << s) - 1) >> s);
 }
 
+// Dense finish: with at most kDenseMax components left, one pass over the live
+// edges keeps the lightest edge of every component pair (any other edge
+// between the same two components closes a cycle with a lighter one, so it is
+// not in the tree), and one workgroup finishes Boruvka on that small complete
+// graph with the pair table in LDS.  kDenseMax is the largest count whose
+// table plus per-component state fits the dynamic LDS of one workgroup.
+__host__ __device__ constexpr int32_t dense_pairs(int32_t k) { return k * (k - 1) / 2; }
+__host__ __device__ constexpr size_t dense_finish_lds(int32_t k) {
+  return (size_t)dense_pairs(k) * 8 + (size_t)k * 16;  // table, best key, parent, target
+}
+static constexpr int32_t kDenseMax = 198;
+static constexpr int32_t kDensePairsMax = dense_pairs(kDenseMax);
+static_assert(dense_finish_lds(kDenseMax) <= (size_t)kMaxDynLds, "dense finish exceeds LDS");
+static_assert(dense_finish_lds(kDenseMax + 1) > (size_t)kMaxDynLds, "kDenseMax is not the largest fit");
+static_assert(kDensePairsMax <= kLdsSlots && kDenseMax < 256, "dense limit");
+// index of the unordered pair {a, b}, a < b < k, in row-major upper-triangle order
+__host__ __device__ inline int32_t pair_index(int32_t a, int32_t b, int32_t k) {
+  return a * k - a * (a + 1) / 2 + (b - a - 1);
+}
+
+// The `launched` word of a round: bit i = minima mode i was launched; bits
+// 8..15 = the largest component count the dense finish takes (0: off).
+__host__ __device__ inline int launched_dense_limit(int launched) { return (launched >> 8) & 0xFF; }
+
+// Mode that handles n_r among the launched ones.
+__host__ __device__ inline int pick_mode(int32_t nr, int launched) {
+  if ((launched & (1 << kModeDense)) && nr <= launched_dense_limit(launched)) return kModeDense;
+  if ((launched & (1 << kModeLds)) && nr <= kLdsSlots) return kModeLds;
+  if ((launched & (1 << kModeBucket)) && (int64_t)nr <= kBucketMaxComponents) return kModeBucket;
+  return kModeGlobal;
+}
+
 // Device-resident round state.  Round r's kernels read n[r] and lab_off[r];
 // the finalize kernel of round r writes n[r+1], lab_off[r+1], live[r], sel[r].
 struct DevState {
@@ -55,6 +88,8 @@ struct DevState {
   int64_t edges_added;              // running total of sel[]
   int32_t err;                      // an edge end outside [0, n) was seen
   int32_t err_internal;             // a label lookup gave an impossible value
+  int32_t dense_at;                 // round that ended with the dense finish (-1: none)
+  int32_t pad;
 };
 
 // What the finalize kernel of round r writes to pinned host memory.
@@ -62,7 +97,7 @@ struct HostRound {
   int32_t n_next;
   int32_t err;
   int32_t err_internal;
-  int32_t pad;
+  int32_t dense;  // 1: the dense finish ended the solve in this round
   int64_t live;
   int64_t sel;
   int64_t edges_added;
@@ -88,6 +123,7 @@ struct ScanArgs {
   uint32_t* offT;               // [kMaxBuckets + 1][nseg] run starts
   unsigned long long* slab;     // LDS mode, n_r > kSlabMin: per-workgroup minima [grid][n_r]
   int64_t slab_cap;             // entries of slab
+  unsigned long long* pbest;    // dense mode: lightest key per component pair [kDensePairsMax]
 };
 
 // LDS-mode minima of more than kSlabMin components are flushed through a
@@ -115,16 +151,20 @@ hipError_t launch_graph_epilogue(const int32_t* glist, int ng, const int64_t* vo
                                  const int64_t* cedge, const uint8_t* cin_mst, const uint32_t* gw,
                                  const int32_t* gbad, uint8_t* in_mst, unsigned long long* total, int32_t* status,
                                  hipStream_t s);
-hipError_t launch_init(int32_t n, unsigned long long* best, int32_t* parent, DevState* st, int grid,
-                       hipStream_t s);
+hipError_t launch_init(int32_t n, unsigned long long* best, int32_t* parent, unsigned long long* pbest,
+                       DevState* st, int grid, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, int64_t count, unsigned long long v, int grid,
                            hipStream_t s);
 hipError_t launch_scan(int mode, int stage, const ScanArgs& a, int grid, size_t lds, hipStream_t s);
 hipError_t launch_bucket_min(int round, int launched, const unsigned long long* upd_key, const uint16_t* upd_cl,
                              const uint32_t* offT, int32_t nseg, unsigned long long* best, const DevState* st,
                              int grid, size_t lds, hipStream_t s);
-hipError_t launch_slab_min(int round, int launched, const unsigned long long* slab, int64_t slab_cap, int nwg,
-                           unsigned long long* best, const DevState* st, int grid, hipStream_t s);
+hipError_t launch_slab_min(int round, int launched, int mode, const unsigned long long* slab, int64_t slab_cap,
+                           int nwg, unsigned long long* best, unsigned long long* pbest, const DevState* st,
+                           int grid, hipStream_t s);
+hipError_t launch_dense_finish(int round, int launched, const unsigned long long* pbest, const uint32_t* seg_cnt,
+                               int32_t nseg, uint8_t* in_mst, unsigned long long* total, DevState* st,
+                               HostRound* host, hipStream_t s);
 hipError_t launch_hook(int round, const int32_t* src, const int32_t* dst, const uint32_t* w,
                        const unsigned long long* best, int32_t* parent, const int32_t* labpool, DevState* st,
                        uint8_t* in_mst, uint32_t* part_sel, unsigned long long* part_w, int grid, hipStream_t s);

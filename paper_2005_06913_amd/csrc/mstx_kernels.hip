@@ -117,29 +117,27 @@ __device__ __forceinline__ T block_sum(T v, T* scratch /* [NW] */) {
   return s;
 }
 
-// Mode that handles n_r among the launched ones (bit i of `launched` = mode i).
-__device__ __forceinline__ int pick_mode(int32_t nr, int launched) {
-  if ((launched & (1 << kModeLds)) && nr <= kLdsSlots) return kModeLds;
-  if ((launched & (1 << kModeBucket)) && (int64_t)nr <= kBucketMaxComponents) return kModeBucket;
-  return kModeGlobal;
-}
 
 // --------------------------------------------------------------------- init
 
 // best[0..n) <- none, parent[c] <- c, state for round 0.
 __global__ void __launch_bounds__(kBlock) k_init(int32_t n, unsigned long long* best, int32_t* parent,
-                                                 DevState* st) {
+                                                 unsigned long long* pbest, DevState* st) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += stride) {
     best[c] = kKeyNone;
     parent[c] = (int32_t)c;
   }
+  if (pbest)
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < kDensePairsMax; i += stride)
+      pbest[i] = kKeyNone;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     st->n[0] = n;
     st->lab_off[0] = 0;
     st->err = 0;
     st->err_internal = 0;
     st->edges_added = 0;
+    st->dense_at = -1;
   }
 }
 
@@ -157,8 +155,10 @@ __global__ void __launch_bounds__(kBlock) k_fill_u64(unsigned long long* p, int6
 //   !kFromInput             : rounds >= 2, the record stream, labels lab_{r-1}
 // kMode is the way minima are taken (LDS / BUCKET / GLOBAL); a launch whose
 // mode is not the one pick_mode() selects for the actual n_r returns.
-// Dynamic LDS: LDS mode n_r (<= launch capacity) u64 minima; BUCKET mode the
-// 2 * kSegCap offer staging and the (bucket count + 1) counters.
+// Dynamic LDS: LDS mode n_r (<= launch capacity) u64 minima; DENSE mode
+// n_r (n_r - 1) / 2 u64 pair minima; BUCKET mode the 2 * kSegCap offer staging
+// and the (bucket count + 1) counters.  DENSE mode compacts nothing: its
+// round is the last.
 template <int kMode, bool kFromInput, bool kCompact>
 __global__ void __launch_bounds__(kScanBlock) k_scan(ScanArgs A) {
   extern __shared__ unsigned long long smem[];
@@ -185,6 +185,11 @@ __global__ void __launch_bounds__(kScanBlock) k_scan(ScanArgs A) {
   }
   if (kMode == kModeLds) {
     for (int32_t c = threadIdx.x; c < nr; c += kScanBlock) lbest[c] = kKeyNone;
+    __syncthreads();
+  }
+  const int32_t npairs = kMode == kModeDense ? dense_pairs(nr) : 0;
+  if (kMode == kModeDense) {
+    for (int32_t c = threadIdx.x; c < npairs; c += kScanBlock) lbest[c] = kKeyNone;
     __syncthreads();
   }
   const int wave = threadIdx.x >> 6;
@@ -239,7 +244,10 @@ __global__ void __launch_bounds__(kScanBlock) k_scan(ScanArgs A) {
         live[k] = (a != b) && ((a | b) >= 0);
         if (live[k]) {
           const uint64_t key = make_key(we, e);
-          if (kMode == kModeLds) {
+          if (kMode == kModeDense) {
+            const int32_t lo = a < b ? a : b, hi = a < b ? b : a;
+            lower_lds(lbest, pair_index(lo, hi, nr), key);
+          } else if (kMode == kModeLds) {
             lower_lds(lbest, a, key);
             lower_lds(lbest, b, key);
           } else if (kMode == kModeGlobal) {
@@ -282,7 +290,7 @@ __global__ void __launch_bounds__(kScanBlock) k_scan(ScanArgs A) {
       wave_off += (i < wave) ? v : 0u;
       seg_tot += v;
     }
-    if (kCompact) {
+    if (kCompact && kMode != kModeDense) {
 #pragma unroll
       for (int k = 0; k < kPerThread; ++k) {
         if (live[k]) st_rec(r[k], A.rec + base + wave_off + my_off[k]);
@@ -333,6 +341,18 @@ __global__ void __launch_bounds__(kScanBlock) k_scan(ScanArgs A) {
     __syncthreads();  // LDS (wave_tot, counters, staging) is reused by the next segment
   }
   if (!kCompact && bad) A.st->err = 1;
+  if (kMode == kModeDense) {
+    __syncthreads();
+    if (use_slab(A.slab, A.slab_cap, npairs, gridDim.x)) {
+      unsigned long long* row = A.slab + (int64_t)blockIdx.x * npairs;
+      for (int32_t c = threadIdx.x; c < npairs; c += kScanBlock) row[c] = lbest[c];
+    } else {
+      for (int32_t c = threadIdx.x; c < npairs; c += kScanBlock) {
+        const unsigned long long v = lbest[c];
+        if (v != kKeyNone) lower_global(A.pbest, c, v);
+      }
+    }
+  }
   if (kMode == kModeLds) {
     __syncthreads();
     if (use_slab(A.slab, A.slab_cap, nr, gridDim.x)) {
@@ -350,18 +370,28 @@ __global__ void __launch_bounds__(kScanBlock) k_scan(ScanArgs A) {
 
 // best[c] = min over the nwg workgroup rows of the slab (LDS mode with more
 // than kSlabMin components; the scan that wrote the slab had nwg workgroups).
-// Block (x, y): components x*256.., rows y*kSlabRowsPerBlock..; each partial
-// minimum is merged with a filtered atomicMin (best[] was reset to "none").
+// In dense mode the columns are the component pairs and the target is the
+// pair table pbest[].  Block (x, y): columns x*256.., rows
+// y*kSlabRowsPerBlock..; each partial minimum is merged with a filtered
+// atomicMin (the target was reset to "none").
 static constexpr int kSlabRowsPerBlock = 32;
-__global__ void __launch_bounds__(kBlock) k_slab_min(int round, int launched,
+__global__ void __launch_bounds__(kBlock) k_slab_min(int round, int launched, int mode,
                                                      const unsigned long long* __restrict__ slab,
                                                      int64_t slab_cap, int nwg,
                                                      unsigned long long* __restrict__ best,
+                                                     unsigned long long* __restrict__ pbest,
                                                      const DevState* __restrict__ st) {
-  const int32_t nr = st->n[round];
+  int32_t nr = st->n[round];
   if (nr <= 1 && round > 0) return;
   if (round > 0 && st->err) return;
-  if (pick_mode(nr, launched) != kModeLds || !use_slab(slab, slab_cap, nr, nwg)) return;
+  // runs after the scan of `mode` (LDS or dense) and only if that scan ran
+  if (pick_mode(nr, launched) != mode) return;
+  if (mode == kModeDense) {
+    // columns are the component pairs, the target the pair minima
+    nr = dense_pairs(nr);
+    best = pbest;
+  }
+  if (!use_slab(slab, slab_cap, nr, nwg)) return;
   const int b0 = blockIdx.y * kSlabRowsPerBlock;
   const int b1 = min(nwg, b0 + kSlabRowsPerBlock);
   for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < nr; c += (int64_t)gridDim.x * kBlock) {
@@ -461,6 +491,157 @@ __global__ void __launch_bounds__(kScanBlock) k_bucket_min(int round, int launch
   }
 }
 
+// ------------------------------------------------------------ dense finish
+
+static constexpr int kDenseThreads = 1024;
+static constexpr int kDenseWaves = kDenseThreads / 64;
+static constexpr int kDenseRowSlots = (kDenseMax + kDenseWaves - 1) / kDenseWaves;
+
+// Finishes the solve on the k = n_r <= kDenseMax components of round r, one
+// workgroup: vertex u of the small graph is component u, edge {u, v} the
+// lightest original edge between them, pbest[pair_index(u, v)] (none: no
+// edge).  Boruvka again, on that graph, with everything in LDS: every group
+// of the small graph takes its lightest outgoing key (row minima, then an LDS
+// atomicMin per group), hooks onto the group at the far end (of a mutual pair
+// the smaller id stays root), and pointer jumping flattens the parents.  The
+// keys are distinct, so the selected edges are exactly the MST edges between
+// the k components.  Records round r as the last one: n_{r+1} = 0, live_r =
+// the surviving edges counted by the scan, sel_r = the edges added here.
+__global__ void __launch_bounds__(kDenseThreads) k_dense_finish(int round, int launched,
+                                                               const unsigned long long* __restrict__ pbest,
+                                                               const uint32_t* __restrict__ seg_cnt, int32_t nseg,
+                                                               uint8_t* __restrict__ in_mst, unsigned long long* total,
+                                                               DevState* st, HostRound* host) {
+  extern __shared__ unsigned long long dsm[];
+  __shared__ unsigned long long red_w[kDenseWaves];
+  __shared__ int64_t red_n[kDenseWaves];
+  const int32_t k = st->n[round];
+  if (k <= 1 && round > 0) return;
+  if (round > 0 && st->err) return;
+  if (pick_mode(k, launched) != kModeDense) return;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int32_t np = dense_pairs(k);
+  unsigned long long* tab = dsm;            // [np]
+  unsigned long long* gbest = tab + np;     // [k] lightest key leaving group g (g a root)
+  int32_t* par = reinterpret_cast<int32_t*>(gbest + k);  // [k]
+  int32_t* tgt = par + k;                                // [k] group at the far end of gbest[g]
+  for (int32_t i = tid; i < np; i += kDenseThreads) tab[i] = pbest[i];
+  for (int32_t v = tid; v < k; v += kDenseThreads) par[v] = v;
+  unsigned long long wsum = 0;
+  int64_t added = 0;
+  __syncthreads();
+  for (;;) {
+    for (int32_t v = tid; v < k; v += kDenseThreads) gbest[v] = kKeyNone;
+    __syncthreads();
+    // row minima: wave wv owns rows wv, wv + 16, ...; par[] is flat here
+    unsigned long long rmin[kDenseRowSlots];
+    int32_t rarg[kDenseRowSlots];
+    bool any = false;
+#pragma unroll
+    for (int q = 0; q < kDenseRowSlots; ++q) {
+      const int32_t u = wv + kDenseWaves * q;
+      rmin[q] = kKeyNone;
+      rarg[q] = -1;
+      if (u < k) {
+        const int32_t gu = par[u];
+        unsigned long long best = kKeyNone;
+        int32_t arg = -1;
+        for (int32_t v = lane; v < k; v += 64) {
+          if (par[v] != gu) {
+            const unsigned long long key = v < u ? tab[pair_index(v, u, k)] : tab[pair_index(u, v, k)];
+            if (key < best) {
+              best = key;
+              arg = v;
+            }
+          }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+          const unsigned long long ok = __shfl_xor(best, off, 64);
+          const int32_t oa = __shfl_xor(arg, off, 64);
+          if (ok < best) {
+            best = ok;
+            arg = oa;
+          }
+        }
+        rmin[q] = best;
+        rarg[q] = arg;
+        if (best != kKeyNone) {
+          any = true;
+          if (lane == 0) atomicMin(&gbest[gu], best);
+        }
+      }
+    }
+    if (!__syncthreads_or(any)) break;  // no edge between different groups is left
+    // the row that holds a group's minimum names the group at its far end
+#pragma unroll
+    for (int q = 0; q < kDenseRowSlots; ++q) {
+      const int32_t u = wv + kDenseWaves * q;
+      if (u < k && lane == 0 && rmin[q] != kKeyNone && rmin[q] == gbest[par[u]]) tgt[par[u]] = par[rarg[q]];
+    }
+    __syncthreads();
+    // hook: group g onto tgt[g], except the smaller group of a mutual pair
+    // (both then hold the same key, which is added once)
+    for (int32_t g = tid; g < k; g += kDenseThreads) {
+      if (par[g] == g && gbest[g] != kKeyNone) {
+        const int32_t t = tgt[g];
+        if (!(tgt[t] == g && g < t)) {
+          par[g] = t;
+          const unsigned long long key = gbest[g];
+          in_mst[(uint32_t)key] = 1;
+          wsum += key >> 32;
+          ++added;
+        }
+      }
+    }
+    __syncthreads();
+    // pointer jumping until every parent is a root
+    for (;;) {
+      bool changed = false;
+      for (int32_t v = tid; v < k; v += kDenseThreads) {
+        const int32_t p = par[v], pp = par[p];
+        if (pp != p) {
+          par[v] = pp;
+          changed = true;
+        }
+      }
+      if (!__syncthreads_or(changed)) break;
+    }
+  }
+  int64_t live = 0;
+  for (int32_t i = tid; i < nseg; i += kDenseThreads) live += seg_cnt[i];
+  for (int off = 32; off > 0; off >>= 1) {
+    wsum += __shfl_xor(wsum, off, 64);
+    added += __shfl_xor(added, off, 64);
+    live += __shfl_xor(live, off, 64);
+  }
+  __shared__ int64_t red_l[kDenseWaves];
+  if (lane == 0) {
+    red_w[wv] = wsum;
+    red_n[wv] = added;
+    red_l[wv] = live;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    unsigned long long W = 0;
+    int64_t A = 0, Lv = 0;
+    for (int i = 0; i < kDenseWaves; ++i) {
+      W += red_w[i];
+      A += red_n[i];
+      Lv += red_l[i];
+    }
+    *total += W;
+    st->live[round] = Lv;
+    st->sel[round] = A;
+    st->edges_added += A;
+    st->n[round + 1] = 0;
+    st->lab_off[round + 1] = st->lab_off[round];
+    st->dense_at = round;
+    HostRound h{0, st->err, st->err_internal, 1, Lv, A, st->edges_added};
+    host[round] = h;
+    __threadfence_system();
+  }
+}
+
 // -------------------------------------------------------------------- hook
 
 // Root of x by plain loads (values may be stale, but every value ever stored
@@ -499,6 +680,7 @@ __global__ void __launch_bounds__(kBlock) k_hook(int round, const int32_t* __res
   __shared__ unsigned long long red64[kBlock / 64];
   const int32_t nr = st->n[round];
   if (nr <= 1 && round > 0) return;
+  if (st->dense_at == round) return;  // the dense finish ended the solve
   uint32_t sel = 0;
   unsigned long long wsum = 0;
   const int64_t stride = (int64_t)gridDim.x * kBlock;
@@ -561,6 +743,7 @@ __global__ void __launch_bounds__(kBlock) k_compress(int round, int32_t* parent,
                                                      const DevState* __restrict__ st) {
   const int32_t nr = st->n[round];
   if (nr <= 1 && round > 0) return;
+  if (st->dense_at == round) return;  // the dense finish ended the solve
   const int64_t stride = (int64_t)gridDim.x * kBlock;
   for (int64_t base = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63); base < nr; base += stride) {
     const int64_t ci = base + lane_id();
@@ -598,6 +781,7 @@ __global__ void __launch_bounds__(1024) k_finalize(int round, const int32_t* __r
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   const int32_t nr = st->n[round];
+  if (st->dense_at == round) return;  // the dense finish wrote this round's record
   if (nr <= 1 && round > 0) {
     if (tid == 0) {
       st->n[round + 1] = 0;
@@ -706,6 +890,7 @@ __global__ void __launch_bounds__(kBlock) k_relabel(int round, const int32_t* __
                                                     const DevState* __restrict__ st) {
   const int32_t nr = st->n[round];
   if (nr <= 1 && round > 0) return;
+  if (st->dense_at == round) return;  // the dense finish ended the solve
   const int32_t nn = st->n[round + 1];
   const int64_t off = st->lab_off[round];
   const int64_t stride = (int64_t)gridDim.x * kBlock;
@@ -750,16 +935,22 @@ hipError_t configure_kernels() {
   MSTX_CFG(kModeBucket, true, false);
   MSTX_CFG(kModeBucket, true, true);
   MSTX_CFG(kModeBucket, false, true);
+  MSTX_CFG(kModeDense, true, false);
+  MSTX_CFG(kModeDense, true, true);
+  MSTX_CFG(kModeDense, false, true);
 #undef MSTX_CFG
+  hipError_t r3 = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dense_finish),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxDynLds);
+  if (r3 != hipSuccess) e = r3;
   hipError_t r2 = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bucket_min),
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxDynLds);
   if (r2 != hipSuccess) e = r2;
   return e;
 }
 
-hipError_t launch_init(int32_t n, unsigned long long* best, int32_t* parent, DevState* st, int grid,
-                       hipStream_t s) {
-  k_init<<<grid, kBlock, 0, s>>>(n, best, parent, st);
+hipError_t launch_init(int32_t n, unsigned long long* best, int32_t* parent, unsigned long long* pbest,
+                       DevState* st, int grid, hipStream_t s) {
+  k_init<<<grid, kBlock, 0, s>>>(n, best, parent, pbest, st);
   MSTX_LAUNCH_CHECK();
   return hipSuccess;
 }
@@ -779,6 +970,7 @@ hipError_t launch_scan(int mode, int stage, const ScanArgs& a, int grid, size_t 
     else k_scan<M, false, true><<<grid, kScanBlock, lds, s>>>(a);                \
   } while (0)
   if (mode == kModeLds) MSTX_SCAN(kModeLds);
+  else if (mode == kModeDense) MSTX_SCAN(kModeDense);
   else if (mode == kModeBucket) MSTX_SCAN(kModeBucket);
   else MSTX_SCAN(kModeGlobal);
 #undef MSTX_SCAN
@@ -795,10 +987,21 @@ hipError_t launch_bucket_min(int round, int launched, const unsigned long long* 
   return hipSuccess;
 }
 
-hipError_t launch_slab_min(int round, int launched, const unsigned long long* slab, int64_t slab_cap, int nwg,
-                           unsigned long long* best, const DevState* st, int grid, hipStream_t s) {
+hipError_t launch_slab_min(int round, int launched, int mode, const unsigned long long* slab, int64_t slab_cap,
+                           int nwg, unsigned long long* best, unsigned long long* pbest, const DevState* st,
+                           int grid, hipStream_t s) {
   const dim3 g2(grid, (nwg + kSlabRowsPerBlock - 1) / kSlabRowsPerBlock);
-  k_slab_min<<<g2, kBlock, 0, s>>>(round, launched, slab, slab_cap, nwg, best, st);
+  k_slab_min<<<g2, kBlock, 0, s>>>(round, launched, mode, slab, slab_cap, nwg, best, pbest, st);
+  MSTX_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+hipError_t launch_dense_finish(int round, int launched, const unsigned long long* pbest, const uint32_t* seg_cnt,
+                               int32_t nseg, uint8_t* in_mst, unsigned long long* total, DevState* st,
+                               HostRound* host, hipStream_t s) {
+  const int32_t kmax = launched_dense_limit(launched) < kDenseMax ? launched_dense_limit(launched) : kDenseMax;
+  const size_t lds = dense_finish_lds(kmax);
+  k_dense_finish<<<1, kDenseThreads, lds, s>>>(round, launched, pbest, seg_cnt, nseg, in_mst, total, st, host);
   MSTX_LAUNCH_CHECK();
   return hipSuccess;
 }

@@ -24,6 +24,30 @@ def _concat(parts, name):
                    np.concatenate(w).astype(np.uint32), name)
 
 
+DENSE_MAX = 198  # largest component count the library's dense finish takes
+
+
+def stats_consistent(gpu_stats, oracle_stats, limit=DENSE_MAX):
+    """Whether per-round statistics (components, live edges, edges added) of a
+    solve that may end with the dense finish agree with the oracle's Boruvka
+    rounds.
+
+    Without a dense finish the rows are equal.  A dense finish at round r ends
+    the rows at r: rows before r are equal, row r has the oracle's component
+    and live-edge counts (at most `limit` components), and its edges added are
+    the oracle's added edges of round r and every later round together.
+    """
+    g = [tuple(int(x) for x in r) for r in gpu_stats]
+    o = [tuple(int(x) for x in r) for r in oracle_stats]
+    if g == o:
+        return True
+    r = len(g) - 1
+    if r < 0 or r >= len(o) or g[:r] != o[:r]:
+        return False
+    return (g[r][0] == o[r][0] <= limit and g[r][1] == o[r][1]
+            and g[r][2] == sum(row[2] for row in o[r:]))
+
+
 def ties_multigraph(n, m, seed, wmax=4):
     """Random multigraph with self-loops, parallel edges and heavily tied weights."""
     rng = np.random.default_rng(seed)

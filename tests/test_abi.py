@@ -1,0 +1,130 @@
+"""The C ABI without a GPU: the library loads, exports every function that
+include/mstx.h declares, and its host-only paths (argument checks that run
+before any HIP call, status strings, options, workspace sizing) behave as the
+header states.  Also the host-side helper that compares round statistics.
+"""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import gpu_cases
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mstx.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*[A-Za-z_][\w\s\*]*?\b(mst_\w+)\s*\(", text, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2005_06913_amd import binding, build
+    if not os.path.exists(build.LIB):
+        build.build_library()
+    return binding.load_library()
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    for must in ("mst_solve", "mst_solve_batched", "mst_select_min_edges", "mst_workspace_bytes",
+                 "mst_set_dense_limit", "mst_status_string"):
+        assert must in names, names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_status_strings(lib):
+    from paper_2005_06913_amd import binding as B
+    codes = [B.MSTX_OK, B.MSTX_DISCONNECTED, B.MSTX_ERR_INVALID_ARG, B.MSTX_ERR_VERTEX_RANGE,
+             B.MSTX_ERR_TOO_LARGE, B.MSTX_ERR_OUT_OF_MEMORY, B.MSTX_ERR_DEVICE]
+    texts = [B.mst_status_string(c) for c in codes]
+    assert len(set(texts)) == len(codes)
+    assert B.mst_status_string(12345) == "unknown status"
+
+
+def test_host_argument_checks(lib):
+    """Errors the header says are decided on the host return before any device call."""
+    c = ctypes
+    null = c.c_void_p(0)
+    dummy = c.c_void_p(16)  # never dereferenced: the checks fail first
+    B = __import__("paper_2005_06913_amd.binding", fromlist=["x"])
+    assert lib.mst_solve(-1, 0, null, null, null, null, null, null) == B.MSTX_ERR_INVALID_ARG
+    assert lib.mst_solve(4, -1, null, null, null, null, null, null) == B.MSTX_ERR_INVALID_ARG
+    assert lib.mst_solve(4, 1 << 32, dummy, dummy, dummy, dummy, dummy, null) == B.MSTX_ERR_TOO_LARGE
+    assert lib.mst_solve(4, 3, null, dummy, dummy, dummy, dummy, null) == B.MSTX_ERR_INVALID_ARG
+    assert lib.mst_select_min_edges(-5, 0, null, null, null, null, null) == B.MSTX_ERR_INVALID_ARG
+    assert lib.mst_solve_batched(-1, None, None, null, null, null, null, null, null, null) == \
+        B.MSTX_ERR_INVALID_ARG
+    vo = np.array([0, 3, 2], np.int64)  # decreasing offsets
+    eo = np.array([0, 1, 2], np.int64)
+    ptr = lambda a: a.ctypes.data_as(c.c_void_p)
+    assert lib.mst_solve_batched(2, ptr(vo), ptr(eo), dummy, dummy, dummy, dummy, dummy, dummy, null) == \
+        B.MSTX_ERR_INVALID_ARG
+    assert lib.mst_last_round_stats(None, 4) == B.MSTX_ERR_INVALID_ARG
+    assert lib.mst_last_round_stats(None, -1) == B.MSTX_ERR_INVALID_ARG
+    assert lib.mst_workspace_bytes(-1, 5) == 0 and lib.mst_workspace_bytes(5, 1 << 32) == 0
+
+
+def test_dense_limit_option(lib):
+    from paper_2005_06913_amd import binding as B
+    prev = B.mst_set_dense_limit(-1)
+    assert prev == gpu_cases.DENSE_MAX  # default
+    try:
+        assert B.mst_set_dense_limit(1000) == prev
+        assert B.mst_set_dense_limit(-1) == gpu_cases.DENSE_MAX  # clamped
+        assert B.mst_set_dense_limit(0) == gpu_cases.DENSE_MAX
+        assert B.mst_set_dense_limit(-7) == 0
+        with B.dense_limit(17):
+            assert B.mst_set_dense_limit(-1) == 17
+        assert B.mst_set_dense_limit(-1) == 0
+    finally:
+        B.mst_set_dense_limit(prev)
+
+
+def test_workspace_bytes(lib):
+    from paper_2005_06913_amd import binding as B
+    a = B.mst_workspace_bytes(1000, 8000)
+    b = B.mst_workspace_bytes(1 << 20, 1 << 23)
+    assert 0 < a < b
+    # the edge stream dominates: at least 16 B of records per edge
+    assert b >= 16 * (1 << 23)
+    vo = np.array([0, 100, 20000], np.int64)
+    eo = np.array([0, 400, 90000], np.int64)
+    assert B.mst_batched_workspace_bytes(vo, eo) > 0
+
+
+def test_kernel_names(lib):
+    from paper_2005_06913_amd import binding as B
+    names = [lib.mst_profile_kernel_name(i).decode() for i in range(64)]
+    names = [x for x in names if x]
+    assert "k_dense_finish" in names and "k_hook" in names
+    assert "k_scan<3, false, true>" in names
+    assert len(names) == len(set(names))
+    prof = B.mst_profile_read()  # host counters only: no device call
+    assert set(prof) == set(names)
+
+
+# ------------------------------------------------- round statistics helper
+
+def test_stats_consistent_rules():
+    o = [(1000, 8000, 700), (300, 7000, 250), (50, 6500, 40), (10, 3000, 8), (2, 400, 1)]
+    assert gpu_cases.stats_consistent(o, o)
+    # dense finish at round 2 (50 components): adds 40 + 8 + 1
+    assert gpu_cases.stats_consistent(o[:2] + [(50, 6500, 49)], o)
+    # wrong sum, wrong live count, a count above the limit, a changed prefix
+    assert not gpu_cases.stats_consistent(o[:2] + [(50, 6500, 48)], o)
+    assert not gpu_cases.stats_consistent(o[:2] + [(50, 6400, 49)], o)
+    assert not gpu_cases.stats_consistent(o[:2] + [(50, 6500, 49)], o, limit=49)
+    assert not gpu_cases.stats_consistent([(1000, 8000, 701)] + o[1:2] + [(50, 6500, 49)], o)
+    assert not gpu_cases.stats_consistent(o + [(1, 0, 0)], o)
+    assert not gpu_cases.stats_consistent([], o)
