@@ -196,13 +196,49 @@ __global__ void __launch_bounds__(kScanBlock) k_scan(ScanArgs A) {
   const uint64_t lt = lanemask_lt();
   bool bad = false;
 
+  // Raw loads of a segment: (src, dst, w, e) from the caller's arrays or the
+  // record (a, b, w, e) of the previous round.  The next segment of this
+  // workgroup is loaded while the current one is processed (its loads stay in
+  // flight across the barriers, which wait for LDS only).
+  auto seg_count = [&](int32_t s) -> uint32_t {
+    const uint64_t base = (uint64_t)s * kSegCap;
+    if (kFromInput) return base >= A.m ? 0u : (uint32_t)min((uint64_t)kSegCap, (uint64_t)A.m - base);
+    return A.seg_cnt[s];
+  };
+  auto load_seg = [&](int32_t s, uint32_t count, uint4* x) {
+    const uint64_t base = (uint64_t)s * kSegCap;
+#pragma unroll
+    for (int k = 0; k < kPerThread; ++k) {
+      const uint32_t j = k * kScanBlock + threadIdx.x;
+      x[k] = make_uint4(0, 0, 0, 0);
+      if (j < count) {
+        if (kFromInput) {
+          const uint32_t e = (uint32_t)(base + j);
+          x[k] = make_uint4((uint32_t)ld_stream(A.src + e), (uint32_t)ld_stream(A.dst + e), ld_stream(A.w + e), e);
+        } else {
+          x[k] = ld_rec(A.rec + base + j);
+        }
+      }
+    }
+  };
+  uint4 nx[kPerThread];
+  uint32_t ncount = 0;
+  if ((int32_t)blockIdx.x < A.nseg) {
+    ncount = seg_count(blockIdx.x);
+    load_seg(blockIdx.x, ncount, nx);
+  }
   for (int32_t s = blockIdx.x; s < A.nseg; s += gridDim.x) {
     const uint64_t base = (uint64_t)s * kSegCap;
-    uint32_t count;
-    if (kFromInput) {
-      count = base >= A.m ? 0u : (uint32_t)min((uint64_t)kSegCap, (uint64_t)A.m - base);
-    } else {
-      count = A.seg_cnt[s];
+    const uint32_t count = ncount;
+    uint4 cx[kPerThread];
+#pragma unroll
+    for (int k = 0; k < kPerThread; ++k) cx[k] = nx[k];
+    {
+      const int32_t sn = s + (int32_t)gridDim.x;
+      if (sn < A.nseg) {
+        ncount = seg_count(sn);
+        load_seg(sn, ncount, nx);
+      }
     }
     if (kMode == kModeBucket) {
       for (int i = threadIdx.x; i <= nbk; i += kScanBlock) bcnt[i] = 0;
@@ -219,10 +255,10 @@ __global__ void __launch_bounds__(kScanBlock) k_scan(ScanArgs A) {
         int32_t a, b;
         uint32_t we, e;
         if (kFromInput) {
-          e = (uint32_t)(base + j);
-          a = ld_stream(A.src + e);
-          b = ld_stream(A.dst + e);
-          we = ld_stream(A.w + e);
+          a = (int32_t)cx[k].x;
+          b = (int32_t)cx[k].y;
+          we = cx[k].z;
+          e = cx[k].w;
           if (!kCompact) {
             if ((uint32_t)a >= (uint32_t)A.n || (uint32_t)b >= (uint32_t)A.n) {
               bad = true;
@@ -233,11 +269,10 @@ __global__ void __launch_bounds__(kScanBlock) k_scan(ScanArgs A) {
             b = lab[b];
           }
         } else {
-          const uint4 x = ld_rec(A.rec + base + j);
-          a = lab[(int32_t)x.x];
-          b = lab[(int32_t)x.y];
-          we = x.z;
-          e = x.w;
+          a = lab[(int32_t)cx[k].x];
+          b = lab[(int32_t)cx[k].y];
+          we = cx[k].z;
+          e = cx[k].w;
         }
         r[k] = make_uint4((uint32_t)a, (uint32_t)b, we, e);
         // a live edge never touches an isolated (label -1) component
