@@ -39,6 +39,13 @@ WORKLOAD_TEXT = {
                     "graph, local ids, int64 offsets, seed 5",
 }
 BATCHES = {"batched_4096": dict(num_graphs=4096, seed=5)}
+WORKLOAD_TEXT["cpu_context"] = ("Table 1 shapes of the paper: n in {10K, 100K, 1M} x average degree in {3, 6, 9}, "
+                                "random spanning tree + uniform extra pairs, weights a permutation of 1..m, "
+                                "seed 100 + 3i + j; the paper's four CPU variants over a thread sweep, and the "
+                                "GPU solve of the same graphs when a GPU is present")
+PAPER_SPEEDUPS = {"parallel_lock": {"vs_sequential": 1.94, "vs_sequential_covered": 1.40},
+                  "parallel_cas": {"vs_sequential": 2.03, "vs_sequential_covered": 1.403},
+                  "host": "Intel Xeon E-2186G, 6 cores / 12 threads, 3.86 GHz; best at 4 threads"}
 WORKLOAD_TEXT["served"] = ("Poisson request stream, each request one connected random graph: n log-uniform in "
                            "[1024, 1048576], average degree uniform in [4, 32], random spanning tree + uniform "
                            "extra pairs, weights a permutation of 1..m, seed 6")
@@ -325,12 +332,107 @@ def bench_served(args, dev):
     return 0
 
 
+def bench_cpu_context(args) -> int:
+    """The paper's CPU variants on its Table 1 shapes: time per solve for the
+    sequential, covered-sequential, lock and CAS variants over a thread sweep,
+    speedups in the paper's two forms, and the GPU solve of the same graphs
+    (if a GPU is present).  Context only: the paper's own figures are quoted,
+    not reproduced (another machine)."""
+    import numpy as np
+
+    from paper_2005_06913_amd import cpu_baselines as C
+    from paper_2005_06913_amd import graphgen as G
+
+    C.load_library()
+    cores = os.cpu_count() or 1
+    threads = [t for t in (1, 2, 4, 8, 16) if t <= 2 * cores]
+    gpu = None
+    try:
+        import torch
+        if torch.cuda.is_available():
+            import paper_2005_06913_amd as P
+            P.load_library()
+            gpu = (torch, P, torch.device("cuda:0"))
+    except ImportError:
+        pass
+
+    def timed(fn, reps):
+        best = None
+        out = None
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            out = fn()
+            el = time.perf_counter() - t0
+            best = el if best is None else min(best, el)
+        return best, out
+
+    rows = []
+    for i, n in enumerate((10_000, 100_000, 1_000_000)):
+        for j, d in enumerate((3, 6, 9)):
+            g = G.paper_shape(n, d, seed=100 + 3 * i + j)
+            reps = 3 if n < 1_000_000 else 1
+            row = {"graph": f"Graph{n // 1000 if n < 1_000_000 else 1}{'K' if n < 1_000_000 else 'M'}_{d}",
+                   "n": g.n, "m": g.m, "ms": {}}
+            ref = None
+            for v in C.VARIANTS:
+                name = C.mst_cpu_variant_name(v)
+                for t in ((1,) if v in (C.MSTX_CPU_SEQ_PLAIN, C.MSTX_CPU_SEQ_COVERED) else threads):
+                    el, r = timed(lambda: C.mst_cpu_solve(v, t, g.n, g.src, g.dst, g.w), reps)
+                    assert r.status == 0, (row["graph"], name, t, r.status)
+                    if ref is None:
+                        ref = r
+                    assert r.total == ref.total and np.array_equal(r.in_mst, ref.in_mst), (row["graph"], name, t)
+                    key = name if v in (C.MSTX_CPU_SEQ_PLAIN, C.MSTX_CPU_SEQ_COVERED) else f"{name}@{t}"
+                    row["ms"][key] = el * 1e3
+            seq, cov = row["ms"]["sequential"], row["ms"]["sequential_covered"]
+            for name in ("parallel_lock", "parallel_cas"):
+                best_t = min(threads, key=lambda t: row["ms"][f"{name}@{t}"])
+                row[name] = {"best_threads": best_t, "vs_sequential": seq / row["ms"][f"{name}@{best_t}"],
+                             "vs_sequential_covered": cov / row["ms"][f"{name}@{best_t}"],
+                             "at_4_threads_vs_sequential": seq / row["ms"][f"{name}@4"] if 4 in threads else None}
+            row["cas_over_lock_at_4"] = (row["ms"]["parallel_lock@4"] / row["ms"]["parallel_cas@4"]
+                                         if 4 in threads else None)
+            if gpu is not None:
+                torch, P, dev = gpu
+                s_, d_, w_ = (torch.from_numpy(a).to(dev) for a in (g.src, g.dst, g.w))
+                in_mst = torch.empty(g.m, dtype=torch.uint8, device=dev)
+                tot = torch.empty(1, dtype=torch.uint64, device=dev)
+                for _ in range(3):
+                    P.mst_solve(g.n, s_, d_, w_, in_mst, tot)
+                torch.cuda.synchronize()
+                el, st = timed(lambda: P.mst_solve(g.n, s_, d_, w_, in_mst, tot), 10)
+                assert st == 0 and np.array_equal(in_mst.cpu().numpy(), ref.in_mst), row["graph"]
+                row["ms"]["gpu_mst_solve"] = el * 1e3
+                row["gpu_vs_best_cpu"] = min(v for k, v in row["ms"].items() if k != "gpu_mst_solve") / (el * 1e3)
+            log(f"[cpu_context] {row['graph']}: seq {seq:.1f} ms, covered {cov:.1f} ms, "
+                f"lock x{row['parallel_lock']['vs_sequential']:.2f}@{row['parallel_lock']['best_threads']}, "
+                f"cas x{row['parallel_cas']['vs_sequential']:.2f}@{row['parallel_cas']['best_threads']}")
+            rows.append(row)
+    best = max(r["parallel_cas"]["vs_sequential"] for r in rows)
+    try:
+        model = next((ln.split(":", 1)[1].strip() for ln in open("/proc/cpuinfo") if ln.startswith("model name")), "")
+    except OSError:
+        model = ""
+    out = {
+        "metric": "speedup of the paper's CAS variant over the unoptimized sequential variant (best over graphs)",
+        "value": best, "unit": "x", "n_gpus": 1 if gpu else 0, "steps": 1, "warmup": 0, "ms_per_step": None,
+        "higher_is_better": True, "scaling": "strong", "vs_baseline": best / PAPER_SPEEDUPS["parallel_cas"]["vs_sequential"],
+        "dtype": "u32", "data": "synthetic",
+        "config": {"workload": f"cpu_context: {WORKLOAD_TEXT['cpu_context']}", "threads": threads,
+                   "host": {"cores": cores, "model": model}, "leg": "CPU context (paper's variants)"},
+        "paper": PAPER_SPEEDUPS,
+        "rows": rows,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="random_n1M_d16", choices=sorted(WORKLOAD_TEXT) + ["served"])
+    ap.add_argument("--workload", default="random_n1M_d16", choices=sorted(WORKLOAD_TEXT))
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="time budget of the CPU oracle leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cold-reps", type=int, default=5, help="extra solves after a 1 GiB cache flush")
@@ -355,6 +457,9 @@ def main() -> int:
               "the batched and served forms shard by graph and are not part of this benchmark.",
               file=sys.stderr)
         return 2
+
+    if args.workload == "cpu_context":
+        return bench_cpu_context(args)
 
     import numpy as np
     import torch
