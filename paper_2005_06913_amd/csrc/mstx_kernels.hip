@@ -8,9 +8,14 @@
 //             internal (the paper's "covered" edge); otherwise offer the
 //             packed key (w << 32) | e to the minima of both components --
 //             the order is strict, so ties cannot occur.  From round 1 on
-//             the survivors are also compacted in place.  Three ways to
+//             the survivors are also compacted in place.  Four ways to
 //             take the minima, chosen per round on the device from the
 //             actual component count n_r:
+//               DENSE   n_r <= kDenseMax: the lightest edge of every
+//                       component PAIR in LDS; k_dense_finish then completes
+//                       the tree in one workgroup and the round is the last
+//                       (any other edge between two components closes a
+//                       cycle with a lighter one);
 //               LDS     n_r fits one workgroup's LDS: per-workgroup minima
 //                       with ds_min_u64, flushed once to HBM;
 //               BUCKET  components are split into <= 1024 contiguous
