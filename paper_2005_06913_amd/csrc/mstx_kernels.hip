@@ -210,19 +210,22 @@ __global__ void __launch_bounds__(kScanBlock) k_scan(ScanArgs A) {
     if (kFromInput) return base >= A.m ? 0u : (uint32_t)min((uint64_t)kSegCap, (uint64_t)A.m - base);
     return A.seg_cnt[s];
   };
+  // Record loads are unconditional (lanes past the segment's count read its
+  // first slot, in bounds, and are masked later) so that no branch makes the
+  // compiler wait for them early.
   auto load_seg = [&](int32_t s, uint32_t count, uint4* x) {
     const uint64_t base = (uint64_t)s * kSegCap;
 #pragma unroll
     for (int k = 0; k < kPerThread; ++k) {
       const uint32_t j = k * kScanBlock + threadIdx.x;
-      x[k] = make_uint4(0, 0, 0, 0);
-      if (j < count) {
-        if (kFromInput) {
+      if (kFromInput) {
+        x[k] = make_uint4(0, 0, 0, 0);
+        if (j < count) {
           const uint32_t e = (uint32_t)(base + j);
           x[k] = make_uint4((uint32_t)ld_stream(A.src + e), (uint32_t)ld_stream(A.dst + e), ld_stream(A.w + e), e);
-        } else {
-          x[k] = ld_rec(A.rec + base + j);
         }
+      } else {
+        x[k] = ld_rec(A.rec + base + (j < count ? j : 0u));
       }
     }
   };
@@ -235,16 +238,52 @@ __global__ void __launch_bounds__(kScanBlock) k_scan(ScanArgs A) {
   for (int32_t s = blockIdx.x; s < A.nseg; s += gridDim.x) {
     const uint64_t base = (uint64_t)s * kSegCap;
     const uint32_t count = ncount;
+    // the next segment of this workgroup; for the record stream, after the
+    // last one the current segment is loaded again (cache hits), so the loads
+    // are issued on every path and the compiler's wait counts stay exact
+    const bool has_next = s + (int32_t)gridDim.x < A.nseg;
+    const int32_t sn = has_next ? s + (int32_t)gridDim.x : s;
     uint4 cx[kPerThread];
 #pragma unroll
     for (int k = 0; k < kPerThread; ++k) cx[k] = nx[k];
-    {
-      const int32_t sn = s + (int32_t)gridDim.x;
-      if (sn < A.nseg) {
+    // Vector-memory counters retire in issue order.  The next segment's
+    // count goes first.  From the caller's arrays the next segment's loads
+    // follow (round 1's label lookups miss to the last-level cache anyway);
+    // from the record stream this segment's label lookups go first, so they
+    // complete while the next records are still in flight.
+    if (kFromInput) {
+      if (has_next) {
         ncount = seg_count(sn);
         load_seg(sn, ncount, nx);
       }
+    } else {
+      ncount = seg_count(sn);
     }
+    __asm__ __volatile__("" ::: "memory");
+    int32_t ga[kPerThread], gb[kPerThread];
+#pragma unroll
+    for (int k = 0; k < kPerThread; ++k) {
+      const uint32_t j = k * kScanBlock + threadIdx.x;
+      const bool in = j < count;
+      int32_t a = (int32_t)cx[k].x, b = (int32_t)cx[k].y;
+      if (kFromInput && !kCompact) {
+        if (in && ((uint32_t)a >= (uint32_t)A.n || (uint32_t)b >= (uint32_t)A.n)) {
+          bad = true;
+          a = b = -1;  // dropped
+        }
+      } else {
+        // lanes past the count look up entry 0
+        const int32_t va = lab[in ? a : 0];
+        const int32_t vb = lab[in ? b : 0];
+        a = va;
+        b = vb;
+      }
+      ga[k] = a;
+      gb[k] = b;
+    }
+    __asm__ __volatile__("" ::: "memory");
+    if (!kFromInput) load_seg(sn, ncount, nx);
+    __asm__ __volatile__("" ::: "memory");
     if (kMode == kModeBucket) {
       for (int i = threadIdx.x; i <= nbk; i += kScanBlock) bcnt[i] = 0;
       __syncthreads();
@@ -257,28 +296,8 @@ __global__ void __launch_bounds__(kScanBlock) k_scan(ScanArgs A) {
       live[k] = false;
       r[k] = make_uint4(0, 0, 0, 0);
       if (j < count) {
-        int32_t a, b;
-        uint32_t we, e;
-        if (kFromInput) {
-          a = (int32_t)cx[k].x;
-          b = (int32_t)cx[k].y;
-          we = cx[k].z;
-          e = cx[k].w;
-          if (!kCompact) {
-            if ((uint32_t)a >= (uint32_t)A.n || (uint32_t)b >= (uint32_t)A.n) {
-              bad = true;
-              a = b = -1;  // dropped
-            }
-          } else {
-            a = lab[a];
-            b = lab[b];
-          }
-        } else {
-          a = lab[(int32_t)cx[k].x];
-          b = lab[(int32_t)cx[k].y];
-          we = cx[k].z;
-          e = cx[k].w;
-        }
+        const int32_t a = ga[k], b = gb[k];
+        const uint32_t we = cx[k].z, e = cx[k].w;
         r[k] = make_uint4((uint32_t)a, (uint32_t)b, we, e);
         // a live edge never touches an isolated (label -1) component
         live[k] = (a != b) && ((a | b) >= 0);
