@@ -63,7 +63,7 @@ def kernel_source_hash() -> str:
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2005_06913_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
+    for f in sorted(x for x in os.listdir(csrc) if x.endswith((".hip", ".h"))):
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(f.encode() + b"\0" + fh.read())
     return h.hexdigest()

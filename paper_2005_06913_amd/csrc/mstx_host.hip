@@ -75,8 +75,8 @@ Layout plan(int32_t n, int64_t m) {
   L.slab_cap = n > kSlabMin ? (int64_t)kSlabRows * std::min<int32_t>(n, kLdsSlots) : 0;
   if (L.slab_cap) L.slab = take(8 * (size_t)L.slab_cap);
   if (L.bucket) {
-    L.upd_key = take(8 * (size_t)nseg * 2 * kSegCap);
-    L.upd_cl = take(2 * (size_t)nseg * 2 * kSegCap);
+    L.upd_key = take(8 * (size_t)nseg * kOfferCap);
+    L.upd_cl = take(2 * (size_t)nseg * kOfferCap);
     L.offT = take(4 * (size_t)(kMaxBuckets + 1) * nseg);
   }
   L.bytes = off;

@@ -34,8 +34,18 @@ static constexpr int32_t kLdsSlots = kMaxDynLds / 8;  // 20000 u64 minima
 static constexpr int kMaxBuckets = 1023;
 static constexpr int kMaxBucketShift = 14;
 static constexpr int64_t kBucketMaxComponents = (int64_t)kMaxBuckets << kMaxBucketShift;
+// Offer staging of one segment (2 offers per live edge).  With at most
+// kOfferPadBuckets buckets every bucket's run is padded to a multiple of
+// kOfferAlign offers, so each run of keys starts on a 128-byte line and the
+// consumer fetches no line twice; the pad slots are written (whole lines)
+// but never read.  A run is described by one word: start (bits 0..15) and
+// length (bits 16..31).
+static constexpr int kOfferAlign = 16;
+static constexpr int kOfferPadBuckets = 256;
+static constexpr int kOfferCap = 2 * kSegCap + kOfferAlign * kOfferPadBuckets;
+static_assert(kOfferCap < (1 << 16) && 2 * kSegCap < (1 << 16), "offer run word");
 // Bytes of dynamic LDS a BUCKET-mode scan uses: offer staging + counters.
-static constexpr int kBucketScanLds = 2 * kSegCap * (8 + 2) + (kMaxBuckets + 1) * 4;
+static constexpr int kBucketScanLds = kOfferCap * (8 + 2) + (kMaxBuckets + 1) * 4;
 
 // Bucket width 2^shift >= ceil(nr / 256) (about 256 buckets, so one
 // k_bucket_min workgroup per CU) and the bucket count.

@@ -184,9 +184,9 @@ __global__ void __launch_bounds__(kScanBlock) k_scan(ScanArgs A) {
   uint16_t* scl = nullptr;
   if (kMode == kModeBucket) {
     bucket_geometry(nr, &shift, &nbk);
-    skey = smem;                                            // [2 * kSegCap]
-    scl = reinterpret_cast<uint16_t*>(skey + 2 * kSegCap);  // [2 * kSegCap]
-    bcnt = reinterpret_cast<uint32_t*>(scl + 2 * kSegCap);  // [nbk + 1]
+    skey = smem;                                        // [kOfferCap]
+    scl = reinterpret_cast<uint16_t*>(skey + kOfferCap);  // [kOfferCap]
+    bcnt = reinterpret_cast<uint32_t*>(scl + kOfferCap);  // [nbk + 1]
   }
   if (kMode == kModeLds) {
     for (int32_t c = threadIdx.x; c < nr; c += kScanBlock) lbest[c] = kKeyNone;
@@ -358,8 +358,9 @@ __global__ void __launch_bounds__(kScanBlock) k_scan(ScanArgs A) {
     if (threadIdx.x == 0) A.seg_cnt[s] = seg_tot;
 
     if (kMode == kModeBucket) {
-      // exclusive scan of the bucket counters (nbk + 1 <= kScanBlock)
-      const uint32_t v = (int)threadIdx.x < nbk ? bcnt[threadIdx.x] : 0u;
+      // exclusive scan of the (padded) bucket counts (nbk + 1 <= kScanBlock)
+      const uint32_t cnt = (int)threadIdx.x < nbk ? bcnt[threadIdx.x] : 0u;
+      const uint32_t v = nbk <= kOfferPadBuckets ? (cnt + kOfferAlign - 1) & ~(uint32_t)(kOfferAlign - 1) : cnt;
       uint32_t x = v;
       for (int off = 1; off < 64; off <<= 1) {
         const uint32_t y = __shfl_up(x, off, 64);
@@ -371,10 +372,8 @@ __global__ void __launch_bounds__(kScanBlock) k_scan(ScanArgs A) {
       for (int i = 0; i < wave; ++i) wbase += red[i];
       const uint32_t excl = wbase + x - v;
       __syncthreads();  // every thread has read its counter
-      if ((int)threadIdx.x <= nbk) {
-        bcnt[threadIdx.x] = excl;  // for threadIdx == nbk this is the total
-        A.offT[(int64_t)threadIdx.x * A.nseg + s] = excl;
-      }
+      if ((int)threadIdx.x <= nbk) bcnt[threadIdx.x] = excl;  // for threadIdx == nbk this is the total
+      if ((int)threadIdx.x < nbk) A.offT[(int64_t)threadIdx.x * A.nseg + s] = excl | (cnt << 16);
       __syncthreads();
 #pragma unroll
       for (int k = 0; k < kPerThread; ++k) {
@@ -390,8 +389,8 @@ __global__ void __launch_bounds__(kScanBlock) k_scan(ScanArgs A) {
         }
       }
       __syncthreads();
-      const uint32_t total = 2 * seg_tot;
-      const uint64_t obase = (uint64_t)s * (2 * kSegCap);
+      const uint32_t total = bcnt[nbk];  // offers + pads
+      const uint64_t obase = (uint64_t)s * kOfferCap;
       for (uint32_t i = threadIdx.x; i < total; i += kScanBlock) {
         st_stream(skey[i], A.upd_key + obase + i);
         st_stream(scl[i], A.upd_cl + obase + i);
@@ -469,14 +468,14 @@ __global__ void __launch_bounds__(kBlock) k_slab_min(int round, int launched, in
 }
 
 // One workgroup per bucket p: the minimum offer for every component of the
-// bucket, over the runs [offT[p][s], offT[p+1][s]) of every segment s, taken
+// bucket, over the run offT[p][s] (start, length) of every segment s, taken
 // in LDS and written to best[] (every entry of the bucket, "none" included).
 // Runs are short (about 2 * kSegCap / buckets offers), so each half-wave
 // reads kRunsInFlight runs at once, each with coalesced loads; the run bounds
 // of a chunk of segments are staged in LDS first.
 static constexpr int kChunkRuns = 2048;
 static constexpr int kRunsInFlight = 8;
-static constexpr size_t kBucketMinExtraLds = 2 * kChunkRuns * sizeof(uint32_t);
+static constexpr size_t kBucketMinExtraLds = kChunkRuns * sizeof(uint32_t);
 
 __global__ void __launch_bounds__(kScanBlock) k_bucket_min(int round, int launched,
                                                            const unsigned long long* __restrict__ upd_key,
@@ -494,21 +493,16 @@ __global__ void __launch_bounds__(kScanBlock) k_bucket_min(int round, int launch
   const int p = blockIdx.x;
   if (p >= nbk) return;
   const int B = 1 << shift;
-  uint32_t* run_lo = reinterpret_cast<uint32_t*>(table + B);
-  uint32_t* run_hi = run_lo + kChunkRuns;
+  uint32_t* run_w = reinterpret_cast<uint32_t*>(table + B);  // run words of a chunk
   for (int i = threadIdx.x; i < B; i += kScanBlock) table[i] = kKeyNone;
-  const uint32_t* lo_row = offT + (int64_t)p * nseg;
-  const uint32_t* hi_row = offT + (int64_t)(p + 1) * nseg;
+  const uint32_t* row = offT + (int64_t)p * nseg;
   const int half = threadIdx.x >> 5;  // 0 .. 2 * kScanWaves - 1
   const int hl = threadIdx.x & 31;
   constexpr int kHalves = 2 * kScanWaves;
   for (int32_t c0 = 0; c0 < nseg; c0 += kChunkRuns) {
     const int nrun = min(kChunkRuns, nseg - c0);
     __syncthreads();  // table initialised / previous chunk's bounds consumed
-    for (int i = threadIdx.x; i < nrun; i += kScanBlock) {
-      run_lo[i] = lo_row[c0 + i];
-      run_hi[i] = hi_row[c0 + i];
-    }
+    for (int i = threadIdx.x; i < nrun; i += kScanBlock) run_w[i] = row[c0 + i];
     __syncthreads();
     for (int j0 = half * kRunsInFlight; j0 < nrun; j0 += kHalves * kRunsInFlight) {
       uint32_t lo[kRunsInFlight], len[kRunsInFlight];
@@ -518,8 +512,9 @@ __global__ void __launch_bounds__(kScanBlock) k_bucket_min(int round, int launch
         lo[q] = 0;
         len[q] = 0;
         if (j0 + q < nrun) {
-          lo[q] = run_lo[j0 + q];
-          len[q] = run_hi[j0 + q] - lo[q];
+          const uint32_t wd = run_w[j0 + q];
+          lo[q] = wd & 0xFFFFu;
+          len[q] = wd >> 16;
         }
         maxlen = max(maxlen, len[q]);
       }
@@ -531,7 +526,7 @@ __global__ void __launch_bounds__(kScanBlock) k_bucket_min(int round, int launch
           k[q] = kKeyNone;
           c[q] = 0;
           if (i < len[q]) {
-            const uint64_t at = (uint64_t)(c0 + j0 + q) * (2 * kSegCap) + lo[q] + i;
+            const uint64_t at = (uint64_t)(c0 + j0 + q) * kOfferCap + lo[q] + i;
             k[q] = ld_stream(upd_key + at);
             c[q] = ld_stream(upd_cl + at);
           }
