@@ -366,7 +366,7 @@ int enqueue_scan(Solve& S, int r, int stage, int64_t bound, bool exact, hipError
     }
     if (mode == kModeDense && S.in_mst) {
       const int kd = T.start(kDenseFinish, r, mode);
-      err = launch_dense_finish(r, launched, S.pbest, S.seg_cnt, S.L.nseg, S.in_mst, S.total, S.st,
+      err = launch_dense_finish(r, launched, S.pbest, S.seg_cnt, S.L.nseg, S.rec, S.in_mst, S.total, S.st,
                                 S.dc->host_rounds, S.s);
       T.stop(kd);
       if (err != hipSuccess) return launched;
@@ -396,8 +396,7 @@ hipError_t enqueue_round(Solve& S, int r, int64_t bound) {
   if (err != hipSuccess) return err;
   const int gh = grid_for(std::max<int64_t>(bound, 1));
   int k = T.start(kHook, r, -1);
-  err = launch_hook(r, S.src, S.dst, S.w, S.best, S.parent, S.labpool, S.st, S.in_mst, S.part_sel, S.part_w, gh,
-                    S.s);
+  err = launch_hook(r, S.src, S.dst, S.rec, S.best, S.parent, S.st, S.in_mst, S.part_sel, S.part_w, gh, S.s);
   T.stop(k);
   if (err != hipSuccess) return err;
   k = T.start(kCompress, r, -1);
@@ -467,10 +466,13 @@ int solve_locked(DeviceCache* dc, const Layout& L, int32_t n, int64_t m, const i
   nr_of[0] = n;
   int r_enq = 0;
   for (int r = 0; r < max_rounds; ++r) {
-    if (r_enq == r && r + 1 <= kMaxRounds - 1) {
+    // a round that can only be the dense finish is the last one: nothing to enqueue after it
+    const bool final_round = (S.launched[r] & 0xFF) == (1 << kModeDense);
+    if (r_enq == r && r + 1 <= kMaxRounds - 1 && !final_round) {
       HIP_OK(enqueue_round(S, r + 1, n_known / 2));
       r_enq = r + 1;
     }
+    if (r_enq < r) break;  // never: the round before was final (status stays MSTX_ERR_DEVICE)
     HIP_OK(hipEventSynchronize(dc->round_ev[r]));
     const HostRound M = dc->host_rounds[r];
     rounds = r + 1;

@@ -167,14 +167,17 @@ __global__ void __launch_bounds__(kBlock) k_fill_u64(unsigned long long* p, int6
 template <int kMode, bool kFromInput, bool kCompact>
 __global__ void __launch_bounds__(kScanBlock) k_scan(ScanArgs A) {
   extern __shared__ unsigned long long smem[];
-  __shared__ uint32_t wave_tot[kScanWaves];
+  __shared__ uint32_t slot_tot[kPerThread * kScanWaves];  // survivors per (slot k, wave)
   __shared__ uint32_t red[kScanWaves];
+  static_assert(kPerThread * kScanWaves == 64, "one lane per (slot, wave) pair");
   const int32_t nr = A.st->n[A.round];
   if (nr <= 1 && A.round > 0) return;
   // a round enqueued before the host saw an input error in round 0 does nothing
   if (A.round > 0 && A.st->err) return;
   if (pick_mode(nr, A.launched) != kMode) return;
   const int32_t* __restrict__ lab = kCompact ? A.labpool + A.st->lab_off[A.round - 1] : nullptr;
+  // keys carry stream positions from round 1 on (see below)
+  constexpr bool kPosKey = kCompact && !(kFromInput && kMode == kModeDense);
 
   unsigned long long* lbest = smem;  // LDS mode
   // BUCKET mode: geometry derived from n_r exactly as k_bucket_min does
@@ -301,32 +304,19 @@ __global__ void __launch_bounds__(kScanBlock) k_scan(ScanArgs A) {
         r[k] = make_uint4((uint32_t)a, (uint32_t)b, we, e);
         // a live edge never touches an isolated (label -1) component
         live[k] = (a != b) && ((a | b) >= 0);
-        if (live[k]) {
-          const uint64_t key = make_key(we, e);
-          if (kMode == kModeDense) {
-            const int32_t lo = a < b ? a : b, hi = a < b ? b : a;
-            lower_lds(lbest, pair_index(lo, hi, nr), key);
-          } else if (kMode == kModeLds) {
-            lower_lds(lbest, a, key);
-            lower_lds(lbest, b, key);
-          } else if (kMode == kModeGlobal) {
-            lower_global(A.best, a, key);
-            lower_global(A.best, b, key);
-          }
-        }
       }
     }
 
-    // survivors of this segment: wave-level offsets (slot-major inside a wave)
+    // survivors of this segment, in input order: record j = k * kScanBlock +
+    // threadIdx.x, so the order is (slot k, wave, lane); rank inside the
+    // wave's slot now, offsets of the (k, wave) groups after the barrier
     uint32_t my_off[kPerThread];
-    uint32_t run = 0;
 #pragma unroll
     for (int k = 0; k < kPerThread; ++k) {
       const uint64_t mask = __ballot(live[k]);
-      my_off[k] = run + (uint32_t)__popcll(mask & lt);
-      run += (uint32_t)__popcll(mask);
+      my_off[k] = (uint32_t)__popcll(mask & lt);
+      if (lane_id() == 0) slot_tot[k * kScanWaves + wave] = (uint32_t)__popcll(mask);
     }
-    if (lane_id() == 0) wave_tot[wave] = run;
 
     // BUCKET mode: claim a slot in the offer staging for both ends
     uint32_t slot_a[kPerThread], slot_b[kPerThread];
@@ -342,17 +332,52 @@ __global__ void __launch_bounds__(kScanBlock) k_scan(ScanArgs A) {
     }
     __syncthreads();  // all reads of this segment are done past this point
 
-    uint32_t wave_off = 0, seg_tot = 0;
+    uint32_t seg_tot;
+    {
+      // exclusive scan of the 64 group counts across one wave's lanes
+      const uint32_t v = slot_tot[lane_id()];
+      uint32_t x = v;
+      for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off, 64);
+        if (lane_id() >= off) x += y;
+      }
+      seg_tot = __shfl(x, 63, 64);
+      const uint32_t excl = x - v;
 #pragma unroll
-    for (int i = 0; i < kScanWaves; ++i) {
-      const uint32_t v = wave_tot[i];
-      wave_off += (i < wave) ? v : 0u;
-      seg_tot += v;
+      for (int k = 0; k < kPerThread; ++k) my_off[k] += __shfl(excl, k * kScanWaves + wave, 64);
+    }
+    // Keys: the weight in the high half; in the low half the edge's index
+    // (round 0, and a dense round that reads the caller's arrays) or the
+    // edge's position in the record stream after this scan.  The stream keeps
+    // the input order (stable compaction inside fixed segments), so
+    // positions break ties exactly as indices do, and the hook reads the
+    // record there (this round's labels and the edge index) instead of
+    // following the label maps of every earlier round.  A dense round moves
+    // no record: its positions are the ones read.
+    uint64_t key[kPerThread];
+#pragma unroll
+    for (int k = 0; k < kPerThread; ++k) {
+      const uint32_t j = k * kScanBlock + threadIdx.x;
+      const uint32_t pos = kMode == kModeDense ? (uint32_t)(base + j) : (uint32_t)(base + my_off[k]);
+      key[k] = make_key(r[k].z, kPosKey ? pos : r[k].w);
+      if (live[k]) {
+        const int32_t a = (int32_t)r[k].x, b = (int32_t)r[k].y;
+        if (kMode == kModeDense) {
+          const int32_t lo = a < b ? a : b, hi = a < b ? b : a;
+          lower_lds(lbest, pair_index(lo, hi, nr), key[k]);
+        } else if (kMode == kModeLds) {
+          lower_lds(lbest, a, key[k]);
+          lower_lds(lbest, b, key[k]);
+        } else if (kMode == kModeGlobal) {
+          lower_global(A.best, a, key[k]);
+          lower_global(A.best, b, key[k]);
+        }
+      }
     }
     if (kCompact && kMode != kModeDense) {
 #pragma unroll
       for (int k = 0; k < kPerThread; ++k) {
-        if (live[k]) st_rec(r[k], A.rec + base + wave_off + my_off[k]);
+        if (live[k]) st_rec(r[k], A.rec + base + my_off[k]);
       }
     }
     if (threadIdx.x == 0) A.seg_cnt[s] = seg_tot;
@@ -378,13 +403,12 @@ __global__ void __launch_bounds__(kScanBlock) k_scan(ScanArgs A) {
 #pragma unroll
       for (int k = 0; k < kPerThread; ++k) {
         if (live[k]) {
-          const uint64_t key = make_key(r[k].z, r[k].w);
           const int32_t a = (int32_t)r[k].x, b = (int32_t)r[k].y;
           const uint32_t pa = bcnt[a >> shift] + slot_a[k];
           const uint32_t pb = bcnt[b >> shift] + slot_b[k];
-          skey[pa] = key;
+          skey[pa] = key[k];
           scl[pa] = (uint16_t)(a & ((1 << shift) - 1));
-          skey[pb] = key;
+          skey[pb] = key[k];
           scl[pb] = (uint16_t)(b & ((1 << shift) - 1));
         }
       }
@@ -396,7 +420,7 @@ __global__ void __launch_bounds__(kScanBlock) k_scan(ScanArgs A) {
         st_stream(scl[i], A.upd_cl + obase + i);
       }
     }
-    __syncthreads();  // LDS (wave_tot, counters, staging) is reused by the next segment
+    __syncthreads();  // LDS (group counts, counters, staging) is reused by the next segment
   }
   if (!kCompact && bad) A.st->err = 1;
   if (kMode == kModeDense) {
@@ -553,8 +577,9 @@ static constexpr int kDenseRowSlots = (kDenseMax + kDenseWaves - 1) / kDenseWave
 
 // Finishes the solve on the k = n_r <= kDenseMax components of round r, one
 // workgroup: vertex u of the small graph is component u, edge {u, v} the
-// lightest original edge between them, pbest[pair_index(u, v)] (none: no
-// edge).  Boruvka again, on that graph, with everything in LDS: every group
+// lightest original edge between them, key pbest[pair_index(u, v)] (none: no
+// edge; the key's low half is the edge index, or from round 2 on the
+// position of its record).  Boruvka again, on that graph, with everything in LDS: every group
 // of the small graph takes its lightest outgoing key (row minima, then an LDS
 // atomicMin per group), hooks onto the group at the far end (of a mutual pair
 // the smaller id stays root), and pointer jumping flattens the parents.  The
@@ -564,6 +589,7 @@ static constexpr int kDenseRowSlots = (kDenseMax + kDenseWaves - 1) / kDenseWave
 __global__ void __launch_bounds__(kDenseThreads) k_dense_finish(int round, int launched,
                                                                const unsigned long long* __restrict__ pbest,
                                                                const uint32_t* __restrict__ seg_cnt, int32_t nseg,
+                                                               const uint4* __restrict__ rec,
                                                                uint8_t* __restrict__ in_mst, unsigned long long* total,
                                                                DevState* st, HostRound* host) {
   extern __shared__ unsigned long long dsm[];
@@ -641,7 +667,9 @@ __global__ void __launch_bounds__(kDenseThreads) k_dense_finish(int round, int l
         if (!(tgt[t] == g && g < t)) {
           par[g] = t;
           const unsigned long long key = gbest[g];
-          in_mst[(uint32_t)key] = 1;
+          // from round 2 on the key holds the record's position (the dense
+          // scan moves no record), before that the edge index
+          in_mst[round >= 2 ? rec[(uint32_t)key].w : (uint32_t)key] = 1;
           wsum += key >> 32;
           ++added;
         }
@@ -714,21 +742,22 @@ __device__ __forceinline__ int32_t walk_root(int32_t* parent, int32_t x) {
   return x;
 }
 
-// For each component c with a minimum edge e = low32(best[c]): d = the other
-// end's component (the ends' labels are followed through the label maps of
-// the earlier rounds).  If c and d chose each other only the smaller id acts,
-// so every distinct selected edge has one owner thread.  Then: repeat
-// { x = root(c), y = root(d); CAS parent[max] from max to min }.  Parents
-// always point to smaller ids, so the forest never gets a cycle.  When the
-// CAS fails, the value it returns (a fresh, strictly smaller ancestor) is
-// where that side's walk resumes, so stale loads cannot make the loop spin.
+// For each component c with a minimum key: the edge e and d = the other
+// end's component.  Round 0: the key holds e, and the ends are the caller's
+// vertex ids.  Later rounds: the key holds the edge's position in the record
+// stream, whose record has this round's labels of both ends and e.  If c and
+// d chose each other only the smaller id acts, so every distinct selected
+// edge has one owner thread.  Then: repeat { x = root(c), y = root(d); CAS
+// parent[max] from max to min }.  Parents always point to smaller ids, so
+// the forest never gets a cycle.  When the CAS fails, the value it returns
+// (a fresh, strictly smaller ancestor) is where that side's walk resumes, so
+// stale loads cannot make the loop spin.
 __global__ void __launch_bounds__(kBlock) k_hook(int round, const int32_t* __restrict__ src,
                                                  const int32_t* __restrict__ dst,
-                                                 const uint32_t* __restrict__ w,
+                                                 const uint4* __restrict__ rec,
                                                  const unsigned long long* __restrict__ best,
-                                                 int32_t* parent, const int32_t* __restrict__ labpool,
-                                                 DevState* __restrict__ st, uint8_t* __restrict__ in_mst,
-                                                 uint32_t* __restrict__ part_sel,
+                                                 int32_t* parent, DevState* __restrict__ st,
+                                                 uint8_t* __restrict__ in_mst, uint32_t* __restrict__ part_sel,
                                                  unsigned long long* __restrict__ part_w) {
   __shared__ uint32_t red32[kBlock / 64];
   __shared__ unsigned long long red64[kBlock / 64];
@@ -742,13 +771,17 @@ __global__ void __launch_bounds__(kBlock) k_hook(int round, const int32_t* __res
     const int32_t c = (int32_t)ci;
     const unsigned long long key = best[c];
     if (key == kKeyNone) continue;
-    const uint32_t e = (uint32_t)key;
-    int32_t u = src[e];
-    int32_t v = dst[e];
-    for (int j = 0; j < round; ++j) {
-      const int64_t off = st->lab_off[j];
-      u = labpool[off + u];
-      v = labpool[off + v];
+    int32_t u, v;
+    uint32_t e;
+    if (round == 0) {
+      e = (uint32_t)key;
+      u = src[e];
+      v = dst[e];
+    } else {
+      const uint4 x = ld_rec(rec + (uint32_t)key);
+      u = (int32_t)x.x;
+      v = (int32_t)x.y;
+      e = x.w;
     }
     const int32_t d = (u == c) ? v : u;
     if ((uint32_t)d >= (uint32_t)nr || (u != c && v != c)) {
@@ -1051,19 +1084,19 @@ hipError_t launch_slab_min(int round, int launched, int mode, const unsigned lon
 }
 
 hipError_t launch_dense_finish(int round, int launched, const unsigned long long* pbest, const uint32_t* seg_cnt,
-                               int32_t nseg, uint8_t* in_mst, unsigned long long* total, DevState* st,
-                               HostRound* host, hipStream_t s) {
+                               int32_t nseg, const uint4* rec, uint8_t* in_mst, unsigned long long* total,
+                               DevState* st, HostRound* host, hipStream_t s) {
   const int32_t kmax = launched_dense_limit(launched) < kDenseMax ? launched_dense_limit(launched) : kDenseMax;
   const size_t lds = dense_finish_lds(kmax);
-  k_dense_finish<<<1, kDenseThreads, lds, s>>>(round, launched, pbest, seg_cnt, nseg, in_mst, total, st, host);
+  k_dense_finish<<<1, kDenseThreads, lds, s>>>(round, launched, pbest, seg_cnt, nseg, rec, in_mst, total, st, host);
   MSTX_LAUNCH_CHECK();
   return hipSuccess;
 }
 
-hipError_t launch_hook(int round, const int32_t* src, const int32_t* dst, const uint32_t* w,
-                       const unsigned long long* best, int32_t* parent, const int32_t* labpool, DevState* st,
-                       uint8_t* in_mst, uint32_t* part_sel, unsigned long long* part_w, int grid, hipStream_t s) {
-  k_hook<<<grid, kBlock, 0, s>>>(round, src, dst, w, best, parent, labpool, st, in_mst, part_sel, part_w);
+hipError_t launch_hook(int round, const int32_t* src, const int32_t* dst, const uint4* rec,
+                       const unsigned long long* best, int32_t* parent, DevState* st, uint8_t* in_mst,
+                       uint32_t* part_sel, unsigned long long* part_w, int grid, hipStream_t s) {
+  k_hook<<<grid, kBlock, 0, s>>>(round, src, dst, rec, best, parent, st, in_mst, part_sel, part_w);
   MSTX_LAUNCH_CHECK();
   return hipSuccess;
 }
