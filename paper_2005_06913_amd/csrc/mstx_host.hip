@@ -318,7 +318,7 @@ struct Solve {
 
 // Enqueues the scan of `stage` (0: round 0, 1: round 1, 2: rounds >= 2) for a
 // round whose component count is at most `bound`.  Returns the launched mask.
-int enqueue_scan(Solve& S, int r, int stage, int64_t bound, bool exact, hipError_t& err) {
+int enqueue_scan(Solve& S, int r, int stage, int64_t bound, bool exact, hipError_t& err, int64_t n_prev = 0) {
   LaunchTimer& T = t_timer;
   const int hi_mode = mode_for(bound, S.dense_limit);
   int launched = 1 << hi_mode;
@@ -331,7 +331,7 @@ int enqueue_scan(Solve& S, int r, int stage, int64_t bound, bool exact, hipError
   if (!S.L.bucket) launched &= ~(1 << kModeBucket), launched |= (bound > kLdsSlots ? 1 << kModeGlobal : 0);
   launched |= S.dense_limit << 8;
   ScanArgs A{r,      launched, S.src,     S.dst,    S.w,    (uint32_t)S.m, S.n,     S.labpool, S.rec,
-             S.seg_cnt, S.L.nseg, S.best, S.st, S.upd_key, S.upd_cl, S.offT, S.slab, S.L.slab_cap, S.pbest};
+             S.seg_cnt, S.L.nseg, S.best, S.st, S.upd_key, S.upd_cl, S.offT, S.slab, S.L.slab_cap, S.pbest, -1};
   const int cus = S.dc->cus;
   for (int mode : {kModeDense, kModeLds, kModeBucket, kModeGlobal}) {
     if (!(launched & (1 << mode))) continue;
@@ -351,6 +351,16 @@ int enqueue_scan(Solve& S, int r, int stage, int64_t bound, bool exact, hipError
     } else {
       lds = 0;
       grid = std::min(S.L.nseg, 2 * cus);
+    }
+    // the previous round's label map (n_prev entries, exact) goes to LDS
+    // beside the minima table when both fit: the lookups become LDS reads
+    A.lab_lds_off = -1;
+    if (stage == 2 && (mode == kModeLds || mode == kModeDense) && n_prev > 0) {
+      const size_t off = (lds + 15) & ~size_t(15);
+      if (off + 4 * (size_t)n_prev <= (size_t)kMaxDynLds) {
+        A.lab_lds_off = (int32_t)off;
+        lds = off + 4 * (size_t)n_prev;
+      }
     }
     const int k = T.start(scan_kind(stage, mode), r, mode);
     err = launch_scan(mode, stage, A, grid, lds, S.s);
@@ -388,11 +398,11 @@ int enqueue_scan(Solve& S, int r, int stage, int64_t bound, bool exact, hipError
 }
 
 // Enqueues round r (component count at most `bound`, exact when r == 0).
-hipError_t enqueue_round(Solve& S, int r, int64_t bound) {
+hipError_t enqueue_round(Solve& S, int r, int64_t bound, int64_t n_prev = 0) {
   LaunchTimer& T = t_timer;
   hipError_t err = hipSuccess;
   const int stage = r == 0 ? 0 : (r == 1 ? 1 : 2);
-  S.launched[r] = enqueue_scan(S, r, stage, bound, r == 0, err);
+  S.launched[r] = enqueue_scan(S, r, stage, bound, r == 0, err, n_prev);
   if (err != hipSuccess) return err;
   const int gh = grid_for(std::max<int64_t>(bound, 1));
   int k = T.start(kHook, r, -1);
@@ -469,7 +479,8 @@ int solve_locked(DeviceCache* dc, const Layout& L, int32_t n, int64_t m, const i
     // a round that can only be the dense finish is the last one: nothing to enqueue after it
     const bool final_round = (S.launched[r] & 0xFF) == (1 << kModeDense);
     if (r_enq == r && r + 1 <= kMaxRounds - 1 && !final_round) {
-      HIP_OK(enqueue_round(S, r + 1, n_known / 2));
+      // n_known entered round r: the size of the label map round r + 1 reads
+      HIP_OK(enqueue_round(S, r + 1, n_known / 2, n_known));
       r_enq = r + 1;
     }
     if (r_enq < r) break;  // never: the round before was final (status stays MSTX_ERR_DEVICE)

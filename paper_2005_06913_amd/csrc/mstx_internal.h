@@ -134,6 +134,7 @@ struct ScanArgs {
   unsigned long long* slab;     // LDS mode, n_r > kSlabMin: per-workgroup minima [grid][n_r]
   int64_t slab_cap;             // entries of slab
   unsigned long long* pbest;    // dense mode: lightest key per component pair [kDensePairsMax]
+  int32_t lab_lds_off;          // rounds >= 2: byte offset of the label map copy in LDS (-1: none)
 };
 
 // LDS-mode minima of more than kSlabMin components are flushed through a

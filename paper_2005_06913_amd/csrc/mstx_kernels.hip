@@ -178,6 +178,15 @@ __global__ void __launch_bounds__(kScanBlock) k_scan(ScanArgs A) {
   const int32_t* __restrict__ lab = kCompact ? A.labpool + A.st->lab_off[A.round - 1] : nullptr;
   // keys carry stream positions from round 1 on (see below)
   constexpr bool kPosKey = kCompact && !(kFromInput && kMode == kModeDense);
+  // rounds >= 2 in LDS / DENSE mode: the previous round's label map may be
+  // staged in LDS behind the minima table (the host sized the allocation)
+  const int32_t* llab = nullptr;
+  if (!kFromInput && (kMode == kModeLds || kMode == kModeDense) && A.lab_lds_off >= 0) {
+    int32_t* dst_l = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(smem) + A.lab_lds_off);
+    const int32_t nprev = A.st->n[A.round - 1];
+    for (int32_t i = threadIdx.x; i < nprev; i += kScanBlock) dst_l[i] = lab[i];
+    llab = dst_l;  // visible to all after the table initialisation's barrier below
+  }
 
   unsigned long long* lbest = smem;  // LDS mode
   // BUCKET mode: geometry derived from n_r exactly as k_bucket_min does
@@ -274,6 +283,9 @@ __global__ void __launch_bounds__(kScanBlock) k_scan(ScanArgs A) {
           bad = true;
           a = b = -1;  // dropped
         }
+      } else if (!kFromInput && (kMode == kModeLds || kMode == kModeDense) && llab != nullptr) {
+        a = llab[in ? a : 0];
+        b = llab[in ? b : 0];
       } else {
         // lanes past the count look up entry 0
         const int32_t va = lab[in ? a : 0];
