@@ -13,7 +13,9 @@
  *
  * Method (Sections 2.1 and 2.2.2): Boruvka rounds.  Each round every component
  * selects its lightest outgoing edge (64-bit atomic minimum on the packed key
- * (w << 32) | e), components are united along the selected edges by
+ * (w << 32) | e; from round 1 on the low half is the edge's position in the
+ * stably compacted edge stream, which orders edges exactly as e does),
+ * components are united along the selected edges by
  * compare-and-swap hooking of the larger root under the smaller one, parent
  * pointers are compressed, components are renumbered densely, and edges that
  * became internal are dropped (the paper's "covered" edges).  Rounds repeat

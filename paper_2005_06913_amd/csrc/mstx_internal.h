@@ -6,7 +6,8 @@
 
 namespace mstx {
 
-// No edge: larger than every real key ((w << 32) | e with e <= 0xFFFFFFFE).
+// No edge: larger than every real key ((w << 32) | e, or the record position
+// instead of e, both <= 0xFFFFFFFE).
 static constexpr unsigned long long kKeyNone = ~0ull;
 
 // Rounds recorded: components with an outgoing edge at least halve every

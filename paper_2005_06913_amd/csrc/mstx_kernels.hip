@@ -7,7 +7,9 @@
 //   scan      every live edge: labels of both ends at this round; drop it if
 //             internal (the paper's "covered" edge); otherwise offer the
 //             packed key (w << 32) | e to the minima of both components --
-//             the order is strict, so ties cannot occur.  From round 1 on
+//             the order is strict, so ties cannot occur (from round 1 on
+//             the low half is the record's position in the stream, which
+//             orders like e; the hook reads the record there).  From round 1 on
 //             the survivors are also compacted in place.  Four ways to
 //             take the minima, chosen per round on the device from the
 //             actual component count n_r:
