@@ -35,7 +35,7 @@ constexpr int kMaxGrid = 4096;  // capacity of the per-block partial arrays (hoo
 
 struct Layout {
   size_t best, parent, root_of, labpool, rootmask, rootcnt, rootpre, rec, seg_cnt, part_sel, part_w, state,
-      pbest, upd_key, upd_cl, offT, slab, bytes;
+      pbest, btot, upd_key, upd_cl, offT, slab, bytes;
   int64_t slab_cap;  // u64 entries of the LDS-mode slab (0: none)
   int32_t nseg;
   bool bucket;  // offer buffers present
@@ -72,6 +72,7 @@ Layout plan(int32_t n, int64_t m) {
   L.part_w = take(8 * (size_t)kMaxGrid);
   L.state = take(sizeof(DevState));
   L.pbest = take(8 * (size_t)kDensePairsMax);
+  L.btot = take(4 * (size_t)kMaxBuckets);
   L.slab_cap = n > kSlabMin ? (int64_t)kSlabRows * std::min<int32_t>(n, kLdsSlots) : 0;
   if (L.slab_cap) L.slab = take(8 * (size_t)L.slab_cap);
   if (L.bucket) {
@@ -312,6 +313,7 @@ struct Solve {
   uint32_t* offT;
   unsigned long long* slab;
   unsigned long long* pbest;
+  uint32_t* btot;
   int dense_limit;            // 0: no dense finish
   std::vector<int> launched;  // per round
 };
@@ -331,7 +333,8 @@ int enqueue_scan(Solve& S, int r, int stage, int64_t bound, bool exact, hipError
   if (!S.L.bucket) launched &= ~(1 << kModeBucket), launched |= (bound > kLdsSlots ? 1 << kModeGlobal : 0);
   launched |= S.dense_limit << 8;
   ScanArgs A{r,      launched, S.src,     S.dst,    S.w,    (uint32_t)S.m, S.n,     S.labpool, S.rec,
-             S.seg_cnt, S.L.nseg, S.best, S.st, S.upd_key, S.upd_cl, S.offT, S.slab, S.L.slab_cap, S.pbest, -1};
+             S.seg_cnt, S.L.nseg, S.best, S.st, S.upd_key, S.upd_cl, S.offT, S.slab, S.L.slab_cap, S.pbest, -1,
+             S.btot};
   const int cus = S.dc->cus;
   for (int mode : {kModeDense, kModeLds, kModeBucket, kModeGlobal}) {
     if (!(launched & (1 << mode))) continue;
@@ -385,10 +388,11 @@ int enqueue_scan(Solve& S, int r, int stage, int64_t bound, bool exact, hipError
       int shift, nbk;
       bucket_geometry((int32_t)std::min<int64_t>(bound, kBucketMaxComponents), &shift, &nbk);
       // a smaller actual count can have more (narrower) buckets, but never more than 256
-      // unless the width is at its maximum
-      const int grid_b = std::max(nbk, 256);
+      // unless the width is at its maximum; the extra workgroups serve buckets with
+      // more than twice the average offers (at most half as many again)
+      const int grid_b = std::max(nbk, 256) * 3 / 2 + 1;
       const int kb = T.start(kBucketMin, r, kModeBucket);
-      err = launch_bucket_min(r, launched, S.upd_key, S.upd_cl, S.offT, S.L.nseg, S.best, S.st, grid_b,
+      err = launch_bucket_min(r, launched, S.upd_key, S.upd_cl, S.offT, S.L.nseg, S.btot, S.best, S.st, grid_b,
                               (size_t)8 << shift, S.s);
       T.stop(kb);
       if (err != hipSuccess) return launched;
@@ -419,7 +423,7 @@ hipError_t enqueue_round(Solve& S, int r, int64_t bound, int64_t n_prev = 0) {
   T.stop(k);
   if (err != hipSuccess) return err;
   k = T.start(kRelabel, r, -1);
-  err = launch_relabel(r, S.root_of, S.rootmask, S.rootpre, S.labpool, S.parent, S.best, S.st, gh, S.s);
+  err = launch_relabel(r, S.root_of, S.rootmask, S.rootpre, S.labpool, S.parent, S.best, S.btot, S.st, gh, S.s);
   T.stop(k);
   if (err != hipSuccess) return err;
   return hipEventRecord(S.dc->round_ev[r], S.s);
@@ -458,6 +462,7 @@ int solve_locked(DeviceCache* dc, const Layout& L, int32_t n, int64_t m, const i
   S.offT = L.bucket ? at<uint32_t>(B, L.offT) : nullptr;
   S.slab = L.slab_cap ? at<unsigned long long>(B, L.slab) : nullptr;
   S.pbest = at<unsigned long long>(B, L.pbest);
+  S.btot = at<uint32_t>(B, L.btot);
   S.dense_limit = g_dense_limit.load();
   const int max_rounds = std::min(rounds_bound(n) + 1, kMaxRounds);
   S.launched.assign(kMaxRounds + 1, 0);
@@ -466,7 +471,7 @@ int solve_locked(DeviceCache* dc, const Layout& L, int32_t n, int64_t m, const i
   T.begin(s);
   HIP_OK(hipMemsetAsync(in_mst, 0, (size_t)m, s));
   HIP_OK(hipMemsetAsync(total, 0, sizeof(uint64_t), s));
-  HIP_OK(launch_init(n, S.best, S.parent, S.dense_limit > 0 ? S.pbest : nullptr, S.st, grid_for(n), s));
+  HIP_OK(launch_init(n, S.best, S.parent, S.dense_limit > 0 ? S.pbest : nullptr, S.btot, S.st, grid_for(n), s));
   HIP_OK(enqueue_round(S, 0, n));
 
   int status = MSTX_ERR_DEVICE;  // until the loop decides
@@ -745,12 +750,13 @@ int select_min_edges(int32_t n, int64_t m, const int32_t* src, const int32_t* ds
   S.offT = L.bucket ? at<uint32_t>(B, L.offT) : nullptr;
   S.slab = L.slab_cap ? at<unsigned long long>(B, L.slab) : nullptr;
   S.pbest = at<unsigned long long>(B, L.pbest);
+  S.btot = at<uint32_t>(B, L.btot);
   S.dense_limit = 0;  // per-vertex minima: never the pair table
   S.in_mst = nullptr;
   S.launched.assign(1, 0);
   t_timer.begin(s);
   t_timer.on = false;
-  HIP_OK(launch_init(n, S.best, at<int32_t>(B, L.parent), nullptr, S.st, grid_for(n), s));
+  HIP_OK(launch_init(n, S.best, at<int32_t>(B, L.parent), nullptr, S.btot, S.st, grid_for(n), s));
   if (m > 0) {
     hipError_t err = hipSuccess;
     enqueue_scan(S, 0, 0, n, true, err);

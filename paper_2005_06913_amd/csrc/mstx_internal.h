@@ -136,6 +136,7 @@ struct ScanArgs {
   int64_t slab_cap;             // entries of slab
   unsigned long long* pbest;    // dense mode: lightest key per component pair [kDensePairsMax]
   int32_t lab_lds_off;          // rounds >= 2: byte offset of the label map copy in LDS (-1: none)
+  uint32_t* btot;               // BUCKET mode: offers per bucket, summed over the scan [kMaxBuckets]
 };
 
 // LDS-mode minima of more than kSlabMin components are flushed through a
@@ -164,13 +165,13 @@ hipError_t launch_graph_epilogue(const int32_t* glist, int ng, const int64_t* vo
                                  const int32_t* gbad, uint8_t* in_mst, unsigned long long* total, int32_t* status,
                                  hipStream_t s);
 hipError_t launch_init(int32_t n, unsigned long long* best, int32_t* parent, unsigned long long* pbest,
-                       DevState* st, int grid, hipStream_t s);
+                       uint32_t* btot, DevState* st, int grid, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, int64_t count, unsigned long long v, int grid,
                            hipStream_t s);
 hipError_t launch_scan(int mode, int stage, const ScanArgs& a, int grid, size_t lds, hipStream_t s);
 hipError_t launch_bucket_min(int round, int launched, const unsigned long long* upd_key, const uint16_t* upd_cl,
-                             const uint32_t* offT, int32_t nseg, unsigned long long* best, const DevState* st,
-                             int grid, size_t lds, hipStream_t s);
+                             const uint32_t* offT, int32_t nseg, const uint32_t* btot, unsigned long long* best,
+                             const DevState* st, int grid, size_t lds, hipStream_t s);
 hipError_t launch_slab_min(int round, int launched, int mode, const unsigned long long* slab, int64_t slab_cap,
                            int nwg, unsigned long long* best, unsigned long long* pbest, const DevState* st,
                            int grid, hipStream_t s);
@@ -189,6 +190,6 @@ hipError_t launch_finalize(int round, const int32_t* rootcnt, int32_t* rootpre, 
                            hipStream_t s);
 hipError_t launch_relabel(int round, const int32_t* root_of, const unsigned long long* rootmask,
                           const int32_t* rootpre, int32_t* labpool, int32_t* parent, unsigned long long* best,
-                          const DevState* st, int grid, hipStream_t s);
+                          uint32_t* btot, const DevState* st, int grid, hipStream_t s);
 
 }  // namespace mstx

@@ -129,7 +129,7 @@ __device__ __forceinline__ T block_sum(T v, T* scratch /* [NW] */) {
 
 // best[0..n) <- none, parent[c] <- c, state for round 0.
 __global__ void __launch_bounds__(kBlock) k_init(int32_t n, unsigned long long* best, int32_t* parent,
-                                                 unsigned long long* pbest, DevState* st) {
+                                                 unsigned long long* pbest, uint32_t* btot, DevState* st) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += stride) {
     best[c] = kKeyNone;
@@ -138,6 +138,8 @@ __global__ void __launch_bounds__(kBlock) k_init(int32_t n, unsigned long long* 
   if (pbest)
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < kDensePairsMax; i += stride)
       pbest[i] = kKeyNone;
+  if (btot)
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < kMaxBuckets; i += stride) btot[i] = 0;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     st->n[0] = n;
     st->lab_off[0] = 0;
@@ -214,6 +216,7 @@ __global__ void __launch_bounds__(kScanBlock) k_scan(ScanArgs A) {
   const int wave = threadIdx.x >> 6;
   const uint64_t lt = lanemask_lt();
   bool bad = false;
+  uint32_t my_btot = 0;  // BUCKET mode: offers of bucket threadIdx.x in this workgroup's segments
 
   // Raw loads of a segment: (src, dst, w, e) from the caller's arrays or the
   // record (a, b, w, e) of the previous round.  The next segment of this
@@ -399,6 +402,7 @@ __global__ void __launch_bounds__(kScanBlock) k_scan(ScanArgs A) {
     if (kMode == kModeBucket) {
       // exclusive scan of the (padded) bucket counts (nbk + 1 <= kScanBlock)
       const uint32_t cnt = (int)threadIdx.x < nbk ? bcnt[threadIdx.x] : 0u;
+      my_btot += cnt;
       const uint32_t v = nbk <= kOfferPadBuckets ? (cnt + kOfferAlign - 1) & ~(uint32_t)(kOfferAlign - 1) : cnt;
       uint32_t x = v;
       for (int off = 1; off < 64; off <<= 1) {
@@ -437,6 +441,7 @@ __global__ void __launch_bounds__(kScanBlock) k_scan(ScanArgs A) {
     __syncthreads();  // LDS (group counts, counters, staging) is reused by the next segment
   }
   if (!kCompact && bad) A.st->err = 1;
+  if (kMode == kModeBucket && my_btot) atomicAdd(A.btot + threadIdx.x, my_btot);
   if (kMode == kModeDense) {
     __syncthreads();
     if (use_slab(A.slab, A.slab_cap, npairs, gridDim.x)) {
@@ -505,54 +510,148 @@ __global__ void __launch_bounds__(kBlock) k_slab_min(int round, int launched, in
   }
 }
 
-// One workgroup per bucket p: the minimum offer for every component of the
-// bucket, over the run offT[p][s] (start, length) of every segment s, taken
-// in LDS and written to best[] (every entry of the bucket, "none" included).
-// Runs are short (about 2 * kSegCap / buckets offers), so each half-wave
-// reads kRunsInFlight runs at once, each with coalesced loads; the run bounds
-// of a chunk of segments are staged in LDS first.
+// Exclusive prefix sum of one value per thread over a 1024-thread block;
+// *total receives the sum.  `sh` holds kScanWaves words.
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* sh, uint32_t* total) {
+  uint32_t x = v;
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(x, off, 64);
+    if (lane_id() >= off) x += y;
+  }
+  const int wv = threadIdx.x >> 6;
+  if (lane_id() == 63) sh[wv] = x;
+  __syncthreads();
+  uint32_t base = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < kScanWaves; ++i) {
+    const uint32_t t = sh[i];
+    base += i < wv ? t : 0u;
+    tot += t;
+  }
+  __syncthreads();  // sh may be reused
+  *total = tot;
+  return base + x - v;
+}
+
+// The minimum offer of every component of a bucket, over the run
+// offT[p][s] (start, length) of the bucket in every segment s, taken in LDS.
+//
+// Work units: every bucket gets one workgroup, and a bucket with more than
+// twice the average number of offers (`btot`, counted by the scan: a hub of
+// a skewed graph) gets more, each taking an equal share of the segments;
+// the extra workgroups of a launch beyond the units return.  A bucket with
+// one unit writes its minima into best[] (reset to "none" for the round); a
+// bucket with several merges them with filtered atomics.
+//
+// Inside a workgroup the runs of a chunk of segments are cut into items of
+// at most kItemOffers offers (a run can be long when the edge order has
+// locality, e.g. a grid), and half-waves take kRunsInFlight items at a time,
+// each read with coalesced loads.
 static constexpr int kChunkRuns = 2048;
 static constexpr int kRunsInFlight = 8;
-static constexpr size_t kBucketMinExtraLds = kChunkRuns * sizeof(uint32_t);
+static constexpr uint32_t kItemOffers = 128;
+// LDS behind the minima table: run words, item prefix, unit prefix
+static constexpr size_t kBucketMinExtraLds = (2 * kChunkRuns + 1 + kMaxBuckets + 1) * sizeof(uint32_t);
+static_assert(kChunkRuns == 2 * kScanBlock, "two runs per thread in the item scan");
 
 __global__ void __launch_bounds__(kScanBlock) k_bucket_min(int round, int launched,
                                                            const unsigned long long* __restrict__ upd_key,
                                                            const uint16_t* __restrict__ upd_cl,
                                                            const uint32_t* __restrict__ offT, int32_t nseg,
+                                                           const uint32_t* __restrict__ btot,
                                                            unsigned long long* __restrict__ best,
                                                            const DevState* __restrict__ st) {
-  extern __shared__ unsigned long long table[];  // [B] minima, then the run bounds
+  extern __shared__ unsigned long long table[];  // [B] minima, then the staging below
+  __shared__ uint32_t sh[kScanWaves];
   const int32_t nr = st->n[round];
   if (nr <= 1 && round > 0) return;
   if (round > 0 && st->err) return;  // the scan of this round did nothing either
   if (pick_mode(nr, launched) != kModeBucket) return;
   int shift, nbk;
   bucket_geometry(nr, &shift, &nbk);
-  const int p = blockIdx.x;
-  if (p >= nbk) return;
   const int B = 1 << shift;
-  uint32_t* run_w = reinterpret_cast<uint32_t*>(table + B);  // run words of a chunk
-  for (int i = threadIdx.x; i < B; i += kScanBlock) table[i] = kKeyNone;
+  uint32_t* run_w = reinterpret_cast<uint32_t*>(table + B);  // [kChunkRuns]
+  uint32_t* iprefix = run_w + kChunkRuns;                    // [kChunkRuns + 1]
+  uint32_t* uprefix = iprefix + kChunkRuns + 1;              // [kMaxBuckets + 1]
+  const int tid = threadIdx.x;
+
+  // work units of every bucket (nbk <= kScanBlock - 1: one bucket per thread)
+  uint32_t all;
+  const uint32_t tot_p = tid < nbk ? btot[tid] : 0u;
+  (void)block_excl_scan(tot_p, sh, &all);
+  // target >= twice the average, so the extra units number at most nbk / 2
+  const uint64_t target = max((uint64_t)1, (2 * (uint64_t)all + (uint32_t)nbk - 1) / (uint32_t)nbk);
+  uint32_t units = tid < nbk ? 1u + (uint32_t)((uint64_t)tot_p / target) : 0u;
+  uint32_t total_units;
+  uint32_t ex = block_excl_scan(units, sh, &total_units);
+  if (total_units > gridDim.x) {  // never with the host's grid; one unit per bucket then
+    ex = (uint32_t)tid;
+    total_units = (uint32_t)nbk;
+  }
+  if (tid < nbk) uprefix[tid] = ex;
+  if (tid == 0) uprefix[nbk] = total_units;
+  __syncthreads();
+  const uint32_t b = blockIdx.x;
+  if (b >= total_units) return;
+  int lo = 0, hi = nbk;  // uprefix[lo] <= b < uprefix[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (uprefix[mid] <= b) lo = mid;
+    else hi = mid;
+  }
+  const int p = lo;
+  const uint32_t U = uprefix[p + 1] - uprefix[p], u = b - uprefix[p];
+  const int32_t s_begin = (int32_t)((int64_t)nseg * u / U), s_end = (int32_t)((int64_t)nseg * (u + 1) / U);
+
+  for (int i = tid; i < B; i += kScanBlock) table[i] = kKeyNone;
   const uint32_t* row = offT + (int64_t)p * nseg;
-  const int half = threadIdx.x >> 5;  // 0 .. 2 * kScanWaves - 1
-  const int hl = threadIdx.x & 31;
+  const int half = tid >> 5;  // 0 .. 2 * kScanWaves - 1
+  const int hl = tid & 31;
   constexpr int kHalves = 2 * kScanWaves;
-  for (int32_t c0 = 0; c0 < nseg; c0 += kChunkRuns) {
-    const int nrun = min(kChunkRuns, nseg - c0);
-    __syncthreads();  // table initialised / previous chunk's bounds consumed
-    for (int i = threadIdx.x; i < nrun; i += kScanBlock) run_w[i] = row[c0 + i];
-    __syncthreads();
-    for (int j0 = half * kRunsInFlight; j0 < nrun; j0 += kHalves * kRunsInFlight) {
-      uint32_t lo[kRunsInFlight], len[kRunsInFlight];
+  for (int32_t c0 = s_begin; c0 < s_end; c0 += kChunkRuns) {
+    const int nrun = min(kChunkRuns, s_end - c0);
+    __syncthreads();  // table initialised / previous chunk's staging consumed
+    // runs 2 tid and 2 tid + 1, and their item counts
+    const uint32_t w0 = 2 * tid < nrun ? row[c0 + 2 * tid] : 0u;
+    const uint32_t w1 = 2 * tid + 1 < nrun ? row[c0 + 2 * tid + 1] : 0u;
+    const uint32_t n0 = ((w0 >> 16) + kItemOffers - 1) / kItemOffers;
+    const uint32_t n1 = ((w1 >> 16) + kItemOffers - 1) / kItemOffers;
+    uint32_t nitems;
+    const uint32_t e0 = block_excl_scan(n0 + n1, sh, &nitems);
+    run_w[2 * tid] = w0;
+    run_w[2 * tid + 1] = w1;
+    iprefix[2 * tid] = e0;
+    iprefix[2 * tid + 1] = e0 + n0;
+    if (tid == 0) iprefix[nrun] = nitems;
+    // runs of at most one item (the common case) are taken directly, one per
+    // item slot, without the search for a long run's pieces
+    const bool short_runs = !__syncthreads_or(n0 > 1 || n1 > 1);
+    const uint32_t nslots = short_runs ? (uint32_t)nrun : nitems;
+    for (uint32_t i0 = half * kRunsInFlight; i0 < nslots; i0 += kHalves * kRunsInFlight) {
+      uint64_t at0[kRunsInFlight];
+      uint32_t len[kRunsInFlight];
       uint32_t maxlen = 0;
 #pragma unroll
       for (int q = 0; q < kRunsInFlight; ++q) {
-        lo[q] = 0;
+        at0[q] = 0;
         len[q] = 0;
-        if (j0 + q < nrun) {
-          const uint32_t wd = run_w[j0 + q];
-          lo[q] = wd & 0xFFFFu;
-          len[q] = wd >> 16;
+        const uint32_t it = i0 + q;
+        if (it < nslots) {
+          int rl = (int)it;  // short runs: item it is run it
+          uint32_t piece = 0;
+          if (!short_runs) {
+            int rh = nrun;  // iprefix[rl] <= it < iprefix[rh]
+            rl = 0;
+            while (rh - rl > 1) {
+              const int mid = (rl + rh) >> 1;
+              if (iprefix[mid] <= it) rl = mid;
+              else rh = mid;
+            }
+            piece = (it - iprefix[rl]) * kItemOffers;
+          }
+          const uint32_t wd = run_w[rl];
+          at0[q] = (uint64_t)(c0 + rl) * kOfferCap + (wd & 0xFFFFu) + piece;
+          len[q] = min(kItemOffers, (wd >> 16) - piece);
         }
         maxlen = max(maxlen, len[q]);
       }
@@ -564,9 +663,8 @@ __global__ void __launch_bounds__(kScanBlock) k_bucket_min(int round, int launch
           k[q] = kKeyNone;
           c[q] = 0;
           if (i < len[q]) {
-            const uint64_t at = (uint64_t)(c0 + j0 + q) * kOfferCap + lo[q] + i;
-            k[q] = ld_stream(upd_key + at);
-            c[q] = ld_stream(upd_cl + at);
+            k[q] = ld_stream(upd_key + at0[q] + i);
+            c[q] = ld_stream(upd_cl + at0[q] + i);
           }
         }
 #pragma unroll
@@ -578,8 +676,12 @@ __global__ void __launch_bounds__(kScanBlock) k_bucket_min(int round, int launch
   }
   __syncthreads();
   const int64_t base = (int64_t)p << shift;
-  for (int i = threadIdx.x; i < B; i += kScanBlock) {
-    if (base + i < nr) best[base + i] = table[i];
+  for (int i = tid; i < B; i += kScanBlock) {
+    const unsigned long long v = table[i];
+    if (base + i < nr && v != kKeyNone) {
+      if (U == 1) best[base + i] = v;
+      else lower_global(best, base + i, v);
+    }
   }
 }
 
@@ -987,7 +1089,7 @@ __global__ void __launch_bounds__(kBlock) k_relabel(int round, const int32_t* __
                                                     const unsigned long long* __restrict__ rootmask,
                                                     const int32_t* __restrict__ rootpre,
                                                     int32_t* __restrict__ labpool, int32_t* parent,
-                                                    unsigned long long* best,
+                                                    unsigned long long* best, uint32_t* __restrict__ btot,
                                                     const DevState* __restrict__ st) {
   const int32_t nr = st->n[round];
   if (nr <= 1 && round > 0) return;
@@ -1007,6 +1109,8 @@ __global__ void __launch_bounds__(kBlock) k_relabel(int round, const int32_t* __
     parent[c] = (int32_t)c;
     best[c] = kKeyNone;
   }
+  if (btot)
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < kMaxBuckets; i += stride) btot[i] = 0;
 }
 
 // ------------------------------------------------------------ launchers
@@ -1050,8 +1154,8 @@ hipError_t configure_kernels() {
 }
 
 hipError_t launch_init(int32_t n, unsigned long long* best, int32_t* parent, unsigned long long* pbest,
-                       DevState* st, int grid, hipStream_t s) {
-  k_init<<<grid, kBlock, 0, s>>>(n, best, parent, pbest, st);
+                       uint32_t* btot, DevState* st, int grid, hipStream_t s) {
+  k_init<<<grid, kBlock, 0, s>>>(n, best, parent, pbest, btot, st);
   MSTX_LAUNCH_CHECK();
   return hipSuccess;
 }
@@ -1080,9 +1184,9 @@ hipError_t launch_scan(int mode, int stage, const ScanArgs& a, int grid, size_t 
 }
 
 hipError_t launch_bucket_min(int round, int launched, const unsigned long long* upd_key, const uint16_t* upd_cl,
-                             const uint32_t* offT, int32_t nseg, unsigned long long* best, const DevState* st,
-                             int grid, size_t lds, hipStream_t s) {
-  k_bucket_min<<<grid, kScanBlock, lds + kBucketMinExtraLds, s>>>(round, launched, upd_key, upd_cl, offT, nseg,
+                             const uint32_t* offT, int32_t nseg, const uint32_t* btot, unsigned long long* best,
+                             const DevState* st, int grid, size_t lds, hipStream_t s) {
+  k_bucket_min<<<grid, kScanBlock, lds + kBucketMinExtraLds, s>>>(round, launched, upd_key, upd_cl, offT, nseg, btot,
                                                                   best, st);
   MSTX_LAUNCH_CHECK();
   return hipSuccess;
@@ -1135,8 +1239,8 @@ hipError_t launch_finalize(int round, const int32_t* rootcnt, int32_t* rootpre, 
 
 hipError_t launch_relabel(int round, const int32_t* root_of, const unsigned long long* rootmask,
                           const int32_t* rootpre, int32_t* labpool, int32_t* parent, unsigned long long* best,
-                          const DevState* st, int grid, hipStream_t s) {
-  k_relabel<<<grid, kBlock, 0, s>>>(round, root_of, rootmask, rootpre, labpool, parent, best, st);
+                          uint32_t* btot, const DevState* st, int grid, hipStream_t s) {
+  k_relabel<<<grid, kBlock, 0, s>>>(round, root_of, rootmask, rootpre, labpool, parent, best, btot, st);
   MSTX_LAUNCH_CHECK();
   return hipSuccess;
 }
