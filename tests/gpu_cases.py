@@ -83,6 +83,11 @@ def small_cases():
         ties_multigraph(5000, 9000, seed=28, wmax=1),  # every weight equal but the path
         G.rmat(14, 120_000, seed=29),
         G.planted_weights(G.tree_plus_extra(50_000, 400_000, seed=30)),
+        # more than 20000 vertices: offers sorted into buckets.  Skewed degrees put
+        # most offers into a few buckets (extra workgroups for them); a grid's
+        # row-major edge order gives long runs (cut into items)
+        G.rmat(16, 400_000, seed=33),
+        G.grid2d(256, 256, seed=34, name="grid_256x256"),
         _concat([(G.tree_plus_extra(700, 3000, seed=31), 0), (G.tree_plus_extra(500, 900, seed=32), 10_000),
                  (G.Graph(5, np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0, np.uint32)), 0)],
                 "disconnected_3parts_plus_isolated"),
