@@ -410,7 +410,7 @@ hipError_t enqueue_round(Solve& S, int r, int64_t bound, int64_t n_prev = 0) {
   if (err != hipSuccess) return err;
   const int gh = grid_for(std::max<int64_t>(bound, 1));
   int k = T.start(kHook, r, -1);
-  err = launch_hook(r, S.src, S.dst, S.rec, S.best, S.parent, S.st, S.in_mst, S.part_sel, S.part_w, gh, S.s);
+  err = launch_hook(r, S.rec, S.best, S.parent, S.st, S.in_mst, S.part_sel, S.part_w, gh, S.s);
   T.stop(k);
   if (err != hipSuccess) return err;
   k = T.start(kCompress, r, -1);

@@ -178,9 +178,8 @@ hipError_t launch_slab_min(int round, int launched, int mode, const unsigned lon
 hipError_t launch_dense_finish(int round, int launched, const unsigned long long* pbest, const uint32_t* seg_cnt,
                                int32_t nseg, const uint4* rec, uint8_t* in_mst, unsigned long long* total,
                                DevState* st, HostRound* host, hipStream_t s);
-hipError_t launch_hook(int round, const int32_t* src, const int32_t* dst, const uint4* rec,
-                       const unsigned long long* best, int32_t* parent, DevState* st, uint8_t* in_mst,
-                       uint32_t* part_sel, unsigned long long* part_w, int grid, hipStream_t s);
+hipError_t launch_hook(int round, const uint4* rec, const unsigned long long* best, int32_t* parent, DevState* st,
+                       uint8_t* in_mst, uint32_t* part_sel, unsigned long long* part_w, int grid, hipStream_t s);
 hipError_t launch_compress(int round, int32_t* parent, int32_t* root_of, const unsigned long long* best,
                            unsigned long long* rootmask, int32_t* rootcnt, const DevState* st, int grid,
                            hipStream_t s);

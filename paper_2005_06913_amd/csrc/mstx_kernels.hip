@@ -397,6 +397,17 @@ __global__ void __launch_bounds__(kScanBlock) k_scan(ScanArgs A) {
         if (live[k]) st_rec(r[k], A.rec + base + my_off[k]);
       }
     }
+    if (kFromInput && !kCompact && kMode != kModeDense) {
+      // round 0: src ^ dst of every edge, in the (still unused) record
+      // buffer, so the hook finds the other end of a vertex's edge with one
+      // 4-byte read
+      uint32_t* xends = reinterpret_cast<uint32_t*>(A.rec);
+#pragma unroll
+      for (int k = 0; k < kPerThread; ++k) {
+        const uint32_t j = k * kScanBlock + threadIdx.x;
+        if (j < count) st_stream(cx[k].x ^ cx[k].y, xends + base + j);
+      }
+    }
     if (threadIdx.x == 0) A.seg_cnt[s] = seg_tot;
 
     if (kMode == kModeBucket) {
@@ -859,8 +870,8 @@ __device__ __forceinline__ int32_t walk_root(int32_t* parent, int32_t x) {
 }
 
 // For each component c with a minimum key: the edge e and d = the other
-// end's component.  Round 0: the key holds e, and the ends are the caller's
-// vertex ids.  Later rounds: the key holds the edge's position in the record
+// end's component.  Round 0: the key holds e, and d = c ^ (src ^ dst of e),
+// which the round-0 scan stored in the record buffer.  Later rounds: the key holds the edge's position in the record
 // stream, whose record has this round's labels of both ends and e.  If c and
 // d chose each other only the smaller id acts, so every distinct selected
 // edge has one owner thread.  Then: repeat { x = root(c), y = root(d); CAS
@@ -868,9 +879,7 @@ __device__ __forceinline__ int32_t walk_root(int32_t* parent, int32_t x) {
 // the forest never gets a cycle.  When the CAS fails, the value it returns
 // (a fresh, strictly smaller ancestor) is where that side's walk resumes, so
 // stale loads cannot make the loop spin.
-__global__ void __launch_bounds__(kBlock) k_hook(int round, const int32_t* __restrict__ src,
-                                                 const int32_t* __restrict__ dst,
-                                                 const uint4* __restrict__ rec,
+__global__ void __launch_bounds__(kBlock) k_hook(int round, const uint4* __restrict__ rec,
                                                  const unsigned long long* __restrict__ best,
                                                  int32_t* parent, DevState* __restrict__ st,
                                                  uint8_t* __restrict__ in_mst, uint32_t* __restrict__ part_sel,
@@ -889,17 +898,20 @@ __global__ void __launch_bounds__(kBlock) k_hook(int round, const int32_t* __res
     if (key == kKeyNone) continue;
     int32_t u, v;
     uint32_t e;
+    int32_t d;
     if (round == 0) {
+      // the round-0 scan stored src ^ dst of every edge in the record buffer
       e = (uint32_t)key;
-      u = src[e];
-      v = dst[e];
+      d = (int32_t)(reinterpret_cast<const uint32_t*>(rec)[e] ^ (uint32_t)c);
+      u = c;
+      v = d;
     } else {
       const uint4 x = ld_rec(rec + (uint32_t)key);
       u = (int32_t)x.x;
       v = (int32_t)x.y;
       e = x.w;
+      d = (u == c) ? v : u;
     }
-    const int32_t d = (u == c) ? v : u;
     if ((uint32_t)d >= (uint32_t)nr || (u != c && v != c)) {
       st->err_internal = 1;  // inconsistent labels: never expected, reported as a device error
       continue;
@@ -1211,10 +1223,9 @@ hipError_t launch_dense_finish(int round, int launched, const unsigned long long
   return hipSuccess;
 }
 
-hipError_t launch_hook(int round, const int32_t* src, const int32_t* dst, const uint4* rec,
-                       const unsigned long long* best, int32_t* parent, DevState* st, uint8_t* in_mst,
-                       uint32_t* part_sel, unsigned long long* part_w, int grid, hipStream_t s) {
-  k_hook<<<grid, kBlock, 0, s>>>(round, src, dst, rec, best, parent, st, in_mst, part_sel, part_w);
+hipError_t launch_hook(int round, const uint4* rec, const unsigned long long* best, int32_t* parent, DevState* st,
+                       uint8_t* in_mst, uint32_t* part_sel, unsigned long long* part_w, int grid, hipStream_t s) {
+  k_hook<<<grid, kBlock, 0, s>>>(round, rec, best, parent, st, in_mst, part_sel, part_w);
   MSTX_LAUNCH_CHECK();
   return hipSuccess;
 }
