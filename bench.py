@@ -551,10 +551,12 @@ def main() -> int:
     if dk["alg_bytes_per_launch"] > 0:  # mean bytes per launch / mean duration per launch
         achieved = dk["alg_bytes_per_launch"] / (dk["ms_per_launch"] * 1e-3) / 1e9
         bound_kernel = dom
-    else:  # dominant kernel has no byte model (not a scan): report the scan family
+    elif scan_kinds:  # dominant kernel has no byte model (not a scan): report the scan family
         sk = max(scan_kinds, key=lambda k: kernels[k]["ms_total"])
         achieved = kernels[sk]["alg_bytes_per_launch"] / (kernels[sk]["ms_per_launch"] * 1e-3) / 1e9
         bound_kernel = sk
+    else:
+        achieved, bound_kernel = 0.0, dom
     scan_ms = sum(kernels[k]["ms_total"] for k in step_kinds)
     scan_bytes = sum(prof[k][2] for k in scan_kinds)
 

@@ -187,6 +187,18 @@ int mst_workspace_release(void* stream);
  */
 int32_t mst_set_dense_limit(int32_t limit);
 
+/*
+ * Small graphs (Section 2.1's rounds, one launch): mst_solve solves a graph
+ * with at most `limit` vertices and at most 131072 edges with a single
+ * workgroup that keeps every vertex's state in LDS and runs all rounds behind
+ * workgroup barriers, instead of one kernel chain per round (the path
+ * mst_solve_batched uses for its small graphs).  The tree and the round
+ * statistics are the same (no dense finish on this path).  limit is clamped
+ * to [0, 8192] (0: off; the default is 8192); limit < 0 only queries.
+ * Returns the previous limit.  Process-wide; read at the start of each call.
+ */
+int32_t mst_set_small_limit(int32_t limit);
+
 /* Static description of a status code. */
 const char* mst_status_string(int status);
 

@@ -21,12 +21,14 @@ from .binding import (  # noqa: F401
     Solution,
     dense_limit,
     load_library,
+    small_limit,
     mst_batched_workspace_bytes,
     mst_last_round_stats,
     mst_profile_enable,
     mst_profile_read,
     mst_select_min_edges,
     mst_set_dense_limit,
+    mst_set_small_limit,
     mst_solve,
     mst_solve_batched,
     mst_status_string,

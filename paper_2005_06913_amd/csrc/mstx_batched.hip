@@ -51,15 +51,23 @@ __device__ __forceinline__ int32_t small_root(int32_t* par, int32_t x) {
 // of the larger root under the smaller, compression; the loop ends when a
 // round selects no edge.  Writes in_mst for the graph's edges (zeroed by the
 // caller), total[g] and status[g].
+//
+// With glist == nullptr the launch is one workgroup for the single graph
+// (n_single, m_single), and `stats` (when not null) receives the round
+// statistics in the single-graph form: stats[0] = rows, then per row
+// (components entering the round, isolated ones dropped; edges between
+// different components; edges added).
 __global__ void __launch_bounds__(kSmallBlock) k_small_solve(const int32_t* __restrict__ glist,
                                                              const int64_t* __restrict__ voff,
                                                              const int64_t* __restrict__ eoff,
+                                                             int32_t n_single, int64_t m_single,
                                                              const int32_t* __restrict__ src,
                                                              const int32_t* __restrict__ dst,
                                                              const uint32_t* __restrict__ w,
                                                              uint8_t* __restrict__ in_mst,
                                                              unsigned long long* __restrict__ total_out,
-                                                             int32_t* __restrict__ status_out) {
+                                                             int32_t* __restrict__ status_out,
+                                                             int64_t* __restrict__ stats) {
   extern __shared__ unsigned long long sbest[];  // [kSmallN]
   int32_t* comp = reinterpret_cast<int32_t*>(sbest + kSmallN);
   int32_t* par = comp + kSmallN;
@@ -67,12 +75,15 @@ __global__ void __launch_bounds__(kSmallBlock) k_small_solve(const int32_t* __re
   __shared__ uint32_t bad;
   __shared__ unsigned long long red_w[kSmallBlock / 64];
   __shared__ uint32_t red_c[kSmallBlock / 64];
+  __shared__ uint32_t round_live, round_nonisolated;
 
-  const int g = glist[blockIdx.x];
-  const int64_t e0 = eoff[g];
-  const int64_t m = eoff[g + 1] - e0;
-  const int32_t n = (int32_t)(voff[g + 1] - voff[g]);
+  const int g = glist ? glist[blockIdx.x] : 0;
+  const int64_t e0 = glist ? eoff[g] : 0;
+  const int64_t m = glist ? eoff[g + 1] - e0 : m_single;
+  const int32_t n = glist ? (int32_t)(voff[g + 1] - voff[g]) : n_single;
   const int tid = threadIdx.x;
+  int64_t n_round = n;  // components entering the round (statistics)
+  int rows = 0;
 
   for (int32_t v = tid; v < n; v += kSmallBlock) comp[v] = v;
   if (tid == 0) bad = 0;
@@ -85,9 +96,14 @@ __global__ void __launch_bounds__(kSmallBlock) k_small_solve(const int32_t* __re
       sbest[v] = kKeyNone;
       par[v] = v;
     }
-    if (tid == 0) round_sel = 0;
+    if (tid == 0) {
+      round_sel = 0;
+      round_live = 0;
+      round_nonisolated = 0;
+    }
     __syncthreads();
     // edge scan: lightest outgoing key per component root
+    uint32_t live = 0;
     for (int64_t j = tid; j < m; j += kSmallBlock) {
       const int32_t a0 = src[e0 + j], b0 = dst[e0 + j];
       if ((uint32_t)a0 >= (uint32_t)n || (uint32_t)b0 >= (uint32_t)n) {
@@ -96,17 +112,20 @@ __global__ void __launch_bounds__(kSmallBlock) k_small_solve(const int32_t* __re
       }
       const int32_t a = comp[a0], b = comp[b0];
       if (a == b) continue;
+      ++live;
       const unsigned long long key = ((unsigned long long)w[e0 + j] << 32) | (unsigned long long)j;
       if (key < sbest[a]) atomicMin(sbest + a, key);
       if (key < sbest[b]) atomicMin(sbest + b, key);
     }
+    if (stats && live) atomicAdd(&round_live, live);
     __syncthreads();
     // hooking: every root with a minimum unites with the other end's root
-    uint32_t sel = 0;
+    uint32_t sel = 0, nonisolated = 0;
     for (int32_t c = tid; c < n; c += kSmallBlock) {
       if (comp[c] != c) continue;
       const unsigned long long key = sbest[c];
       if (key == kKeyNone) continue;
+      ++nonisolated;
       const int64_t j = (int64_t)(uint32_t)key;
       const int32_t u = comp[src[e0 + j]], v = comp[dst[e0 + j]];
       const int32_t d = (u == c) ? v : u;
@@ -130,8 +149,18 @@ __global__ void __launch_bounds__(kSmallBlock) k_small_solve(const int32_t* __re
       }
     }
     if (sel) atomicAdd(&round_sel, sel);
+    if (stats && nonisolated) atomicAdd(&round_nonisolated, nonisolated);
     my_cnt += sel;
     __syncthreads();
+    if (stats && tid == 0 && (round == 0 || n_round > 1) && !bad) {
+      // a row for every round the single-graph path would run
+      stats[1 + 3 * rows + 0] = n_round;
+      stats[1 + 3 * rows + 1] = round_live;
+      stats[1 + 3 * rows + 2] = round_sel;
+    }
+    if (round == 0 || n_round > 1) ++rows;
+    // isolated components (no outgoing edge) leave; each added edge merges two
+    n_round = (int64_t)round_nonisolated - (int64_t)round_sel;
     if (round_sel == 0) break;
     // compression: the final root of every root of this round goes to a buffer
     // of its own (the minima are no longer needed), so a concurrent halving
@@ -165,6 +194,7 @@ __global__ void __launch_bounds__(kSmallBlock) k_small_solve(const int32_t* __re
     int32_t st = (n <= 1 || (int64_t)tc == (int64_t)n - 1) ? MSTX_OK : MSTX_DISCONNECTED;
     if (bad) st = MSTX_ERR_VERTEX_RANGE;
     status_out[g] = st;
+    if (stats) stats[0] = rows;
   }
 }
 
@@ -276,7 +306,16 @@ hipError_t launch_small_solve(const int32_t* glist, int num, const int64_t* voff
                               const int32_t* src, const int32_t* dst, const uint32_t* w, uint8_t* in_mst,
                               unsigned long long* total, int32_t* status, hipStream_t s) {
   if (num <= 0) return hipSuccess;
-  k_small_solve<<<num, kSmallBlock, kSmallSolveLds, s>>>(glist, voff, eoff, src, dst, w, in_mst, total, status);
+  k_small_solve<<<num, kSmallBlock, kSmallSolveLds, s>>>(glist, voff, eoff, 0, 0, src, dst, w, in_mst, total,
+                                                          status, nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_small_solve_single(int32_t n, int64_t m, const int32_t* src, const int32_t* dst,
+                                     const uint32_t* w, uint8_t* in_mst, unsigned long long* total,
+                                     int32_t* status, int64_t* stats, hipStream_t s) {
+  k_small_solve<<<1, kSmallBlock, kSmallSolveLds, s>>>(nullptr, nullptr, nullptr, n, m, src, dst, w, in_mst, total,
+                                                        status, stats);
   return hipGetLastError();
 }
 

@@ -94,6 +94,8 @@ struct DeviceCache {
   bool configured = false;
   void* aux = nullptr;  // batched-call scratch
   size_t aux_bytes = 0;
+  void* small_dev = nullptr;       // single small graph: status + round statistics
+  int64_t* small_host = nullptr;   // pinned copy of the same
 };
 
 // One cache per (device, stream): calls on different streams have their own
@@ -103,6 +105,9 @@ std::mutex g_caches_mu;
 // Largest component count the dense finish takes (0: every round is a plain
 // Boruvka round); mst_set_dense_limit() changes it.
 std::atomic<int> g_dense_limit{kDenseMax};
+// Largest vertex count for which mst_solve takes the one-workgroup path
+// (0: never); mst_set_small_limit() changes it.
+std::atomic<int> g_small_limit{kSmallN};
 std::map<std::pair<int, hipStream_t>, std::unique_ptr<DeviceCache>> g_caches;
 
 thread_local std::vector<int64_t> t_last_stats;
@@ -197,7 +202,7 @@ enum Kind {
   kScan0Global = 0, kScan0Lds, kScan0Bucket, kScan0Dense,
   kScan1Global, kScan1Lds, kScan1Bucket, kScan1Dense,
   kScanRGlobal, kScanRLds, kScanRBucket, kScanRDense,
-  kBucketMin, kSlabMin_, kDenseFinish, kHook, kCompress, kFinalize, kRelabel, kKinds
+  kBucketMin, kSlabMin_, kDenseFinish, kHook, kCompress, kFinalize, kRelabel, kSmallSolve, kKinds
 };
 // Names as rocprofv3 reports the kernels (template arguments: minima mode
 // 0 global / 1 LDS / 2 bucket / 3 dense, reads the caller's arrays, compacts).
@@ -206,7 +211,7 @@ const char* const kKindNames[kKinds] = {
     "k_scan<0, true, true>",   "k_scan<1, true, true>",   "k_scan<2, true, true>",   "k_scan<3, true, true>",
     "k_scan<0, false, true>",  "k_scan<1, false, true>",  "k_scan<2, false, true>",  "k_scan<3, false, true>",
     "k_bucket_min",            "k_slab_min",              "k_dense_finish",          "k_hook",
-    "k_compress",              "k_finalize",              "k_relabel"};
+    "k_compress",              "k_finalize",              "k_relabel",               "k_small_solve"};
 
 int scan_kind(int stage, int mode) { return kNumModes * stage + mode; }
 
@@ -533,6 +538,44 @@ int solve_locked(DeviceCache* dc, const Layout& L, int32_t n, int64_t m, const i
   return status;
 }
 
+// A graph of at most kSmallN vertices in one launch (the batched path's
+// one-workgroup solve); the cache is locked by the caller.
+int solve_small_locked(DeviceCache* dc, int32_t n, int64_t m, const int32_t* src, const int32_t* dst,
+                       const uint32_t* w, uint8_t* in_mst, uint64_t* total, hipStream_t s) {
+  const size_t words = 1 + kSmallStatsWords;  // status word, then the statistics
+  if (!dc->small_dev) {
+    if (hipMalloc(&dc->small_dev, 8 * words) != hipSuccess) {
+      (void)hipGetLastError();
+      dc->small_dev = nullptr;
+      return MSTX_ERR_OUT_OF_MEMORY;
+    }
+    HIP_OK(hipHostMalloc((void**)&dc->small_host, 8 * words, hipHostMallocDefault));
+  }
+  int64_t* dev = static_cast<int64_t*>(dc->small_dev);
+  LaunchTimer& T = t_timer;
+  T.begin(s);
+  HIP_OK(hipMemsetAsync(in_mst, 0, (size_t)m, s));
+  const int k = T.start(kSmallSolve, 0, -1);
+  HIP_OK(launch_small_solve_single(n, m, src, dst, w, in_mst, reinterpret_cast<unsigned long long*>(total),
+                                   reinterpret_cast<int32_t*>(dev), dev + 1, s));
+  T.stop(k);
+  HIP_OK(hipMemcpyAsync(dc->small_host, dev, 8 * words, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  const int32_t status = *reinterpret_cast<const int32_t*>(dc->small_host);
+  const int64_t* st = dc->small_host + 1;
+  const int rows = (int)std::min<int64_t>(std::max<int64_t>(st[0], 0), kMaxRounds + 1);
+  // algorithmic bytes: every round reads the 12-byte edges once, plus one
+  // final round that finds nothing to add
+  T.commit(0, {}, {});
+  if (T.on) {
+    std::lock_guard<std::mutex> g(g_prof.mu);
+    g_prof.bytes[kSmallSolve] += 12.0 * (double)m * (double)(rows + 1);
+  }
+  if (status < 0) return status;
+  t_last_stats.assign(st + 1, st + 1 + 3 * rows);
+  return status;
+}
+
 int solve(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, const uint32_t* w, uint8_t* in_mst,
           uint64_t* total, hipStream_t s) {
   t_last_stats.clear();
@@ -546,6 +589,12 @@ int solve(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, const ui
   if (n == 0) return MSTX_ERR_VERTEX_RANGE;  // m > 0 edges, no valid vertex id
   DeviceCache* dc = nullptr;
   std::unique_lock<std::mutex> lock;
+  if (n <= g_small_limit.load() && m <= kSmallMaxEdges) {
+    // one workgroup runs every round with the vertex state in LDS
+    int rc = acquire(dc, lock, 0, s);
+    if (rc != MSTX_OK) return rc;
+    return solve_small_locked(dc, n, m, src, dst, w, in_mst, total, s);
+  }
   int rc = acquire(dc, lock, L.bytes, s);
   if (rc != MSTX_OK) return rc;
   return solve_locked(dc, L, n, m, src, dst, w, in_mst, total, s);
@@ -875,6 +924,8 @@ int mst_workspace_release(void* stream) {
   if (victim->base && hipFree(victim->base) != hipSuccess) return MSTX_ERR_DEVICE;
   if (victim->aux && hipFree(victim->aux) != hipSuccess) return MSTX_ERR_DEVICE;
   if (victim->host_rounds && hipHostFree(victim->host_rounds) != hipSuccess) return MSTX_ERR_DEVICE;
+  if (victim->small_dev && hipFree(victim->small_dev) != hipSuccess) return MSTX_ERR_DEVICE;
+  if (victim->small_host && hipHostFree(victim->small_host) != hipSuccess) return MSTX_ERR_DEVICE;
   for (auto& e : victim->round_ev)
     if (e) (void)hipEventDestroy(e);
   return MSTX_OK;
@@ -883,6 +934,11 @@ int mst_workspace_release(void* stream) {
 size_t mst_workspace_bytes(int32_t n, int64_t m) {
   if (n < 0 || m < 0 || m > (int64_t)0xFFFFFFFFLL) return 0;
   return mstx::plan(n, m).bytes;
+}
+
+int32_t mst_set_small_limit(int32_t limit) {
+  if (limit < 0) return mstx::g_small_limit.load();
+  return mstx::g_small_limit.exchange(std::min<int32_t>(limit, mstx::kSmallN));
 }
 
 int32_t mst_set_dense_limit(int32_t limit) {

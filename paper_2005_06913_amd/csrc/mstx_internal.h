@@ -149,6 +149,11 @@ __host__ __device__ inline bool use_slab(const unsigned long long* slab, int64_t
 // Batched solve: graphs with at most kSmallN vertices are solved by one
 // workgroup each with the vertex state in LDS (best u64 + comp + parents).
 static constexpr int32_t kSmallN = 8192;
+// A single graph (mst_solve) with at most the small-graph limit of vertices
+// (kSmallN by default, see mst_set_small_limit) and at most kSmallMaxEdges
+// edges is solved the same way: one launch instead of a chain per round.
+static constexpr int64_t kSmallMaxEdges = 1 << 17;
+static constexpr int kSmallStatsWords = 1 + 3 * (kMaxRounds + 1);
 static constexpr int kSmallSolveLds = kSmallN * (8 + 4 + 4);
 
 hipError_t configure_kernels();
@@ -156,6 +161,9 @@ hipError_t configure_batched_kernels();
 hipError_t launch_small_solve(const int32_t* glist, int num, const int64_t* voff, const int64_t* eoff,
                               const int32_t* src, const int32_t* dst, const uint32_t* w, uint8_t* in_mst,
                               unsigned long long* total, int32_t* status, hipStream_t s);
+hipError_t launch_small_solve_single(int32_t n, int64_t m, const int32_t* src, const int32_t* dst,
+                                     const uint32_t* w, uint8_t* in_mst, unsigned long long* total,
+                                     int32_t* status, int64_t* stats, hipStream_t s);
 hipError_t launch_gather(const int32_t* glist, int ng, const int64_t* voff, const int64_t* eoff,
                          const int64_t* cvert, const int64_t* cedge, int64_t chunk_edges, const int32_t* src,
                          const int32_t* dst, const uint32_t* w, int32_t* gsrc, int32_t* gdst, uint32_t* gw,

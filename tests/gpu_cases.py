@@ -25,6 +25,7 @@ def _concat(parts, name):
 
 
 DENSE_MAX = 198  # largest component count the library's dense finish takes
+SMALL_MAX = 8192  # largest vertex count of the library's one-workgroup path
 
 
 def stats_consistent(gpu_stats, oracle_stats, limit=DENSE_MAX):

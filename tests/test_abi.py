@@ -34,7 +34,7 @@ def lib():
 def test_header_declares_entry_points():
     names = declared_functions()
     for must in ("mst_solve", "mst_solve_batched", "mst_select_min_edges", "mst_workspace_bytes",
-                 "mst_set_dense_limit", "mst_status_string"):
+                 "mst_set_dense_limit", "mst_set_small_limit", "mst_status_string"):
         assert must in names, names
 
 
@@ -89,6 +89,20 @@ def test_dense_limit_option(lib):
         assert B.mst_set_dense_limit(-1) == 0
     finally:
         B.mst_set_dense_limit(prev)
+
+
+def test_small_limit_option(lib):
+    from paper_2005_06913_amd import binding as B
+    prev = B.mst_set_small_limit(-1)
+    assert prev == gpu_cases.SMALL_MAX
+    try:
+        assert B.mst_set_small_limit(100000) == prev
+        assert B.mst_set_small_limit(-1) == gpu_cases.SMALL_MAX  # clamped
+        with B.small_limit(0):
+            assert B.mst_set_small_limit(-1) == 0
+        assert B.mst_set_small_limit(-1) == gpu_cases.SMALL_MAX
+    finally:
+        B.mst_set_small_limit(prev)
 
 
 def test_workspace_bytes(lib):

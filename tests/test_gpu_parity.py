@@ -39,22 +39,23 @@ def to_dev(dev, src, dst, w):
             torch.from_numpy(np.ascontiguousarray(w, np.uint32)).to(dev))
 
 
-def gpu_solve(dev, n, src, dst, w, limit=gpu_cases.DENSE_MAX):
+def gpu_solve(dev, n, src, dst, w, limit=gpu_cases.DENSE_MAX, small=gpu_cases.SMALL_MAX):
     import paper_2005_06913_amd as P
     s, d, ww = to_dev(dev, src, dst, w)
     m = len(src)
     in_mst = torch.full((m,), 7, dtype=torch.uint8, device=dev)  # garbage: must be overwritten
     total = torch.full((1,), 12345, dtype=torch.int64, device=dev).view(torch.uint64)
-    with P.dense_limit(limit):
+    with P.dense_limit(limit), P.small_limit(small):
         st = P.mst_solve(n, s, d, ww, in_mst, total)
     torch.cuda.synchronize()
     stats = P.mst_last_round_stats()
     return st, in_mst.cpu().numpy(), int(total.view(torch.int64).cpu().item()), stats
 
 
-def check_against_oracle(dev, name, n, src, dst, w, stats=True, limit=gpu_cases.DENSE_MAX):
-    print(f"[case] {name} n={n} m={len(src)} dense_limit={limit}", flush=True)
-    st, in_mst, total, gstats = gpu_solve(dev, n, src, dst, w, limit)
+def check_against_oracle(dev, name, n, src, dst, w, stats=True, limit=gpu_cases.DENSE_MAX,
+                         small=gpu_cases.SMALL_MAX):
+    print(f"[case] {name} n={n} m={len(src)} dense_limit={limit} small_limit={small}", flush=True)
+    st, in_mst, total, gstats = gpu_solve(dev, n, src, dst, w, limit, small)
     k = oracle.kruskal(n, src, dst, w)
     assert st == k.status, f"{name}: status {st} != oracle {k.status}"
     assert total == k.total, f"{name}: total {total} != oracle {k.total}"
@@ -99,31 +100,50 @@ def test_min_edge_keys_golden(dev):
 
 # ------------------------------------------------------------- full solve
 
-@pytest.mark.parametrize("limit", [gpu_cases.DENSE_MAX, 0, 2, 9, 64])
+# (dense-finish limit, small-graph limit): the defaults (graphs of at most
+# 8192 vertices take the one-workgroup path), and the per-round kernel chain
+# with the dense finish at its default, off, and starting earlier or later
+PATHS = [(gpu_cases.DENSE_MAX, gpu_cases.SMALL_MAX), (gpu_cases.DENSE_MAX, 0), (0, 0), (2, 0), (9, 0), (64, 0)]
+
+
+@pytest.mark.parametrize("limit,small", PATHS, ids=[f"dense{a}-small{b}" for a, b in PATHS])
 @pytest.mark.parametrize("idx", range(len(gpu_cases.small_cases())))
-def test_solve_small(dev, idx, limit):
+def test_solve_small(dev, idx, limit, small):
     g = gpu_cases.small_cases()[idx]
-    check_against_oracle(dev, g.name, g.n, g.src, g.dst, g.w, limit=limit)
+    check_against_oracle(dev, g.name, g.n, g.src, g.dst, g.w, limit=limit, small=small)
 
 
 def test_dense_finish_ends_early(dev):
     """The dense finish replaces the oracle's last rounds (n=1000, m=8000: a
     few hundred components after round 0, a few dozen after round 1)."""
     g = gpu_cases.small_cases()[0]
-    gstats = check_against_oracle(dev, g.name, g.n, g.src, g.dst, g.w)
+    gstats = check_against_oracle(dev, g.name, g.n, g.src, g.dst, g.w, small=0)
     b = oracle.boruvka(g.n, g.src, g.dst, g.w)
     assert len(gstats) < len(b.stats), (gstats, b.stats)
     # a graph of at most 198 vertices is solved by the dense finish in round 0
     k64 = gpu_cases.small_cases()[7]
     assert k64.n == 64
-    gstats = check_against_oracle(dev, k64.name, k64.n, k64.src, k64.dst, k64.w)
+    gstats = check_against_oracle(dev, k64.name, k64.n, k64.src, k64.dst, k64.w, small=0)
     assert len(gstats) == 1 and gstats[0][2] == 63
 
 
-@pytest.mark.parametrize("limit", [gpu_cases.DENSE_MAX, 0])
-def test_solve_golden(dev, limit):
+def test_small_path_matches_chain(dev):
+    """The one-workgroup path and the per-round chain give the same bytes and the
+    oracle's round statistics exactly (the small path has no dense finish)."""
+    for g in gpu_cases.small_cases():
+        if g.n > gpu_cases.SMALL_MAX or len(g.src) > (1 << 17):
+            continue
+        a = gpu_solve(dev, g.n, g.src, g.dst, g.w, small=gpu_cases.SMALL_MAX)
+        c = gpu_solve(dev, g.n, g.src, g.dst, g.w, limit=0, small=0)
+        assert a[0] == c[0] and a[2] == c[2] and np.array_equal(a[1], c[1]), g.name
+        if a[0] == 0:
+            assert np.array_equal(a[3], oracle.boruvka(g.n, g.src, g.dst, g.w).stats), g.name
+
+
+@pytest.mark.parametrize("limit,small", [(gpu_cases.DENSE_MAX, gpu_cases.SMALL_MAX), (gpu_cases.DENSE_MAX, 0), (0, 0)])
+def test_solve_golden(dev, limit, small):
     for fx in mst_pins.all_fixtures():
-        st, in_mst, total, stats = gpu_solve(dev, fx.n, fx.src, fx.dst, fx.w, limit)
+        st, in_mst, total, stats = gpu_solve(dev, fx.n, fx.src, fx.dst, fx.w, limit, small)
         assert st == fx.status, fx.name
         assert total == fx.total, fx.name
         assert np.array_equal(in_mst, fx.in_mst), fx.name
@@ -133,11 +153,11 @@ def test_solve_golden(dev, limit):
                 assert [tuple(r) for r in stats.tolist()] == fx.rounds, fx.name
 
 
-@pytest.mark.parametrize("limit", [gpu_cases.DENSE_MAX, 0])
+@pytest.mark.parametrize("limit,small", [(gpu_cases.DENSE_MAX, gpu_cases.SMALL_MAX), (gpu_cases.DENSE_MAX, 0), (0, 0)])
 @pytest.mark.parametrize("case", gpu_cases.edge_cases(), ids=[c[0] for c in gpu_cases.edge_cases()])
-def test_solve_edge_cases(dev, case, limit):
+def test_solve_edge_cases(dev, case, limit, small):
     name, n, src, dst, w = case
-    check_against_oracle(dev, name, n, src, dst, w, stats=False, limit=limit)
+    check_against_oracle(dev, name, n, src, dst, w, stats=False, limit=limit, small=small)
 
 
 def test_vertex_range_error(dev):
@@ -146,8 +166,9 @@ def test_vertex_range_error(dev):
         src = np.array([0, 1, bad_src], np.int32)
         dst = np.array([1, 2, 0], np.int32)
         w = np.array([1, 2, 3], np.uint32)
-        st, _, _, _ = gpu_solve(dev, 5, src, dst, w)
-        assert st == P.MSTX_ERR_VERTEX_RANGE
+        for small in (gpu_cases.SMALL_MAX, 0):
+            st, _, _, _ = gpu_solve(dev, 5, src, dst, w, small=small)
+            assert st == P.MSTX_ERR_VERTEX_RANGE
         s, d, ww = to_dev(dev, src, dst, w)
         out = torch.zeros(5, dtype=torch.int64, device=dev).view(torch.uint64)
         assert P.mst_select_min_edges(5, s, d, ww, out) == P.MSTX_ERR_VERTEX_RANGE
