@@ -18,6 +18,8 @@
 // the graph as in the single-graph solve.
 
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 #include <stdint.h>
 
 #include "mstx.h"
@@ -248,30 +250,32 @@ __global__ void __launch_bounds__(256) k_gather(const int32_t* __restrict__ glis
   }
 }
 
-// One workgroup per chunk graph k: copies the union's flags back to the
-// caller's in_mst range of graph glist[k], sums the weight and count of the
-// marked edges, and sets total[g], status[g].
-__global__ void __launch_bounds__(256) k_graph_epilogue(const int32_t* __restrict__ glist,
-                                                        const int64_t* __restrict__ voff,
+// Chunk graph k, slice y of `slice` edges (a 2-D grid: large graphs get many
+// workgroups): copies the union's flags back to the caller's in_mst
+// range of graph glist[k] and adds the weight and count of the marked edges
+// of the slice to acc_w[k], acc_c[k] (zeroed by the caller; one atomic per
+// workgroup).
+static constexpr int64_t kEpilogueSlice = 16384;  // edges per workgroup (at least)
+__global__ void __launch_bounds__(256) k_graph_epilogue(const int32_t* __restrict__ glist, int64_t slice,
                                                         const int64_t* __restrict__ eoff,
                                                         const int64_t* __restrict__ cedge,
                                                         const uint8_t* __restrict__ cin_mst,
                                                         const uint32_t* __restrict__ gw,
-                                                        const int32_t* __restrict__ gbad,
                                                         uint8_t* __restrict__ in_mst,
-                                                        unsigned long long* __restrict__ total_out,
-                                                        int32_t* __restrict__ status_out) {
+                                                        unsigned long long* __restrict__ acc_w,
+                                                        uint32_t* __restrict__ acc_c) {
   __shared__ unsigned long long rw[4];
   __shared__ uint32_t rc[4];
   const int k = blockIdx.x;
-  const int g = glist[k];
-  const int64_t p0 = cedge[k], p1 = cedge[k + 1];
-  const int64_t j0 = eoff[g];
+  const int64_t p_first = cedge[k] + (int64_t)blockIdx.y * slice;
+  const int64_t p_end = min(cedge[k + 1], p_first + slice);
+  if (p_first >= p_end) return;  // uniform: the graph has fewer slices
+  const int64_t to = eoff[glist[k]] - cedge[k];  // caller index = chunk index + to
   unsigned long long sw = 0;
   uint32_t cnt = 0;
-  for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+  for (int64_t p = p_first + threadIdx.x; p < p_end; p += blockDim.x) {
     const uint8_t f = cin_mst[p];
-    in_mst[j0 + (p - p0)] = f;
+    in_mst[p + to] = f;
     if (f) {
       sw += gw[p];
       ++cnt;
@@ -287,14 +291,29 @@ __global__ void __launch_bounds__(256) k_graph_epilogue(const int32_t* __restric
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    unsigned long long tw = rw[0] + rw[1] + rw[2] + rw[3];
+    const unsigned long long tw = rw[0] + rw[1] + rw[2] + rw[3];
     const uint32_t tc = rc[0] + rc[1] + rc[2] + rc[3];
-    const int64_t n = voff[g + 1] - voff[g];
-    total_out[g] = tw;
-    int32_t st = (n <= 1 || (int64_t)tc == n - 1) ? MSTX_OK : MSTX_DISCONNECTED;
-    if (gbad[k]) st = MSTX_ERR_VERTEX_RANGE;
-    status_out[g] = st;
+    if (tw) atomicAdd(acc_w + k, tw);
+    if (tc) atomicAdd(acc_c + k, tc);
   }
+}
+
+// Per chunk graph: total[g] and status[g] from the accumulated sums.
+__global__ void __launch_bounds__(256) k_graph_status(const int32_t* __restrict__ glist, int ng,
+                                                      const int64_t* __restrict__ voff,
+                                                      const unsigned long long* __restrict__ acc_w,
+                                                      const uint32_t* __restrict__ acc_c,
+                                                      const int32_t* __restrict__ gbad,
+                                                      unsigned long long* __restrict__ total_out,
+                                                      int32_t* __restrict__ status_out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= ng) return;
+  const int g = glist[k];
+  const int64_t n = voff[g + 1] - voff[g];
+  total_out[g] = acc_w[k];
+  int32_t st = (n <= 1 || (int64_t)acc_c[k] == n - 1) ? MSTX_OK : MSTX_DISCONNECTED;
+  if (gbad[k]) st = MSTX_ERR_VERTEX_RANGE;
+  status_out[g] = st;
 }
 
 hipError_t configure_batched_kernels() {
@@ -331,11 +350,22 @@ hipError_t launch_gather(const int32_t* glist, int ng, const int64_t* voff, cons
 }
 
 hipError_t launch_graph_epilogue(const int32_t* glist, int ng, const int64_t* voff, const int64_t* eoff,
-                                 const int64_t* cedge, const uint8_t* cin_mst, const uint32_t* gw,
-                                 const int32_t* gbad, uint8_t* in_mst, unsigned long long* total, int32_t* status,
-                                 hipStream_t s) {
+                                 const int64_t* cedge, int64_t max_graph_m, const uint8_t* cin_mst,
+                                 const uint32_t* gw, const int32_t* gbad, uint8_t* in_mst,
+                                 unsigned long long* acc_w, uint32_t* acc_c, unsigned long long* total,
+                                 int32_t* status, hipStream_t s) {
   if (ng <= 0) return hipSuccess;
-  k_graph_epilogue<<<ng, 256, 0, s>>>(glist, voff, eoff, cedge, cin_mst, gw, gbad, in_mst, total, status);
+  hipError_t e = hipMemsetAsync(acc_w, 0, 8 * (size_t)ng, s);
+  if (e == hipSuccess) e = hipMemsetAsync(acc_c, 0, 4 * (size_t)ng, s);
+  if (e != hipSuccess) return e;
+  // at most 65535 slices per graph (the grid's y limit)
+  const int64_t slice = std::max<int64_t>(kEpilogueSlice, (max_graph_m + 65534) / 65535);
+  const int64_t slices = std::max<int64_t>(1, (max_graph_m + slice - 1) / slice);
+  k_graph_epilogue<<<dim3(ng, (unsigned)slices), 256, 0, s>>>(glist, slice, eoff, cedge, cin_mst, gw, in_mst,
+                                                               acc_w, acc_c);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_graph_status<<<(ng + 255) / 256, 256, 0, s>>>(glist, ng, voff, acc_w, acc_c, gbad, total, status);
   return hipGetLastError();
 }
 

@@ -604,7 +604,7 @@ int solve(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, const ui
 
 // Device scratch of a batched call besides the solve workspace.
 struct BatchLayout {
-  size_t voff, eoff, small, large, cvert, cedge, gbad, gsrc, gdst, gw, cin, total, bytes;
+  size_t voff, eoff, small, large, cvert, cedge, gbad, gsrc, gdst, gw, cin, total, acc_w, acc_c, bytes;
 };
 
 BatchLayout plan_batch(int32_t G, int64_t nsmall, int64_t nlarge, int64_t nchunk_meta, int64_t max_chunk_m) {
@@ -627,6 +627,8 @@ BatchLayout plan_batch(int32_t G, int64_t nsmall, int64_t nlarge, int64_t nchunk
   B.gw = take(4 * (size_t)std::max<int64_t>(max_chunk_m, 1));
   B.cin = take((size_t)std::max<int64_t>(max_chunk_m, 1));
   B.total = take(8);
+  B.acc_w = take(8 * (size_t)std::max<int64_t>(nlarge, 1));
+  B.acc_c = take(4 * (size_t)std::max<int64_t>(nlarge, 1));
   B.bytes = off;
   return B;
 }
@@ -762,8 +764,11 @@ int solve_batched(int32_t G, const int64_t* voff, const int64_t* eoff, const int
     } else {
       HIP_OK(hipMemsetAsync(cin, 0, 1, s));
     }
-    HIP_OK(launch_graph_epilogue(d_large + i0, ng, d_voff, d_eoff, d_cedge + at_meta, cin, gw, d_gbad + i0,
-                                 in_mst, tot, status, s));
+    int64_t max_graph_m = 0;
+    for (int32_t q = 0; q < ng; ++q) max_graph_m = std::max(max_graph_m, cedge[at_meta + q + 1] - cedge[at_meta + q]);
+    HIP_OK(launch_graph_epilogue(d_large + i0, ng, d_voff, d_eoff, d_cedge + at_meta, max_graph_m, cin, gw,
+                                 d_gbad + i0, in_mst, at<unsigned long long>(A, BL.acc_w),
+                                 at<uint32_t>(A, BL.acc_c), tot, status, s));
   }
   HIP_OK(hipStreamSynchronize(s));
   return MSTX_OK;

@@ -169,9 +169,10 @@ hipError_t launch_gather(const int32_t* glist, int ng, const int64_t* voff, cons
                          const int32_t* dst, const uint32_t* w, int32_t* gsrc, int32_t* gdst, uint32_t* gw,
                          int32_t* gbad, hipStream_t s);
 hipError_t launch_graph_epilogue(const int32_t* glist, int ng, const int64_t* voff, const int64_t* eoff,
-                                 const int64_t* cedge, const uint8_t* cin_mst, const uint32_t* gw,
-                                 const int32_t* gbad, uint8_t* in_mst, unsigned long long* total, int32_t* status,
-                                 hipStream_t s);
+                                 const int64_t* cedge, int64_t max_graph_m, const uint8_t* cin_mst,
+                                 const uint32_t* gw, const int32_t* gbad, uint8_t* in_mst,
+                                 unsigned long long* acc_w, uint32_t* acc_c, unsigned long long* total,
+                                 int32_t* status, hipStream_t s);
 hipError_t launch_init(int32_t n, unsigned long long* best, int32_t* parent, unsigned long long* pbest,
                        uint32_t* btot, DevState* st, int grid, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, int64_t count, unsigned long long v, int grid,
