@@ -48,8 +48,9 @@ __device__ __forceinline__ int32_t small_root(int32_t* par, int32_t x) {
 
 // One workgroup per graph of `glist` (graphs with n <= kSmallN).  LDS holds
 // best[n] (u64 minimum key per component root), comp[n] (round-start root of
-// each vertex) and par[n] (union-find over the roots during hooking).  Each
-// round: minima over the graph's edges (re-read from HBM / cache), CAS hooking
+// each vertex) and par[n] (union-find over the roots during hooking), and the
+// graph's edges when they fit behind them.  Each round: minima over the
+// graph's edges (from LDS, else re-read from HBM / cache), CAS hooking
 // of the larger root under the smaller, compression; the loop ends when a
 // round selects no edge.  Writes in_mst for the graph's edges (zeroed by the
 // caller), total[g] and status[g].
@@ -69,10 +70,8 @@ __global__ void __launch_bounds__(kSmallBlock) k_small_solve(const int32_t* __re
                                                              uint8_t* __restrict__ in_mst,
                                                              unsigned long long* __restrict__ total_out,
                                                              int32_t* __restrict__ status_out,
-                                                             int64_t* __restrict__ stats) {
-  extern __shared__ unsigned long long sbest[];  // [kSmallN]
-  int32_t* comp = reinterpret_cast<int32_t*>(sbest + kSmallN);
-  int32_t* par = comp + kSmallN;
+                                                             int64_t* __restrict__ stats, uint32_t lds_bytes) {
+  extern __shared__ unsigned long long sbest[];  // [n], then comp [n], par [n], the edge cache
   __shared__ uint32_t round_sel;
   __shared__ uint32_t bad;
   __shared__ unsigned long long red_w[kSmallBlock / 64];
@@ -86,6 +85,25 @@ __global__ void __launch_bounds__(kSmallBlock) k_small_solve(const int32_t* __re
   const int tid = threadIdx.x;
   int64_t n_round = n;  // components entering the round (statistics)
   int rows = 0;
+  int32_t* comp = reinterpret_cast<int32_t*>(sbest + n);
+  int32_t* par = comp + n;
+  // The graph's edges stay in LDS behind the vertex state when they fit
+  // (12 B each): every round then reads them from LDS instead of HBM / L2.
+  const uint64_t cache_at = ((uint64_t)16 * (uint32_t)n + 15) & ~(uint64_t)15;
+  const bool cached = cache_at + 12 * (uint64_t)m <= lds_bytes;
+  int32_t* csrc = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(sbest) + cache_at);
+  int32_t* cdst = csrc + m;
+  uint32_t* cw = reinterpret_cast<uint32_t*>(cdst + m);
+  if (cached) {
+    for (int64_t j = tid; j < m; j += kSmallBlock) {
+      csrc[j] = src[e0 + j];
+      cdst[j] = dst[e0 + j];
+      cw[j] = w[e0 + j];
+    }
+  }
+  const int32_t* esrc = cached ? csrc : src + e0;
+  const int32_t* edst = cached ? cdst : dst + e0;
+  const uint32_t* ew = cached ? cw : w + e0;
 
   for (int32_t v = tid; v < n; v += kSmallBlock) comp[v] = v;
   if (tid == 0) bad = 0;
@@ -107,7 +125,7 @@ __global__ void __launch_bounds__(kSmallBlock) k_small_solve(const int32_t* __re
     // edge scan: lightest outgoing key per component root
     uint32_t live = 0;
     for (int64_t j = tid; j < m; j += kSmallBlock) {
-      const int32_t a0 = src[e0 + j], b0 = dst[e0 + j];
+      const int32_t a0 = esrc[j], b0 = edst[j];
       if ((uint32_t)a0 >= (uint32_t)n || (uint32_t)b0 >= (uint32_t)n) {
         bad = 1;
         continue;
@@ -115,7 +133,7 @@ __global__ void __launch_bounds__(kSmallBlock) k_small_solve(const int32_t* __re
       const int32_t a = comp[a0], b = comp[b0];
       if (a == b) continue;
       ++live;
-      const unsigned long long key = ((unsigned long long)w[e0 + j] << 32) | (unsigned long long)j;
+      const unsigned long long key = ((unsigned long long)ew[j] << 32) | (unsigned long long)j;
       if (key < sbest[a]) atomicMin(sbest + a, key);
       if (key < sbest[b]) atomicMin(sbest + b, key);
     }
@@ -129,7 +147,7 @@ __global__ void __launch_bounds__(kSmallBlock) k_small_solve(const int32_t* __re
       if (key == kKeyNone) continue;
       ++nonisolated;
       const int64_t j = (int64_t)(uint32_t)key;
-      const int32_t u = comp[src[e0 + j]], v = comp[dst[e0 + j]];
+      const int32_t u = comp[esrc[j]], v = comp[edst[j]];
       const int32_t d = (u == c) ? v : u;
       if (d < c && sbest[d] == key) continue;  // mutual choice: d hooks it
       int32_t x = c, y = d;
@@ -318,7 +336,7 @@ __global__ void __launch_bounds__(256) k_graph_status(const int32_t* __restrict_
 
 hipError_t configure_batched_kernels() {
   return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_small_solve),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmallSolveLds);
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxDynLds);
 }
 
 hipError_t launch_small_solve(const int32_t* glist, int num, const int64_t* voff, const int64_t* eoff,
@@ -326,15 +344,18 @@ hipError_t launch_small_solve(const int32_t* glist, int num, const int64_t* voff
                               unsigned long long* total, int32_t* status, hipStream_t s) {
   if (num <= 0) return hipSuccess;
   k_small_solve<<<num, kSmallBlock, kSmallSolveLds, s>>>(glist, voff, eoff, 0, 0, src, dst, w, in_mst, total,
-                                                          status, nullptr);
+                                                          status, nullptr, (uint32_t)kSmallSolveLds);
   return hipGetLastError();
 }
 
 hipError_t launch_small_solve_single(int32_t n, int64_t m, const int32_t* src, const int32_t* dst,
                                      const uint32_t* w, uint8_t* in_mst, unsigned long long* total,
                                      int32_t* status, int64_t* stats, hipStream_t s) {
-  k_small_solve<<<1, kSmallBlock, kSmallSolveLds, s>>>(nullptr, nullptr, nullptr, n, m, src, dst, w, in_mst, total,
-                                                        status, stats);
+  // the vertex state, and the edges too when both fit the workgroup's LDS
+  const size_t state = ((size_t)16 * (size_t)n + 15) & ~(size_t)15;
+  const size_t lds = state + 12 * (size_t)m <= (size_t)kMaxDynLds ? state + 12 * (size_t)m : (size_t)16 * n;
+  k_small_solve<<<1, kSmallBlock, lds, s>>>(nullptr, nullptr, nullptr, n, m, src, dst, w, in_mst, total, status,
+                                             stats, (uint32_t)lds);
   return hipGetLastError();
 }
 
