@@ -180,8 +180,8 @@ int mst_workspace_release(void* stream);
  * limit * (limit - 1) / 2 keys in LDS) and one workgroup completes Boruvka on
  * that small complete graph; it is the last round.  The tree is the same; the
  * per-round statistics then end with that round, whose "edges added" is the
- * sum over the rounds it replaces.  limit is clamped to [0, 198] (0: off,
- * every round is a plain Boruvka round; the default is 198).  limit < 0 only
+ * sum over the rounds it replaces.  limit is clamped to [0, 200] (0: off,
+ * every round is a plain Boruvka round; the default is 200).  limit < 0 only
  * queries.  Returns the previous limit.  Process-wide; read at the start of
  * each call (mst_solve_batched's large graphs included).
  */

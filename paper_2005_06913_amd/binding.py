@@ -106,7 +106,7 @@ def mst_workspace_release(stream=None) -> int:
 
 def mst_set_dense_limit(limit: int) -> int:
     """Set the component count at or below which a solve ends with the dense
-    finish (0: off, clamped to 198; negative: query).  Returns the previous limit."""
+    finish (0: off, clamped to 200; negative: query).  Returns the previous limit."""
     return int(load_library().mst_set_dense_limit(int(limit)))
 
 

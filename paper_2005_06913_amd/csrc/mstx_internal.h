@@ -27,9 +27,10 @@ static constexpr int kModeBucket = 2;  // offers sorted into component buckets +
 static constexpr int kModeDense = 3;   // last round: lightest edge per component pair, then finish
 static constexpr int kNumModes = 4;
 
-// LDS: up to 160 KB of dynamic LDS per workgroup (gfx950 has 160 KB per CU).
-static constexpr int kMaxDynLds = 160000;
-static constexpr int32_t kLdsSlots = kMaxDynLds / 8;  // 20000 u64 minima
+// gfx950 has 160 KiB of LDS per CU and gives all of it to one workgroup if
+// asked; 1 KiB stays for the kernels' static LDS (at most 640 B today).
+static constexpr int kMaxDynLds = 160 * 1024 - 1024;
+static constexpr int32_t kLdsSlots = kMaxDynLds / 8;  // 20352 u64 minima
 // Buckets hold 2^shift components, 64 <= 2^shift <= 16384 (the LDS table of
 // k_bucket_min), at most 1023 buckets (one counter per scan thread + total).
 static constexpr int kMaxBuckets = 1023;
@@ -67,7 +68,7 @@ __host__ __device__ constexpr int32_t dense_pairs(int32_t k) { return k * (k - 1
 __host__ __device__ constexpr size_t dense_finish_lds(int32_t k) {
   return (size_t)dense_pairs(k) * 8 + (size_t)k * 16;  // table, best key, parent, target
 }
-static constexpr int32_t kDenseMax = 198;
+static constexpr int32_t kDenseMax = 200;
 static constexpr int32_t kDensePairsMax = dense_pairs(kDenseMax);
 static_assert(dense_finish_lds(kDenseMax) <= (size_t)kMaxDynLds, "dense finish exceeds LDS");
 static_assert(dense_finish_lds(kDenseMax + 1) > (size_t)kMaxDynLds, "kDenseMax is not the largest fit");

@@ -24,8 +24,9 @@ def _concat(parts, name):
                    np.concatenate(w).astype(np.uint32), name)
 
 
-DENSE_MAX = 198  # largest component count the library's dense finish takes
+DENSE_MAX = 200  # largest component count the library's dense finish takes
 SMALL_MAX = 8192  # largest vertex count of the library's one-workgroup path
+LDS_SLOTS = 20352  # largest component count whose minima the scan keeps in LDS
 
 
 def stats_consistent(gpu_stats, oracle_stats, limit=DENSE_MAX):
@@ -84,7 +85,10 @@ def small_cases():
         ties_multigraph(5000, 9000, seed=28, wmax=1),  # every weight equal but the path
         G.rmat(14, 120_000, seed=29),
         G.planted_weights(G.tree_plus_extra(50_000, 400_000, seed=30)),
-        # more than 20000 vertices: offers sorted into buckets.  Skewed degrees put
+        # either side of the LDS-table limit: round 0 in LDS mode at it, bucket mode above
+        G.tree_plus_extra(LDS_SLOTS, 5 * LDS_SLOTS + 3, seed=35, name="lds_limit_n20352"),
+        G.tree_plus_extra(LDS_SLOTS + 1, 5 * LDS_SLOTS + 5, seed=36, name="lds_limit_n20353"),
+        # more than 20352 vertices: offers sorted into buckets.  Skewed degrees put
         # most offers into a few buckets (extra workgroups for them); a grid's
         # row-major edge order gives long runs (cut into items)
         G.rmat(16, 400_000, seed=33),

@@ -120,7 +120,7 @@ def test_dense_finish_ends_early(dev):
     gstats = check_against_oracle(dev, g.name, g.n, g.src, g.dst, g.w, small=0)
     b = oracle.boruvka(g.n, g.src, g.dst, g.w)
     assert len(gstats) < len(b.stats), (gstats, b.stats)
-    # a graph of at most 198 vertices is solved by the dense finish in round 0
+    # a graph of at most 200 vertices is solved by the dense finish in round 0
     k64 = gpu_cases.small_cases()[7]
     assert k64.n == 64
     gstats = check_against_oracle(dev, k64.name, k64.n, k64.src, k64.dst, k64.w, small=0)
