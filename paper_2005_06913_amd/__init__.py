@@ -22,6 +22,7 @@ from .binding import (  # noqa: F401
     dense_limit,
     load_library,
     small_limit,
+    tail_limit,
     mst_batched_workspace_bytes,
     mst_last_round_stats,
     mst_profile_enable,
@@ -29,6 +30,7 @@ from .binding import (  # noqa: F401
     mst_select_min_edges,
     mst_set_dense_limit,
     mst_set_small_limit,
+    mst_set_tail_limit,
     mst_solve,
     mst_solve_batched,
     mst_status_string,

@@ -26,7 +26,8 @@ MSTX_ERR_DEVICE = -5
 
 EXPORTS = ("mst_solve", "mst_solve_batched", "mst_batched_workspace_bytes", "mst_select_min_edges",
            "mst_last_round_stats", "mst_workspace_bytes", "mst_status_string", "mst_profile_enable",
-           "mst_profile_read", "mst_profile_kernel_name", "mst_workspace_release", "mst_set_dense_limit", "mst_set_small_limit")
+           "mst_profile_read", "mst_profile_kernel_name", "mst_workspace_release", "mst_set_dense_limit", "mst_set_small_limit",
+           "mst_set_tail_limit")
 
 _lib = None
 
@@ -71,6 +72,8 @@ def load_library(path: str = LIB_PATH):
     lib.mst_set_dense_limit.restype = ctypes.c_int32
     lib.mst_set_small_limit.argtypes = [ctypes.c_int32]
     lib.mst_set_small_limit.restype = ctypes.c_int32
+    lib.mst_set_tail_limit.argtypes = [ctypes.c_int32]
+    lib.mst_set_tail_limit.restype = ctypes.c_int32
     lib.mst_profile_kernel_name.argtypes = [ctypes.c_int]
     lib.mst_profile_kernel_name.restype = ctypes.c_char_p
     _lib = lib
@@ -114,6 +117,30 @@ def mst_set_small_limit(limit: int) -> int:
     """Set the vertex count up to which mst_solve uses the one-workgroup path
     (0: off, clamped to 8192; negative: query).  Returns the previous limit."""
     return int(load_library().mst_set_small_limit(int(limit)))
+
+
+def mst_set_tail_limit(limit: int) -> int:
+    """Set the component-count bound up to which a round's hook .. relabel run as
+    one workgroup (0: off, clamped to 10240; negative: query).  Returns the
+    previous limit."""
+    return int(load_library().mst_set_tail_limit(int(limit)))
+
+
+class tail_limit:
+    """Context manager: ``with tail_limit(0): ...`` runs every round's hook .. relabel
+    as grid-wide kernels."""
+
+    def __init__(self, limit: int):
+        self.limit = limit
+        self.prev = None
+
+    def __enter__(self):
+        self.prev = mst_set_tail_limit(self.limit)
+        return self
+
+    def __exit__(self, *exc):
+        mst_set_tail_limit(self.prev)
+        return False
 
 
 class small_limit:

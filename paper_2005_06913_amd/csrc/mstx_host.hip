@@ -35,7 +35,7 @@ constexpr int kMaxGrid = 4096;  // capacity of the per-block partial arrays (hoo
 
 struct Layout {
   size_t best, parent, root_of, labpool, rootmask, rootcnt, rootpre, rec, seg_cnt, part_sel, part_w, state,
-      pbest, btot, upd_key, upd_cl, offT, slab, bytes;
+      pbest, btot, offers, offT, slab, bytes;
   int64_t slab_cap;  // u64 entries of the LDS-mode slab (0: none)
   int32_t nseg;
   bool bucket;  // offer buffers present
@@ -76,8 +76,7 @@ Layout plan(int32_t n, int64_t m) {
   L.slab_cap = n > kSlabMin ? (int64_t)kSlabRows * std::min<int32_t>(n, kLdsSlots) : 0;
   if (L.slab_cap) L.slab = take(8 * (size_t)L.slab_cap);
   if (L.bucket) {
-    L.upd_key = take(8 * (size_t)nseg * kOfferCap);
-    L.upd_cl = take(2 * (size_t)nseg * kOfferCap);
+    L.offers = take(8 * (size_t)nseg * kOfferCap);
     L.offT = take(4 * (size_t)(kMaxBuckets + 1) * nseg);
   }
   L.bytes = off;
@@ -108,6 +107,9 @@ std::atomic<int> g_dense_limit{kDenseMax};
 // Largest vertex count for which mst_solve takes the one-workgroup path
 // (0: never); mst_set_small_limit() changes it.
 std::atomic<int> g_small_limit{kSmallN};
+// Largest component-count bound for which a round's hook .. relabel run as
+// one workgroup (0: never); mst_set_tail_limit() changes it.
+std::atomic<int> g_tail_limit{kTailMax};
 std::map<std::pair<int, hipStream_t>, std::unique_ptr<DeviceCache>> g_caches;
 
 thread_local std::vector<int64_t> t_last_stats;
@@ -202,7 +204,7 @@ enum Kind {
   kScan0Global = 0, kScan0Lds, kScan0Bucket, kScan0Dense,
   kScan1Global, kScan1Lds, kScan1Bucket, kScan1Dense,
   kScanRGlobal, kScanRLds, kScanRBucket, kScanRDense,
-  kBucketMin, kSlabMin_, kDenseFinish, kHook, kCompress, kFinalize, kRelabel, kSmallSolve, kKinds
+  kBucketMin, kSlabMin_, kDenseFinish, kHook, kCompress, kFinalize, kRelabel, kSmallSolve, kRoundTail, kKinds
 };
 // Names as rocprofv3 reports the kernels (template arguments: minima mode
 // 0 global / 1 LDS / 2 bucket / 3 dense, reads the caller's arrays, compacts).
@@ -211,7 +213,8 @@ const char* const kKindNames[kKinds] = {
     "k_scan<0, true, true>",   "k_scan<1, true, true>",   "k_scan<2, true, true>",   "k_scan<3, true, true>",
     "k_scan<0, false, true>",  "k_scan<1, false, true>",  "k_scan<2, false, true>",  "k_scan<3, false, true>",
     "k_bucket_min",            "k_slab_min",              "k_dense_finish",          "k_hook",
-    "k_compress",              "k_finalize",              "k_relabel",               "k_small_solve"};
+    "k_compress",              "k_finalize",              "k_relabel",               "k_small_solve",
+    "k_round_tail"};
 
 int scan_kind(int stage, int mode) { return kNumModes * stage + mode; }
 
@@ -313,13 +316,13 @@ struct Solve {
   uint32_t* part_sel;
   unsigned long long* part_w;
   DevState* st;
-  unsigned long long* upd_key;
-  uint16_t* upd_cl;
+  unsigned long long* offers;
   uint32_t* offT;
   unsigned long long* slab;
   unsigned long long* pbest;
   uint32_t* btot;
   int dense_limit;            // 0: no dense finish
+  int tail_limit;             // 0: every round takes the multi-workgroup hook .. relabel
   std::vector<int> launched;  // per round
 };
 
@@ -338,7 +341,7 @@ int enqueue_scan(Solve& S, int r, int stage, int64_t bound, bool exact, hipError
   if (!S.L.bucket) launched &= ~(1 << kModeBucket), launched |= (bound > kLdsSlots ? 1 << kModeGlobal : 0);
   launched |= S.dense_limit << 8;
   ScanArgs A{r,      launched, S.src,     S.dst,    S.w,    (uint32_t)S.m, S.n,     S.labpool, S.rec,
-             S.seg_cnt, S.L.nseg, S.best, S.st, S.upd_key, S.upd_cl, S.offT, S.slab, S.L.slab_cap, S.pbest, -1,
+             S.seg_cnt, S.L.nseg, S.best, S.st, S.offers, S.offT, S.slab, S.L.slab_cap, S.pbest, -1,
              S.btot};
   const int cus = S.dc->cus;
   for (int mode : {kModeDense, kModeLds, kModeBucket, kModeGlobal}) {
@@ -361,13 +364,15 @@ int enqueue_scan(Solve& S, int r, int stage, int64_t bound, bool exact, hipError
       grid = std::min(S.L.nseg, 2 * cus);
     }
     // the previous round's label map (n_prev entries, exact) goes to LDS
-    // beside the minima table when both fit: the lookups become LDS reads
+    // beside the minima table when both fit: the lookups become LDS reads.
+    // Staged entries take 2 bytes (LDS mode) or 1 byte (DENSE mode).
     A.lab_lds_off = -1;
     if (stage == 2 && (mode == kModeLds || mode == kModeDense) && n_prev > 0) {
       const size_t off = (lds + 15) & ~size_t(15);
-      if (off + 4 * (size_t)n_prev <= (size_t)kMaxDynLds) {
+      const size_t bytes = (mode == kModeDense ? 1 : 2) * (size_t)n_prev;
+      if (off + bytes <= (size_t)kMaxDynLds) {
         A.lab_lds_off = (int32_t)off;
-        lds = off + 4 * (size_t)n_prev;
+        lds = off + bytes;
       }
     }
     const int k = T.start(scan_kind(stage, mode), r, mode);
@@ -397,7 +402,7 @@ int enqueue_scan(Solve& S, int r, int stage, int64_t bound, bool exact, hipError
       // more than twice the average offers (at most half as many again)
       const int grid_b = std::max(nbk, 256) * 3 / 2 + 1;
       const int kb = T.start(kBucketMin, r, kModeBucket);
-      err = launch_bucket_min(r, launched, S.upd_key, S.upd_cl, S.offT, S.L.nseg, S.btot, S.best, S.st, grid_b,
+      err = launch_bucket_min(r, launched, S.offers, S.offT, S.L.nseg, S.btot, S.best, S.st, grid_b,
                               (size_t)8 << shift, S.s);
       T.stop(kb);
       if (err != hipSuccess) return launched;
@@ -414,6 +419,15 @@ hipError_t enqueue_round(Solve& S, int r, int64_t bound, int64_t n_prev = 0) {
   S.launched[r] = enqueue_scan(S, r, stage, bound, r == 0, err, n_prev);
   if (err != hipSuccess) return err;
   const int gh = grid_for(std::max<int64_t>(bound, 1));
+  if (bound <= S.tail_limit) {
+    // few components: the rest of the round in one workgroup
+    const int k = T.start(kRoundTail, r, -1);
+    err = launch_round_tail(r, (int32_t)bound, S.rec, S.best, S.parent, S.labpool, S.seg_cnt, S.L.nseg, S.in_mst,
+                            S.total, S.btot, S.st, S.dc->host_rounds, S.s);
+    T.stop(k);
+    if (err != hipSuccess) return err;
+    return hipEventRecord(S.dc->round_ev[r], S.s);
+  }
   int k = T.start(kHook, r, -1);
   err = launch_hook(r, S.rec, S.best, S.parent, S.st, S.in_mst, S.part_sel, S.part_w, gh, S.s);
   T.stop(k);
@@ -462,13 +476,13 @@ int solve_locked(DeviceCache* dc, const Layout& L, int32_t n, int64_t m, const i
   S.part_sel = at<uint32_t>(B, L.part_sel);
   S.part_w = at<unsigned long long>(B, L.part_w);
   S.st = at<DevState>(B, L.state);
-  S.upd_key = L.bucket ? at<unsigned long long>(B, L.upd_key) : nullptr;
-  S.upd_cl = L.bucket ? at<uint16_t>(B, L.upd_cl) : nullptr;
+  S.offers = L.bucket ? at<unsigned long long>(B, L.offers) : nullptr;
   S.offT = L.bucket ? at<uint32_t>(B, L.offT) : nullptr;
   S.slab = L.slab_cap ? at<unsigned long long>(B, L.slab) : nullptr;
   S.pbest = at<unsigned long long>(B, L.pbest);
   S.btot = at<uint32_t>(B, L.btot);
   S.dense_limit = g_dense_limit.load();
+  S.tail_limit = g_tail_limit.load();
   const int max_rounds = std::min(rounds_bound(n) + 1, kMaxRounds);
   S.launched.assign(kMaxRounds + 1, 0);
 
@@ -486,8 +500,9 @@ int solve_locked(DeviceCache* dc, const Layout& L, int32_t n, int64_t m, const i
   nr_of[0] = n;
   int r_enq = 0;
   for (int r = 0; r < max_rounds; ++r) {
-    // a round that can only be the dense finish is the last one: nothing to enqueue after it
-    const bool final_round = (S.launched[r] & 0xFF) == (1 << kModeDense);
+    // a round whose scan takes the dense finish (its count n_known is exact
+    // here) is the last one: nothing to enqueue after it
+    const bool final_round = pick_mode(n_known, S.launched[r]) == kModeDense;
     if (r_enq == r && r + 1 <= kMaxRounds - 1 && !final_round) {
       // n_known entered round r: the size of the label map round r + 1 reads
       HIP_OK(enqueue_round(S, r + 1, n_known / 2, n_known));
@@ -799,8 +814,7 @@ int select_min_edges(int32_t n, int64_t m, const int32_t* src, const int32_t* ds
   S.rec = at<uint4>(B, L.rec);
   S.labpool = at<int32_t>(B, L.labpool);
   S.st = at<DevState>(B, L.state);
-  S.upd_key = L.bucket ? at<unsigned long long>(B, L.upd_key) : nullptr;
-  S.upd_cl = L.bucket ? at<uint16_t>(B, L.upd_cl) : nullptr;
+  S.offers = L.bucket ? at<unsigned long long>(B, L.offers) : nullptr;
   S.offT = L.bucket ? at<uint32_t>(B, L.offT) : nullptr;
   S.slab = L.slab_cap ? at<unsigned long long>(B, L.slab) : nullptr;
   S.pbest = at<unsigned long long>(B, L.pbest);
@@ -944,6 +958,11 @@ size_t mst_workspace_bytes(int32_t n, int64_t m) {
 int32_t mst_set_small_limit(int32_t limit) {
   if (limit < 0) return mstx::g_small_limit.load();
   return mstx::g_small_limit.exchange(std::min<int32_t>(limit, mstx::kSmallN));
+}
+
+int32_t mst_set_tail_limit(int32_t limit) {
+  if (limit < 0) return mstx::g_tail_limit.load();
+  return mstx::g_tail_limit.exchange(std::min<int32_t>(limit, mstx::kTailMax));
 }
 
 int32_t mst_set_dense_limit(int32_t limit) {

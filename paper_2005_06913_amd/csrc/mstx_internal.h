@@ -46,8 +46,15 @@ static constexpr int kOfferAlign = 16;
 static constexpr int kOfferPadBuckets = 256;
 static constexpr int kOfferCap = 2 * kSegCap + kOfferAlign * kOfferPadBuckets;
 static_assert(kOfferCap < (1 << 16) && 2 * kSegCap < (1 << 16), "offer run word");
+// An offer is one word: the key's weight in bits 32..63, the key's low half
+// minus the segment's first position (the edge's slot in its segment) in
+// bits kOfferSlotShift.., and the component's index inside its bucket in the
+// bits below.  The consumer knows the segment of every run, so it rebuilds
+// the key exactly.
+static constexpr int kOfferSlotShift = kMaxBucketShift;
+static_assert(((uint64_t)(kSegCap - 1) << kOfferSlotShift) < (1ull << 32), "offer slot field");
 // Bytes of dynamic LDS a BUCKET-mode scan uses: offer staging + counters.
-static constexpr int kBucketScanLds = kOfferCap * (8 + 2) + (kMaxBuckets + 1) * 4;
+static constexpr int kBucketScanLds = kOfferCap * 8 + (kMaxBuckets + 1) * 4;
 
 // Bucket width 2^shift >= ceil(nr / 256) (about 256 buckets, so one
 // k_bucket_min workgroup per CU) and the bucket count.
@@ -66,13 +73,18 @@ __host__ __device__ inline void bucket_geometry(int32_t nr, int* shift, int* nbk
 // table plus per-component state fits the dynamic LDS of one workgroup.
 __host__ __device__ constexpr int32_t dense_pairs(int32_t k) { return k * (k - 1) / 2; }
 __host__ __device__ constexpr size_t dense_finish_lds(int32_t k) {
-  return (size_t)dense_pairs(k) * 8 + (size_t)k * 16;  // table, best key, parent, target
+  return (size_t)dense_pairs(k) * 8 + (size_t)k * 16;  // table; per group: key, added key, parent, target
 }
 static constexpr int32_t kDenseMax = 200;
 static constexpr int32_t kDensePairsMax = dense_pairs(kDenseMax);
 static_assert(dense_finish_lds(kDenseMax) <= (size_t)kMaxDynLds, "dense finish exceeds LDS");
 static_assert(dense_finish_lds(kDenseMax + 1) > (size_t)kMaxDynLds, "kDenseMax is not the largest fit");
 static_assert(kDensePairsMax <= kLdsSlots && kDenseMax < 256, "dense limit");
+// Rounds with at most kTailMax components close in one workgroup
+// (k_round_tail: hook, compress, finalize and relabel with the parent forest
+// in LDS, 8 bytes per component, and ten components' edges per thread in
+// registers).
+static constexpr int32_t kTailMax = 10240;
 // index of the unordered pair {a, b}, a < b < k, in row-major upper-triangle order
 __host__ __device__ inline int32_t pair_index(int32_t a, int32_t b, int32_t k) {
   return a * k - a * (a + 1) / 2 + (b - a - 1);
@@ -130,8 +142,7 @@ struct ScanArgs {
   int32_t nseg;
   unsigned long long* best;
   DevState* st;
-  unsigned long long* upd_key;  // BUCKET mode offers: [nseg][2 * kSegCap]
-  uint16_t* upd_cl;
+  unsigned long long* offers;   // BUCKET mode offers: [nseg][kOfferCap]
   uint32_t* offT;               // [kMaxBuckets + 1][nseg] run starts
   unsigned long long* slab;     // LDS mode, n_r > kSlabMin: per-workgroup minima [grid][n_r]
   int64_t slab_cap;             // entries of slab
@@ -179,8 +190,7 @@ hipError_t launch_init(int32_t n, unsigned long long* best, int32_t* parent, uns
 hipError_t launch_fill_u64(unsigned long long* p, int64_t count, unsigned long long v, int grid,
                            hipStream_t s);
 hipError_t launch_scan(int mode, int stage, const ScanArgs& a, int grid, size_t lds, hipStream_t s);
-hipError_t launch_bucket_min(int round, int launched, const unsigned long long* upd_key, const uint16_t* upd_cl,
-                             const uint32_t* offT, int32_t nseg, const uint32_t* btot, unsigned long long* best,
+hipError_t launch_bucket_min(int round, int launched, const unsigned long long* offers, const uint32_t* offT, int32_t nseg, const uint32_t* btot, unsigned long long* best,
                              const DevState* st, int grid, size_t lds, hipStream_t s);
 hipError_t launch_slab_min(int round, int launched, int mode, const unsigned long long* slab, int64_t slab_cap,
                            int nwg, unsigned long long* best, unsigned long long* pbest, const DevState* st,
@@ -193,6 +203,10 @@ hipError_t launch_hook(int round, const uint4* rec, const unsigned long long* be
 hipError_t launch_compress(int round, int32_t* parent, int32_t* root_of, const unsigned long long* best,
                            unsigned long long* rootmask, int32_t* rootcnt, const DevState* st, int grid,
                            hipStream_t s);
+hipError_t launch_round_tail(int round, int32_t cap, const uint4* rec, unsigned long long* best, int32_t* parent,
+                             int32_t* labpool, const uint32_t* seg_cnt, int32_t nseg, uint8_t* in_mst,
+                             unsigned long long* total, uint32_t* btot, DevState* st, HostRound* host,
+                             hipStream_t s);
 hipError_t launch_finalize(int round, const int32_t* rootcnt, int32_t* rootpre, const uint32_t* part_live,
                            int32_t nlive, const uint32_t* part_sel, const unsigned long long* part_w,
                            int32_t nhook, DevState* st, unsigned long long* total, HostRound* host,

@@ -50,6 +50,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "mstx_internal.h"
 
 namespace mstx {
@@ -183,12 +185,17 @@ __global__ void __launch_bounds__(kScanBlock) k_scan(ScanArgs A) {
   // keys carry stream positions from round 1 on (see below)
   constexpr bool kPosKey = kCompact && !(kFromInput && kMode == kModeDense);
   // rounds >= 2 in LDS / DENSE mode: the previous round's label map may be
-  // staged in LDS behind the minima table (the host sized the allocation)
-  const int32_t* llab = nullptr;
+  // staged in LDS behind the minima table (the host sized the allocation).
+  // Its values are labels of this round, below n_r, or -1 (isolated): they
+  // are stored plus one in 2 bytes (LDS mode, n_r <= kLdsSlots) or 1 byte
+  // (DENSE mode, n_r <= kDenseMax).
+  using LabT = std::conditional_t<kMode == kModeDense, uint8_t, uint16_t>;
+  static_assert(kLdsSlots < 0xFFFF && kDenseMax < 0xFF, "staged labels plus one fit their type");
+  const LabT* llab = nullptr;
   if (!kFromInput && (kMode == kModeLds || kMode == kModeDense) && A.lab_lds_off >= 0) {
-    int32_t* dst_l = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(smem) + A.lab_lds_off);
+    LabT* dst_l = reinterpret_cast<LabT*>(reinterpret_cast<char*>(smem) + A.lab_lds_off);
     const int32_t nprev = A.st->n[A.round - 1];
-    for (int32_t i = threadIdx.x; i < nprev; i += kScanBlock) dst_l[i] = lab[i];
+    for (int32_t i = threadIdx.x; i < nprev; i += kScanBlock) dst_l[i] = (LabT)(lab[i] + 1);
     llab = dst_l;  // visible to all after the table initialisation's barrier below
   }
 
@@ -196,13 +203,11 @@ __global__ void __launch_bounds__(kScanBlock) k_scan(ScanArgs A) {
   // BUCKET mode: geometry derived from n_r exactly as k_bucket_min does
   int shift = 0, nbk = 0;
   uint32_t* bcnt = nullptr;
-  unsigned long long* skey = nullptr;
-  uint16_t* scl = nullptr;
+  unsigned long long* soff = nullptr;
   if (kMode == kModeBucket) {
     bucket_geometry(nr, &shift, &nbk);
-    skey = smem;                                        // [kOfferCap]
-    scl = reinterpret_cast<uint16_t*>(skey + kOfferCap);  // [kOfferCap]
-    bcnt = reinterpret_cast<uint32_t*>(scl + kOfferCap);  // [nbk + 1]
+    soff = smem;                                           // [kOfferCap]
+    bcnt = reinterpret_cast<uint32_t*>(soff + kOfferCap);  // [nbk + 1]
   }
   if (kMode == kModeLds) {
     for (int32_t c = threadIdx.x; c < nr; c += kScanBlock) lbest[c] = kKeyNone;
@@ -289,8 +294,8 @@ __global__ void __launch_bounds__(kScanBlock) k_scan(ScanArgs A) {
           a = b = -1;  // dropped
         }
       } else if (!kFromInput && (kMode == kModeLds || kMode == kModeDense) && llab != nullptr) {
-        a = llab[in ? a : 0];
-        b = llab[in ? b : 0];
+        a = (int32_t)llab[in ? a : 0] - 1;
+        b = (int32_t)llab[in ? b : 0] - 1;
       } else {
         // lanes past the count look up entry 0
         const int32_t va = lab[in ? a : 0];
@@ -435,19 +440,17 @@ __global__ void __launch_bounds__(kScanBlock) k_scan(ScanArgs A) {
           const int32_t a = (int32_t)r[k].x, b = (int32_t)r[k].y;
           const uint32_t pa = bcnt[a >> shift] + slot_a[k];
           const uint32_t pb = bcnt[b >> shift] + slot_b[k];
-          skey[pa] = key[k];
-          scl[pa] = (uint16_t)(a & ((1 << shift) - 1));
-          skey[pb] = key[k];
-          scl[pb] = (uint16_t)(b & ((1 << shift) - 1));
+          // the key's low half is this segment's first position plus the slot
+          const uint64_t o = (key[k] & 0xFFFFFFFF00000000ull) |
+                             ((uint64_t)((uint32_t)key[k] - (uint32_t)base) << kOfferSlotShift);
+          soff[pa] = o | (uint32_t)(a & ((1 << shift) - 1));
+          soff[pb] = o | (uint32_t)(b & ((1 << shift) - 1));
         }
       }
       __syncthreads();
       const uint32_t total = bcnt[nbk];  // offers + pads
       const uint64_t obase = (uint64_t)s * kOfferCap;
-      for (uint32_t i = threadIdx.x; i < total; i += kScanBlock) {
-        st_stream(skey[i], A.upd_key + obase + i);
-        st_stream(scl[i], A.upd_cl + obase + i);
-      }
+      for (uint32_t i = threadIdx.x; i < total; i += kScanBlock) st_stream(soff[i], A.offers + obase + i);
     }
     __syncthreads();  // LDS (group counts, counters, staging) is reused by the next segment
   }
@@ -566,8 +569,7 @@ static constexpr size_t kBucketMinExtraLds = (2 * kChunkRuns + 1 + kMaxBuckets +
 static_assert(kChunkRuns == 2 * kScanBlock, "two runs per thread in the item scan");
 
 __global__ void __launch_bounds__(kScanBlock) k_bucket_min(int round, int launched,
-                                                           const unsigned long long* __restrict__ upd_key,
-                                                           const uint16_t* __restrict__ upd_cl,
+                                                           const unsigned long long* __restrict__ offers,
                                                            const uint32_t* __restrict__ offT, int32_t nseg,
                                                            const uint32_t* __restrict__ btot,
                                                            unsigned long long* __restrict__ best,
@@ -639,11 +641,11 @@ __global__ void __launch_bounds__(kScanBlock) k_bucket_min(int round, int launch
     const bool short_runs = !__syncthreads_or(n0 > 1 || n1 > 1);
     const uint32_t nslots = short_runs ? (uint32_t)nrun : nitems;
     for (uint32_t i0 = half * kRunsInFlight; i0 < nslots; i0 += kHalves * kRunsInFlight) {
-      uint64_t at0[kRunsInFlight];
-      uint32_t len[kRunsInFlight];
+      uint32_t seg[kRunsInFlight], at0[kRunsInFlight], len[kRunsInFlight];
       uint32_t maxlen = 0;
 #pragma unroll
       for (int q = 0; q < kRunsInFlight; ++q) {
+        seg[q] = 0;
         at0[q] = 0;
         len[q] = 0;
         const uint32_t it = i0 + q;
@@ -661,26 +663,28 @@ __global__ void __launch_bounds__(kScanBlock) k_bucket_min(int round, int launch
             piece = (it - iprefix[rl]) * kItemOffers;
           }
           const uint32_t wd = run_w[rl];
-          at0[q] = (uint64_t)(c0 + rl) * kOfferCap + (wd & 0xFFFFu) + piece;
+          seg[q] = (uint32_t)(c0 + rl);
+          at0[q] = (wd & 0xFFFFu) + piece;
           len[q] = min(kItemOffers, (wd >> 16) - piece);
         }
         maxlen = max(maxlen, len[q]);
       }
       for (uint32_t i = hl; i < maxlen; i += 32) {
-        unsigned long long k[kRunsInFlight];
-        int c[kRunsInFlight];
+        unsigned long long o[kRunsInFlight];
 #pragma unroll
         for (int q = 0; q < kRunsInFlight; ++q) {
-          k[q] = kKeyNone;
-          c[q] = 0;
-          if (i < len[q]) {
-            k[q] = ld_stream(upd_key + at0[q] + i);
-            c[q] = ld_stream(upd_cl + at0[q] + i);
-          }
+          o[q] = 0;
+          if (i < len[q]) o[q] = ld_stream(offers + (uint64_t)seg[q] * kOfferCap + at0[q] + i);
         }
 #pragma unroll
         for (int q = 0; q < kRunsInFlight; ++q) {
-          if (k[q] != kKeyNone) lower_lds(table, c[q], k[q]);
+          if (i < len[q]) {
+            // the key: weight, and the segment's first position plus the slot
+            const uint32_t lo = seg[q] * (uint32_t)kSegCap +
+                                (uint32_t)((o[q] >> kOfferSlotShift) & (uint64_t)(kSegCap - 1));
+            lower_lds(table, (int32_t)(o[q] & ((1u << kOfferSlotShift) - 1)),
+                      (o[q] & 0xFFFFFFFF00000000ull) | lo);
+          }
         }
       }
     }
@@ -700,19 +704,28 @@ __global__ void __launch_bounds__(kScanBlock) k_bucket_min(int round, int launch
 
 static constexpr int kDenseThreads = 1024;
 static constexpr int kDenseWaves = kDenseThreads / 64;
-static constexpr int kDenseRowSlots = (kDenseMax + kDenseWaves - 1) / kDenseWaves;
+// Rows of the small graph are scanned by groups of adjacent lanes.
+static constexpr int kDenseRowThreads = 4;
+static_assert(kDenseMax * kDenseRowThreads <= kDenseThreads, "one lane group per row");
+static constexpr int kDenseUnroll = 8;
+// The pair table is loaded two keys at a time, all loads issued first.
+static constexpr int kDenseLoadIters = (kDensePairsMax / 2 + kDenseThreads - 1) / kDenseThreads;
 
 // Finishes the solve on the k = n_r <= kDenseMax components of round r, one
 // workgroup: vertex u of the small graph is component u, edge {u, v} the
 // lightest original edge between them, key pbest[pair_index(u, v)] (none: no
 // edge; the key's low half is the edge index, or from round 2 on the
-// position of its record).  Boruvka again, on that graph, with everything in LDS: every group
-// of the small graph takes its lightest outgoing key (row minima, then an LDS
-// atomicMin per group), hooks onto the group at the far end (of a mutual pair
-// the smaller id stays root), and pointer jumping flattens the parents.  The
-// keys are distinct, so the selected edges are exactly the MST edges between
-// the k components.  Records round r as the last one: n_{r+1} = 0, live_r =
-// the surviving edges counted by the scan, sel_r = the edges added here.
+// position of its record).  Boruvka again, on that graph, with everything in
+// LDS: every group of the small graph takes its lightest outgoing key (row
+// minima by lane groups, then an LDS atomicMin per group), hooks onto the
+// group at the far end (of a mutual pair the smaller id stays root), and
+// pointer jumping flattens the parents.  The keys are distinct, so the
+// selected edges are exactly the MST edges between the k components; their
+// key low halves are collected and marked in in_mst[] once at the end.
+// Records round r as the last one: n_{r+1} = 0, live_r = the surviving edges
+// counted by the scan, sel_r = the edges added here.
+// LDS: table [np] u64, group minimum [k] u64, selected key low halves [k] u32,
+// parent [k] u16, target group [k] u16 (dense_finish_lds(k) bytes).
 __global__ void __launch_bounds__(kDenseThreads) k_dense_finish(int round, int launched,
                                                                const unsigned long long* __restrict__ pbest,
                                                                const uint32_t* __restrict__ seg_cnt, int32_t nseg,
@@ -722,69 +735,100 @@ __global__ void __launch_bounds__(kDenseThreads) k_dense_finish(int round, int l
   extern __shared__ unsigned long long dsm[];
   __shared__ unsigned long long red_w[kDenseWaves];
   __shared__ int64_t red_n[kDenseWaves];
+  __shared__ int64_t red_l[kDenseWaves];
+  __shared__ uint32_t nsel;
   const int32_t k = st->n[round];
   if (k <= 1 && round > 0) return;
   if (round > 0 && st->err) return;
   if (pick_mode(k, launched) != kModeDense) return;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int32_t np = dense_pairs(k);
-  unsigned long long* tab = dsm;            // [np]
-  unsigned long long* gbest = tab + np;     // [k] lightest key leaving group g (g a root)
-  int32_t* par = reinterpret_cast<int32_t*>(gbest + k);  // [k]
-  int32_t* tgt = par + k;                                // [k] group at the far end of gbest[g]
-  for (int32_t i = tid; i < np; i += kDenseThreads) tab[i] = pbest[i];
-  for (int32_t v = tid; v < k; v += kDenseThreads) par[v] = v;
+  unsigned long long* tab = dsm;                                    // [np]
+  unsigned long long* gbest = tab + np;                             // [k] lightest key leaving group g (g a root)
+  uint32_t* selpos = reinterpret_cast<uint32_t*>(gbest + k);        // [k] low halves of the added keys
+  uint16_t* par = reinterpret_cast<uint16_t*>(selpos + k);          // [k]
+  uint16_t* tgt = par + k;                                          // [k] group at the far end of gbest[g]
+  {
+    // pbest holds kDensePairsMax keys (256-byte aligned): the clamped loads stay inside
+    const ulonglong2* p2 = reinterpret_cast<const ulonglong2*>(pbest);
+    const int32_t nq = np >> 1;
+    ulonglong2 v[kDenseLoadIters];
+#pragma unroll
+    for (int q = 0; q < kDenseLoadIters; ++q) {
+      const int32_t i = q * kDenseThreads + tid;
+      v[q] = p2[i < nq ? i : 0];
+    }
+#pragma unroll
+    for (int q = 0; q < kDenseLoadIters; ++q) {
+      const int32_t i = q * kDenseThreads + tid;
+      if (i < nq) {
+        tab[2 * i] = v[q].x;
+        tab[2 * i + 1] = v[q].y;
+      }
+    }
+    if ((np & 1) && tid == 0) tab[np - 1] = pbest[np - 1];
+  }
+  for (int32_t v = tid; v < k; v += kDenseThreads) par[v] = (uint16_t)v;
+  if (tid == 0) nsel = 0;
   unsigned long long wsum = 0;
   int64_t added = 0;
+  const int32_t u = tid / kDenseRowThreads;
+  const int sub = tid % kDenseRowThreads;
   __syncthreads();
   for (;;) {
     for (int32_t v = tid; v < k; v += kDenseThreads) gbest[v] = kKeyNone;
     __syncthreads();
-    // row minima: wave wv owns rows wv, wv + 16, ...; par[] is flat here
-    unsigned long long rmin[kDenseRowSlots];
-    int32_t rarg[kDenseRowSlots];
-    bool any = false;
+    // row u: entries {v, u} for v < u lie in earlier rows, {u, v} for v > u
+    // in row u itself; lane `sub` of the group takes v = sub, sub + 4, ...
+    // (kDenseUnroll columns per step with every LDS read issued before the
+    // compares; for v = u the index may name another pair, or is clamped to 0,
+    // and par[u] == gu drops it)
+    unsigned long long best = kKeyNone;
+    int32_t arg = 0, gu = 0;
+    if (u < k) {
+      gu = par[u];
+      int32_t v0 = sub;
+      for (; v0 + (kDenseUnroll - 1) * kDenseRowThreads < k; v0 += kDenseUnroll * kDenseRowThreads) {
+        int32_t pv[kDenseUnroll];
+        unsigned long long key[kDenseUnroll];
 #pragma unroll
-    for (int q = 0; q < kDenseRowSlots; ++q) {
-      const int32_t u = wv + kDenseWaves * q;
-      rmin[q] = kKeyNone;
-      rarg[q] = -1;
-      if (u < k) {
-        const int32_t gu = par[u];
-        unsigned long long best = kKeyNone;
-        int32_t arg = -1;
-        for (int32_t v = lane; v < k; v += 64) {
-          if (par[v] != gu) {
-            const unsigned long long key = v < u ? tab[pair_index(v, u, k)] : tab[pair_index(u, v, k)];
-            if (key < best) {
-              best = key;
-              arg = v;
-            }
+        for (int q = 0; q < kDenseUnroll; ++q) {
+          const int32_t v = v0 + q * kDenseRowThreads;
+          pv[q] = par[v];
+          key[q] = tab[max(pair_index(min(u, v), max(u, v), k), 0)];
+        }
+#pragma unroll
+        for (int q = 0; q < kDenseUnroll; ++q) {
+          if (pv[q] != gu && key[q] < best) {
+            best = key[q];
+            arg = v0 + q * kDenseRowThreads;
           }
         }
-        for (int off = 32; off > 0; off >>= 1) {
-          const unsigned long long ok = __shfl_xor(best, off, 64);
-          const int32_t oa = __shfl_xor(arg, off, 64);
-          if (ok < best) {
-            best = ok;
-            arg = oa;
+      }
+      for (int32_t v = v0; v < k; v += kDenseRowThreads) {
+        if (par[v] != gu) {
+          const unsigned long long key = tab[pair_index(min(u, v), max(u, v), k)];
+          if (key < best) {
+            best = key;
+            arg = v;
           }
-        }
-        rmin[q] = best;
-        rarg[q] = arg;
-        if (best != kKeyNone) {
-          any = true;
-          if (lane == 0) atomicMin(&gbest[gu], best);
         }
       }
     }
-    if (!__syncthreads_or(any)) break;  // no edge between different groups is left
-    // the row that holds a group's minimum names the group at its far end
 #pragma unroll
-    for (int q = 0; q < kDenseRowSlots; ++q) {
-      const int32_t u = wv + kDenseWaves * q;
-      if (u < k && lane == 0 && rmin[q] != kKeyNone && rmin[q] == gbest[par[u]]) tgt[par[u]] = par[rarg[q]];
+    for (int off = 1; off < kDenseRowThreads; off <<= 1) {
+      const unsigned long long ok = __shfl_xor(best, off, 64);
+      const int32_t oa = __shfl_xor(arg, off, 64);
+      if (ok < best) {
+        best = ok;
+        arg = oa;
+      }
     }
+    const bool has = sub == 0 && best != kKeyNone;
+    if (has) atomicMin(&gbest[gu], best);
+    if (!__syncthreads_or(has)) break;  // no edge between different groups is left
+    // the row that holds a group's minimum names the group at its far end
+    if (has && best == gbest[gu]) tgt[gu] = par[arg];
     __syncthreads();
     // hook: group g onto tgt[g], except the smaller group of a mutual pair
     // (both then hold the same key, which is added once)
@@ -792,11 +836,9 @@ __global__ void __launch_bounds__(kDenseThreads) k_dense_finish(int round, int l
       if (par[g] == g && gbest[g] != kKeyNone) {
         const int32_t t = tgt[g];
         if (!(tgt[t] == g && g < t)) {
-          par[g] = t;
+          par[g] = (uint16_t)t;
           const unsigned long long key = gbest[g];
-          // from round 2 on the key holds the record's position (the dense
-          // scan moves no record), before that the edge index
-          in_mst[round >= 2 ? rec[(uint32_t)key].w : (uint32_t)key] = 1;
+          selpos[atomicAdd(&nsel, 1u)] = (uint32_t)key;
           wsum += key >> 32;
           ++added;
         }
@@ -809,12 +851,19 @@ __global__ void __launch_bounds__(kDenseThreads) k_dense_finish(int round, int l
       for (int32_t v = tid; v < k; v += kDenseThreads) {
         const int32_t p = par[v], pp = par[p];
         if (pp != p) {
-          par[v] = pp;
+          par[v] = (uint16_t)pp;
           changed = true;
         }
       }
       if (!__syncthreads_or(changed)) break;
     }
+  }
+  // from round 2 on the key holds the record's position (the dense scan moves
+  // no record), before that the edge index
+  const uint32_t nadd = nsel;
+  for (uint32_t i = tid; i < nadd; i += kDenseThreads) {
+    const uint32_t x = selpos[i];
+    in_mst[round >= 2 ? rec[x].w : x] = 1;
   }
   int64_t live = 0;
   for (int32_t i = tid; i < nseg; i += kDenseThreads) live += seg_cnt[i];
@@ -823,7 +872,6 @@ __global__ void __launch_bounds__(kDenseThreads) k_dense_finish(int round, int l
     added += __shfl_xor(added, off, 64);
     live += __shfl_xor(live, off, 64);
   }
-  __shared__ int64_t red_l[kDenseWaves];
   if (lane == 0) {
     red_w[wv] = wsum;
     red_n[wv] = added;
@@ -1125,6 +1173,253 @@ __global__ void __launch_bounds__(kBlock) k_relabel(int round, const int32_t* __
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < kMaxBuckets; i += stride) btot[i] = 0;
 }
 
+// -------------------------------------------------------- small round tail
+
+// Hook, compress, finalize and relabel of one round in one workgroup, for a
+// round with n_r <= kTailMax components (the host launches it only when its
+// bound on n_r is that small).  The same steps as k_hook .. k_relabel, with
+// the parent forest in LDS: every component with a minimum edge names the
+// component at the far end; of a mutual pair only the smaller id acts; the
+// larger root is linked under the smaller by compare-and-swap (LDS), so every
+// root is its component's smallest id and the labels (rank among the kept
+// roots, -1 for an isolated component) equal the multi-kernel path's.
+// LDS: parent [n_r] and target / root [n_r], int32 each.
+static constexpr int kTailThreads = 1024;
+static constexpr int kTailPer = (kTailMax + kTailThreads - 1) / kTailThreads;
+
+__global__ void __launch_bounds__(kTailThreads) k_round_tail(int round, int32_t cap, const uint4* __restrict__ rec,
+                                                            unsigned long long* best, int32_t* parent,
+                                                            int32_t* __restrict__ labpool,
+                                                            const uint32_t* __restrict__ seg_cnt, int32_t nseg,
+                                                            uint8_t* __restrict__ in_mst,
+                                                            unsigned long long* total, uint32_t* __restrict__ btot,
+                                                            DevState* st, HostRound* host) {
+  extern __shared__ int32_t tsm[];
+  __shared__ int64_t red_a[kTailThreads / 64];
+  __shared__ int64_t red_b[kTailThreads / 64];
+  __shared__ unsigned long long red_w[kTailThreads / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  // Every read that does not depend on another is issued here, before the
+  // first use: the round's count and state, the minimum keys of components
+  // below the host's bound cap (<= the vertex count, so inside best[]), the
+  // scan's survivor counts.
+  const int32_t nr = st->n[round];
+  const int32_t dense_at = st->dense_at;
+  unsigned long long key[kTailPer];
+#pragma unroll
+  for (int q = 0; q < kTailPer; ++q) {
+    const int32_t c = tid + q * kTailThreads;
+    const unsigned long long k = best[c < cap ? c : 0];
+    key[q] = c < cap ? k : kKeyNone;
+  }
+  int64_t live = 0;
+  for (int32_t i0 = 0; i0 < nseg; i0 += 8 * kTailThreads) {
+    uint32_t v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int32_t i = i0 + q * kTailThreads + tid;
+      const uint32_t x = seg_cnt[i < nseg ? i : 0];  // nseg >= 1
+      v[q] = i < nseg ? x : 0u;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) live += v[q];
+  }
+  const int64_t off = st->lab_off[round];
+  int64_t added0 = 0;
+  unsigned long long total0 = 0;
+  int err0 = 0, erri0 = 0;
+  if (tid == 0) {
+    added0 = st->edges_added;
+    total0 = *total;
+    err0 = st->err;
+    erri0 = st->err_internal;
+  }
+  if (dense_at == round) return;  // the dense finish wrote this round's record
+  if (nr <= 1 && round > 0) {
+    if (tid == 0) {
+      st->n[round + 1] = 0;
+      st->lab_off[round + 1] = off;
+      HostRound h{0, err0, erri0, 0, 0, 0, added0};
+      host[round] = h;
+      __threadfence_system();
+    }
+    return;
+  }
+  if (nr > cap) {  // never: the host's bound covers n_r
+    if (tid == 0) {
+      st->err_internal = 1;
+      HostRound h{0, err0, 1, 0, 0, 0, added0};
+      host[round] = h;
+      __threadfence_system();
+    }
+    return;
+  }
+  int32_t* par = tsm;       // [nr]
+  int32_t* tgt = tsm + nr;  // [nr] far end of the minimum edge (-1: none), then the root
+#pragma unroll
+  for (int q = 0; q < kTailPer; ++q)
+    if (tid + q * kTailThreads >= nr) key[q] = kKeyNone;
+  // the records of the minimum edges of components tid, tid + 1024, ...: all
+  // loads issued (unconditionally, clamped to slot 0) before any is used
+  int32_t d[kTailPer];
+  uint32_t e[kTailPer];
+  bool bad = false;
+  if (round == 0) {
+    // the round-0 scan stored src ^ dst of every edge in the record buffer
+    const uint32_t* xends = reinterpret_cast<const uint32_t*>(rec);
+    uint32_t xv[kTailPer];
+#pragma unroll
+    for (int q = 0; q < kTailPer; ++q) xv[q] = xends[key[q] != kKeyNone ? (uint32_t)key[q] : 0u];
+#pragma unroll
+    for (int q = 0; q < kTailPer; ++q) {
+      const int32_t c = tid + q * kTailThreads;
+      e[q] = (uint32_t)key[q];
+      d[q] = key[q] != kKeyNone ? (int32_t)(xv[q] ^ (uint32_t)c) : -1;
+    }
+  } else {
+    uint2 ab[kTailPer];
+#pragma unroll
+    for (int q = 0; q < kTailPer; ++q) {
+      const uint32_t pos = key[q] != kKeyNone ? (uint32_t)key[q] : 0u;
+      ab[q] = *reinterpret_cast<const uint2*>(rec + pos);
+      e[q] = rec[pos].w;
+    }
+#pragma unroll
+    for (int q = 0; q < kTailPer; ++q) {
+      const int32_t c = tid + q * kTailThreads;
+      const int32_t u = (int32_t)ab[q].x, v = (int32_t)ab[q].y;
+      d[q] = key[q] == kKeyNone ? -1 : (u == c ? v : u);
+      if (key[q] != kKeyNone && u != c && v != c) {
+        bad = true;  // inconsistent labels: never expected, reported as a device error
+        d[q] = -1;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kTailPer; ++q) {
+    if (key[q] != kKeyNone && (uint32_t)d[q] >= (uint32_t)nr) {
+      bad = true;
+      d[q] = -1;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kTailPer; ++q) {
+    const int32_t c = tid + q * kTailThreads;
+    if (c < nr) {
+      par[c] = c;
+      tgt[c] = d[q];
+    }
+  }
+  const bool any_bad = __syncthreads_or(bad);
+  // hook; of a mutual pair (each the other's far end, so the same edge) the
+  // smaller id acts
+  uint32_t sel = 0;
+  unsigned long long wsum = 0;
+#pragma unroll
+  for (int q = 0; q < kTailPer; ++q) {
+    const int32_t c = tid + q * kTailThreads;
+    if (d[q] < 0 || (d[q] < c && tgt[d[q]] == c)) continue;
+    int32_t x = c, y = d[q];
+    while (true) {
+      const int32_t rx = walk_root(par, x);
+      const int32_t ry = walk_root(par, y);
+      if (rx == ry) break;
+      const int32_t hi = rx > ry ? rx : ry;
+      const int32_t lo = rx > ry ? ry : rx;
+      const int32_t old = atomicCAS(par + hi, hi, lo);
+      if (old == hi) {
+        in_mst[e[q]] = 1;
+        ++sel;
+        wsum += (uint32_t)(key[q] >> 32);  // the edge's weight
+        break;
+      }
+      if (hi == rx) x = old;
+      else y = old;
+    }
+  }
+  __syncthreads();
+  // roots: tgt[c] = root of c, -1 for an isolated component (no minimum
+  // edge: nothing hooked onto it and it hooked onto nothing)
+#pragma unroll
+  for (int q = 0; q < kTailPer; ++q) {
+    const int32_t c = tid + q * kTailThreads;
+    if (c < nr) tgt[c] = d[q] < 0 && par[c] == c ? -1 : walk_root(par, c);
+  }
+  __syncthreads();
+  // new labels: rank of each kept root (tgt[c] == c) in id order; thread t
+  // ranks components t * kTailPer .. t * kTailPer + kTailPer - 1, into par[]
+  int32_t mine = 0;
+#pragma unroll
+  for (int q = 0; q < kTailPer; ++q) {
+    const int32_t c = tid * kTailPer + q;
+    if (c < nr && tgt[c] == c) ++mine;
+  }
+  int32_t x = mine;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int32_t y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
+  }
+  if (lane == 63) red_a[wv] = x;
+  __syncthreads();
+  int32_t rank = x - mine, roots = 0;
+  for (int i = 0; i < kTailThreads / 64; ++i) {
+    rank += i < wv ? (int32_t)red_a[i] : 0;
+    roots += (int32_t)red_a[i];
+  }
+#pragma unroll
+  for (int q = 0; q < kTailPer; ++q) {
+    const int32_t c = tid * kTailPer + q;
+    if (c < nr && tgt[c] == c) par[c] = rank++;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kTailPer; ++q) {
+    const int32_t c = tid + q * kTailThreads;
+    if (c < nr) {
+      const int32_t r = tgt[c];
+      labpool[off + c] = r < 0 ? -1 : par[r];
+    }
+  }
+  // the next round's parent[] and best[] (n_{r+1} = roots), bucket counters
+  for (int32_t c = tid; c < roots; c += kTailThreads) {
+    parent[c] = c;
+    best[c] = kKeyNone;
+  }
+  if (btot)
+    for (int32_t i = tid; i < kMaxBuckets; i += kTailThreads) btot[i] = 0;
+  // the round's record
+  live = wave_sum(live);
+  int64_t sel64 = wave_sum((int64_t)sel);
+  wsum = wave_sum(wsum);
+  __syncthreads();  // red_a is rewritten
+  if (lane == 0) {
+    red_a[wv] = live;
+    red_b[wv] = sel64;
+    red_w[wv] = wsum;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int64_t L = 0, T = 0;
+    unsigned long long W = 0;
+    for (int i = 0; i < kTailThreads / 64; ++i) {
+      L += red_a[i];
+      T += red_b[i];
+      W += red_w[i];
+    }
+    const int erri = any_bad ? 1 : erri0;
+    st->err_internal = erri;
+    st->live[round] = L;
+    st->sel[round] = T;
+    st->edges_added = added0 + T;
+    st->n[round + 1] = roots;
+    st->lab_off[round + 1] = off + nr;
+    *total = total0 + W;
+    HostRound h{roots, err0, erri, 0, L, T, added0 + T};
+    host[round] = h;
+    __threadfence_system();
+  }
+}
+
 // ------------------------------------------------------------ launchers
 
 #define MSTX_LAUNCH_CHECK()            \
@@ -1156,6 +1451,9 @@ hipError_t configure_kernels() {
   MSTX_CFG(kModeDense, true, true);
   MSTX_CFG(kModeDense, false, true);
 #undef MSTX_CFG
+  hipError_t r4 = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_round_tail),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxDynLds);
+  if (r4 != hipSuccess) e = r4;
   hipError_t r3 = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dense_finish),
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxDynLds);
   if (r3 != hipSuccess) e = r3;
@@ -1195,10 +1493,10 @@ hipError_t launch_scan(int mode, int stage, const ScanArgs& a, int grid, size_t 
   return hipSuccess;
 }
 
-hipError_t launch_bucket_min(int round, int launched, const unsigned long long* upd_key, const uint16_t* upd_cl,
+hipError_t launch_bucket_min(int round, int launched, const unsigned long long* offers,
                              const uint32_t* offT, int32_t nseg, const uint32_t* btot, unsigned long long* best,
                              const DevState* st, int grid, size_t lds, hipStream_t s) {
-  k_bucket_min<<<grid, kScanBlock, lds + kBucketMinExtraLds, s>>>(round, launched, upd_key, upd_cl, offT, nseg, btot,
+  k_bucket_min<<<grid, kScanBlock, lds + kBucketMinExtraLds, s>>>(round, launched, offers, offT, nseg, btot,
                                                                   best, st);
   MSTX_LAUNCH_CHECK();
   return hipSuccess;
@@ -1219,6 +1517,17 @@ hipError_t launch_dense_finish(int round, int launched, const unsigned long long
   const int32_t kmax = launched_dense_limit(launched) < kDenseMax ? launched_dense_limit(launched) : kDenseMax;
   const size_t lds = dense_finish_lds(kmax);
   k_dense_finish<<<1, kDenseThreads, lds, s>>>(round, launched, pbest, seg_cnt, nseg, rec, in_mst, total, st, host);
+  MSTX_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+hipError_t launch_round_tail(int round, int32_t cap, const uint4* rec, unsigned long long* best, int32_t* parent,
+                             int32_t* labpool, const uint32_t* seg_cnt, int32_t nseg, uint8_t* in_mst,
+                             unsigned long long* total, uint32_t* btot, DevState* st, HostRound* host,
+                             hipStream_t s) {
+  const size_t lds = 8 * (size_t)(cap < 1 ? 1 : (cap > kTailMax ? kTailMax : cap));
+  k_round_tail<<<1, kTailThreads, lds, s>>>(round, cap < kTailMax ? cap : kTailMax, rec, best, parent, labpool, seg_cnt, nseg, in_mst, total, btot,
+                                            st, host);
   MSTX_LAUNCH_CHECK();
   return hipSuccess;
 }

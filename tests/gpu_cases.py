@@ -27,6 +27,7 @@ def _concat(parts, name):
 DENSE_MAX = 200  # largest component count the library's dense finish takes
 SMALL_MAX = 8192  # largest vertex count of the library's one-workgroup path
 LDS_SLOTS = 20352  # largest component count whose minima the scan keeps in LDS
+TAIL_MAX = 10240  # largest round bound whose hook .. relabel run in one workgroup
 
 
 def stats_consistent(gpu_stats, oracle_stats, limit=DENSE_MAX):

@@ -34,7 +34,7 @@ def lib():
 def test_header_declares_entry_points():
     names = declared_functions()
     for must in ("mst_solve", "mst_solve_batched", "mst_select_min_edges", "mst_workspace_bytes",
-                 "mst_set_dense_limit", "mst_set_small_limit", "mst_status_string"):
+                 "mst_set_dense_limit", "mst_set_small_limit", "mst_set_tail_limit", "mst_status_string"):
         assert must in names, names
 
 
@@ -105,6 +105,20 @@ def test_small_limit_option(lib):
         B.mst_set_small_limit(prev)
 
 
+def test_tail_limit_option(lib):
+    from paper_2005_06913_amd import binding as B
+    prev = B.mst_set_tail_limit(-1)
+    assert prev == gpu_cases.TAIL_MAX
+    try:
+        assert B.mst_set_tail_limit(10 ** 6) == prev
+        assert B.mst_set_tail_limit(-1) == gpu_cases.TAIL_MAX  # clamped
+        with B.tail_limit(0):
+            assert B.mst_set_tail_limit(-1) == 0
+        assert B.mst_set_tail_limit(-1) == gpu_cases.TAIL_MAX
+    finally:
+        B.mst_set_tail_limit(prev)
+
+
 def test_workspace_bytes(lib):
     from paper_2005_06913_amd import binding as B
     a = B.mst_workspace_bytes(1000, 8000)
@@ -121,7 +135,7 @@ def test_kernel_names(lib):
     from paper_2005_06913_amd import binding as B
     names = [lib.mst_profile_kernel_name(i).decode() for i in range(64)]
     names = [x for x in names if x]
-    assert "k_dense_finish" in names and "k_hook" in names
+    assert "k_dense_finish" in names and "k_hook" in names and "k_round_tail" in names
     assert "k_scan<3, false, true>" in names
     assert len(names) == len(set(names))
     prof = B.mst_profile_read()  # host counters only: no device call

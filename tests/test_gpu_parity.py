@@ -39,13 +39,13 @@ def to_dev(dev, src, dst, w):
             torch.from_numpy(np.ascontiguousarray(w, np.uint32)).to(dev))
 
 
-def gpu_solve(dev, n, src, dst, w, limit=gpu_cases.DENSE_MAX, small=gpu_cases.SMALL_MAX):
+def gpu_solve(dev, n, src, dst, w, limit=gpu_cases.DENSE_MAX, small=gpu_cases.SMALL_MAX, tail=gpu_cases.TAIL_MAX):
     import paper_2005_06913_amd as P
     s, d, ww = to_dev(dev, src, dst, w)
     m = len(src)
     in_mst = torch.full((m,), 7, dtype=torch.uint8, device=dev)  # garbage: must be overwritten
     total = torch.full((1,), 12345, dtype=torch.int64, device=dev).view(torch.uint64)
-    with P.dense_limit(limit), P.small_limit(small):
+    with P.dense_limit(limit), P.small_limit(small), P.tail_limit(tail):
         st = P.mst_solve(n, s, d, ww, in_mst, total)
     torch.cuda.synchronize()
     stats = P.mst_last_round_stats()
@@ -53,9 +53,10 @@ def gpu_solve(dev, n, src, dst, w, limit=gpu_cases.DENSE_MAX, small=gpu_cases.SM
 
 
 def check_against_oracle(dev, name, n, src, dst, w, stats=True, limit=gpu_cases.DENSE_MAX,
-                         small=gpu_cases.SMALL_MAX):
-    print(f"[case] {name} n={n} m={len(src)} dense_limit={limit} small_limit={small}", flush=True)
-    st, in_mst, total, gstats = gpu_solve(dev, n, src, dst, w, limit, small)
+                         small=gpu_cases.SMALL_MAX, tail=gpu_cases.TAIL_MAX):
+    print(f"[case] {name} n={n} m={len(src)} dense_limit={limit} small_limit={small} tail_limit={tail}",
+          flush=True)
+    st, in_mst, total, gstats = gpu_solve(dev, n, src, dst, w, limit, small, tail)
     k = oracle.kruskal(n, src, dst, w)
     assert st == k.status, f"{name}: status {st} != oracle {k.status}"
     assert total == k.total, f"{name}: total {total} != oracle {k.total}"
@@ -100,17 +101,23 @@ def test_min_edge_keys_golden(dev):
 
 # ------------------------------------------------------------- full solve
 
-# (dense-finish limit, small-graph limit): the defaults (graphs of at most
-# 8192 vertices take the one-workgroup path), and the per-round kernel chain
-# with the dense finish at its default, off, and starting earlier or later
-PATHS = [(gpu_cases.DENSE_MAX, gpu_cases.SMALL_MAX), (gpu_cases.DENSE_MAX, 0), (0, 0), (2, 0), (9, 0), (64, 0)]
+# (dense-finish limit, small-graph limit, round-tail limit): the defaults
+# (graphs of at most 8192 vertices take the one-workgroup path), and the
+# per-round kernel chain with the dense finish at its default, off, and
+# starting earlier or later, with late rounds closed in one workgroup or by
+# the grid-wide hook .. relabel kernels
+D, S, T = gpu_cases.DENSE_MAX, gpu_cases.SMALL_MAX, gpu_cases.TAIL_MAX
+PATHS = [(D, S, T), (D, 0, T), (D, 0, 0), (0, 0, T), (0, 0, 0), (2, 0, T), (9, 0, 0), (64, 0, T), (64, 0, 0)]
+PATH_IDS = [f"dense{a}-small{b}-tail{c}" for a, b, c in PATHS]
+FEW_PATHS = [(D, S, T), (D, 0, T), (0, 0, T), (0, 0, 0)]
+FEW_IDS = [f"dense{a}-small{b}-tail{c}" for a, b, c in FEW_PATHS]
 
 
-@pytest.mark.parametrize("limit,small", PATHS, ids=[f"dense{a}-small{b}" for a, b in PATHS])
+@pytest.mark.parametrize("limit,small,tail", PATHS, ids=PATH_IDS)
 @pytest.mark.parametrize("idx", range(len(gpu_cases.small_cases())))
-def test_solve_small(dev, idx, limit, small):
+def test_solve_small(dev, idx, limit, small, tail):
     g = gpu_cases.small_cases()[idx]
-    check_against_oracle(dev, g.name, g.n, g.src, g.dst, g.w, limit=limit, small=small)
+    check_against_oracle(dev, g.name, g.n, g.src, g.dst, g.w, limit=limit, small=small, tail=tail)
 
 
 def test_dense_finish_ends_early(dev):
@@ -134,16 +141,19 @@ def test_small_path_matches_chain(dev):
         if g.n > gpu_cases.SMALL_MAX or len(g.src) > (1 << 17):
             continue
         a = gpu_solve(dev, g.n, g.src, g.dst, g.w, small=gpu_cases.SMALL_MAX)
-        c = gpu_solve(dev, g.n, g.src, g.dst, g.w, limit=0, small=0)
-        assert a[0] == c[0] and a[2] == c[2] and np.array_equal(a[1], c[1]), g.name
+        c = gpu_solve(dev, g.n, g.src, g.dst, g.w, limit=0, small=0, tail=0)
+        t = gpu_solve(dev, g.n, g.src, g.dst, g.w, limit=0, small=0)
+        for x in (a, t):
+            assert x[0] == c[0] and x[2] == c[2] and np.array_equal(x[1], c[1]), g.name
+            assert np.array_equal(x[3], c[3]), g.name
         if a[0] == 0:
             assert np.array_equal(a[3], oracle.boruvka(g.n, g.src, g.dst, g.w).stats), g.name
 
 
-@pytest.mark.parametrize("limit,small", [(gpu_cases.DENSE_MAX, gpu_cases.SMALL_MAX), (gpu_cases.DENSE_MAX, 0), (0, 0)])
-def test_solve_golden(dev, limit, small):
+@pytest.mark.parametrize("limit,small,tail", FEW_PATHS, ids=FEW_IDS)
+def test_solve_golden(dev, limit, small, tail):
     for fx in mst_pins.all_fixtures():
-        st, in_mst, total, stats = gpu_solve(dev, fx.n, fx.src, fx.dst, fx.w, limit, small)
+        st, in_mst, total, stats = gpu_solve(dev, fx.n, fx.src, fx.dst, fx.w, limit, small, tail)
         assert st == fx.status, fx.name
         assert total == fx.total, fx.name
         assert np.array_equal(in_mst, fx.in_mst), fx.name
@@ -153,11 +163,11 @@ def test_solve_golden(dev, limit, small):
                 assert [tuple(r) for r in stats.tolist()] == fx.rounds, fx.name
 
 
-@pytest.mark.parametrize("limit,small", [(gpu_cases.DENSE_MAX, gpu_cases.SMALL_MAX), (gpu_cases.DENSE_MAX, 0), (0, 0)])
+@pytest.mark.parametrize("limit,small,tail", FEW_PATHS, ids=FEW_IDS)
 @pytest.mark.parametrize("case", gpu_cases.edge_cases(), ids=[c[0] for c in gpu_cases.edge_cases()])
-def test_solve_edge_cases(dev, case, limit, small):
+def test_solve_edge_cases(dev, case, limit, small, tail):
     name, n, src, dst, w = case
-    check_against_oracle(dev, name, n, src, dst, w, stats=False, limit=limit, small=small)
+    check_against_oracle(dev, name, n, src, dst, w, stats=False, limit=limit, small=small, tail=tail)
 
 
 def test_vertex_range_error(dev):
@@ -192,11 +202,12 @@ def test_determinism_and_reuse(dev):
 
 # ----------------------------------------------- full-size configurations
 
-@pytest.mark.parametrize("name", ["random_n1M_d16", "grid_1024x1024"])
-def test_solve_full_size(dev, name):
+@pytest.mark.parametrize("name,tail", [("random_n1M_d16", gpu_cases.TAIL_MAX), ("grid_1024x1024", gpu_cases.TAIL_MAX),
+                                       ("grid_1024x1024", 0)])
+def test_solve_full_size(dev, name, tail):
     from paper_2005_06913_amd import graphgen as G
     g = G.workload(name)
-    check_against_oracle(dev, g.name, g.n, g.src, g.dst, g.w, stats=(name == "grid_1024x1024"))
+    check_against_oracle(dev, g.name, g.n, g.src, g.dst, g.w, stats=(name == "grid_1024x1024"), tail=tail)
 
 
 def test_solve_full_size_planted(dev):
