@@ -335,7 +335,9 @@ int enqueue_scan(Solve& S, int r, int stage, int64_t bound, bool exact, hipError
   if (!exact) {
     // the actual count may be much smaller than the bound
     if (hi_mode != kModeDense && S.dense_limit > 0 && bound / 8 <= S.dense_limit) launched |= 1 << kModeDense;
-    if (hi_mode != kModeLds && hi_mode != kModeDense && bound / 8 <= kLdsSlots) launched |= 1 << kModeLds;
+    // (a skewed graph can lose far more than half its components in a round,
+    // and a launch that finds another mode chosen returns at once)
+    if (hi_mode != kModeLds && hi_mode != kModeDense && bound / 64 <= kLdsSlots) launched |= 1 << kModeLds;
     if (hi_mode == kModeGlobal && bound / 8 <= kBucketMaxComponents) launched |= 1 << kModeBucket;
   }
   if (!S.L.bucket) launched &= ~(1 << kModeBucket), launched |= (bound > kLdsSlots ? 1 << kModeGlobal : 0);
