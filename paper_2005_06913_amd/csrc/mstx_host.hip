@@ -397,15 +397,15 @@ int enqueue_scan(Solve& S, int r, int stage, int64_t bound, bool exact, hipError
       if (err != hipSuccess) return launched;
     }
     if (mode == kModeBucket) {
-      int shift, nbk;
-      bucket_geometry((int32_t)std::min<int64_t>(bound, kBucketMaxComponents), &shift, &nbk);
+      const BucketGeom bg = bucket_geometry((int32_t)std::min<int64_t>(bound, kBucketMaxComponents));
+      const int nbk = bg.nbk;
       // a smaller actual count can have more (narrower) buckets, but never more than 256
       // unless the width is at its maximum; the extra workgroups serve buckets with
       // more than twice the average offers (at most half as many again)
       const int grid_b = std::max(nbk, 256) * 3 / 2 + 1;
       const int kb = T.start(kBucketMin, r, kModeBucket);
       err = launch_bucket_min(r, launched, S.offers, S.offT, S.L.nseg, S.btot, S.best, S.st, grid_b,
-                              (size_t)8 << shift, S.s);
+                              (size_t)8 * bg.width, S.s);
       T.stop(kb);
       if (err != hipSuccess) return launched;
     }

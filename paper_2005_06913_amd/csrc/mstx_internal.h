@@ -31,8 +31,9 @@ static constexpr int kNumModes = 4;
 // asked; 1 KiB stays for the kernels' static LDS (at most 640 B today).
 static constexpr int kMaxDynLds = 160 * 1024 - 1024;
 static constexpr int32_t kLdsSlots = kMaxDynLds / 8;  // 20352 u64 minima
-// Buckets hold 2^shift components, 64 <= 2^shift <= 16384 (the LDS table of
-// k_bucket_min), at most 1023 buckets (one counter per scan thread + total).
+// Buckets hold at most 2^kMaxBucketShift = 16384 consecutive components (the
+// LDS table of k_bucket_min), at most 1023 buckets (one counter per scan
+// thread + total).
 static constexpr int kMaxBuckets = 1023;
 static constexpr int kMaxBucketShift = 14;
 static constexpr int64_t kBucketMaxComponents = (int64_t)kMaxBuckets << kMaxBucketShift;
@@ -56,13 +57,24 @@ static_assert(((uint64_t)(kSegCap - 1) << kOfferSlotShift) < (1ull << 32), "offe
 // Bytes of dynamic LDS a BUCKET-mode scan uses: offer staging + counters.
 static constexpr int kBucketScanLds = kOfferCap * 8 + (kMaxBuckets + 1) * 4;
 
-// Bucket width 2^shift >= ceil(nr / 256) (about 256 buckets, so one
-// k_bucket_min workgroup per CU) and the bucket count.
-__host__ __device__ inline void bucket_geometry(int32_t nr, int* shift, int* nbk) {
-  int s = 6;
-  while (s < kMaxBucketShift && ((int64_t)256 << s) < (int64_t)nr) ++s;
-  *shift = s;
-  *nbk = (int)(((int64_t)nr + (1 << s) - 1) >> s);
+// Buckets of width ceil(nr / 256) (at least 64, at most 16384): 256
+// buckets, one k_bucket_min workgroup per CU, unless the width is at a
+// bound.  Bucket of component c = c / width, by a multiply with a 32-bit
+// reciprocal and one correction step (c < 2^24 here).
+struct BucketGeom {
+  int32_t width;
+  int32_t nbk;
+  uint32_t magic;  // floor((2^32 - 1) / width) + 1
+};
+__host__ __device__ inline BucketGeom bucket_geometry(int32_t nr) {
+  int64_t wd = ((int64_t)nr + 255) / 256;
+  if (wd < 64) wd = 64;
+  if (wd > (1 << kMaxBucketShift)) wd = 1 << kMaxBucketShift;
+  BucketGeom g;
+  g.width = (int32_t)wd;
+  g.nbk = (int32_t)(((int64_t)nr + wd - 1) / wd);
+  g.magic = (uint32_t)(0xFFFFFFFFull / (uint64_t)wd + 1);
+  return g;
 }
 
 // Dense finish: with at most kDenseMax components left, one pass over the live

@@ -102,6 +102,13 @@ __device__ __forceinline__ void lower_lds(unsigned long long* t, int32_t c, uint
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
+// c / g.width for 0 <= c < 2^24: the reciprocal product is at most one too large
+__device__ __forceinline__ int32_t bucket_of(int32_t c, const BucketGeom& g) {
+  int32_t q = (int32_t)__umulhi((uint32_t)c, g.magic);
+  if (q * g.width > c) --q;
+  return q;
+}
+
 __device__ __forceinline__ uint64_t lanemask_lt() {
   const int l = lane_id();
   return l == 0 ? 0ull : (~0ull >> (64 - l));
@@ -201,11 +208,13 @@ __global__ void __launch_bounds__(kScanBlock) k_scan(ScanArgs A) {
 
   unsigned long long* lbest = smem;  // LDS mode
   // BUCKET mode: geometry derived from n_r exactly as k_bucket_min does
-  int shift = 0, nbk = 0;
+  BucketGeom bg{1, 0, 0};
+  int nbk = 0;
   uint32_t* bcnt = nullptr;
   unsigned long long* soff = nullptr;
   if (kMode == kModeBucket) {
-    bucket_geometry(nr, &shift, &nbk);
+    bg = bucket_geometry(nr);
+    nbk = bg.nbk;
     soff = smem;                                           // [kOfferCap]
     bcnt = reinterpret_cast<uint32_t*>(soff + kOfferCap);  // [nbk + 1]
   }
@@ -341,14 +350,17 @@ __global__ void __launch_bounds__(kScanBlock) k_scan(ScanArgs A) {
     }
 
     // BUCKET mode: claim a slot in the offer staging for both ends
+    // (slot in its bucket's run in bits 0..15, the bucket in bits 16..)
     uint32_t slot_a[kPerThread], slot_b[kPerThread];
     if (kMode == kModeBucket) {
 #pragma unroll
       for (int k = 0; k < kPerThread; ++k) {
         slot_a[k] = slot_b[k] = 0;
         if (live[k]) {
-          slot_a[k] = atomicAdd(&bcnt[(int32_t)r[k].x >> shift], 1u);
-          slot_b[k] = atomicAdd(&bcnt[(int32_t)r[k].y >> shift], 1u);
+          const uint32_t qa = (uint32_t)bucket_of((int32_t)r[k].x, bg);
+          const uint32_t qb = (uint32_t)bucket_of((int32_t)r[k].y, bg);
+          slot_a[k] = atomicAdd(&bcnt[qa], 1u) | (qa << 16);
+          slot_b[k] = atomicAdd(&bcnt[qb], 1u) | (qb << 16);
         }
       }
     }
@@ -438,13 +450,14 @@ __global__ void __launch_bounds__(kScanBlock) k_scan(ScanArgs A) {
       for (int k = 0; k < kPerThread; ++k) {
         if (live[k]) {
           const int32_t a = (int32_t)r[k].x, b = (int32_t)r[k].y;
-          const uint32_t pa = bcnt[a >> shift] + slot_a[k];
-          const uint32_t pb = bcnt[b >> shift] + slot_b[k];
+          const int32_t qa = (int32_t)(slot_a[k] >> 16), qb = (int32_t)(slot_b[k] >> 16);
+          const uint32_t pa = bcnt[qa] + (slot_a[k] & 0xFFFFu);
+          const uint32_t pb = bcnt[qb] + (slot_b[k] & 0xFFFFu);
           // the key's low half is this segment's first position plus the slot
           const uint64_t o = (key[k] & 0xFFFFFFFF00000000ull) |
                              ((uint64_t)((uint32_t)key[k] - (uint32_t)base) << kOfferSlotShift);
-          soff[pa] = o | (uint32_t)(a & ((1 << shift) - 1));
-          soff[pb] = o | (uint32_t)(b & ((1 << shift) - 1));
+          soff[pa] = o | (uint32_t)(a - qa * bg.width);
+          soff[pb] = o | (uint32_t)(b - qb * bg.width);
         }
       }
       __syncthreads();
@@ -580,9 +593,9 @@ __global__ void __launch_bounds__(kScanBlock) k_bucket_min(int round, int launch
   if (nr <= 1 && round > 0) return;
   if (round > 0 && st->err) return;  // the scan of this round did nothing either
   if (pick_mode(nr, launched) != kModeBucket) return;
-  int shift, nbk;
-  bucket_geometry(nr, &shift, &nbk);
-  const int B = 1 << shift;
+  const BucketGeom bg = bucket_geometry(nr);
+  const int nbk = bg.nbk;
+  const int B = bg.width;
   uint32_t* run_w = reinterpret_cast<uint32_t*>(table + B);  // [kChunkRuns]
   uint32_t* iprefix = run_w + kChunkRuns;                    // [kChunkRuns + 1]
   uint32_t* uprefix = iprefix + kChunkRuns + 1;              // [kMaxBuckets + 1]
@@ -690,7 +703,7 @@ __global__ void __launch_bounds__(kScanBlock) k_bucket_min(int round, int launch
     }
   }
   __syncthreads();
-  const int64_t base = (int64_t)p << shift;
+  const int64_t base = (int64_t)p * B;
   for (int i = tid; i < B; i += kScanBlock) {
     const unsigned long long v = table[i];
     if (base + i < nr && v != kKeyNone) {
@@ -707,25 +720,35 @@ static constexpr int kDenseWaves = kDenseThreads / 64;
 // Rows of the small graph are scanned by groups of adjacent lanes.
 static constexpr int kDenseRowThreads = 4;
 static_assert(kDenseMax * kDenseRowThreads <= kDenseThreads, "one lane group per row");
-static constexpr int kDenseUnroll = 8;
+static_assert(kDenseMax <= 256, "the new ids of one round are ranked by one wave");
 // The pair table is loaded two keys at a time, all loads issued first.
 static constexpr int kDenseLoadIters = (kDensePairsMax / 2 + kDenseThreads - 1) / kDenseThreads;
+// A contracted table has at most k/2 vertices, so a quarter of the entries:
+// the old entries under it, per thread.
+static constexpr int kDenseTopQ = (dense_pairs(kDenseMax / 2) + kDenseThreads - 1) / kDenseThreads;
+
+// first pair index of row i of the k-vertex table
+__device__ __forceinline__ int32_t dense_row_start(int32_t i, int32_t k) { return i * k - i * (i + 1) / 2; }
 
 // Finishes the solve on the k = n_r <= kDenseMax components of round r, one
 // workgroup: vertex u of the small graph is component u, edge {u, v} the
 // lightest original edge between them, key pbest[pair_index(u, v)] (none: no
 // edge; the key's low half is the edge index, or from round 2 on the
 // position of its record).  Boruvka again, on that graph, with everything in
-// LDS: every group of the small graph takes its lightest outgoing key (row
-// minima by lane groups, then an LDS atomicMin per group), hooks onto the
-// group at the far end (of a mutual pair the smaller id stays root), and
-// pointer jumping flattens the parents.  The keys are distinct, so the
-// selected edges are exactly the MST edges between the k components; their
-// key low halves are collected and marked in in_mst[] once at the end.
-// Records round r as the last one: n_{r+1} = 0, live_r = the surviving edges
-// counted by the scan, sel_r = the edges added here.
-// LDS: table [np] u64, group minimum [k] u64, selected key low halves [k] u32,
-// parent [k] u16, target group [k] u16 (dense_finish_lds(k) bytes).
+// LDS, contracting the graph after every round:
+//   * every vertex takes its lightest key (row minimum, lane groups of 4);
+//   * it hooks onto the vertex at the far end, except the smaller of a mutual
+//     pair (both hold the same key, added once); pointer jumping flattens;
+//   * the roots get new ids 0..k'-1 in id order, and the table is rebuilt for
+//     the k' new vertices: entry {A, B} = minimum over the old entries whose
+//     ends went to A and B (read into registers first, then LDS atomicMin
+//     into the smaller table, which overlaps the old one).
+// The keys are distinct, so the selected edges are exactly the MST edges
+// between the k components; their key low halves are collected and marked in
+// in_mst[] once at the end.  Records round r as the last one: n_{r+1} = 0,
+// live_r = the surviving edges counted by the scan, sel_r = the edges added.
+// LDS: table [np] u64, row minimum [k] u64, added key low halves [k] u32,
+// parent [k] u16, target / new id [k] u16 (dense_finish_lds(k) bytes).
 __global__ void __launch_bounds__(kDenseThreads) k_dense_finish(int round, int launched,
                                                                const unsigned long long* __restrict__ pbest,
                                                                const uint32_t* __restrict__ seg_cnt, int32_t nseg,
@@ -737,21 +760,42 @@ __global__ void __launch_bounds__(kDenseThreads) k_dense_finish(int round, int l
   __shared__ int64_t red_n[kDenseWaves];
   __shared__ int64_t red_l[kDenseWaves];
   __shared__ uint32_t nsel;
-  const int32_t k = st->n[round];
-  if (k <= 1 && round > 0) return;
-  if (round > 0 && st->err) return;
-  if (pick_mode(k, launched) != kModeDense) return;
+  __shared__ int32_t knext;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int32_t np = dense_pairs(k);
-  unsigned long long* tab = dsm;                                    // [np]
-  unsigned long long* gbest = tab + np;                             // [k] lightest key leaving group g (g a root)
-  uint32_t* selpos = reinterpret_cast<uint32_t*>(gbest + k);        // [k] low halves of the added keys
-  uint16_t* par = reinterpret_cast<uint16_t*>(selpos + k);          // [k]
-  uint16_t* tgt = par + k;                                          // [k] group at the far end of gbest[g]
+  // reads that depend on nothing else first: the scan's survivor counts and
+  // the state tid 0 updates at the end
+  int64_t live = 0;
+  for (int32_t i0 = 0; i0 < nseg; i0 += 8 * kDenseThreads) {
+    uint32_t v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int32_t i = i0 + q * kDenseThreads + tid;
+      const uint32_t x = seg_cnt[i < nseg ? i : 0];  // nseg >= 1
+      v[q] = i < nseg ? x : 0u;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) live += v[q];
+  }
+  int64_t added0 = 0;
+  unsigned long long total0 = 0;
+  if (tid == 0) {
+    added0 = st->edges_added;
+    total0 = *total;
+  }
+  const int32_t k0 = st->n[round];
+  if (k0 <= 1 && round > 0) return;
+  if (round > 0 && st->err) return;
+  if (pick_mode(k0, launched) != kModeDense) return;
+  const int32_t np0 = dense_pairs(k0);
+  unsigned long long* tab = dsm;                                // [np0]
+  unsigned long long* gbest = tab + np0;                        // [k0] row minimum
+  uint32_t* selpos = reinterpret_cast<uint32_t*>(gbest + k0);   // [k0] low halves of the added keys
+  uint16_t* par = reinterpret_cast<uint16_t*>(selpos + k0);     // [k0]
+  uint16_t* tgt = par + k0;                                     // [k0] far end of the row minimum, then new id
   {
     // pbest holds kDensePairsMax keys (256-byte aligned): the clamped loads stay inside
     const ulonglong2* p2 = reinterpret_cast<const ulonglong2*>(pbest);
-    const int32_t nq = np >> 1;
+    const int32_t nq = np0 >> 1;
     ulonglong2 v[kDenseLoadIters];
 #pragma unroll
     for (int q = 0; q < kDenseLoadIters; ++q) {
@@ -766,52 +810,41 @@ __global__ void __launch_bounds__(kDenseThreads) k_dense_finish(int round, int l
         tab[2 * i + 1] = v[q].y;
       }
     }
-    if ((np & 1) && tid == 0) tab[np - 1] = pbest[np - 1];
+    if ((np0 & 1) && tid == 0) tab[np0 - 1] = pbest[np0 - 1];
   }
-  for (int32_t v = tid; v < k; v += kDenseThreads) par[v] = (uint16_t)v;
   if (tid == 0) nsel = 0;
   unsigned long long wsum = 0;
   int64_t added = 0;
   const int32_t u = tid / kDenseRowThreads;
   const int sub = tid % kDenseRowThreads;
+  int32_t k = k0;
   __syncthreads();
   for (;;) {
-    for (int32_t v = tid; v < k; v += kDenseThreads) gbest[v] = kKeyNone;
-    __syncthreads();
-    // row u: entries {v, u} for v < u lie in earlier rows, {u, v} for v > u
-    // in row u itself; lane `sub` of the group takes v = sub, sub + 4, ...
-    // (kDenseUnroll columns per step with every LDS read issued before the
-    // compares; for v = u the index may name another pair, or is clamped to 0,
-    // and par[u] == gu drops it)
+    // row u: entries {v, u} for v < u at row_start(v) + u - v - 1 (the
+    // start advances by 4k - 4v - 10 from v to v + 4), {u, v} for v > u at
+    // row_start(u) + v - u - 1; lane `sub` takes v = sub, sub + 4, ...
     unsigned long long best = kKeyNone;
-    int32_t arg = 0, gu = 0;
+    int32_t arg = 0;
     if (u < k) {
-      gu = par[u];
-      int32_t v0 = sub;
-      for (; v0 + (kDenseUnroll - 1) * kDenseRowThreads < k; v0 += kDenseUnroll * kDenseRowThreads) {
-        int32_t pv[kDenseUnroll];
-        unsigned long long key[kDenseUnroll];
-#pragma unroll
-        for (int q = 0; q < kDenseUnroll; ++q) {
-          const int32_t v = v0 + q * kDenseRowThreads;
-          pv[q] = par[v];
-          key[q] = tab[max(pair_index(min(u, v), max(u, v), k), 0)];
+      int32_t v = sub;
+      int32_t rs = dense_row_start(sub, k);
+#pragma unroll 4
+      for (; v < u; v += kDenseRowThreads) {
+        const unsigned long long key = tab[rs + u - v - 1];
+        if (key < best) {
+          best = key;
+          arg = v;
         }
-#pragma unroll
-        for (int q = 0; q < kDenseUnroll; ++q) {
-          if (pv[q] != gu && key[q] < best) {
-            best = key[q];
-            arg = v0 + q * kDenseRowThreads;
-          }
-        }
+        rs += kDenseRowThreads * (k - v) - 10;
       }
-      for (int32_t v = v0; v < k; v += kDenseRowThreads) {
-        if (par[v] != gu) {
-          const unsigned long long key = tab[pair_index(min(u, v), max(u, v), k)];
-          if (key < best) {
-            best = key;
-            arg = v;
-          }
+      if (v == u) v += kDenseRowThreads;
+      const int32_t base = dense_row_start(u, k) - u - 1;
+#pragma unroll 4
+      for (; v < k; v += kDenseRowThreads) {
+        const unsigned long long key = tab[base + v];
+        if (key < best) {
+          best = key;
+          arg = v;
         }
       }
     }
@@ -824,20 +857,20 @@ __global__ void __launch_bounds__(kDenseThreads) k_dense_finish(int round, int l
         arg = oa;
       }
     }
-    const bool has = sub == 0 && best != kKeyNone;
-    if (has) atomicMin(&gbest[gu], best);
-    if (!__syncthreads_or(has)) break;  // no edge between different groups is left
-    // the row that holds a group's minimum names the group at its far end
-    if (has && best == gbest[gu]) tgt[gu] = par[arg];
-    __syncthreads();
-    // hook: group g onto tgt[g], except the smaller group of a mutual pair
-    // (both then hold the same key, which is added once)
+    const bool head = sub == 0 && u < k;
+    if (head) {
+      gbest[u] = best;
+      tgt[u] = (uint16_t)arg;
+      par[u] = (uint16_t)u;
+    }
+    if (!__syncthreads_or(head && best != kKeyNone)) break;  // no edge is left
+    // hook: vertex g onto tgt[g], except the smaller vertex of a mutual pair
     for (int32_t g = tid; g < k; g += kDenseThreads) {
-      if (par[g] == g && gbest[g] != kKeyNone) {
+      const unsigned long long key = gbest[g];
+      if (key != kKeyNone) {
         const int32_t t = tgt[g];
         if (!(tgt[t] == g && g < t)) {
           par[g] = (uint16_t)t;
-          const unsigned long long key = gbest[g];
           selpos[atomicAdd(&nsel, 1u)] = (uint32_t)key;
           wsum += key >> 32;
           ++added;
@@ -857,6 +890,71 @@ __global__ void __launch_bounds__(kDenseThreads) k_dense_finish(int round, int l
       }
       if (!__syncthreads_or(changed)) break;
     }
+    // new ids of the roots that have an edge, in id order (one wave; k <=
+    // 256).  A root without one is a vertex with no edge at all: it is done
+    // and leaves the table, so k' <= k / 2.
+    if (wv == 0) {
+      int32_t nroots = 0;
+      for (int32_t c0 = 0; c0 < k; c0 += 64) {
+        const int32_t v = c0 + lane;
+        const bool root = v < k && par[v] == v && gbest[v] != kKeyNone;
+        const uint64_t mask = __ballot(root);
+        if (root) tgt[v] = (uint16_t)(nroots + __popcll(mask & lanemask_lt()));
+        nroots += __popcll(mask);
+      }
+      if (lane == 0) knext = nroots;
+    }
+    __syncthreads();
+    const int32_t kn = knext;
+    if (kn <= 1) break;
+    // contraction: entry {i, j} (an edge: neither end is done) goes to
+    // {A, B}, the new ids of the roots of i and j, unless A = B.  The new
+    // table takes the top of the old one, [top, np): those old entries are
+    // read into registers first, the ones below top straight from LDS after.
+    const int32_t np = dense_pairs(k), npn = dense_pairs(kn), top = np - npn;
+    auto new_index = [&](int32_t idx) -> int32_t {
+      // row i of entry idx: the root of the quadratic, corrected by one step
+      const float t = (float)(2 * k - 1);
+      int32_t i = (int32_t)floorf((t - sqrtf(t * t - 8.0f * (float)idx)) * 0.5f);
+      i = i < 0 ? 0 : i;
+      if (dense_row_start(i, k) > idx) --i;
+      if (dense_row_start(i + 1, k) <= idx) ++i;
+      const int32_t j = idx - dense_row_start(i, k) + i + 1;
+      const int32_t A = tgt[par[i]], B = tgt[par[j]];
+      return A == B ? -1 : pair_index(A < B ? A : B, A < B ? B : A, kn);
+    };
+    unsigned long long ck[kDenseTopQ];
+    int32_t ci[kDenseTopQ];
+#pragma unroll
+    for (int q = 0; q < kDenseTopQ; ++q) {
+      const int32_t idx = top + q * kDenseThreads + tid;
+      ck[q] = kKeyNone;
+      ci[q] = -1;
+      if (idx < np) {
+        const unsigned long long key = tab[idx];
+        if (key != kKeyNone) {
+          ci[q] = new_index(idx);
+          ck[q] = key;
+        }
+      }
+    }
+    __syncthreads();  // the top of the old table is in registers
+    unsigned long long* ntab = tab + top;
+    for (int32_t i = tid; i < npn; i += kDenseThreads) ntab[i] = kKeyNone;
+    __syncthreads();
+    for (int32_t idx = tid; idx < top; idx += kDenseThreads) {
+      const unsigned long long key = tab[idx];
+      if (key != kKeyNone) {
+        const int32_t ni = new_index(idx);
+        if (ni >= 0) atomicMin(&ntab[ni], key);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kDenseTopQ; ++q)
+      if (ci[q] >= 0) atomicMin(&ntab[ci[q]], ck[q]);
+    tab = ntab;
+    k = kn;
+    __syncthreads();
   }
   // from round 2 on the key holds the record's position (the dense scan moves
   // no record), before that the edge index
@@ -865,8 +963,6 @@ __global__ void __launch_bounds__(kDenseThreads) k_dense_finish(int round, int l
     const uint32_t x = selpos[i];
     in_mst[round >= 2 ? rec[x].w : x] = 1;
   }
-  int64_t live = 0;
-  for (int32_t i = tid; i < nseg; i += kDenseThreads) live += seg_cnt[i];
   for (int off = 32; off > 0; off >>= 1) {
     wsum += __shfl_xor(wsum, off, 64);
     added += __shfl_xor(added, off, 64);
@@ -886,14 +982,14 @@ __global__ void __launch_bounds__(kDenseThreads) k_dense_finish(int round, int l
       A += red_n[i];
       Lv += red_l[i];
     }
-    *total += W;
+    *total = total0 + W;
     st->live[round] = Lv;
     st->sel[round] = A;
-    st->edges_added += A;
+    st->edges_added = added0 + A;
     st->n[round + 1] = 0;
     st->lab_off[round + 1] = st->lab_off[round];
     st->dense_at = round;
-    HostRound h{0, st->err, st->err_internal, 1, Lv, A, st->edges_added};
+    HostRound h{0, st->err, st->err_internal, 1, Lv, A, added0 + A};
     host[round] = h;
     __threadfence_system();
   }
