@@ -153,7 +153,11 @@ int acquire(DeviceCache*& dc, std::unique_lock<std::mutex>& lock, size_t bytes, 
   lock = std::unique_lock<std::mutex>(dc->mu);
   if (!dc->configured) {
     HIP_OK(hipHostMalloc((void**)&dc->host_rounds, sizeof(HostRound) * (kMaxRounds + 1), hipHostMallocDefault));
-    for (int i = 0; i <= kMaxRounds; ++i) HIP_OK(hipEventCreateWithFlags(&dc->round_ev[i], hipEventDisableTiming));
+    // The round events carry no system-scope fence (a cache write-back per
+    // round): the kernel that writes a round's record publishes it itself
+    // with a system-scope fence, and the host checks that it is there.
+    for (int i = 0; i <= kMaxRounds; ++i)
+      HIP_OK(hipEventCreateWithFlags(&dc->round_ev[i], hipEventDisableTiming | hipEventDisableSystemFence));
     hipDeviceProp_t prop;
     HIP_OK(hipGetDeviceProperties(&prop, dev));
     dc->cus = prop.multiProcessorCount;
@@ -450,6 +454,23 @@ hipError_t enqueue_round(Solve& S, int r, int64_t bound, int64_t n_prev = 0) {
   return hipEventRecord(S.dc->round_ev[r], S.s);
 }
 
+// A round record as the device left it in pinned host memory (read through
+// volatile accesses: the device writes it behind the compiler's back).
+constexpr int32_t kRecordPending = -2;
+HostRound load_record(const HostRound* p) {
+  const volatile HostRound* v = p;
+  HostRound h;
+  h.n_next = v->n_next;
+  h.err = v->err;
+  h.err_internal = v->err_internal;
+  h.dense = v->dense;
+  h.live = v->live;
+  h.sel = v->sel;
+  h.edges_added = v->edges_added;
+  std::atomic_thread_fence(std::memory_order_acquire);
+  return h;
+}
+
 // The round loop of one graph (n >= 1, m >= 1) on a workspace of at least
 // plan(n, m).bytes; the device cache is locked by the caller.
 int solve_locked(DeviceCache* dc, const Layout& L, int32_t n, int64_t m, const int32_t* src, const int32_t* dst,
@@ -493,6 +514,9 @@ int solve_locked(DeviceCache* dc, const Layout& L, int32_t n, int64_t m, const i
   HIP_OK(hipMemsetAsync(in_mst, 0, (size_t)m, s));
   HIP_OK(hipMemsetAsync(total, 0, sizeof(uint64_t), s));
   HIP_OK(launch_init(n, S.best, S.parent, S.dense_limit > 0 ? S.pbest : nullptr, S.btot, S.st, grid_for(n), s));
+  // every record reads "pending" until the device writes it
+  for (int r = 0; r <= kMaxRounds; ++r) dc->host_rounds[r].n_next = kRecordPending;
+  std::atomic_thread_fence(std::memory_order_seq_cst);
   HIP_OK(enqueue_round(S, 0, n));
 
   int status = MSTX_ERR_DEVICE;  // until the loop decides
@@ -512,7 +536,13 @@ int solve_locked(DeviceCache* dc, const Layout& L, int32_t n, int64_t m, const i
     }
     if (r_enq < r) break;  // never: the round before was final (status stays MSTX_ERR_DEVICE)
     HIP_OK(hipEventSynchronize(dc->round_ev[r]));
-    const HostRound M = dc->host_rounds[r];
+    HostRound M = load_record(dc->host_rounds + r);
+    if (M.n_next == kRecordPending) {
+      // not visible yet: wait for the whole stream, then it must be
+      HIP_OK(hipStreamSynchronize(s));
+      M = load_record(dc->host_rounds + r);
+      if (M.n_next == kRecordPending) break;  // status stays MSTX_ERR_DEVICE
+    }
     rounds = r + 1;
     if (r == 0 && M.err) {
       status = MSTX_ERR_VERTEX_RANGE;
