@@ -46,6 +46,11 @@ __device__ __forceinline__ int32_t small_root(int32_t* par, int32_t x) {
   return x;
 }
 
+__device__ __forceinline__ uint32_t small_wave_sum(uint32_t v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
 // One workgroup per graph of `glist` (graphs with n <= kSmallN).  LDS holds
 // best[n] (u64 minimum key per component root), comp[n] (round-start root of
 // each vertex) and par[n] (union-find over the roots during hooking), and the
@@ -95,10 +100,28 @@ __global__ void __launch_bounds__(kSmallBlock) k_small_solve(const int32_t* __re
   int32_t* cdst = csrc + m;
   uint32_t* cw = reinterpret_cast<uint32_t*>(cdst + m);
   if (cached) {
-    for (int64_t j = tid; j < m; j += kSmallBlock) {
-      csrc[j] = src[e0 + j];
-      cdst[j] = dst[e0 + j];
-      cw[j] = w[e0 + j];
+    // eight edges per thread in flight at a time (loads clamped to edge 0,
+    // the graph has one when m > 0, then stored for the edges that exist)
+    for (int64_t j0 = 0; j0 < m; j0 += 8 * kSmallBlock) {
+      int32_t a[8], b[8];
+      uint32_t c[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int64_t j = j0 + q * kSmallBlock + tid;
+        const int64_t jc = j < m ? j : 0;
+        a[q] = src[e0 + jc];
+        b[q] = dst[e0 + jc];
+        c[q] = w[e0 + jc];
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int64_t j = j0 + q * kSmallBlock + tid;
+        if (j < m) {
+          csrc[j] = a[q];
+          cdst[j] = b[q];
+          cw[j] = c[q];
+        }
+      }
     }
   }
   const int32_t* esrc = cached ? csrc : src + e0;
@@ -137,7 +160,12 @@ __global__ void __launch_bounds__(kSmallBlock) k_small_solve(const int32_t* __re
       if (key < sbest[a]) atomicMin(sbest + a, key);
       if (key < sbest[b]) atomicMin(sbest + b, key);
     }
-    if (stats && live) atomicAdd(&round_live, live);
+    // round counters: one LDS atomic per wave (1024 same-address atomics
+    // would serialise)
+    if (stats) {
+      live = small_wave_sum(live);
+      if ((tid & 63) == 0 && live) atomicAdd(&round_live, live);
+    }
     __syncthreads();
     // hooking: every root with a minimum unites with the other end's root
     uint32_t sel = 0, nonisolated = 0;
@@ -168,9 +196,13 @@ __global__ void __launch_bounds__(kSmallBlock) k_small_solve(const int32_t* __re
         else y = old;
       }
     }
-    if (sel) atomicAdd(&round_sel, sel);
-    if (stats && nonisolated) atomicAdd(&round_nonisolated, nonisolated);
     my_cnt += sel;
+    sel = small_wave_sum(sel);
+    if ((tid & 63) == 0 && sel) atomicAdd(&round_sel, sel);
+    if (stats) {
+      nonisolated = small_wave_sum(nonisolated);
+      if ((tid & 63) == 0 && nonisolated) atomicAdd(&round_nonisolated, nonisolated);
+    }
     __syncthreads();
     if (stats && tid == 0 && (round == 0 || n_round > 1) && !bad) {
       // a row for every round the single-graph path would run
