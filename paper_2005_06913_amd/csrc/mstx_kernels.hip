@@ -1127,7 +1127,9 @@ __global__ void __launch_bounds__(kBlock) k_compress(int round, int32_t* parent,
 // rootpre, W = ceil(n_r / 64); n_{r+1} = total.  Reduces this round's
 // per-block partials: live edges (part_live[0..nlive)), edges added and
 // their weight (part_sel / part_w [0..nhook)); adds the weight to *total;
-// writes the round's record for the host (pinned host memory).
+// writes the round's record for the host (pinned host memory).  The
+// partials are read first, several per thread in flight; the counts are
+// scanned 16 consecutive words per thread (four 16-byte loads) per pass.
 __global__ void __launch_bounds__(1024) k_finalize(int round, const int32_t* __restrict__ rootcnt,
                                                    int32_t* __restrict__ rootpre,
                                                    const uint32_t* __restrict__ part_live, int32_t nlive,
@@ -1139,6 +1141,40 @@ __global__ void __launch_bounds__(1024) k_finalize(int round, const int32_t* __r
   __shared__ unsigned long long shw[16];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
+  // partials (nlive >= 1 and nhook >= 1: clamped reads stay inside)
+  int64_t live = 0, sel = 0;
+  unsigned long long ws = 0;
+  for (int32_t i0 = 0; i0 < nlive; i0 += 8 * 1024) {
+    uint32_t v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int32_t i = i0 + q * 1024 + tid;
+      const uint32_t x = part_live[i < nlive ? i : 0];
+      v[q] = i < nlive ? x : 0u;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) live += v[q];
+  }
+  for (int32_t i0 = 0; i0 < nhook; i0 += 4 * 1024) {
+    uint32_t c[4];
+    unsigned long long x[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int32_t i = i0 + q * 1024 + tid;
+      const int32_t ic = i < nhook ? i : 0;
+      c[q] = part_sel[ic];
+      x[q] = part_w[ic];
+      if (i >= nhook) {
+        c[q] = 0;
+        x[q] = 0;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      sel += c[q];
+      ws += x[q];
+    }
+  }
   const int32_t nr = st->n[round];
   if (st->dense_at == round) return;  // the dense finish wrote this round's record
   if (nr <= 1 && round > 0) {
@@ -1151,24 +1187,28 @@ __global__ void __launch_bounds__(1024) k_finalize(int round, const int32_t* __r
     }
     return;
   }
-  // tiles of 1024 x 4 words: one int4 per thread, block-wide exclusive scan, carry
+  // passes of 1024 x 16 words: exclusive scan with a carry
   const int32_t W = (nr + 63) >> 6;
   int64_t carry = 0;
-  for (int32_t t0 = 0; t0 < W; t0 += 4096) {
-    const int32_t g = t0 + 4 * tid;
-    int32_t v0 = 0, v1 = 0, v2 = 0, v3 = 0;
-    if (g + 3 < W) {
-      const int4 q = *reinterpret_cast<const int4*>(rootcnt + g);
-      v0 = q.x;
-      v1 = q.y;
-      v2 = q.z;
-      v3 = q.w;
+  for (int32_t t0 = 0; t0 < W; t0 += 16 * 1024) {
+    const int32_t g0 = t0 + 16 * tid;
+    int32_t v[16];
+    if (g0 + 15 < W) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int4 q = *reinterpret_cast<const int4*>(rootcnt + g0 + 4 * k);
+        v[4 * k] = q.x;
+        v[4 * k + 1] = q.y;
+        v[4 * k + 2] = q.z;
+        v[4 * k + 3] = q.w;
+      }
     } else {
-      if (g + 0 < W) v0 = rootcnt[g + 0];
-      if (g + 1 < W) v1 = rootcnt[g + 1];
-      if (g + 2 < W) v2 = rootcnt[g + 2];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) v[k] = g0 + k < W ? rootcnt[g0 + k] : 0;
     }
-    const int64_t mine = (int64_t)v0 + v1 + v2 + v3;
+    int64_t mine = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) mine += v[k];
     int64_t x = mine;
     for (int off = 1; off < 64; off <<= 1) {
       const int64_t y = __shfl_up(x, off, 64);
@@ -1181,27 +1221,27 @@ __global__ void __launch_bounds__(1024) k_finalize(int round, const int32_t* __r
       wave_base += (i < wv) ? sh[i] : 0;
       tile_tot += sh[i];
     }
-    const int64_t e0 = carry + wave_base + x - mine;
-    const int32_t p0 = (int32_t)e0, p1 = (int32_t)(e0 + v0), p2 = (int32_t)(e0 + v0 + v1),
-                  p3 = (int32_t)(e0 + v0 + v1 + v2);
-    if (g + 3 < W) {
-      *reinterpret_cast<int4*>(rootpre + g) = make_int4(p0, p1, p2, p3);
+    int64_t e = carry + wave_base + x - mine;
+    int32_t pre[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      pre[k] = (int32_t)e;
+      e += v[k];
+    }
+    if (g0 + 15 < W) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        *reinterpret_cast<int4*>(rootpre + g0 + 4 * k) = make_int4(pre[4 * k], pre[4 * k + 1], pre[4 * k + 2],
+                                                                     pre[4 * k + 3]);
     } else {
-      if (g + 0 < W) rootpre[g + 0] = p0;
-      if (g + 1 < W) rootpre[g + 1] = p1;
-      if (g + 2 < W) rootpre[g + 2] = p2;
+#pragma unroll
+      for (int k = 0; k < 16; ++k)
+        if (g0 + k < W) rootpre[g0 + k] = pre[k];
     }
     carry += tile_tot;
-    __syncthreads();  // sh[] is rewritten by the next tile
+    __syncthreads();  // sh[] is rewritten by the next pass
   }
   const int64_t total_roots = carry;
-  int64_t live = 0, sel = 0;
-  unsigned long long ws = 0;
-  for (int32_t i = tid; i < nlive; i += 1024) live += part_live[i];
-  for (int32_t i = tid; i < nhook; i += 1024) {
-    sel += part_sel[i];
-    ws += part_w[i];
-  }
   live = wave_sum(live);
   sel = wave_sum(sel);
   ws = wave_sum(ws);
