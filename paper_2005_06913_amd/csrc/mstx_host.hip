@@ -340,8 +340,13 @@ int enqueue_scan(Solve& S, int r, int stage, int64_t bound, bool exact, hipError
     // the actual count may be much smaller than the bound
     if (hi_mode != kModeDense && S.dense_limit > 0 && bound / 8 <= S.dense_limit) launched |= 1 << kModeDense;
     // (a skewed graph can lose far more than half its components in a round,
-    // and a launch that finds another mode chosen returns at once)
-    if (hi_mode != kModeLds && hi_mode != kModeDense && bound / 64 <= kLdsSlots) launched |= 1 << kModeLds;
+    // and a launch that finds another mode chosen returns at once.  Round 1
+    // is covered for an 8-fold drop only: on random and grid graphs the first
+    // round leaves about a quarter of the vertices and the extra launch would
+    // return every time; a graph that falls further still takes bucket mode,
+    // correct, for that one round)
+    const int64_t drop = stage == 1 ? 8 : 64;
+    if (hi_mode != kModeLds && hi_mode != kModeDense && bound / drop <= kLdsSlots) launched |= 1 << kModeLds;
     if (hi_mode == kModeGlobal && bound / 8 <= kBucketMaxComponents) launched |= 1 << kModeBucket;
   }
   if (!S.L.bucket) launched &= ~(1 << kModeBucket), launched |= (bound > kLdsSlots ? 1 << kModeGlobal : 0);
