@@ -20,11 +20,13 @@
 //                       cycle with a lighter one);
 //               LDS     n_r fits one workgroup's LDS: per-workgroup minima
 //                       with ds_min_u64, flushed once to HBM;
-//               BUCKET  components are split into <= 1024 contiguous
-//                       buckets; the scan counting-sorts its (component,
-//                       key) offers by bucket in LDS and writes them out;
-//                       k_bucket_min (one workgroup per bucket) takes the
-//                       minima in LDS and writes best[] -- no global atomics;
+//               BUCKET  components are split into 256 (at most 1023)
+//                       buckets of consecutive components; the scan
+//                       counting-sorts its 8-byte offers (weight, slot in
+//                       the segment, component in the bucket) by bucket in
+//                       LDS and writes them out; k_bucket_min (a workgroup
+//                       per bucket, more for a heavy one) takes the minima
+//                       in LDS and writes best[];
 //               GLOBAL  filtered 64-bit atomicMin on best[] (very large n_r).
 //   hook      every component with a minimum: CAS the larger root's parent
 //             to the smaller root; the winner marks the edge.
@@ -33,6 +35,8 @@
 //   finalize  one workgroup: exclusive scan of the root counts (dense new
 //             labels), per-round totals, a small record for the host.
 //   relabel   old label -> new label map; reset parent[] and the minima.
+//   (round tail: when the round has few components, hook .. relabel run in
+//   one workgroup with the parent forest in LDS, k_round_tail.)
 //
 // Layout: vertex state is structure-of-arrays in HBM.  The edge stream of
 // round 0 is the caller's src/dst/w arrays; from round 1 on it is a record
