@@ -21,6 +21,7 @@ from .binding import (  # noqa: F401
     Solution,
     dense_limit,
     load_library,
+    mid_limit,
     small_limit,
     tail_limit,
     mst_batched_workspace_bytes,
@@ -29,6 +30,7 @@ from .binding import (  # noqa: F401
     mst_profile_read,
     mst_select_min_edges,
     mst_set_dense_limit,
+    mst_set_mid_limit,
     mst_set_small_limit,
     mst_set_tail_limit,
     mst_solve,

@@ -27,7 +27,7 @@ MSTX_ERR_DEVICE = -5
 EXPORTS = ("mst_solve", "mst_solve_batched", "mst_batched_workspace_bytes", "mst_select_min_edges",
            "mst_last_round_stats", "mst_workspace_bytes", "mst_status_string", "mst_profile_enable",
            "mst_profile_read", "mst_profile_kernel_name", "mst_workspace_release", "mst_set_dense_limit", "mst_set_small_limit",
-           "mst_set_tail_limit")
+           "mst_set_tail_limit", "mst_set_mid_limit")
 
 _lib = None
 
@@ -74,6 +74,8 @@ def load_library(path: str = LIB_PATH):
     lib.mst_set_small_limit.restype = ctypes.c_int32
     lib.mst_set_tail_limit.argtypes = [ctypes.c_int32]
     lib.mst_set_tail_limit.restype = ctypes.c_int32
+    lib.mst_set_mid_limit.argtypes = [ctypes.c_int32]
+    lib.mst_set_mid_limit.restype = ctypes.c_int32
     lib.mst_profile_kernel_name.argtypes = [ctypes.c_int]
     lib.mst_profile_kernel_name.restype = ctypes.c_char_p
     _lib = lib
@@ -124,6 +126,31 @@ def mst_set_tail_limit(limit: int) -> int:
     one workgroup (0: off, clamped to 10240; negative: query).  Returns the
     previous limit."""
     return int(load_library().mst_set_tail_limit(int(limit)))
+
+
+def mst_set_mid_limit(limit: int) -> int:
+    """Set the vertex count up to which mst_solve_batched solves a graph above
+    8192 vertices (and with at most 2^21 edges) with one workgroup instead of in
+    a disjoint-union chunk (at most 8192: off, clamped to 16280; negative:
+    query).  Returns the previous limit."""
+    return int(load_library().mst_set_mid_limit(int(limit)))
+
+
+class mid_limit:
+    """Context manager: ``with mid_limit(0): ...`` solves every batched graph above
+    8192 vertices in disjoint-union chunks."""
+
+    def __init__(self, limit: int):
+        self.limit = limit
+        self.prev = None
+
+    def __enter__(self):
+        self.prev = mst_set_mid_limit(self.limit)
+        return self
+
+    def __exit__(self, *exc):
+        mst_set_mid_limit(self.prev)
+        return False
 
 
 class tail_limit:

@@ -2,13 +2,16 @@
 //
 // The minimum spanning forest of a disjoint union of graphs is the union of
 // their forests, and Boruvka never merges components of different graphs, so
-// a batch is solved in two parts:
+// a batch is solved in three parts:
 //
 //   * graphs with at most kSmallN vertices: one workgroup per graph runs every
 //     Boruvka round of Section 2.1 with the vertex state in LDS (component of
 //     each vertex, union-find parents, minimum keys); rounds are separated by
 //     workgroup barriers only, so thousands of small graphs proceed
 //     independently and in parallel;
+//   * graphs with up to kMidN vertices and kMidMaxEdges edges: one workgroup
+//     per graph as well, 10 bytes of LDS per vertex (minimum key and a 2-byte
+//     union-find), the edges streamed from memory every round;
 //   * larger graphs: gathered into chunks that are solved as one disjoint
 //     union by the single-graph round kernels (k_gather renumbers vertices and
 //     edges into the union, k_graph_epilogue scatters the flags back and sums
@@ -250,6 +253,271 @@ __global__ void __launch_bounds__(kSmallBlock) k_small_solve(const int32_t* __re
   }
 }
 
+// ---------------------------------------------------------------- mid-size
+
+static constexpr int kMidBlock = 1024;
+static constexpr int kMidUnroll = 8;      // edges per thread with loads in flight
+static constexpr int kMidPerThread = 16;  // vertices per thread (registers)
+static_assert(kMidN <= kMidPerThread * kMidBlock, "every vertex has a register slot");
+static_assert(kMidN < 65536, "vertex ids fit the 2-byte union-find");
+
+// The union-find of a mid-size graph: one u16 per vertex in LDS.  At the
+// start of a round it is flat (P[v] = root of v's component, P[root] = root);
+// hooking changes only roots' entries (CAS of the larger root to the
+// smaller); path halving writes only ancestors into non-roots.
+__device__ __forceinline__ int32_t p_load(const uint16_t* P, int32_t x) {
+  return __hip_atomic_load(P + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ int32_t p_root(uint16_t* P, int32_t x) {
+  int32_t p = p_load(P, x);
+  while (p != x) {
+    const int32_t gp = p_load(P, p);
+    if (gp == p) return p;
+    __hip_atomic_store(P + x, (uint16_t)gp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    x = gp;
+    p = p_load(P, x);
+  }
+  return x;
+}
+// P[hi]: hi -> lo by a compare-and-swap of the 32-bit word holding it (LDS has
+// no 16-bit CAS).  Returns hi on success, else the value P[hi] holds (a
+// smaller ancestor).  A failure caused by the other half of the word, which
+// only ever decreases, is retried.
+__device__ __forceinline__ int32_t p_cas(uint16_t* P, int32_t hi, int32_t lo) {
+  uint32_t* word = reinterpret_cast<uint32_t*>(P) + (hi >> 1);
+  const int sh = (hi & 1) * 16;
+  uint32_t cur = __hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  while (true) {
+    const int32_t h = (int32_t)((cur >> sh) & 0xFFFFu);
+    if (h != hi) return h;
+    const uint32_t nw = (cur & ~(0xFFFFu << sh)) | ((uint32_t)lo << sh);
+    if (__hip_atomic_compare_exchange_strong(word, &cur, nw, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_WORKGROUP))
+      return hi;
+  }
+}
+
+// One workgroup per graph of `glist` (kSmallN < n <= kMidN, m <= kMidMaxEdges),
+// the rounds of Section 2.1 as in k_small_solve, with 10 bytes of LDS per
+// vertex: the minimum key per root (u64) and the union-find P (u16), which is
+// both the round-start root of every vertex and the parent forest of the
+// hooking.  The edges are streamed from memory every round (12 bytes each).
+// Thread t owns vertices t + q * kMidBlock (q < kMidPerThread).  Each round:
+//   minima   LDS 64-bit atomic min of (w << 32) | local index at the roots of
+//            every edge's ends;
+//   partner  for every owned root c with a minimum, d = the root at the edge's
+//            other end (the edge's loads of all owned roots in flight at
+//            once), kept in a register; none when c and d chose each other
+//            and d is the smaller (d acts);
+//   hooking  CAS of the larger root under the smaller in P, retried from the
+//            fresh ancestor the CAS returns; the edge's flag and weight;
+//   compress every owned vertex's final root into a register, then P flat
+//            again (so no halving store can replace a final value) and the
+//            minima of the new roots reset.
+// The loop ends when a round selects no edge.  Writes in_mst for the graph's
+// edges (zeroed by the caller), total[g] and status[g].
+//
+// kContracted: the graph is the contraction of batch graph g by its first
+// union rounds (see k_graph_epilogue): its vertices are the n' = nlist[i]
+// components left, its edges the graph's edges (same local indices, so the
+// same keys) with both ends given as 16-bit component numbers packed in
+// pairs[poff[i] + j] (a loop for an edge inside a component).  The union
+// rounds' edges are already flagged and their weight is in total[g]; their
+// count is pcnt[i] and pbad[i] flags out-of-range ids, so the status is that
+// of the whole graph.
+template <bool kContracted>
+__global__ void __launch_bounds__(kMidBlock) k_mid_solve(MidArgs A) {
+  extern __shared__ unsigned long long mbest[];  // [n], then P [n] (whole words)
+  __shared__ uint32_t round_sel;
+  __shared__ uint32_t bad;
+  __shared__ unsigned long long red_w[kMidBlock / 64];
+  __shared__ uint32_t red_c[kMidBlock / 64];
+
+  const int g = A.glist[blockIdx.x];
+  const int64_t e0 = A.eoff[g];
+  const int64_t m = A.eoff[g + 1] - e0;
+  const int32_t n_graph = (int32_t)(A.voff[g + 1] - A.voff[g]);
+  const int32_t n = kContracted ? A.nlist[blockIdx.x] : n_graph;
+  const int tid = threadIdx.x;
+  if (kContracted && (n < 0 || n > A.max_n)) {  // never: each union round at least halves the components
+    if (tid == 0) A.status[g] = MSTX_ERR_DEVICE;
+    return;
+  }
+  uint16_t* P = reinterpret_cast<uint16_t*>(mbest + n);
+  const int32_t* gs = kContracted ? nullptr : A.src + e0;
+  const int32_t* gd = kContracted ? nullptr : A.dst + e0;
+  const uint32_t* gp = kContracted ? A.pairs + A.poff[blockIdx.x] : nullptr;
+  const uint32_t* gw = A.w + e0;
+  uint8_t* in_mst = A.in_mst;
+
+  for (int32_t v = tid; v < n; v += kMidBlock) {
+    mbest[v] = kKeyNone;
+    P[v] = (uint16_t)v;
+  }
+  if (tid == 0) bad = 0;
+  bool my_bad = false;
+  unsigned long long my_w = 0;
+  uint32_t my_cnt = 0;
+  __syncthreads();
+
+  // (a contracted graph with no component left has only loops)
+  for (int round = 0; round < kMaxRounds && m > 0 && n > 0; ++round) {
+    if (tid == 0) round_sel = 0;
+    // minima: kMidUnroll edges per thread loaded at once (clamped to edge 0,
+    // which exists as m > 0), then offered for the edges that exist
+    for (int64_t j0 = 0; j0 < m; j0 += (int64_t)kMidUnroll * kMidBlock) {
+      int32_t a[kMidUnroll], b[kMidUnroll];
+      uint32_t c[kMidUnroll];
+#pragma unroll
+      for (int q = 0; q < kMidUnroll; ++q) {
+        const int64_t j = j0 + q * kMidBlock + tid;
+        const int64_t jc = j < m ? j : 0;
+        if (kContracted) {
+          a[q] = (int32_t)gp[jc];  // both ends, split below
+        } else {
+          a[q] = gs[jc];
+          b[q] = gd[jc];
+        }
+        c[q] = gw[jc];
+      }
+      // keeps every load above issued here, none sunk into the branches below
+      // (the edge arrays are not __restrict__, so the clobber pins them)
+      __asm__ __volatile__("" ::: "memory");
+#pragma unroll
+      for (int q = 0; q < kMidUnroll; ++q) {
+        const int64_t j = j0 + q * kMidBlock + tid;
+        if (j >= m) continue;
+        if (kContracted) {
+          b[q] = (int32_t)((uint32_t)a[q] >> 16);
+          a[q] = a[q] & 0xFFFF;
+        }
+        if ((uint32_t)a[q] >= (uint32_t)n || (uint32_t)b[q] >= (uint32_t)n) {
+          my_bad = true;  // dropped in every round
+          continue;
+        }
+        const int32_t ca = P[a[q]], cb = P[b[q]];
+        if (ca == cb) continue;
+        const unsigned long long key = ((unsigned long long)c[q] << 32) | (unsigned long long)j;
+        if (key < mbest[ca]) atomicMin(mbest + ca, key);
+        if (key < mbest[cb]) atomicMin(mbest + cb, key);
+      }
+    }
+    if (my_bad) bad = 1;
+    __syncthreads();
+    // partner of every owned root (loads clamped to edge 0)
+    int32_t d[kMidPerThread];
+    {
+      int32_t eu[kMidPerThread], ev[kMidPerThread];
+#pragma unroll
+      for (int q = 0; q < kMidPerThread; ++q) {
+        const int32_t c = tid + q * kMidBlock;
+        const int32_t cc = c < n ? c : 0;
+        const unsigned long long key = mbest[cc];
+        const bool has = c < n && P[cc] == c && key != kKeyNone;
+        const uint32_t j = has ? (uint32_t)key : 0u;
+        if (kContracted) {
+          eu[q] = (int32_t)gp[j];
+        } else {
+          eu[q] = gs[j];
+          ev[q] = gd[j];
+        }
+        d[q] = has ? 0 : -1;
+      }
+      __asm__ __volatile__("" ::: "memory");
+#pragma unroll
+      for (int q = 0; q < kMidPerThread; ++q) {
+        if (d[q] < 0) continue;
+        const int32_t c = tid + q * kMidBlock;
+        if (kContracted) {
+          ev[q] = (int32_t)((uint32_t)eu[q] >> 16);
+          eu[q] = eu[q] & 0xFFFF;
+        }
+        // a selected edge passed the range check, so its ends index P
+        const int32_t pu = P[eu[q]], pv = P[ev[q]];
+        const int32_t o = (pu == c) ? pv : pu;
+        d[q] = (o < c && mbest[o] == mbest[c]) ? -1 : o;  // mutual choice: o hooks it
+      }
+    }
+    __syncthreads();
+    // hooking in LDS
+    uint32_t sel = 0;
+#pragma unroll
+    for (int q = 0; q < kMidPerThread; ++q) {
+      if (d[q] < 0) continue;
+      const int32_t c = tid + q * kMidBlock;
+      const unsigned long long key = mbest[c];
+      int32_t x = c, y = d[q];
+      while (true) {
+        const int32_t rx = p_root(P, x);
+        const int32_t ry = p_root(P, y);
+        if (rx == ry) break;
+        const int32_t hi = rx > ry ? rx : ry;
+        const int32_t lo = rx > ry ? ry : rx;
+        const int32_t old = p_cas(P, hi, lo);
+        if (old == hi) {
+          in_mst[e0 + (uint32_t)key] = 1;
+          my_w += (uint32_t)(key >> 32);
+          ++sel;
+          break;
+        }
+        // the CAS returned a fresh, strictly smaller ancestor: resume there
+        if (hi == rx) x = old;
+        else y = old;
+      }
+    }
+    my_cnt += sel;
+    sel = small_wave_sum(sel);
+    if ((tid & 63) == 0 && sel) atomicAdd(&round_sel, sel);
+    __syncthreads();
+    if (round_sel == 0) break;
+    // compression: final roots of the owned vertices into registers (halving
+    // stores in P only ever write ancestors, which the walks tolerate), then
+    // P flat again
+#pragma unroll
+    for (int q = 0; q < kMidPerThread; ++q) {
+      const int32_t v = tid + q * kMidBlock;
+      d[q] = v < n ? p_root(P, v) : 0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kMidPerThread; ++q) {
+      const int32_t v = tid + q * kMidBlock;
+      if (v >= n) continue;
+      P[v] = (uint16_t)d[q];
+      if (d[q] == v) mbest[v] = kKeyNone;  // a root of the next round
+    }
+    __syncthreads();
+  }
+  // per-graph totals
+  for (int off = 32; off > 0; off >>= 1) {
+    my_w += __shfl_xor(my_w, off, 64);
+    my_cnt += __shfl_xor(my_cnt, off, 64);
+  }
+  if ((tid & 63) == 0) {
+    red_w[tid >> 6] = my_w;
+    red_c[tid >> 6] = my_cnt;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    unsigned long long tw = 0;
+    uint32_t tc = 0;
+    for (int i = 0; i < kMidBlock / 64; ++i) {
+      tw += red_w[i];
+      tc += red_c[i];
+    }
+    int64_t count = tc;
+    if (kContracted) {
+      tw += A.total[g];  // the union rounds' edges
+      count += A.pcnt[blockIdx.x];
+      if (A.pbad[blockIdx.x]) bad = 1;
+    }
+    A.total[g] = tw;
+    int32_t st = (n_graph <= 1 || count == (int64_t)n_graph - 1) ? MSTX_OK : MSTX_DISCONNECTED;
+    if (bad) st = MSTX_ERR_VERTEX_RANGE;
+    A.status[g] = st;
+  }
+}
+
 // Union of the chunk's graphs glist[0..ng): chunk edge p belongs to graph k with
 // cedge[k] <= p < cedge[k+1]; its ends become union ids cvert[k] + local id.
 // An end outside [0, n_g) makes the edge a self-loop at cvert[k] and flags the
@@ -305,6 +573,64 @@ __global__ void __launch_bounds__(256) k_gather(const int32_t* __restrict__ glis
 // range of graph glist[k] and adds the weight and count of the marked edges
 // of the slice to acc_w[k], acc_c[k] (zeroed by the caller; one atomic per
 // workgroup).
+// ------------------------------------------------------------ contraction
+//
+// A chunk of graphs whose union has run its first Boruvka rounds is finished
+// graph by graph on the mid-size path: every graph's remaining components get
+// consecutive numbers from 0 (k_contract_labels, k_contract_bounds) and its
+// edges become pairs of those numbers (k_graph_epilogue).
+
+// vlab[v] = the component of union vertex v after `rounds` rounds, as that
+// round's label (-1: the component had no outgoing edge, so it is final).
+__global__ void __launch_bounds__(256) k_contract_labels(int rounds, int32_t n, const int32_t* __restrict__ labpool,
+                                                         const DevState* __restrict__ st,
+                                                         int32_t* __restrict__ vlab) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+    int32_t x = labpool[st->lab_off[0] + v];
+    for (int r = 1; r < rounds && x >= 0; ++r) x = st->n[r] <= 1 ? -1 : labpool[st->lab_off[r] + x];
+    vlab[v] = x;
+  }
+}
+
+// Per chunk graph k (one workgroup each): its first component label and the
+// number of its components.  Labels are given in increasing order of the
+// components' roots and no component spans two graphs, so a graph's labels
+// are consecutive.
+static constexpr int kBoundsBlock = 1024;
+__global__ void __launch_bounds__(kBoundsBlock) k_contract_bounds(const int64_t* __restrict__ cvert,
+                                                                  const int32_t* __restrict__ vlab,
+                                                                  int32_t* __restrict__ cbase,
+                                                                  int32_t* __restrict__ cnum) {
+  __shared__ int32_t slo[kBoundsBlock / 64], shi[kBoundsBlock / 64];
+  const int k = blockIdx.x;
+  int32_t lo = INT32_MAX, hi = -1;
+  for (int64_t v = cvert[k] + threadIdx.x; v < cvert[k + 1]; v += kBoundsBlock) {
+    const int32_t x = vlab[v];
+    if (x >= 0) {
+      lo = min(lo, x);
+      hi = max(hi, x);
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    lo = min(lo, __shfl_xor(lo, off, 64));
+    hi = max(hi, __shfl_xor(hi, off, 64));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    slo[threadIdx.x >> 6] = lo;
+    shi[threadIdx.x >> 6] = hi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < kBoundsBlock / 64; ++i) {
+      lo = min(lo, slo[i]);
+      hi = max(hi, shi[i]);
+    }
+    cbase[k] = hi < 0 ? 0 : lo;
+    cnum[k] = hi < 0 ? 0 : hi - lo + 1;
+  }
+}
+
 static constexpr int64_t kEpilogueSlice = 16384;  // edges per workgroup (at least)
 __global__ void __launch_bounds__(256) k_graph_epilogue(const int32_t* __restrict__ glist, int64_t slice,
                                                         const int64_t* __restrict__ eoff,
@@ -313,7 +639,7 @@ __global__ void __launch_bounds__(256) k_graph_epilogue(const int32_t* __restric
                                                         const uint32_t* __restrict__ gw,
                                                         uint8_t* __restrict__ in_mst,
                                                         unsigned long long* __restrict__ acc_w,
-                                                        uint32_t* __restrict__ acc_c) {
+                                                        uint32_t* __restrict__ acc_c, ContractArgs C) {
   __shared__ unsigned long long rw[4];
   __shared__ uint32_t rc[4];
   const int k = blockIdx.x;
@@ -323,12 +649,20 @@ __global__ void __launch_bounds__(256) k_graph_epilogue(const int32_t* __restric
   const int64_t to = eoff[glist[k]] - cedge[k];  // caller index = chunk index + to
   unsigned long long sw = 0;
   uint32_t cnt = 0;
+  const int32_t base = C.vlab ? C.cbase[k] : 0;
+  const int64_t pair_at = C.vlab ? C.poff[k] - cedge[k] : 0;  // pair index = chunk edge index + pair_at
   for (int64_t p = p_first + threadIdx.x; p < p_end; p += blockDim.x) {
     const uint8_t f = cin_mst[p];
     in_mst[p + to] = f;
     if (f) {
       sw += gw[p];
       ++cnt;
+    }
+    if (C.vlab) {
+      // both ends' components after the union rounds, numbered from the
+      // graph's first; an edge inside a final component becomes a loop
+      const int32_t a = C.vlab[C.gsrc[p]], b = C.vlab[C.gdst[p]];
+      C.pairs[p + pair_at] = (a >= 0 && b >= 0) ? ((uint32_t)(a - base) | ((uint32_t)(b - base) << 16)) : 0u;
     }
   }
   for (int off = 32; off > 0; off >>= 1) {
@@ -355,20 +689,52 @@ __global__ void __launch_bounds__(256) k_graph_status(const int32_t* __restrict_
                                                       const uint32_t* __restrict__ acc_c,
                                                       const int32_t* __restrict__ gbad,
                                                       unsigned long long* __restrict__ total_out,
-                                                      int32_t* __restrict__ status_out) {
+                                                      int32_t* __restrict__ status_out, int32_t* __restrict__ pcnt,
+                                                      int32_t* __restrict__ pbad) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= ng) return;
   const int g = glist[k];
   const int64_t n = voff[g + 1] - voff[g];
   total_out[g] = acc_w[k];
+  if (pcnt) {  // contracted graph: the mid-size solve finishes it
+    pcnt[k] = (int32_t)acc_c[k];
+    pbad[k] = gbad[k];
+    return;
+  }
   int32_t st = (n <= 1 || (int64_t)acc_c[k] == n - 1) ? MSTX_OK : MSTX_DISCONNECTED;
   if (gbad[k]) st = MSTX_ERR_VERTEX_RANGE;
   status_out[g] = st;
 }
 
 hipError_t configure_batched_kernels() {
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_small_solve),
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_small_solve),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxDynLds);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mid_solve<false>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxDynLds);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mid_solve<true>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxDynLds);
+}
+
+hipError_t launch_mid_solve(const MidArgs& A, int num, int32_t max_n, bool contracted, hipStream_t s) {
+  if (num <= 0) return hipSuccess;
+  if (max_n < 1 || max_n > kMidN || (contracted && A.max_n != max_n)) return hipErrorInvalidValue;
+  const size_t lds = mid_solve_lds(max_n);  // the LDS layout holds max_n <= kMidN vertices
+  if (contracted) k_mid_solve<true><<<num, kMidBlock, lds, s>>>(A);
+  else k_mid_solve<false><<<num, kMidBlock, lds, s>>>(A);
+  return hipGetLastError();
+}
+
+hipError_t launch_contract(int rounds, int32_t n, const int32_t* labpool, const DevState* st, int32_t* vlab, int ng,
+                           const int64_t* cvert, int32_t* cbase, int32_t* cnum, hipStream_t s) {
+  if (ng <= 0 || n <= 0) return hipSuccess;
+  const int grid = (int)std::min<int64_t>(8192, ((int64_t)n + 255) / 256);
+  k_contract_labels<<<grid, 256, 0, s>>>(rounds, n, labpool, st, vlab);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_contract_bounds<<<ng, kBoundsBlock, 0, s>>>(cvert, vlab, cbase, cnum);
+  return hipGetLastError();
 }
 
 hipError_t launch_small_solve(const int32_t* glist, int num, const int64_t* voff, const int64_t* eoff,
@@ -406,7 +772,8 @@ hipError_t launch_graph_epilogue(const int32_t* glist, int ng, const int64_t* vo
                                  const int64_t* cedge, int64_t max_graph_m, const uint8_t* cin_mst,
                                  const uint32_t* gw, const int32_t* gbad, uint8_t* in_mst,
                                  unsigned long long* acc_w, uint32_t* acc_c, unsigned long long* total,
-                                 int32_t* status, hipStream_t s) {
+                                 int32_t* status, const ContractArgs& C, int32_t* pcnt, int32_t* pbad,
+                                 hipStream_t s) {
   if (ng <= 0) return hipSuccess;
   hipError_t e = hipMemsetAsync(acc_w, 0, 8 * (size_t)ng, s);
   if (e == hipSuccess) e = hipMemsetAsync(acc_c, 0, 4 * (size_t)ng, s);
@@ -415,10 +782,11 @@ hipError_t launch_graph_epilogue(const int32_t* glist, int ng, const int64_t* vo
   const int64_t slice = std::max<int64_t>(kEpilogueSlice, (max_graph_m + 65534) / 65535);
   const int64_t slices = std::max<int64_t>(1, (max_graph_m + slice - 1) / slice);
   k_graph_epilogue<<<dim3(ng, (unsigned)slices), 256, 0, s>>>(glist, slice, eoff, cedge, cin_mst, gw, in_mst,
-                                                               acc_w, acc_c);
+                                                               acc_w, acc_c, C);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  k_graph_status<<<(ng + 255) / 256, 256, 0, s>>>(glist, ng, voff, acc_w, acc_c, gbad, total, status);
+  k_graph_status<<<(ng + 255) / 256, 256, 0, s>>>(glist, ng, voff, acc_w, acc_c, gbad, total, status, pcnt,
+                                                   pbad);
   return hipGetLastError();
 }
 

@@ -107,6 +107,10 @@ std::atomic<int> g_dense_limit{kDenseMax};
 // Largest vertex count for which mst_solve takes the one-workgroup path
 // (0: never); mst_set_small_limit() changes it.
 std::atomic<int> g_small_limit{kSmallN};
+// Largest vertex count for which mst_solve_batched solves a graph above
+// kSmallN vertices with one workgroup (k_mid_solve) instead of the union
+// chunks (0: never); mst_set_mid_limit() changes it.
+std::atomic<int> g_mid_limit{kMidN};
 // Largest component-count bound for which a round's hook .. relabel run as
 // one workgroup (0: never); mst_set_tail_limit() changes it.
 std::atomic<int> g_tail_limit{kTailMax};
@@ -478,7 +482,8 @@ HostRound load_record(const HostRound* p) {
 
 // The round loop of one graph (n >= 1, m >= 1) on a workspace of at least
 // plan(n, m).bytes; the device cache is locked by the caller.
-int solve_locked(DeviceCache* dc, const Layout& L, int32_t n, int64_t m, const int32_t* src, const int32_t* dst,
+// The solve state of a graph on the cached workspace laid out by L.
+Solve make_solve(DeviceCache* dc, const Layout& L, int32_t n, int64_t m, const int32_t* src, const int32_t* dst,
                  const uint32_t* w, uint8_t* in_mst, uint64_t* total, hipStream_t s) {
   void* B = dc->base;
   Solve S;
@@ -511,8 +516,27 @@ int solve_locked(DeviceCache* dc, const Layout& L, int32_t n, int64_t m, const i
   S.btot = at<uint32_t>(B, L.btot);
   S.dense_limit = g_dense_limit.load();
   S.tail_limit = g_tail_limit.load();
-  const int max_rounds = std::min(rounds_bound(n) + 1, kMaxRounds);
   S.launched.assign(kMaxRounds + 1, 0);
+  return S;
+}
+
+// Algorithmic bytes of round r's scan: the edge stream read once, the
+// previous label map read once, the minima initialised and written once, the
+// compacted survivors written once (a dense round instead writes its pair
+// table once and compacts nothing).
+double round_scan_bytes(const HostRound* rec, const std::vector<int32_t>& nr_of, int r, int32_t n, int64_t m) {
+  const HostRound& M = rec[r];
+  const double nrd = (double)nr_of[r];
+  const double out = M.dense ? 8.0 * (double)dense_pairs(nr_of[r]) : 16.0 * nrd + 16.0 * (double)M.live;
+  if (r == 0) return 12.0 * (double)m + (M.dense ? out : 16.0 * nrd);
+  if (r == 1) return 12.0 * (double)m + 4.0 * (double)n + out;
+  return 16.0 * (double)rec[r - 1].live + 4.0 * (double)nr_of[r - 1] + out;
+}
+
+int solve_locked(DeviceCache* dc, const Layout& L, int32_t n, int64_t m, const int32_t* src, const int32_t* dst,
+                 const uint32_t* w, uint8_t* in_mst, uint64_t* total, hipStream_t s) {
+  Solve S = make_solve(dc, L, n, m, src, dst, w, in_mst, total, s);
+  const int max_rounds = std::min(rounds_bound(n) + 1, kMaxRounds);
 
   LaunchTimer& T = t_timer;
   T.begin(s);
@@ -576,18 +600,50 @@ int solve_locked(DeviceCache* dc, const Layout& L, int32_t n, int64_t m, const i
     t_last_stats[3 * r + 1] = M.live;
     t_last_stats[3 * r + 2] = M.sel;
     chosen[r] = pick_mode(nr_of[r], S.launched[r]);
-    // algorithmic bytes of this round's scan: the edge stream read once, the
-    // previous label map read once, the minima initialised and written once,
-    // the compacted survivors written once (a dense round instead writes its
-    // pair table once and compacts nothing)
-    const double nrd = (double)nr_of[r];
-    const double out = M.dense ? 8.0 * (double)dense_pairs(nr_of[r]) : 16.0 * nrd + 16.0 * (double)M.live;
-    if (r == 0) bytes[r] = 12.0 * (double)m + (M.dense ? out : 16.0 * nrd);
-    else if (r == 1) bytes[r] = 12.0 * (double)m + 4.0 * (double)n + out;
-    else bytes[r] = 16.0 * (double)dc->host_rounds[r - 1].live + 4.0 * (double)nr_of[r - 1] + out;
+    bytes[r] = round_scan_bytes(dc->host_rounds, nr_of, r, n, m);
   }
   T.commit(rounds, chosen, bytes);
   return status;
+}
+
+// The first `rounds` (1 or 2) Boruvka rounds of a graph (n >= 1, m >= 1), no
+// more: their edges are flagged in in_mst, and the label maps of every round
+// stay in the label pool for the contraction that follows.  No dense finish
+// (it would end the solve without a label map).  The device cache is locked
+// by the caller.
+int contract_locked(DeviceCache* dc, const Layout& L, int32_t n, int64_t m, const int32_t* src, const int32_t* dst,
+                    const uint32_t* w, uint8_t* in_mst, uint64_t* total, int rounds, hipStream_t s) {
+  Solve S = make_solve(dc, L, n, m, src, dst, w, in_mst, total, s);
+  S.dense_limit = 0;
+  LaunchTimer& T = t_timer;
+  T.begin(s);
+  HIP_OK(hipMemsetAsync(in_mst, 0, (size_t)m, s));
+  HIP_OK(hipMemsetAsync(total, 0, sizeof(uint64_t), s));
+  HIP_OK(launch_init(n, S.best, S.parent, nullptr, S.btot, S.st, grid_for(n), s));
+  for (int r = 0; r <= kMaxRounds; ++r) dc->host_rounds[r].n_next = kRecordPending;
+  std::atomic_thread_fence(std::memory_order_seq_cst);
+  HIP_OK(enqueue_round(S, 0, n));
+  if (rounds >= 2) HIP_OK(enqueue_round(S, 1, n / 2, n));  // each round at least halves the components
+  HIP_OK(hipStreamSynchronize(s));
+  std::vector<int32_t> nr_of(kMaxRounds + 2, 0);
+  nr_of[0] = n;
+  int done = 0;
+  for (int r = 0; r < rounds; ++r) {
+    const HostRound M = load_record(dc->host_rounds + r);
+    // ids were made valid by the gather, so any error is internal
+    if (M.n_next == kRecordPending || M.err || M.err_internal) return MSTX_ERR_DEVICE;
+    done = r + 1;
+    nr_of[r + 1] = M.n_next;
+    if (M.n_next <= 1) break;  // a later round did nothing (and wrote no record)
+  }
+  std::vector<int> chosen(kMaxRounds + 1, -1);
+  std::vector<double> bytes(kMaxRounds + 1, 0.0);
+  for (int r = 0; r < done; ++r) {
+    chosen[r] = pick_mode(nr_of[r], S.launched[r]);
+    bytes[r] = round_scan_bytes(dc->host_rounds, nr_of, r, n, m);
+  }
+  T.commit(done, chosen, bytes);
+  return MSTX_OK;
 }
 
 // A graph of at most kSmallN vertices in one launch (the batched path's
@@ -654,12 +710,33 @@ int solve(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, const ui
 
 // ----------------------------------------------------------------- batched
 
+// Which path a graph of a batch takes: one workgroup with everything in LDS
+// (small); one workgroup with the edges streamed every round (mid); the first
+// one or two rounds in a chunk of the disjoint union solved by the round
+// kernels, then the mid path on what is left (contract1 / contract2: each
+// round at least halves the components, so at most mid_limit remain); or
+// every round in a union chunk (large).
+enum class BatchPath { kSmall, kMid, kContract1, kContract2, kLarge };
+BatchPath batch_path(int64_t n, int64_t m, int32_t mid_limit) {
+  if (n <= kSmallN) return BatchPath::kSmall;
+  if (mid_limit > kSmallN && m <= kMidMaxEdges) {
+    if (n <= mid_limit) return BatchPath::kMid;
+    if (n <= 2 * (int64_t)mid_limit) return BatchPath::kContract1;
+    if (n <= 4 * (int64_t)mid_limit) return BatchPath::kContract2;
+  }
+  return BatchPath::kLarge;
+}
+
 // Device scratch of a batched call besides the solve workspace.
 struct BatchLayout {
-  size_t voff, eoff, small, large, cvert, cedge, gbad, gsrc, gdst, gw, cin, total, acc_w, acc_c, bytes;
+  size_t voff, eoff, small, mid, large, cvert, cedge, gbad, gsrc, gdst, gw, cin, total, acc_w, acc_c, cpoff,
+      cbase, cnum, pcnt, pbad, pairs, bytes;
 };
 
-BatchLayout plan_batch(int32_t G, int64_t nsmall, int64_t nlarge, int64_t nchunk_meta, int64_t max_chunk_m) {
+// nlarge counts every graph that goes through a union chunk (ncon of them
+// are then contracted, with con_m edges in all).
+BatchLayout plan_batch(int32_t G, int64_t nsmall, int64_t nmid, int64_t nlarge, int64_t nchunk_meta,
+                       int64_t max_chunk_m, int64_t ncon, int64_t con_m) {
   BatchLayout B{};
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -670,6 +747,7 @@ BatchLayout plan_batch(int32_t G, int64_t nsmall, int64_t nlarge, int64_t nchunk
   B.voff = take(8 * ((size_t)G + 1));
   B.eoff = take(8 * ((size_t)G + 1));
   B.small = take(4 * (size_t)std::max<int64_t>(nsmall, 1));
+  B.mid = take(4 * (size_t)std::max<int64_t>(nmid, 1));
   B.large = take(4 * (size_t)std::max<int64_t>(nlarge, 1));
   B.cvert = take(8 * (size_t)std::max<int64_t>(nchunk_meta, 1));
   B.cedge = take(8 * (size_t)std::max<int64_t>(nchunk_meta, 1));
@@ -681,6 +759,12 @@ BatchLayout plan_batch(int32_t G, int64_t nsmall, int64_t nlarge, int64_t nchunk
   B.total = take(8);
   B.acc_w = take(8 * (size_t)std::max<int64_t>(nlarge, 1));
   B.acc_c = take(4 * (size_t)std::max<int64_t>(nlarge, 1));
+  B.cpoff = take(8 * (size_t)std::max<int64_t>(ncon, 1));
+  B.cbase = take(4 * (size_t)std::max<int64_t>(ncon, 1));
+  B.cnum = take(4 * (size_t)std::max<int64_t>(ncon, 1));
+  B.pcnt = take(4 * (size_t)std::max<int64_t>(ncon, 1));
+  B.pbad = take(4 * (size_t)std::max<int64_t>(ncon, 1));
+  B.pairs = take(4 * (size_t)std::max<int64_t>(con_m, 1));
   B.bytes = off;
   return B;
 }
@@ -717,61 +801,106 @@ int check_batch_args(int32_t G, const int64_t* voff, const int64_t* eoff, const 
   return MSTX_OK;
 }
 
-int solve_batched(int32_t G, const int64_t* voff, const int64_t* eoff, const int32_t* src, const int32_t* dst,
-                  const uint32_t* w, uint8_t* in_mst, uint64_t* total, int32_t* status, hipStream_t s) {
-  t_last_stats.clear();
-  if (G == 0) return MSTX_OK;
-  // graphs small enough for one workgroup, largest first; the others go in chunks
-  std::vector<int32_t> small, large;
-  for (int32_t g = 0; g < G; ++g) {
-    if (voff[g + 1] - voff[g] <= kSmallN) small.push_back(g);
-    else large.push_back(g);
-  }
-  std::stable_sort(small.begin(), small.end(), [&](int32_t a, int32_t b) {
-    return eoff[a + 1] - eoff[a] > eoff[b + 1] - eoff[b];
-  });
-  // chunks of large graphs: consecutive in `large`, union within the bucket-mode limit
-  std::vector<int32_t> chunk_begin{0};
-  std::vector<int64_t> cvert, cedge;  // per chunk: (ng + 1) offsets each, concatenated
-  std::vector<int64_t> meta_at;      // start of each chunk's offsets in cvert/cedge
+// How a batch is split: the graphs of each path and the union chunks.
+struct BatchPlan {
+  std::vector<int32_t> small, mid;
+  // graphs that go through union chunks: those solved there entirely
+  // (uni[0..nplain)), then the contracted ones (two rounds, then one)
+  std::vector<int32_t> uni;
+  int64_t nplain = 0;
+  // chunk c: uni[cfirst[c] .. cfirst[c + 1]), its first crounds[c] rounds in
+  // the union (0: all of them); its graphs' vertex and edge offsets inside the
+  // union are cvert / cedge[meta_at[c] ..] (ng + 1 each)
+  std::vector<int32_t> cfirst;
+  std::vector<int> crounds;
+  std::vector<int64_t> cvert, cedge, meta_at;
+  std::vector<int64_t> cpoff;  // contracted graph i = uni[nplain + i]: start of its edge pairs
+  int64_t con_m = 0;
   int64_t max_chunk_n = 0, max_chunk_m = 0;
-  {
+  int32_t mid_max_n = 0;
+};
+
+BatchPlan plan_batch_graphs(int32_t G, const int64_t* voff, const int64_t* eoff, int32_t mid_limit) {
+  BatchPlan P;
+  std::vector<int32_t> plain, con2, con1;
+  for (int32_t g = 0; g < G; ++g) {
+    switch (batch_path(voff[g + 1] - voff[g], eoff[g + 1] - eoff[g], mid_limit)) {
+      case BatchPath::kSmall: P.small.push_back(g); break;
+      case BatchPath::kMid: P.mid.push_back(g); break;
+      case BatchPath::kContract1: con1.push_back(g); break;
+      case BatchPath::kContract2: con2.push_back(g); break;
+      case BatchPath::kLarge: plain.push_back(g); break;
+    }
+  }
+  // most edges first, so the longest workgroups of a launch start first
+  auto more_edges = [&](int32_t a, int32_t b) { return eoff[a + 1] - eoff[a] > eoff[b + 1] - eoff[b]; };
+  for (auto* v : {&P.small, &P.mid, &plain, &con2, &con1}) std::stable_sort(v->begin(), v->end(), more_edges);
+  for (int32_t g : P.mid) P.mid_max_n = std::max<int32_t>(P.mid_max_n, (int32_t)(voff[g + 1] - voff[g]));
+  P.uni = plain;
+  P.uni.insert(P.uni.end(), con2.begin(), con2.end());
+  P.uni.insert(P.uni.end(), con1.begin(), con1.end());
+  P.nplain = (int64_t)plain.size();
+  // chunks: consecutive graphs of one kind, union within the bucket-mode limit
+  auto add_chunks = [&](int32_t i0, int32_t i1, int rounds) {
     int64_t cn = 0, cm = 0;
-    for (size_t i = 0; i < large.size(); ++i) {
-      const int32_t g = large[i];
+    for (int32_t i = i0; i < i1; ++i) {
+      const int32_t g = P.uni[i];
       const int64_t ng = voff[g + 1] - voff[g], mg = eoff[g + 1] - eoff[g];
-      if ((int)i > chunk_begin.back() && (cn + ng > kBucketMaxComponents || cm + mg > (int64_t)0xFFFFFFFFLL)) {
-        chunk_begin.push_back((int32_t)i);
+      if (i == i0 || cn + ng > kBucketMaxComponents || cm + mg > (int64_t)0xFFFFFFFFLL) {
+        P.cfirst.push_back(i);
+        P.crounds.push_back(rounds);
         cn = cm = 0;
       }
       cn += ng;
       cm += mg;
-      max_chunk_n = std::max(max_chunk_n, cn);
-      max_chunk_m = std::max(max_chunk_m, cm);
+      P.max_chunk_n = std::max(P.max_chunk_n, cn);
+      P.max_chunk_m = std::max(P.max_chunk_m, cm);
     }
-    chunk_begin.push_back((int32_t)large.size());
-    for (size_t c = 0; c + 1 < chunk_begin.size(); ++c) {
-      meta_at.push_back((int64_t)cvert.size());
-      int64_t a = 0, b = 0;
-      for (int32_t i = chunk_begin[c]; i < chunk_begin[c + 1]; ++i) {
-        cvert.push_back(a);
-        cedge.push_back(b);
-        a += voff[large[i] + 1] - voff[large[i]];
-        b += eoff[large[i] + 1] - eoff[large[i]];
-      }
-      cvert.push_back(a);
-      cedge.push_back(b);
+  };
+  const int32_t n2 = (int32_t)(P.nplain + (int64_t)con2.size());
+  add_chunks(0, (int32_t)P.nplain, 0);
+  add_chunks((int32_t)P.nplain, n2, 2);
+  add_chunks(n2, (int32_t)P.uni.size(), 1);
+  P.cfirst.push_back((int32_t)P.uni.size());
+  for (size_t c = 0; c + 1 < P.cfirst.size(); ++c) {
+    P.meta_at.push_back((int64_t)P.cvert.size());
+    int64_t a = 0, b = 0;
+    for (int32_t i = P.cfirst[c]; i < P.cfirst[c + 1]; ++i) {
+      P.cvert.push_back(a);
+      P.cedge.push_back(b);
+      a += voff[P.uni[i] + 1] - voff[P.uni[i]];
+      b += eoff[P.uni[i] + 1] - eoff[P.uni[i]];
     }
+    P.cvert.push_back(a);
+    P.cedge.push_back(b);
   }
-  if (max_chunk_n > INT32_MAX) return MSTX_ERR_TOO_LARGE;
-  const Layout L = plan((int32_t)std::max<int64_t>(max_chunk_n, 1), std::max<int64_t>(max_chunk_m, 1));
-  const BatchLayout BL = plan_batch(G, (int64_t)small.size(), (int64_t)large.size(), (int64_t)cvert.size(),
-                                    max_chunk_m);
+  for (size_t i = (size_t)P.nplain; i < P.uni.size(); ++i) {
+    P.cpoff.push_back(P.con_m);
+    P.con_m += eoff[P.uni[i] + 1] - eoff[P.uni[i]];
+  }
+  return P;
+}
+
+BatchLayout plan_batch(int32_t G, const BatchPlan& P) {
+  return plan_batch(G, (int64_t)P.small.size(), (int64_t)P.mid.size(), (int64_t)P.uni.size(), (int64_t)P.cvert.size(),
+                    P.max_chunk_m, (int64_t)P.cpoff.size(), P.con_m);
+}
+
+int solve_batched(int32_t G, const int64_t* voff, const int64_t* eoff, const int32_t* src, const int32_t* dst,
+                  const uint32_t* w, uint8_t* in_mst, uint64_t* total, int32_t* status, hipStream_t s) {
+  t_last_stats.clear();
+  if (G == 0) return MSTX_OK;
+  const int32_t mid_limit = g_mid_limit.load();
+  const BatchPlan P = plan_batch_graphs(G, voff, eoff, mid_limit);
+  if (P.max_chunk_n > INT32_MAX) return MSTX_ERR_TOO_LARGE;
+  const int64_t nuni = (int64_t)P.uni.size(), ncon = (int64_t)P.cpoff.size();
+  const Layout L = plan((int32_t)std::max<int64_t>(P.max_chunk_n, 1), std::max<int64_t>(P.max_chunk_m, 1));
+  const BatchLayout BL = plan_batch(G, P);
   if (L.bytes + BL.bytes > workspace_limit()) return MSTX_ERR_OUT_OF_MEMORY;
 
   DeviceCache* dc = nullptr;
   std::unique_lock<std::mutex> lock;
-  int rc = acquire(dc, lock, large.empty() ? 0 : L.bytes, s);
+  int rc = acquire(dc, lock, nuni == 0 ? 0 : L.bytes, s);
   if (rc != MSTX_OK) return rc;
   rc = grow_aux(dc, BL.bytes);
   if (rc != MSTX_OK) return rc;
@@ -779,7 +908,8 @@ int solve_batched(int32_t G, const int64_t* voff, const int64_t* eoff, const int
   auto* d_voff = at<int64_t>(A, BL.voff);
   auto* d_eoff = at<int64_t>(A, BL.eoff);
   auto* d_small = at<int32_t>(A, BL.small);
-  auto* d_large = at<int32_t>(A, BL.large);
+  auto* d_mid = at<int32_t>(A, BL.mid);
+  auto* d_uni = at<int32_t>(A, BL.large);
   auto* d_cvert = at<int64_t>(A, BL.cvert);
   auto* d_cedge = at<int64_t>(A, BL.cedge);
   auto* d_gbad = at<int32_t>(A, BL.gbad);
@@ -788,39 +918,79 @@ int solve_batched(int32_t G, const int64_t* voff, const int64_t* eoff, const int
   auto* gw = at<uint32_t>(A, BL.gw);
   auto* cin = at<uint8_t>(A, BL.cin);
   auto* ctotal = at<uint64_t>(A, BL.total);
+  auto* d_cpoff = at<int64_t>(A, BL.cpoff);
+  auto* d_cbase = at<int32_t>(A, BL.cbase);
+  auto* d_cnum = at<int32_t>(A, BL.cnum);
+  auto* d_pcnt = at<int32_t>(A, BL.pcnt);
+  auto* d_pbad = at<int32_t>(A, BL.pbad);
+  auto* d_pairs = at<uint32_t>(A, BL.pairs);
   auto* tot = reinterpret_cast<unsigned long long*>(total);
 
   HIP_OK(hipMemcpyAsync(d_voff, voff, 8 * ((size_t)G + 1), hipMemcpyHostToDevice, s));
   HIP_OK(hipMemcpyAsync(d_eoff, eoff, 8 * ((size_t)G + 1), hipMemcpyHostToDevice, s));
-  if (!small.empty())
-    HIP_OK(hipMemcpyAsync(d_small, small.data(), 4 * small.size(), hipMemcpyHostToDevice, s));
-  if (!large.empty()) {
-    HIP_OK(hipMemcpyAsync(d_large, large.data(), 4 * large.size(), hipMemcpyHostToDevice, s));
-    HIP_OK(hipMemcpyAsync(d_cvert, cvert.data(), 8 * cvert.size(), hipMemcpyHostToDevice, s));
-    HIP_OK(hipMemcpyAsync(d_cedge, cedge.data(), 8 * cedge.size(), hipMemcpyHostToDevice, s));
-    HIP_OK(hipMemsetAsync(d_gbad, 0, 4 * large.size(), s));
+  if (!P.small.empty())
+    HIP_OK(hipMemcpyAsync(d_small, P.small.data(), 4 * P.small.size(), hipMemcpyHostToDevice, s));
+  if (!P.mid.empty()) HIP_OK(hipMemcpyAsync(d_mid, P.mid.data(), 4 * P.mid.size(), hipMemcpyHostToDevice, s));
+  if (nuni > 0) {
+    HIP_OK(hipMemcpyAsync(d_uni, P.uni.data(), 4 * (size_t)nuni, hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(d_cvert, P.cvert.data(), 8 * P.cvert.size(), hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(d_cedge, P.cedge.data(), 8 * P.cedge.size(), hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemsetAsync(d_gbad, 0, 4 * (size_t)nuni, s));
   }
+  if (ncon > 0) HIP_OK(hipMemcpyAsync(d_cpoff, P.cpoff.data(), 8 * (size_t)ncon, hipMemcpyHostToDevice, s));
   if (eoff[G] > 0) HIP_OK(hipMemsetAsync(in_mst, 0, (size_t)eoff[G], s));
-  HIP_OK(launch_small_solve(d_small, (int)small.size(), d_voff, d_eoff, src, dst, w, in_mst, tot, status, s));
+  {
+    const MidArgs M{d_mid,   d_voff,  d_eoff,  src,    dst, w,      nullptr, nullptr,
+                    nullptr, nullptr, nullptr, in_mst, tot, status, P.mid_max_n};
+    HIP_OK(launch_mid_solve(M, (int)P.mid.size(), P.mid_max_n, false, s));
+  }
+  HIP_OK(launch_small_solve(d_small, (int)P.small.size(), d_voff, d_eoff, src, dst, w, in_mst, tot, status, s));
 
-  for (size_t c = 0; c + 1 < chunk_begin.size(); ++c) {
-    const int32_t i0 = chunk_begin[c], ng = chunk_begin[c + 1] - i0;
-    const int64_t at_meta = meta_at[c];
-    const int64_t cn = cvert[at_meta + ng], cm = cedge[at_meta + ng];
-    HIP_OK(launch_gather(d_large + i0, ng, d_voff, d_eoff, d_cvert + at_meta, d_cedge + at_meta, cm, src, dst, w,
+  for (size_t c = 0; c + 1 < P.cfirst.size(); ++c) {
+    const int32_t i0 = P.cfirst[c], ng = P.cfirst[c + 1] - i0;
+    const int rounds = P.crounds[c];
+    const int64_t at_meta = P.meta_at[c];
+    const int64_t cn = P.cvert[at_meta + ng], cm = P.cedge[at_meta + ng];
+    HIP_OK(launch_gather(d_uni + i0, ng, d_voff, d_eoff, d_cvert + at_meta, d_cedge + at_meta, cm, src, dst, w,
                          gsrc, gdst, gw, d_gbad + i0, s));
+    const Layout Lc = plan((int32_t)cn, std::max<int64_t>(cm, 1));
     if (cm > 0) {
-      const Layout Lc = plan((int32_t)cn, cm);
-      rc = solve_locked(dc, Lc, (int32_t)cn, cm, gsrc, gdst, gw, cin, ctotal, s);
+      rc = rounds == 0 ? solve_locked(dc, Lc, (int32_t)cn, cm, gsrc, gdst, gw, cin, ctotal, s)
+                       : contract_locked(dc, Lc, (int32_t)cn, cm, gsrc, gdst, gw, cin, ctotal, rounds, s);
       if (rc < 0) return rc;
     } else {
       HIP_OK(hipMemsetAsync(cin, 0, 1, s));
     }
+    ContractArgs C{};
+    int32_t* pcnt = nullptr;
+    int32_t* pbad = nullptr;
+    if (rounds > 0) {
+      const int64_t pos0 = i0 - P.nplain;
+      if (cm > 0) {
+        int32_t* vlab = at<int32_t>(dc->base, Lc.root_of);  // free once the rounds are done
+        HIP_OK(launch_contract(rounds, (int32_t)cn, at<int32_t>(dc->base, Lc.labpool), at<DevState>(dc->base, Lc.state),
+                               vlab, ng, d_cvert + at_meta, d_cbase + pos0, d_cnum + pos0, s));
+        C = ContractArgs{vlab, d_cbase + pos0, gsrc, gdst, d_pairs, d_cpoff + pos0};
+      } else {
+        HIP_OK(hipMemsetAsync(d_cnum + pos0, 0, 4 * (size_t)ng, s));  // no edges: nothing left to join
+      }
+      pcnt = d_pcnt + pos0;
+      pbad = d_pbad + pos0;
+    }
     int64_t max_graph_m = 0;
-    for (int32_t q = 0; q < ng; ++q) max_graph_m = std::max(max_graph_m, cedge[at_meta + q + 1] - cedge[at_meta + q]);
-    HIP_OK(launch_graph_epilogue(d_large + i0, ng, d_voff, d_eoff, d_cedge + at_meta, max_graph_m, cin, gw,
+    for (int32_t q = 0; q < ng; ++q)
+      max_graph_m = std::max(max_graph_m, P.cedge[at_meta + q + 1] - P.cedge[at_meta + q]);
+    HIP_OK(launch_graph_epilogue(d_uni + i0, ng, d_voff, d_eoff, d_cedge + at_meta, max_graph_m, cin, gw,
                                  d_gbad + i0, in_mst, at<unsigned long long>(A, BL.acc_w),
-                                 at<uint32_t>(A, BL.acc_c), tot, status, s));
+                                 at<uint32_t>(A, BL.acc_c), tot, status, C, pcnt, pbad, s));
+  }
+  if (ncon > 0) {
+    // the contracted graphs of every chunk in one launch: at most mid_limit
+    // components each are left
+    const int32_t max_n = std::min<int32_t>(mid_limit, kMidN);
+    const MidArgs M{d_uni + P.nplain, d_voff, d_eoff, nullptr, nullptr, w,      d_pairs, d_cpoff,
+                    d_cnum,           d_pcnt, d_pbad, in_mst,  tot,     status, max_n};
+    HIP_OK(launch_mid_solve(M, (int)ncon, max_n, true, s));
   }
   HIP_OK(hipStreamSynchronize(s));
   return MSTX_OK;
@@ -900,22 +1070,11 @@ size_t mst_batched_workspace_bytes(int32_t num_graphs, const int64_t* vertex_off
   if (mstx::check_batch_args(num_graphs, vertex_offsets, edge_offsets, (void*)1, (void*)1, (void*)1, (void*)1,
                              (void*)1, (void*)1) != MSTX_OK)
     return 0;
-  int64_t cn = 0, cm = 0, maxn = 0, maxm = 0, nsmall = 0, nlarge = 0;
-  for (int32_t g = 0; g < num_graphs; ++g) {
-    const int64_t ng = vertex_offsets[g + 1] - vertex_offsets[g], mg = edge_offsets[g + 1] - edge_offsets[g];
-    if (ng <= mstx::kSmallN) {
-      ++nsmall;
-      continue;
-    }
-    ++nlarge;
-    if (cn > 0 && (cn + ng > mstx::kBucketMaxComponents || cm + mg > (int64_t)0xFFFFFFFFLL)) cn = cm = 0;
-    cn += ng;
-    cm += mg;
-    maxn = std::max(maxn, cn);
-    maxm = std::max(maxm, cm);
-  }
-  const size_t solve_ws = nlarge ? mstx::plan((int32_t)std::min<int64_t>(maxn, INT32_MAX), maxm).bytes : 0;
-  return solve_ws + mstx::plan_batch(num_graphs, nsmall, nlarge, 2 * nlarge + 2, maxm).bytes;
+  const mstx::BatchPlan P =
+      mstx::plan_batch_graphs(num_graphs, vertex_offsets, edge_offsets, mstx::g_mid_limit.load());
+  const size_t solve_ws =
+      P.uni.empty() ? 0 : mstx::plan((int32_t)std::min<int64_t>(P.max_chunk_n, INT32_MAX), P.max_chunk_m).bytes;
+  return solve_ws + mstx::plan_batch(num_graphs, P).bytes;
 }
 
 int mst_select_min_edges(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, const uint32_t* w,
@@ -995,6 +1154,11 @@ size_t mst_workspace_bytes(int32_t n, int64_t m) {
 int32_t mst_set_small_limit(int32_t limit) {
   if (limit < 0) return mstx::g_small_limit.load();
   return mstx::g_small_limit.exchange(std::min<int32_t>(limit, mstx::kSmallN));
+}
+
+int32_t mst_set_mid_limit(int32_t limit) {
+  if (limit < 0) return mstx::g_mid_limit.load();
+  return mstx::g_mid_limit.exchange(std::min<int32_t>(limit, mstx::kMidN));
 }
 
 int32_t mst_set_tail_limit(int32_t limit) {

@@ -28,6 +28,8 @@ DENSE_MAX = 200  # largest component count the library's dense finish takes
 SMALL_MAX = 8192  # largest vertex count of the library's one-workgroup path
 LDS_SLOTS = 20352  # largest component count whose minima the scan keeps in LDS
 TAIL_MAX = 10240  # largest round bound whose hook .. relabel run in one workgroup
+MID_MAX = 16280  # largest vertex count of a batched graph solved by one workgroup, edges streamed
+MID_MAX_EDGES = 1 << 21  # ... and its largest edge count
 
 
 def stats_consistent(gpu_stats, oracle_stats, limit=DENSE_MAX):

@@ -34,7 +34,8 @@ def lib():
 def test_header_declares_entry_points():
     names = declared_functions()
     for must in ("mst_solve", "mst_solve_batched", "mst_select_min_edges", "mst_workspace_bytes",
-                 "mst_set_dense_limit", "mst_set_small_limit", "mst_set_tail_limit", "mst_status_string"):
+                 "mst_set_dense_limit", "mst_set_small_limit", "mst_set_tail_limit", "mst_set_mid_limit",
+                 "mst_status_string"):
         assert must in names, names
 
 
@@ -117,6 +118,25 @@ def test_tail_limit_option(lib):
         assert B.mst_set_tail_limit(-1) == gpu_cases.TAIL_MAX
     finally:
         B.mst_set_tail_limit(prev)
+
+
+def test_mid_limit_option(lib):
+    from paper_2005_06913_amd import binding as B
+    prev = B.mst_set_mid_limit(-1)
+    assert prev == gpu_cases.MID_MAX
+    vo = np.array([0, 100, 12100], np.int64)
+    eo = np.array([0, 400, 100400], np.int64)
+    try:
+        with_mid = B.mst_batched_workspace_bytes(vo, eo)
+        assert B.mst_set_mid_limit(10 ** 6) == prev
+        assert B.mst_set_mid_limit(-1) == gpu_cases.MID_MAX  # clamped
+        with B.mid_limit(0):
+            assert B.mst_set_mid_limit(-1) == 0
+            # the union path needs the round kernels' workspace: records per edge
+            assert B.mst_batched_workspace_bytes(vo, eo) > with_mid
+        assert B.mst_set_mid_limit(-1) == gpu_cases.MID_MAX
+    finally:
+        B.mst_set_mid_limit(prev)
 
 
 def test_workspace_bytes(lib):

@@ -1,10 +1,15 @@
 """GPU parity of the batched solve: every graph of a batch against the oracle.
 
-A batch mixes graphs solved by one workgroup each (n <= 8192) with larger
-graphs solved as chunks of a disjoint union; ties, self-loops, parallel
-edges, isolated vertices, empty graphs and out-of-range ids are included.
-Every graph's edge flags, total and status must equal the oracle's on that
-graph alone.
+A batch mixes graphs solved by one workgroup each with everything in LDS
+(n <= 8192), graphs solved by one workgroup each with the edges streamed every
+round (up to 16280 vertices and 2^21 edges), graphs contracted by one or two
+rounds of a disjoint union and then finished like those (up to 2x and 4x
+16280 vertices) and larger graphs solved entirely as chunks of a disjoint
+union; the middle classes are also forced onto the union path
+(``mid_limit(0)``) so both stay covered.  Ties, self-loops, parallel edges,
+isolated vertices, empty graphs and out-of-range ids are included.  Every
+graph's edge flags, total and status must equal the oracle's on that graph
+alone.
 """
 
 import numpy as np
@@ -68,22 +73,91 @@ def check_batch(dev, graphs, name):
         assert np.array_equal(in_mst[a:b], k.in_mst), f"{name} graph {i}: edge set"
 
 
-def test_batched_small_and_large(dev):
+# the mid-size class on its own path, and forced onto the union path
+MID_PATHS = {"mid": gpu_cases.MID_MAX, "union": 0}
+
+
+def batch_graphs(b):
+    return [(int(b.vertex_offsets[g + 1] - b.vertex_offsets[g]),) + tuple(
+        arr[b.edge_offsets[g]:b.edge_offsets[g + 1]] for arr in (b.src, b.dst, b.w)) for g in range(b.num_graphs)]
+
+
+@pytest.mark.parametrize("path", list(MID_PATHS))
+def test_batched_small_and_large(dev, path):
+    import paper_2005_06913_amd as P
     from paper_2005_06913_amd import graphgen as G
     b = G.batch(40, seed=7, n_lo=64, n_hi=40_000)
-    graphs = [(int(b.vertex_offsets[g + 1] - b.vertex_offsets[g]),) + tuple(
-        arr[b.edge_offsets[g]:b.edge_offsets[g + 1]] for arr in (b.src, b.dst, b.w)) for g in range(b.num_graphs)]
-    assert any(x[0] > 8192 for x in graphs) and any(x[0] <= 8192 for x in graphs)
-    check_batch(dev, graphs, "mixed_40")
+    graphs = batch_graphs(b)
+    assert any(x[0] > gpu_cases.SMALL_MAX for x in graphs) and any(x[0] <= gpu_cases.SMALL_MAX for x in graphs)
+    with P.mid_limit(MID_PATHS[path]):
+        check_batch(dev, graphs, f"mixed_40_{path}")
 
 
-def test_batched_degenerate_members(dev):
+@pytest.mark.parametrize("path", list(MID_PATHS))
+def test_batched_mid_boundaries(dev, path):
+    """Graphs at the edges of every class: 8193 and 16280 vertices (mid),
+    16281 and 32560 (one union round, then mid), 32561 and 65120 (two union
+    rounds, then mid), 65121 (union only), 2^21 edges exactly (mid, contracted)
+    and 2^21 + 1 (union only), path graphs whose first round joins everything
+    (increasing weights) or only halves the components (alternating weights)."""
+    import paper_2005_06913_amd as P
+    from paper_2005_06913_amd import graphgen as G
+    E = gpu_cases.MID_MAX_EDGES
+    M = gpu_cases.MID_MAX
+    n_alt = 2 * M - 7
+    alt = np.where(np.arange(n_alt - 1) % 2 == 0, 1000, 1).astype(np.uint32) + np.arange(n_alt - 1, dtype=np.uint32)
+    parts = [
+        G.tree_plus_extra(gpu_cases.SMALL_MAX + 1, 6 * gpu_cases.SMALL_MAX, seed=41),
+        G.tree_plus_extra(M, 8 * M, seed=42),
+        G.tree_plus_extra(M + 1, 3 * M, seed=43),
+        G.tree_plus_extra(2 * M, 4 * M, seed=46),
+        G.tree_plus_extra(2 * M + 1, 5 * M, seed=47),
+        G.tree_plus_extra(4 * M, 6 * M, seed=48),
+        G.tree_plus_extra(4 * M + 1, 6 * M, seed=49),
+        G.tree_plus_extra(12_000, E, seed=44),
+        G.tree_plus_extra(40_000, E, seed=50),
+        G.tree_plus_extra(12_000, E + 1, seed=45),
+        G.path_graph(M - 5),
+        G.path_graph(3 * M),
+        G.path_graph(n_alt, alt),
+    ]
+    graphs = [(g.n, g.src, g.dst, g.w) for g in parts]
+    with P.mid_limit(MID_PATHS[path]):
+        check_batch(dev, graphs, f"mid_boundaries_{path}")
+
+
+def test_batched_many_contracted(dev):
+    """Graphs of both contracted classes, more of them than one union chunk
+    holds, several average degrees, against the oracle."""
+    from paper_2005_06913_amd import graphgen as G
+    b = G.batch(140, seed=23, n_lo=gpu_cases.MID_MAX + 1, n_hi=4 * gpu_cases.MID_MAX, d_lo=2.0, d_hi=12.0)
+    assert sum(int(b.vertex_offsets[g + 1] - b.vertex_offsets[g]) for g in range(b.num_graphs)) > 1 << 22
+    check_batch(dev, batch_graphs(b), "many_contracted_140")
+
+
+def test_batched_many_mid(dev):
+    """Many mid-size graphs at once (more workgroups than the chip holds at a
+    time), several average degrees, against the oracle."""
+    from paper_2005_06913_amd import graphgen as G
+    b = G.batch(600, seed=19, n_lo=gpu_cases.SMALL_MAX + 1, n_hi=gpu_cases.MID_MAX, d_lo=2.0, d_hi=24.0)
+    check_batch(dev, batch_graphs(b), "many_mid_600")
+
+
+@pytest.mark.parametrize("path", list(MID_PATHS))
+def test_batched_degenerate_members(dev, path):
+    import paper_2005_06913_amd as P
+    with P.mid_limit(MID_PATHS[path]):
+        degenerate_members(dev, path)
+
+
+def degenerate_members(dev, path):
+    from paper_2005_06913_amd import graphgen as G
     graphs = []
     for name, n, s, d, w in gpu_cases.edge_cases():
         graphs.append((n, s, d, w))
     for g in gpu_cases.small_cases()[:6]:
         graphs.append((g.n, g.src, g.dst, g.w))
-    t = gpu_cases.ties_multigraph(9000, 40_000, seed=3)  # above the one-workgroup size, ties
+    t = gpu_cases.ties_multigraph(9000, 40_000, seed=3)  # above the all-LDS one-workgroup size, ties
     graphs.append((t.n, t.src, t.dst, t.w))
     # an out-of-range id in one small and one large graph: only those graphs fail
     graphs.append((5, np.array([0, 7], np.int32), np.array([1, 2], np.int32), np.array([1, 2], np.uint32)))
@@ -91,7 +165,19 @@ def test_batched_degenerate_members(dev):
     bs = big.src.copy()
     bs[17] = 10_000
     graphs.append((big.n, bs, big.dst, big.w))
-    check_batch(dev, graphs, "degenerate")
+    # the contracted classes: ties and an out-of-range id; isolated vertices
+    # (half the graph has no edge); a star, joined by its first round
+    for n, m, seed in ((25_000, 90_000, 5), (50_000, 150_000, 6)):
+        t = gpu_cases.ties_multigraph(n, m, seed=seed)
+        graphs.append((t.n, t.src, t.dst, t.w))
+        ts = t.src.copy()
+        ts[m // 2] = -3
+        graphs.append((t.n, ts, t.dst, t.w))
+    half = G.tree_plus_extra(20_000, 70_000, seed=7)
+    graphs.append((40_000, half.src, half.dst, half.w))
+    star = G.star_graph(30_000, seed=8)
+    graphs.append((star.n, star.src, star.dst, star.w))
+    check_batch(dev, graphs, f"degenerate_{path}")
 
 
 def test_batched_equals_single(dev):
