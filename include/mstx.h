@@ -200,15 +200,20 @@ int32_t mst_set_dense_limit(int32_t limit);
 int32_t mst_set_small_limit(int32_t limit);
 
 /*
- * Mid-size graphs of mst_solve_batched (Section 2.1's rounds, one launch for
- * all of them): a graph with more than 8192 and at most `limit` vertices and
- * at most 2097152 edges is solved by one workgroup that keeps each vertex's
+ * Mid-size graphs of mst_solve_batched (Section 2.1's rounds, one workgroup
+ * per graph): a graph with more than 8192 and at most `limit` vertices and at
+ * most 2097152 edges is solved by one workgroup that keeps each vertex's
  * minimum key and a 2-byte union-find in LDS (10 bytes per vertex) and reads
- * the graph's edges once per round, instead of as part of a disjoint union
- * solved by the round kernels.  The results are the same.  limit is clamped
- * to [0, 16280] (at most 8192: off; the default is 16280); limit < 0 only
- * queries.  Returns the previous limit.  Process-wide; read at the start of
- * each mst_solve_batched and mst_batched_workspace_bytes call.
+ * the graph's edges once per round.  A graph with more than `limit` and at
+ * most 65536 vertices (same edge bound) is first contracted by one workgroup
+ * round by round (minima in LDS windows, components renumbered densely, the
+ * edges rewritten as 16-bit pairs in the batched workspace) until at most
+ * `limit` components are left, which are then solved the same way.  Larger
+ * graphs, and all of them when this path is off, are solved as parts of a
+ * disjoint union by the round kernels.  The results are the same.  limit is
+ * clamped to [0, 16280] (at most 8192: off; the default is 16280); limit < 0
+ * only queries.  Returns the previous limit.  Process-wide; read at the start
+ * of each mst_solve_batched and mst_batched_workspace_bytes call.
  */
 int32_t mst_set_mid_limit(int32_t limit);
 

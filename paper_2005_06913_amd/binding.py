@@ -130,9 +130,10 @@ def mst_set_tail_limit(limit: int) -> int:
 
 def mst_set_mid_limit(limit: int) -> int:
     """Set the vertex count up to which mst_solve_batched solves a graph above
-    8192 vertices (and with at most 2^21 edges) with one workgroup instead of in
-    a disjoint-union chunk (at most 8192: off, clamped to 16280; negative:
-    query).  Returns the previous limit."""
+    8192 vertices (and with at most 2^21 edges) with one workgroup; graphs with
+    up to 65536 vertices are first contracted by one workgroup to at most that
+    many components.  At most 8192: off (disjoint-union chunks instead);
+    clamped to 16280; negative: query.  Returns the previous limit."""
     return int(load_library().mst_set_mid_limit(int(limit)))
 
 

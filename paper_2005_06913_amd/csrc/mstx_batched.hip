@@ -2,7 +2,7 @@
 //
 // The minimum spanning forest of a disjoint union of graphs is the union of
 // their forests, and Boruvka never merges components of different graphs, so
-// a batch is solved in three parts:
+// a batch is solved in four parts:
 //
 //   * graphs with at most kSmallN vertices: one workgroup per graph runs every
 //     Boruvka round of Section 2.1 with the vertex state in LDS (component of
@@ -11,7 +11,10 @@
 //     independently and in parallel;
 //   * graphs with up to kMidN vertices and kMidMaxEdges edges: one workgroup
 //     per graph as well, 10 bytes of LDS per vertex (minimum key and a 2-byte
-//     union-find), the edges streamed from memory every round;
+//     union-find), the edges streamed from memory every round (k_mid_solve);
+//   * graphs with up to kPreMaxN vertices (same edge bound): one workgroup per
+//     graph contracts it round by round until at most kMidN components are
+//     left (k_pre_contract), then k_mid_solve finishes the contracted graph;
 //   * larger graphs: gathered into chunks that are solved as one disjoint
 //     union by the single-graph round kernels (k_gather renumbers vertices and
 //     edges into the union, k_graph_epilogue scatters the flags back and sums
@@ -318,13 +321,12 @@ __device__ __forceinline__ int32_t p_cas(uint16_t* P, int32_t hi, int32_t lo) {
 // edges (zeroed by the caller), total[g] and status[g].
 //
 // kContracted: the graph is the contraction of batch graph g by its first
-// union rounds (see k_graph_epilogue): its vertices are the n' = nlist[i]
-// components left, its edges the graph's edges (same local indices, so the
-// same keys) with both ends given as 16-bit component numbers packed in
-// pairs[poff[i] + j] (a loop for an edge inside a component).  The union
-// rounds' edges are already flagged and their weight is in total[g]; their
-// count is pcnt[i] and pbad[i] flags out-of-range ids, so the status is that
-// of the whole graph.
+// rounds (k_pre_contract): its vertices are the n' = nlist[i] components left,
+// its edges the graph's edges (same local indices, so the same keys) with both
+// ends given as 16-bit component numbers packed in pairs[poff[i] + j] (a loop
+// for an edge inside a component).  The first rounds' edges are already
+// flagged and their weight is in total[g]; their count is pcnt[i] and pbad[i]
+// flags out-of-range ids, so the status is that of the whole graph.
 template <bool kContracted>
 __global__ void __launch_bounds__(kMidBlock) k_mid_solve(MidArgs A) {
   extern __shared__ unsigned long long mbest[];  // [n], then P [n] (whole words)
@@ -518,6 +520,296 @@ __global__ void __launch_bounds__(kMidBlock) k_mid_solve(MidArgs A) {
   }
 }
 
+// ------------------------------------------------------- mid-size contraction
+
+static constexpr int kPreBlock = 1024;
+static constexpr int kPrePer = kPreMaxN / kPreBlock;  // components per thread: tid + q * kPreBlock
+static constexpr int32_t kPreWin = kMaxDynLds / 8;    // minima per LDS window
+static constexpr uint16_t kNoLabel = 0xFFFF;          // a final component (no outgoing edge)
+static_assert(kPrePer <= 64, "one mask bit per owned component");
+
+// Exclusive prefix sum over the kPreBlock threads of the workgroup; *total
+// receives the sum.  Every thread must call it.
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* wsum /* [kPreBlock / 64] */,
+                                                         uint32_t* total) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  uint32_t x = v;
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
+  }
+  __syncthreads();  // wsum's previous contents are no longer read
+  if (lane == 63) wsum[wv] = x;
+  __syncthreads();
+  uint32_t before = 0, all = 0;
+  for (int i = 0; i < kPreBlock / 64; ++i) {
+    const uint32_t t = wsum[i];
+    if (i < wv) before += t;
+    all += t;
+  }
+  *total = all;
+  return before + x - v;
+}
+
+// One workgroup per graph of `glist` (n <= kPreMaxN, m <= kMidMaxEdges): the
+// rounds of Section 2.1 on densely numbered components while more than
+// `target` of them are left, so that the mid-size solve (k_mid_solve in its
+// contracted form) can finish the graph in LDS.  Components are numbered
+// 0 .. N-1 at the start of every round, so the ends of an edge are its
+// components; round 0 reads the caller's edges (ids checked against [0, n)),
+// later rounds the 16-bit pairs the previous round wrote.  Each round:
+//   minima    windows of kPreWin components in LDS (64-bit atomic min of
+//             (w << 32) | local index), each flushed to the graph's scratch;
+//   hooking   u16 union-find P[N] in LDS, CAS of the larger root under the
+//             smaller (partners are plain edge ends: no lookup races the
+//             hooks), the edge's flag, weight and count;
+//   numbering P flat (final roots through the scratch), then consecutive
+//             numbers for the roots that had a minimum edge (block scan); a
+//             root without one is a final component;
+//   edges     pairs[poff[i] + j] <- the new numbers of both ends, or a loop
+//             (0, 0) for an edge inside a final component or out of range.
+// Outputs: nlist[i] = components left (their numbers in the pairs), pcnt[i] =
+// edges added, pbad[i] = out-of-range ids seen, total[g] = their weight.
+__global__ void __launch_bounds__(kPreBlock) k_pre_contract(PreArgs A) {
+  extern __shared__ unsigned long long wbest[];      // [kPreWin] minima window
+  uint16_t* P = reinterpret_cast<uint16_t*>(wbest);  // [N] union-find, then the new numbers
+  __shared__ uint32_t wsum[kPreBlock / 64];
+  __shared__ uint32_t round_sel;
+  __shared__ uint32_t bad;
+  __shared__ unsigned long long red_w[kPreBlock / 64];
+  __shared__ uint32_t red_c[kPreBlock / 64];
+
+  const int i = blockIdx.x;
+  const int g = A.glist[i];
+  const int64_t e0 = A.eoff[g];
+  const int64_t m = A.eoff[g + 1] - e0;
+  const int32_t n = (int32_t)(A.voff[g + 1] - A.voff[g]);
+  const int tid = threadIdx.x;
+  if (n > kPreMaxN) {  // never: the host sends no such graph
+    if (tid == 0) A.nlist[i] = -1;
+    return;
+  }
+  unsigned long long* gbest = A.scratch + A.soff[i];  // [n]
+  int32_t* gtmp = reinterpret_cast<int32_t*>(gbest);  // [n], once the minima are read
+  const int32_t* gs = A.src + e0;
+  const int32_t* gd = A.dst + e0;
+  const uint32_t* gw = A.w + e0;
+  uint32_t* gp = A.pairs + A.poff[i];
+  if (tid == 0) bad = 0;
+  bool my_bad = false;
+  unsigned long long my_w = 0;
+  uint32_t my_cnt = 0;
+  int32_t N = n;
+  bool from_input = true;
+  __syncthreads();
+
+  // ends of edge j (clamped loads issued by the caller): from the caller's
+  // arrays, range-checked, or unpacked from a pair; false for a dropped edge
+  auto ends = [&](int32_t& a, int32_t& b) -> bool {
+    if (from_input) {
+      if ((uint32_t)a >= (uint32_t)n || (uint32_t)b >= (uint32_t)n) {
+        my_bad = true;
+        return false;
+      }
+      return true;
+    }
+    b = (int32_t)((uint32_t)a >> 16);
+    a &= 0xFFFF;
+    return true;
+  };
+
+  for (int round = 0; round < kMaxRounds && N > A.target && m > 0; ++round) {
+    // minima, one window of components at a time
+    for (int32_t lo = 0; lo < N; lo += kPreWin) {
+      const int32_t span = min(N - lo, kPreWin);
+      for (int32_t c = tid; c < span; c += kPreBlock) wbest[c] = kKeyNone;
+      __syncthreads();
+      for (int64_t j0 = 0; j0 < m; j0 += (int64_t)kMidUnroll * kPreBlock) {
+        int32_t a[kMidUnroll], b[kMidUnroll];
+        uint32_t c[kMidUnroll];
+#pragma unroll
+        for (int q = 0; q < kMidUnroll; ++q) {
+          const int64_t j = j0 + q * kPreBlock + tid;
+          const int64_t jc = j < m ? j : 0;
+          if (from_input) {
+            a[q] = gs[jc];
+            b[q] = gd[jc];
+          } else {
+            a[q] = (int32_t)gp[jc];
+          }
+          c[q] = gw[jc];
+        }
+        __asm__ __volatile__("" ::: "memory");
+#pragma unroll
+        for (int q = 0; q < kMidUnroll; ++q) {
+          const int64_t j = j0 + q * kPreBlock + tid;
+          if (j >= m || !ends(a[q], b[q]) || a[q] == b[q]) continue;
+          const unsigned long long key = ((unsigned long long)c[q] << 32) | (unsigned long long)j;
+          const uint32_t ra = (uint32_t)(a[q] - lo), rb = (uint32_t)(b[q] - lo);
+          if (ra < (uint32_t)span && key < wbest[ra]) atomicMin(wbest + ra, key);
+          if (rb < (uint32_t)span && key < wbest[rb]) atomicMin(wbest + rb, key);
+        }
+      }
+      __syncthreads();
+      for (int32_t c = tid; c < span; c += kPreBlock) gbest[lo + c] = wbest[c];
+      __syncthreads();
+    }
+    if (my_bad) bad = 1;
+    // hooking over the N components
+    for (int32_t c = tid; c < N; c += kPreBlock) P[c] = (uint16_t)c;
+    if (tid == 0) round_sel = 0;
+    __syncthreads();
+    uint64_t had = 0;  // bit q: component tid + q * kPreBlock had a minimum edge
+    uint32_t sel = 0;
+    for (int q0 = 0; q0 < kPrePer && tid + q0 * kPreBlock < N; q0 += 4) {
+      unsigned long long key[4], kd[4];
+      int32_t eu[4], ev[4], d[4];
+      bool has[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int32_t c = tid + (q0 + r) * kPreBlock;
+        key[r] = gbest[c < N ? c : 0];
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int32_t c = tid + (q0 + r) * kPreBlock;
+        has[r] = c < N && key[r] != kKeyNone;
+        const uint32_t j = has[r] ? (uint32_t)key[r] : 0u;  // a selected edge exists, so m > 0
+        if (from_input) {
+          eu[r] = gs[j];
+          ev[r] = gd[j];
+        } else {
+          eu[r] = (int32_t)gp[j];
+        }
+      }
+      __asm__ __volatile__("" ::: "memory");
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int32_t c = tid + (q0 + r) * kPreBlock;
+        if (!from_input) {
+          ev[r] = (int32_t)((uint32_t)eu[r] >> 16);
+          eu[r] &= 0xFFFF;
+        }
+        d[r] = (eu[r] == c) ? ev[r] : eu[r];  // a selected edge passed the range check
+        kd[r] = gbest[has[r] ? d[r] : 0];
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if (!has[r]) continue;
+        had |= 1ull << (q0 + r);
+        const int32_t c = tid + (q0 + r) * kPreBlock;
+        if (d[r] < c && kd[r] == key[r]) continue;  // mutual choice: d hooks it
+        int32_t x = c, y = d[r];
+        while (true) {
+          const int32_t rx = p_root(P, x);
+          const int32_t ry = p_root(P, y);
+          if (rx == ry) break;
+          const int32_t hi = rx > ry ? rx : ry;
+          const int32_t lo = rx > ry ? ry : rx;
+          const int32_t old = p_cas(P, hi, lo);
+          if (old == hi) {
+            A.in_mst[e0 + (uint32_t)key[r]] = 1;
+            my_w += (uint32_t)(key[r] >> 32);
+            ++sel;
+            break;
+          }
+          if (hi == rx) x = old;
+          else y = old;
+        }
+      }
+    }
+    my_cnt += sel;
+    sel = small_wave_sum(sel);
+    if ((tid & 63) == 0 && sel) atomicAdd(&round_sel, sel);
+    __syncthreads();
+    // flatten: final roots through the scratch (the minima are read), so no
+    // halving store can replace a final value
+    for (int32_t c = tid; c < N; c += kPreBlock) gtmp[c] = p_root(P, c);
+    __syncthreads();
+    for (int32_t c = tid; c < N; c += kPreBlock) P[c] = (uint16_t)gtmp[c];
+    __syncthreads();
+    // consecutive numbers for the roots that had a minimum edge
+    uint32_t roots = 0;
+#pragma unroll 8
+    for (int q = 0; q < kPrePer; ++q) {
+      const int32_t c = tid + q * kPreBlock;
+      if (c < N && P[c] == c && ((had >> q) & 1)) ++roots;
+    }
+    uint32_t n_next = 0;
+    uint32_t next = block_exclusive_scan(roots, wsum, &n_next);
+#pragma unroll 8
+    for (int q = 0; q < kPrePer; ++q) {
+      const int32_t c = tid + q * kPreBlock;
+      if (c < N && P[c] == c) gtmp[c] = ((had >> q) & 1) ? (int32_t)next++ : -1;
+    }
+    __syncthreads();
+    for (int32_t c = tid; c < N; c += kPreBlock) {
+      const int32_t l = gtmp[P[c]];
+      P[c] = l < 0 ? kNoLabel : (uint16_t)l;
+    }
+    __syncthreads();
+    // the edges as pairs of the new numbers
+    for (int64_t j0 = 0; j0 < m; j0 += (int64_t)kMidUnroll * kPreBlock) {
+      int32_t a[kMidUnroll], b[kMidUnroll];
+#pragma unroll
+      for (int q = 0; q < kMidUnroll; ++q) {
+        const int64_t j = j0 + q * kPreBlock + tid;
+        const int64_t jc = j < m ? j : 0;
+        if (from_input) {
+          a[q] = gs[jc];
+          b[q] = gd[jc];
+        } else {
+          a[q] = (int32_t)gp[jc];
+        }
+      }
+      __asm__ __volatile__("" ::: "memory");
+#pragma unroll
+      for (int q = 0; q < kMidUnroll; ++q) {
+        const int64_t j = j0 + q * kPreBlock + tid;
+        if (j >= m) continue;
+        uint32_t pr = 0;
+        if (ends(a[q], b[q])) {
+          const uint32_t la = P[a[q]], lb = P[b[q]];
+          if (la != kNoLabel && lb != kNoLabel) pr = la | (lb << 16);
+        }
+        gp[j] = pr;
+      }
+    }
+    __syncthreads();
+    N = (int32_t)n_next;
+    from_input = false;
+  }
+  if (from_input && m > 0) {
+    // no round ran (at most `target` vertices): the ends as they are
+    for (int64_t j = tid; j < m; j += kPreBlock) {
+      int32_t a = gs[j], b = gd[j];
+      gp[j] = ends(a, b) ? ((uint32_t)a | ((uint32_t)b << 16)) : 0u;
+    }
+    if (my_bad) bad = 1;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    my_w += __shfl_xor(my_w, off, 64);
+    my_cnt += __shfl_xor(my_cnt, off, 64);
+  }
+  if ((tid & 63) == 0) {
+    red_w[tid >> 6] = my_w;
+    red_c[tid >> 6] = my_cnt;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    unsigned long long tw = 0;
+    uint32_t tc = 0;
+    for (int k = 0; k < kPreBlock / 64; ++k) {
+      tw += red_w[k];
+      tc += red_c[k];
+    }
+    A.total[g] = tw;
+    A.pcnt[i] = (int32_t)tc;
+    A.pbad[i] = bad;
+    A.nlist[i] = N;
+  }
+}
+
 // Union of the chunk's graphs glist[0..ng): chunk edge p belongs to graph k with
 // cedge[k] <= p < cedge[k+1]; its ends become union ids cvert[k] + local id.
 // An end outside [0, n_g) makes the edge a self-loop at cvert[k] and flags the
@@ -573,73 +865,15 @@ __global__ void __launch_bounds__(256) k_gather(const int32_t* __restrict__ glis
 // range of graph glist[k] and adds the weight and count of the marked edges
 // of the slice to acc_w[k], acc_c[k] (zeroed by the caller; one atomic per
 // workgroup).
-// ------------------------------------------------------------ contraction
-//
-// A chunk of graphs whose union has run its first Boruvka rounds is finished
-// graph by graph on the mid-size path: every graph's remaining components get
-// consecutive numbers from 0 (k_contract_labels, k_contract_bounds) and its
-// edges become pairs of those numbers (k_graph_epilogue).
-
-// vlab[v] = the component of union vertex v after `rounds` rounds, as that
-// round's label (-1: the component had no outgoing edge, so it is final).
-__global__ void __launch_bounds__(256) k_contract_labels(int rounds, int32_t n, const int32_t* __restrict__ labpool,
-                                                         const DevState* __restrict__ st,
-                                                         int32_t* __restrict__ vlab) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
-    int32_t x = labpool[st->lab_off[0] + v];
-    for (int r = 1; r < rounds && x >= 0; ++r) x = st->n[r] <= 1 ? -1 : labpool[st->lab_off[r] + x];
-    vlab[v] = x;
-  }
-}
-
-// Per chunk graph k (one workgroup each): its first component label and the
-// number of its components.  Labels are given in increasing order of the
-// components' roots and no component spans two graphs, so a graph's labels
-// are consecutive.
-static constexpr int kBoundsBlock = 1024;
-__global__ void __launch_bounds__(kBoundsBlock) k_contract_bounds(const int64_t* __restrict__ cvert,
-                                                                  const int32_t* __restrict__ vlab,
-                                                                  int32_t* __restrict__ cbase,
-                                                                  int32_t* __restrict__ cnum) {
-  __shared__ int32_t slo[kBoundsBlock / 64], shi[kBoundsBlock / 64];
-  const int k = blockIdx.x;
-  int32_t lo = INT32_MAX, hi = -1;
-  for (int64_t v = cvert[k] + threadIdx.x; v < cvert[k + 1]; v += kBoundsBlock) {
-    const int32_t x = vlab[v];
-    if (x >= 0) {
-      lo = min(lo, x);
-      hi = max(hi, x);
-    }
-  }
-  for (int off = 32; off > 0; off >>= 1) {
-    lo = min(lo, __shfl_xor(lo, off, 64));
-    hi = max(hi, __shfl_xor(hi, off, 64));
-  }
-  if ((threadIdx.x & 63) == 0) {
-    slo[threadIdx.x >> 6] = lo;
-    shi[threadIdx.x >> 6] = hi;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int i = 1; i < kBoundsBlock / 64; ++i) {
-      lo = min(lo, slo[i]);
-      hi = max(hi, shi[i]);
-    }
-    cbase[k] = hi < 0 ? 0 : lo;
-    cnum[k] = hi < 0 ? 0 : hi - lo + 1;
-  }
-}
-
 static constexpr int64_t kEpilogueSlice = 16384;  // edges per workgroup (at least)
+static constexpr int kEpilogueUnroll = 8;          // edges per thread in flight
 __global__ void __launch_bounds__(256) k_graph_epilogue(const int32_t* __restrict__ glist, int64_t slice,
                                                         const int64_t* __restrict__ eoff,
                                                         const int64_t* __restrict__ cedge,
-                                                        const uint8_t* __restrict__ cin_mst,
-                                                        const uint32_t* __restrict__ gw,
+                                                        const uint8_t* cin_mst, const uint32_t* gw,
                                                         uint8_t* __restrict__ in_mst,
                                                         unsigned long long* __restrict__ acc_w,
-                                                        uint32_t* __restrict__ acc_c, ContractArgs C) {
+                                                        uint32_t* __restrict__ acc_c) {
   __shared__ unsigned long long rw[4];
   __shared__ uint32_t rc[4];
   const int k = blockIdx.x;
@@ -649,20 +883,29 @@ __global__ void __launch_bounds__(256) k_graph_epilogue(const int32_t* __restric
   const int64_t to = eoff[glist[k]] - cedge[k];  // caller index = chunk index + to
   unsigned long long sw = 0;
   uint32_t cnt = 0;
-  const int32_t base = C.vlab ? C.cbase[k] : 0;
-  const int64_t pair_at = C.vlab ? C.poff[k] - cedge[k] : 0;  // pair index = chunk edge index + pair_at
-  for (int64_t p = p_first + threadIdx.x; p < p_end; p += blockDim.x) {
-    const uint8_t f = cin_mst[p];
-    in_mst[p + to] = f;
-    if (f) {
-      sw += gw[p];
-      ++cnt;
+  // kEpilogueUnroll edges per thread with their loads (clamped to the
+  // slice's first edge) in flight together; the memory clobbers keep them
+  // issued before the first use
+  for (int64_t p0 = p_first + threadIdx.x; p0 < p_end; p0 += kEpilogueUnroll * 256) {
+    uint8_t f[kEpilogueUnroll];
+    uint32_t wq[kEpilogueUnroll];
+#pragma unroll
+    for (int q = 0; q < kEpilogueUnroll; ++q) {
+      const int64_t p = p0 + q * 256;
+      const int64_t pc = p < p_end ? p : p_first;
+      f[q] = cin_mst[pc];
+      wq[q] = gw[pc];
     }
-    if (C.vlab) {
-      // both ends' components after the union rounds, numbered from the
-      // graph's first; an edge inside a final component becomes a loop
-      const int32_t a = C.vlab[C.gsrc[p]], b = C.vlab[C.gdst[p]];
-      C.pairs[p + pair_at] = (a >= 0 && b >= 0) ? ((uint32_t)(a - base) | ((uint32_t)(b - base) << 16)) : 0u;
+    __asm__ __volatile__("" ::: "memory");
+#pragma unroll
+    for (int q = 0; q < kEpilogueUnroll; ++q) {
+      const int64_t p = p0 + q * 256;
+      if (p >= p_end) continue;
+      in_mst[p + to] = f[q];
+      if (f[q]) {
+        sw += wq[q];
+        ++cnt;
+      }
     }
   }
   for (int off = 32; off > 0; off >>= 1) {
@@ -689,18 +932,12 @@ __global__ void __launch_bounds__(256) k_graph_status(const int32_t* __restrict_
                                                       const uint32_t* __restrict__ acc_c,
                                                       const int32_t* __restrict__ gbad,
                                                       unsigned long long* __restrict__ total_out,
-                                                      int32_t* __restrict__ status_out, int32_t* __restrict__ pcnt,
-                                                      int32_t* __restrict__ pbad) {
+                                                      int32_t* __restrict__ status_out) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= ng) return;
   const int g = glist[k];
   const int64_t n = voff[g + 1] - voff[g];
   total_out[g] = acc_w[k];
-  if (pcnt) {  // contracted graph: the mid-size solve finishes it
-    pcnt[k] = (int32_t)acc_c[k];
-    pbad[k] = gbad[k];
-    return;
-  }
   int32_t st = (n <= 1 || (int64_t)acc_c[k] == n - 1) ? MSTX_OK : MSTX_DISCONNECTED;
   if (gbad[k]) st = MSTX_ERR_VERTEX_RANGE;
   status_out[g] = st;
@@ -713,8 +950,11 @@ hipError_t configure_batched_kernels() {
   e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mid_solve<false>),
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxDynLds);
   if (e != hipSuccess) return e;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mid_solve<true>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxDynLds);
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mid_solve<true>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxDynLds);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pre_contract), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)kMaxDynLds);
 }
 
 hipError_t launch_mid_solve(const MidArgs& A, int num, int32_t max_n, bool contracted, hipStream_t s) {
@@ -726,16 +966,13 @@ hipError_t launch_mid_solve(const MidArgs& A, int num, int32_t max_n, bool contr
   return hipGetLastError();
 }
 
-hipError_t launch_contract(int rounds, int32_t n, const int32_t* labpool, const DevState* st, int32_t* vlab, int ng,
-                           const int64_t* cvert, int32_t* cbase, int32_t* cnum, hipStream_t s) {
-  if (ng <= 0 || n <= 0) return hipSuccess;
-  const int grid = (int)std::min<int64_t>(8192, ((int64_t)n + 255) / 256);
-  k_contract_labels<<<grid, 256, 0, s>>>(rounds, n, labpool, st, vlab);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  k_contract_bounds<<<ng, kBoundsBlock, 0, s>>>(cvert, vlab, cbase, cnum);
+hipError_t launch_pre_contract(const PreArgs& A, int num, hipStream_t s) {
+  if (num <= 0) return hipSuccess;
+  if (A.target < 1 || A.target > kMidN) return hipErrorInvalidValue;
+  k_pre_contract<<<num, kPreBlock, kMaxDynLds, s>>>(A);
   return hipGetLastError();
 }
+
 
 hipError_t launch_small_solve(const int32_t* glist, int num, const int64_t* voff, const int64_t* eoff,
                               const int32_t* src, const int32_t* dst, const uint32_t* w, uint8_t* in_mst,
@@ -772,8 +1009,7 @@ hipError_t launch_graph_epilogue(const int32_t* glist, int ng, const int64_t* vo
                                  const int64_t* cedge, int64_t max_graph_m, const uint8_t* cin_mst,
                                  const uint32_t* gw, const int32_t* gbad, uint8_t* in_mst,
                                  unsigned long long* acc_w, uint32_t* acc_c, unsigned long long* total,
-                                 int32_t* status, const ContractArgs& C, int32_t* pcnt, int32_t* pbad,
-                                 hipStream_t s) {
+                                 int32_t* status, hipStream_t s) {
   if (ng <= 0) return hipSuccess;
   hipError_t e = hipMemsetAsync(acc_w, 0, 8 * (size_t)ng, s);
   if (e == hipSuccess) e = hipMemsetAsync(acc_c, 0, 4 * (size_t)ng, s);
@@ -782,11 +1018,10 @@ hipError_t launch_graph_epilogue(const int32_t* glist, int ng, const int64_t* vo
   const int64_t slice = std::max<int64_t>(kEpilogueSlice, (max_graph_m + 65534) / 65535);
   const int64_t slices = std::max<int64_t>(1, (max_graph_m + slice - 1) / slice);
   k_graph_epilogue<<<dim3(ng, (unsigned)slices), 256, 0, s>>>(glist, slice, eoff, cedge, cin_mst, gw, in_mst,
-                                                               acc_w, acc_c, C);
+                                                               acc_w, acc_c);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  k_graph_status<<<(ng + 255) / 256, 256, 0, s>>>(glist, ng, voff, acc_w, acc_c, gbad, total, status, pcnt,
-                                                   pbad);
+  k_graph_status<<<(ng + 255) / 256, 256, 0, s>>>(glist, ng, voff, acc_w, acc_c, gbad, total, status);
   return hipGetLastError();
 }
 

@@ -606,46 +606,6 @@ int solve_locked(DeviceCache* dc, const Layout& L, int32_t n, int64_t m, const i
   return status;
 }
 
-// The first `rounds` (1 or 2) Boruvka rounds of a graph (n >= 1, m >= 1), no
-// more: their edges are flagged in in_mst, and the label maps of every round
-// stay in the label pool for the contraction that follows.  No dense finish
-// (it would end the solve without a label map).  The device cache is locked
-// by the caller.
-int contract_locked(DeviceCache* dc, const Layout& L, int32_t n, int64_t m, const int32_t* src, const int32_t* dst,
-                    const uint32_t* w, uint8_t* in_mst, uint64_t* total, int rounds, hipStream_t s) {
-  Solve S = make_solve(dc, L, n, m, src, dst, w, in_mst, total, s);
-  S.dense_limit = 0;
-  LaunchTimer& T = t_timer;
-  T.begin(s);
-  HIP_OK(hipMemsetAsync(in_mst, 0, (size_t)m, s));
-  HIP_OK(hipMemsetAsync(total, 0, sizeof(uint64_t), s));
-  HIP_OK(launch_init(n, S.best, S.parent, nullptr, S.btot, S.st, grid_for(n), s));
-  for (int r = 0; r <= kMaxRounds; ++r) dc->host_rounds[r].n_next = kRecordPending;
-  std::atomic_thread_fence(std::memory_order_seq_cst);
-  HIP_OK(enqueue_round(S, 0, n));
-  if (rounds >= 2) HIP_OK(enqueue_round(S, 1, n / 2, n));  // each round at least halves the components
-  HIP_OK(hipStreamSynchronize(s));
-  std::vector<int32_t> nr_of(kMaxRounds + 2, 0);
-  nr_of[0] = n;
-  int done = 0;
-  for (int r = 0; r < rounds; ++r) {
-    const HostRound M = load_record(dc->host_rounds + r);
-    // ids were made valid by the gather, so any error is internal
-    if (M.n_next == kRecordPending || M.err || M.err_internal) return MSTX_ERR_DEVICE;
-    done = r + 1;
-    nr_of[r + 1] = M.n_next;
-    if (M.n_next <= 1) break;  // a later round did nothing (and wrote no record)
-  }
-  std::vector<int> chosen(kMaxRounds + 1, -1);
-  std::vector<double> bytes(kMaxRounds + 1, 0.0);
-  for (int r = 0; r < done; ++r) {
-    chosen[r] = pick_mode(nr_of[r], S.launched[r]);
-    bytes[r] = round_scan_bytes(dc->host_rounds, nr_of, r, n, m);
-  }
-  T.commit(done, chosen, bytes);
-  return MSTX_OK;
-}
-
 // A graph of at most kSmallN vertices in one launch (the batched path's
 // one-workgroup solve); the cache is locked by the caller.
 int solve_small_locked(DeviceCache* dc, int32_t n, int64_t m, const int32_t* src, const int32_t* dst,
@@ -711,32 +671,29 @@ int solve(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, const ui
 // ----------------------------------------------------------------- batched
 
 // Which path a graph of a batch takes: one workgroup with everything in LDS
-// (small); one workgroup with the edges streamed every round (mid); the first
-// one or two rounds in a chunk of the disjoint union solved by the round
-// kernels, then the mid path on what is left (contract1 / contract2: each
-// round at least halves the components, so at most mid_limit remain); or
-// every round in a union chunk (large).
-enum class BatchPath { kSmall, kMid, kContract1, kContract2, kLarge };
+// (small); one workgroup with the edges streamed every round (mid); one
+// workgroup contracting it round by round until at most mid_limit components
+// are left, then the mid path on those (contract); or every round in a chunk
+// of the disjoint union solved by the round kernels (large).
+enum class BatchPath { kSmall, kMid, kContract, kLarge };
 BatchPath batch_path(int64_t n, int64_t m, int32_t mid_limit) {
   if (n <= kSmallN) return BatchPath::kSmall;
   if (mid_limit > kSmallN && m <= kMidMaxEdges) {
     if (n <= mid_limit) return BatchPath::kMid;
-    if (n <= 2 * (int64_t)mid_limit) return BatchPath::kContract1;
-    if (n <= 4 * (int64_t)mid_limit) return BatchPath::kContract2;
+    if (n <= kPreMaxN) return BatchPath::kContract;
   }
   return BatchPath::kLarge;
 }
 
 // Device scratch of a batched call besides the solve workspace.
 struct BatchLayout {
-  size_t voff, eoff, small, mid, large, cvert, cedge, gbad, gsrc, gdst, gw, cin, total, acc_w, acc_c, cpoff,
-      cbase, cnum, pcnt, pbad, pairs, bytes;
+  size_t voff, eoff, small, mid, large, cvert, cedge, gbad, gsrc, gdst, gw, cin, total, acc_w, acc_c, con, cpoff,
+      csoff, cscratch, cnum, pcnt, pbad, pairs, bytes;
 };
 
-// nlarge counts every graph that goes through a union chunk (ncon of them
-// are then contracted, with con_m edges in all).
+// ncon graphs are contracted, with con_n vertices and con_m edges in all.
 BatchLayout plan_batch(int32_t G, int64_t nsmall, int64_t nmid, int64_t nlarge, int64_t nchunk_meta,
-                       int64_t max_chunk_m, int64_t ncon, int64_t con_m) {
+                       int64_t max_chunk_m, int64_t ncon, int64_t con_n, int64_t con_m) {
   BatchLayout B{};
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -759,8 +716,10 @@ BatchLayout plan_batch(int32_t G, int64_t nsmall, int64_t nmid, int64_t nlarge, 
   B.total = take(8);
   B.acc_w = take(8 * (size_t)std::max<int64_t>(nlarge, 1));
   B.acc_c = take(4 * (size_t)std::max<int64_t>(nlarge, 1));
+  B.con = take(4 * (size_t)std::max<int64_t>(ncon, 1));
   B.cpoff = take(8 * (size_t)std::max<int64_t>(ncon, 1));
-  B.cbase = take(4 * (size_t)std::max<int64_t>(ncon, 1));
+  B.csoff = take(8 * (size_t)std::max<int64_t>(ncon, 1));
+  B.cscratch = take(8 * (size_t)std::max<int64_t>(con_n, 1));
   B.cnum = take(4 * (size_t)std::max<int64_t>(ncon, 1));
   B.pcnt = take(4 * (size_t)std::max<int64_t>(ncon, 1));
   B.pbad = take(4 * (size_t)std::max<int64_t>(ncon, 1));
@@ -803,64 +762,51 @@ int check_batch_args(int32_t G, const int64_t* voff, const int64_t* eoff, const 
 
 // How a batch is split: the graphs of each path and the union chunks.
 struct BatchPlan {
-  std::vector<int32_t> small, mid;
-  // graphs that go through union chunks: those solved there entirely
-  // (uni[0..nplain)), then the contracted ones (two rounds, then one)
-  std::vector<int32_t> uni;
-  int64_t nplain = 0;
-  // chunk c: uni[cfirst[c] .. cfirst[c + 1]), its first crounds[c] rounds in
-  // the union (0: all of them); its graphs' vertex and edge offsets inside the
-  // union are cvert / cedge[meta_at[c] ..] (ng + 1 each)
+  std::vector<int32_t> small, mid, con, uni;
+  // chunk c: uni[cfirst[c] .. cfirst[c + 1]); its graphs' vertex and edge
+  // offsets inside the union are cvert / cedge[meta_at[c] ..] (ng + 1 each)
   std::vector<int32_t> cfirst;
-  std::vector<int> crounds;
   std::vector<int64_t> cvert, cedge, meta_at;
-  std::vector<int64_t> cpoff;  // contracted graph i = uni[nplain + i]: start of its edge pairs
-  int64_t con_m = 0;
+  std::vector<int64_t> cpoff, csoff;  // contracted graph i: start of its edge pairs, of its scratch
+  int64_t con_n = 0, con_m = 0;
   int64_t max_chunk_n = 0, max_chunk_m = 0;
   int32_t mid_max_n = 0;
 };
 
 BatchPlan plan_batch_graphs(int32_t G, const int64_t* voff, const int64_t* eoff, int32_t mid_limit) {
   BatchPlan P;
-  std::vector<int32_t> plain, con2, con1;
   for (int32_t g = 0; g < G; ++g) {
     switch (batch_path(voff[g + 1] - voff[g], eoff[g + 1] - eoff[g], mid_limit)) {
       case BatchPath::kSmall: P.small.push_back(g); break;
       case BatchPath::kMid: P.mid.push_back(g); break;
-      case BatchPath::kContract1: con1.push_back(g); break;
-      case BatchPath::kContract2: con2.push_back(g); break;
-      case BatchPath::kLarge: plain.push_back(g); break;
+      case BatchPath::kContract: P.con.push_back(g); break;
+      case BatchPath::kLarge: P.uni.push_back(g); break;
     }
   }
   // most edges first, so the longest workgroups of a launch start first
   auto more_edges = [&](int32_t a, int32_t b) { return eoff[a + 1] - eoff[a] > eoff[b + 1] - eoff[b]; };
-  for (auto* v : {&P.small, &P.mid, &plain, &con2, &con1}) std::stable_sort(v->begin(), v->end(), more_edges);
+  for (auto* v : {&P.small, &P.mid, &P.con, &P.uni}) std::stable_sort(v->begin(), v->end(), more_edges);
   for (int32_t g : P.mid) P.mid_max_n = std::max<int32_t>(P.mid_max_n, (int32_t)(voff[g + 1] - voff[g]));
-  P.uni = plain;
-  P.uni.insert(P.uni.end(), con2.begin(), con2.end());
-  P.uni.insert(P.uni.end(), con1.begin(), con1.end());
-  P.nplain = (int64_t)plain.size();
-  // chunks: consecutive graphs of one kind, union within the bucket-mode limit
-  auto add_chunks = [&](int32_t i0, int32_t i1, int rounds) {
-    int64_t cn = 0, cm = 0;
-    for (int32_t i = i0; i < i1; ++i) {
-      const int32_t g = P.uni[i];
-      const int64_t ng = voff[g + 1] - voff[g], mg = eoff[g + 1] - eoff[g];
-      if (i == i0 || cn + ng > kBucketMaxComponents || cm + mg > (int64_t)0xFFFFFFFFLL) {
-        P.cfirst.push_back(i);
-        P.crounds.push_back(rounds);
-        cn = cm = 0;
-      }
-      cn += ng;
-      cm += mg;
-      P.max_chunk_n = std::max(P.max_chunk_n, cn);
-      P.max_chunk_m = std::max(P.max_chunk_m, cm);
+  for (int32_t g : P.con) {
+    P.cpoff.push_back(P.con_m);
+    P.csoff.push_back(P.con_n);
+    P.con_m += eoff[g + 1] - eoff[g];
+    P.con_n += voff[g + 1] - voff[g];
+  }
+  // chunks: consecutive graphs, union within the bucket-mode limit
+  int64_t cn = 0, cm = 0;
+  for (int32_t i = 0; i < (int32_t)P.uni.size(); ++i) {
+    const int32_t g = P.uni[i];
+    const int64_t ng = voff[g + 1] - voff[g], mg = eoff[g + 1] - eoff[g];
+    if (i == 0 || cn + ng > kBucketMaxComponents || cm + mg > (int64_t)0xFFFFFFFFLL) {
+      P.cfirst.push_back(i);
+      cn = cm = 0;
     }
-  };
-  const int32_t n2 = (int32_t)(P.nplain + (int64_t)con2.size());
-  add_chunks(0, (int32_t)P.nplain, 0);
-  add_chunks((int32_t)P.nplain, n2, 2);
-  add_chunks(n2, (int32_t)P.uni.size(), 1);
+    cn += ng;
+    cm += mg;
+    P.max_chunk_n = std::max(P.max_chunk_n, cn);
+    P.max_chunk_m = std::max(P.max_chunk_m, cm);
+  }
   P.cfirst.push_back((int32_t)P.uni.size());
   for (size_t c = 0; c + 1 < P.cfirst.size(); ++c) {
     P.meta_at.push_back((int64_t)P.cvert.size());
@@ -874,16 +820,12 @@ BatchPlan plan_batch_graphs(int32_t G, const int64_t* voff, const int64_t* eoff,
     P.cvert.push_back(a);
     P.cedge.push_back(b);
   }
-  for (size_t i = (size_t)P.nplain; i < P.uni.size(); ++i) {
-    P.cpoff.push_back(P.con_m);
-    P.con_m += eoff[P.uni[i] + 1] - eoff[P.uni[i]];
-  }
   return P;
 }
 
 BatchLayout plan_batch(int32_t G, const BatchPlan& P) {
   return plan_batch(G, (int64_t)P.small.size(), (int64_t)P.mid.size(), (int64_t)P.uni.size(), (int64_t)P.cvert.size(),
-                    P.max_chunk_m, (int64_t)P.cpoff.size(), P.con_m);
+                    P.max_chunk_m, (int64_t)P.con.size(), P.con_n, P.con_m);
 }
 
 int solve_batched(int32_t G, const int64_t* voff, const int64_t* eoff, const int32_t* src, const int32_t* dst,
@@ -893,7 +835,7 @@ int solve_batched(int32_t G, const int64_t* voff, const int64_t* eoff, const int
   const int32_t mid_limit = g_mid_limit.load();
   const BatchPlan P = plan_batch_graphs(G, voff, eoff, mid_limit);
   if (P.max_chunk_n > INT32_MAX) return MSTX_ERR_TOO_LARGE;
-  const int64_t nuni = (int64_t)P.uni.size(), ncon = (int64_t)P.cpoff.size();
+  const int64_t nuni = (int64_t)P.uni.size(), ncon = (int64_t)P.con.size();
   const Layout L = plan((int32_t)std::max<int64_t>(P.max_chunk_n, 1), std::max<int64_t>(P.max_chunk_m, 1));
   const BatchLayout BL = plan_batch(G, P);
   if (L.bytes + BL.bytes > workspace_limit()) return MSTX_ERR_OUT_OF_MEMORY;
@@ -918,8 +860,9 @@ int solve_batched(int32_t G, const int64_t* voff, const int64_t* eoff, const int
   auto* gw = at<uint32_t>(A, BL.gw);
   auto* cin = at<uint8_t>(A, BL.cin);
   auto* ctotal = at<uint64_t>(A, BL.total);
+  auto* d_con = at<int32_t>(A, BL.con);
   auto* d_cpoff = at<int64_t>(A, BL.cpoff);
-  auto* d_cbase = at<int32_t>(A, BL.cbase);
+  auto* d_csoff = at<int64_t>(A, BL.csoff);
   auto* d_cnum = at<int32_t>(A, BL.cnum);
   auto* d_pcnt = at<int32_t>(A, BL.pcnt);
   auto* d_pbad = at<int32_t>(A, BL.pbad);
@@ -937,8 +880,23 @@ int solve_batched(int32_t G, const int64_t* voff, const int64_t* eoff, const int
     HIP_OK(hipMemcpyAsync(d_cedge, P.cedge.data(), 8 * P.cedge.size(), hipMemcpyHostToDevice, s));
     HIP_OK(hipMemsetAsync(d_gbad, 0, 4 * (size_t)nuni, s));
   }
-  if (ncon > 0) HIP_OK(hipMemcpyAsync(d_cpoff, P.cpoff.data(), 8 * (size_t)ncon, hipMemcpyHostToDevice, s));
+  if (ncon > 0) {
+    HIP_OK(hipMemcpyAsync(d_con, P.con.data(), 4 * (size_t)ncon, hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(d_cpoff, P.cpoff.data(), 8 * (size_t)ncon, hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(d_csoff, P.csoff.data(), 8 * (size_t)ncon, hipMemcpyHostToDevice, s));
+  }
   if (eoff[G] > 0) HIP_OK(hipMemsetAsync(in_mst, 0, (size_t)eoff[G], s));
+  if (ncon > 0) {
+    // the contracted graphs: their first rounds, then the mid-size solve on
+    // the at most mid_limit components left
+    const int32_t max_n = std::min<int32_t>(mid_limit, kMidN);
+    const PreArgs C{d_con,   d_voff,  d_eoff, src,    dst, w,   d_csoff, at<unsigned long long>(A, BL.cscratch),
+                    d_pairs, d_cpoff, d_cnum, d_pcnt, d_pbad, in_mst, tot,  max_n};
+    HIP_OK(launch_pre_contract(C, (int)ncon, s));
+    const MidArgs M{d_con,  d_voff, d_eoff, nullptr, nullptr, w,   d_pairs, d_cpoff,
+                    d_cnum, d_pcnt, d_pbad, in_mst,  tot,     status, max_n};
+    HIP_OK(launch_mid_solve(M, (int)ncon, max_n, true, s));
+  }
   {
     const MidArgs M{d_mid,   d_voff,  d_eoff,  src,    dst, w,      nullptr, nullptr,
                     nullptr, nullptr, nullptr, in_mst, tot, status, P.mid_max_n};
@@ -948,49 +906,23 @@ int solve_batched(int32_t G, const int64_t* voff, const int64_t* eoff, const int
 
   for (size_t c = 0; c + 1 < P.cfirst.size(); ++c) {
     const int32_t i0 = P.cfirst[c], ng = P.cfirst[c + 1] - i0;
-    const int rounds = P.crounds[c];
     const int64_t at_meta = P.meta_at[c];
     const int64_t cn = P.cvert[at_meta + ng], cm = P.cedge[at_meta + ng];
     HIP_OK(launch_gather(d_uni + i0, ng, d_voff, d_eoff, d_cvert + at_meta, d_cedge + at_meta, cm, src, dst, w,
                          gsrc, gdst, gw, d_gbad + i0, s));
-    const Layout Lc = plan((int32_t)cn, std::max<int64_t>(cm, 1));
     if (cm > 0) {
-      rc = rounds == 0 ? solve_locked(dc, Lc, (int32_t)cn, cm, gsrc, gdst, gw, cin, ctotal, s)
-                       : contract_locked(dc, Lc, (int32_t)cn, cm, gsrc, gdst, gw, cin, ctotal, rounds, s);
+      const Layout Lc = plan((int32_t)cn, cm);
+      rc = solve_locked(dc, Lc, (int32_t)cn, cm, gsrc, gdst, gw, cin, ctotal, s);
       if (rc < 0) return rc;
     } else {
       HIP_OK(hipMemsetAsync(cin, 0, 1, s));
-    }
-    ContractArgs C{};
-    int32_t* pcnt = nullptr;
-    int32_t* pbad = nullptr;
-    if (rounds > 0) {
-      const int64_t pos0 = i0 - P.nplain;
-      if (cm > 0) {
-        int32_t* vlab = at<int32_t>(dc->base, Lc.root_of);  // free once the rounds are done
-        HIP_OK(launch_contract(rounds, (int32_t)cn, at<int32_t>(dc->base, Lc.labpool), at<DevState>(dc->base, Lc.state),
-                               vlab, ng, d_cvert + at_meta, d_cbase + pos0, d_cnum + pos0, s));
-        C = ContractArgs{vlab, d_cbase + pos0, gsrc, gdst, d_pairs, d_cpoff + pos0};
-      } else {
-        HIP_OK(hipMemsetAsync(d_cnum + pos0, 0, 4 * (size_t)ng, s));  // no edges: nothing left to join
-      }
-      pcnt = d_pcnt + pos0;
-      pbad = d_pbad + pos0;
     }
     int64_t max_graph_m = 0;
     for (int32_t q = 0; q < ng; ++q)
       max_graph_m = std::max(max_graph_m, P.cedge[at_meta + q + 1] - P.cedge[at_meta + q]);
     HIP_OK(launch_graph_epilogue(d_uni + i0, ng, d_voff, d_eoff, d_cedge + at_meta, max_graph_m, cin, gw,
                                  d_gbad + i0, in_mst, at<unsigned long long>(A, BL.acc_w),
-                                 at<uint32_t>(A, BL.acc_c), tot, status, C, pcnt, pbad, s));
-  }
-  if (ncon > 0) {
-    // the contracted graphs of every chunk in one launch: at most mid_limit
-    // components each are left
-    const int32_t max_n = std::min<int32_t>(mid_limit, kMidN);
-    const MidArgs M{d_uni + P.nplain, d_voff, d_eoff, nullptr, nullptr, w,      d_pairs, d_cpoff,
-                    d_cnum,           d_pcnt, d_pbad, in_mst,  tot,     status, max_n};
-    HIP_OK(launch_mid_solve(M, (int)ncon, max_n, true, s));
+                                 at<uint32_t>(A, BL.acc_c), tot, status, s));
   }
   HIP_OK(hipStreamSynchronize(s));
   return MSTX_OK;

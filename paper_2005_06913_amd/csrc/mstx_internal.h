@@ -197,7 +197,7 @@ hipError_t launch_small_solve(const int32_t* glist, int num, const int64_t* voff
                               unsigned long long* total, int32_t* status, hipStream_t s);
 // Arguments of the mid-size solve: graphs glist[i] of the batch (voff, eoff,
 // src, dst, w as the caller gave them), or, when contracted, the same graphs
-// after their first union rounds: nlist[i] components left, both ends of local
+// after their first rounds (k_pre_contract): nlist[i] components left, both ends of local
 // edge j as 16-bit component numbers in pairs[poff[i] + j], pcnt[i] edges and
 // their weight (in total[g]) taken by the union rounds, pbad[i] set when the
 // graph had out-of-range ids, max_n the launch's bound on nlist.
@@ -218,20 +218,31 @@ struct MidArgs {
   int32_t* status;
   int32_t max_n;
 };
-// Contraction of a chunk's edges in its epilogue (vlab == nullptr: none):
-// vlab = component label of every union vertex, cbase[k] = graph k's first
-// label, pairs[poff[k] + j] <- the pair of local edge j of graph k.
-struct ContractArgs {
-  const int32_t* vlab;
-  const int32_t* cbase;
-  const int32_t* gsrc;
-  const int32_t* gdst;
+hipError_t launch_mid_solve(const MidArgs& A, int num, int32_t max_n, bool contracted, hipStream_t s);
+// Arguments of the contraction of graphs glist[i] (n <= kPreMaxN) by their
+// first rounds until at most `target` components are left: scratch from
+// element soff[i] holds n u64; the outputs (pairs, nlist, pcnt, pbad, total,
+// in_mst) are those MidArgs describes for the contracted solve.
+static constexpr int32_t kPreMaxN = 65536;
+struct PreArgs {
+  const int32_t* glist;
+  const int64_t* voff;
+  const int64_t* eoff;
+  const int32_t* src;
+  const int32_t* dst;
+  const uint32_t* w;
+  const int64_t* soff;
+  unsigned long long* scratch;
   uint32_t* pairs;
   const int64_t* poff;
+  int32_t* nlist;
+  int32_t* pcnt;
+  int32_t* pbad;
+  uint8_t* in_mst;
+  unsigned long long* total;
+  int32_t target;
 };
-hipError_t launch_mid_solve(const MidArgs& A, int num, int32_t max_n, bool contracted, hipStream_t s);
-hipError_t launch_contract(int rounds, int32_t n, const int32_t* labpool, const DevState* st, int32_t* vlab, int ng,
-                           const int64_t* cvert, int32_t* cbase, int32_t* cnum, hipStream_t s);
+hipError_t launch_pre_contract(const PreArgs& A, int num, hipStream_t s);
 hipError_t launch_small_solve_single(int32_t n, int64_t m, const int32_t* src, const int32_t* dst,
                                      const uint32_t* w, uint8_t* in_mst, unsigned long long* total,
                                      int32_t* status, int64_t* stats, hipStream_t s);
@@ -243,8 +254,7 @@ hipError_t launch_graph_epilogue(const int32_t* glist, int ng, const int64_t* vo
                                  const int64_t* cedge, int64_t max_graph_m, const uint8_t* cin_mst,
                                  const uint32_t* gw, const int32_t* gbad, uint8_t* in_mst,
                                  unsigned long long* acc_w, uint32_t* acc_c, unsigned long long* total,
-                                 int32_t* status, const ContractArgs& C, int32_t* pcnt, int32_t* pbad,
-                                 hipStream_t s);
+                                 int32_t* status, hipStream_t s);
 hipError_t launch_init(int32_t n, unsigned long long* best, int32_t* parent, unsigned long long* pbest,
                        uint32_t* btot, DevState* st, int grid, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, int64_t count, unsigned long long v, int grid,

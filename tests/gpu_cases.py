@@ -30,6 +30,7 @@ LDS_SLOTS = 20352  # largest component count whose minima the scan keeps in LDS
 TAIL_MAX = 10240  # largest round bound whose hook .. relabel run in one workgroup
 MID_MAX = 16280  # largest vertex count of a batched graph solved by one workgroup, edges streamed
 MID_MAX_EDGES = 1 << 21  # ... and its largest edge count
+PRE_MAX = 65536  # largest vertex count of a batched graph contracted by one workgroup first
 
 
 def stats_consistent(gpu_stats, oracle_stats, limit=DENSE_MAX):

@@ -2,11 +2,11 @@
 
 A batch mixes graphs solved by one workgroup each with everything in LDS
 (n <= 8192), graphs solved by one workgroup each with the edges streamed every
-round (up to 16280 vertices and 2^21 edges), graphs contracted by one or two
-rounds of a disjoint union and then finished like those (up to 2x and 4x
-16280 vertices) and larger graphs solved entirely as chunks of a disjoint
-union; the middle classes are also forced onto the union path
-(``mid_limit(0)``) so both stay covered.  Ties, self-loops, parallel edges,
+round (up to 16280 vertices and 2^21 edges), graphs contracted round by round
+by one workgroup to at most 16280 components and then finished like those (up
+to 65536 vertices) and larger graphs solved as chunks of a disjoint union; the
+middle classes are also forced onto the union path (``mid_limit(0)``) so both
+stay covered.  Ties, self-loops, parallel edges,
 isolated vertices, empty graphs and out-of-range ids are included.  Every
 graph's edge flags, total and status must equal the oracle's on that graph
 alone.
@@ -96,10 +96,11 @@ def test_batched_small_and_large(dev, path):
 @pytest.mark.parametrize("path", list(MID_PATHS))
 def test_batched_mid_boundaries(dev, path):
     """Graphs at the edges of every class: 8193 and 16280 vertices (mid),
-    16281 and 32560 (one union round, then mid), 32561 and 65120 (two union
-    rounds, then mid), 65121 (union only), 2^21 edges exactly (mid, contracted)
-    and 2^21 + 1 (union only), path graphs whose first round joins everything
-    (increasing weights) or only halves the components (alternating weights)."""
+    16281, 32560, 32561 and 65536 (contracted by one to three rounds, one to
+    four LDS windows of minima), 65537 (union), 2^21 edges exactly (mid,
+    contracted) and 2^21 + 1 (union), path graphs whose first round joins
+    everything (increasing weights) or only halves the components
+    (alternating weights)."""
     import paper_2005_06913_amd as P
     from paper_2005_06913_amd import graphgen as G
     E = gpu_cases.MID_MAX_EDGES
@@ -112,8 +113,8 @@ def test_batched_mid_boundaries(dev, path):
         G.tree_plus_extra(M + 1, 3 * M, seed=43),
         G.tree_plus_extra(2 * M, 4 * M, seed=46),
         G.tree_plus_extra(2 * M + 1, 5 * M, seed=47),
-        G.tree_plus_extra(4 * M, 6 * M, seed=48),
-        G.tree_plus_extra(4 * M + 1, 6 * M, seed=49),
+        G.tree_plus_extra(gpu_cases.PRE_MAX, 6 * M, seed=48),
+        G.tree_plus_extra(gpu_cases.PRE_MAX + 1, 6 * M, seed=49),
         G.tree_plus_extra(12_000, E, seed=44),
         G.tree_plus_extra(40_000, E, seed=50),
         G.tree_plus_extra(12_000, E + 1, seed=45),
@@ -127,12 +128,16 @@ def test_batched_mid_boundaries(dev, path):
 
 
 def test_batched_many_contracted(dev):
-    """Graphs of both contracted classes, more of them than one union chunk
-    holds, several average degrees, against the oracle."""
+    """Many graphs of the contracted class (more workgroups than the chip holds
+    at a time; also more vertices than one union chunk holds, for the union
+    path), several average degrees, against the oracle."""
+    import paper_2005_06913_amd as P
     from paper_2005_06913_amd import graphgen as G
-    b = G.batch(140, seed=23, n_lo=gpu_cases.MID_MAX + 1, n_hi=4 * gpu_cases.MID_MAX, d_lo=2.0, d_hi=12.0)
+    b = G.batch(140, seed=23, n_lo=gpu_cases.MID_MAX + 1, n_hi=gpu_cases.PRE_MAX, d_lo=2.0, d_hi=12.0)
     assert sum(int(b.vertex_offsets[g + 1] - b.vertex_offsets[g]) for g in range(b.num_graphs)) > 1 << 22
     check_batch(dev, batch_graphs(b), "many_contracted_140")
+    with P.mid_limit(0):
+        check_batch(dev, batch_graphs(b), "many_contracted_140_union")
 
 
 def test_batched_many_mid(dev):
