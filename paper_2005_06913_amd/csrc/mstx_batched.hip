@@ -71,25 +71,23 @@ __device__ __forceinline__ uint32_t small_wave_sum(uint32_t v) {
 // statistics in the single-graph form: stats[0] = rows, then per row
 // (components entering the round, isolated ones dropped; edges between
 // different components; edges added).
-__global__ void __launch_bounds__(kSmallBlock) k_small_solve(const int32_t* __restrict__ glist,
-                                                             const int64_t* __restrict__ voff,
-                                                             const int64_t* __restrict__ eoff,
-                                                             int32_t n_single, int64_t m_single,
-                                                             const int32_t* __restrict__ src,
-                                                             const int32_t* __restrict__ dst,
-                                                             const uint32_t* __restrict__ w,
-                                                             uint8_t* __restrict__ in_mst,
-                                                             unsigned long long* __restrict__ total_out,
-                                                             int32_t* __restrict__ status_out,
-                                                             int64_t* __restrict__ stats, uint32_t lds_bytes) {
-  extern __shared__ unsigned long long sbest[];  // [n], then comp [n], par [n], the edge cache
+// (The body of one workgroup, item `item` of glist; sbest is the dynamic LDS.)
+__device__ __forceinline__ void small_solve_body(unsigned long long* sbest /* [n], then comp [n], par [n], the edge cache */,
+                                                 int item, const int32_t* __restrict__ glist,
+                                                 const int64_t* __restrict__ voff, const int64_t* __restrict__ eoff,
+                                                 int32_t n_single, int64_t m_single, const int32_t* __restrict__ src,
+                                                 const int32_t* __restrict__ dst, const uint32_t* __restrict__ w,
+                                                 uint8_t* __restrict__ in_mst,
+                                                 unsigned long long* __restrict__ total_out,
+                                                 int32_t* __restrict__ status_out, int64_t* __restrict__ stats,
+                                                 uint32_t lds_bytes) {
   __shared__ uint32_t round_sel;
   __shared__ uint32_t bad;
   __shared__ unsigned long long red_w[kSmallBlock / 64];
   __shared__ uint32_t red_c[kSmallBlock / 64];
   __shared__ uint32_t round_live, round_nonisolated;
 
-  const int g = glist ? glist[blockIdx.x] : 0;
+  const int g = glist ? glist[item] : 0;
   const int64_t e0 = glist ? eoff[g] : 0;
   const int64_t m = glist ? eoff[g + 1] - e0 : m_single;
   const int32_t n = glist ? (int32_t)(voff[g + 1] - voff[g]) : n_single;
@@ -256,6 +254,22 @@ __global__ void __launch_bounds__(kSmallBlock) k_small_solve(const int32_t* __re
   }
 }
 
+__global__ void __launch_bounds__(kSmallBlock) k_small_solve(const int32_t* __restrict__ glist,
+                                                             const int64_t* __restrict__ voff,
+                                                             const int64_t* __restrict__ eoff,
+                                                             int32_t n_single, int64_t m_single,
+                                                             const int32_t* __restrict__ src,
+                                                             const int32_t* __restrict__ dst,
+                                                             const uint32_t* __restrict__ w,
+                                                             uint8_t* __restrict__ in_mst,
+                                                             unsigned long long* __restrict__ total_out,
+                                                             int32_t* __restrict__ status_out,
+                                                             int64_t* __restrict__ stats, uint32_t lds_bytes) {
+  extern __shared__ unsigned long long dyn_lds[];
+  small_solve_body(dyn_lds, blockIdx.x, glist, voff, eoff, n_single, m_single, src, dst, w, in_mst, total_out,
+                   status_out, stats, lds_bytes);
+}
+
 // ---------------------------------------------------------------- mid-size
 
 static constexpr int kMidBlock = 1024;
@@ -327,19 +341,20 @@ __device__ __forceinline__ int32_t p_cas(uint16_t* P, int32_t hi, int32_t lo) {
 // for an edge inside a component).  The first rounds' edges are already
 // flagged and their weight is in total[g]; their count is pcnt[i] and pbad[i]
 // flags out-of-range ids, so the status is that of the whole graph.
+// (The body of one workgroup, item `item` of A.glist; mbest is the dynamic LDS.)
 template <bool kContracted>
-__global__ void __launch_bounds__(kMidBlock) k_mid_solve(MidArgs A) {
-  extern __shared__ unsigned long long mbest[];  // [n], then P [n] (whole words)
+__device__ __forceinline__ void mid_solve_body(unsigned long long* mbest /* [n], then P [n] (whole words) */,
+                                               const MidArgs& A, int item) {
   __shared__ uint32_t round_sel;
   __shared__ uint32_t bad;
   __shared__ unsigned long long red_w[kMidBlock / 64];
   __shared__ uint32_t red_c[kMidBlock / 64];
 
-  const int g = A.glist[blockIdx.x];
+  const int g = A.glist[item];
   const int64_t e0 = A.eoff[g];
   const int64_t m = A.eoff[g + 1] - e0;
   const int32_t n_graph = (int32_t)(A.voff[g + 1] - A.voff[g]);
-  const int32_t n = kContracted ? A.nlist[blockIdx.x] : n_graph;
+  const int32_t n = kContracted ? A.nlist[item] : n_graph;
   const int tid = threadIdx.x;
   if (kContracted && (n < 0 || n > A.max_n)) {  // never: each union round at least halves the components
     if (tid == 0) A.status[g] = MSTX_ERR_DEVICE;
@@ -348,7 +363,7 @@ __global__ void __launch_bounds__(kMidBlock) k_mid_solve(MidArgs A) {
   uint16_t* P = reinterpret_cast<uint16_t*>(mbest + n);
   const int32_t* gs = kContracted ? nullptr : A.src + e0;
   const int32_t* gd = kContracted ? nullptr : A.dst + e0;
-  const uint32_t* gp = kContracted ? A.pairs + A.poff[blockIdx.x] : nullptr;
+  const uint32_t* gp = kContracted ? A.pairs + A.poff[item] : nullptr;
   const uint32_t* gw = A.w + e0;
   uint8_t* in_mst = A.in_mst;
 
@@ -510,8 +525,8 @@ __global__ void __launch_bounds__(kMidBlock) k_mid_solve(MidArgs A) {
     int64_t count = tc;
     if (kContracted) {
       tw += A.total[g];  // the union rounds' edges
-      count += A.pcnt[blockIdx.x];
-      if (A.pbad[blockIdx.x]) bad = 1;
+      count += A.pcnt[item];
+      if (A.pbad[item]) bad = 1;
     }
     A.total[g] = tw;
     int32_t st = (n_graph <= 1 || count == (int64_t)n_graph - 1) ? MSTX_OK : MSTX_DISCONNECTED;
@@ -570,8 +585,9 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* w
 //             (0, 0) for an edge inside a final component or out of range.
 // Outputs: nlist[i] = components left (their numbers in the pairs), pcnt[i] =
 // edges added, pbad[i] = out-of-range ids seen, total[g] = their weight.
-__global__ void __launch_bounds__(kPreBlock) k_pre_contract(PreArgs A) {
-  extern __shared__ unsigned long long wbest[];      // [kPreWin] minima window
+// (The body of one workgroup, item `item` of A.glist; wbest is the dynamic LDS.)
+__device__ __forceinline__ void pre_contract_body(unsigned long long* wbest /* [kPreWin] minima window */,
+                                                  const PreArgs& A, int item) {
   uint16_t* P = reinterpret_cast<uint16_t*>(wbest);  // [N] union-find, then the new numbers
   __shared__ uint32_t wsum[kPreBlock / 64];
   __shared__ uint32_t round_sel;
@@ -579,7 +595,7 @@ __global__ void __launch_bounds__(kPreBlock) k_pre_contract(PreArgs A) {
   __shared__ unsigned long long red_w[kPreBlock / 64];
   __shared__ uint32_t red_c[kPreBlock / 64];
 
-  const int i = blockIdx.x;
+  const int i = item;
   const int g = A.glist[i];
   const int64_t e0 = A.eoff[g];
   const int64_t m = A.eoff[g + 1] - e0;
@@ -810,6 +826,29 @@ __global__ void __launch_bounds__(kPreBlock) k_pre_contract(PreArgs A) {
   }
 }
 
+// ------------------------------------------------------- one launch per batch
+
+// Every graph of a batch that one workgroup solves, in one launch: items
+// [0, ncon) are contracted (k_pre_contract's rounds, then the contracted
+// mid-size solve, in the same workgroup), [ncon, ncon + nmid) mid-size and
+// the rest small.  Each class comes most edges first, so the longest
+// workgroups start first and the small graphs fill the tail.
+__global__ void __launch_bounds__(kMidBlock) k_batch_solve(BatchSolveArgs B) {
+  extern __shared__ unsigned long long dyn_lds[];
+  const int i = blockIdx.x;
+  if (i < B.ncon) {
+    pre_contract_body(dyn_lds, B.pre, i);
+    __syncthreads();  // the contraction's outputs and LDS, then the mid-size solve's
+    mid_solve_body<true>(dyn_lds, B.con, i);
+  } else if (i < B.ncon + B.nmid) {
+    mid_solve_body<false>(dyn_lds, B.mid, i - B.ncon);
+  } else {
+    const MidArgs& S = B.small;
+    small_solve_body(dyn_lds, i - B.ncon - B.nmid, S.glist, S.voff, S.eoff, 0, 0, S.src, S.dst, S.w, S.in_mst,
+                     S.total, S.status, nullptr, (uint32_t)kMaxDynLds);
+  }
+}
+
 // Union of the chunk's graphs glist[0..ng): chunk edge p belongs to graph k with
 // cedge[k] <= p < cedge[k+1]; its ends become union ids cvert[k] + local id.
 // An end outside [0, n_g) makes the edge a self-loop at cvert[k] and flags the
@@ -947,41 +986,23 @@ hipError_t configure_batched_kernels() {
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_small_solve),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxDynLds);
   if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mid_solve<false>),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxDynLds);
-  if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mid_solve<true>),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxDynLds);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pre_contract), hipFuncAttributeMaxDynamicSharedMemorySize,
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch_solve), hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)kMaxDynLds);
 }
 
-hipError_t launch_mid_solve(const MidArgs& A, int num, int32_t max_n, bool contracted, hipStream_t s) {
+hipError_t launch_batch_solve(const BatchSolveArgs& B, int nsmall, hipStream_t s) {
+  const int num = B.ncon + B.nmid + nsmall;
   if (num <= 0) return hipSuccess;
-  if (max_n < 1 || max_n > kMidN || (contracted && A.max_n != max_n)) return hipErrorInvalidValue;
-  const size_t lds = mid_solve_lds(max_n);  // the LDS layout holds max_n <= kMidN vertices
-  if (contracted) k_mid_solve<true><<<num, kMidBlock, lds, s>>>(A);
-  else k_mid_solve<false><<<num, kMidBlock, lds, s>>>(A);
-  return hipGetLastError();
-}
-
-hipError_t launch_pre_contract(const PreArgs& A, int num, hipStream_t s) {
-  if (num <= 0) return hipSuccess;
-  if (A.target < 1 || A.target > kMidN) return hipErrorInvalidValue;
-  k_pre_contract<<<num, kPreBlock, kMaxDynLds, s>>>(A);
+  if (B.ncon > 0 && (B.pre.target < 1 || B.pre.target > kMidN || B.con.max_n != B.pre.target))
+    return hipErrorInvalidValue;
+  if (B.nmid > 0 && (B.mid.max_n < 1 || B.mid.max_n > kMidN)) return hipErrorInvalidValue;
+  static_assert(kSmallSolveLds <= kMaxDynLds && kSmallBlock == kMidBlock && kPreBlock == kMidBlock,
+                "one workgroup shape and LDS allocation serve every class");
+  k_batch_solve<<<num, kMidBlock, kMaxDynLds, s>>>(B);
   return hipGetLastError();
 }
 
 
-hipError_t launch_small_solve(const int32_t* glist, int num, const int64_t* voff, const int64_t* eoff,
-                              const int32_t* src, const int32_t* dst, const uint32_t* w, uint8_t* in_mst,
-                              unsigned long long* total, int32_t* status, hipStream_t s) {
-  if (num <= 0) return hipSuccess;
-  k_small_solve<<<num, kSmallBlock, kSmallSolveLds, s>>>(glist, voff, eoff, 0, 0, src, dst, w, in_mst, total,
-                                                          status, nullptr, (uint32_t)kSmallSolveLds);
-  return hipGetLastError();
-}
 
 hipError_t launch_small_solve_single(int32_t n, int64_t m, const int32_t* src, const int32_t* dst,
                                      const uint32_t* w, uint8_t* in_mst, unsigned long long* total,

@@ -886,23 +886,24 @@ int solve_batched(int32_t G, const int64_t* voff, const int64_t* eoff, const int
     HIP_OK(hipMemcpyAsync(d_csoff, P.csoff.data(), 8 * (size_t)ncon, hipMemcpyHostToDevice, s));
   }
   if (eoff[G] > 0) HIP_OK(hipMemsetAsync(in_mst, 0, (size_t)eoff[G], s));
-  if (ncon > 0) {
-    // the contracted graphs: their first rounds, then the mid-size solve on
-    // the at most mid_limit components left
-    const int32_t max_n = std::min<int32_t>(mid_limit, kMidN);
-    const PreArgs C{d_con,   d_voff,  d_eoff, src,    dst, w,   d_csoff, at<unsigned long long>(A, BL.cscratch),
-                    d_pairs, d_cpoff, d_cnum, d_pcnt, d_pbad, in_mst, tot,  max_n};
-    HIP_OK(launch_pre_contract(C, (int)ncon, s));
-    const MidArgs M{d_con,  d_voff, d_eoff, nullptr, nullptr, w,   d_pairs, d_cpoff,
-                    d_cnum, d_pcnt, d_pbad, in_mst,  tot,     status, max_n};
-    HIP_OK(launch_mid_solve(M, (int)ncon, max_n, true, s));
-  }
   {
-    const MidArgs M{d_mid,   d_voff,  d_eoff,  src,    dst, w,      nullptr, nullptr,
+    // every graph one workgroup solves, in one launch: the contracted ones
+    // (their first rounds, then the mid-size solve on the at most mid_limit
+    // components left), the mid-size ones, the small ones
+    const int32_t max_n = std::min<int32_t>(mid_limit, kMidN);
+    BatchSolveArgs B{};
+    B.pre = PreArgs{d_con,   d_voff,  d_eoff, src,    dst,    w,      d_csoff, at<unsigned long long>(A, BL.cscratch),
+                    d_pairs, d_cpoff, d_cnum, d_pcnt, d_pbad, in_mst, tot,     max_n};
+    B.con = MidArgs{d_con,  d_voff, d_eoff, nullptr, nullptr, w,   d_pairs, d_cpoff,
+                    d_cnum, d_pcnt, d_pbad, in_mst,  tot,     status, max_n};
+    B.mid = MidArgs{d_mid,   d_voff,  d_eoff,  src,    dst, w,      nullptr, nullptr,
                     nullptr, nullptr, nullptr, in_mst, tot, status, P.mid_max_n};
-    HIP_OK(launch_mid_solve(M, (int)P.mid.size(), P.mid_max_n, false, s));
+    B.small = MidArgs{d_small, d_voff,  d_eoff,  src,    dst, w,      nullptr, nullptr,
+                      nullptr, nullptr, nullptr, in_mst, tot, status, 0};
+    B.ncon = (int32_t)ncon;
+    B.nmid = (int32_t)P.mid.size();
+    HIP_OK(launch_batch_solve(B, (int)P.small.size(), s));
   }
-  HIP_OK(launch_small_solve(d_small, (int)P.small.size(), d_voff, d_eoff, src, dst, w, in_mst, tot, status, s));
 
   for (size_t c = 0; c + 1 < P.cfirst.size(); ++c) {
     const int32_t i0 = P.cfirst[c], ng = P.cfirst[c + 1] - i0;

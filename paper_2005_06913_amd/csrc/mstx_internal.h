@@ -192,9 +192,6 @@ static_assert(mid_solve_lds(kMidN) <= (size_t)kMaxDynLds, "the mid-size layout f
 
 hipError_t configure_kernels();
 hipError_t configure_batched_kernels();
-hipError_t launch_small_solve(const int32_t* glist, int num, const int64_t* voff, const int64_t* eoff,
-                              const int32_t* src, const int32_t* dst, const uint32_t* w, uint8_t* in_mst,
-                              unsigned long long* total, int32_t* status, hipStream_t s);
 // Arguments of the mid-size solve: graphs glist[i] of the batch (voff, eoff,
 // src, dst, w as the caller gave them), or, when contracted, the same graphs
 // after their first rounds (k_pre_contract): nlist[i] components left, both ends of local
@@ -218,7 +215,6 @@ struct MidArgs {
   int32_t* status;
   int32_t max_n;
 };
-hipError_t launch_mid_solve(const MidArgs& A, int num, int32_t max_n, bool contracted, hipStream_t s);
 // Arguments of the contraction of graphs glist[i] (n <= kPreMaxN) by their
 // first rounds until at most `target` components are left: scratch from
 // element soff[i] holds n u64; the outputs (pairs, nlist, pcnt, pbad, total,
@@ -242,7 +238,18 @@ struct PreArgs {
   unsigned long long* total;
   int32_t target;
 };
-hipError_t launch_pre_contract(const PreArgs& A, int num, hipStream_t s);
+// One launch for every graph of a batch solved by one workgroup: ncon
+// contracted (pre, then con), nmid mid-size (mid), nsmall small (small's
+// glist, voff, eoff, src, dst, w, in_mst, total, status).
+struct BatchSolveArgs {
+  PreArgs pre;
+  MidArgs con;
+  MidArgs mid;
+  MidArgs small;
+  int32_t ncon;
+  int32_t nmid;
+};
+hipError_t launch_batch_solve(const BatchSolveArgs& B, int nsmall, hipStream_t s);
 hipError_t launch_small_solve_single(int32_t n, int64_t m, const int32_t* src, const int32_t* dst,
                                      const uint32_t* w, uint8_t* in_mst, unsigned long long* total,
                                      int32_t* status, int64_t* stats, hipStream_t s);
