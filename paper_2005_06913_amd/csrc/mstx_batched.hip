@@ -541,7 +541,8 @@ static constexpr int kPreBlock = 1024;
 static constexpr int kPrePer = kPreMaxN / kPreBlock;  // components per thread: tid + q * kPreBlock
 static constexpr int32_t kPreWin = kMaxDynLds / 8;    // minima per LDS window
 static constexpr uint16_t kNoLabel = 0xFFFF;          // a final component (no outgoing edge)
-static_assert(kPrePer <= 64, "one mask bit per owned component");
+static constexpr int kPreHookBatch = 4;               // owned components whose lookups overlap
+static_assert(kPrePer <= 64 && kPrePer % kPreHookBatch == 0, "one mask bit per owned component");
 
 // Exclusive prefix sum over the kPreBlock threads of the workgroup; *total
 // receives the sum.  Every thread must call it.
@@ -677,17 +678,17 @@ __device__ __forceinline__ void pre_contract_body(unsigned long long* wbest /* [
     __syncthreads();
     uint64_t had = 0;  // bit q: component tid + q * kPreBlock had a minimum edge
     uint32_t sel = 0;
-    for (int q0 = 0; q0 < kPrePer && tid + q0 * kPreBlock < N; q0 += 4) {
-      unsigned long long key[4], kd[4];
-      int32_t eu[4], ev[4], d[4];
-      bool has[4];
+    for (int q0 = 0; q0 < kPrePer && tid + q0 * kPreBlock < N; q0 += kPreHookBatch) {
+      unsigned long long key[kPreHookBatch], kd[kPreHookBatch];
+      int32_t eu[kPreHookBatch], ev[kPreHookBatch], d[kPreHookBatch];
+      bool has[kPreHookBatch];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
+      for (int r = 0; r < kPreHookBatch; ++r) {
         const int32_t c = tid + (q0 + r) * kPreBlock;
         key[r] = gbest[c < N ? c : 0];
       }
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
+      for (int r = 0; r < kPreHookBatch; ++r) {
         const int32_t c = tid + (q0 + r) * kPreBlock;
         has[r] = c < N && key[r] != kKeyNone;
         const uint32_t j = has[r] ? (uint32_t)key[r] : 0u;  // a selected edge exists, so m > 0
@@ -700,7 +701,7 @@ __device__ __forceinline__ void pre_contract_body(unsigned long long* wbest /* [
       }
       __asm__ __volatile__("" ::: "memory");
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
+      for (int r = 0; r < kPreHookBatch; ++r) {
         const int32_t c = tid + (q0 + r) * kPreBlock;
         if (!from_input) {
           ev[r] = (int32_t)((uint32_t)eu[r] >> 16);
@@ -710,7 +711,7 @@ __device__ __forceinline__ void pre_contract_body(unsigned long long* wbest /* [
         kd[r] = gbest[has[r] ? d[r] : 0];
       }
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
+      for (int r = 0; r < kPreHookBatch; ++r) {
         if (!has[r]) continue;
         had |= 1ull << (q0 + r);
         const int32_t c = tid + (q0 + r) * kPreBlock;
