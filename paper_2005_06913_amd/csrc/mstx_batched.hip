@@ -203,10 +203,8 @@ __device__ __forceinline__ void small_solve_body(unsigned long long* sbest /* [n
     my_cnt += sel;
     sel = small_wave_sum(sel);
     if ((tid & 63) == 0 && sel) atomicAdd(&round_sel, sel);
-    if (stats) {
-      nonisolated = small_wave_sum(nonisolated);
-      if ((tid & 63) == 0 && nonisolated) atomicAdd(&round_nonisolated, nonisolated);
-    }
+    nonisolated = small_wave_sum(nonisolated);
+    if ((tid & 63) == 0 && nonisolated) atomicAdd(&round_nonisolated, nonisolated);
     __syncthreads();
     if (stats && tid == 0 && (round == 0 || n_round > 1) && !bad) {
       // a row for every round the single-graph path would run
@@ -217,7 +215,10 @@ __device__ __forceinline__ void small_solve_body(unsigned long long* sbest /* [n
     if (round == 0 || n_round > 1) ++rows;
     // isolated components (no outgoing edge) leave; each added edge merges two
     n_round = (int64_t)round_nonisolated - (int64_t)round_sel;
-    if (round_sel == 0) break;
+    // done when no edge was added, or when at most one component with an
+    // outgoing edge is left (its edges can only lead to itself: a component
+    // without one never gains one)
+    if (round_sel == 0 || n_round <= 1) break;
     // compression: the final root of every root of this round goes to a buffer
     // of its own (the minima are no longer needed), so a concurrent halving
     // store into par[] cannot replace it; then every vertex takes its root's root
@@ -345,7 +346,7 @@ __device__ __forceinline__ int32_t p_cas(uint16_t* P, int32_t hi, int32_t lo) {
 template <bool kContracted>
 __device__ __forceinline__ void mid_solve_body(unsigned long long* mbest /* [n], then P [n] (whole words) */,
                                                const MidArgs& A, int item) {
-  __shared__ uint32_t round_sel;
+  __shared__ uint32_t round_sel, round_live;
   __shared__ uint32_t bad;
   __shared__ unsigned long long red_w[kMidBlock / 64];
   __shared__ uint32_t red_c[kMidBlock / 64];
@@ -379,7 +380,10 @@ __device__ __forceinline__ void mid_solve_body(unsigned long long* mbest /* [n],
 
   // (a contracted graph with no component left has only loops)
   for (int round = 0; round < kMaxRounds && m > 0 && n > 0; ++round) {
-    if (tid == 0) round_sel = 0;
+    if (tid == 0) {
+      round_sel = 0;
+      round_live = 0;
+    }
     // minima: kMidUnroll edges per thread loaded at once (clamped to edge 0,
     // which exists as m > 0), then offered for the edges that exist
     for (int64_t j0 = 0; j0 < m; j0 += (int64_t)kMidUnroll * kMidBlock) {
@@ -423,6 +427,7 @@ __device__ __forceinline__ void mid_solve_body(unsigned long long* mbest /* [n],
     __syncthreads();
     // partner of every owned root (loads clamped to edge 0)
     int32_t d[kMidPerThread];
+    uint32_t live = 0;  // owned roots with a minimum edge
     {
       int32_t eu[kMidPerThread], ev[kMidPerThread];
 #pragma unroll
@@ -439,6 +444,7 @@ __device__ __forceinline__ void mid_solve_body(unsigned long long* mbest /* [n],
           ev[q] = gd[j];
         }
         d[q] = has ? 0 : -1;
+        live += has ? 1u : 0u;
       }
       __asm__ __volatile__("" ::: "memory");
 #pragma unroll
@@ -484,9 +490,13 @@ __device__ __forceinline__ void mid_solve_body(unsigned long long* mbest /* [n],
     }
     my_cnt += sel;
     sel = small_wave_sum(sel);
+    live = small_wave_sum(live);
     if ((tid & 63) == 0 && sel) atomicAdd(&round_sel, sel);
+    if ((tid & 63) == 0 && live) atomicAdd(&round_live, live);
     __syncthreads();
-    if (round_sel == 0) break;
+    // done when no edge was added, or when at most one component with an
+    // outgoing edge is left (each added edge merges two of them)
+    if (round_sel == 0 || (int64_t)round_live - (int64_t)round_sel <= 1) break;
     // compression: final roots of the owned vertices into registers (halving
     // stores in P only ever write ancestors, which the walks tolerate), then
     // P flat again
