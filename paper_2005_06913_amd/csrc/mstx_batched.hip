@@ -278,6 +278,16 @@ static constexpr int kMidUnroll = 8;      // edges per thread with loads in flig
 static constexpr int kMidPerThread = 16;  // vertices per thread (registers)
 static_assert(kMidN <= kMidPerThread * kMidBlock, "every vertex has a register slot");
 static_assert(kMidN < 65536, "vertex ids fit the 2-byte union-find");
+// The mid-size solve's dense finish: at most kMidDense components with an
+// outgoing edge left.  LDS then holds a byte per vertex twice (root numbers,
+// vertex numbers), the minimum key of every component pair, and the minima,
+// parents and round-start roots of the components.
+static constexpr int32_t kMidDense = 178;
+__host__ __device__ constexpr size_t mid_dense_pairs_at(int32_t n) { return ((size_t)2 * (size_t)n + 7) & ~(size_t)7; }
+static_assert(mid_dense_pairs_at(kMidN) + 8 * (size_t)kMidDense * (kMidDense - 1) / 2 + 16 * (size_t)kMidDense <=
+                  (size_t)kMaxDynLds,
+              "the dense finish fits the LDS allocation");
+static_assert(kMidDense < 255 && kMidDense <= kMidBlock, "dense numbers fit a byte; one thread per component");
 
 // The union-find of a mid-size graph: one u16 per vertex in LDS.  At the
 // start of a round it is flat (P[v] = root of v's component, P[root] = root);
@@ -315,6 +325,29 @@ __device__ __forceinline__ int32_t p_cas(uint16_t* P, int32_t hi, int32_t lo) {
   }
 }
 
+// Exclusive prefix sum over the 1024 threads of the workgroup; *total
+// receives the sum.  Every thread must call it.
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* wsum /* [16] */,
+                                                         uint32_t* total) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  uint32_t x = v;
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
+  }
+  __syncthreads();  // wsum's previous contents are no longer read
+  if (lane == 63) wsum[wv] = x;
+  __syncthreads();
+  uint32_t before = 0, all = 0;
+  for (int i = 0; i < 16; ++i) {
+    const uint32_t t = wsum[i];
+    if (i < wv) before += t;
+    all += t;
+  }
+  *total = all;
+  return before + x - v;
+}
+
 // One workgroup per graph of `glist` (kSmallN < n <= kMidN, m <= kMidMaxEdges),
 // the rounds of Section 2.1 as in k_small_solve, with 10 bytes of LDS per
 // vertex: the minimum key per root (u64) and the union-find P (u16), which is
@@ -332,7 +365,10 @@ __device__ __forceinline__ int32_t p_cas(uint16_t* P, int32_t hi, int32_t lo) {
 //   compress every owned vertex's final root into a register, then P flat
 //            again (so no halving store can replace a final value) and the
 //            minima of the new roots reset.
-// The loop ends when a round selects no edge.  Writes in_mst for the graph's
+// The loop ends when a round selects no edge or at most one component with an
+// outgoing edge is left.  Once at most kMidDense such components are left, one
+// more pass over the edges takes the minimum key of every pair of them in LDS
+// and the remaining rounds run on that table (dense finish, no more passes).  Writes in_mst for the graph's
 // edges (zeroed by the caller), total[g] and status[g].
 //
 // kContracted: the graph is the contraction of batch graph g by its first
@@ -347,6 +383,7 @@ template <bool kContracted>
 __device__ __forceinline__ void mid_solve_body(unsigned long long* mbest /* [n], then P [n] (whole words) */,
                                                const MidArgs& A, int item) {
   __shared__ uint32_t round_sel, round_live;
+  __shared__ uint32_t wsum[16];
   __shared__ uint32_t bad;
   __shared__ unsigned long long red_w[kMidBlock / 64];
   __shared__ uint32_t red_c[kMidBlock / 64];
@@ -376,10 +413,155 @@ __device__ __forceinline__ void mid_solve_body(unsigned long long* mbest /* [n],
   bool my_bad = false;
   unsigned long long my_w = 0;
   uint32_t my_cnt = 0;
+  // bit q: owned vertex tid + q * kMidBlock is a root that may still have an
+  // outgoing edge (every vertex at the start); their number, uniform
+  uint32_t livem = 0;
+  for (int q = 0; q < kMidPerThread; ++q)
+    if (tid + q * kMidBlock < n) livem |= 1u << q;
+  int32_t live_count = n;
   __syncthreads();
+
+  // ends of local edge j from the loaded words (a pair, or src and dst)
+  auto split = [&](int32_t& a, int32_t& b) {
+    if (kContracted) {
+      b = (int32_t)((uint32_t)a >> 16);
+      a &= 0xFFFF;
+    }
+  };
 
   // (a contracted graph with no component left has only loops)
   for (int round = 0; round < kMaxRounds && m > 0 && n > 0; ++round) {
+    if (live_count <= kMidDense) {
+      // ---- dense finish.  Numbers 0 .. D-1 for the live roots (block scan),
+      // every vertex's number (0xFF: final component), then P and the minima
+      // are no longer needed and the pair table takes their place.
+      uint8_t* rootnum = reinterpret_cast<uint8_t*>(mbest);  // [n] by root
+      uint8_t* vnum = rootnum + n;                           // [n] by vertex
+      uint32_t D = 0;
+      uint32_t next = block_exclusive_scan((uint32_t)__popc(livem), wsum, &D);
+      if (D > (uint32_t)kMidDense) {  // never: D is the count kept above; uniform
+        live_count = (int32_t)D;
+        goto plain_round;
+      }
+#pragma unroll
+      for (int q = 0; q < kMidPerThread; ++q) {
+        const int32_t v = tid + q * kMidBlock;
+        if (v < n && P[v] == v) rootnum[v] = ((livem >> q) & 1) ? (uint8_t)next++ : (uint8_t)0xFF;
+      }
+      __syncthreads();
+      for (int32_t v = tid; v < n; v += kMidBlock) vnum[v] = rootnum[P[v]];
+      __syncthreads();
+      if (D <= 1) break;  // uniform
+      const int32_t npairs = (int32_t)(D * (D - 1) / 2);
+      unsigned long long* T = reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(mbest) + mid_dense_pairs_at(n));
+      unsigned long long* dbest = T + npairs;                    // [D]
+      int32_t* dpar = reinterpret_cast<int32_t*>(dbest + D);      // [D] union-find
+      int32_t* dcomp = dpar + D;                                  // [D] round-start roots
+      for (int32_t x = tid; x < npairs; x += kMidBlock) T[x] = kKeyNone;
+      if (tid < (int)D) {
+        dpar[tid] = tid;
+        dcomp[tid] = tid;
+      }
+      __syncthreads();
+      // the minimum key of every pair of numbers (lo < hi at lo * (2D - lo - 1) / 2 + hi - lo - 1)
+      for (int64_t j0 = 0; j0 < m; j0 += (int64_t)kMidUnroll * kMidBlock) {
+        int32_t a[kMidUnroll], b[kMidUnroll];
+        uint32_t c[kMidUnroll];
+#pragma unroll
+        for (int q = 0; q < kMidUnroll; ++q) {
+          const int64_t j = j0 + q * kMidBlock + tid;
+          const int64_t jc = j < m ? j : 0;
+          if (kContracted) {
+            a[q] = (int32_t)gp[jc];
+          } else {
+            a[q] = gs[jc];
+            b[q] = gd[jc];
+          }
+          c[q] = gw[jc];
+        }
+        __asm__ __volatile__("" ::: "memory");
+#pragma unroll
+        for (int q = 0; q < kMidUnroll; ++q) {
+          const int64_t j = j0 + q * kMidBlock + tid;
+          if (j >= m) continue;
+          split(a[q], b[q]);
+          if ((uint32_t)a[q] >= (uint32_t)n || (uint32_t)b[q] >= (uint32_t)n) continue;
+          const uint32_t na = vnum[a[q]], nb = vnum[b[q]];
+          if (na == 0xFF || nb == 0xFF || na == nb) continue;
+          const uint32_t lo = na < nb ? na : nb, hi = na < nb ? nb : na;
+          const uint32_t x = lo * (2 * D - lo - 1) / 2 + hi - lo - 1;
+          const unsigned long long key = ((unsigned long long)c[q] << 32) | (unsigned long long)j;
+          if (key < T[x]) atomicMin(T + x, key);
+        }
+      }
+      __syncthreads();
+      // Boruvka rounds on the table, one thread per component
+      for (int dr = 0; dr < kMaxRounds; ++dr) {
+        if (tid < (int)D) dbest[tid] = kKeyNone;
+        if (tid == 0) round_sel = 0;
+        __syncthreads();
+        for (int32_t x = tid; x < (int32_t)(D * D); x += kMidBlock) {
+          const uint32_t lo = (uint32_t)x / D, hi = (uint32_t)x % D;
+          if (hi <= lo) continue;
+          const unsigned long long key = T[lo * (2 * D - lo - 1) / 2 + hi - lo - 1];
+          if (key == kKeyNone) continue;
+          const int32_t ra = dcomp[lo], rb = dcomp[hi];
+          if (ra == rb) continue;
+          if (key < dbest[ra]) atomicMin(dbest + ra, key);
+          if (key < dbest[rb]) atomicMin(dbest + rb, key);
+        }
+        __syncthreads();
+        uint32_t dsel = 0;
+        if (tid < (int)D && dcomp[tid] == tid && dbest[tid] != kKeyNone) {
+          const int32_t c = tid;
+          const unsigned long long key = dbest[c];
+          const uint32_t j = (uint32_t)key;
+          int32_t ea, eb;
+          if (kContracted) {
+            ea = (int32_t)gp[j];
+          } else {
+            ea = gs[j];
+            eb = gd[j];
+          }
+          split(ea, eb);
+          const int32_t ra = dcomp[vnum[ea]], rb = dcomp[vnum[eb]];
+          const int32_t o = (ra == c) ? rb : ra;
+          if (!(o < c && dbest[o] == key)) {  // mutual choice: o hooks it
+            int32_t x = c, y = o;
+            while (true) {
+              const int32_t rx = small_root(dpar, x);
+              const int32_t ry = small_root(dpar, y);
+              if (rx == ry) break;
+              const int32_t hi = rx > ry ? rx : ry;
+              const int32_t lo = rx > ry ? ry : rx;
+              const int32_t old = atomicCAS(dpar + hi, hi, lo);
+              if (old == hi) {
+                in_mst[e0 + j] = 1;
+                my_w += (uint32_t)(key >> 32);
+                ++my_cnt;
+                dsel = 1;
+                break;
+              }
+              if (hi == rx) x = old;
+              else y = old;
+            }
+          }
+        }
+        dsel = small_wave_sum(dsel);
+        if ((tid & 63) == 0 && dsel) atomicAdd(&round_sel, dsel);
+        __syncthreads();
+        if (round_sel == 0) break;  // uniform
+        const int32_t r = tid < (int)D ? small_root(dpar, tid) : 0;
+        __syncthreads();
+        if (tid < (int)D) {
+          dpar[tid] = r;
+          dcomp[tid] = r;
+        }
+        __syncthreads();
+      }
+      break;
+    }
+  plain_round:
     if (tid == 0) {
       round_sel = 0;
       round_live = 0;
@@ -428,6 +610,7 @@ __device__ __forceinline__ void mid_solve_body(unsigned long long* mbest /* [n],
     // partner of every owned root (loads clamped to edge 0)
     int32_t d[kMidPerThread];
     uint32_t live = 0;  // owned roots with a minimum edge
+    uint32_t hasm = 0;  // which
     {
       int32_t eu[kMidPerThread], ev[kMidPerThread];
 #pragma unroll
@@ -445,6 +628,7 @@ __device__ __forceinline__ void mid_solve_body(unsigned long long* mbest /* [n],
         }
         d[q] = has ? 0 : -1;
         live += has ? 1u : 0u;
+        hasm |= has ? (1u << q) : 0u;
       }
       __asm__ __volatile__("" ::: "memory");
 #pragma unroll
@@ -496,7 +680,8 @@ __device__ __forceinline__ void mid_solve_body(unsigned long long* mbest /* [n],
     __syncthreads();
     // done when no edge was added, or when at most one component with an
     // outgoing edge is left (each added edge merges two of them)
-    if (round_sel == 0 || (int64_t)round_live - (int64_t)round_sel <= 1) break;
+    live_count = (int32_t)((int64_t)round_live - (int64_t)round_sel);
+    if (round_sel == 0 || live_count <= 1) break;
     // compression: final roots of the owned vertices into registers (halving
     // stores in P only ever write ancestors, which the walks tolerate), then
     // P flat again
@@ -506,12 +691,18 @@ __device__ __forceinline__ void mid_solve_body(unsigned long long* mbest /* [n],
       d[q] = v < n ? p_root(P, v) : 0;
     }
     __syncthreads();
+    // a new root may have an outgoing edge only if it had one this round (a
+    // root without one was joined by nobody)
+    livem = 0;
 #pragma unroll
     for (int q = 0; q < kMidPerThread; ++q) {
       const int32_t v = tid + q * kMidBlock;
       if (v >= n) continue;
       P[v] = (uint16_t)d[q];
-      if (d[q] == v) mbest[v] = kKeyNone;  // a root of the next round
+      if (d[q] == v) {
+        mbest[v] = kKeyNone;  // a root of the next round
+        livem |= hasm & (1u << q);
+      }
     }
     __syncthreads();
   }
@@ -553,29 +744,6 @@ static constexpr int32_t kPreWin = kMaxDynLds / 8;    // minima per LDS window
 static constexpr uint16_t kNoLabel = 0xFFFF;          // a final component (no outgoing edge)
 static constexpr int kPreHookBatch = 4;               // owned components whose lookups overlap
 static_assert(kPrePer <= 64 && kPrePer % kPreHookBatch == 0, "one mask bit per owned component");
-
-// Exclusive prefix sum over the kPreBlock threads of the workgroup; *total
-// receives the sum.  Every thread must call it.
-__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* wsum /* [kPreBlock / 64] */,
-                                                         uint32_t* total) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  uint32_t x = v;
-  for (int off = 1; off < 64; off <<= 1) {
-    const uint32_t y = __shfl_up(x, off, 64);
-    if (lane >= off) x += y;
-  }
-  __syncthreads();  // wsum's previous contents are no longer read
-  if (lane == 63) wsum[wv] = x;
-  __syncthreads();
-  uint32_t before = 0, all = 0;
-  for (int i = 0; i < kPreBlock / 64; ++i) {
-    const uint32_t t = wsum[i];
-    if (i < wv) before += t;
-    all += t;
-  }
-  *total = all;
-  return before + x - v;
-}
 
 // One workgroup per graph of `glist` (n <= kPreMaxN, m <= kMidMaxEdges): the
 // rounds of Section 2.1 on densely numbered components while more than
