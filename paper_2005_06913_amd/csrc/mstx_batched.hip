@@ -756,7 +756,8 @@ static_assert(kPrePer <= 64 && kPrePer % kPreHookBatch == 0, "one mask bit per o
 //             (w << 32) | local index), each flushed to the graph's scratch;
 //   hooking   u16 union-find P[N] in LDS, CAS of the larger root under the
 //             smaller (partners are plain edge ends: no lookup races the
-//             hooks), the edge's flag, weight and count;
+//             hooks; an edge two components chose is added by whichever CAS
+//             wins), the edge's flag, weight and count;
 //   numbering P flat (final roots through the scratch), then consecutive
 //             numbers for the roots that had a minimum edge (block scan); a
 //             root without one is a final component;
@@ -857,7 +858,7 @@ __device__ __forceinline__ void pre_contract_body(unsigned long long* wbest /* [
     uint64_t had = 0;  // bit q: component tid + q * kPreBlock had a minimum edge
     uint32_t sel = 0;
     for (int q0 = 0; q0 < kPrePer && tid + q0 * kPreBlock < N; q0 += kPreHookBatch) {
-      unsigned long long key[kPreHookBatch], kd[kPreHookBatch];
+      unsigned long long key[kPreHookBatch];
       int32_t eu[kPreHookBatch], ev[kPreHookBatch], d[kPreHookBatch];
       bool has[kPreHookBatch];
 #pragma unroll
@@ -886,14 +887,15 @@ __device__ __forceinline__ void pre_contract_body(unsigned long long* wbest /* [
           eu[r] &= 0xFFFF;
         }
         d[r] = (eu[r] == c) ? ev[r] : eu[r];  // a selected edge passed the range check
-        kd[r] = gbest[has[r] ? d[r] : 0];
       }
 #pragma unroll
       for (int r = 0; r < kPreHookBatch; ++r) {
         if (!has[r]) continue;
         had |= 1ull << (q0 + r);
+        // no mutual-choice check (it would cost a third dependent load): when
+        // c and d chose each other both threads try the same CAS, one wins,
+        // and the other then finds both ends under one root
         const int32_t c = tid + (q0 + r) * kPreBlock;
-        if (d[r] < c && kd[r] == key[r]) continue;  // mutual choice: d hooks it
         int32_t x = c, y = d[r];
         while (true) {
           const int32_t rx = p_root(P, x);
