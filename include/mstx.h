@@ -119,6 +119,31 @@ int mst_select_min_edges(int32_t n, int64_t m, const int32_t* src, const int32_t
                          const uint32_t* w, uint64_t* out_best, void* stream);
 
 /*
+ * The edge list of one graph given as a symmetric adjacency structure (CSR),
+ * the input form the solve entry points take (Section 2.1's undirected graph,
+ * each edge once): every arc u -> v with u < v becomes the edge (src = u,
+ * dst = v, w = the arc's weight), in row-major arc order; the mirrored arcs
+ * (u > v) and self-loops are dropped.  A batch is converted graph by graph
+ * (ids stay local to the graph).
+ *   n         vertices, >= 0
+ *   nnz       arcs, >= 0
+ *   row_ptr   DEVICE int64[n+1]: 0 = row_ptr[0] <= ... <= row_ptr[n] = nnz;
+ *             the arcs of u are [row_ptr[u], row_ptr[u+1])
+ *   col, w    DEVICE int32[nnz] (arc targets, in [0, n)), uint32[nnz]
+ *   out_src, out_dst, out_w
+ *             DEVICE int32 / int32 / uint32 [nnz] (an upper bound): the edges
+ *             are written from the start, owned by the caller
+ *   out_m     HOST int64: the number of edges written
+ * Returns MSTX_OK; MSTX_ERR_INVALID_ARG (negative sizes, NULL arrays, or a
+ * row_ptr not as above, checked on the device); MSTX_ERR_VERTEX_RANGE (a
+ * column outside [0, n)); MSTX_ERR_TOO_LARGE (more than 0xFFFFFFFF edges);
+ * MSTX_ERR_OUT_OF_MEMORY or MSTX_ERR_DEVICE.  After an error the outputs are
+ * unspecified.  Blocks until the count is on the host.
+ */
+int mst_csr_to_edges(int32_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col, const uint32_t* w,
+                     int32_t* out_src, int32_t* out_dst, uint32_t* out_w, int64_t* out_m, void* stream);
+
+/*
  * Per-round statistics of the most recent mst_solve call made by the calling
  * thread.  For round r (0-based), out[3r+0] = components with at least one
  * outgoing edge candidate at the start of the round (all components in round

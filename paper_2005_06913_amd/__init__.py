@@ -25,6 +25,7 @@ from .binding import (  # noqa: F401
     small_limit,
     tail_limit,
     mst_batched_workspace_bytes,
+    mst_csr_to_edges,
     mst_last_round_stats,
     mst_profile_enable,
     mst_profile_read,

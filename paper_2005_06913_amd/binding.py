@@ -27,7 +27,7 @@ MSTX_ERR_DEVICE = -5
 EXPORTS = ("mst_solve", "mst_solve_batched", "mst_batched_workspace_bytes", "mst_select_min_edges",
            "mst_last_round_stats", "mst_workspace_bytes", "mst_status_string", "mst_profile_enable",
            "mst_profile_read", "mst_profile_kernel_name", "mst_workspace_release", "mst_set_dense_limit", "mst_set_small_limit",
-           "mst_set_tail_limit", "mst_set_mid_limit")
+           "mst_set_tail_limit", "mst_set_mid_limit", "mst_csr_to_edges")
 
 _lib = None
 
@@ -56,6 +56,8 @@ def load_library(path: str = LIB_PATH):
     lib.mst_batched_workspace_bytes.restype = ctypes.c_size_t
     lib.mst_select_min_edges.argtypes = [i32, i64, p, p, p, p, p]
     lib.mst_select_min_edges.restype = ctypes.c_int
+    lib.mst_csr_to_edges.argtypes = [i32, i64, p, p, p, p, p, p, p, p]
+    lib.mst_csr_to_edges.restype = ctypes.c_int
     lib.mst_last_round_stats.argtypes = [p, i32]
     lib.mst_last_round_stats.restype = ctypes.c_int
     lib.mst_workspace_bytes.argtypes = [i32, i64]
@@ -264,6 +266,28 @@ def mst_select_min_edges(n, src, dst, w, out_best, stream=None) -> int:
     args = (_dev_ptr(src, torch.int32, "src", m), _dev_ptr(dst, torch.int32, "dst", m),
             _dev_ptr(w, torch.uint32, "w", m), _dev_ptr(out_best, torch.uint64, "out_best", int(n)))
     return int(load_library().mst_select_min_edges(int(n), m, *args, _stream_handle(stream)))
+
+
+def mst_csr_to_edges(n, row_ptr, col, w, stream=None):
+    """C ``mst_csr_to_edges``: the edge list of a symmetric CSR adjacency (every
+    arc u -> v with u < v, in row-major arc order) as new device tensors
+    ``(src int32, dst int32, w uint32)``.  Raises MstxError on an error status."""
+    import torch
+    nnz = int(col.numel())
+    dev = row_ptr.device
+    src = torch.empty(nnz, dtype=torch.int32, device=dev)
+    dst = torch.empty(nnz, dtype=torch.int32, device=dev)
+    ww = torch.empty(nnz, dtype=torch.uint32, device=dev)
+    m = ctypes.c_int64(0)
+    rc = load_library().mst_csr_to_edges(
+        int(n), nnz, _dev_ptr(row_ptr, torch.int64, "row_ptr", int(n) + 1), _dev_ptr(col, torch.int32, "col", nnz),
+        _dev_ptr(w, torch.uint32, "w", nnz), _dev_ptr(src, torch.int32, "out_src"),
+        _dev_ptr(dst, torch.int32, "out_dst"), _dev_ptr(ww, torch.uint32, "out_w"), ctypes.byref(m),
+        _stream_handle(stream))
+    if rc < 0:
+        raise MstxError(rc)
+    k = int(m.value)
+    return src[:k], dst[:k], ww[:k]
 
 
 def mst_last_round_stats(max_rounds: int = 40):

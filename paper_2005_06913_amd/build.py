@@ -14,7 +14,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libmstx.so")
-SOURCES = ["mstx_kernels.hip", "mstx_batched.hip", "mstx_host.hip"]
+SOURCES = ["mstx_kernels.hip", "mstx_batched.hip", "mstx_csr.hip", "mstx_host.hip"]
 CPU_LIB = os.path.join(PKG, "libmstx_cpu.so")
 CPU_SOURCES = ["mstx_cpu.cpp"]
 CXX = os.environ.get("CXX", "g++")

@@ -72,8 +72,8 @@ __device__ __forceinline__ uint32_t small_wave_sum(uint32_t v) {
 // (components entering the round, isolated ones dropped; edges between
 // different components; edges added).
 // (The body of one workgroup, item `item` of glist; sbest is the dynamic LDS.)
-__device__ __forceinline__ void small_solve_body(unsigned long long* sbest /* [n], then comp [n], par [n], the edge cache */,
-                                                 int item, const int32_t* __restrict__ glist,
+// sbest: [n] minima, then comp [n], par [n], the edge cache
+__device__ __forceinline__ void small_solve_body(unsigned long long* sbest, int item, const int32_t* __restrict__ glist,
                                                  const int64_t* __restrict__ voff, const int64_t* __restrict__ eoff,
                                                  int32_t n_single, int64_t m_single, const int32_t* __restrict__ src,
                                                  const int32_t* __restrict__ dst, const uint32_t* __restrict__ w,
@@ -439,129 +439,128 @@ __device__ __forceinline__ void mid_solve_body(unsigned long long* mbest /* [n],
       uint8_t* vnum = rootnum + n;                           // [n] by vertex
       uint32_t D = 0;
       uint32_t next = block_exclusive_scan((uint32_t)__popc(livem), wsum, &D);
-      if (D > (uint32_t)kMidDense) {  // never: D is the count kept above; uniform
-        live_count = (int32_t)D;
-        goto plain_round;
-      }
+      if (D <= (uint32_t)kMidDense) {  // always: D is the count kept above (uniform)
 #pragma unroll
-      for (int q = 0; q < kMidPerThread; ++q) {
-        const int32_t v = tid + q * kMidBlock;
-        if (v < n && P[v] == v) rootnum[v] = ((livem >> q) & 1) ? (uint8_t)next++ : (uint8_t)0xFF;
-      }
-      __syncthreads();
-      for (int32_t v = tid; v < n; v += kMidBlock) vnum[v] = rootnum[P[v]];
-      __syncthreads();
-      if (D <= 1) break;  // uniform
-      const int32_t npairs = (int32_t)(D * (D - 1) / 2);
-      unsigned long long* T = reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(mbest) + mid_dense_pairs_at(n));
-      unsigned long long* dbest = T + npairs;                    // [D]
-      int32_t* dpar = reinterpret_cast<int32_t*>(dbest + D);      // [D] union-find
-      int32_t* dcomp = dpar + D;                                  // [D] round-start roots
-      for (int32_t x = tid; x < npairs; x += kMidBlock) T[x] = kKeyNone;
-      if (tid < (int)D) {
-        dpar[tid] = tid;
-        dcomp[tid] = tid;
-      }
-      __syncthreads();
-      // the minimum key of every pair of numbers (lo < hi at lo * (2D - lo - 1) / 2 + hi - lo - 1)
-      for (int64_t j0 = 0; j0 < m; j0 += (int64_t)kMidUnroll * kMidBlock) {
-        int32_t a[kMidUnroll], b[kMidUnroll];
-        uint32_t c[kMidUnroll];
-#pragma unroll
-        for (int q = 0; q < kMidUnroll; ++q) {
-          const int64_t j = j0 + q * kMidBlock + tid;
-          const int64_t jc = j < m ? j : 0;
-          if (kContracted) {
-            a[q] = (int32_t)gp[jc];
-          } else {
-            a[q] = gs[jc];
-            b[q] = gd[jc];
-          }
-          c[q] = gw[jc];
-        }
-        __asm__ __volatile__("" ::: "memory");
-#pragma unroll
-        for (int q = 0; q < kMidUnroll; ++q) {
-          const int64_t j = j0 + q * kMidBlock + tid;
-          if (j >= m) continue;
-          split(a[q], b[q]);
-          if ((uint32_t)a[q] >= (uint32_t)n || (uint32_t)b[q] >= (uint32_t)n) continue;
-          const uint32_t na = vnum[a[q]], nb = vnum[b[q]];
-          if (na == 0xFF || nb == 0xFF || na == nb) continue;
-          const uint32_t lo = na < nb ? na : nb, hi = na < nb ? nb : na;
-          const uint32_t x = lo * (2 * D - lo - 1) / 2 + hi - lo - 1;
-          const unsigned long long key = ((unsigned long long)c[q] << 32) | (unsigned long long)j;
-          if (key < T[x]) atomicMin(T + x, key);
-        }
-      }
-      __syncthreads();
-      // Boruvka rounds on the table, one thread per component
-      for (int dr = 0; dr < kMaxRounds; ++dr) {
-        if (tid < (int)D) dbest[tid] = kKeyNone;
-        if (tid == 0) round_sel = 0;
-        __syncthreads();
-        for (int32_t x = tid; x < (int32_t)(D * D); x += kMidBlock) {
-          const uint32_t lo = (uint32_t)x / D, hi = (uint32_t)x % D;
-          if (hi <= lo) continue;
-          const unsigned long long key = T[lo * (2 * D - lo - 1) / 2 + hi - lo - 1];
-          if (key == kKeyNone) continue;
-          const int32_t ra = dcomp[lo], rb = dcomp[hi];
-          if (ra == rb) continue;
-          if (key < dbest[ra]) atomicMin(dbest + ra, key);
-          if (key < dbest[rb]) atomicMin(dbest + rb, key);
+        for (int q = 0; q < kMidPerThread; ++q) {
+          const int32_t v = tid + q * kMidBlock;
+          if (v < n && P[v] == v) rootnum[v] = ((livem >> q) & 1) ? (uint8_t)next++ : (uint8_t)0xFF;
         }
         __syncthreads();
-        uint32_t dsel = 0;
-        if (tid < (int)D && dcomp[tid] == tid && dbest[tid] != kKeyNone) {
-          const int32_t c = tid;
-          const unsigned long long key = dbest[c];
-          const uint32_t j = (uint32_t)key;
-          int32_t ea, eb;
-          if (kContracted) {
-            ea = (int32_t)gp[j];
-          } else {
-            ea = gs[j];
-            eb = gd[j];
+        for (int32_t v = tid; v < n; v += kMidBlock) vnum[v] = rootnum[P[v]];
+        __syncthreads();
+        if (D <= 1) break;  // uniform
+        const int32_t npairs = (int32_t)(D * (D - 1) / 2);
+        unsigned long long* T =
+            reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(mbest) + mid_dense_pairs_at(n));
+        unsigned long long* dbest = T + npairs;                    // [D]
+        int32_t* dpar = reinterpret_cast<int32_t*>(dbest + D);      // [D] union-find
+        int32_t* dcomp = dpar + D;                                  // [D] round-start roots
+        for (int32_t x = tid; x < npairs; x += kMidBlock) T[x] = kKeyNone;
+        if (tid < (int)D) {
+          dpar[tid] = tid;
+          dcomp[tid] = tid;
+        }
+        __syncthreads();
+        // the minimum key of every pair of numbers (lo < hi at lo * (2D - lo - 1) / 2 + hi - lo - 1)
+        for (int64_t j0 = 0; j0 < m; j0 += (int64_t)kMidUnroll * kMidBlock) {
+          int32_t a[kMidUnroll], b[kMidUnroll];
+          uint32_t c[kMidUnroll];
+#pragma unroll
+          for (int q = 0; q < kMidUnroll; ++q) {
+            const int64_t j = j0 + q * kMidBlock + tid;
+            const int64_t jc = j < m ? j : 0;
+            if (kContracted) {
+              a[q] = (int32_t)gp[jc];
+            } else {
+              a[q] = gs[jc];
+              b[q] = gd[jc];
+            }
+            c[q] = gw[jc];
           }
-          split(ea, eb);
-          const int32_t ra = dcomp[vnum[ea]], rb = dcomp[vnum[eb]];
-          const int32_t o = (ra == c) ? rb : ra;
-          if (!(o < c && dbest[o] == key)) {  // mutual choice: o hooks it
-            int32_t x = c, y = o;
-            while (true) {
-              const int32_t rx = small_root(dpar, x);
-              const int32_t ry = small_root(dpar, y);
-              if (rx == ry) break;
-              const int32_t hi = rx > ry ? rx : ry;
-              const int32_t lo = rx > ry ? ry : rx;
-              const int32_t old = atomicCAS(dpar + hi, hi, lo);
-              if (old == hi) {
-                in_mst[e0 + j] = 1;
-                my_w += (uint32_t)(key >> 32);
-                ++my_cnt;
-                dsel = 1;
-                break;
+          __asm__ __volatile__("" ::: "memory");
+#pragma unroll
+          for (int q = 0; q < kMidUnroll; ++q) {
+            const int64_t j = j0 + q * kMidBlock + tid;
+            if (j >= m) continue;
+            split(a[q], b[q]);
+            if ((uint32_t)a[q] >= (uint32_t)n || (uint32_t)b[q] >= (uint32_t)n) continue;
+            const uint32_t na = vnum[a[q]], nb = vnum[b[q]];
+            if (na == 0xFF || nb == 0xFF || na == nb) continue;
+            const uint32_t lo = na < nb ? na : nb, hi = na < nb ? nb : na;
+            const uint32_t x = lo * (2 * D - lo - 1) / 2 + hi - lo - 1;
+            const unsigned long long key = ((unsigned long long)c[q] << 32) | (unsigned long long)j;
+            if (key < T[x]) atomicMin(T + x, key);
+          }
+        }
+        __syncthreads();
+        // Boruvka rounds on the table, one thread per component
+        for (int dr = 0; dr < kMaxRounds; ++dr) {
+          if (tid < (int)D) dbest[tid] = kKeyNone;
+          if (tid == 0) round_sel = 0;
+          __syncthreads();
+          for (int32_t x = tid; x < (int32_t)(D * D); x += kMidBlock) {
+            const uint32_t lo = (uint32_t)x / D, hi = (uint32_t)x % D;
+            if (hi <= lo) continue;
+            const unsigned long long key = T[lo * (2 * D - lo - 1) / 2 + hi - lo - 1];
+            if (key == kKeyNone) continue;
+            const int32_t ra = dcomp[lo], rb = dcomp[hi];
+            if (ra == rb) continue;
+            if (key < dbest[ra]) atomicMin(dbest + ra, key);
+            if (key < dbest[rb]) atomicMin(dbest + rb, key);
+          }
+          __syncthreads();
+          uint32_t dsel = 0;
+          if (tid < (int)D && dcomp[tid] == tid && dbest[tid] != kKeyNone) {
+            const int32_t c = tid;
+            const unsigned long long key = dbest[c];
+            const uint32_t j = (uint32_t)key;
+            int32_t ea, eb;
+            if (kContracted) {
+              ea = (int32_t)gp[j];
+            } else {
+              ea = gs[j];
+              eb = gd[j];
+            }
+            split(ea, eb);
+            const int32_t ra = dcomp[vnum[ea]], rb = dcomp[vnum[eb]];
+            const int32_t o = (ra == c) ? rb : ra;
+            if (!(o < c && dbest[o] == key)) {  // mutual choice: o hooks it
+              int32_t x = c, y = o;
+              while (true) {
+                const int32_t rx = small_root(dpar, x);
+                const int32_t ry = small_root(dpar, y);
+                if (rx == ry) break;
+                const int32_t hi = rx > ry ? rx : ry;
+                const int32_t lo = rx > ry ? ry : rx;
+                const int32_t old = atomicCAS(dpar + hi, hi, lo);
+                if (old == hi) {
+                  in_mst[e0 + j] = 1;
+                  my_w += (uint32_t)(key >> 32);
+                  ++my_cnt;
+                  dsel = 1;
+                  break;
+                }
+                if (hi == rx) x = old;
+                else y = old;
               }
-              if (hi == rx) x = old;
-              else y = old;
             }
           }
+          dsel = small_wave_sum(dsel);
+          if ((tid & 63) == 0 && dsel) atomicAdd(&round_sel, dsel);
+          __syncthreads();
+          if (round_sel == 0) break;  // uniform
+          const int32_t r = tid < (int)D ? small_root(dpar, tid) : 0;
+          __syncthreads();
+          if (tid < (int)D) {
+            dpar[tid] = r;
+            dcomp[tid] = r;
+          }
+          __syncthreads();
         }
-        dsel = small_wave_sum(dsel);
-        if ((tid & 63) == 0 && dsel) atomicAdd(&round_sel, dsel);
-        __syncthreads();
-        if (round_sel == 0) break;  // uniform
-        const int32_t r = tid < (int)D ? small_root(dpar, tid) : 0;
-        __syncthreads();
-        if (tid < (int)D) {
-          dpar[tid] = r;
-          dcomp[tid] = r;
-        }
-        __syncthreads();
+        break;
       }
-      break;
+      live_count = (int32_t)D;
     }
-  plain_round:
     if (tid == 0) {
       round_sel = 0;
       round_live = 0;

@@ -396,7 +396,8 @@ int enqueue_scan(Solve& S, int r, int stage, int64_t bound, bool exact, hipError
     if (err != hipSuccess) return launched;
     if ((mode == kModeLds || mode == kModeDense) && S.slab) {
       const int ks = T.start(kSlabMin_, r, mode);
-      const int64_t cols = mode == kModeDense ? kDensePairsMax : std::min<int64_t>(std::max<int64_t>(bound, 1), kLdsSlots);
+      const int64_t cols =
+          mode == kModeDense ? kDensePairsMax : std::min<int64_t>(std::max<int64_t>(bound, 1), kLdsSlots);
       err = launch_slab_min(r, launched, mode, S.slab, S.L.slab_cap, grid, S.best, S.pbest, S.st, grid_for(cols),
                             S.s);
       T.stop(ks);
@@ -929,6 +930,34 @@ int solve_batched(int32_t G, const int64_t* voff, const int64_t* eoff, const int
   return MSTX_OK;
 }
 
+int csr_to_edges(int32_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col, const uint32_t* w,
+                 int32_t* out_src, int32_t* out_dst, uint32_t* out_w, int64_t* out_m, hipStream_t s) {
+  const int64_t ntiles = csr_tiles(nnz);
+  const size_t cnt_bytes = align_up(4 * (size_t)std::max<int64_t>(ntiles, 1));
+  const size_t off_bytes = align_up(8 * (size_t)(ntiles + 1));
+  DeviceCache* dc = nullptr;
+  std::unique_lock<std::mutex> lock;
+  int rc = acquire(dc, lock, 0, s);
+  if (rc != MSTX_OK) return rc;
+  rc = grow_aux(dc, cnt_bytes + off_bytes + 256);
+  if (rc != MSTX_OK) return rc;
+  auto* cnt = at<uint32_t>(dc->aux, 0);
+  auto* off = at<int64_t>(dc->aux, cnt_bytes);
+  auto* err = at<uint32_t>(dc->aux, cnt_bytes + off_bytes);
+  HIP_OK(hipMemsetAsync(err, 0, sizeof(uint32_t), s));
+  HIP_OK(launch_csr_to_edges(n, nnz, row_ptr, col, w, cnt, off, err, out_src, out_dst, out_w, s));
+  uint32_t herr = 0;
+  int64_t m = 0;
+  HIP_OK(hipMemcpyAsync(&herr, err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  if (ntiles > 0) HIP_OK(hipMemcpyAsync(&m, off + ntiles, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  if (herr & 1u) return MSTX_ERR_INVALID_ARG;
+  if (herr & 2u) return MSTX_ERR_VERTEX_RANGE;
+  if (m > (int64_t)0xFFFFFFFFLL) return MSTX_ERR_TOO_LARGE;
+  *out_m = m;
+  return MSTX_OK;
+}
+
 int select_min_edges(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, const uint32_t* w,
                      uint64_t* out_best, hipStream_t s) {
   const Layout L = plan(n, m);
@@ -1008,6 +1037,13 @@ size_t mst_batched_workspace_bytes(int32_t num_graphs, const int64_t* vertex_off
   const size_t solve_ws =
       P.uni.empty() ? 0 : mstx::plan((int32_t)std::min<int64_t>(P.max_chunk_n, INT32_MAX), P.max_chunk_m).bytes;
   return solve_ws + mstx::plan_batch(num_graphs, P).bytes;
+}
+
+int mst_csr_to_edges(int32_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col, const uint32_t* w,
+                     int32_t* out_src, int32_t* out_dst, uint32_t* out_w, int64_t* out_m, void* stream) {
+  if (n < 0 || nnz < 0 || !row_ptr || !out_m) return MSTX_ERR_INVALID_ARG;
+  if (nnz > 0 && (!col || !w || !out_src || !out_dst || !out_w)) return MSTX_ERR_INVALID_ARG;
+  return mstx::csr_to_edges(n, nnz, row_ptr, col, w, out_src, out_dst, out_w, out_m, (hipStream_t)stream);
 }
 
 int mst_select_min_edges(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, const uint32_t* w,

@@ -250,6 +250,13 @@ struct BatchSolveArgs {
   int32_t nmid;
 };
 hipError_t launch_batch_solve(const BatchSolveArgs& B, int nsmall, hipStream_t s);
+// Edge list of a symmetric CSR adjacency (mstx_csr.hip): csr_tiles(nnz) tile
+// counts (cnt), their exclusive scan plus the total (off, csr_tiles + 1), an
+// error word (bit 0: row_ptr, bit 1: a column outside [0, n)) the caller zeroes.
+int64_t csr_tiles(int64_t nnz);
+hipError_t launch_csr_to_edges(int32_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col, const uint32_t* w,
+                               uint32_t* cnt, int64_t* off, uint32_t* err, int32_t* out_src, int32_t* out_dst,
+                               uint32_t* out_w, hipStream_t s);
 hipError_t launch_small_solve_single(int32_t n, int64_t m, const int32_t* src, const int32_t* dst,
                                      const uint32_t* w, uint8_t* in_mst, unsigned long long* total,
                                      int32_t* status, int64_t* stats, hipStream_t s);
@@ -267,8 +274,9 @@ hipError_t launch_init(int32_t n, unsigned long long* best, int32_t* parent, uns
 hipError_t launch_fill_u64(unsigned long long* p, int64_t count, unsigned long long v, int grid,
                            hipStream_t s);
 hipError_t launch_scan(int mode, int stage, const ScanArgs& a, int grid, size_t lds, hipStream_t s);
-hipError_t launch_bucket_min(int round, int launched, const unsigned long long* offers, const uint32_t* offT, int32_t nseg, const uint32_t* btot, unsigned long long* best,
-                             const DevState* st, int grid, size_t lds, hipStream_t s);
+hipError_t launch_bucket_min(int round, int launched, const unsigned long long* offers, const uint32_t* offT,
+                             int32_t nseg, const uint32_t* btot, unsigned long long* best, const DevState* st, int grid,
+                             size_t lds, hipStream_t s);
 hipError_t launch_slab_min(int round, int launched, int mode, const unsigned long long* slab, int64_t slab_cap,
                            int nwg, unsigned long long* best, unsigned long long* pbest, const DevState* st,
                            int grid, hipStream_t s);

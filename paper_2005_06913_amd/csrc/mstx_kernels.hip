@@ -1666,8 +1666,8 @@ hipError_t launch_round_tail(int round, int32_t cap, const uint4* rec, unsigned 
                              unsigned long long* total, uint32_t* btot, DevState* st, HostRound* host,
                              hipStream_t s) {
   const size_t lds = 8 * (size_t)(cap < 1 ? 1 : (cap > kTailMax ? kTailMax : cap));
-  k_round_tail<<<1, kTailThreads, lds, s>>>(round, cap < kTailMax ? cap : kTailMax, rec, best, parent, labpool, seg_cnt, nseg, in_mst, total, btot,
-                                            st, host);
+  k_round_tail<<<1, kTailThreads, lds, s>>>(round, cap < kTailMax ? cap : kTailMax, rec, best, parent, labpool,
+                                            seg_cnt, nseg, in_mst, total, btot, st, host);
   MSTX_LAUNCH_CHECK();
   return hipSuccess;
 }

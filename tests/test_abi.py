@@ -35,7 +35,7 @@ def test_header_declares_entry_points():
     names = declared_functions()
     for must in ("mst_solve", "mst_solve_batched", "mst_select_min_edges", "mst_workspace_bytes",
                  "mst_set_dense_limit", "mst_set_small_limit", "mst_set_tail_limit", "mst_set_mid_limit",
-                 "mst_status_string"):
+                 "mst_csr_to_edges", "mst_status_string"):
         assert must in names, names
 
 
@@ -118,6 +118,22 @@ def test_tail_limit_option(lib):
         assert B.mst_set_tail_limit(-1) == gpu_cases.TAIL_MAX
     finally:
         B.mst_set_tail_limit(prev)
+
+
+def test_csr_to_edges_host_checks(lib):
+    """Argument errors are reported on the host, before any HIP call."""
+    import ctypes
+    from paper_2005_06913_amd import binding as B
+    m = ctypes.c_int64(-7)
+    one = ctypes.c_void_p(1)  # never dereferenced: the checks fail first
+    assert lib.mst_csr_to_edges(-1, 0, one, None, None, None, None, None, ctypes.byref(m), None) == \
+        B.MSTX_ERR_INVALID_ARG
+    assert lib.mst_csr_to_edges(3, -1, one, None, None, None, None, None, ctypes.byref(m), None) == \
+        B.MSTX_ERR_INVALID_ARG
+    assert lib.mst_csr_to_edges(3, 4, None, one, one, one, one, one, ctypes.byref(m), None) == B.MSTX_ERR_INVALID_ARG
+    assert lib.mst_csr_to_edges(3, 4, one, None, one, one, one, one, ctypes.byref(m), None) == B.MSTX_ERR_INVALID_ARG
+    assert lib.mst_csr_to_edges(3, 4, one, one, one, one, one, one, None, None) == B.MSTX_ERR_INVALID_ARG
+    assert m.value == -7
 
 
 def test_mid_limit_option(lib):
