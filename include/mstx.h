@@ -93,7 +93,11 @@ int mst_solve(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, cons
  *                     MSTX_DISCONNECTED / MSTX_ERR_VERTEX_RANGE (then the
  *                     graph's outputs are those of its in-range edges)
  * Ties break by the edge's position inside its graph, as in mst_solve, so
- * every graph's result equals mst_solve on that graph alone.
+ * every graph's result equals mst_solve on that graph alone.  Graphs with at
+ * most 8192 vertices and 2097152 edges are solved by one workgroup each (see
+ * mst_set_mid_limit for larger ones); graphs with more edges, and graphs too
+ * large for the one-workgroup paths, as parts of a disjoint union solved by
+ * the round kernels.
  * Returns MSTX_OK when the call ran (see out_status per graph),
  * MSTX_ERR_INVALID_ARG (bad offsets or NULL arrays), MSTX_ERR_TOO_LARGE (a
  * graph with more than 0xFFFFFFFF edges), MSTX_ERR_OUT_OF_MEMORY or

@@ -676,10 +676,13 @@ int solve(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, const ui
 // workgroup contracting it round by round until at most mid_limit components
 // are left, then the mid path on those (contract); or every round in a chunk
 // of the disjoint union solved by the round kernels (large).
+// A graph with more than kMidMaxEdges edges goes to the union whatever its
+// vertex count: one workgroup would stream all of them every round.
 enum class BatchPath { kSmall, kMid, kContract, kLarge };
 BatchPath batch_path(int64_t n, int64_t m, int32_t mid_limit) {
+  if (m > kMidMaxEdges) return BatchPath::kLarge;
   if (n <= kSmallN) return BatchPath::kSmall;
-  if (mid_limit > kSmallN && m <= kMidMaxEdges) {
+  if (mid_limit > kSmallN) {
     if (n <= mid_limit) return BatchPath::kMid;
     if (n <= kPreMaxN) return BatchPath::kContract;
   }

@@ -178,6 +178,9 @@ def degenerate_members(dev, path):
         ts = t.src.copy()
         ts[m // 2] = -3
         graphs.append((t.n, ts, t.dst, t.w))
+    # few vertices but more edges than one workgroup streams (the union path)
+    dense = gpu_cases.ties_multigraph(2000, gpu_cases.MID_MAX_EDGES, seed=9)
+    graphs.append((dense.n, dense.src, dense.dst, dense.w))
     half = G.tree_plus_extra(20_000, 70_000, seed=7)
     graphs.append((40_000, half.src, half.dst, half.w))
     star = G.star_graph(30_000, seed=8)
