@@ -814,7 +814,10 @@ __device__ __forceinline__ void pre_contract_body(unsigned long long* wbest /* [
   };
 
   for (int round = 0; round < kMaxRounds && N > A.target && m > 0; ++round) {
-    // minima, one window of components at a time
+    // minima, one window of components at a time.  The first pass of round 0
+    // reads the caller's arrays and writes every edge's ends as a pair (the
+    // vertices are round 0's components; a loop for an out-of-range edge), so
+    // every later step reads 4-byte pairs instead of src and dst.
     for (int32_t lo = 0; lo < N; lo += kPreWin) {
       const int32_t span = min(N - lo, kPreWin);
       for (int32_t c = tid; c < span; c += kPreBlock) wbest[c] = kKeyNone;
@@ -838,7 +841,10 @@ __device__ __forceinline__ void pre_contract_body(unsigned long long* wbest /* [
 #pragma unroll
         for (int q = 0; q < kMidUnroll; ++q) {
           const int64_t j = j0 + q * kPreBlock + tid;
-          if (j >= m || !ends(a[q], b[q]) || a[q] == b[q]) continue;
+          if (j >= m) continue;
+          const bool ok = ends(a[q], b[q]);
+          if (from_input) gp[j] = ok ? ((uint32_t)a[q] | ((uint32_t)b[q] << 16)) : 0u;
+          if (!ok || a[q] == b[q]) continue;
           const unsigned long long key = ((unsigned long long)c[q] << 32) | (unsigned long long)j;
           const uint32_t ra = (uint32_t)(a[q] - lo), rb = (uint32_t)(b[q] - lo);
           if (ra < (uint32_t)span && key < wbest[ra]) atomicMin(wbest + ra, key);
@@ -848,6 +854,7 @@ __device__ __forceinline__ void pre_contract_body(unsigned long long* wbest /* [
       __syncthreads();
       for (int32_t c = tid; c < span; c += kPreBlock) gbest[lo + c] = wbest[c];
       __syncthreads();
+      from_input = false;  // the pairs are written (uniform)
     }
     if (my_bad) bad = 1;
     // hooking over the N components
