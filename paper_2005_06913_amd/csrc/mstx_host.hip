@@ -681,7 +681,9 @@ int solve(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, const ui
 enum class BatchPath { kSmall, kMid, kContract, kLarge };
 BatchPath batch_path(int64_t n, int64_t m, int32_t mid_limit) {
   if (m > kMidMaxEdges) return BatchPath::kLarge;
-  if (n <= kSmallN) return BatchPath::kSmall;
+  // the small solve when its LDS also holds the edges (or the mid-size path
+  // is off); otherwise the mid-size solve, whose dense finish saves passes
+  if (n <= kSmallN && (small_edges_cached(n, m) || mid_limit <= kSmallN)) return BatchPath::kSmall;
   if (mid_limit > kSmallN) {
     if (n <= mid_limit) return BatchPath::kMid;
     if (n <= kPreMaxN) return BatchPath::kContract;

@@ -179,6 +179,11 @@ static constexpr int32_t kSmallN = 8192;
 static constexpr int64_t kSmallMaxEdges = 1 << 17;
 static constexpr int kSmallStatsWords = 1 + 3 * (kMaxRounds + 1);
 static constexpr int kSmallSolveLds = kSmallN * (8 + 4 + 4);
+// Whether the one-workgroup small solve keeps a graph's edges (12 B each) in
+// LDS behind its vertex state (16 B per vertex) in the batched launch.
+__host__ __device__ constexpr bool small_edges_cached(int64_t n, int64_t m) {
+  return ((16 * n + 15) & ~(int64_t)15) + 12 * m <= (int64_t)kMaxDynLds;
+}
 // Batched solve: graphs with kSmallN < n <= kMidN vertices (default; see
 // mst_set_mid_limit) and at most kMidMaxEdges edges are solved by one
 // workgroup each as well, with 10 bytes of LDS per vertex: the minimum key
