@@ -1,8 +1,9 @@
 """GPU parity of the batched solve: every graph of a batch against the oracle.
 
 A batch mixes graphs solved by one workgroup each with everything in LDS
-(n <= 8192), graphs solved by one workgroup each with the edges streamed every
-round (up to 16280 vertices and 2^21 edges), graphs contracted round by round
+(n <= 8192 and the edges fit there too), graphs solved by one workgroup each
+with the edges streamed every round (the other graphs of up to 16280 vertices
+and 2^21 edges), graphs contracted round by round
 by one workgroup to at most 16280 components and then finished like those (up
 to 65536 vertices) and larger graphs solved as chunks of a disjoint union; the
 middle classes are also forced onto the union path (``mid_limit(0)``) so both
