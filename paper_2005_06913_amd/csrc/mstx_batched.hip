@@ -4,17 +4,19 @@
 // their forests, and Boruvka never merges components of different graphs, so
 // a batch is solved in four parts:
 //
-//   * graphs with at most kSmallN vertices: one workgroup per graph runs every
-//     Boruvka round of Section 2.1 with the vertex state in LDS (component of
-//     each vertex, union-find parents, minimum keys); rounds are separated by
+//   * graphs with at most kSmallN vertices whose edges fit in LDS behind the
+//     vertex state: one workgroup per graph runs every Boruvka round of
+//     Section 2.1 with the vertex state (component of each vertex, union-find
+//     parents, minimum keys) and the edges in LDS; rounds are separated by
 //     workgroup barriers only, so thousands of small graphs proceed
 //     independently and in parallel;
-//   * graphs with up to kMidN vertices and kMidMaxEdges edges: one workgroup
-//     per graph as well, 10 bytes of LDS per vertex (minimum key and a 2-byte
-//     union-find), the edges streamed from memory every round (k_mid_solve);
+//   * the other graphs with up to kMidN vertices and kMidMaxEdges edges: one
+//     workgroup per graph as well, 10 bytes of LDS per vertex (minimum key and
+//     a 2-byte union-find), the edges streamed from memory every round and a
+//     dense finish on a pair table (the mid-size solve);
 //   * graphs with up to kPreMaxN vertices (same edge bound): one workgroup per
 //     graph contracts it round by round until at most kMidN components are
-//     left (k_pre_contract), then k_mid_solve finishes the contracted graph;
+//     left, then the mid-size solve finishes the contracted graph;
 //   * larger graphs: gathered into chunks that are solved as one disjoint
 //     union by the single-graph round kernels (k_gather renumbers vertices and
 //     edges into the union, k_graph_epilogue scatters the flags back and sums
@@ -372,7 +374,7 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* w
 // edges (zeroed by the caller), total[g] and status[g].
 //
 // kContracted: the graph is the contraction of batch graph g by its first
-// rounds (k_pre_contract): its vertices are the n' = nlist[i] components left,
+// rounds (pre_contract_body): its vertices are the n' = nlist[i] components left,
 // its edges the graph's edges (same local indices, so the same keys) with both
 // ends given as 16-bit component numbers packed in pairs[poff[i] + j] (a loop
 // for an edge inside a component).  The first rounds' edges are already
@@ -394,7 +396,7 @@ __device__ __forceinline__ void mid_solve_body(unsigned long long* mbest /* [n],
   const int32_t n_graph = (int32_t)(A.voff[g + 1] - A.voff[g]);
   const int32_t n = kContracted ? A.nlist[item] : n_graph;
   const int tid = threadIdx.x;
-  if (kContracted && (n < 0 || n > A.max_n)) {  // never: each union round at least halves the components
+  if (kContracted && (n < 0 || n > A.max_n)) {  // never: each contraction round at least halves the components
     if (tid == 0) A.status[g] = MSTX_ERR_DEVICE;
     return;
   }
@@ -724,7 +726,7 @@ __device__ __forceinline__ void mid_solve_body(unsigned long long* mbest /* [n],
     }
     int64_t count = tc;
     if (kContracted) {
-      tw += A.total[g];  // the union rounds' edges
+      tw += A.total[g];  // the contraction rounds' edges
       count += A.pcnt[item];
       if (A.pbad[item]) bad = 1;
     }
@@ -746,7 +748,7 @@ static_assert(kPrePer <= 64 && kPrePer % kPreHookBatch == 0, "one mask bit per o
 
 // One workgroup per graph of `glist` (n <= kPreMaxN, m <= kMidMaxEdges): the
 // rounds of Section 2.1 on densely numbered components while more than
-// `target` of them are left, so that the mid-size solve (k_mid_solve in its
+// `target` of them are left, so that the mid-size solve (mid_solve_body in its
 // contracted form) can finish the graph in LDS.  Components are numbered
 // 0 .. N-1 at the start of every round, so the ends of an edge are its
 // components; round 0 reads the caller's edges (ids checked against [0, n)),
@@ -1016,7 +1018,7 @@ __device__ __forceinline__ void pre_contract_body(unsigned long long* wbest /* [
 // ------------------------------------------------------- one launch per batch
 
 // Every graph of a batch that one workgroup solves, in one launch: items
-// [0, ncon) are contracted (k_pre_contract's rounds, then the contracted
+// [0, ncon) are contracted (pre_contract_body's rounds, then the contracted
 // mid-size solve, in the same workgroup), [ncon, ncon + nmid) mid-size and
 // the rest small.  Each class comes most edges first, so the longest
 // workgroups start first and the small graphs fill the tail.

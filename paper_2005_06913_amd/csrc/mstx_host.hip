@@ -108,7 +108,7 @@ std::atomic<int> g_dense_limit{kDenseMax};
 // (0: never); mst_set_small_limit() changes it.
 std::atomic<int> g_small_limit{kSmallN};
 // Largest vertex count for which mst_solve_batched solves a graph above
-// kSmallN vertices with one workgroup (k_mid_solve) instead of the union
+// kSmallN vertices with one workgroup (the mid-size solve) instead of the union
 // chunks (0: never); mst_set_mid_limit() changes it.
 std::atomic<int> g_mid_limit{kMidN};
 // Largest component-count bound for which a round's hook .. relabel run as

@@ -199,9 +199,9 @@ hipError_t configure_kernels();
 hipError_t configure_batched_kernels();
 // Arguments of the mid-size solve: graphs glist[i] of the batch (voff, eoff,
 // src, dst, w as the caller gave them), or, when contracted, the same graphs
-// after their first rounds (k_pre_contract): nlist[i] components left, both ends of local
+// after their first rounds (pre_contract_body): nlist[i] components left, both ends of local
 // edge j as 16-bit component numbers in pairs[poff[i] + j], pcnt[i] edges and
-// their weight (in total[g]) taken by the union rounds, pbad[i] set when the
+// their weight (in total[g]) taken by the contraction rounds, pbad[i] set when the
 // graph had out-of-range ids, max_n the launch's bound on nlist.
 struct MidArgs {
   const int32_t* glist;
