@@ -96,7 +96,8 @@ def test_batched_small_and_large(dev, path):
 
 @pytest.mark.parametrize("path", list(MID_PATHS))
 def test_batched_mid_boundaries(dev, path):
-    """Graphs at the edges of every class: 8193 and 16280 vertices (mid),
+    """Graphs at the edges of every class: a small graph whose edges just fit in
+    LDS and one with one edge more, 8193 and 16280 vertices (mid),
     16281, 32560, 32561 and 65536 (contracted by one to three rounds, one to
     four LDS windows of minima), 65537 (union), 2^21 edges exactly (mid,
     contracted) and 2^21 + 1 (union), path graphs whose first round joins
@@ -122,6 +123,11 @@ def test_batched_mid_boundaries(dev, path):
         G.path_graph(M - 5),
         G.path_graph(3 * M),
         G.path_graph(n_alt, alt),
+        # n = 4096: 16 B per vertex and 12 B per edge fill the 162816 B of LDS
+        # at 8106 edges (the small solve keeps them) and overflow at 8107
+        # (the mid-size solve streams them)
+        G.tree_plus_extra(4096, 8106, seed=51),
+        G.tree_plus_extra(4096, 8107, seed=52),
     ]
     graphs = [(g.n, g.src, g.dst, g.w) for g in parts]
     with P.mid_limit(MID_PATHS[path]):
