@@ -259,6 +259,21 @@ int32_t mst_set_mid_limit(int32_t limit);
  */
 int32_t mst_set_tail_limit(int32_t limit);
 
+/*
+ * Minima of large rounds (Section 2.1's edge loop): a round of mst_solve
+ * whose bound on the component count is above the LDS range (20352) and at
+ * most `limit` takes its per-component minima by sorting the edges' offers
+ * into buckets of consecutive components, each bucket's minima taken in one
+ * workgroup's LDS; a round above the limit takes them with filtered 64-bit
+ * atomic minima in device memory (one per edge end).  The tree, the labels
+ * and the round statistics are the same.  limit is clamped to
+ * [0, 16760832] (0: never bucket mode; the default is 16760832, the largest
+ * count the 1023 buckets of 16384 components cover); limit < 0 only queries.
+ * Returns the previous limit.  Process-wide; read at the start of each call
+ * (mst_solve_batched's large graphs and mst_select_min_edges included).
+ */
+int32_t mst_set_bucket_limit(int32_t limit);
+
 /* Static description of a status code. */
 const char* mst_status_string(int status);
 

@@ -77,8 +77,6 @@ def _bind(path: str):
     lib.oracle_check_mst.restype = ctypes.c_int
     lib.oracle_min_edge_keys.argtypes = [i32, i64, p, p, p, p]
     lib.oracle_min_edge_keys.restype = ctypes.c_int
-    lib.oracle_count_components.argtypes = [i32, i64, p, p]
-    lib.oracle_count_components.restype = ctypes.c_int64
     return lib
 
 
@@ -155,11 +153,6 @@ class Oracle:
         st = self.lib.oracle_min_edge_keys(n, src.shape[0], _ptr(src), _ptr(dst), _ptr(w), _ptr(keys))
         return int(st), keys[:max(n, 0)]
 
-    def count_components(self, n: int, src, dst) -> int:
-        src = np.ascontiguousarray(src, dtype=np.int32)
-        dst = np.ascontiguousarray(dst, dtype=np.int32)
-        return int(self.lib.oracle_count_components(n, src.shape[0], _ptr(src), _ptr(dst)))
-
 
 def default() -> Oracle:
     """The oracle built from ``mst_oracle.c`` (rebuilt when the source is newer)."""
@@ -186,6 +179,3 @@ def check_mst(n: int, src, dst, w, in_mst, total: int) -> int:
 def min_edge_keys(n: int, src, dst, w):
     return default().min_edge_keys(n, src, dst, w)
 
-
-def count_components(n: int, src, dst) -> int:
-    return default().count_components(n, src, dst)

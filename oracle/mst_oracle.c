@@ -463,27 +463,6 @@ int oracle_check_mst(int32_t n, int64_t m, const int32_t* src, const int32_t* ds
     return CHECK_OK;
 }
 
-/* Components of the input graph (connectivity only), for tests. */
-int64_t oracle_count_components(int32_t n, int64_t m, const int32_t* src, const int32_t* dst) {
-    if (n < 0 || m < 0) return -1;
-    uf_t u;
-    if (uf_init(&u, n) != ORACLE_OK) return -1;
-    int64_t c = n;
-    for (int64_t e = 0; e < m; ++e) {
-        if (src[e] < 0 || src[e] >= n || dst[e] < 0 || dst[e] >= n) {
-            uf_free(&u);
-            return -1;
-        }
-        int32_t a = uf_find(&u, src[e]), b = uf_find(&u, dst[e]);
-        if (a != b) {
-            uf_union_roots(&u, a, b);
-            --c;
-        }
-    }
-    uf_free(&u);
-    return c;
-}
-
 /*
  * The first Boruvka step on its own (Section 2.1, the edge loop with every
  * vertex its own component): keys[v] = smallest (w[e] << 32) | e over the

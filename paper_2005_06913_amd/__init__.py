@@ -19,6 +19,7 @@ from .binding import (  # noqa: F401
     MSTX_OK,
     MstxError,
     Solution,
+    bucket_limit,
     dense_limit,
     load_library,
     mid_limit,
@@ -30,6 +31,7 @@ from .binding import (  # noqa: F401
     mst_profile_enable,
     mst_profile_read,
     mst_select_min_edges,
+    mst_set_bucket_limit,
     mst_set_dense_limit,
     mst_set_mid_limit,
     mst_set_small_limit,

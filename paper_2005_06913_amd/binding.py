@@ -27,7 +27,7 @@ MSTX_ERR_DEVICE = -5
 EXPORTS = ("mst_solve", "mst_solve_batched", "mst_batched_workspace_bytes", "mst_select_min_edges",
            "mst_last_round_stats", "mst_workspace_bytes", "mst_status_string", "mst_profile_enable",
            "mst_profile_read", "mst_profile_kernel_name", "mst_workspace_release", "mst_set_dense_limit", "mst_set_small_limit",
-           "mst_set_tail_limit", "mst_set_mid_limit", "mst_csr_to_edges")
+           "mst_set_tail_limit", "mst_set_mid_limit", "mst_set_bucket_limit", "mst_csr_to_edges")
 
 _lib = None
 
@@ -78,6 +78,8 @@ def load_library(path: str = LIB_PATH):
     lib.mst_set_tail_limit.restype = ctypes.c_int32
     lib.mst_set_mid_limit.argtypes = [ctypes.c_int32]
     lib.mst_set_mid_limit.restype = ctypes.c_int32
+    lib.mst_set_bucket_limit.argtypes = [ctypes.c_int32]
+    lib.mst_set_bucket_limit.restype = ctypes.c_int32
     lib.mst_profile_kernel_name.argtypes = [ctypes.c_int]
     lib.mst_profile_kernel_name.restype = ctypes.c_char_p
     _lib = lib
@@ -137,6 +139,31 @@ def mst_set_mid_limit(limit: int) -> int:
     many components.  At most 8192: off (disjoint-union chunks instead);
     clamped to 16280; negative: query.  Returns the previous limit."""
     return int(load_library().mst_set_mid_limit(int(limit)))
+
+
+def mst_set_bucket_limit(limit: int) -> int:
+    """Set the component-count bound up to which a round above the LDS range
+    takes its minima in bucket mode; above it the filtered global atomics
+    (0: never bucket mode; clamped to 16760832; negative: query).  Returns the
+    previous limit."""
+    return int(load_library().mst_set_bucket_limit(int(limit)))
+
+
+class bucket_limit:
+    """Context manager: ``with bucket_limit(0): ...`` takes every round above the
+    LDS range with filtered global atomic minima."""
+
+    def __init__(self, limit: int):
+        self.limit = limit
+        self.prev = None
+
+    def __enter__(self):
+        self.prev = mst_set_bucket_limit(self.limit)
+        return self
+
+    def __exit__(self, *exc):
+        mst_set_bucket_limit(self.prev)
+        return False
 
 
 class mid_limit:

@@ -992,6 +992,8 @@ __device__ __forceinline__ void pre_contract_body(unsigned long long* wbest /* [
     }
     if (my_bad) bad = 1;
   }
+  // no edges at all: every vertex is a final component, none is left to solve
+  if (m == 0) N = 0;
   for (int off = 32; off > 0; off >>= 1) {
     my_w += __shfl_xor(my_w, off, 64);
     my_cnt += __shfl_xor(my_cnt, off, 64);

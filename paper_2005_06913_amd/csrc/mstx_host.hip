@@ -114,6 +114,10 @@ std::atomic<int> g_mid_limit{kMidN};
 // Largest component-count bound for which a round's hook .. relabel run as
 // one workgroup (0: never); mst_set_tail_limit() changes it.
 std::atomic<int> g_tail_limit{kTailMax};
+// Largest component-count bound for which a round's scan takes its minima in
+// bucket mode; above it (and above the LDS range) the filtered global atomics
+// of GLOBAL mode.  mst_set_bucket_limit() changes it.
+std::atomic<int64_t> g_bucket_limit{kBucketMaxComponents};
 std::map<std::pair<int, hipStream_t>, std::unique_ptr<DeviceCache>> g_caches;
 
 thread_local std::vector<int64_t> t_last_stats;
@@ -172,13 +176,14 @@ int acquire(DeviceCache*& dc, std::unique_lock<std::mutex>& lock, size_t bytes, 
     dc->configured = true;
   }
   if (bytes > 0 && dc->bytes < bytes) {
+    // stream-ordered: only this stream uses the workspace, so growing it
+    // waits for this stream's earlier work and for no other stream's
     if (dc->base) {
-      HIP_OK(hipDeviceSynchronize());
-      HIP_OK(hipFree(dc->base));
+      HIP_OK(hipFreeAsync(dc->base, stream));
       dc->base = nullptr;
       dc->bytes = 0;
     }
-    if (hipMalloc(&dc->base, bytes) != hipSuccess) {
+    if (hipMallocAsync(&dc->base, bytes, stream) != hipSuccess) {
       (void)hipGetLastError();
       dc->base = nullptr;
       return MSTX_ERR_OUT_OF_MEMORY;
@@ -293,10 +298,10 @@ struct LaunchTimer {
 thread_local LaunchTimer t_timer;
 
 // Mode that handles `bound` components when it is the exact count.
-int mode_for(int64_t nr, int dense_limit) {
+int mode_for(int64_t nr, int dense_limit, int64_t bucket_limit) {
   if (nr <= dense_limit) return kModeDense;
   if (nr <= kLdsSlots) return kModeLds;
-  if (nr <= kBucketMaxComponents) return kModeBucket;
+  if (nr <= bucket_limit) return kModeBucket;
   return kModeGlobal;
 }
 
@@ -331,6 +336,7 @@ struct Solve {
   uint32_t* btot;
   int dense_limit;            // 0: no dense finish
   int tail_limit;             // 0: every round takes the multi-workgroup hook .. relabel
+  int64_t bucket_limit;       // largest bound that may take bucket mode (0: never)
   std::vector<int> launched;  // per round
 };
 
@@ -338,7 +344,8 @@ struct Solve {
 // round whose component count is at most `bound`.  Returns the launched mask.
 int enqueue_scan(Solve& S, int r, int stage, int64_t bound, bool exact, hipError_t& err, int64_t n_prev = 0) {
   LaunchTimer& T = t_timer;
-  const int hi_mode = mode_for(bound, S.dense_limit);
+  const bool buckets = S.L.bucket && S.bucket_limit > 0;
+  const int hi_mode = mode_for(bound, S.dense_limit, buckets ? S.bucket_limit : 0);
   int launched = 1 << hi_mode;
   if (!exact) {
     // the actual count may be much smaller than the bound
@@ -351,9 +358,9 @@ int enqueue_scan(Solve& S, int r, int stage, int64_t bound, bool exact, hipError
     // correct, for that one round)
     const int64_t drop = stage == 1 ? 8 : 64;
     if (hi_mode != kModeLds && hi_mode != kModeDense && bound / drop <= kLdsSlots) launched |= 1 << kModeLds;
-    if (hi_mode == kModeGlobal && bound / 8 <= kBucketMaxComponents) launched |= 1 << kModeBucket;
+    if (hi_mode == kModeGlobal && buckets && bound / 8 <= S.bucket_limit) launched |= 1 << kModeBucket;
   }
-  if (!S.L.bucket) launched &= ~(1 << kModeBucket), launched |= (bound > kLdsSlots ? 1 << kModeGlobal : 0);
+  if (!buckets) launched &= ~(1 << kModeBucket), launched |= (bound > kLdsSlots ? 1 << kModeGlobal : 0);
   launched |= S.dense_limit << 8;
   ScanArgs A{r,      launched, S.src,     S.dst,    S.w,    (uint32_t)S.m, S.n,     S.labpool, S.rec,
              S.seg_cnt, S.L.nseg, S.best, S.st, S.offers, S.offT, S.slab, S.L.slab_cap, S.pbest, -1,
@@ -517,6 +524,7 @@ Solve make_solve(DeviceCache* dc, const Layout& L, int32_t n, int64_t m, const i
   S.btot = at<uint32_t>(B, L.btot);
   S.dense_limit = g_dense_limit.load();
   S.tail_limit = g_tail_limit.load();
+  S.bucket_limit = g_bucket_limit.load();
   S.launched.assign(kMaxRounds + 1, 0);
   return S;
 }
@@ -734,15 +742,15 @@ BatchLayout plan_batch(int32_t G, int64_t nsmall, int64_t nmid, int64_t nlarge, 
   return B;
 }
 
-int grow_aux(DeviceCache* dc, size_t bytes) {
+int grow_aux(DeviceCache* dc, size_t bytes, hipStream_t stream) {
   if (dc->aux_bytes >= bytes) return MSTX_OK;
+  // stream-ordered, as the workspace in acquire()
   if (dc->aux) {
-    HIP_OK(hipDeviceSynchronize());
-    HIP_OK(hipFree(dc->aux));
+    HIP_OK(hipFreeAsync(dc->aux, stream));
     dc->aux = nullptr;
     dc->aux_bytes = 0;
   }
-  if (hipMalloc(&dc->aux, bytes) != hipSuccess) {
+  if (hipMallocAsync(&dc->aux, bytes, stream) != hipSuccess) {
     (void)hipGetLastError();
     dc->aux = nullptr;
     return MSTX_ERR_OUT_OF_MEMORY;
@@ -850,7 +858,7 @@ int solve_batched(int32_t G, const int64_t* voff, const int64_t* eoff, const int
   std::unique_lock<std::mutex> lock;
   int rc = acquire(dc, lock, nuni == 0 ? 0 : L.bytes, s);
   if (rc != MSTX_OK) return rc;
-  rc = grow_aux(dc, BL.bytes);
+  rc = grow_aux(dc, BL.bytes, s);
   if (rc != MSTX_OK) return rc;
   void* A = dc->aux;
   auto* d_voff = at<int64_t>(A, BL.voff);
@@ -944,7 +952,7 @@ int csr_to_edges(int32_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* 
   std::unique_lock<std::mutex> lock;
   int rc = acquire(dc, lock, 0, s);
   if (rc != MSTX_OK) return rc;
-  rc = grow_aux(dc, cnt_bytes + off_bytes + 256);
+  rc = grow_aux(dc, cnt_bytes + off_bytes + 256, s);
   if (rc != MSTX_OK) return rc;
   auto* cnt = at<uint32_t>(dc->aux, 0);
   auto* off = at<int64_t>(dc->aux, cnt_bytes);
@@ -994,6 +1002,7 @@ int select_min_edges(int32_t n, int64_t m, const int32_t* src, const int32_t* ds
   S.pbest = at<unsigned long long>(B, L.pbest);
   S.btot = at<uint32_t>(B, L.btot);
   S.dense_limit = 0;  // per-vertex minima: never the pair table
+  S.bucket_limit = g_bucket_limit.load();
   S.in_mst = nullptr;
   S.launched.assign(1, 0);
   t_timer.begin(s);
@@ -1109,9 +1118,10 @@ int mst_workspace_release(void* stream) {
     victim = std::move(it->second);
     mstx::g_caches.erase(it);
   }
+  // the workspace and the batched scratch are stream-ordered allocations
+  if (victim->base && hipFreeAsync(victim->base, (hipStream_t)stream) != hipSuccess) return MSTX_ERR_DEVICE;
+  if (victim->aux && hipFreeAsync(victim->aux, (hipStream_t)stream) != hipSuccess) return MSTX_ERR_DEVICE;
   if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return MSTX_ERR_DEVICE;
-  if (victim->base && hipFree(victim->base) != hipSuccess) return MSTX_ERR_DEVICE;
-  if (victim->aux && hipFree(victim->aux) != hipSuccess) return MSTX_ERR_DEVICE;
   if (victim->host_rounds && hipHostFree(victim->host_rounds) != hipSuccess) return MSTX_ERR_DEVICE;
   if (victim->small_dev && hipFree(victim->small_dev) != hipSuccess) return MSTX_ERR_DEVICE;
   if (victim->small_host && hipHostFree(victim->small_host) != hipSuccess) return MSTX_ERR_DEVICE;
@@ -1138,6 +1148,11 @@ int32_t mst_set_mid_limit(int32_t limit) {
 int32_t mst_set_tail_limit(int32_t limit) {
   if (limit < 0) return mstx::g_tail_limit.load();
   return mstx::g_tail_limit.exchange(std::min<int32_t>(limit, mstx::kTailMax));
+}
+
+int32_t mst_set_bucket_limit(int32_t limit) {
+  if (limit < 0) return (int32_t)mstx::g_bucket_limit.load();
+  return (int32_t)mstx::g_bucket_limit.exchange(std::min<int64_t>(limit, mstx::kBucketMaxComponents));
 }
 
 int32_t mst_set_dense_limit(int32_t limit) {

@@ -37,6 +37,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 MSTX_ERR_OUT_OF_MEMORY = -4
+MSTX_ERR_DEVICE = -5
 
 
 @dataclass
@@ -172,6 +173,7 @@ class MstServer:
         self.stop = False
         self.workers = []
         self.batches = []  # (slot, sizes) log for tests
+        self.errors = []  # (slot, request ids, exception) of batches whose execution raised
         self.in_flight_bytes = 0
         self.peak_in_flight_bytes = 0
 
@@ -237,16 +239,25 @@ class MstServer:
                 self.peak_in_flight_bytes = max(self.peak_in_flight_bytes, self.in_flight_bytes)
             if not batch:
                 continue
-            self.ex.execute(slot, batch, solo)
-            now = time.perf_counter()
-            with self.cv:
-                self.in_flight_bytes -= used
-                self.batches.append((slot, [r.rid for r in batch]))
-            for r in batch:
-                r.done_at = now
-                r.batch_size = len(batch)
-                r.slot = slot
-                r.done.set()
+            try:
+                self.ex.execute(slot, batch, solo)
+            except Exception as exc:  # a failed batch fails its requests, not the worker
+                code = getattr(exc, "status", MSTX_ERR_DEVICE)
+                for r in batch:
+                    r.status = code if isinstance(code, int) and code < 0 else MSTX_ERR_DEVICE
+                    r.in_mst = None
+                    r.total = 0
+                self.errors.append((slot, [r.rid for r in batch], repr(exc)))
+            finally:
+                now = time.perf_counter()
+                with self.cv:
+                    self.in_flight_bytes -= used
+                    self.batches.append((slot, [r.rid for r in batch]))
+                for r in batch:
+                    r.done_at = now
+                    r.batch_size = len(batch)
+                    r.slot = slot
+                    r.done.set()
 
 
 class PlainServer:

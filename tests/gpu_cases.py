@@ -31,6 +31,7 @@ TAIL_MAX = 10240  # largest round bound whose hook .. relabel run in one workgro
 MID_MAX = 16280  # largest vertex count of a batched graph solved by one workgroup, edges streamed
 MID_MAX_EDGES = 1 << 21  # ... and its largest edge count
 PRE_MAX = 65536  # largest vertex count of a batched graph contracted by one workgroup first
+BUCKET_MAX = 1023 << 14  # largest component count whose minima bucket mode takes
 
 
 def stats_consistent(gpu_stats, oracle_stats, limit=DENSE_MAX):

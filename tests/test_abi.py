@@ -35,6 +35,7 @@ def test_header_declares_entry_points():
     names = declared_functions()
     for must in ("mst_solve", "mst_solve_batched", "mst_select_min_edges", "mst_workspace_bytes",
                  "mst_set_dense_limit", "mst_set_small_limit", "mst_set_tail_limit", "mst_set_mid_limit",
+                 "mst_set_bucket_limit",
                  "mst_csr_to_edges", "mst_status_string"):
         assert must in names, names
 
@@ -104,6 +105,20 @@ def test_small_limit_option(lib):
         assert B.mst_set_small_limit(-1) == gpu_cases.SMALL_MAX
     finally:
         B.mst_set_small_limit(prev)
+
+
+def test_bucket_limit_option(lib):
+    from paper_2005_06913_amd import binding as B
+    prev = B.mst_set_bucket_limit(-1)
+    assert prev == gpu_cases.BUCKET_MAX
+    try:
+        assert B.mst_set_bucket_limit(2 ** 31 - 1) == prev
+        assert B.mst_set_bucket_limit(-1) == gpu_cases.BUCKET_MAX  # clamped
+        with B.bucket_limit(0):
+            assert B.mst_set_bucket_limit(-1) == 0
+        assert B.mst_set_bucket_limit(-1) == gpu_cases.BUCKET_MAX
+    finally:
+        B.mst_set_bucket_limit(prev)
 
 
 def test_tail_limit_option(lib):

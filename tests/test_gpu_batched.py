@@ -192,7 +192,43 @@ def degenerate_members(dev, path):
     graphs.append((40_000, half.src, half.dst, half.w))
     star = G.star_graph(30_000, seed=8)
     graphs.append((star.n, star.src, star.dst, star.w))
+    # no edges at all, in every class: small, mid-size, contracted, union
+    z32, zw = np.zeros(0, np.int32), np.zeros(0, np.uint32)
+    for n in (4000, 12_000, 20_000, gpu_cases.PRE_MAX, gpu_cases.PRE_MAX + 1):
+        graphs.append((n, z32, z32, zw))
     check_batch(dev, graphs, f"degenerate_{path}")
+
+
+@pytest.mark.timeout(600)
+def test_batched_4096_full_vs_oracle(dev):
+    """The full batched workload (4096 graphs, n log-uniform in [64, 65536],
+    average degree uniform in [4, 32], seed 5; about 3.3e8 edges): every
+    graph's edge flags, total and status against Kruskal on that graph alone
+    (host threads share the oracle calls)."""
+    import concurrent.futures as cf
+    import os
+
+    from paper_2005_06913_amd import graphgen as G
+    print("[case] batched_4096 seed 5, full size", flush=True)
+    b = G.batch(4096, seed=5)
+    vo, eo = b.vertex_offsets, b.edge_offsets
+    rc, in_mst, total, status = run_batched(dev, vo, eo, b.src, b.dst, b.w)
+    assert rc == 0
+    print("[case] batched_4096: GPU done, oracle per graph", flush=True)
+
+    def check(g):
+        x = b.graph(g)
+        k = oracle.kruskal(x.n, x.src, x.dst, x.w)
+        a, c = eo[g], eo[g + 1]
+        return (int(status[g]) == k.status and int(total[g]) == k.total
+                and bool(np.array_equal(in_mst[a:c], k.in_mst)))
+
+    oracle.default()  # built and loaded once, before the threads share it
+    workers = min(16, os.cpu_count() or 1)
+    with cf.ThreadPoolExecutor(max_workers=workers) as ex:
+        ok = list(ex.map(check, range(b.num_graphs)))
+    bad = [g for g, x in enumerate(ok) if not x]
+    assert not bad, f"{len(bad)} graphs differ from the oracle, first {bad[:8]}"
 
 
 def test_batched_equals_single(dev):

@@ -39,13 +39,14 @@ def to_dev(dev, src, dst, w):
             torch.from_numpy(np.ascontiguousarray(w, np.uint32)).to(dev))
 
 
-def gpu_solve(dev, n, src, dst, w, limit=gpu_cases.DENSE_MAX, small=gpu_cases.SMALL_MAX, tail=gpu_cases.TAIL_MAX):
+def gpu_solve(dev, n, src, dst, w, limit=gpu_cases.DENSE_MAX, small=gpu_cases.SMALL_MAX, tail=gpu_cases.TAIL_MAX,
+              bucket=gpu_cases.BUCKET_MAX):
     import paper_2005_06913_amd as P
     s, d, ww = to_dev(dev, src, dst, w)
     m = len(src)
     in_mst = torch.full((m,), 7, dtype=torch.uint8, device=dev)  # garbage: must be overwritten
     total = torch.full((1,), 12345, dtype=torch.int64, device=dev).view(torch.uint64)
-    with P.dense_limit(limit), P.small_limit(small), P.tail_limit(tail):
+    with P.dense_limit(limit), P.small_limit(small), P.tail_limit(tail), P.bucket_limit(bucket):
         st = P.mst_solve(n, s, d, ww, in_mst, total)
     torch.cuda.synchronize()
     stats = P.mst_last_round_stats()
@@ -53,10 +54,10 @@ def gpu_solve(dev, n, src, dst, w, limit=gpu_cases.DENSE_MAX, small=gpu_cases.SM
 
 
 def check_against_oracle(dev, name, n, src, dst, w, stats=True, limit=gpu_cases.DENSE_MAX,
-                         small=gpu_cases.SMALL_MAX, tail=gpu_cases.TAIL_MAX):
-    print(f"[case] {name} n={n} m={len(src)} dense_limit={limit} small_limit={small} tail_limit={tail}",
-          flush=True)
-    st, in_mst, total, gstats = gpu_solve(dev, n, src, dst, w, limit, small, tail)
+                         small=gpu_cases.SMALL_MAX, tail=gpu_cases.TAIL_MAX, bucket=gpu_cases.BUCKET_MAX):
+    print(f"[case] {name} n={n} m={len(src)} dense_limit={limit} small_limit={small} tail_limit={tail} "
+          f"bucket_limit={bucket}", flush=True)
+    st, in_mst, total, gstats = gpu_solve(dev, n, src, dst, w, limit, small, tail, bucket)
     k = oracle.kruskal(n, src, dst, w)
     assert st == k.status, f"{name}: status {st} != oracle {k.status}"
     assert total == k.total, f"{name}: total {total} != oracle {k.total}"
@@ -85,6 +86,22 @@ def test_min_edge_keys(dev, idx):
     assert st == 0
     got = out.view(torch.int64).cpu().numpy().view(np.uint64)
     assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("idx", [i for i, g in enumerate(gpu_cases.small_cases()) if g.n > gpu_cases.LDS_SLOTS])
+def test_min_edge_keys_global_mode(dev, idx):
+    """Round-0 minima by filtered global atomics (bucket mode off) on every case
+    above the LDS range."""
+    import paper_2005_06913_amd as P
+    g = gpu_cases.small_cases()[idx]
+    print(f"[case] min-edge global {g.name}", flush=True)
+    s, d, w = to_dev(dev, g.src, g.dst, g.w)
+    out = torch.zeros(g.n, dtype=torch.int64, device=dev).view(torch.uint64)
+    with P.bucket_limit(0):
+        assert P.mst_select_min_edges(g.n, s, d, w, out) == 0
+    st, want = oracle.min_edge_keys(g.n, g.src, g.dst, g.w)
+    assert st == 0
+    assert np.array_equal(out.view(torch.int64).cpu().numpy().view(np.uint64), want)
 
 
 def test_min_edge_keys_golden(dev):
@@ -118,6 +135,18 @@ FEW_IDS = [f"dense{a}-small{b}-tail{c}" for a, b, c in FEW_PATHS]
 def test_solve_small(dev, idx, limit, small, tail):
     g = gpu_cases.small_cases()[idx]
     check_against_oracle(dev, g.name, g.n, g.src, g.dst, g.w, limit=limit, small=small, tail=tail)
+
+
+# GLOBAL minima mode (bucket mode off): every round above the LDS range takes
+# filtered 64-bit atomic minima in device memory
+GLOBAL_CASES = [i for i, g in enumerate(gpu_cases.small_cases()) if g.n > gpu_cases.LDS_SLOTS]
+
+
+@pytest.mark.parametrize("limit,small,tail", FEW_PATHS[1:], ids=FEW_IDS[1:])
+@pytest.mark.parametrize("idx", GLOBAL_CASES)
+def test_solve_global_mode(dev, idx, limit, small, tail):
+    g = gpu_cases.small_cases()[idx]
+    check_against_oracle(dev, g.name, g.n, g.src, g.dst, g.w, limit=limit, small=small, tail=tail, bucket=0)
 
 
 def test_dense_finish_ends_early(dev):
@@ -230,9 +259,21 @@ def test_solve_full_size_rmat(dev):
 
 
 @pytest.mark.parametrize("n,d", [(10_000, 3), (10_000, 9), (100_000, 3), (100_000, 6), (100_000, 9),
-                                 (1_000_000, 3)])
+                                 (1_000_000, 3), (1_000_000, 6), (1_000_000, 9)])
 def test_solve_paper_shapes(dev, n, d):
     """Table 1 shapes (n vertices, average degree d): edge set, total and round statistics."""
     from paper_2005_06913_amd import graphgen as G
     g = G.paper_shape(n, d, seed=100 + d)
     check_against_oracle(dev, g.name, g.n, g.src, g.dst, g.w, stats=True)
+
+
+@pytest.mark.parametrize("tail", [gpu_cases.TAIL_MAX, 0])
+def test_solve_increasing_path_2_20(dev, tail):
+    """A path of n = 2^20 vertices with increasing weights: every vertex's
+    lightest edge goes to its successor, so round 0 adds all n - 1 edges as one
+    hook chain of depth n - 1 (the deepest the compare-and-swap hooking and the
+    pointer jumping meet)."""
+    from paper_2005_06913_amd import graphgen as G
+    g = G.path_graph(1 << 20)
+    gstats = check_against_oracle(dev, g.name, g.n, g.src, g.dst, g.w, tail=tail)
+    assert len(gstats) == 1 and int(gstats[0][2]) == g.n - 1

@@ -1,4 +1,5 @@
-"""GPU serving: every result in the mix equals the graph solved alone, bit-exact.
+"""GPU serving: every result in the mix equals the oracle on that graph alone
+and the GPU solve of it alone, bit-exact.
 
 Three slots on three streams solve overlapping batches of requests of
 uneven sizes (one-workgroup graphs and larger union-chunk graphs) that
@@ -37,13 +38,15 @@ def test_served_equals_alone(dev):
     srv.close()
     assert max(len(ids) for _, ids in srv.batches) > 1  # requests were batched
     for r in reqs:
+        # in the mix == the oracle on that graph alone == the GPU on it alone
+        k = oracle.kruskal(r.n, r.src, r.dst, r.w)
+        assert r.status == k.status == 0, (r.rid, r.status, k.status)
+        assert r.total == k.total, r.rid
+        assert np.array_equal(r.in_mst, k.in_mst), r.rid
         alone = P.solve(r.n, torch.from_numpy(r.src).to(dev), torch.from_numpy(r.dst).to(dev),
                         torch.from_numpy(r.w).to(dev))
-        assert r.status == alone.status == 0
-        assert r.total == alone.total
-        assert np.array_equal(r.in_mst, alone.in_mst.cpu().numpy())
-    k = oracle.kruskal(reqs[0].n, reqs[0].src, reqs[0].dst, reqs[0].w)
-    assert np.array_equal(reqs[0].in_mst, k.in_mst)
+        assert alone.status == 0 and alone.total == k.total, r.rid
+        assert np.array_equal(alone.in_mst.cpu().numpy(), k.in_mst), r.rid
     ex.release()
 
 

@@ -104,3 +104,32 @@ def test_large_requests_run_alone_and_caps():
         else:
             assert sum(ms) <= 30_000 or len(ids) == 1
     assert all(r.status == 0 for r in reqs)
+
+
+class FailingExecutor(FakeExecutor):
+    """Raises on every batch holding request 3; solves the others."""
+
+    def execute(self, slot, reqs, solo=False):
+        if any(r.rid == 3 for r in reqs):
+            raise RuntimeError("device lost")
+        super().execute(slot, reqs, solo)
+
+
+def test_failed_batch_releases_slot_and_requests():
+    """An executor that raises fails that batch's requests (device error status),
+    frees its memory share and keeps the worker serving the rest."""
+    ex = FailingExecutor(delay=0.005)
+    srv = serve.MstServer(ex, slots=2, hbm_budget_bytes=1 << 30).start()
+    reqs = make_requests(30, seed=4)
+    serve.poisson_replay(srv, reqs, qps=500.0, seed=5)
+    srv.close()
+    assert srv.in_flight_bytes == 0
+    assert srv.errors and any(3 in ids for _, ids, _ in srv.errors)
+    failed = {rid for _, ids, _ in srv.errors for rid in ids}
+    for r in reqs:
+        if r.rid in failed:
+            assert r.status == serve.MSTX_ERR_DEVICE and r.in_mst is None
+        else:
+            k = oracle.kruskal(r.n, r.src, r.dst, r.w)
+            assert r.status == k.status == 0 and r.total == k.total
+            assert np.array_equal(r.in_mst, k.in_mst)
