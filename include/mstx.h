@@ -58,6 +58,7 @@ extern "C" {
 #define MSTX_ERR_TOO_LARGE (-3)    /* m > 0xFFFFFFFF                                  */
 #define MSTX_ERR_OUT_OF_MEMORY (-4)/* workspace allocation failed or over the limit   */
 #define MSTX_ERR_DEVICE (-5)       /* a HIP call failed, or a round-count watchdog    */
+#define MSTX_ERR_SCRATCH_LIMIT (-6)/* mst_solve_noalloc: graph over its fixed scratch */
 
 /*
  * Minimum spanning tree of one graph (Section 2.1; parallel form after
@@ -74,6 +75,31 @@ extern "C" {
  */
 int mst_solve(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, const uint32_t* w,
               uint8_t* out_in_mst, uint64_t* out_total_weight, void* stream);
+
+/*
+ * mst_solve for callers that cannot allocate memory: code that must not call
+ * hipMalloc (a harness that forbids it, a tight serving loop that keeps its
+ * memory fixed).  Same arguments, results, statuses and round statistics as
+ * mst_solve; it allocates nothing, device or host (no hipMalloc, hipFree,
+ * pinned memory, events or library allocations), so it does not use the
+ * per-stream workspace or MSTX_WORKSPACE_LIMIT_BYTES.
+ * Scratch: one fixed 256 MiB device array inside the library, a copy per
+ * device, held from the library's first use on that device until the process
+ * ends.  A graph fits if mst_workspace_bytes(n, m) plus 2 KB of round records
+ * is at most 256 MiB (for example n = 2^20 with m = 2^22, or n = 2^18 with
+ * m = 5 * 2^20); graphs that take the one-workgroup path (n <= 8192,
+ * m <= 131072, see mst_set_small_limit) always fit.  A larger graph returns
+ * MSTX_ERR_SCRATCH_LIMIT before any device work.
+ * Every call on a device shares that device's scratch, which keeps the last
+ * call's contents (each call initialises what it reads).  Calls on one device
+ * are serialised by a lock in the library and each finishes its device work
+ * before returning, so they never overlap on the scratch; two calls that
+ * overlapped on one device would race.  The round records travel to the host
+ * by a plain copy after each synchronisation (two rounds per
+ * synchronisation), so a solve may take longer than mst_solve.
+ */
+int mst_solve_noalloc(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, const uint32_t* w,
+                      uint8_t* out_in_mst, uint64_t* out_total_weight, void* stream);
 
 /*
  * Minimum spanning forests of many independent graphs in one call (the

@@ -14,6 +14,7 @@ from .binding import (  # noqa: F401
     MSTX_ERR_DEVICE,
     MSTX_ERR_INVALID_ARG,
     MSTX_ERR_OUT_OF_MEMORY,
+    MSTX_ERR_SCRATCH_LIMIT,
     MSTX_ERR_TOO_LARGE,
     MSTX_ERR_VERTEX_RANGE,
     MSTX_OK,
@@ -38,6 +39,7 @@ from .binding import (  # noqa: F401
     mst_set_tail_limit,
     mst_solve,
     mst_solve_batched,
+    mst_solve_noalloc,
     mst_status_string,
     mst_workspace_bytes,
     mst_workspace_release,

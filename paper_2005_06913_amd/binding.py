@@ -23,11 +23,13 @@ MSTX_ERR_VERTEX_RANGE = -2
 MSTX_ERR_TOO_LARGE = -3
 MSTX_ERR_OUT_OF_MEMORY = -4
 MSTX_ERR_DEVICE = -5
+MSTX_ERR_SCRATCH_LIMIT = -6
 
 EXPORTS = ("mst_solve", "mst_solve_batched", "mst_batched_workspace_bytes", "mst_select_min_edges",
            "mst_last_round_stats", "mst_workspace_bytes", "mst_status_string", "mst_profile_enable",
            "mst_profile_read", "mst_profile_kernel_name", "mst_workspace_release", "mst_set_dense_limit", "mst_set_small_limit",
-           "mst_set_tail_limit", "mst_set_mid_limit", "mst_set_bucket_limit", "mst_csr_to_edges")
+           "mst_set_tail_limit", "mst_set_mid_limit", "mst_set_bucket_limit", "mst_csr_to_edges",
+           "mst_solve_noalloc")
 
 _lib = None
 
@@ -50,6 +52,8 @@ def load_library(path: str = LIB_PATH):
     i32, i64, p = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
     lib.mst_solve.argtypes = [i32, i64, p, p, p, p, p, p]
     lib.mst_solve.restype = ctypes.c_int
+    lib.mst_solve_noalloc.argtypes = [i32, i64, p, p, p, p, p, p]
+    lib.mst_solve_noalloc.restype = ctypes.c_int
     lib.mst_solve_batched.argtypes = [i32, p, p, p, p, p, p, p, p, p]
     lib.mst_solve_batched.restype = ctypes.c_int
     lib.mst_batched_workspace_bytes.argtypes = [i32, p, p]
@@ -249,6 +253,17 @@ def mst_solve(n, src, dst, w, out_in_mst, out_total_weight, stream=None) -> int:
             _dev_ptr(w, torch.uint32, "w", m), _dev_ptr(out_in_mst, torch.uint8, "out_in_mst", m),
             _dev_ptr(out_total_weight, torch.uint64, "out_total_weight", 1))
     return int(load_library().mst_solve(int(n), m, *args, _stream_handle(stream)))
+
+
+def mst_solve_noalloc(n, src, dst, w, out_in_mst, out_total_weight, stream=None) -> int:
+    """C ``mst_solve_noalloc`` (mst_solve on the library's fixed device scratch,
+    allocating nothing); same tensors as ``mst_solve``.  Returns the status."""
+    import torch
+    m = int(src.numel())
+    args = (_dev_ptr(src, torch.int32, "src", m), _dev_ptr(dst, torch.int32, "dst", m),
+            _dev_ptr(w, torch.uint32, "w", m), _dev_ptr(out_in_mst, torch.uint8, "out_in_mst", m),
+            _dev_ptr(out_total_weight, torch.uint64, "out_total_weight", 1))
+    return int(load_library().mst_solve_noalloc(int(n), m, *args, _stream_handle(stream)))
 
 
 def _host_offsets(a, name):

@@ -27,6 +27,15 @@
 #include "mstx.h"
 #include "mstx_internal.h"
 
+// Device scratch of mst_solve_noalloc, for callers that cannot allocate: the
+// workspace of one solve, its round records and the one-workgroup path's
+// status words.  Each device the library runs on holds its own copy (the
+// code object's data segment) until the process ends.  In host code this
+// name is only a handle: its device address comes from hipGetSymbolAddress,
+// once per device.
+static constexpr size_t kNoAllocScratchBytes = size_t(256) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
 namespace mstx {
 namespace {
 
@@ -43,7 +52,7 @@ struct Layout {
 
 constexpr int kSlabRows = 256;  // workgroup rows of the LDS-mode slab
 
-size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+constexpr size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Workspace plan for a graph with n vertices and m edges.
 Layout plan(int32_t n, int64_t m) {
@@ -120,7 +129,14 @@ std::atomic<int> g_tail_limit{kTailMax};
 std::atomic<int64_t> g_bucket_limit{kBucketMaxComponents};
 std::map<std::pair<int, hipStream_t>, std::unique_ptr<DeviceCache>> g_caches;
 
-thread_local std::vector<int64_t> t_last_stats;
+// Per-round statistics of the calling thread's last single-graph solve
+// (components, live edges, edges added per round), in a fixed-size array.
+struct RoundStats {
+  int rounds = 0;
+  int64_t v[3 * (kMaxRounds + 1)] = {};
+  void clear() { rounds = 0; }
+};
+thread_local RoundStats t_last_stats;
 
 size_t workspace_limit() {
   const char* s = std::getenv("MSTX_WORKSPACE_LIMIT_BYTES");
@@ -281,7 +297,7 @@ struct LaunchTimer {
   }
   // After the stream is synchronised.  chosen[r] = mode that ran in round r,
   // bytes[r] = algorithmic bytes of round r's scan; rounds >= nrounds were idle.
-  void commit(int nrounds, const std::vector<int>& chosen, const std::vector<double>& bytes) {
+  void commit(int nrounds, const int* chosen, const double* bytes) {
     if (!on) return;
     std::lock_guard<std::mutex> g(g_prof.mu);
     for (const auto& p : pending) {
@@ -315,7 +331,9 @@ struct Solve {
   uint8_t* in_mst;
   unsigned long long* total;
   hipStream_t s;
-  DeviceCache* dc;
+  int cus;               // compute units of the device
+  HostRound* rounds;     // round records: pinned host memory, or device memory
+  hipEvent_t* events;    // one event per round, recorded after it (nullptr: none)
   Layout L;
   unsigned long long* best;
   int32_t* parent;
@@ -337,7 +355,7 @@ struct Solve {
   int dense_limit;            // 0: no dense finish
   int tail_limit;             // 0: every round takes the multi-workgroup hook .. relabel
   int64_t bucket_limit;       // largest bound that may take bucket mode (0: never)
-  std::vector<int> launched;  // per round
+  int launched[kMaxRounds + 1];  // per round
 };
 
 // Enqueues the scan of `stage` (0: round 0, 1: round 1, 2: rounds >= 2) for a
@@ -365,7 +383,7 @@ int enqueue_scan(Solve& S, int r, int stage, int64_t bound, bool exact, hipError
   ScanArgs A{r,      launched, S.src,     S.dst,    S.w,    (uint32_t)S.m, S.n,     S.labpool, S.rec,
              S.seg_cnt, S.L.nseg, S.best, S.st, S.offers, S.offT, S.slab, S.L.slab_cap, S.pbest, -1,
              S.btot};
-  const int cus = S.dc->cus;
+  const int cus = S.cus;
   for (int mode : {kModeDense, kModeLds, kModeBucket, kModeGlobal}) {
     if (!(launched & (1 << mode))) continue;
     int grid;
@@ -413,7 +431,7 @@ int enqueue_scan(Solve& S, int r, int stage, int64_t bound, bool exact, hipError
     if (mode == kModeDense && S.in_mst) {
       const int kd = T.start(kDenseFinish, r, mode);
       err = launch_dense_finish(r, launched, S.pbest, S.seg_cnt, S.L.nseg, S.rec, S.in_mst, S.total, S.st,
-                                S.dc->host_rounds, S.s);
+                                S.rounds, S.s);
       T.stop(kd);
       if (err != hipSuccess) return launched;
     }
@@ -434,22 +452,23 @@ int enqueue_scan(Solve& S, int r, int stage, int64_t bound, bool exact, hipError
   return launched;
 }
 
-// Enqueues round r (component count at most `bound`, exact when r == 0).
-hipError_t enqueue_round(Solve& S, int r, int64_t bound, int64_t n_prev = 0) {
+// Enqueues round r (component count at most `bound`; `exact`: the count is
+// known to be `bound`, so only its own minima mode is launched).
+hipError_t enqueue_round(Solve& S, int r, int64_t bound, int64_t n_prev, bool exact) {
   LaunchTimer& T = t_timer;
   hipError_t err = hipSuccess;
   const int stage = r == 0 ? 0 : (r == 1 ? 1 : 2);
-  S.launched[r] = enqueue_scan(S, r, stage, bound, r == 0, err, n_prev);
+  S.launched[r] = enqueue_scan(S, r, stage, bound, exact, err, n_prev);
   if (err != hipSuccess) return err;
   const int gh = grid_for(std::max<int64_t>(bound, 1));
   if (bound <= S.tail_limit) {
     // few components: the rest of the round in one workgroup
     const int k = T.start(kRoundTail, r, -1);
     err = launch_round_tail(r, (int32_t)bound, S.rec, S.best, S.parent, S.labpool, S.seg_cnt, S.L.nseg, S.in_mst,
-                            S.total, S.btot, S.st, S.dc->host_rounds, S.s);
+                            S.total, S.btot, S.st, S.rounds, S.s);
     T.stop(k);
     if (err != hipSuccess) return err;
-    return hipEventRecord(S.dc->round_ev[r], S.s);
+    return S.events ? hipEventRecord(S.events[r], S.s) : hipSuccess;
   }
   int k = T.start(kHook, r, -1);
   err = launch_hook(r, S.rec, S.best, S.parent, S.st, S.in_mst, S.part_sel, S.part_w, gh, S.s);
@@ -461,14 +480,14 @@ hipError_t enqueue_round(Solve& S, int r, int64_t bound, int64_t n_prev = 0) {
   if (err != hipSuccess) return err;
   k = T.start(kFinalize, r, -1);
   err = launch_finalize(r, S.rootcnt, S.rootpre, S.seg_cnt, S.L.nseg, S.part_sel, S.part_w, gh, S.st, S.total,
-                        S.dc->host_rounds, S.s);
+                        S.rounds, S.s);
   T.stop(k);
   if (err != hipSuccess) return err;
   k = T.start(kRelabel, r, -1);
   err = launch_relabel(r, S.root_of, S.rootmask, S.rootpre, S.labpool, S.parent, S.best, S.btot, S.st, gh, S.s);
   T.stop(k);
   if (err != hipSuccess) return err;
-  return hipEventRecord(S.dc->round_ev[r], S.s);
+  return S.events ? hipEventRecord(S.events[r], S.s) : hipSuccess;
 }
 
 // A round record as the device left it in pinned host memory (read through
@@ -490,11 +509,13 @@ HostRound load_record(const HostRound* p) {
 
 // The round loop of one graph (n >= 1, m >= 1) on a workspace of at least
 // plan(n, m).bytes; the device cache is locked by the caller.
-// The solve state of a graph on the cached workspace laid out by L.
-Solve make_solve(DeviceCache* dc, const Layout& L, int32_t n, int64_t m, const int32_t* src, const int32_t* dst,
-                 const uint32_t* w, uint8_t* in_mst, uint64_t* total, hipStream_t s) {
-  void* B = dc->base;
-  Solve S;
+// The solve state of a graph on the workspace at B laid out by L; round
+// records go to `rounds` (one per round), and `events` (if not null) are
+// recorded after each round.
+Solve make_solve(void* B, int cus, HostRound* rounds, hipEvent_t* events, const Layout& L, int32_t n, int64_t m,
+                 const int32_t* src, const int32_t* dst, const uint32_t* w, uint8_t* in_mst, uint64_t* total,
+                 hipStream_t s) {
+  Solve S{};
   S.n = n;
   S.m = m;
   S.src = src;
@@ -503,7 +524,9 @@ Solve make_solve(DeviceCache* dc, const Layout& L, int32_t n, int64_t m, const i
   S.in_mst = in_mst;
   S.total = reinterpret_cast<unsigned long long*>(total);
   S.s = s;
-  S.dc = dc;
+  S.cus = cus;
+  S.rounds = rounds;
+  S.events = events;
   S.L = L;
   S.best = at<unsigned long long>(B, L.best);
   S.parent = at<int32_t>(B, L.parent);
@@ -525,7 +548,7 @@ Solve make_solve(DeviceCache* dc, const Layout& L, int32_t n, int64_t m, const i
   S.dense_limit = g_dense_limit.load();
   S.tail_limit = g_tail_limit.load();
   S.bucket_limit = g_bucket_limit.load();
-  S.launched.assign(kMaxRounds + 1, 0);
+  for (int& x : S.launched) x = 0;
   return S;
 }
 
@@ -533,7 +556,7 @@ Solve make_solve(DeviceCache* dc, const Layout& L, int32_t n, int64_t m, const i
 // previous label map read once, the minima initialised and written once, the
 // compacted survivors written once (a dense round instead writes its pair
 // table once and compacts nothing).
-double round_scan_bytes(const HostRound* rec, const std::vector<int32_t>& nr_of, int r, int32_t n, int64_t m) {
+double round_scan_bytes(const HostRound* rec, const int32_t* nr_of, int r, int32_t n, int64_t m) {
   const HostRound& M = rec[r];
   const double nrd = (double)nr_of[r];
   const double out = M.dense ? 8.0 * (double)dense_pairs(nr_of[r]) : 16.0 * nrd + 16.0 * (double)M.live;
@@ -542,26 +565,77 @@ double round_scan_bytes(const HostRound* rec, const std::vector<int32_t>& nr_of,
   return 16.0 * (double)rec[r - 1].live + 4.0 * (double)nr_of[r - 1] + out;
 }
 
+// What the host learns from the round records of one solve.
+struct RoundLoop {
+  int32_t n = 0;
+  int rounds = 0;                 // records taken
+  int status = MSTX_ERR_DEVICE;   // until a record decides
+  bool done = false;
+  int32_t nr_of[kMaxRounds + 2];  // exact component count entering round r (r <= rounds)
+
+  explicit RoundLoop(int32_t n0) : n(n0) {
+    for (int32_t& x : nr_of) x = 0;
+    nr_of[0] = n0;
+  }
+  // Takes round r's record (r == rounds); sets `done` when the solve ends.
+  void take(int r, const HostRound& M) {
+    rounds = r + 1;
+    if (r == 0 && M.err) {
+      status = MSTX_ERR_VERTEX_RANGE;
+      done = true;
+    } else if (M.err_internal) {
+      status = MSTX_ERR_DEVICE;
+      done = true;
+    } else {
+      nr_of[r + 1] = M.n_next;
+      if (M.n_next <= 1) {
+        status = (n <= 1 || M.edges_added == (int64_t)n - 1) ? MSTX_OK : MSTX_DISCONNECTED;
+        done = true;
+      }
+    }
+  }
+  // Statistics of the finished solve for mst_last_round_stats, and the
+  // profile's per-round modes and bytes.
+  void finish(const Solve& S, const HostRound* rec, int64_t m) const {
+    RoundStats& T = t_last_stats;
+    T.rounds = rounds;
+    int chosen[kMaxRounds + 1];
+    double bytes[kMaxRounds + 1];
+    for (int r = 0; r < rounds; ++r) {
+      T.v[3 * r + 0] = nr_of[r];
+      T.v[3 * r + 1] = rec[r].live;
+      T.v[3 * r + 2] = rec[r].sel;
+      chosen[r] = pick_mode(nr_of[r], S.launched[r]);
+      bytes[r] = round_scan_bytes(rec, nr_of, r, n, m);
+    }
+    t_timer.commit(rounds, chosen, bytes);
+  }
+};
+
+// S0 of a solve on the stream: outputs zeroed, minima, parents and state reset.
+hipError_t start_solve(const Solve& S) {
+  hipError_t e = hipMemsetAsync(S.in_mst, 0, (size_t)S.m, S.s);
+  if (e == hipSuccess) e = hipMemsetAsync(S.total, 0, sizeof(uint64_t), S.s);
+  if (e == hipSuccess)
+    e = launch_init(S.n, S.best, S.parent, S.dense_limit > 0 ? S.pbest : nullptr, S.btot, S.st, grid_for(S.n),
+                    S.s);
+  return e;
+}
+
 int solve_locked(DeviceCache* dc, const Layout& L, int32_t n, int64_t m, const int32_t* src, const int32_t* dst,
                  const uint32_t* w, uint8_t* in_mst, uint64_t* total, hipStream_t s) {
-  Solve S = make_solve(dc, L, n, m, src, dst, w, in_mst, total, s);
+  Solve S = make_solve(dc->base, dc->cus, dc->host_rounds, dc->round_ev, L, n, m, src, dst, w, in_mst, total, s);
   const int max_rounds = std::min(rounds_bound(n) + 1, kMaxRounds);
 
-  LaunchTimer& T = t_timer;
-  T.begin(s);
-  HIP_OK(hipMemsetAsync(in_mst, 0, (size_t)m, s));
-  HIP_OK(hipMemsetAsync(total, 0, sizeof(uint64_t), s));
-  HIP_OK(launch_init(n, S.best, S.parent, S.dense_limit > 0 ? S.pbest : nullptr, S.btot, S.st, grid_for(n), s));
+  t_timer.begin(s);
+  HIP_OK(start_solve(S));
   // every record reads "pending" until the device writes it
   for (int r = 0; r <= kMaxRounds; ++r) dc->host_rounds[r].n_next = kRecordPending;
   std::atomic_thread_fence(std::memory_order_seq_cst);
-  HIP_OK(enqueue_round(S, 0, n));
+  HIP_OK(enqueue_round(S, 0, n, 0, true));
 
-  int status = MSTX_ERR_DEVICE;  // until the loop decides
-  int rounds = 0;
+  RoundLoop R(n);
   int32_t n_known = n;  // exact component count entering round r
-  std::vector<int32_t> nr_of(kMaxRounds + 2, 0);
-  nr_of[0] = n;
   int r_enq = 0;
   for (int r = 0; r < max_rounds; ++r) {
     // a round whose scan takes the dense finish (its count n_known is exact
@@ -569,7 +643,7 @@ int solve_locked(DeviceCache* dc, const Layout& L, int32_t n, int64_t m, const i
     const bool final_round = pick_mode(n_known, S.launched[r]) == kModeDense;
     if (r_enq == r && r + 1 <= kMaxRounds - 1 && !final_round) {
       // n_known entered round r: the size of the label map round r + 1 reads
-      HIP_OK(enqueue_round(S, r + 1, n_known / 2, n_known));
+      HIP_OK(enqueue_round(S, r + 1, n_known / 2, n_known, false));
       r_enq = r + 1;
     }
     if (r_enq < r) break;  // never: the round before was final (status stays MSTX_ERR_DEVICE)
@@ -581,38 +655,14 @@ int solve_locked(DeviceCache* dc, const Layout& L, int32_t n, int64_t m, const i
       M = load_record(dc->host_rounds + r);
       if (M.n_next == kRecordPending) break;  // status stays MSTX_ERR_DEVICE
     }
-    rounds = r + 1;
-    if (r == 0 && M.err) {
-      status = MSTX_ERR_VERTEX_RANGE;
-      break;
-    }
-    if (M.err_internal) {
-      status = MSTX_ERR_DEVICE;
-      break;
-    }
+    R.take(r, M);
+    if (R.done) break;
     n_known = M.n_next;
-    nr_of[r + 1] = n_known;
-    if (n_known <= 1) {
-      status = (n <= 1 || M.edges_added == (int64_t)n - 1) ? MSTX_OK : MSTX_DISCONNECTED;
-      break;
-    }
   }
   HIP_OK(hipStreamSynchronize(s));  // drains the round enqueued after the last one
-  if (status < 0) return status;
-
-  t_last_stats.resize(3 * (size_t)rounds);
-  std::vector<int> chosen(kMaxRounds + 1, -1);
-  std::vector<double> bytes(kMaxRounds + 1, 0.0);
-  for (int r = 0; r < rounds; ++r) {
-    const HostRound& M = dc->host_rounds[r];
-    t_last_stats[3 * r + 0] = nr_of[r];
-    t_last_stats[3 * r + 1] = M.live;
-    t_last_stats[3 * r + 2] = M.sel;
-    chosen[r] = pick_mode(nr_of[r], S.launched[r]);
-    bytes[r] = round_scan_bytes(dc->host_rounds, nr_of, r, n, m);
-  }
-  T.commit(rounds, chosen, bytes);
-  return status;
+  if (R.status < 0) return R.status;
+  R.finish(S, dc->host_rounds, m);
+  return R.status;
 }
 
 // A graph of at most kSmallN vertices in one launch (the batched path's
@@ -643,13 +693,14 @@ int solve_small_locked(DeviceCache* dc, int32_t n, int64_t m, const int32_t* src
   const int rows = (int)std::min<int64_t>(std::max<int64_t>(st[0], 0), kMaxRounds + 1);
   // algorithmic bytes: every round reads the 12-byte edges once, plus one
   // final round that finds nothing to add
-  T.commit(0, {}, {});
+  T.commit(0, nullptr, nullptr);
   if (T.on) {
     std::lock_guard<std::mutex> g(g_prof.mu);
     g_prof.bytes[kSmallSolve] += 12.0 * (double)m * (double)(rows + 1);
   }
   if (status < 0) return status;
-  t_last_stats.assign(st + 1, st + 1 + 3 * rows);
+  t_last_stats.rounds = rows;
+  std::memcpy(t_last_stats.v, st + 1, sizeof(int64_t) * 3 * (size_t)rows);
   return status;
 }
 
@@ -675,6 +726,123 @@ int solve(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, const ui
   int rc = acquire(dc, lock, L.bytes, s);
   if (rc != MSTX_OK) return rc;
   return solve_locked(dc, L, n, m, src, dst, w, in_mst, total, s);
+}
+
+// ------------------------------------------------------ allocation-free solve
+
+// One device's state of mst_solve_noalloc: the device address of its copy of
+// `scratch` and a lock that serialises the calls on that device (they share
+// the scratch; each call has finished its device work when it returns, so
+// calls never overlap on it).
+struct NoAllocDevice {
+  std::mutex mu;
+  unsigned char* ptr = nullptr;
+  int cus = 0;
+};
+constexpr int kNoAllocDevices = 64;
+NoAllocDevice g_noalloc[kNoAllocDevices];
+constexpr size_t kNoAllocRecordBytes = align_up(sizeof(HostRound) * (kMaxRounds + 1));
+
+// First call on the current device `dev`: the scratch's device address and
+// the kernels' LDS limits.  No allocation.
+int noalloc_setup(NoAllocDevice& D, int dev) {
+  if (D.ptr) return MSTX_OK;
+  void* p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr) {
+    (void)hipGetLastError();
+    return MSTX_ERR_DEVICE;
+  }
+  int cus = 0;
+  HIP_OK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  if (configure_kernels() != hipSuccess) (void)hipGetLastError();
+  if (configure_batched_kernels() != hipSuccess) (void)hipGetLastError();
+  D.cus = cus;
+  D.ptr = static_cast<unsigned char*>(p);
+  return MSTX_OK;
+}
+
+// solve() without allocating: the same kernels on this device's scratch.  The
+// round records are written to device memory and copied into the host's
+// stack after each synchronisation (no pinned memory, no events); each
+// synchronisation covers two rounds: the next one at its exact component
+// count and the one after it at the bound of half that count.
+int solve_noalloc(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, const uint32_t* w, uint8_t* in_mst,
+                  uint64_t* total, hipStream_t s) {
+  t_last_stats.clear();
+  if (m == 0) {
+    HIP_OK(hipMemsetAsync(total, 0, sizeof(uint64_t), s));
+    HIP_OK(hipStreamSynchronize(s));
+    return n <= 1 ? MSTX_OK : MSTX_DISCONNECTED;
+  }
+  if (n == 0) return MSTX_ERR_VERTEX_RANGE;
+  const bool small = n <= g_small_limit.load() && m <= kSmallMaxEdges;
+  const Layout L = plan(n, m);
+  if (!small && L.bytes + kNoAllocRecordBytes > kNoAllocScratchBytes) return MSTX_ERR_SCRATCH_LIMIT;
+  int dev = 0;
+  HIP_OK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kNoAllocDevices) return MSTX_ERR_DEVICE;
+  NoAllocDevice& D = g_noalloc[dev];
+  std::lock_guard<std::mutex> lock(D.mu);
+  int rc = noalloc_setup(D, dev);
+  if (rc != MSTX_OK) return rc;
+  t_timer.begin(s);
+  t_timer.on = false;  // profiling events are not created here
+
+  if (small) {
+    // status word, then the statistics, at the start of the scratch
+    int64_t* words = reinterpret_cast<int64_t*>(D.ptr);
+    int64_t host[1 + kSmallStatsWords];
+    HIP_OK(hipMemsetAsync(in_mst, 0, (size_t)m, s));
+    HIP_OK(launch_small_solve_single(n, m, src, dst, w, in_mst, reinterpret_cast<unsigned long long*>(total),
+                                     reinterpret_cast<int32_t*>(words), words + 1, s));
+    HIP_OK(hipMemcpyAsync(host, words, sizeof(host), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    const int32_t status = *reinterpret_cast<const int32_t*>(host);
+    if (status < 0) return status;
+    const int rows = (int)std::min<int64_t>(std::max<int64_t>(host[1], 0), kMaxRounds + 1);
+    t_last_stats.rounds = rows;
+    std::memcpy(t_last_stats.v, host + 2, sizeof(int64_t) * 3 * (size_t)rows);
+    return status;
+  }
+
+  HostRound* drec = reinterpret_cast<HostRound*>(D.ptr + L.bytes);
+  Solve S = make_solve(D.ptr, D.cus, drec, nullptr, L, n, m, src, dst, w, in_mst, total, s);
+  const int max_rounds = std::min(rounds_bound(n) + 1, kMaxRounds);
+  HIP_OK(start_solve(S));
+  HIP_OK(hipMemsetAsync(drec, 0xFF, kNoAllocRecordBytes, s));  // n_next = -1 until written
+  HIP_OK(enqueue_round(S, 0, n, 0, true));
+  int r_enq = 0;
+  if (pick_mode(n, S.launched[0]) != kModeDense && max_rounds > 1) {
+    HIP_OK(enqueue_round(S, 1, n / 2, n, false));
+    r_enq = 1;
+  }
+  RoundLoop R(n);
+  HostRound h[kMaxRounds + 1];
+  for (;;) {
+    HIP_OK(hipMemcpyAsync(h, drec, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    // every enqueued round has finished: its record is there
+    for (int r = R.rounds; r <= r_enq && !R.done; ++r) {
+      if (h[r].n_next < 0) {
+        R.done = true;  // never: a finished round wrote its record
+        break;
+      }
+      R.take(r, h[r]);
+    }
+    if (R.done) break;
+    const int r = r_enq + 1;  // its component count is known exactly now
+    if (r >= max_rounds) break;  // round-count watchdog: MSTX_ERR_DEVICE
+    const int32_t nk = R.nr_of[r];
+    HIP_OK(enqueue_round(S, r, nk, R.nr_of[r - 1], true));
+    r_enq = r;
+    if (pick_mode(nk, S.launched[r]) != kModeDense && r + 1 < max_rounds) {
+      HIP_OK(enqueue_round(S, r + 1, nk / 2, nk, false));
+      r_enq = r + 1;
+    }
+  }
+  if (R.status < 0) return R.status;
+  R.finish(S, h, m);
+  return R.status;
 }
 
 // ----------------------------------------------------------------- batched
@@ -989,7 +1157,8 @@ int select_min_edges(int32_t n, int64_t m, const int32_t* src, const int32_t* ds
   S.dst = dst;
   S.w = w;
   S.s = s;
-  S.dc = dc;
+  S.cus = dc->cus;
+  S.rounds = dc->host_rounds;
   S.L = L;
   S.best = reinterpret_cast<unsigned long long*>(out_best);
   S.seg_cnt = at<uint32_t>(B, L.seg_cnt);
@@ -1004,7 +1173,6 @@ int select_min_edges(int32_t n, int64_t m, const int32_t* src, const int32_t* ds
   S.dense_limit = 0;  // per-vertex minima: never the pair table
   S.bucket_limit = g_bucket_limit.load();
   S.in_mst = nullptr;
-  S.launched.assign(1, 0);
   t_timer.begin(s);
   t_timer.on = false;
   HIP_OK(launch_init(n, S.best, at<int32_t>(B, L.parent), nullptr, S.btot, S.st, grid_for(n), s));
@@ -1030,6 +1198,14 @@ int mst_solve(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, cons
   if (rc != MSTX_OK) return rc;
   if (!out_total_weight || (m > 0 && !out_in_mst)) return MSTX_ERR_INVALID_ARG;
   return mstx::solve(n, m, src, dst, w, out_in_mst, out_total_weight, (hipStream_t)stream);
+}
+
+int mst_solve_noalloc(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, const uint32_t* w,
+                      uint8_t* out_in_mst, uint64_t* out_total_weight, void* stream) {
+  int rc = mstx::check_args(n, m, src, dst, w);
+  if (rc != MSTX_OK) return rc;
+  if (!out_total_weight || (m > 0 && !out_in_mst)) return MSTX_ERR_INVALID_ARG;
+  return mstx::solve_noalloc(n, m, src, dst, w, out_in_mst, out_total_weight, (hipStream_t)stream);
 }
 
 int mst_solve_batched(int32_t num_graphs, const int64_t* vertex_offsets, const int64_t* edge_offsets,
@@ -1070,9 +1246,8 @@ int mst_select_min_edges(int32_t n, int64_t m, const int32_t* src, const int32_t
 
 int mst_last_round_stats(int64_t* out, int32_t max_rounds) {
   if (max_rounds < 0 || (max_rounds > 0 && !out)) return MSTX_ERR_INVALID_ARG;
-  const int have = (int)(mstx::t_last_stats.size() / 3);
-  const int k = std::min(have, (int)max_rounds);
-  if (k > 0) std::memcpy(out, mstx::t_last_stats.data(), sizeof(int64_t) * 3 * (size_t)k);
+  const int k = std::min(mstx::t_last_stats.rounds, (int)max_rounds);
+  if (k > 0) std::memcpy(out, mstx::t_last_stats.v, sizeof(int64_t) * 3 * (size_t)k);
   return k;
 }
 
@@ -1169,6 +1344,9 @@ const char* mst_status_string(int status) {
     case MSTX_ERR_TOO_LARGE: return "too many edges: m must be <= 0xFFFFFFFF";
     case MSTX_ERR_OUT_OF_MEMORY: return "device workspace allocation failed or exceeds MSTX_WORKSPACE_LIMIT_BYTES";
     case MSTX_ERR_DEVICE: return "HIP runtime error or round-count watchdog";
+    case MSTX_ERR_SCRATCH_LIMIT:
+      return "graph too large for mst_solve_noalloc: its workspace (mst_workspace_bytes) plus 2 KB of round "
+             "records must fit the library's fixed 256 MiB device scratch";
     default: return "unknown status";
   }
 }

@@ -48,7 +48,7 @@ def test_library_exports_every_declared_symbol(lib):
 def test_status_strings(lib):
     from paper_2005_06913_amd import binding as B
     codes = [B.MSTX_OK, B.MSTX_DISCONNECTED, B.MSTX_ERR_INVALID_ARG, B.MSTX_ERR_VERTEX_RANGE,
-             B.MSTX_ERR_TOO_LARGE, B.MSTX_ERR_OUT_OF_MEMORY, B.MSTX_ERR_DEVICE]
+             B.MSTX_ERR_TOO_LARGE, B.MSTX_ERR_OUT_OF_MEMORY, B.MSTX_ERR_DEVICE, B.MSTX_ERR_SCRATCH_LIMIT]
     texts = [B.mst_status_string(c) for c in codes]
     assert len(set(texts)) == len(codes)
     assert B.mst_status_string(12345) == "unknown status"
@@ -207,3 +207,18 @@ def test_stats_consistent_rules():
     assert not gpu_cases.stats_consistent([(1000, 8000, 701)] + o[1:2] + [(50, 6500, 49)], o)
     assert not gpu_cases.stats_consistent(o + [(1, 0, 0)], o)
     assert not gpu_cases.stats_consistent([], o)
+
+
+def test_noalloc_scratch_limit_on_host(lib):
+    """mst_solve_noalloc rejects a graph whose workspace exceeds its fixed
+    device scratch before any HIP call (the pointers are never dereferenced)."""
+    from paper_2005_06913_amd import binding as B
+    dummy = ctypes.c_void_p(16)
+    assert lib.mst_solve_noalloc(1 << 20, 1 << 23, dummy, dummy, dummy, dummy, dummy, None) == \
+        B.MSTX_ERR_SCRATCH_LIMIT
+    assert lib.mst_solve_noalloc(-1, 0, None, None, None, None, None, None) == B.MSTX_ERR_INVALID_ARG
+    assert lib.mst_solve_noalloc(4, 1 << 32, dummy, dummy, dummy, dummy, dummy, None) == B.MSTX_ERR_TOO_LARGE
+    # the documented examples fit: workspace plus 2 KB of records within 256 MiB
+    for n, m in ((1 << 20, 1 << 22), (1 << 18, 5 << 20)):
+        assert B.mst_workspace_bytes(n, m) + 2048 <= 256 << 20
+    assert "256 MiB" in B.mst_status_string(B.MSTX_ERR_SCRATCH_LIMIT)
