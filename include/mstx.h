@@ -15,9 +15,10 @@
  * selects its lightest outgoing edge (64-bit atomic minimum on the packed key
  * (w << 32) | e; from round 1 on the low half is the edge's position in the
  * stably compacted edge stream, which orders edges exactly as e does),
- * components are united along the selected edges by
- * compare-and-swap hooking of the larger root under the smaller one, parent
- * pointers are compressed, components are renumbered densely, and edges that
+ * components are united along the selected edges (each component's parent
+ * becomes the component its lightest edge reaches; of two components that
+ * chose each other the smaller id stays the root), parent pointers are
+ * compressed, components are renumbered densely, and edges that
  * became internal are dropped (the paper's "covered" edges).  Rounds repeat
  * until no component has an outgoing edge.  When few components remain the
  * last round is a dense finish (contraction of the remaining graph to the

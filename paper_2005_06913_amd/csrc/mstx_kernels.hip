@@ -1,6 +1,6 @@
 // mstx_kernels.hip -- device kernels of the parallel Boruvka MST for CDNA4 (gfx950).
 //
-// One Boruvka round (Durbhakula, arXiv 2005.06913, Section 2.1; CAS union of
+// One Boruvka round (Durbhakula, arXiv 2005.06913, Section 2.1; union and find of
 // Section 2.2.2) is a short chain of kernels, each a global barrier for the
 // next:
 //
@@ -28,8 +28,9 @@
 //                       per bucket, more for a heavy one) takes the minima
 //                       in LDS and writes best[];
 //               GLOBAL  filtered 64-bit atomicMin on best[] (very large n_r).
-//   hook      every component with a minimum: CAS the larger root's parent
-//             to the smaller root; the winner marks the edge.
+//   hook      every component with a minimum: its parent becomes the
+//             component at the far end of its lightest edge (the smaller of
+//             a mutual pair stays a root); it marks that edge.
 //   compress  pointer jumping: every component finds its root; a wave ballot
 //             records which roots still have an outgoing edge.
 //   finalize  one workgroup: exclusive scan of the root counts (dense new
@@ -1003,7 +1004,7 @@ __global__ void __launch_bounds__(kDenseThreads) k_dense_finish(int round, int l
 
 // Root of x by plain loads (values may be stale, but every value ever stored
 // in parent[] is an ancestor, so the walk ends at a node that was a root;
-// the caller's CAS checks that it still is).  Path halving with plain
+// a caller that links it checks that it still is).  Path halving with plain
 // stores: only non-roots are written, always with an ancestor.
 __device__ __forceinline__ int32_t walk_root(int32_t* parent, int32_t x) {
   int32_t p = parent[x];
@@ -1019,17 +1020,21 @@ __device__ __forceinline__ int32_t walk_root(int32_t* parent, int32_t x) {
 
 // For each component c with a minimum key: the edge e and d = the other
 // end's component.  Round 0: the key holds e, and d = c ^ (src ^ dst of e),
-// which the round-0 scan stored in the record buffer.  Later rounds: the key holds the edge's position in the record
-// stream, whose record has this round's labels of both ends and e.  If c and
-// d chose each other only the smaller id acts, so every distinct selected
-// edge has one owner thread.  Then: repeat { x = root(c), y = root(d); CAS
-// parent[max] from max to min }.  Parents always point to smaller ids, so
-// the forest never gets a cycle.  When the CAS fails, the value it returns
-// (a fresh, strictly smaller ancestor) is where that side's walk resumes, so
-// stale loads cannot make the loop spin.
+// which the round-0 scan stored in the record buffer.  Later rounds: the key
+// holds the edge's position in the record stream, whose record has this
+// round's labels of both ends and e.
+// Hooking by successors: c's parent becomes d.  Following the lightest
+// edges from any component reaches exactly one pair of components that chose
+// each other (the keys are distinct and strictly decrease along the way), so
+// the only cycles are those mutual pairs; the smaller component of a pair
+// stays a root.  The parents then form a forest whose trees are the merged
+// components, with plain stores only (each thread writes its own entry).
+// Every component that got a parent owns its edge: a mutual pair's common
+// edge is marked once (by the larger), every other selected edge by the one
+// component that chose it.  k_compress finds the roots.
 __global__ void __launch_bounds__(kBlock) k_hook(int round, const uint4* __restrict__ rec,
                                                  const unsigned long long* __restrict__ best,
-                                                 int32_t* parent, DevState* __restrict__ st,
+                                                 int32_t* __restrict__ parent, DevState* __restrict__ st,
                                                  uint8_t* __restrict__ in_mst, uint32_t* __restrict__ part_sel,
                                                  unsigned long long* __restrict__ part_w) {
   __shared__ uint32_t red32[kBlock / 64];
@@ -1060,28 +1065,16 @@ __global__ void __launch_bounds__(kBlock) k_hook(int round, const uint4* __restr
       e = x.w;
       d = (u == c) ? v : u;
     }
-    if ((uint32_t)d >= (uint32_t)nr || (u != c && v != c)) {
+    if ((uint32_t)d >= (uint32_t)nr || d == c || (u != c && v != c)) {
       st->err_internal = 1;  // inconsistent labels: never expected, reported as a device error
       continue;
     }
-    if (d < c && best[d] == key) continue;  // mutual choice: d hooks it
-    int32_t x = c, y = d;
-    while (true) {
-      const int32_t rx = walk_root(parent, x);
-      const int32_t ry = walk_root(parent, y);
-      if (rx == ry) break;
-      const int32_t hi = rx > ry ? rx : ry;
-      const int32_t lo = rx > ry ? ry : rx;
-      const int32_t old = atomicCAS(parent + hi, hi, lo);
-      if (old == hi) {
-        in_mst[e] = 1;
-        ++sel;
-        wsum += (uint32_t)(key >> 32);  // the edge's weight
-        break;
-      }
-      if (hi == rx) x = old;
-      else y = old;
-    }
+    // d > c: c stays a root if d chose the same edge (a mutual pair)
+    if (d > c && best[d] == key) continue;
+    parent[c] = d;
+    in_mst[e] = 1;
+    ++sel;
+    wsum += (uint32_t)(key >> 32);  // the edge's weight
   }
   sel = block_sum<kBlock / 64>(sel, red32);
   wsum = block_sum<kBlock / 64>(wsum, red64);
