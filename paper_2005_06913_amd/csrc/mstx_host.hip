@@ -43,8 +43,8 @@ constexpr int kBlockThreads = 256;
 constexpr int kMaxGrid = 4096;  // capacity of the per-block partial arrays (hook)
 
 struct Layout {
-  size_t best, parent, root_of, labpool, rootmask, rootcnt, rootpre, rec, seg_cnt, part_sel, part_w, state,
-      pbest, btot, offers, offT, slab, bytes;
+  size_t best, parent, root_of, labpool, cmap, rootmask, rootcnt, rootpre, rec, seg_cnt, seg_live, part_sel,
+      part_w, state, pbest, btot, offers, offT, slab, bytes;
   int64_t slab_cap;  // u64 entries of the LDS-mode slab (0: none)
   int32_t nseg;
   bool bucket;  // offer buffers present
@@ -72,11 +72,13 @@ Layout plan(int32_t n, int64_t m) {
   L.parent = take(4 * N);
   L.root_of = take(4 * N);
   L.labpool = take(4 * (2 * N + 64));  // label maps: n_0 + n_1 + ... < 2n
+  L.cmap = take(4 * 2 * (size_t)kNarrowMax);  // composed maps of rounds that keep their records
   L.rootmask = take(8 * words);
   L.rootcnt = take(4 * words);
   L.rootpre = take(4 * words);
   L.rec = take(16 * (size_t)nseg * kSegCap);
   L.seg_cnt = take(4 * (size_t)nseg);
+  L.seg_live = take(4 * (size_t)nseg);
   L.part_sel = take(4 * (size_t)kMaxGrid);
   L.part_w = take(8 * (size_t)kMaxGrid);
   L.state = take(sizeof(DevState));
@@ -230,20 +232,21 @@ int rounds_bound(int32_t n) {
 // with the round's algorithmic bytes (what the method must move, from the
 // round statistics).
 enum Kind {
-  kScan0Global = 0, kScan0Lds, kScan0Bucket, kScan0Dense,
-  kScan1Global, kScan1Lds, kScan1Bucket, kScan1Dense,
-  kScanRGlobal, kScanRLds, kScanRBucket, kScanRDense,
-  kBucketMin, kSlabMin_, kDenseFinish, kHook, kCompress, kFinalize, kRelabel, kSmallSolve, kRoundTail, kKinds
+  kScanFirst = 0,  // 4 stages x 4 minima modes: kind = kNumModes * stage + mode
+  kBucketMin = 16, kSlabMin_, kDenseFinish, kHook, kCompress, kFinalize, kRelabel, kSmallSolve, kRoundTail, kKinds
 };
+constexpr int kScanKinds = 16;
 // Names as rocprofv3 reports the kernels (template arguments: minima mode
-// 0 global / 1 LDS / 2 bucket / 3 dense, reads the caller's arrays, compacts).
+// 0 global / 1 LDS / 2 bucket / 3 dense; the stream read: 0 the caller's
+// edges, 1 the caller's edges through round 0's labels, 2 wide records,
+// 3 narrow records).
 const char* const kKindNames[kKinds] = {
-    "k_scan<0, true, false>",  "k_scan<1, true, false>",  "k_scan<2, true, false>",  "k_scan<3, true, false>",
-    "k_scan<0, true, true>",   "k_scan<1, true, true>",   "k_scan<2, true, true>",   "k_scan<3, true, true>",
-    "k_scan<0, false, true>",  "k_scan<1, false, true>",  "k_scan<2, false, true>",  "k_scan<3, false, true>",
-    "k_bucket_min",            "k_slab_min",              "k_dense_finish",          "k_hook",
-    "k_compress",              "k_finalize",              "k_relabel",               "k_small_solve",
-    "k_round_tail"};
+    "k_scan<0, 0>", "k_scan<1, 0>", "k_scan<2, 0>", "k_scan<3, 0>",
+    "k_scan<0, 1>", "k_scan<1, 1>", "k_scan<2, 1>", "k_scan<3, 1>",
+    "k_scan<0, 2>", "k_scan<1, 2>", "k_scan<2, 2>", "k_scan<3, 2>",
+    "k_scan<0, 3>", "k_scan<1, 3>", "k_scan<2, 3>", "k_scan<3, 3>",
+    "k_bucket_min", "k_slab_min", "k_dense_finish", "k_hook", "k_compress", "k_finalize", "k_relabel",
+    "k_small_solve", "k_round_tail"};
 
 int scan_kind(int stage, int mode) { return kNumModes * stage + mode; }
 
@@ -305,7 +308,7 @@ struct LaunchTimer {
       if (hipEventElapsedTime(&ms, p.a, p.b) != hipSuccess) continue;
       g_prof.ms[p.kind] += ms;
       g_prof.launches[p.kind] += 1;
-      if (p.kind <= kScanRDense && p.round < nrounds && p.mode == chosen[p.round])
+      if (p.kind < kScanKinds && p.round < nrounds && p.mode == chosen[p.round])
         g_prof.bytes[p.kind] += bytes[p.round];
     }
     pending.clear();
@@ -344,6 +347,7 @@ struct Solve {
   int32_t* rootpre;
   uint4* rec;
   uint32_t* seg_cnt;
+  uint32_t* seg_live;
   uint32_t* part_sel;
   unsigned long long* part_w;
   DevState* st;
@@ -356,44 +360,38 @@ struct Solve {
   int tail_limit;             // 0: every round takes the multi-workgroup hook .. relabel
   int64_t bucket_limit;       // largest bound that may take bucket mode (0: never)
   int launched[kMaxRounds + 1];  // per round
+  int stage[kMaxRounds + 1];     // the stream each enqueued round reads (scan_stage)
+  int64_t dom[kMaxRounds + 1];   // entries of its label map
+  int keep[kMaxRounds + 2];      // round r keeps its records in place (from round r - 1's record)
 };
 
-// Enqueues the scan of `stage` (0: round 0, 1: round 1, 2: rounds >= 2) for a
-// round whose component count is at most `bound`.  Returns the launched mask.
-int enqueue_scan(Solve& S, int r, int stage, int64_t bound, bool exact, hipError_t& err, int64_t n_prev = 0) {
+// Enqueues the scan of round r reading stream `stage` (scan_stage) whose
+// component count is at most `bound`; `dom` bounds the entries of the round's
+// label map.  Returns the launched mask.
+int enqueue_scan(Solve& S, int r, int stage, int64_t bound, bool exact, hipError_t& err, int64_t dom = 0) {
   LaunchTimer& T = t_timer;
   const bool buckets = S.L.bucket && S.bucket_limit > 0;
-  const int hi_mode = mode_for(bound, S.dense_limit, buckets ? S.bucket_limit : 0);
-  int launched = 1 << hi_mode;
-  if (!exact) {
-    // the actual count may be much smaller than the bound
-    if (hi_mode != kModeDense && S.dense_limit > 0 && bound / 8 <= S.dense_limit) launched |= 1 << kModeDense;
-    // (a skewed graph can lose far more than half its components in a round,
-    // and a launch that finds another mode chosen returns at once.  Round 1
-    // is covered for an 8-fold drop only: on random and grid graphs the first
-    // round leaves about a quarter of the vertices and the extra launch would
-    // return every time; a graph that falls further still takes bucket mode,
-    // correct, for that one round)
-    const int64_t drop = stage == 1 ? 8 : 64;
-    if (hi_mode != kModeLds && hi_mode != kModeDense && bound / drop <= kLdsSlots) launched |= 1 << kModeLds;
-    if (hi_mode == kModeGlobal && buckets && bound / 8 <= S.bucket_limit) launched |= 1 << kModeBucket;
-  }
-  if (!buckets) launched &= ~(1 << kModeBucket), launched |= (bound > kLdsSlots ? 1 << kModeGlobal : 0);
+  // the actual count may be much smaller than the bound: a skewed graph can
+  // lose far more than half its components in a round.  Round 1 is covered
+  // for an 8-fold drop only: on random and grid graphs the first round leaves
+  // about a quarter of the vertices and the extra launch would return every
+  // time; a graph that falls further still takes bucket mode, correct, for
+  // that one round
+  int launched = scan_modes(bound, exact, stage, S.dense_limit, buckets, S.bucket_limit);
   launched |= S.dense_limit << 8;
-  ScanArgs A{r,      launched, S.src,     S.dst,    S.w,    (uint32_t)S.m, S.n,     S.labpool, S.rec,
-             S.seg_cnt, S.L.nseg, S.best, S.st, S.offers, S.offT, S.slab, S.L.slab_cap, S.pbest, -1,
-             S.btot};
+  ScanArgs A{r,         launched,   S.src,    S.dst,  S.w,      (uint32_t)S.m, S.n,      S.labpool,
+             S.rec,     S.seg_cnt,  S.seg_live, S.L.nseg, S.best, S.st,     S.offers,      S.offT,   S.slab,
+             S.L.slab_cap, S.pbest, -1,         S.btot};
   const int cus = S.cus;
   for (int mode : {kModeDense, kModeLds, kModeBucket, kModeGlobal}) {
     if (!(launched & (1 << mode))) continue;
     int grid;
     size_t lds;
     if (mode == kModeDense) {
-      lds = (size_t)dense_pairs((int32_t)std::min<int64_t>(std::max<int64_t>(bound, 2), S.dense_limit)) * 8;
+      lds = (size_t)scan_table_lds(mode, bound, S.dense_limit);
       grid = std::min(S.L.nseg, cus);
     } else if (mode == kModeLds) {
-      const int64_t slots = std::max<int64_t>(1, std::min<int64_t>(bound, kLdsSlots));
-      lds = (size_t)slots * 8;
+      lds = (size_t)scan_table_lds(mode, bound, S.dense_limit);
       const int per_cu = (int)std::max<int64_t>(1, std::min<int64_t>(4, 65536 / ((int64_t)lds + 1024)));
       grid = std::min(S.L.nseg, cus * per_cu);
     } else if (mode == kModeBucket) {
@@ -403,17 +401,15 @@ int enqueue_scan(Solve& S, int r, int stage, int64_t bound, bool exact, hipError
       lds = 0;
       grid = std::min(S.L.nseg, 2 * cus);
     }
-    // the previous round's label map (n_prev entries, exact) goes to LDS
-    // beside the minima table when both fit: the lookups become LDS reads.
-    // Staged entries take 2 bytes (LDS mode) or 1 byte (DENSE mode).
+    // the round's label map (at most dom entries) goes to LDS beside the
+    // minima table when both fit: the lookups become LDS reads.  Staged
+    // entries take 2 bytes (LDS mode) or 1 byte (DENSE mode).
     A.lab_lds_off = -1;
-    if (stage == 2 && (mode == kModeLds || mode == kModeDense) && n_prev > 0) {
+    if (stage >= 2 && (mode == kModeLds || mode == kModeDense) && dom > 0 &&
+        map_fits_lds(mode, bound, S.dense_limit, dom)) {
       const size_t off = (lds + 15) & ~size_t(15);
-      const size_t bytes = (mode == kModeDense ? 1 : 2) * (size_t)n_prev;
-      if (off + bytes <= (size_t)kMaxDynLds) {
-        A.lab_lds_off = (int32_t)off;
-        lds = off + bytes;
-      }
+      A.lab_lds_off = (int32_t)off;
+      lds = off + (mode == kModeDense ? 1 : 2) * (size_t)dom;
     }
     const int k = T.start(scan_kind(stage, mode), r, mode);
     err = launch_scan(mode, stage, A, grid, lds, S.s);
@@ -430,7 +426,7 @@ int enqueue_scan(Solve& S, int r, int stage, int64_t bound, bool exact, hipError
     }
     if (mode == kModeDense && S.in_mst) {
       const int kd = T.start(kDenseFinish, r, mode);
-      err = launch_dense_finish(r, launched, S.pbest, S.seg_cnt, S.L.nseg, S.rec, S.in_mst, S.total, S.st,
+      err = launch_dense_finish(r, launched, S.pbest, S.seg_live, S.L.nseg, S.rec, S.in_mst, S.total, S.st,
                                 S.rounds, S.s);
       T.stop(kd);
       if (err != hipSuccess) return launched;
@@ -454,24 +450,30 @@ int enqueue_scan(Solve& S, int r, int stage, int64_t bound, bool exact, hipError
 
 // Enqueues round r (component count at most `bound`; `exact`: the count is
 // known to be `bound`, so only its own minima mode is launched).
+// n_prev is the exact count entering round r - 1, which fixes the stream
+// round r reads; its label map has n_prev entries, or, if round r - 1 kept
+// its records in place (S.keep[r - 1], known from round r - 2's record), as
+// many as round r - 1's.
 hipError_t enqueue_round(Solve& S, int r, int64_t bound, int64_t n_prev, bool exact) {
   LaunchTimer& T = t_timer;
   hipError_t err = hipSuccess;
-  const int stage = r == 0 ? 0 : (r == 1 ? 1 : 2);
-  S.launched[r] = enqueue_scan(S, r, stage, bound, exact, err, n_prev);
+  const int stage = scan_stage(r, n_prev);
+  S.stage[r] = stage;
+  S.dom[r] = r == 0 ? 0 : (S.keep[r - 1] ? S.dom[r - 1] : n_prev);
+  S.launched[r] = enqueue_scan(S, r, stage, bound, exact, err, S.dom[r]);
   if (err != hipSuccess) return err;
   const int gh = grid_for(std::max<int64_t>(bound, 1));
   if (bound <= S.tail_limit) {
     // few components: the rest of the round in one workgroup
     const int k = T.start(kRoundTail, r, -1);
-    err = launch_round_tail(r, (int32_t)bound, S.rec, S.best, S.parent, S.labpool, S.seg_cnt, S.L.nseg, S.in_mst,
-                            S.total, S.btot, S.st, S.rounds, S.s);
+    err = launch_round_tail(r, (int32_t)bound, S.rec, S.best, S.parent, S.labpool, S.seg_cnt, S.seg_live,
+                            S.L.nseg, S.in_mst, S.total, S.btot, S.st, S.rounds, S.s);
     T.stop(k);
     if (err != hipSuccess) return err;
     return S.events ? hipEventRecord(S.events[r], S.s) : hipSuccess;
   }
   int k = T.start(kHook, r, -1);
-  err = launch_hook(r, S.rec, S.best, S.parent, S.st, S.in_mst, S.part_sel, S.part_w, gh, S.s);
+  err = launch_hook(r, S.rec, S.labpool, S.best, S.parent, S.st, S.in_mst, S.part_sel, S.part_w, gh, S.s);
   T.stop(k);
   if (err != hipSuccess) return err;
   k = T.start(kCompress, r, -1);
@@ -479,8 +481,8 @@ hipError_t enqueue_round(Solve& S, int r, int64_t bound, int64_t n_prev, bool ex
   T.stop(k);
   if (err != hipSuccess) return err;
   k = T.start(kFinalize, r, -1);
-  err = launch_finalize(r, S.rootcnt, S.rootpre, S.seg_cnt, S.L.nseg, S.part_sel, S.part_w, gh, S.st, S.total,
-                        S.rounds, S.s);
+  err = launch_finalize(r, S.rootcnt, S.rootpre, S.seg_cnt, S.seg_live, S.L.nseg, S.part_sel, S.part_w, gh,
+                        S.st, S.total, S.rounds, S.s);
   T.stop(k);
   if (err != hipSuccess) return err;
   k = T.start(kRelabel, r, -1);
@@ -503,6 +505,10 @@ HostRound load_record(const HostRound* p) {
   h.live = v->live;
   h.sel = v->sel;
   h.edges_added = v->edges_added;
+  h.stream = v->stream;
+  h.map_n = v->map_n;
+  h.keep = v->keep;
+  h.keep_next = v->keep_next;
   std::atomic_thread_fence(std::memory_order_acquire);
   return h;
 }
@@ -537,6 +543,7 @@ Solve make_solve(void* B, int cus, HostRound* rounds, hipEvent_t* events, const 
   S.rootpre = at<int32_t>(B, L.rootpre);
   S.rec = at<uint4>(B, L.rec);
   S.seg_cnt = at<uint32_t>(B, L.seg_cnt);
+  S.seg_live = at<uint32_t>(B, L.seg_live);
   S.part_sel = at<uint32_t>(B, L.part_sel);
   S.part_w = at<unsigned long long>(B, L.part_w);
   S.st = at<DevState>(B, L.state);
@@ -549,20 +556,27 @@ Solve make_solve(void* B, int cus, HostRound* rounds, hipEvent_t* events, const 
   S.tail_limit = g_tail_limit.load();
   S.bucket_limit = g_bucket_limit.load();
   for (int& x : S.launched) x = 0;
+  for (int& x : S.keep) x = 0;
   return S;
 }
 
-// Algorithmic bytes of round r's scan: the edge stream read once, the
-// previous label map read once, the minima initialised and written once, the
-// compacted survivors written once (a dense round instead writes its pair
-// table once and compacts nothing).
-double round_scan_bytes(const HostRound* rec, const int32_t* nr_of, int r, int32_t n, int64_t m) {
+// Algorithmic bytes of round r's scan: the edge stream read once (12 B per
+// input edge, 16 B per wide record, 8 B per narrow record, plus its 4-byte
+// edge index when the round rewrites it), the round's label map read once
+// (4 B per entry), the minima initialised and written once (16 B per
+// component), the survivors written once (16 B wide, 12 B narrow with the
+// edge index; none when the round keeps its records); a dense round instead
+// writes its pair table once (8 B per pair) and moves no record.
+double round_scan_bytes(const HostRound* rec, const int32_t* nr_of, int r, int64_t m) {
   const HostRound& M = rec[r];
   const double nrd = (double)nr_of[r];
-  const double out = M.dense ? 8.0 * (double)dense_pairs(nr_of[r]) : 16.0 * nrd + 16.0 * (double)M.live;
-  if (r == 0) return 12.0 * (double)m + (M.dense ? out : 16.0 * nrd);
-  if (r == 1) return 12.0 * (double)m + 4.0 * (double)n + out;
-  return 16.0 * (double)rec[r - 1].live + 4.0 * (double)nr_of[r - 1] + out;
+  const bool narrow_in = r >= 2 && nr_of[r - 1] <= kNarrowMax;
+  const bool moves = r >= 1 && !M.dense && !M.keep;
+  double b = r <= 1 ? 12.0 * (double)m : (narrow_in ? (moves ? 12.0 : 8.0) : 16.0) * (double)M.stream;
+  b += 4.0 * (double)M.map_n;
+  b += M.dense ? 8.0 * (double)dense_pairs(nr_of[r]) : 16.0 * nrd;
+  if (moves) b += (nr_of[r] <= kNarrowMax ? 12.0 : 16.0) * (double)M.live;
+  return b;
 }
 
 // What the host learns from the round records of one solve.
@@ -606,7 +620,7 @@ struct RoundLoop {
       T.v[3 * r + 1] = rec[r].live;
       T.v[3 * r + 2] = rec[r].sel;
       chosen[r] = pick_mode(nr_of[r], S.launched[r]);
-      bytes[r] = round_scan_bytes(rec, nr_of, r, n, m);
+      bytes[r] = round_scan_bytes(rec, nr_of, r, m);
     }
     t_timer.commit(rounds, chosen, bytes);
   }
@@ -617,8 +631,8 @@ hipError_t start_solve(const Solve& S) {
   hipError_t e = hipMemsetAsync(S.in_mst, 0, (size_t)S.m, S.s);
   if (e == hipSuccess) e = hipMemsetAsync(S.total, 0, sizeof(uint64_t), S.s);
   if (e == hipSuccess)
-    e = launch_init(S.n, S.best, S.parent, S.dense_limit > 0 ? S.pbest : nullptr, S.btot, S.st, grid_for(S.n),
-                    S.s);
+    e = launch_init(S.n, S.m, (int64_t)((S.L.cmap - S.L.labpool) / 4), S.dense_limit, S.best, S.parent,
+                    S.dense_limit > 0 ? S.pbest : nullptr, S.btot, S.st, grid_for(S.n), S.s);
   return e;
 }
 
@@ -656,6 +670,7 @@ int solve_locked(DeviceCache* dc, const Layout& L, int32_t n, int64_t m, const i
       if (M.n_next == kRecordPending) break;  // status stays MSTX_ERR_DEVICE
     }
     R.take(r, M);
+    S.keep[r + 1] = M.keep_next;
     if (R.done) break;
     n_known = M.n_next;
   }
@@ -828,6 +843,7 @@ int solve_noalloc(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, 
         break;
       }
       R.take(r, h[r]);
+      S.keep[r + 1] = h[r].keep_next;
     }
     if (R.done) break;
     const int r = r_enq + 1;  // its component count is known exactly now
@@ -1162,6 +1178,7 @@ int select_min_edges(int32_t n, int64_t m, const int32_t* src, const int32_t* ds
   S.L = L;
   S.best = reinterpret_cast<unsigned long long*>(out_best);
   S.seg_cnt = at<uint32_t>(B, L.seg_cnt);
+  S.seg_live = at<uint32_t>(B, L.seg_live);
   S.rec = at<uint4>(B, L.rec);
   S.labpool = at<int32_t>(B, L.labpool);
   S.st = at<DevState>(B, L.state);
@@ -1175,7 +1192,8 @@ int select_min_edges(int32_t n, int64_t m, const int32_t* src, const int32_t* ds
   S.in_mst = nullptr;
   t_timer.begin(s);
   t_timer.on = false;
-  HIP_OK(launch_init(n, S.best, at<int32_t>(B, L.parent), nullptr, S.btot, S.st, grid_for(n), s));
+  HIP_OK(launch_init(n, m, (int64_t)((L.cmap - L.labpool) / 4), 0, S.best, at<int32_t>(B, L.parent), nullptr,
+                     S.btot, S.st, grid_for(n), s));
   if (m > 0) {
     hipError_t err = hipSuccess;
     enqueue_scan(S, 0, 0, n, true, err);

@@ -114,14 +114,92 @@ __host__ __device__ inline int pick_mode(int32_t nr, int launched) {
   return kModeGlobal;
 }
 
-// Device-resident round state.  Round r's kernels read n[r] and lab_off[r];
-// the finalize kernel of round r writes n[r+1], lab_off[r+1], live[r], sel[r].
+// Record formats of the edge stream (rounds >= 1).  A wide record is
+// {a, b, w, e} in 16 bytes.  Once a round's labels fit 16 bits (n_r <=
+// kNarrowMax) its survivors are written as narrow records, a | b << 16 | w <<
+// 32 in 8 bytes, with e stored apart: segment s (kSegCap records) keeps its
+// narrow records in the first 32 KB of its 64 KB wide area and their edge
+// indices in the next 16 KB, so an in-place rewrite never leaves the segment.
+static constexpr int32_t kNarrowMax = 65536;
+__host__ __device__ constexpr uint64_t narrow_rec_index(uint32_t pos) {
+  return (uint64_t)pos + (uint64_t)(pos & ~(uint32_t)(kSegCap - 1));  // u64 index
+}
+__host__ __device__ constexpr uint64_t narrow_e_index(uint32_t pos) {
+  return 4 * (uint64_t)(pos & ~(uint32_t)(kSegCap - 1)) + 2 * kSegCap + (pos & (kSegCap - 1));  // u32 index
+}
+// Records a round reads: 0 the caller's arrays (round 0), 1 the caller's
+// arrays through round 0's labels (round 1), 2 wide records, 3 narrow records.
+// Round q >= 2 reads narrow records iff n_{q-1} <= kNarrowMax.
+__host__ __device__ constexpr int scan_stage(int q, int64_t n_prev) {
+  return q == 0 ? 0 : (q == 1 ? 1 : (n_prev <= kNarrowMax ? 3 : 2));
+}
+// A round that reads narrow records may keep them where they are (no
+// rewrite) when fewer than 1/kKeepDeadDen of the records the previous round
+// read were dead there, and the composed label map the round after it then
+// reads (two buffers of kNarrowMax entries, used alternately) can still be
+// staged in that round's LDS; later rounds read the labels of the round that
+// last wrote the records through that map.
+static constexpr int kKeepDeadDen = 4;
+
+// Minima modes launched for a round whose component count is at most
+// `bound` (exact: it is the count), reading stream `stage`; bit i = mode i.
+// Besides the mode of the bound itself, the LDS mode is launched whenever a
+// 64-fold drop (8-fold in round 1) would bring the count into its range, and
+// the dense mode whenever an 8-fold drop would: a launch that finds another
+// mode chosen returns at once.
+__host__ __device__ inline int scan_modes(int64_t bound, bool exact, int stage, int dense_limit, bool buckets,
+                                          int64_t bucket_limit) {
+  const int64_t blim = buckets ? bucket_limit : 0;
+  const int hi = bound <= dense_limit ? kModeDense
+                 : bound <= kLdsSlots ? kModeLds
+                 : bound <= blim      ? kModeBucket
+                                      : kModeGlobal;
+  int mask = 1 << hi;
+  if (!exact) {
+    if (hi != kModeDense && dense_limit > 0 && bound / 8 <= dense_limit) mask |= 1 << kModeDense;
+    const int64_t drop = stage == 1 ? 8 : 64;
+    if (hi != kModeLds && hi != kModeDense && bound / drop <= kLdsSlots) mask |= 1 << kModeLds;
+    if (hi == kModeGlobal && buckets && bound / 8 <= bucket_limit) mask |= 1 << kModeBucket;
+  }
+  if (!buckets) {
+    mask &= ~(1 << kModeBucket);
+    if (bound > kLdsSlots) mask |= 1 << kModeGlobal;
+  }
+  return mask;
+}
+// Dynamic LDS of the minima table of an LDS or dense launch for `bound`.
+__host__ __device__ inline int64_t scan_table_lds(int mode, int64_t bound, int dense_limit) {
+  if (mode == kModeDense) {
+    const int64_t k = bound < 2 ? 2 : (bound < dense_limit ? bound : dense_limit);
+    return (int64_t)dense_pairs((int32_t)k) * 8;
+  }
+  const int64_t slots = bound < 1 ? 1 : (bound < kLdsSlots ? bound : kLdsSlots);
+  return slots * 8;
+}
+// Whether an LDS or dense launch for `bound` can stage a label map of `dom`
+// entries behind its table (2 bytes each, 1 in dense mode).
+__host__ __device__ inline bool map_fits_lds(int mode, int64_t bound, int dense_limit, int64_t dom) {
+  const int64_t off = (scan_table_lds(mode, bound, dense_limit) + 15) & ~(int64_t)15;
+  return off + (mode == kModeDense ? 1 : 2) * dom <= (int64_t)kMaxDynLds;
+}
+
+// Device-resident round state.  Round r's kernels read n[r], lab_off[r],
+// keep[r], map_off[r] and map_n[r]; the finalize kernel of round r writes
+// n[r+1], lab_off[r+1], live[r], sel[r], stream[r+1], keep[r+1], map_off[r+1]
+// and map_n[r+1].
 struct DevState {
   int32_t n[kMaxRounds + 2];        // components entering round r (isolated ones dropped)
   int64_t lab_off[kMaxRounds + 2];  // offset of round r's label map in the label pool
   int64_t live[kMaxRounds + 1];     // edges between different components at round r
   int64_t sel[kMaxRounds + 1];      // edges added in round r
+  int64_t stream[kMaxRounds + 2];   // records (or input edges) round r reads
+  int64_t map_off[kMaxRounds + 2];  // label-pool offset of the map from record labels to round r's
+  int32_t map_n[kMaxRounds + 2];    // ... and its entries
+  int32_t keep[kMaxRounds + 2];     // round r does not rewrite the records it reads
   int64_t edges_added;              // running total of sel[]
+  int64_t m;                        // input edges
+  int64_t cmap_off;                 // label-pool offset of the two composed-map buffers
+  int32_t dense_limit;              // the dense finish's component limit of this solve (0: off)
   int32_t err;                      // an edge end outside [0, n) was seen
   int32_t err_internal;             // a label lookup gave an impossible value
   int32_t dense_at;                 // round that ended with the dense finish (-1: none)
@@ -137,6 +215,11 @@ struct HostRound {
   int64_t live;
   int64_t sel;
   int64_t edges_added;
+  int64_t stream;  // records (or input edges) the round read
+  int32_t map_n;      // entries of the label map the round read
+  int32_t keep;       // 1: the round kept its records in place
+  int32_t keep_next;  // 1: the next round keeps its records in place
+  int32_t pad;
 };
 
 // Arguments of the scan kernel (passed by value).
@@ -150,7 +233,8 @@ struct ScanArgs {
   int32_t n;
   const int32_t* labpool;
   uint4* rec;
-  uint32_t* seg_cnt;
+  uint32_t* seg_cnt;   // records per segment (written when the round rewrites them)
+  uint32_t* seg_live;  // live records per segment this round
   int32_t nseg;
   unsigned long long* best;
   DevState* st;
@@ -274,8 +358,9 @@ hipError_t launch_graph_epilogue(const int32_t* glist, int ng, const int64_t* vo
                                  const uint32_t* gw, const int32_t* gbad, uint8_t* in_mst,
                                  unsigned long long* acc_w, uint32_t* acc_c, unsigned long long* total,
                                  int32_t* status, hipStream_t s);
-hipError_t launch_init(int32_t n, unsigned long long* best, int32_t* parent, unsigned long long* pbest,
-                       uint32_t* btot, DevState* st, int grid, hipStream_t s);
+hipError_t launch_init(int32_t n, int64_t m, int64_t cmap_off, int dense_limit, unsigned long long* best,
+                       int32_t* parent, unsigned long long* pbest, uint32_t* btot, DevState* st, int grid,
+                       hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, int64_t count, unsigned long long v, int grid,
                            hipStream_t s);
 hipError_t launch_scan(int mode, int stage, const ScanArgs& a, int grid, size_t lds, hipStream_t s);
@@ -285,22 +370,23 @@ hipError_t launch_bucket_min(int round, int launched, const unsigned long long* 
 hipError_t launch_slab_min(int round, int launched, int mode, const unsigned long long* slab, int64_t slab_cap,
                            int nwg, unsigned long long* best, unsigned long long* pbest, const DevState* st,
                            int grid, hipStream_t s);
-hipError_t launch_dense_finish(int round, int launched, const unsigned long long* pbest, const uint32_t* seg_cnt,
+hipError_t launch_dense_finish(int round, int launched, const unsigned long long* pbest, const uint32_t* seg_live,
                                int32_t nseg, const uint4* rec, uint8_t* in_mst, unsigned long long* total,
                                DevState* st, HostRound* host, hipStream_t s);
-hipError_t launch_hook(int round, const uint4* rec, const unsigned long long* best, int32_t* parent, DevState* st,
-                       uint8_t* in_mst, uint32_t* part_sel, unsigned long long* part_w, int grid, hipStream_t s);
+hipError_t launch_hook(int round, const uint4* rec, const int32_t* labpool, const unsigned long long* best,
+                       int32_t* parent, DevState* st, uint8_t* in_mst, uint32_t* part_sel,
+                       unsigned long long* part_w, int grid, hipStream_t s);
 hipError_t launch_compress(int round, int32_t* parent, int32_t* root_of, const unsigned long long* best,
                            unsigned long long* rootmask, int32_t* rootcnt, const DevState* st, int grid,
                            hipStream_t s);
 hipError_t launch_round_tail(int round, int32_t cap, const uint4* rec, unsigned long long* best, int32_t* parent,
-                             int32_t* labpool, const uint32_t* seg_cnt, int32_t nseg, uint8_t* in_mst,
-                             unsigned long long* total, uint32_t* btot, DevState* st, HostRound* host,
-                             hipStream_t s);
-hipError_t launch_finalize(int round, const int32_t* rootcnt, int32_t* rootpre, const uint32_t* part_live,
-                           int32_t nlive, const uint32_t* part_sel, const unsigned long long* part_w,
-                           int32_t nhook, DevState* st, unsigned long long* total, HostRound* host,
-                           hipStream_t s);
+                             int32_t* labpool, const uint32_t* seg_cnt, const uint32_t* seg_live, int32_t nseg,
+                             uint8_t* in_mst, unsigned long long* total, uint32_t* btot, DevState* st,
+                             HostRound* host, hipStream_t s);
+hipError_t launch_finalize(int round, const int32_t* rootcnt, int32_t* rootpre, const uint32_t* seg_cnt,
+                           const uint32_t* seg_live, int32_t nseg, const uint32_t* part_sel,
+                           const unsigned long long* part_w, int32_t nhook, DevState* st,
+                           unsigned long long* total, HostRound* host, hipStream_t s);
 hipError_t launch_relabel(int round, const int32_t* root_of, const unsigned long long* rootmask,
                           const int32_t* rootpre, int32_t* labpool, int32_t* parent, unsigned long long* best,
                           uint32_t* btot, const DevState* st, int grid, hipStream_t s);

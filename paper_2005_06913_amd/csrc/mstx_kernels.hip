@@ -139,10 +139,30 @@ __device__ __forceinline__ T block_sum(T v, T* scratch /* [NW] */) {
 }
 
 
+// Copies the n label-map entries at src (labels >= -1) into LDS as label + 1,
+// eight loads in flight per thread.
+template <typename LabT, int kThreads>
+__device__ __forceinline__ void stage_map(LabT* dst, const int32_t* __restrict__ src, int32_t n) {
+  for (int32_t i0 = 0; i0 < n; i0 += 8 * kThreads) {
+    int32_t v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int32_t i = i0 + q * kThreads + (int32_t)threadIdx.x;
+      v[q] = src[i < n ? i : 0];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int32_t i = i0 + q * kThreads + (int32_t)threadIdx.x;
+      if (i < n) dst[i] = (LabT)(v[q] + 1);
+    }
+  }
+}
+
 // --------------------------------------------------------------------- init
 
 // best[0..n) <- none, parent[c] <- c, state for round 0.
-__global__ void __launch_bounds__(kBlock) k_init(int32_t n, unsigned long long* best, int32_t* parent,
+__global__ void __launch_bounds__(kBlock) k_init(int32_t n, int64_t m, int64_t cmap_off, int dense_limit,
+                                                 unsigned long long* best, int32_t* parent,
                                                  unsigned long long* pbest, uint32_t* btot, DevState* st) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += stride) {
@@ -157,6 +177,13 @@ __global__ void __launch_bounds__(kBlock) k_init(int32_t n, unsigned long long* 
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     st->n[0] = n;
     st->lab_off[0] = 0;
+    st->m = m;
+    st->stream[0] = m;
+    st->map_off[0] = 0;
+    st->map_n[0] = 0;
+    st->keep[0] = 0;
+    st->cmap_off = cmap_off;
+    st->dense_limit = dense_limit;
     st->err = 0;
     st->err_internal = 0;
     st->edges_added = 0;
@@ -171,19 +198,27 @@ __global__ void __launch_bounds__(kBlock) k_fill_u64(unsigned long long* p, int6
 
 // --------------------------------------------------------------------- scan
 
-// One kernel for every round and mode.
-//   kFromInput && !kCompact : round 0, the caller's edges, labels = vertex ids,
-//                             ids checked against [0, n) (st->err on failure)
-//   kFromInput &&  kCompact : round 1, the caller's edges, labels lab_0[id]
-//   !kFromInput             : rounds >= 2, the record stream, labels lab_{r-1}
-// kMode is the way minima are taken (LDS / BUCKET / GLOBAL); a launch whose
-// mode is not the one pick_mode() selects for the actual n_r returns.
+// One kernel for every round and mode.  kStage is the edge stream the round
+// reads (scan_stage):
+//   0  round 0: the caller's edges, labels = vertex ids, ids checked against
+//      [0, n) (st->err on failure); nothing is compacted
+//   1  round 1: the caller's edges, labels through round 0's map
+//   2  wide records {a, b, w, e} of an earlier round, labels through the map
+//      of this round (map_off / map_n)
+//   3  narrow records (a | b << 16 | w << 32, e apart), the same way
+// From round 1 on the survivors are rewritten in place (narrow when this
+// round's labels fit 16 bits), unless the round keeps its narrow records
+// where they are (st->keep) or is a dense round (its round is the last).
+// kMode is the way minima are taken (LDS / BUCKET / GLOBAL / DENSE); a launch
+// whose mode is not the one pick_mode() selects for the actual n_r returns.
 // Dynamic LDS: LDS mode n_r (<= launch capacity) u64 minima; DENSE mode
 // n_r (n_r - 1) / 2 u64 pair minima; BUCKET mode the 2 * kSegCap offer staging
-// and the (bucket count + 1) counters.  DENSE mode compacts nothing: its
-// round is the last.
-template <int kMode, bool kFromInput, bool kCompact>
+// and the (bucket count + 1) counters.
+template <int kMode, int kStage>
 __global__ void __launch_bounds__(kScanBlock) k_scan(ScanArgs A) {
+  constexpr bool kFromInput = kStage <= 1;
+  constexpr bool kCompact = kStage >= 1;  // labels come through a map; survivors may be rewritten
+  constexpr bool kNarrowIn = kStage == 3;
   extern __shared__ unsigned long long smem[];
   __shared__ uint32_t slot_tot[kPerThread * kScanWaves];  // survivors per (slot k, wave)
   __shared__ uint32_t red[kScanWaves];
@@ -193,21 +228,25 @@ __global__ void __launch_bounds__(kScanBlock) k_scan(ScanArgs A) {
   // a round enqueued before the host saw an input error in round 0 does nothing
   if (A.round > 0 && A.st->err) return;
   if (pick_mode(nr, A.launched) != kMode) return;
-  const int32_t* __restrict__ lab = kCompact ? A.labpool + A.st->lab_off[A.round - 1] : nullptr;
+  const int32_t* lab = kCompact ? A.labpool + A.st->map_off[A.round] : nullptr;
+  // this round's survivors: rewritten (moved to their compacted positions),
+  // narrow or wide, or left where they are
+  const bool keep = kNarrowIn && A.st->keep[A.round] != 0;
+  const bool moved = kCompact && kMode != kModeDense && !keep;
+  const bool narrow_out = nr <= kNarrowMax;
   // keys carry stream positions from round 1 on (see below)
   constexpr bool kPosKey = kCompact && !(kFromInput && kMode == kModeDense);
-  // rounds >= 2 in LDS / DENSE mode: the previous round's label map may be
-  // staged in LDS behind the minima table (the host sized the allocation).
-  // Its values are labels of this round, below n_r, or -1 (isolated): they
-  // are stored plus one in 2 bytes (LDS mode, n_r <= kLdsSlots) or 1 byte
-  // (DENSE mode, n_r <= kDenseMax).
+  // rounds >= 2 in LDS / DENSE mode: this round's label map may be staged in
+  // LDS behind the minima table (the host sized the allocation for it).  Its
+  // values are labels of this round, below n_r, or -1 (isolated): they are
+  // stored plus one in 2 bytes (LDS mode, n_r <= kLdsSlots) or 1 byte (DENSE
+  // mode, n_r <= kDenseMax).
   using LabT = std::conditional_t<kMode == kModeDense, uint8_t, uint16_t>;
   static_assert(kLdsSlots < 0xFFFF && kDenseMax < 0xFF, "staged labels plus one fit their type");
   const LabT* llab = nullptr;
   if (!kFromInput && (kMode == kModeLds || kMode == kModeDense) && A.lab_lds_off >= 0) {
     LabT* dst_l = reinterpret_cast<LabT*>(reinterpret_cast<char*>(smem) + A.lab_lds_off);
-    const int32_t nprev = A.st->n[A.round - 1];
-    for (int32_t i = threadIdx.x; i < nprev; i += kScanBlock) dst_l[i] = (LabT)(lab[i] + 1);
+    stage_map<LabT, kScanBlock>(dst_l, lab, A.st->map_n[A.round]);
     llab = dst_l;  // visible to all after the table initialisation's barrier below
   }
 
@@ -236,11 +275,16 @@ __global__ void __launch_bounds__(kScanBlock) k_scan(ScanArgs A) {
   const uint64_t lt = lanemask_lt();
   bool bad = false;
   uint32_t my_btot = 0;  // BUCKET mode: offers of bucket threadIdx.x in this workgroup's segments
+  const unsigned long long* nrec_in = reinterpret_cast<const unsigned long long*>(A.rec);
+  const uint32_t* ne_in = reinterpret_cast<const uint32_t*>(A.rec);
 
-  // Raw loads of a segment: (src, dst, w, e) from the caller's arrays or the
-  // record (a, b, w, e) of the previous round.  The next segment of this
-  // workgroup is loaded while the current one is processed (its loads stay in
-  // flight across the barriers, which wait for LDS only).
+  // Raw loads of a segment: (src, dst, w, e) from the caller's arrays, the
+  // wide record (a, b, w, e), or the narrow record (a | b << 16, -, w, e) of
+  // an earlier round (e only when the round moves its survivors; loaded
+  // first, so that the wait for the record words also covers it: vector
+  // memory loads complete in issue order).  The next segment of this
+  // workgroup is loaded while the current one is processed (its loads stay
+  // in flight across the barriers, which wait for LDS only).
   auto seg_count = [&](int32_t s) -> uint32_t {
     const uint64_t base = (uint64_t)s * kSegCap;
     if (kFromInput) return base >= A.m ? 0u : (uint32_t)min((uint64_t)kSegCap, (uint64_t)A.m - base);
@@ -251,6 +295,26 @@ __global__ void __launch_bounds__(kScanBlock) k_scan(ScanArgs A) {
   // compiler wait for them early.
   auto load_seg = [&](int32_t s, uint32_t count, uint4* x) {
     const uint64_t base = (uint64_t)s * kSegCap;
+    if (kNarrowIn) {
+      // this segment's narrow records and their edge indices (narrow_rec_index, narrow_e_index)
+      const unsigned long long* nseg = nrec_in + 2 * base;
+      const uint32_t* eseg = ne_in + 4 * base + 2 * kSegCap;
+      uint32_t ev[kPerThread];
+#pragma unroll
+      for (int k = 0; k < kPerThread; ++k) {
+        const uint32_t j = k * kScanBlock + threadIdx.x;
+        ev[k] = 0;
+        if (moved) ev[k] = ld_stream(eseg + (j < count ? j : 0u));
+      }
+      __asm__ __volatile__("" ::: "memory");  // the e loads are issued before the record loads
+#pragma unroll
+      for (int k = 0; k < kPerThread; ++k) {
+        const uint32_t j = k * kScanBlock + threadIdx.x;
+        const unsigned long long v = ld_stream(nseg + (j < count ? j : 0u));
+        x[k] = make_uint4((uint32_t)v, 0u, (uint32_t)(v >> 32), ev[k]);
+      }
+      return;
+    }
 #pragma unroll
     for (int k = 0; k < kPerThread; ++k) {
       const uint32_t j = k * kScanBlock + threadIdx.x;
@@ -302,6 +366,10 @@ __global__ void __launch_bounds__(kScanBlock) k_scan(ScanArgs A) {
       const uint32_t j = k * kScanBlock + threadIdx.x;
       const bool in = j < count;
       int32_t a = (int32_t)cx[k].x, b = (int32_t)cx[k].y;
+      if (kNarrowIn) {
+        a = (int32_t)(cx[k].x & 0xFFFFu);
+        b = (int32_t)(cx[k].x >> 16);
+      }
       if (kFromInput && !kCompact) {
         if (in && ((uint32_t)a >= (uint32_t)A.n || (uint32_t)b >= (uint32_t)A.n)) {
           bad = true;
@@ -390,14 +458,14 @@ __global__ void __launch_bounds__(kScanBlock) k_scan(ScanArgs A) {
     // edge's position in the record stream after this scan.  The stream keeps
     // the input order (stable compaction inside fixed segments), so
     // positions break ties exactly as indices do, and the hook reads the
-    // record there (this round's labels and the edge index) instead of
-    // following the label maps of every earlier round.  A dense round moves
-    // no record: its positions are the ones read.
+    // record there (the labels and the edge index) instead of following the
+    // label maps of every earlier round.  A round that moves no record (dense,
+    // or keeping its records) keys the positions it read.
     uint64_t key[kPerThread];
 #pragma unroll
     for (int k = 0; k < kPerThread; ++k) {
       const uint32_t j = k * kScanBlock + threadIdx.x;
-      const uint32_t pos = kMode == kModeDense ? (uint32_t)(base + j) : (uint32_t)(base + my_off[k]);
+      const uint32_t pos = moved ? (uint32_t)(base + my_off[k]) : (uint32_t)(base + j);
       key[k] = make_key(r[k].z, kPosKey ? pos : r[k].w);
       if (live[k]) {
         const int32_t a = (int32_t)r[k].x, b = (int32_t)r[k].y;
@@ -413,10 +481,24 @@ __global__ void __launch_bounds__(kScanBlock) k_scan(ScanArgs A) {
         }
       }
     }
-    if (kCompact && kMode != kModeDense) {
+    if (moved) {
+      if (narrow_out) {
+        // this segment's narrow records and their edge indices (narrow_rec_index, narrow_e_index)
+        unsigned long long* nrec_out = reinterpret_cast<unsigned long long*>(A.rec) + 2 * base;
+        uint32_t* ne_out = reinterpret_cast<uint32_t*>(A.rec) + 4 * base + 2 * kSegCap;
 #pragma unroll
-      for (int k = 0; k < kPerThread; ++k) {
-        if (live[k]) st_rec(r[k], A.rec + base + my_off[k]);
+        for (int k = 0; k < kPerThread; ++k) {
+          if (live[k]) {
+            st_stream((unsigned long long)(r[k].x | (r[k].y << 16)) | ((unsigned long long)r[k].z << 32),
+                      nrec_out + my_off[k]);
+            st_stream(r[k].w, ne_out + my_off[k]);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < kPerThread; ++k) {
+          if (live[k]) st_rec(r[k], A.rec + base + my_off[k]);
+        }
       }
     }
     if (kFromInput && !kCompact && kMode != kModeDense) {
@@ -430,7 +512,10 @@ __global__ void __launch_bounds__(kScanBlock) k_scan(ScanArgs A) {
         if (j < count) st_stream(cx[k].x ^ cx[k].y, xends + base + j);
       }
     }
-    if (threadIdx.x == 0) A.seg_cnt[s] = seg_tot;
+    if (threadIdx.x == 0) {
+      A.seg_live[s] = seg_tot;
+      if (moved) A.seg_cnt[s] = seg_tot;
+    }
 
     if (kMode == kModeBucket) {
       // exclusive scan of the (padded) bucket counts (nbk + 1 <= kScanBlock)
@@ -756,7 +841,7 @@ __device__ __forceinline__ int32_t dense_row_start(int32_t i, int32_t k) { retur
 // parent [k] u16, target / new id [k] u16 (dense_finish_lds(k) bytes).
 __global__ void __launch_bounds__(kDenseThreads) k_dense_finish(int round, int launched,
                                                                const unsigned long long* __restrict__ pbest,
-                                                               const uint32_t* __restrict__ seg_cnt, int32_t nseg,
+                                                               const uint32_t* __restrict__ seg_live, int32_t nseg,
                                                                const uint4* __restrict__ rec,
                                                                uint8_t* __restrict__ in_mst, unsigned long long* total,
                                                                DevState* st, HostRound* host) {
@@ -767,7 +852,7 @@ __global__ void __launch_bounds__(kDenseThreads) k_dense_finish(int round, int l
   __shared__ uint32_t nsel;
   __shared__ int32_t knext;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  // reads that depend on nothing else first: the scan's survivor counts and
+  // reads that depend on nothing else first: the scan's live counts and
   // the state tid 0 updates at the end
   int64_t live = 0;
   for (int32_t i0 = 0; i0 < nseg; i0 += 8 * kDenseThreads) {
@@ -775,7 +860,7 @@ __global__ void __launch_bounds__(kDenseThreads) k_dense_finish(int round, int l
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int32_t i = i0 + q * kDenseThreads + tid;
-      const uint32_t x = seg_cnt[i < nseg ? i : 0];  // nseg >= 1
+      const uint32_t x = seg_live[i < nseg ? i : 0];  // nseg >= 1
       v[q] = i < nseg ? x : 0u;
     }
 #pragma unroll
@@ -962,11 +1047,15 @@ __global__ void __launch_bounds__(kDenseThreads) k_dense_finish(int round, int l
     __syncthreads();
   }
   // from round 2 on the key holds the record's position (the dense scan moves
-  // no record), before that the edge index
+  // no record; narrow records keep their edge indices apart), before that
+  // the edge index
   const uint32_t nadd = nsel;
+  const bool narrow_in = round >= 2 && st->n[round - 1] <= kNarrowMax;
   for (uint32_t i = tid; i < nadd; i += kDenseThreads) {
     const uint32_t x = selpos[i];
-    in_mst[round >= 2 ? rec[x].w : x] = 1;
+    const uint32_t e = round < 2 ? x
+                       : (narrow_in ? reinterpret_cast<const uint32_t*>(rec)[narrow_e_index(x)] : rec[x].w);
+    in_mst[e] = 1;
   }
   for (int off = 32; off > 0; off >>= 1) {
     wsum += __shfl_xor(wsum, off, 64);
@@ -994,7 +1083,8 @@ __global__ void __launch_bounds__(kDenseThreads) k_dense_finish(int round, int l
     st->n[round + 1] = 0;
     st->lab_off[round + 1] = st->lab_off[round];
     st->dense_at = round;
-    HostRound h{0, st->err, st->err_internal, 1, Lv, A, added0 + A};
+    HostRound h{0, st->err, st->err_internal, 1, Lv, A, added0 + A, st->stream[round], st->map_n[round],
+                st->keep[round], 0, 0};
     host[round] = h;
     __threadfence_system();
   }
@@ -1022,7 +1112,9 @@ __device__ __forceinline__ int32_t walk_root(int32_t* parent, int32_t x) {
 // end's component.  Round 0: the key holds e, and d = c ^ (src ^ dst of e),
 // which the round-0 scan stored in the record buffer.  Later rounds: the key
 // holds the edge's position in the record stream, whose record has this
-// round's labels of both ends and e.
+// round's labels of both ends and e (a round that kept its narrow records
+// in place finds the labels of the round that wrote them there, and maps
+// them through its label map).
 // Hooking by successors: c's parent becomes d.  Following the lightest
 // edges from any component reaches exactly one pair of components that chose
 // each other (the keys are distinct and strictly decrease along the way), so
@@ -1033,6 +1125,7 @@ __device__ __forceinline__ int32_t walk_root(int32_t* parent, int32_t x) {
 // edge is marked once (by the larger), every other selected edge by the one
 // component that chose it.  k_compress finds the roots.
 __global__ void __launch_bounds__(kBlock) k_hook(int round, const uint4* __restrict__ rec,
+                                                 const int32_t* __restrict__ labpool,
                                                  const unsigned long long* __restrict__ best,
                                                  int32_t* __restrict__ parent, DevState* __restrict__ st,
                                                  uint8_t* __restrict__ in_mst, uint32_t* __restrict__ part_sel,
@@ -1042,6 +1135,9 @@ __global__ void __launch_bounds__(kBlock) k_hook(int round, const uint4* __restr
   const int32_t nr = st->n[round];
   if (nr <= 1 && round > 0) return;
   if (st->dense_at == round) return;  // the dense finish ended the solve
+  const bool narrow = nr <= kNarrowMax;        // the records at the keys' positions are narrow
+  const bool keep = st->keep[round] != 0;      // ... and hold the labels of the round that wrote them
+  const int32_t* map = labpool + st->map_off[round];
   uint32_t sel = 0;
   unsigned long long wsum = 0;
   const int64_t stride = (int64_t)gridDim.x * kBlock;
@@ -1059,10 +1155,22 @@ __global__ void __launch_bounds__(kBlock) k_hook(int round, const uint4* __restr
       u = c;
       v = d;
     } else {
-      const uint4 x = ld_rec(rec + (uint32_t)key);
-      u = (int32_t)x.x;
-      v = (int32_t)x.y;
-      e = x.w;
+      const uint32_t pos = (uint32_t)key;
+      if (narrow) {
+        const unsigned long long x = reinterpret_cast<const unsigned long long*>(rec)[narrow_rec_index(pos)];
+        e = reinterpret_cast<const uint32_t*>(rec)[narrow_e_index(pos)];
+        u = (int32_t)(x & 0xFFFFu);
+        v = (int32_t)((x >> 16) & 0xFFFFu);
+        if (keep) {
+          u = map[u];
+          v = map[v];
+        }
+      } else {
+        const uint4 x = ld_rec(rec + pos);
+        u = (int32_t)x.x;
+        v = (int32_t)x.y;
+        e = x.w;
+      }
       d = (u == c) ? v : u;
     }
     if ((uint32_t)d >= (uint32_t)nr || d == c || (u != c && v != c)) {
@@ -1120,37 +1228,76 @@ __global__ void __launch_bounds__(kBlock) k_compress(int round, int32_t* parent,
 
 // ---------------------------------------------------------------- finalize
 
+// The stream state round r leaves for round r + 1 (one thread; n_next
+// components enter round r + 1): the records it reads (`stream_next`), the
+// map from the labels in the records to round r + 1's (round r's own label
+// map if round r rewrote the records, else that map composed with round r's,
+// which k_relabel / k_round_tail write), and whether round r + 1 keeps its
+// records in place: only narrow records, only while fewer than
+// 1/kKeepDeadDen of the records round r read were dead, and only if every
+// LDS or dense launch of round r + 2 (bound n_next / 2) can stage the
+// composed map it would then read.
+__device__ __forceinline__ void next_stream_state(DevState* st, int round, int32_t nr, int32_t n_next, int64_t live,
+                                                  int64_t stream_next) {
+  const int64_t read = st->stream[round];
+  st->stream[round + 1] = stream_next;
+  if (st->keep[round]) {
+    st->map_off[round + 1] = st->cmap_off + (int64_t)((round + 1) & 1) * kNarrowMax;
+    st->map_n[round + 1] = st->map_n[round];
+  } else {
+    st->map_off[round + 1] = st->lab_off[round];
+    st->map_n[round + 1] = nr;
+  }
+  bool keep = round >= 1 && nr <= kNarrowMax && (int64_t)kKeepDeadDen * (read - live) < read;
+  if (keep) {
+    const int64_t bound = n_next / 2;
+    const int modes = scan_modes(bound, false, 3, st->dense_limit, true, kBucketMaxComponents);
+    for (int mode : {kModeLds, kModeDense})
+      if ((modes >> mode) & 1) keep = keep && map_fits_lds(mode, bound, st->dense_limit, st->map_n[round + 1]);
+  }
+  st->keep[round + 1] = keep;
+}
+
 // One workgroup of 1024 threads.  Exclusive scan of rootcnt[0..W) into
 // rootpre, W = ceil(n_r / 64); n_{r+1} = total.  Reduces this round's
-// per-block partials: live edges (part_live[0..nlive)), edges added and
-// their weight (part_sel / part_w [0..nhook)); adds the weight to *total;
-// writes the round's record for the host (pinned host memory).  The
-// partials are read first, several per thread in flight; the counts are
-// scanned 16 consecutive words per thread (four 16-byte loads) per pass.
+// per-segment counts: live edges (seg_live) and records in the stream
+// (seg_cnt), and the per-block partials of the hook: edges added and their
+// weight (part_sel / part_w [0..nhook)); adds the weight to *total; writes
+// the round's record for the host (pinned host memory) and the stream state
+// of the next round.  The counts and partials are read first, several per
+// thread in flight; the root counts are scanned 16 consecutive words per
+// thread (four 16-byte loads) per pass.
 __global__ void __launch_bounds__(1024) k_finalize(int round, const int32_t* __restrict__ rootcnt,
                                                    int32_t* __restrict__ rootpre,
-                                                   const uint32_t* __restrict__ part_live, int32_t nlive,
+                                                   const uint32_t* __restrict__ seg_cnt,
+                                                   const uint32_t* __restrict__ seg_live, int32_t nseg,
                                                    const uint32_t* __restrict__ part_sel,
                                                    const unsigned long long* __restrict__ part_w,
                                                    int32_t nhook, DevState* st,
                                                    unsigned long long* total, HostRound* host) {
   __shared__ int64_t sh[16];
   __shared__ unsigned long long shw[16];
+  __shared__ int64_t shs[16];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
-  // partials (nlive >= 1 and nhook >= 1: clamped reads stay inside)
-  int64_t live = 0, sel = 0;
+  // counts and partials (nseg >= 1 and nhook >= 1: clamped reads stay inside)
+  int64_t live = 0, recs = 0, sel = 0;
   unsigned long long ws = 0;
-  for (int32_t i0 = 0; i0 < nlive; i0 += 8 * 1024) {
-    uint32_t v[8];
+  for (int32_t i0 = 0; i0 < nseg; i0 += 8 * 1024) {
+    uint32_t v[8], c[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int32_t i = i0 + q * 1024 + tid;
-      const uint32_t x = part_live[i < nlive ? i : 0];
-      v[q] = i < nlive ? x : 0u;
+      const uint32_t x = seg_live[i < nseg ? i : 0];
+      const uint32_t y = seg_cnt[i < nseg ? i : 0];
+      v[q] = i < nseg ? x : 0u;
+      c[q] = i < nseg ? y : 0u;
     }
 #pragma unroll
-    for (int q = 0; q < 8; ++q) live += v[q];
+    for (int q = 0; q < 8; ++q) {
+      live += v[q];
+      recs += c[q];
+    }
   }
   for (int32_t i0 = 0; i0 < nhook; i0 += 4 * 1024) {
     uint32_t c[4];
@@ -1178,7 +1325,7 @@ __global__ void __launch_bounds__(1024) k_finalize(int round, const int32_t* __r
     if (tid == 0) {
       st->n[round + 1] = 0;
       st->lab_off[round + 1] = st->lab_off[round];
-      HostRound h{0, st->err, st->err_internal, 0, 0, 0, st->edges_added};
+      HostRound h{0, st->err, st->err_internal, 0, 0, 0, st->edges_added, 0, 0, 0, 0, 0};
       host[round] = h;
       __threadfence_system();
     }
@@ -1240,19 +1387,22 @@ __global__ void __launch_bounds__(1024) k_finalize(int round, const int32_t* __r
   }
   const int64_t total_roots = carry;
   live = wave_sum(live);
+  recs = wave_sum(recs);
   sel = wave_sum(sel);
   ws = wave_sum(ws);
   __syncthreads();
   if (lane == 0) {
     sh[wv] = live;
     shw[wv] = ws;
+    shs[wv] = recs;
   }
   __syncthreads();
-  int64_t L = 0;
+  int64_t L = 0, Rn = 0;
   unsigned long long S = 0;
   for (int i = 0; i < 16; ++i) {
     L += sh[i];
     S += shw[i];
+    Rn += shs[i];
   }
   __syncthreads();
   if (lane == 0) sh[wv] = sel;
@@ -1266,7 +1416,11 @@ __global__ void __launch_bounds__(1024) k_finalize(int round, const int32_t* __r
     st->n[round + 1] = (int32_t)total_roots;
     st->lab_off[round + 1] = st->lab_off[round] + nr;
     *total += S;
-    HostRound h{(int32_t)total_roots, st->err, st->err_internal, 0, L, T, st->edges_added};
+    // round 0 leaves the stream untouched: round 1 reads the caller's edges
+    next_stream_state(st, round, nr, (int32_t)total_roots, L, round == 0 ? st->m : Rn);
+    HostRound h{(int32_t)total_roots, st->err,          st->err_internal, 0,
+                L,                    T,                st->edges_added,  st->stream[round],
+                st->map_n[round],     st->keep[round],  st->keep[round + 1], 0};
     host[round] = h;
     __threadfence_system();
   }
@@ -1276,8 +1430,10 @@ __global__ void __launch_bounds__(1024) k_finalize(int round, const int32_t* __r
 
 // lab_r[c] = dense new label of c's root: the number of kept roots with a
 // smaller id (rootpre of its 64-word plus a popcount inside the word); -1 for
-// an isolated component.  Then parent[] and best[] are reset for the
-// n_{r+1} components of the next round.
+// an isolated component.  When round r kept its records, the map round r + 1
+// applies to them is lab_r composed with round r's map (the same label of
+// the root, reached through that map).  Then parent[] and best[] are reset
+// for the n_{r+1} components of the next round.
 __global__ void __launch_bounds__(kBlock) k_relabel(int round, const int32_t* __restrict__ root_of,
                                                     const unsigned long long* __restrict__ rootmask,
                                                     const int32_t* __restrict__ rootpre,
@@ -1290,13 +1446,22 @@ __global__ void __launch_bounds__(kBlock) k_relabel(int round, const int32_t* __
   const int32_t nn = st->n[round + 1];
   const int64_t off = st->lab_off[round];
   const int64_t stride = (int64_t)gridDim.x * kBlock;
-  for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < nr; c += stride) {
+  auto label_of = [&](int32_t c) -> int32_t {
     const int32_t r = root_of[c];
     const unsigned long long word = rootmask[r >> 6];
     const int bit = r & 63;
-    int32_t label = -1;
-    if ((word >> bit) & 1ull) label = rootpre[r >> 6] + __popcll(word & ((1ull << bit) - 1ull));
-    labpool[off + c] = label;
+    return ((word >> bit) & 1ull) ? rootpre[r >> 6] + __popcll(word & ((1ull << bit) - 1ull)) : -1;
+  };
+  for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < nr; c += stride)
+    labpool[off + c] = label_of((int32_t)c);
+  if (st->keep[round]) {
+    const int32_t* mi = labpool + st->map_off[round];
+    int32_t* mo = labpool + st->map_off[round + 1];
+    const int32_t ne = st->map_n[round];
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < ne; i += stride) {
+      const int32_t x = mi[i];
+      mo[i] = x < 0 ? -1 : label_of(x);
+    }
   }
   for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < nn; c += stride) {
     parent[c] = (int32_t)c;
@@ -1323,13 +1488,15 @@ static constexpr int kTailPer = (kTailMax + kTailThreads - 1) / kTailThreads;
 __global__ void __launch_bounds__(kTailThreads) k_round_tail(int round, int32_t cap, const uint4* __restrict__ rec,
                                                             unsigned long long* best, int32_t* parent,
                                                             int32_t* __restrict__ labpool,
-                                                            const uint32_t* __restrict__ seg_cnt, int32_t nseg,
+                                                            const uint32_t* __restrict__ seg_cnt,
+                                                            const uint32_t* __restrict__ seg_live, int32_t nseg,
                                                             uint8_t* __restrict__ in_mst,
                                                             unsigned long long* total, uint32_t* __restrict__ btot,
                                                             DevState* st, HostRound* host) {
   extern __shared__ int32_t tsm[];
   __shared__ int64_t red_a[kTailThreads / 64];
   __shared__ int64_t red_b[kTailThreads / 64];
+  __shared__ int64_t red_c[kTailThreads / 64];
   __shared__ unsigned long long red_w[kTailThreads / 64];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   // Every read that does not depend on another is issued here, before the
@@ -1345,17 +1512,22 @@ __global__ void __launch_bounds__(kTailThreads) k_round_tail(int round, int32_t 
     const unsigned long long k = best[c < cap ? c : 0];
     key[q] = c < cap ? k : kKeyNone;
   }
-  int64_t live = 0;
+  int64_t live = 0, recs = 0;
   for (int32_t i0 = 0; i0 < nseg; i0 += 8 * kTailThreads) {
-    uint32_t v[8];
+    uint32_t v[8], c[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int32_t i = i0 + q * kTailThreads + tid;
-      const uint32_t x = seg_cnt[i < nseg ? i : 0];  // nseg >= 1
+      const uint32_t x = seg_live[i < nseg ? i : 0];  // nseg >= 1
+      const uint32_t y = seg_cnt[i < nseg ? i : 0];
       v[q] = i < nseg ? x : 0u;
+      c[q] = i < nseg ? y : 0u;
     }
 #pragma unroll
-    for (int q = 0; q < 8; ++q) live += v[q];
+    for (int q = 0; q < 8; ++q) {
+      live += v[q];
+      recs += c[q];
+    }
   }
   const int64_t off = st->lab_off[round];
   int64_t added0 = 0;
@@ -1372,7 +1544,7 @@ __global__ void __launch_bounds__(kTailThreads) k_round_tail(int round, int32_t 
     if (tid == 0) {
       st->n[round + 1] = 0;
       st->lab_off[round + 1] = off;
-      HostRound h{0, err0, erri0, 0, 0, 0, added0};
+      HostRound h{0, err0, erri0, 0, 0, 0, added0, 0, 0, 0, 0, 0};
       host[round] = h;
       __threadfence_system();
     }
@@ -1381,7 +1553,7 @@ __global__ void __launch_bounds__(kTailThreads) k_round_tail(int round, int32_t 
   if (nr > cap) {  // never: the host's bound covers n_r
     if (tid == 0) {
       st->err_internal = 1;
-      HostRound h{0, err0, 1, 0, 0, 0, added0};
+      HostRound h{0, err0, 1, 0, 0, 0, added0, 0, 0, 0, 0, 0};
       host[round] = h;
       __threadfence_system();
     }
@@ -1410,12 +1582,32 @@ __global__ void __launch_bounds__(kTailThreads) k_round_tail(int round, int32_t 
       d[q] = key[q] != kKeyNone ? (int32_t)(xv[q] ^ (uint32_t)c) : -1;
     }
   } else {
+    // the record at the key's position: wide, or narrow (this round's labels
+    // when the scan rewrote it, else those of the round that wrote it,
+    // mapped through this round's label map)
     uint2 ab[kTailPer];
+    if (nr <= kNarrowMax) {
+      const unsigned long long* nrec = reinterpret_cast<const unsigned long long*>(rec);
+      const uint32_t* ne = reinterpret_cast<const uint32_t*>(rec);
 #pragma unroll
-    for (int q = 0; q < kTailPer; ++q) {
-      const uint32_t pos = key[q] != kKeyNone ? (uint32_t)key[q] : 0u;
-      ab[q] = *reinterpret_cast<const uint2*>(rec + pos);
-      e[q] = rec[pos].w;
+      for (int q = 0; q < kTailPer; ++q) {
+        const uint32_t pos = key[q] != kKeyNone ? (uint32_t)key[q] : 0u;
+        const unsigned long long x = nrec[narrow_rec_index(pos)];
+        e[q] = ne[narrow_e_index(pos)];
+        ab[q] = make_uint2((uint32_t)(x & 0xFFFFu), (uint32_t)((x >> 16) & 0xFFFFu));
+      }
+      if (st->keep[round]) {
+        const int32_t* map = labpool + st->map_off[round];
+#pragma unroll
+        for (int q = 0; q < kTailPer; ++q) ab[q] = make_uint2((uint32_t)map[ab[q].x], (uint32_t)map[ab[q].y]);
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < kTailPer; ++q) {
+        const uint32_t pos = key[q] != kKeyNone ? (uint32_t)key[q] : 0u;
+        ab[q] = *reinterpret_cast<const uint2*>(rec + pos);
+        e[q] = rec[pos].w;
+      }
     }
 #pragma unroll
     for (int q = 0; q < kTailPer; ++q) {
@@ -1513,6 +1705,27 @@ __global__ void __launch_bounds__(kTailThreads) k_round_tail(int round, int32_t 
       labpool[off + c] = r < 0 ? -1 : par[r];
     }
   }
+  if (st->keep[round]) {
+    // the records stay as they are: the next round's map is this round's
+    // map composed with the labels just given
+    const int32_t* mi = labpool + st->map_off[round];
+    int32_t* mo = labpool + st->cmap_off + (int64_t)((round + 1) & 1) * kNarrowMax;
+    const int32_t ne = st->map_n[round];
+    for (int32_t i0 = 0; i0 < ne; i0 += 8 * kTailThreads) {
+      int32_t x[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int32_t i = i0 + q * kTailThreads + tid;
+        x[q] = mi[i < ne ? i : 0];
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int32_t i = i0 + q * kTailThreads + tid;
+        const int32_t r = x[q] < 0 ? -1 : tgt[x[q]];
+        if (i < ne) mo[i] = r < 0 ? -1 : par[r];
+      }
+    }
+  }
   // the next round's parent[] and best[] (n_{r+1} = roots), bucket counters
   for (int32_t c = tid; c < roots; c += kTailThreads) {
     parent[c] = c;
@@ -1522,21 +1735,24 @@ __global__ void __launch_bounds__(kTailThreads) k_round_tail(int round, int32_t 
     for (int32_t i = tid; i < kMaxBuckets; i += kTailThreads) btot[i] = 0;
   // the round's record
   live = wave_sum(live);
+  recs = wave_sum(recs);
   int64_t sel64 = wave_sum((int64_t)sel);
   wsum = wave_sum(wsum);
   __syncthreads();  // red_a is rewritten
   if (lane == 0) {
     red_a[wv] = live;
     red_b[wv] = sel64;
+    red_c[wv] = recs;
     red_w[wv] = wsum;
   }
   __syncthreads();
   if (tid == 0) {
-    int64_t L = 0, T = 0;
+    int64_t L = 0, T = 0, R = 0;
     unsigned long long W = 0;
     for (int i = 0; i < kTailThreads / 64; ++i) {
       L += red_a[i];
       T += red_b[i];
+      R += red_c[i];
       W += red_w[i];
     }
     const int erri = any_bad ? 1 : erri0;
@@ -1547,7 +1763,9 @@ __global__ void __launch_bounds__(kTailThreads) k_round_tail(int round, int32_t 
     st->n[round + 1] = roots;
     st->lab_off[round + 1] = off + nr;
     *total = total0 + W;
-    HostRound h{roots, err0, erri, 0, L, T, added0 + T};
+    next_stream_state(st, round, nr, roots, L, round == 0 ? st->m : R);
+    HostRound h{roots, err0, erri, 0, L, T, added0 + T, st->stream[round], st->map_n[round], st->keep[round],
+                st->keep[round + 1], 0};
     host[round] = h;
     __threadfence_system();
   }
@@ -1561,28 +1779,23 @@ __global__ void __launch_bounds__(kTailThreads) k_round_tail(int round, int32_t 
     if (_e != hipSuccess) return _e;   \
   } while (0)
 
-template <int M, bool I, bool C>
+template <int M, int St>
 static hipError_t raise_lds_limit() {
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_scan<M, I, C>),
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_scan<M, St>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxDynLds);
 }
 
 hipError_t configure_kernels() {
   hipError_t e = hipSuccess;
-#define MSTX_CFG(M, I, C)                       \
-  do {                                          \
-    hipError_t r_ = raise_lds_limit<M, I, C>(); \
-    if (r_ != hipSuccess) e = r_;               \
+#define MSTX_CFG(M)                                                        \
+  do {                                                                     \
+    for (hipError_t r_ : {raise_lds_limit<M, 0>(), raise_lds_limit<M, 1>(), \
+                          raise_lds_limit<M, 2>(), raise_lds_limit<M, 3>()}) \
+      if (r_ != hipSuccess) e = r_;                                        \
   } while (0)
-  MSTX_CFG(kModeLds, true, false);
-  MSTX_CFG(kModeLds, true, true);
-  MSTX_CFG(kModeLds, false, true);
-  MSTX_CFG(kModeBucket, true, false);
-  MSTX_CFG(kModeBucket, true, true);
-  MSTX_CFG(kModeBucket, false, true);
-  MSTX_CFG(kModeDense, true, false);
-  MSTX_CFG(kModeDense, true, true);
-  MSTX_CFG(kModeDense, false, true);
+  MSTX_CFG(kModeLds);
+  MSTX_CFG(kModeBucket);
+  MSTX_CFG(kModeDense);
 #undef MSTX_CFG
   hipError_t r4 = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_round_tail),
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxDynLds);
@@ -1596,9 +1809,10 @@ hipError_t configure_kernels() {
   return e;
 }
 
-hipError_t launch_init(int32_t n, unsigned long long* best, int32_t* parent, unsigned long long* pbest,
-                       uint32_t* btot, DevState* st, int grid, hipStream_t s) {
-  k_init<<<grid, kBlock, 0, s>>>(n, best, parent, pbest, btot, st);
+hipError_t launch_init(int32_t n, int64_t m, int64_t cmap_off, int dense_limit, unsigned long long* best,
+                       int32_t* parent, unsigned long long* pbest, uint32_t* btot, DevState* st, int grid,
+                       hipStream_t s) {
+  k_init<<<grid, kBlock, 0, s>>>(n, m, cmap_off, dense_limit, best, parent, pbest, btot, st);
   MSTX_LAUNCH_CHECK();
   return hipSuccess;
 }
@@ -1610,12 +1824,13 @@ hipError_t launch_fill_u64(unsigned long long* p, int64_t count, unsigned long l
 }
 
 hipError_t launch_scan(int mode, int stage, const ScanArgs& a, int grid, size_t lds, hipStream_t s) {
-  // stage 0: round 0 (input, no compaction); 1: round 1 (input, compaction); 2: records
-#define MSTX_SCAN(M)                                                             \
-  do {                                                                           \
-    if (stage == 0) k_scan<M, true, false><<<grid, kScanBlock, lds, s>>>(a);     \
-    else if (stage == 1) k_scan<M, true, true><<<grid, kScanBlock, lds, s>>>(a); \
-    else k_scan<M, false, true><<<grid, kScanBlock, lds, s>>>(a);                \
+  // stage: the edge stream the round reads (scan_stage)
+#define MSTX_SCAN(M)                                                    \
+  do {                                                                  \
+    if (stage == 0) k_scan<M, 0><<<grid, kScanBlock, lds, s>>>(a);      \
+    else if (stage == 1) k_scan<M, 1><<<grid, kScanBlock, lds, s>>>(a); \
+    else if (stage == 2) k_scan<M, 2><<<grid, kScanBlock, lds, s>>>(a); \
+    else k_scan<M, 3><<<grid, kScanBlock, lds, s>>>(a);                 \
   } while (0)
   if (mode == kModeLds) MSTX_SCAN(kModeLds);
   else if (mode == kModeDense) MSTX_SCAN(kModeDense);
@@ -1644,30 +1859,31 @@ hipError_t launch_slab_min(int round, int launched, int mode, const unsigned lon
   return hipSuccess;
 }
 
-hipError_t launch_dense_finish(int round, int launched, const unsigned long long* pbest, const uint32_t* seg_cnt,
+hipError_t launch_dense_finish(int round, int launched, const unsigned long long* pbest, const uint32_t* seg_live,
                                int32_t nseg, const uint4* rec, uint8_t* in_mst, unsigned long long* total,
                                DevState* st, HostRound* host, hipStream_t s) {
   const int32_t kmax = launched_dense_limit(launched) < kDenseMax ? launched_dense_limit(launched) : kDenseMax;
   const size_t lds = dense_finish_lds(kmax);
-  k_dense_finish<<<1, kDenseThreads, lds, s>>>(round, launched, pbest, seg_cnt, nseg, rec, in_mst, total, st, host);
+  k_dense_finish<<<1, kDenseThreads, lds, s>>>(round, launched, pbest, seg_live, nseg, rec, in_mst, total, st, host);
   MSTX_LAUNCH_CHECK();
   return hipSuccess;
 }
 
 hipError_t launch_round_tail(int round, int32_t cap, const uint4* rec, unsigned long long* best, int32_t* parent,
-                             int32_t* labpool, const uint32_t* seg_cnt, int32_t nseg, uint8_t* in_mst,
-                             unsigned long long* total, uint32_t* btot, DevState* st, HostRound* host,
-                             hipStream_t s) {
+                             int32_t* labpool, const uint32_t* seg_cnt, const uint32_t* seg_live, int32_t nseg,
+                             uint8_t* in_mst, unsigned long long* total, uint32_t* btot, DevState* st,
+                             HostRound* host, hipStream_t s) {
   const size_t lds = 8 * (size_t)(cap < 1 ? 1 : (cap > kTailMax ? kTailMax : cap));
   k_round_tail<<<1, kTailThreads, lds, s>>>(round, cap < kTailMax ? cap : kTailMax, rec, best, parent, labpool,
-                                            seg_cnt, nseg, in_mst, total, btot, st, host);
+                                            seg_cnt, seg_live, nseg, in_mst, total, btot, st, host);
   MSTX_LAUNCH_CHECK();
   return hipSuccess;
 }
 
-hipError_t launch_hook(int round, const uint4* rec, const unsigned long long* best, int32_t* parent, DevState* st,
-                       uint8_t* in_mst, uint32_t* part_sel, unsigned long long* part_w, int grid, hipStream_t s) {
-  k_hook<<<grid, kBlock, 0, s>>>(round, rec, best, parent, st, in_mst, part_sel, part_w);
+hipError_t launch_hook(int round, const uint4* rec, const int32_t* labpool, const unsigned long long* best,
+                       int32_t* parent, DevState* st, uint8_t* in_mst, uint32_t* part_sel,
+                       unsigned long long* part_w, int grid, hipStream_t s) {
+  k_hook<<<grid, kBlock, 0, s>>>(round, rec, labpool, best, parent, st, in_mst, part_sel, part_w);
   MSTX_LAUNCH_CHECK();
   return hipSuccess;
 }
@@ -1680,12 +1896,12 @@ hipError_t launch_compress(int round, int32_t* parent, int32_t* root_of, const u
   return hipSuccess;
 }
 
-hipError_t launch_finalize(int round, const int32_t* rootcnt, int32_t* rootpre, const uint32_t* part_live,
-                           int32_t nlive, const uint32_t* part_sel, const unsigned long long* part_w,
-                           int32_t nhook, DevState* st, unsigned long long* total, HostRound* host,
-                           hipStream_t s) {
-  k_finalize<<<1, 1024, 0, s>>>(round, rootcnt, rootpre, part_live, nlive, part_sel, part_w, nhook, st, total,
-                                host);
+hipError_t launch_finalize(int round, const int32_t* rootcnt, int32_t* rootpre, const uint32_t* seg_cnt,
+                           const uint32_t* seg_live, int32_t nseg, const uint32_t* part_sel,
+                           const unsigned long long* part_w, int32_t nhook, DevState* st,
+                           unsigned long long* total, HostRound* host, hipStream_t s) {
+  k_finalize<<<1, 1024, 0, s>>>(round, rootcnt, rootpre, seg_cnt, seg_live, nseg, part_sel, part_w, nhook, st,
+                                total, host);
   MSTX_LAUNCH_CHECK();
   return hipSuccess;
 }

@@ -70,6 +70,36 @@ def ties_multigraph(n, m, seed, wmax=4):
     return G.Graph(n, src[order], dst[order], w[order], f"ties_n{n}_m{m}_s{seed}")
 
 
+def halving_path(k, extra, seed):
+    """A path 0 - 1 - ... - (n - 1), n = 2^k, whose edge (i, i + 1) weighs the
+    position of the lowest set bit of i + 1 (ties broken by i), plus `extra`
+    uniform random extra edges per vertex, all heavier than every path edge.
+    Every round pairs neighbouring components of the path, so the component
+    count halves round by round while almost every edge stays live: rounds
+    that read 16-bit records while bucket, LDS and dense minima follow one
+    another."""
+    rng = np.random.default_rng(seed)
+    n = 1 << k
+    i = np.arange(n - 1, dtype=np.int64)
+    low = i + 1
+    ctz = np.zeros(n - 1, np.int64)
+    while np.any(low % 2 == 0):
+        even = low % 2 == 0
+        ctz[even] += 1
+        low[even] //= 2
+    wp = ctz * n + i + 1
+    me = extra * n
+    a = rng.integers(0, n, me)
+    b = rng.integers(0, n - 1, me)
+    b = b + (b >= a)  # no loops
+    we = (k + 1) * n + 1 + rng.permutation(me)
+    src = np.concatenate([i, a]).astype(np.int32)
+    dst = np.concatenate([i + 1, b]).astype(np.int32)
+    w = np.concatenate([wp, we]).astype(np.uint32)
+    order = rng.permutation(len(src))
+    return G.Graph(n, src[order], dst[order], w[order], f"halving_path_2^{k}_x{extra}")
+
+
 def small_cases():
     """(graph, expect_connected) pairs that the oracle finishes in well under a second."""
     cases = [
@@ -98,6 +128,11 @@ def small_cases():
         # row-major edge order gives long runs (cut into items)
         G.rmat(16, 400_000, seed=33),
         G.grid2d(256, 256, seed=34, name="grid_256x256"),
+        # component counts halving round by round with few edges dying:
+        # 16-bit records kept in place from round 2 on, read through composed
+        # label maps in bucket (2^17), LDS and dense rounds
+        halving_path(17, 8, seed=37),
+        halving_path(15, 6, seed=38),
         _concat([(G.tree_plus_extra(700, 3000, seed=31), 0), (G.tree_plus_extra(500, 900, seed=32), 10_000),
                  (G.Graph(5, np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0, np.uint32)), 0)],
                 "disconnected_3parts_plus_isolated"),

@@ -187,7 +187,9 @@ def test_kernel_names(lib):
     names = [lib.mst_profile_kernel_name(i).decode() for i in range(64)]
     names = [x for x in names if x]
     assert "k_dense_finish" in names and "k_hook" in names and "k_round_tail" in names
-    assert "k_scan<3, false, true>" in names
+    for mode in range(4):
+        for stage in range(4):
+            assert f"k_scan<{mode}, {stage}>" in names
     assert len(names) == len(set(names))
     prof = B.mst_profile_read()  # host counters only: no device call
     assert set(prof) == set(names)

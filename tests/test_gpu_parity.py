@@ -270,9 +270,9 @@ def test_solve_paper_shapes(dev, n, d):
 @pytest.mark.parametrize("tail", [gpu_cases.TAIL_MAX, 0])
 def test_solve_increasing_path_2_20(dev, tail):
     """A path of n = 2^20 vertices with increasing weights: every vertex's
-    lightest edge goes to its successor, so round 0 adds all n - 1 edges as one
-    hook chain of depth n - 1 (the deepest the compare-and-swap hooking and the
-    pointer jumping meet)."""
+    lightest edge goes to its predecessor, so round 0 adds all n - 1 edges as one
+    parent chain of depth n - 1 (the deepest forest the hooking builds and the
+    pointer jumping flattens)."""
     from paper_2005_06913_amd import graphgen as G
     g = G.path_graph(1 << 20)
     gstats = check_against_oracle(dev, g.name, g.n, g.src, g.dst, g.w, tail=tail)
