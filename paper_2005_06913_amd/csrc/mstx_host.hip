@@ -381,19 +381,27 @@ int enqueue_scan(Solve& S, int r, int stage, int64_t bound, bool exact, hipError
   launched |= S.dense_limit << 8;
   ScanArgs A{r,         launched,   S.src,    S.dst,  S.w,      (uint32_t)S.m, S.n,      S.labpool,
              S.rec,     S.seg_cnt,  S.seg_live, S.L.nseg, S.best, S.st,     S.offers,      S.offT,   S.slab,
-             S.L.slab_cap, S.pbest, -1,         S.btot};
+             S.L.slab_cap, S.pbest, 0,          S.btot};
   const int cus = S.cus;
   for (int mode : {kModeDense, kModeLds, kModeBucket, kModeGlobal}) {
     if (!(launched & (1 << mode))) continue;
     int grid;
     size_t lds;
-    if (mode == kModeDense) {
+    if (mode == kModeLds || mode == kModeDense) {
       lds = (size_t)scan_table_lds(mode, bound, S.dense_limit);
-      grid = std::min(S.L.nseg, cus);
-    } else if (mode == kModeLds) {
-      lds = (size_t)scan_table_lds(mode, bound, S.dense_limit);
-      const int per_cu = (int)std::max<int64_t>(1, std::min<int64_t>(4, 65536 / ((int64_t)lds + 1024)));
-      grid = std::min(S.L.nseg, cus * per_cu);
+      // rounds >= 2: room for the round's label map (dom entries, 2 bytes
+      // each, 1 in DENSE mode) behind the table, up to the LDS a workgroup
+      // may take; the kernel lays out the table for the actual count and
+      // stages as much of the map as then fits
+      if (stage >= 2 && dom > 0)
+        lds = std::min<size_t>((size_t)kMaxDynLds,
+                               ((lds + 15) & ~size_t(15)) + (mode == kModeDense ? 1 : 2) * (size_t)dom);
+      if (mode == kModeDense) {
+        grid = std::min(S.L.nseg, cus);
+      } else {
+        const int per_cu = (int)std::max<int64_t>(1, std::min<int64_t>(4, 65536 / ((int64_t)lds + 1024)));
+        grid = std::min(S.L.nseg, cus * per_cu);
+      }
     } else if (mode == kModeBucket) {
       lds = kBucketScanLds;
       grid = std::min(S.L.nseg, cus);
@@ -401,16 +409,7 @@ int enqueue_scan(Solve& S, int r, int stage, int64_t bound, bool exact, hipError
       lds = 0;
       grid = std::min(S.L.nseg, 2 * cus);
     }
-    // the round's label map (at most dom entries) goes to LDS beside the
-    // minima table when both fit: the lookups become LDS reads.  Staged
-    // entries take 2 bytes (LDS mode) or 1 byte (DENSE mode).
-    A.lab_lds_off = -1;
-    if (stage >= 2 && (mode == kModeLds || mode == kModeDense) && dom > 0 &&
-        map_fits_lds(mode, bound, S.dense_limit, dom)) {
-      const size_t off = (lds + 15) & ~size_t(15);
-      A.lab_lds_off = (int32_t)off;
-      lds = off + (mode == kModeDense ? 1 : 2) * (size_t)dom;
-    }
+    A.lds_bytes = (int32_t)lds;
     const int k = T.start(scan_kind(stage, mode), r, mode);
     err = launch_scan(mode, stage, A, grid, lds, S.s);
     T.stop(k);
@@ -452,14 +451,14 @@ int enqueue_scan(Solve& S, int r, int stage, int64_t bound, bool exact, hipError
 // known to be `bound`, so only its own minima mode is launched).
 // n_prev is the exact count entering round r - 1, which fixes the stream
 // round r reads; its label map has n_prev entries, or, if round r - 1 kept
-// its records in place (S.keep[r - 1], known from round r - 2's record), as
+// its records untouched (S.keep[r - 1], known from round r - 2's record), as
 // many as round r - 1's.
 hipError_t enqueue_round(Solve& S, int r, int64_t bound, int64_t n_prev, bool exact) {
   LaunchTimer& T = t_timer;
   hipError_t err = hipSuccess;
   const int stage = scan_stage(r, n_prev);
   S.stage[r] = stage;
-  S.dom[r] = r == 0 ? 0 : (S.keep[r - 1] ? S.dom[r - 1] : n_prev);
+  S.dom[r] = r == 0 ? 0 : (S.keep[r - 1] == kKeepRecords ? S.dom[r - 1] : n_prev);
   S.launched[r] = enqueue_scan(S, r, stage, bound, exact, err, S.dom[r]);
   if (err != hipSuccess) return err;
   const int gh = grid_for(std::max<int64_t>(bound, 1));
@@ -562,20 +561,23 @@ Solve make_solve(void* B, int cus, HostRound* rounds, hipEvent_t* events, const 
 
 // Algorithmic bytes of round r's scan: the edge stream read once (12 B per
 // input edge, 16 B per wide record, 8 B per narrow record, plus its 4-byte
-// edge index when the round rewrites it), the round's label map read once
+// edge index when the round compacts it), the round's label map read once
 // (4 B per entry), the minima initialised and written once (16 B per
 // component), the survivors written once (16 B wide, 12 B narrow with the
-// edge index; none when the round keeps its records); a dense round instead
-// writes its pair table once (8 B per pair) and moves no record.
+// edge index; none when the round keeps its records, every record's 8 B when
+// it relabels them in place); a dense round instead writes its pair table
+// once (8 B per pair) and moves no record.
 double round_scan_bytes(const HostRound* rec, const int32_t* nr_of, int r, int64_t m) {
   const HostRound& M = rec[r];
   const double nrd = (double)nr_of[r];
   const bool narrow_in = r >= 2 && nr_of[r - 1] <= kNarrowMax;
-  const bool moves = r >= 1 && !M.dense && !M.keep;
+  const bool moves = r >= 1 && !M.dense && M.keep == kMoveRecords;
+  const bool relabels = !M.dense && M.keep == kRelabelRecords;
   double b = r <= 1 ? 12.0 * (double)m : (narrow_in ? (moves ? 12.0 : 8.0) : 16.0) * (double)M.stream;
   b += 4.0 * (double)M.map_n;
   b += M.dense ? 8.0 * (double)dense_pairs(nr_of[r]) : 16.0 * nrd;
   if (moves) b += (nr_of[r] <= kNarrowMax ? 12.0 : 16.0) * (double)M.live;
+  if (relabels) b += 8.0 * (double)M.stream;
   return b;
 }
 

@@ -133,13 +133,18 @@ __host__ __device__ constexpr uint64_t narrow_e_index(uint32_t pos) {
 __host__ __device__ constexpr int scan_stage(int q, int64_t n_prev) {
   return q == 0 ? 0 : (q == 1 ? 1 : (n_prev <= kNarrowMax ? 3 : 2));
 }
-// A round that reads narrow records may keep them where they are (no
-// rewrite) when fewer than 1/kKeepDeadDen of the records the previous round
-// read were dead there, and the composed label map the round after it then
-// reads (two buffers of kNarrowMax entries, used alternately) can still be
-// staged in that round's LDS; later rounds read the labels of the round that
-// last wrote the records through that map.
+// What a round that reads narrow records does with them (DevState::keep):
+// kMoveRecords compacts the survivors (the default, and always when at least
+// 1/kKeepDeadDen of the records the previous round read were dead there);
+// otherwise kKeepRecords leaves them untouched when the composed label map
+// the round after it then reads (two buffers of kNarrowMax entries, used
+// alternately) can still be staged in that round's LDS, and
+// kRelabelRecords rewrites every record's labels in place (same positions,
+// no edge-index traffic) when it cannot.
 static constexpr int kKeepDeadDen = 4;
+static constexpr int kMoveRecords = 0;
+static constexpr int kKeepRecords = 1;
+static constexpr int kRelabelRecords = 2;
 
 // Minima modes launched for a round whose component count is at most
 // `bound` (exact: it is the count), reading stream `stage`; bit i = mode i.
@@ -195,7 +200,7 @@ struct DevState {
   int64_t stream[kMaxRounds + 2];   // records (or input edges) round r reads
   int64_t map_off[kMaxRounds + 2];  // label-pool offset of the map from record labels to round r's
   int32_t map_n[kMaxRounds + 2];    // ... and its entries
-  int32_t keep[kMaxRounds + 2];     // round r does not rewrite the records it reads
+  int32_t keep[kMaxRounds + 2];     // what round r does with the records it reads (kMoveRecords ..)
   int64_t edges_added;              // running total of sel[]
   int64_t m;                        // input edges
   int64_t cmap_off;                 // label-pool offset of the two composed-map buffers
@@ -217,8 +222,8 @@ struct HostRound {
   int64_t edges_added;
   int64_t stream;  // records (or input edges) the round read
   int32_t map_n;      // entries of the label map the round read
-  int32_t keep;       // 1: the round kept its records in place
-  int32_t keep_next;  // 1: the next round keeps its records in place
+  int32_t keep;       // what the round did with its records (kMoveRecords ..)
+  int32_t keep_next;  // ... and what the next round does
   int32_t pad;
 };
 
@@ -243,7 +248,8 @@ struct ScanArgs {
   unsigned long long* slab;     // LDS mode, n_r > kSlabMin: per-workgroup minima [grid][n_r]
   int64_t slab_cap;             // entries of slab
   unsigned long long* pbest;    // dense mode: lightest key per component pair [kDensePairsMax]
-  int32_t lab_lds_off;          // rounds >= 2: byte offset of the label map copy in LDS (-1: none)
+  int32_t lds_bytes;            // dynamic LDS of the launch (LDS / DENSE mode: the table for n_r,
+                                // then the first entries of the label map that fit, rounds >= 2)
   uint32_t* btot;               // BUCKET mode: offers per bucket, summed over the scan [kMaxBuckets]
 };
 

@@ -230,24 +230,37 @@ __global__ void __launch_bounds__(kScanBlock) k_scan(ScanArgs A) {
   if (pick_mode(nr, A.launched) != kMode) return;
   const int32_t* lab = kCompact ? A.labpool + A.st->map_off[A.round] : nullptr;
   // this round's survivors: rewritten (moved to their compacted positions),
-  // narrow or wide, or left where they are
-  const bool keep = kNarrowIn && A.st->keep[A.round] != 0;
-  const bool moved = kCompact && kMode != kModeDense && !keep;
+  // narrow or wide, left where they are, or relabelled where they are
+  const int what = kNarrowIn ? A.st->keep[A.round] : kMoveRecords;
+  const bool moved = kCompact && kMode != kModeDense && what == kMoveRecords;
+  const bool inplace = kNarrowIn && kMode != kModeDense && what == kRelabelRecords;
   const bool narrow_out = nr <= kNarrowMax;
   // keys carry stream positions from round 1 on (see below)
   constexpr bool kPosKey = kCompact && !(kFromInput && kMode == kModeDense);
-  // rounds >= 2 in LDS / DENSE mode: this round's label map may be staged in
-  // LDS behind the minima table (the host sized the allocation for it).  Its
-  // values are labels of this round, below n_r, or -1 (isolated): they are
-  // stored plus one in 2 bytes (LDS mode, n_r <= kLdsSlots) or 1 byte (DENSE
-  // mode, n_r <= kDenseMax).
+  // rounds >= 2 in LDS / DENSE mode: the first entries of this round's label
+  // map are staged in LDS behind the minima table for the actual n_r, as
+  // many as the launch's allocation holds.  Its values are labels of this
+  // round, below n_r, or -1 (isolated): they are stored plus one in 2 bytes
+  // (LDS mode, n_r <= kLdsSlots) or 1 byte (DENSE mode, n_r <= kDenseMax).
+  // Lookups: 0 the vertex ids themselves (round 0), 1 the map in memory,
+  // 2 LDS for every label, 3 LDS below the staged count and memory above.
   using LabT = std::conditional_t<kMode == kModeDense, uint8_t, uint16_t>;
   static_assert(kLdsSlots < 0xFFFF && kDenseMax < 0xFF, "staged labels plus one fit their type");
   const LabT* llab = nullptr;
-  if (!kFromInput && (kMode == kModeLds || kMode == kModeDense) && A.lab_lds_off >= 0) {
-    LabT* dst_l = reinterpret_cast<LabT*>(reinterpret_cast<char*>(smem) + A.lab_lds_off);
-    stage_map<LabT, kScanBlock>(dst_l, lab, A.st->map_n[A.round]);
-    llab = dst_l;  // visible to all after the table initialisation's barrier below
+  int lookup = kCompact ? 1 : 0;
+  int32_t nst = 0;
+  if (!kFromInput && (kMode == kModeLds || kMode == kModeDense)) {
+    const int32_t table = kMode == kModeDense ? dense_pairs(nr) * 8 : nr * 8;
+    const int32_t off = (table + 15) & ~15;
+    const int32_t room = (A.lds_bytes - off) / (int32_t)sizeof(LabT);
+    const int32_t nmap = A.st->map_n[A.round];
+    nst = room <= 0 ? 0 : (nmap < room ? nmap : room);
+    if (nst > 0) {
+      LabT* dst_l = reinterpret_cast<LabT*>(reinterpret_cast<char*>(smem) + off);
+      stage_map<LabT, kScanBlock>(dst_l, lab, nst);
+      llab = dst_l;  // visible to all after the table initialisation's barrier below
+      lookup = nst == nmap ? 2 : 3;
+    }
   }
 
   unsigned long long* lbest = smem;  // LDS mode
@@ -292,7 +305,8 @@ __global__ void __launch_bounds__(kScanBlock) k_scan(ScanArgs A) {
   };
   // Record loads are unconditional (lanes past the segment's count read its
   // first slot, in bounds, and are masked later) so that no branch makes the
-  // compiler wait for them early.
+  // compiler wait for them early.  A record segment's count is loaded two
+  // segments ahead, so it has arrived when that segment's loads are issued.
   auto load_seg = [&](int32_t s, uint32_t count, uint4* x) {
     const uint64_t base = (uint64_t)s * kSegCap;
     if (kNarrowIn) {
@@ -303,8 +317,7 @@ __global__ void __launch_bounds__(kScanBlock) k_scan(ScanArgs A) {
 #pragma unroll
       for (int k = 0; k < kPerThread; ++k) {
         const uint32_t j = k * kScanBlock + threadIdx.x;
-        ev[k] = 0;
-        if (moved) ev[k] = ld_stream(eseg + (j < count ? j : 0u));
+        ev[k] = moved ? ld_stream(eseg + (j < count ? j : 0u)) : 0u;
       }
       __asm__ __volatile__("" ::: "memory");  // the e loads are issued before the record loads
 #pragma unroll
@@ -330,9 +343,10 @@ __global__ void __launch_bounds__(kScanBlock) k_scan(ScanArgs A) {
     }
   };
   uint4 nx[kPerThread];
-  uint32_t ncount = 0;
+  uint32_t ncount = 0, nncount = 0;
   if ((int32_t)blockIdx.x < A.nseg) {
     ncount = seg_count(blockIdx.x);
+    if (!kFromInput && (int32_t)(blockIdx.x + gridDim.x) < A.nseg) nncount = seg_count(blockIdx.x + gridDim.x);
     load_seg(blockIdx.x, ncount, nx);
   }
   for (int32_t s = blockIdx.x; s < A.nseg; s += gridDim.x) {
@@ -357,36 +371,47 @@ __global__ void __launch_bounds__(kScanBlock) k_scan(ScanArgs A) {
         load_seg(sn, ncount, nx);
       }
     } else {
-      ncount = seg_count(sn);
+      // the next segment's count arrived during the last segment; the one
+      // after it is loaded now
+      ncount = has_next ? nncount : count;
+      const int64_t snn = (int64_t)s + 2 * (int64_t)gridDim.x;
+      nncount = snn < A.nseg ? seg_count((int32_t)snn) : 0u;
     }
     __asm__ __volatile__("" ::: "memory");
+    // this round's labels of both ends (lanes past the count look up entry 0)
     int32_t ga[kPerThread], gb[kPerThread];
 #pragma unroll
     for (int k = 0; k < kPerThread; ++k) {
-      const uint32_t j = k * kScanBlock + threadIdx.x;
-      const bool in = j < count;
-      int32_t a = (int32_t)cx[k].x, b = (int32_t)cx[k].y;
-      if (kNarrowIn) {
-        a = (int32_t)(cx[k].x & 0xFFFFu);
-        b = (int32_t)(cx[k].x >> 16);
-      }
-      if (kFromInput && !kCompact) {
-        if (in && ((uint32_t)a >= (uint32_t)A.n || (uint32_t)b >= (uint32_t)A.n)) {
+      const bool in = k * kScanBlock + threadIdx.x < count;
+      ga[k] = in ? (int32_t)(kNarrowIn ? cx[k].x & 0xFFFFu : cx[k].x) : 0;
+      gb[k] = in ? (int32_t)(kNarrowIn ? cx[k].x >> 16 : cx[k].y) : 0;
+    }
+    if (kFromInput && !kCompact) {
+#pragma unroll
+      for (int k = 0; k < kPerThread; ++k) {
+        if ((uint32_t)ga[k] >= (uint32_t)A.n || (uint32_t)gb[k] >= (uint32_t)A.n) {
           bad = true;
-          a = b = -1;  // dropped
+          ga[k] = gb[k] = -1;  // dropped
         }
-      } else if (!kFromInput && (kMode == kModeLds || kMode == kModeDense) && llab != nullptr) {
-        a = (int32_t)llab[in ? a : 0] - 1;
-        b = (int32_t)llab[in ? b : 0] - 1;
-      } else {
-        // lanes past the count look up entry 0
-        const int32_t va = lab[in ? a : 0];
-        const int32_t vb = lab[in ? b : 0];
-        a = va;
-        b = vb;
       }
-      ga[k] = a;
-      gb[k] = b;
+    } else if (lookup == 2) {
+#pragma unroll
+      for (int k = 0; k < kPerThread; ++k) {
+        ga[k] = (int32_t)llab[ga[k]] - 1;
+        gb[k] = (int32_t)llab[gb[k]] - 1;
+      }
+    } else if (lookup == 3) {
+#pragma unroll
+      for (int k = 0; k < kPerThread; ++k) {
+        ga[k] = ga[k] < nst ? (int32_t)llab[ga[k]] - 1 : lab[ga[k]];
+        gb[k] = gb[k] < nst ? (int32_t)llab[gb[k]] - 1 : lab[gb[k]];
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < kPerThread; ++k) {
+        ga[k] = lab[ga[k]];
+        gb[k] = lab[gb[k]];
+      }
     }
     __asm__ __volatile__("" ::: "memory");
     if (!kFromInput) load_seg(sn, ncount, nx);
@@ -414,11 +439,12 @@ __global__ void __launch_bounds__(kScanBlock) k_scan(ScanArgs A) {
     // survivors of this segment, in input order: record j = k * kScanBlock +
     // threadIdx.x, so the order is (slot k, wave, lane); rank inside the
     // wave's slot now, offsets of the (k, wave) groups after the barrier
+    // (ranks only when the survivors move)
     uint32_t my_off[kPerThread];
 #pragma unroll
     for (int k = 0; k < kPerThread; ++k) {
       const uint64_t mask = __ballot(live[k]);
-      my_off[k] = (uint32_t)__popcll(mask & lt);
+      my_off[k] = moved ? (uint32_t)__popcll(mask & lt) : 0u;
       if (lane_id() == 0) slot_tot[k * kScanWaves + wave] = (uint32_t)__popcll(mask);
     }
 
@@ -450,8 +476,10 @@ __global__ void __launch_bounds__(kScanBlock) k_scan(ScanArgs A) {
       }
       seg_tot = __shfl(x, 63, 64);
       const uint32_t excl = x - v;
+      if (moved) {
 #pragma unroll
-      for (int k = 0; k < kPerThread; ++k) my_off[k] += __shfl(excl, k * kScanWaves + wave, 64);
+        for (int k = 0; k < kPerThread; ++k) my_off[k] += __shfl(excl, k * kScanWaves + wave, 64);
+      }
     }
     // Keys: the weight in the high half; in the low half the edge's index
     // (round 0, and a dense round that reads the caller's arrays) or the
@@ -478,6 +506,19 @@ __global__ void __launch_bounds__(kScanBlock) k_scan(ScanArgs A) {
         } else if (kMode == kModeGlobal) {
           lower_global(A.best, a, key[k]);
           lower_global(A.best, b, key[k]);
+        }
+      }
+    }
+    if (inplace) {
+      // every record keeps its position and gets this round's labels (an
+      // internal one gets labels 0, 0: internal again in every later round)
+      unsigned long long* nrec_out = reinterpret_cast<unsigned long long*>(A.rec) + 2 * base;
+#pragma unroll
+      for (int k = 0; k < kPerThread; ++k) {
+        const uint32_t j = k * kScanBlock + threadIdx.x;
+        if (j < count) {
+          const unsigned long long lb = live[k] ? (unsigned long long)(r[k].x | (r[k].y << 16)) : 0ull;
+          st_stream(lb | ((unsigned long long)r[k].z << 32), nrec_out + j);
         }
       }
     }
@@ -1136,7 +1177,7 @@ __global__ void __launch_bounds__(kBlock) k_hook(int round, const uint4* __restr
   if (nr <= 1 && round > 0) return;
   if (st->dense_at == round) return;  // the dense finish ended the solve
   const bool narrow = nr <= kNarrowMax;        // the records at the keys' positions are narrow
-  const bool keep = st->keep[round] != 0;      // ... and hold the labels of the round that wrote them
+  const bool keep = st->keep[round] == kKeepRecords;  // ... and hold the labels of the round that wrote them
   const int32_t* map = labpool + st->map_off[round];
   uint32_t sel = 0;
   unsigned long long wsum = 0;
@@ -1232,30 +1273,32 @@ __global__ void __launch_bounds__(kBlock) k_compress(int round, int32_t* parent,
 // components enter round r + 1): the records it reads (`stream_next`), the
 // map from the labels in the records to round r + 1's (round r's own label
 // map if round r rewrote the records, else that map composed with round r's,
-// which k_relabel / k_round_tail write), and whether round r + 1 keeps its
-// records in place: only narrow records, only while fewer than
-// 1/kKeepDeadDen of the records round r read were dead, and only if every
-// LDS or dense launch of round r + 2 (bound n_next / 2) can stage the
-// composed map it would then read.
+// which k_relabel / k_round_tail write), and what round r + 1 does with its
+// records: narrow records, fewer than 1/kKeepDeadDen of the records round r
+// read dead there, are kept in place if every LDS or dense launch of round
+// r + 2 (bound n_next / 2) can stage the composed map it would then read,
+// else relabelled in place; otherwise the survivors are compacted.
 __device__ __forceinline__ void next_stream_state(DevState* st, int round, int32_t nr, int32_t n_next, int64_t live,
                                                   int64_t stream_next) {
   const int64_t read = st->stream[round];
   st->stream[round + 1] = stream_next;
-  if (st->keep[round]) {
+  if (st->keep[round] == kKeepRecords) {
     st->map_off[round + 1] = st->cmap_off + (int64_t)((round + 1) & 1) * kNarrowMax;
     st->map_n[round + 1] = st->map_n[round];
   } else {
     st->map_off[round + 1] = st->lab_off[round];
     st->map_n[round + 1] = nr;
   }
-  bool keep = round >= 1 && nr <= kNarrowMax && (int64_t)kKeepDeadDen * (read - live) < read;
-  if (keep) {
+  int what = kMoveRecords;
+  if (round >= 1 && nr <= kNarrowMax && (int64_t)kKeepDeadDen * (read - live) < read) {
     const int64_t bound = n_next / 2;
     const int modes = scan_modes(bound, false, 3, st->dense_limit, true, kBucketMaxComponents);
+    bool fits = true;
     for (int mode : {kModeLds, kModeDense})
-      if ((modes >> mode) & 1) keep = keep && map_fits_lds(mode, bound, st->dense_limit, st->map_n[round + 1]);
+      if ((modes >> mode) & 1) fits = fits && map_fits_lds(mode, bound, st->dense_limit, st->map_n[round + 1]);
+    what = fits ? kKeepRecords : kRelabelRecords;
   }
-  st->keep[round + 1] = keep;
+  st->keep[round + 1] = what;
 }
 
 // One workgroup of 1024 threads.  Exclusive scan of rootcnt[0..W) into
@@ -1454,7 +1497,7 @@ __global__ void __launch_bounds__(kBlock) k_relabel(int round, const int32_t* __
   };
   for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < nr; c += stride)
     labpool[off + c] = label_of((int32_t)c);
-  if (st->keep[round]) {
+  if (st->keep[round] == kKeepRecords) {
     const int32_t* mi = labpool + st->map_off[round];
     int32_t* mo = labpool + st->map_off[round + 1];
     const int32_t ne = st->map_n[round];
@@ -1596,7 +1639,7 @@ __global__ void __launch_bounds__(kTailThreads) k_round_tail(int round, int32_t 
         e[q] = ne[narrow_e_index(pos)];
         ab[q] = make_uint2((uint32_t)(x & 0xFFFFu), (uint32_t)((x >> 16) & 0xFFFFu));
       }
-      if (st->keep[round]) {
+      if (st->keep[round] == kKeepRecords) {
         const int32_t* map = labpool + st->map_off[round];
 #pragma unroll
         for (int q = 0; q < kTailPer; ++q) ab[q] = make_uint2((uint32_t)map[ab[q].x], (uint32_t)map[ab[q].y]);
@@ -1705,7 +1748,7 @@ __global__ void __launch_bounds__(kTailThreads) k_round_tail(int round, int32_t 
       labpool[off + c] = r < 0 ? -1 : par[r];
     }
   }
-  if (st->keep[round]) {
+  if (st->keep[round] == kKeepRecords) {
     // the records stay as they are: the next round's map is this round's
     // map composed with the labels just given
     const int32_t* mi = labpool + st->map_off[round];
