@@ -128,21 +128,41 @@ def traffic_for(kernel: str):
     return None if k is None else k["traffic_bytes_mean"]
 
 
+def host_info():
+    """The host the CPU legs ran on: CPU model name and logical processor count."""
+    try:
+        model = next((ln.split(":", 1)[1].strip() for ln in open("/proc/cpuinfo") if ln.startswith("model name")), "")
+    except OSError:
+        model = ""
+    return {"model": model, "nproc": os.cpu_count() or 1}
+
+
 def cpu_baseline(g, budget_s: float):
-    """The oracle (Kruskal, plain C, one thread) timed on the host on the same graph."""
+    """The oracle timed on the host on the same graph, one thread: Kruskal (the
+    headline figure) and the paper's sequential Boruvka, each for about half
+    the budget."""
     import oracle
 
     oracle.default()
-    reps, t_total = 0, 0.0
-    while reps == 0 or (t_total < budget_s and reps < 50):
-        t0 = time.perf_counter()
-        res = oracle.kruskal(g.n, g.src, g.dst, g.w)
-        t_total += time.perf_counter() - t0
-        reps += 1
-    per = t_total / reps
+
+    def timed(fn, budget):
+        reps, t_total, res = 0, 0.0, None
+        while reps == 0 or (t_total < budget and reps < 50):
+            t0 = time.perf_counter()
+            res = fn()
+            t_total += time.perf_counter() - t0
+            reps += 1
+        return t_total / reps, reps, res
+
+    per, reps, res = timed(lambda: oracle.kruskal(g.n, g.src, g.dst, g.w), budget_s / 2)
+    per_b, reps_b, res_b = timed(lambda: oracle.boruvka(g.n, g.src, g.dst, g.w), budget_s / 2)
+    assert res_b.total == res.total
     return {"value": g.m / per, "unit": "edges/s", "cores": 1, "kind": "oracle",
             "sample": f"{reps} full Kruskal solve(s) of the same {g.m}-edge graph on one host thread "
-                      f"({per * 1e3:.1f} ms each)", "ms_per_solve": per * 1e3}, res
+                      f"({per * 1e3:.1f} ms each)", "ms_per_solve": per * 1e3,
+            "boruvka": {"value": g.m / per_b, "unit": "edges/s", "ms_per_solve": per_b * 1e3,
+                        "sample": f"{reps_b} full sequential Boruvka solve(s), one host thread"},
+            "host": host_info()}, res
 
 
 def cpu_baseline_batched(b, budget_s: float):
@@ -203,6 +223,20 @@ def bench_batched(args, dev):
         step()
     torch.cuda.synchronize()
     ms_per_step = (time.perf_counter() - t0) * 1e3 / args.steps
+    # the device time of one call (every graph of this batch is solved by
+    # the one-launch k_batch_solve), HIP events on the solve's stream
+    ev = []
+    for _ in range(args.steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        step()
+        e1.record(stream)
+        ev.append((e0, e1))
+    torch.cuda.synchronize()
+    dev_ms = sum(a.elapsed_time(c) for a, c in ev) / len(ev)
+    # algorithmic bytes of a batch: every edge read once (12 B) and its flag
+    # written (1 B), a total and a status per graph (12 B)
+    batch_bytes = 13.0 * m + 12.0 * Gn
     got = in_mst.cpu().numpy()
     got_tot = total.view(torch.int64).cpu().numpy()
     got_st = status.cpu().numpy()
@@ -240,7 +274,12 @@ def bench_batched(args, dev):
         "config": {"workload": f"{args.workload}: {WORKLOAD_TEXT[args.workload]}", "graphs": Gn,
                    "sum_n": int(b.vertex_offsets[-1]), "sum_m": m, "leg": "batched solves",
                    "edges_per_s": m / (ms_per_step * 1e-3)},
-        "roofline": None,
+        "roofline": {"bound": "hbm", "achieved": batch_bytes / (dev_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": batch_bytes / (dev_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_batch_solve", "device_ms_per_call": dev_ms,
+                     "alg_bytes": batch_bytes,
+                     "alg_bytes_model": "one pass over the batch: 12 B per edge read, 1 B per edge written, "
+                                        "12 B per graph"},
         "per_graph_path": {"value": Gn / per_graph_s, "unit": "solves/s", "ms_per_batch": per_graph_s * 1e3,
                            "bit_exact_vs_batched": same},
         "speedup_vs_per_graph": (per_graph_s * 1e3) / ms_per_step,
@@ -523,6 +562,7 @@ def main() -> int:
         step()
     torch.cuda.synchronize()
     prof = P.mst_profile_read()
+    prof_rounds = P.mst_profile_read_rounds()
     P.mst_profile_enable(False)
 
     # cold solves: 1 GiB written before each (evicts the 256 MB infinity cache)
@@ -560,6 +600,37 @@ def main() -> int:
     scan_ms = sum(kernels[k]["ms_total"] for k in step_kinds)
     scan_bytes = sum(prof[k][2] for k in scan_kinds)
 
+    # per round: every kernel's mean duration per step, its algorithmic bytes
+    # and fraction of the HBM peak (launches that returned at once included)
+    per_round = []
+    for r, row in sorted(prof_rounds.items()):
+        entry = {"round": r}
+        if r < len(stats):
+            entry.update({"components": int(stats[r][0]), "live_edges": int(stats[r][1]),
+                          "edges_added": int(stats[r][2])})
+        ks = {}
+        for name, (ms, n_launch, b) in row.items():
+            us = ms * 1e3 / args.steps
+            ks[name] = {"us_per_step": us, "launches_per_step": n_launch / args.steps,
+                        "alg_bytes": b / args.steps,
+                        "frac": (b / args.steps) / (us * 1e-6) / 1e9 / HBM_PEAK_GBS if b and us else None}
+        entry["kernels"] = ks
+        entry["us_per_step"] = sum(v["us_per_step"] for v in ks.values())
+        per_round.append(entry)
+    # the round-0 edge scan with its minima (the scan and the kernel that
+    # finishes its minima): 12 B per edge read + 16 B per vertex
+    bar = None
+    if per_round and per_round[0]["round"] == 0:
+        r0 = per_round[0]["kernels"]
+        parts = [k for k, v in r0.items() if k.startswith("k_scan") and v["alg_bytes"]]
+        parts += [k for k in ("k_bucket_min", "k_slab_min") if k in r0]
+        us0 = sum(r0[k]["us_per_step"] for k in parts)
+        b0 = 12.0 * g.m + 16.0 * g.n
+        bar = {"step": "round-0 edge scan and its minima (" + " + ".join(parts) + ")", "alg_bytes": b0,
+               "us": us0, "achieved_GBs": b0 / (us0 * 1e-6) / 1e9 if us0 else None,
+               "frac": b0 / (us0 * 1e-6) / 1e9 / HBM_PEAK_GBS if us0 else None,
+               "us_at_40pct_of_peak": b0 / (0.4 * HBM_PEAK_GBS * 1e9) * 1e6}
+
     out = {
         "metric": METRIC,
         "value": g.m / (ms_per_step * 1e-3),
@@ -582,6 +653,8 @@ def main() -> int:
         "kernels": kernels,
         "scan_family": {"ms_per_step": scan_ms / args.steps, "alg_bytes_per_step": scan_bytes / args.steps,
                         "achieved_GBs": (scan_bytes / (scan_ms * 1e-3) / 1e9) if scan_ms else 0.0},
+        "round0_scan_step": bar,
+        "per_round": per_round,
         "cold_ms_per_step": {"median": statistics.median(cold) if cold else None, "all": cold},
         "total_weight": res_total,
     }

@@ -221,6 +221,18 @@ int mst_profile_read(double* out_ms, int64_t* out_launches, double* out_bytes, i
 const char* mst_profile_kernel_name(int kind);
 
 /*
+ * The same counters split by Boruvka round (Section 2.1's while loop; the
+ * round a launch was enqueued for).  Row r of each host array holds K
+ * entries (K = the kernel count mst_profile_read returns), kernel i at
+ * [r * K + i], for rounds r < min(max_rounds, 41).  k_bucket_min launches
+ * are credited with 16 B per live edge of their round (two 8-byte offers
+ * read) plus 8 B per component (its minimum written).
+ *   out_ms, out_launches, out_bytes  host arrays of max_rounds * K entries
+ * Returns K, or MSTX_ERR_INVALID_ARG.
+ */
+int mst_profile_read_rounds(double* out_ms, int64_t* out_launches, double* out_bytes, int32_t max_rounds);
+
+/*
  * Frees the workspace cached for (current device, stream), after the stream's
  * work has finished.  For memory-budgeted callers (a server that retires a
  * stream).  Must not run while another thread has a call in flight on the

@@ -31,6 +31,7 @@ from .binding import (  # noqa: F401
     mst_last_round_stats,
     mst_profile_enable,
     mst_profile_read,
+    mst_profile_read_rounds,
     mst_select_min_edges,
     mst_set_bucket_limit,
     mst_set_dense_limit,

@@ -29,7 +29,7 @@ EXPORTS = ("mst_solve", "mst_solve_batched", "mst_batched_workspace_bytes", "mst
            "mst_last_round_stats", "mst_workspace_bytes", "mst_status_string", "mst_profile_enable",
            "mst_profile_read", "mst_profile_kernel_name", "mst_workspace_release", "mst_set_dense_limit", "mst_set_small_limit",
            "mst_set_tail_limit", "mst_set_mid_limit", "mst_set_bucket_limit", "mst_csr_to_edges",
-           "mst_solve_noalloc")
+           "mst_solve_noalloc", "mst_profile_read_rounds")
 
 _lib = None
 
@@ -84,6 +84,8 @@ def load_library(path: str = LIB_PATH):
     lib.mst_set_mid_limit.restype = ctypes.c_int32
     lib.mst_set_bucket_limit.argtypes = [ctypes.c_int32]
     lib.mst_set_bucket_limit.restype = ctypes.c_int32
+    lib.mst_profile_read_rounds.argtypes = [p, p, p, i32]
+    lib.mst_profile_read_rounds.restype = ctypes.c_int
     lib.mst_profile_kernel_name.argtypes = [ctypes.c_int]
     lib.mst_profile_kernel_name.restype = ctypes.c_char_p
     _lib = lib
@@ -361,6 +363,31 @@ def mst_profile_read() -> dict:
         raise MstxError(k)
     k = min(k, cap)
     return {lib.mst_profile_kernel_name(i).decode(): (float(ms[i]), int(n[i]), float(b[i])) for i in range(k)}
+
+
+def mst_profile_read_rounds(max_rounds: int = 41) -> dict:
+    """{round: {kernel: (total ms, launches, algorithmic bytes)}} accumulated while
+    profiling is enabled (kernels with no launch in a round are left out)."""
+    import numpy as np
+    lib = load_library()
+    K = lib.mst_profile_read_rounds(None, None, None, 0)
+    if K < 0:
+        raise MstxError(K)
+    ms = np.zeros(max_rounds * K, np.float64)
+    n = np.zeros(max_rounds * K, np.int64)
+    b = np.zeros(max_rounds * K, np.float64)
+    rc = lib.mst_profile_read_rounds(ms.ctypes.data_as(ctypes.c_void_p), n.ctypes.data_as(ctypes.c_void_p),
+                                     b.ctypes.data_as(ctypes.c_void_p), max_rounds)
+    if rc < 0:
+        raise MstxError(rc)
+    names = [lib.mst_profile_kernel_name(i).decode() for i in range(K)]
+    out = {}
+    for r in range(max_rounds):
+        row = {names[i]: (float(ms[r * K + i]), int(n[r * K + i]), float(b[r * K + i]))
+               for i in range(K) if n[r * K + i]}
+        if row:
+            out[r] = row
+    return out
 
 
 class Solution(NamedTuple):

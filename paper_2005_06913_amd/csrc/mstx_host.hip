@@ -256,6 +256,20 @@ struct Profile {
   double ms[kKinds] = {};
   int64_t launches[kKinds] = {};
   double bytes[kKinds] = {};
+  // the same per round of the solve (round index as the launch was enqueued)
+  double rms[kMaxRounds + 1][kKinds] = {};
+  int64_t rlaunches[kMaxRounds + 1][kKinds] = {};
+  double rbytes[kMaxRounds + 1][kKinds] = {};
+  void clear() {
+    for (int k = 0; k < kKinds; ++k) {
+      ms[k] = bytes[k] = 0.0;
+      launches[k] = 0;
+      for (int r = 0; r <= kMaxRounds; ++r) {
+        rms[r][k] = rbytes[r][k] = 0.0;
+        rlaunches[r][k] = 0;
+      }
+    }
+  }
 };
 Profile g_prof;
 
@@ -299,17 +313,26 @@ struct LaunchTimer {
     if (slot >= 0) (void)hipEventRecord(pending[slot].b, s);
   }
   // After the stream is synchronised.  chosen[r] = mode that ran in round r,
-  // bytes[r] = algorithmic bytes of round r's scan; rounds >= nrounds were idle.
-  void commit(int nrounds, const int* chosen, const double* bytes) {
+  // bytes[r] = algorithmic bytes of round r's scan, bmin[r] those of its
+  // bucket minima; rounds >= nrounds were idle.
+  void commit(int nrounds, const int* chosen, const double* bytes, const double* bmin) {
     if (!on) return;
     std::lock_guard<std::mutex> g(g_prof.mu);
     for (const auto& p : pending) {
       float ms = 0.f;
       if (hipEventElapsedTime(&ms, p.a, p.b) != hipSuccess) continue;
+      double b = 0.0;
+      if (p.round < nrounds && p.mode == chosen[p.round]) {
+        if (p.kind < kScanKinds) b = bytes[p.round];
+        else if (p.kind == kBucketMin) b = bmin[p.round];
+      }
       g_prof.ms[p.kind] += ms;
       g_prof.launches[p.kind] += 1;
-      if (p.kind < kScanKinds && p.round < nrounds && p.mode == chosen[p.round])
-        g_prof.bytes[p.kind] += bytes[p.round];
+      g_prof.bytes[p.kind] += b;
+      const int r = p.round < 0 ? 0 : (p.round > kMaxRounds ? kMaxRounds : p.round);
+      g_prof.rms[r][p.kind] += ms;
+      g_prof.rlaunches[r][p.kind] += 1;
+      g_prof.rbytes[r][p.kind] += b;
     }
     pending.clear();
   }
@@ -616,15 +639,17 @@ struct RoundLoop {
     RoundStats& T = t_last_stats;
     T.rounds = rounds;
     int chosen[kMaxRounds + 1];
-    double bytes[kMaxRounds + 1];
+    double bytes[kMaxRounds + 1], bmin[kMaxRounds + 1];
     for (int r = 0; r < rounds; ++r) {
       T.v[3 * r + 0] = nr_of[r];
       T.v[3 * r + 1] = rec[r].live;
       T.v[3 * r + 2] = rec[r].sel;
       chosen[r] = pick_mode(nr_of[r], S.launched[r]);
       bytes[r] = round_scan_bytes(rec, nr_of, r, m);
+      // bucket minima: two 8-byte offers per live edge read, one 8-byte minimum per component written
+      bmin[r] = 16.0 * (double)rec[r].live + 8.0 * (double)nr_of[r];
     }
-    t_timer.commit(rounds, chosen, bytes);
+    t_timer.commit(rounds, chosen, bytes, bmin);
   }
 };
 
@@ -710,7 +735,7 @@ int solve_small_locked(DeviceCache* dc, int32_t n, int64_t m, const int32_t* src
   const int rows = (int)std::min<int64_t>(std::max<int64_t>(st[0], 0), kMaxRounds + 1);
   // algorithmic bytes: every round reads the 12-byte edges once, plus one
   // final round that finds nothing to add
-  T.commit(0, nullptr, nullptr);
+  T.commit(0, nullptr, nullptr, nullptr);
   if (T.on) {
     std::lock_guard<std::mutex> g(g_prof.mu);
     g_prof.bytes[kSmallSolve] += 12.0 * (double)m * (double)(rows + 1);
@@ -1275,13 +1300,7 @@ int mst_profile_enable(int enable) {
   std::lock_guard<std::mutex> g(mstx::g_prof.mu);
   const int was = mstx::g_prof.enabled ? 1 : 0;
   mstx::g_prof.enabled = enable != 0;
-  if (enable) {
-    for (int k = 0; k < mstx::kKinds; ++k) {
-      mstx::g_prof.ms[k] = 0.0;
-      mstx::g_prof.launches[k] = 0;
-      mstx::g_prof.bytes[k] = 0.0;
-    }
-  }
+  if (enable) mstx::g_prof.clear();
   return was;
 }
 
@@ -1294,6 +1313,19 @@ int mst_profile_read(double* out_ms, int64_t* out_launches, double* out_bytes, i
     out_launches[i] = mstx::g_prof.launches[i];
     out_bytes[i] = mstx::g_prof.bytes[i];
   }
+  return mstx::kKinds;
+}
+
+int mst_profile_read_rounds(double* out_ms, int64_t* out_launches, double* out_bytes, int32_t max_rounds) {
+  if (max_rounds < 0 || (max_rounds > 0 && (!out_ms || !out_launches || !out_bytes))) return MSTX_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> g(mstx::g_prof.mu);
+  const int rows = std::min<int>(max_rounds, mstx::kMaxRounds + 1);
+  for (int r = 0; r < rows; ++r)
+    for (int k = 0; k < mstx::kKinds; ++k) {
+      out_ms[(size_t)r * mstx::kKinds + k] = mstx::g_prof.rms[r][k];
+      out_launches[(size_t)r * mstx::kKinds + k] = mstx::g_prof.rlaunches[r][k];
+      out_bytes[(size_t)r * mstx::kKinds + k] = mstx::g_prof.rbytes[r][k];
+    }
   return mstx::kKinds;
 }
 

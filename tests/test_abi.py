@@ -224,3 +224,18 @@ def test_noalloc_scratch_limit_on_host(lib):
     for n, m in ((1 << 20, 1 << 22), (1 << 18, 5 << 20)):
         assert B.mst_workspace_bytes(n, m) + 2048 <= 256 << 20
     assert "256 MiB" in B.mst_status_string(B.MSTX_ERR_SCRATCH_LIMIT)
+
+
+def test_profile_read_rounds_host(lib):
+    """Per-round profile counters: host arrays only, no device call."""
+    from paper_2005_06913_amd import binding as B
+    K = lib.mst_profile_read_rounds(None, None, None, 0)
+    names = [lib.mst_profile_kernel_name(i).decode() for i in range(K)]
+    assert K > 0 and all(names)
+    assert lib.mst_profile_read_rounds(None, None, None, 3) == B.MSTX_ERR_INVALID_ARG
+    assert lib.mst_profile_read_rounds(None, None, None, -1) == B.MSTX_ERR_INVALID_ARG
+    was = B.mst_profile_enable(True)  # zeroes the counters
+    try:
+        assert B.mst_profile_read_rounds() == {}
+    finally:
+        B.mst_profile_enable(was)
