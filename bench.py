@@ -196,10 +196,13 @@ def bench_batched(args, dev):
     from paper_2005_06913_amd import graphgen as G
 
     P.load_library()
+    from paper_2005_06913_amd import autotune
     log(f"[bench] generating {args.workload}")
     b = G.batch(**BATCHES[args.workload])
     m = int(b.edge_offsets[-1])
     Gn = b.num_graphs
+    tuned = autotune.tuned_batched(Gn, m)
+    knobs = tuned.__enter__()
     src = torch.from_numpy(b.src).to(dev)
     dst = torch.from_numpy(b.dst).to(dev)
     w = torch.from_numpy(b.w).to(dev)
@@ -241,6 +244,7 @@ def bench_batched(args, dev):
     got_tot = total.view(torch.int64).cpu().numpy()
     got_st = status.cpu().numpy()
 
+    tuned.__exit__(None, None, None)
     # plain path: one mst_solve per graph, same device arrays
     log("[bench] per-graph path")
     one_mst = torch.empty(m, dtype=torch.uint8, device=dev)
@@ -273,6 +277,7 @@ def bench_batched(args, dev):
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {WORKLOAD_TEXT[args.workload]}", "graphs": Gn,
                    "sum_n": int(b.vertex_offsets[-1]), "sum_m": m, "leg": "batched solves",
+                   "knobs": knobs or "library defaults",
                    "edges_per_s": m / (ms_per_step * 1e-3)},
         "roofline": {"bound": "hbm", "achieved": batch_bytes / (dev_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": batch_bytes / (dev_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
@@ -524,8 +529,12 @@ def main() -> int:
     if args.workload == "served":
         return bench_served(args, dev)
     P.load_library()
+    from paper_2005_06913_amd import autotune
     log(f"[bench] generating {args.workload}")
     g = G.workload(args.workload)
+    # the autotuner's settings for this graph class on this device, if any
+    tuned = autotune.tuned_single(g.n, g.m)
+    knobs = tuned.__enter__()
     src = torch.from_numpy(g.src).to(dev)
     dst = torch.from_numpy(g.dst).to(dev)
     w = torch.from_numpy(g.w).to(dev)
@@ -578,6 +587,7 @@ def main() -> int:
         e1.synchronize()
         cold.append(e0.elapsed_time(e1))
     del flush
+    tuned.__exit__(None, None, None)
     res_total = int(total.view(torch.int64).item())
 
     # dominant kernel by total time; its algorithmic bytes per launch / mean duration
@@ -645,7 +655,7 @@ def main() -> int:
         "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {WORKLOAD_TEXT[args.workload]}", "n": g.n, "m": g.m,
-                   "leg": "single graph", "rounds": int(len(stats)),
+                   "leg": "single graph", "rounds": int(len(stats)), "knobs": knobs or "library defaults",
                    "round_stats": stats.tolist()},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for(bound_kernel),

@@ -313,6 +313,17 @@ int32_t mst_set_tail_limit(int32_t limit);
  */
 int32_t mst_set_bucket_limit(int32_t limit);
 
+/*
+ * Occupancy of the LDS-mode edge scans (Section 2.1's edge loop with the
+ * per-component minima in LDS): how many scan workgroups share a compute
+ * unit.  0 (the default) chooses from the scan's LDS size (at most 4); 1..8
+ * asks for that many, as far as 160 KB of LDS per compute unit holds them.
+ * The results are the same for every value.  wg_per_cu < 0 only queries.
+ * Returns the previous value.  Process-wide; read when each round is
+ * enqueued.  A tuning knob (paper_2005_06913_amd/autotune.py sets it).
+ */
+int32_t mst_set_scan_occupancy(int32_t wg_per_cu);
+
 /* Static description of a status code. */
 const char* mst_status_string(int status);
 

@@ -36,6 +36,7 @@ from .binding import (  # noqa: F401
     mst_set_bucket_limit,
     mst_set_dense_limit,
     mst_set_mid_limit,
+    mst_set_scan_occupancy,
     mst_set_small_limit,
     mst_set_tail_limit,
     mst_solve,

@@ -29,7 +29,7 @@ EXPORTS = ("mst_solve", "mst_solve_batched", "mst_batched_workspace_bytes", "mst
            "mst_last_round_stats", "mst_workspace_bytes", "mst_status_string", "mst_profile_enable",
            "mst_profile_read", "mst_profile_kernel_name", "mst_workspace_release", "mst_set_dense_limit", "mst_set_small_limit",
            "mst_set_tail_limit", "mst_set_mid_limit", "mst_set_bucket_limit", "mst_csr_to_edges",
-           "mst_solve_noalloc", "mst_profile_read_rounds")
+           "mst_solve_noalloc", "mst_profile_read_rounds", "mst_set_scan_occupancy")
 
 _lib = None
 
@@ -82,6 +82,8 @@ def load_library(path: str = LIB_PATH):
     lib.mst_set_tail_limit.restype = ctypes.c_int32
     lib.mst_set_mid_limit.argtypes = [ctypes.c_int32]
     lib.mst_set_mid_limit.restype = ctypes.c_int32
+    lib.mst_set_scan_occupancy.argtypes = [ctypes.c_int32]
+    lib.mst_set_scan_occupancy.restype = ctypes.c_int32
     lib.mst_set_bucket_limit.argtypes = [ctypes.c_int32]
     lib.mst_set_bucket_limit.restype = ctypes.c_int32
     lib.mst_profile_read_rounds.argtypes = [p, p, p, i32]
@@ -153,6 +155,12 @@ def mst_set_bucket_limit(limit: int) -> int:
     (0: never bucket mode; clamped to 16760832; negative: query).  Returns the
     previous limit."""
     return int(load_library().mst_set_bucket_limit(int(limit)))
+
+
+def mst_set_scan_occupancy(wg_per_cu: int) -> int:
+    """Set how many LDS-mode scan workgroups share a compute unit (0: chosen from
+    the LDS size; negative: query).  Returns the previous value."""
+    return int(load_library().mst_set_scan_occupancy(int(wg_per_cu)))
 
 
 class bucket_limit:

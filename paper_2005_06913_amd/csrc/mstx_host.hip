@@ -129,6 +129,10 @@ std::atomic<int> g_tail_limit{kTailMax};
 // bucket mode; above it (and above the LDS range) the filtered global atomics
 // of GLOBAL mode.  mst_set_bucket_limit() changes it.
 std::atomic<int64_t> g_bucket_limit{kBucketMaxComponents};
+// Workgroups per CU of an LDS-mode scan (0: chosen from its LDS size, at
+// most 4; else this many as far as 160 KB of LDS per CU holds them);
+// mst_set_scan_occupancy() changes it.
+std::atomic<int> g_scan_occupancy{0};
 std::map<std::pair<int, hipStream_t>, std::unique_ptr<DeviceCache>> g_caches;
 
 // Per-round statistics of the calling thread's last single-graph solve
@@ -422,7 +426,10 @@ int enqueue_scan(Solve& S, int r, int stage, int64_t bound, bool exact, hipError
       if (mode == kModeDense) {
         grid = std::min(S.L.nseg, cus);
       } else {
-        const int per_cu = (int)std::max<int64_t>(1, std::min<int64_t>(4, 65536 / ((int64_t)lds + 1024)));
+        const int occ = g_scan_occupancy.load();
+        const int64_t fit = (int64_t)(160 * 1024) / ((int64_t)lds + 1024);  // LDS of one CU
+        const int per_cu = (int)std::max<int64_t>(
+            1, occ > 0 ? std::min<int64_t>(occ, fit) : std::min<int64_t>(4, 65536 / ((int64_t)lds + 1024)));
         grid = std::min(S.L.nseg, cus * per_cu);
       }
     } else if (mode == kModeBucket) {
@@ -1380,6 +1387,11 @@ int32_t mst_set_tail_limit(int32_t limit) {
 int32_t mst_set_bucket_limit(int32_t limit) {
   if (limit < 0) return (int32_t)mstx::g_bucket_limit.load();
   return (int32_t)mstx::g_bucket_limit.exchange(std::min<int64_t>(limit, mstx::kBucketMaxComponents));
+}
+
+int32_t mst_set_scan_occupancy(int32_t wg_per_cu) {
+  if (wg_per_cu < 0) return mstx::g_scan_occupancy.load();
+  return mstx::g_scan_occupancy.exchange(std::min<int32_t>(wg_per_cu, 8));
 }
 
 int32_t mst_set_dense_limit(int32_t limit) {
