@@ -103,6 +103,38 @@ int mst_solve_noalloc(int32_t n, int64_t m, const int32_t* src, const int32_t* d
                       uint8_t* out_in_mst, uint64_t* out_total_weight, void* stream);
 
 /*
+ * mst_solve advanced round by round by the caller, for a server that admits
+ * other work at Boruvka round boundaries (Section 2.1's while loop: each
+ * round acts on every component independently, so other graphs' work can
+ * run between two rounds of this one).  Same arguments, results and
+ * statuses as mst_solve; the arrays must stay valid until mst_solve_end.
+ *   mst_solve_begin    checks the arguments, enqueues round 0 on `stream`
+ *                      and returns at once with *out_handle set (a graph that
+ *                      needs no rounds, m = 0 or the one-workgroup path, is
+ *                      solved before it returns).  At most one stepwise
+ *                      solve per (device, stream) at a time (another returns
+ *                      MSTX_ERR_INVALID_ARG); it has its own workspace, so
+ *                      other calls on the stream may run while it is open.
+ *                      Returns a status as mst_solve (negative: no handle).
+ *   mst_solve_advance  non-blocking: takes the records of the rounds that
+ *                      have finished and enqueues the next round (at most
+ *                      two rounds are enqueued at any time); *out_done = 1
+ *                      once the solve has ended.  Work enqueued on `stream`
+ *                      between two calls runs after the rounds enqueued so
+ *                      far.  Returns MSTX_OK or MSTX_ERR_INVALID_ARG.
+ *   mst_solve_end      completes the solve (blocking), frees the handle and
+ *                      returns the final status (as mst_solve).  The round
+ *                      statistics (mst_last_round_stats) go to the thread
+ *                      whose call finished the solve.
+ * Per-launch profiling (mst_profile_enable) does not cover stepwise solves.
+ */
+typedef struct MstxSolve MstxSolve;
+int mst_solve_begin(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, const uint32_t* w,
+                    uint8_t* out_in_mst, uint64_t* out_total_weight, void* stream, MstxSolve** out_handle);
+int mst_solve_advance(MstxSolve* handle, int32_t* out_done);
+int mst_solve_end(MstxSolve* handle);
+
+/*
  * Minimum spanning forests of many independent graphs in one call (the
  * disjoint union of graphs has the union of their forests as its forest, and
  * Boruvka rounds never merge components of different graphs).

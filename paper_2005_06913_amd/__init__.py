@@ -40,7 +40,10 @@ from .binding import (  # noqa: F401
     mst_set_small_limit,
     mst_set_tail_limit,
     mst_solve,
+    mst_solve_advance,
     mst_solve_batched,
+    mst_solve_begin,
+    mst_solve_end,
     mst_solve_noalloc,
     mst_status_string,
     mst_workspace_bytes,

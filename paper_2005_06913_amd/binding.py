@@ -29,7 +29,8 @@ EXPORTS = ("mst_solve", "mst_solve_batched", "mst_batched_workspace_bytes", "mst
            "mst_last_round_stats", "mst_workspace_bytes", "mst_status_string", "mst_profile_enable",
            "mst_profile_read", "mst_profile_kernel_name", "mst_workspace_release", "mst_set_dense_limit", "mst_set_small_limit",
            "mst_set_tail_limit", "mst_set_mid_limit", "mst_set_bucket_limit", "mst_csr_to_edges",
-           "mst_solve_noalloc", "mst_profile_read_rounds", "mst_set_scan_occupancy")
+           "mst_solve_noalloc", "mst_profile_read_rounds", "mst_set_scan_occupancy", "mst_solve_begin",
+           "mst_solve_advance", "mst_solve_end")
 
 _lib = None
 
@@ -52,6 +53,12 @@ def load_library(path: str = LIB_PATH):
     i32, i64, p = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
     lib.mst_solve.argtypes = [i32, i64, p, p, p, p, p, p]
     lib.mst_solve.restype = ctypes.c_int
+    lib.mst_solve_begin.argtypes = [i32, i64, p, p, p, p, p, p, ctypes.POINTER(p)]
+    lib.mst_solve_begin.restype = ctypes.c_int
+    lib.mst_solve_advance.argtypes = [p, ctypes.POINTER(i32)]
+    lib.mst_solve_advance.restype = ctypes.c_int
+    lib.mst_solve_end.argtypes = [p]
+    lib.mst_solve_end.restype = ctypes.c_int
     lib.mst_solve_noalloc.argtypes = [i32, i64, p, p, p, p, p, p]
     lib.mst_solve_noalloc.restype = ctypes.c_int
     lib.mst_solve_batched.argtypes = [i32, p, p, p, p, p, p, p, p, p]
@@ -274,6 +281,35 @@ def mst_solve_noalloc(n, src, dst, w, out_in_mst, out_total_weight, stream=None)
             _dev_ptr(w, torch.uint32, "w", m), _dev_ptr(out_in_mst, torch.uint8, "out_in_mst", m),
             _dev_ptr(out_total_weight, torch.uint64, "out_total_weight", 1))
     return int(load_library().mst_solve_noalloc(int(n), m, *args, _stream_handle(stream)))
+
+
+def mst_solve_begin(n, src, dst, w, out_in_mst, out_total_weight, stream=None):
+    """C ``mst_solve_begin`` (round-by-round solve): returns (status, handle);
+    the handle is None on a negative status.  The tensors must stay alive
+    until ``mst_solve_end``."""
+    import torch
+    m = int(src.numel())
+    args = (_dev_ptr(src, torch.int32, "src", m), _dev_ptr(dst, torch.int32, "dst", m),
+            _dev_ptr(w, torch.uint32, "w", m), _dev_ptr(out_in_mst, torch.uint8, "out_in_mst", m),
+            _dev_ptr(out_total_weight, torch.uint64, "out_total_weight", 1))
+    h = ctypes.c_void_p(0)
+    st = int(load_library().mst_solve_begin(int(n), m, *args, _stream_handle(stream), ctypes.byref(h)))
+    return st, (h if st >= 0 and h.value else None)
+
+
+def mst_solve_advance(handle) -> bool:
+    """C ``mst_solve_advance``: enqueues the next round if the last has finished;
+    True once the solve has ended."""
+    done = ctypes.c_int32(0)
+    rc = load_library().mst_solve_advance(handle, ctypes.byref(done))
+    if rc < 0:
+        raise MstxError(rc)
+    return bool(done.value)
+
+
+def mst_solve_end(handle) -> int:
+    """C ``mst_solve_end``: completes the solve, frees the handle, returns the status."""
+    return int(load_library().mst_solve_end(handle))
 
 
 def _host_offsets(a, name):

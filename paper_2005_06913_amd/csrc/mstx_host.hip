@@ -106,6 +106,13 @@ struct DeviceCache {
   size_t aux_bytes = 0;
   void* small_dev = nullptr;       // single small graph: status + round statistics
   int64_t* small_host = nullptr;   // pinned copy of the same
+  // the stepwise solve of this stream (mst_solve_begin): its own workspace,
+  // records and events, so calls on the stream may run between its rounds
+  void* step_base = nullptr;
+  size_t step_bytes = 0;
+  HostRound* step_rounds = nullptr;
+  hipEvent_t step_ev[kMaxRounds + 1] = {};
+  bool step_active = false;
 };
 
 // One cache per (device, stream): calls on different streams have their own
@@ -670,48 +677,106 @@ hipError_t start_solve(const Solve& S) {
   return e;
 }
 
+// The rounds of one solve as a state machine.  start() enqueues S0 and
+// round 0; advance() takes every round record that has arrived and enqueues
+// the next round as the pipelining allows (round r + 1 is enqueued before
+// round r's record is waited for); with `block` it waits for each record,
+// otherwise it returns at the first record not there yet.  When the solve
+// has ended it drains the stream and publishes the round statistics.
+struct RoundMachine {
+  Solve S;
+  RoundLoop R;
+  HostRound* rec;
+  hipEvent_t* ev;
+  int64_t m;
+  int max_rounds;
+  int r = 0;            // next round whose record is taken
+  int r_enq = 0;        // last round enqueued
+  int32_t n_known = 0;  // exact component count entering round r
+  bool done = false;
+
+  RoundMachine(void* base, int cus, HostRound* rec_, hipEvent_t* ev_, const Layout& L, int32_t n, int64_t m_,
+               const int32_t* src, const int32_t* dst, const uint32_t* w, uint8_t* in_mst, uint64_t* total,
+               hipStream_t s)
+      : S(make_solve(base, cus, rec_, ev_, L, n, m_, src, dst, w, in_mst, total, s)),
+        R(n),
+        rec(rec_),
+        ev(ev_),
+        m(m_),
+        max_rounds(std::min(rounds_bound(n) + 1, kMaxRounds)),
+        n_known(n) {}
+
+  int start() {
+    HIP_OK(start_solve(S));
+    // every record reads "pending" until the device writes it
+    for (int q = 0; q <= kMaxRounds; ++q) rec[q].n_next = kRecordPending;
+    std::atomic_thread_fence(std::memory_order_seq_cst);
+    HIP_OK(enqueue_round(S, 0, S.n, 0, true));
+    return MSTX_OK;
+  }
+
+  int advance(bool block) {
+    while (!done) {
+      if (r >= max_rounds) {
+        done = true;  // round-count watchdog: status stays MSTX_ERR_DEVICE
+        break;
+      }
+      // a round whose scan takes the dense finish (its count n_known is exact
+      // here) is the last one: nothing to enqueue after it
+      const bool final_round = pick_mode(n_known, S.launched[r]) == kModeDense;
+      if (r_enq == r && r + 1 <= kMaxRounds - 1 && !final_round) {
+        // n_known entered round r: the size of the label map round r + 1 reads
+        HIP_OK(enqueue_round(S, r + 1, n_known / 2, n_known, false));
+        r_enq = r + 1;
+      }
+      if (r_enq < r) {
+        done = true;  // never: the round before was final (status stays MSTX_ERR_DEVICE)
+        break;
+      }
+      if (block) {
+        HIP_OK(hipEventSynchronize(ev[r]));
+      } else {
+        const hipError_t q = hipEventQuery(ev[r]);
+        if (q == hipErrorNotReady) {
+          (void)hipGetLastError();
+          return MSTX_OK;
+        }
+        HIP_OK(q);
+      }
+      HostRound M = load_record(rec + r);
+      if (M.n_next == kRecordPending) {
+        // not visible yet: wait for the whole stream, then it must be
+        HIP_OK(hipStreamSynchronize(S.s));
+        M = load_record(rec + r);
+        if (M.n_next == kRecordPending) {
+          done = true;  // status stays MSTX_ERR_DEVICE
+          break;
+        }
+      }
+      R.take(r, M);
+      S.keep[r + 1] = M.keep_next;
+      if (R.done) {
+        done = true;
+        break;
+      }
+      n_known = M.n_next;
+      ++r;
+    }
+    HIP_OK(hipStreamSynchronize(S.s));  // drains the round enqueued after the last one
+    if (R.status >= 0) R.finish(S, rec, m);
+    return MSTX_OK;
+  }
+};
+
 int solve_locked(DeviceCache* dc, const Layout& L, int32_t n, int64_t m, const int32_t* src, const int32_t* dst,
                  const uint32_t* w, uint8_t* in_mst, uint64_t* total, hipStream_t s) {
-  Solve S = make_solve(dc->base, dc->cus, dc->host_rounds, dc->round_ev, L, n, m, src, dst, w, in_mst, total, s);
-  const int max_rounds = std::min(rounds_bound(n) + 1, kMaxRounds);
-
+  RoundMachine M(dc->base, dc->cus, dc->host_rounds, dc->round_ev, L, n, m, src, dst, w, in_mst, total, s);
   t_timer.begin(s);
-  HIP_OK(start_solve(S));
-  // every record reads "pending" until the device writes it
-  for (int r = 0; r <= kMaxRounds; ++r) dc->host_rounds[r].n_next = kRecordPending;
-  std::atomic_thread_fence(std::memory_order_seq_cst);
-  HIP_OK(enqueue_round(S, 0, n, 0, true));
-
-  RoundLoop R(n);
-  int32_t n_known = n;  // exact component count entering round r
-  int r_enq = 0;
-  for (int r = 0; r < max_rounds; ++r) {
-    // a round whose scan takes the dense finish (its count n_known is exact
-    // here) is the last one: nothing to enqueue after it
-    const bool final_round = pick_mode(n_known, S.launched[r]) == kModeDense;
-    if (r_enq == r && r + 1 <= kMaxRounds - 1 && !final_round) {
-      // n_known entered round r: the size of the label map round r + 1 reads
-      HIP_OK(enqueue_round(S, r + 1, n_known / 2, n_known, false));
-      r_enq = r + 1;
-    }
-    if (r_enq < r) break;  // never: the round before was final (status stays MSTX_ERR_DEVICE)
-    HIP_OK(hipEventSynchronize(dc->round_ev[r]));
-    HostRound M = load_record(dc->host_rounds + r);
-    if (M.n_next == kRecordPending) {
-      // not visible yet: wait for the whole stream, then it must be
-      HIP_OK(hipStreamSynchronize(s));
-      M = load_record(dc->host_rounds + r);
-      if (M.n_next == kRecordPending) break;  // status stays MSTX_ERR_DEVICE
-    }
-    R.take(r, M);
-    S.keep[r + 1] = M.keep_next;
-    if (R.done) break;
-    n_known = M.n_next;
-  }
-  HIP_OK(hipStreamSynchronize(s));  // drains the round enqueued after the last one
-  if (R.status < 0) return R.status;
-  R.finish(S, dc->host_rounds, m);
-  return R.status;
+  int rc = M.start();
+  if (rc != MSTX_OK) return rc;
+  rc = M.advance(true);
+  if (rc != MSTX_OK) return rc;
+  return M.R.status;
 }
 
 // A graph of at most kSmallN vertices in one launch (the batched path's
@@ -893,6 +958,97 @@ int solve_noalloc(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, 
   if (R.status < 0) return R.status;
   R.finish(S, h, m);
   return R.status;
+}
+
+// ---------------------------------------------------------- stepwise solve
+
+// A solve advanced round by round by the caller (mst_solve_begin ..
+// mst_solve_end), on the stepwise workspace of its (device, stream): at most
+// one per stream at a time.  Other calls on the stream run between its rounds.
+struct StepSolve {
+  DeviceCache* dc = nullptr;
+  std::unique_ptr<RoundMachine> rm;
+  hipStream_t s = nullptr;
+  int status = MSTX_ERR_DEVICE;
+  bool done = false;
+};
+
+void step_release(StepSolve* h) {
+  if (!h->dc) return;
+  std::lock_guard<std::mutex> g(h->dc->mu);
+  h->dc->step_active = false;
+  h->dc = nullptr;
+}
+
+int step_begin(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, const uint32_t* w, uint8_t* in_mst,
+               uint64_t* total, hipStream_t s, StepSolve** out) {
+  *out = nullptr;
+  t_last_stats.clear();
+  std::unique_ptr<StepSolve> h(new StepSolve());
+  h->s = s;
+  const Layout L = plan(n, m);
+  if (m == 0 || (n > 0 && n <= g_small_limit.load() && m <= kSmallMaxEdges)) {
+    // nothing to step: no edges, or one launch of the one-workgroup solve
+    const int st = solve(n, m, src, dst, w, in_mst, total, s);
+    if (st < 0) return st;
+    h->status = st;
+    h->done = true;
+    *out = h.release();
+    return MSTX_OK;
+  }
+  if (n == 0) return MSTX_ERR_VERTEX_RANGE;
+  if (L.bytes > workspace_limit()) return MSTX_ERR_OUT_OF_MEMORY;
+  DeviceCache* dc = nullptr;
+  {
+    std::unique_lock<std::mutex> lock;
+    int rc = acquire(dc, lock, 0, s);
+    if (rc != MSTX_OK) return rc;
+    if (dc->step_active) return MSTX_ERR_INVALID_ARG;  // one stepwise solve per stream
+    if (!dc->step_rounds) {
+      HIP_OK(hipHostMalloc((void**)&dc->step_rounds, sizeof(HostRound) * (kMaxRounds + 1), hipHostMallocDefault));
+      for (int i = 0; i <= kMaxRounds; ++i)
+        HIP_OK(hipEventCreateWithFlags(&dc->step_ev[i], hipEventDisableTiming | hipEventDisableSystemFence));
+    }
+    if (dc->step_bytes < L.bytes) {
+      if (dc->step_base) {
+        HIP_OK(hipFreeAsync(dc->step_base, s));
+        dc->step_base = nullptr;
+        dc->step_bytes = 0;
+      }
+      if (hipMallocAsync(&dc->step_base, L.bytes, s) != hipSuccess) {
+        (void)hipGetLastError();
+        dc->step_base = nullptr;
+        return MSTX_ERR_OUT_OF_MEMORY;
+      }
+      dc->step_bytes = L.bytes;
+    }
+    dc->step_active = true;
+  }
+  h->dc = dc;
+  h->rm.reset(new RoundMachine(dc->step_base, dc->cus, dc->step_rounds, dc->step_ev, L, n, m, src, dst, w, in_mst,
+                               total, s));
+  t_timer.begin(s);
+  t_timer.on = false;  // per-launch timing covers blocking solves only
+  const int rc = h->rm->start();
+  if (rc != MSTX_OK) {
+    step_release(h.get());
+    return rc;
+  }
+  *out = h.release();
+  return MSTX_OK;
+}
+
+int step_advance(StepSolve* h, bool block) {
+  if (h->done) return MSTX_OK;
+  t_timer.begin(h->s);
+  t_timer.on = false;
+  const int rc = h->rm->advance(block);
+  if (rc != MSTX_OK || h->rm->done) {
+    h->done = true;
+    h->status = rc != MSTX_OK ? rc : h->rm->R.status;
+    step_release(h);
+  }
+  return MSTX_OK;
 }
 
 // ----------------------------------------------------------------- batched
@@ -1349,6 +1505,7 @@ int mst_workspace_release(void* stream) {
     auto it = mstx::g_caches.find({dev, (hipStream_t)stream});
     if (it == mstx::g_caches.end()) return MSTX_OK;
     std::lock_guard<std::mutex> l(it->second->mu);  // no call of this stream is running
+    if (it->second->step_active) return MSTX_ERR_INVALID_ARG;  // a stepwise solve still owns its workspace
     victim = std::move(it->second);
     mstx::g_caches.erase(it);
   }
@@ -1361,7 +1518,41 @@ int mst_workspace_release(void* stream) {
   if (victim->small_host && hipHostFree(victim->small_host) != hipSuccess) return MSTX_ERR_DEVICE;
   for (auto& e : victim->round_ev)
     if (e) (void)hipEventDestroy(e);
+  if (victim->step_base && hipFree(victim->step_base) != hipSuccess) return MSTX_ERR_DEVICE;
+  if (victim->step_rounds && hipHostFree(victim->step_rounds) != hipSuccess) return MSTX_ERR_DEVICE;
+  for (auto& e : victim->step_ev)
+    if (e) (void)hipEventDestroy(e);
   return MSTX_OK;
+}
+
+int mst_solve_begin(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, const uint32_t* w,
+                    uint8_t* out_in_mst, uint64_t* out_total_weight, void* stream, MstxSolve** out_handle) {
+  if (!out_handle) return MSTX_ERR_INVALID_ARG;
+  *out_handle = nullptr;
+  int rc = mstx::check_args(n, m, src, dst, w);
+  if (rc != MSTX_OK) return rc;
+  if (!out_total_weight || (m > 0 && !out_in_mst)) return MSTX_ERR_INVALID_ARG;
+  mstx::StepSolve* h = nullptr;
+  rc = mstx::step_begin(n, m, src, dst, w, out_in_mst, out_total_weight, (hipStream_t)stream, &h);
+  *out_handle = reinterpret_cast<MstxSolve*>(h);
+  return rc;
+}
+
+int mst_solve_advance(MstxSolve* handle, int32_t* out_done) {
+  if (!handle || !out_done) return MSTX_ERR_INVALID_ARG;
+  auto* h = reinterpret_cast<mstx::StepSolve*>(handle);
+  mstx::step_advance(h, false);
+  *out_done = h->done ? 1 : 0;
+  return MSTX_OK;
+}
+
+int mst_solve_end(MstxSolve* handle) {
+  if (!handle) return MSTX_ERR_INVALID_ARG;
+  auto* h = reinterpret_cast<mstx::StepSolve*>(handle);
+  mstx::step_advance(h, true);
+  const int st = h->status;
+  delete h;
+  return st;
 }
 
 size_t mst_workspace_bytes(int32_t n, int64_t m) {

@@ -7,14 +7,21 @@ free it takes work from the head of the queue, within its share of the
 device-memory budget (admission by HBM budget):
 
 * a request with at least `solo_edges` edges already fills the GPU: it is
-  solved alone with ``mst_solve``;
+  solved alone, round by round (``mst_solve_begin`` / ``mst_solve_advance``
+  / ``mst_solve_end``), and between two of its Boruvka rounds the worker
+  admits the small requests queued by then: it solves them with one
+  ``mst_solve_batched`` call on the same stream, which the device runs
+  after the rounds enqueued so far (round-granular admission: a small
+  request waits for at most about two rounds of a large one, not for the
+  whole solve);
 * otherwise the worker takes the queued requests up to the next large one,
   at most `batch_edges` edges and `max_batch` requests, copies them to the
   device and solves them with one ``mst_solve_batched`` call.
 
 Requests that arrive while other batches are on the GPU are admitted by the
-next free worker: batching is continuous, not a queue in front of a single
-solver, and the caps keep several workers busy at once.
+next free worker, or between the rounds of a large solve: batching is
+continuous, not a queue in front of a single solver, and the caps keep
+several workers busy at once.
 
 Every request's result is exactly the minimum spanning forest of its graph
 (a disjoint union of graphs has the union of their forests as its forest),
@@ -103,6 +110,10 @@ class GpuExecutor:
         vo, eo = batch_offsets(reqs)
         return sum(r.data_bytes() for r in reqs) + self.B.mst_batched_workspace_bytes(vo, eo)
 
+    def begin_solo(self, slot: int, r):
+        """Starts the round-by-round solve of one large request on the slot's stream."""
+        return _SoloJob(self, slot, r)
+
     def execute(self, slot: int, reqs, solo: bool = False) -> None:
         torch = self.torch
         stream = self.streams[slot]
@@ -151,6 +162,38 @@ class GpuExecutor:
             self.B.mst_workspace_release(s)
 
 
+class _SoloJob:
+    """One request solved round by round on a slot's stream (GpuExecutor.begin_solo)."""
+
+    def __init__(self, ex: GpuExecutor, slot: int, r):
+        torch = ex.torch
+        self.ex, self.r, self.stream = ex, r, ex.streams[slot]
+        with torch.cuda.stream(self.stream):
+            self.src = torch.from_numpy(r.src).to(ex.dev, non_blocking=True)
+            self.dst = torch.from_numpy(r.dst).to(ex.dev, non_blocking=True)
+            self.w = torch.from_numpy(r.w).to(ex.dev, non_blocking=True)
+            self.in_mst = torch.empty(r.m, dtype=torch.uint8, device=ex.dev)
+            self.total = torch.empty(1, dtype=torch.uint64, device=ex.dev)
+            st, self.h = ex.B.mst_solve_begin(r.n, self.src, self.dst, self.w, self.in_mst, self.total, self.stream)
+        if st < 0:
+            raise ex.B.MstxError(st)
+
+    def advance(self) -> bool:
+        """True once the solve has ended (its next round is enqueued otherwise)."""
+        return self.h is None or self.ex.B.mst_solve_advance(self.h)
+
+    def finish(self) -> None:
+        r, torch = self.r, self.ex.torch
+        if self.h is not None:
+            r.status = self.ex.B.mst_solve_end(self.h)
+            self.h = None
+        else:
+            r.status = 0
+        with torch.cuda.stream(self.stream):
+            r.in_mst = self.in_mst.cpu().numpy()
+            r.total = int(self.total.view(torch.int64).cpu().item())
+
+
 class MstServer:
     """Continuous batching over `executor` with `slots` concurrent workers.
 
@@ -161,8 +204,9 @@ class MstServer:
     """
 
     def __init__(self, executor, slots: int = 3, hbm_budget_bytes: int = 64 << 30, max_batch: int = 1024,
-                 solo_edges: int = 1 << 19, batch_edges: int = 1 << 22):
+                 solo_edges: int = 1 << 19, batch_edges: int = 1 << 22, step_poll_s: float = 2e-4):
         self.ex = executor
+        self.step_poll_s = step_poll_s  # wait between two polls of a large solve's rounds
         self.slots = slots
         self.share = hbm_budget_bytes // slots
         self.max_batch = max_batch
@@ -172,7 +216,8 @@ class MstServer:
         self.cv = threading.Condition()
         self.stop = False
         self.workers = []
-        self.batches = []  # (slot, sizes) log for tests
+        self.batches = []  # (slot, request ids) log for tests
+        self.interleaved = []  # (slot, large request id, request ids run between its rounds)
         self.errors = []  # (slot, request ids, exception) of batches whose execution raised
         self.in_flight_bytes = 0
         self.peak_in_flight_bytes = 0
@@ -197,6 +242,21 @@ class MstServer:
             self.cv.notify_all()
         for t in self.workers:
             t.join()
+
+    def _take_small(self, budget: int):
+        """Small requests from the head of the queue that fit `budget` bytes (lock
+        held): (requests, bytes).  Stops at the first large request."""
+        batch, used, edges = [], 0, 0
+        while self.queue and len(batch) < self.max_batch:
+            r = self.queue[0]
+            if r.m >= self.solo_edges or edges + r.m > self.batch_edges:
+                break
+            need = self.ex.batch_bytes(batch + [r])
+            if need > budget:
+                break
+            batch.append(self.queue.popleft())
+            used, edges = need, edges + r.m
+        return batch, used
 
     def _take_batch(self):
         """Work for one worker from the head of the queue (called with the lock held):
@@ -239,25 +299,59 @@ class MstServer:
                 self.peak_in_flight_bytes = max(self.peak_in_flight_bytes, self.in_flight_bytes)
             if not batch:
                 continue
-            try:
-                self.ex.execute(slot, batch, solo)
-            except Exception as exc:  # a failed batch fails its requests, not the worker
-                code = getattr(exc, "status", MSTX_ERR_DEVICE)
-                for r in batch:
-                    r.status = code if isinstance(code, int) and code < 0 else MSTX_ERR_DEVICE
-                    r.in_mst = None
-                    r.total = 0
-                self.errors.append((slot, [r.rid for r in batch], repr(exc)))
-            finally:
-                now = time.perf_counter()
+            if solo and hasattr(self.ex, "begin_solo"):
+                self._run_stepwise(slot, batch[0], used)
+            else:
+                self._run_batch(slot, batch, used, solo)
+
+    def _fail(self, slot, batch, exc):
+        code = getattr(exc, "status", MSTX_ERR_DEVICE)
+        for r in batch:
+            r.status = code if isinstance(code, int) and code < 0 else MSTX_ERR_DEVICE
+            r.in_mst = None
+            r.total = 0
+        self.errors.append((slot, [r.rid for r in batch], repr(exc)))
+
+    def _complete(self, slot, batch, used):
+        now = time.perf_counter()
+        with self.cv:
+            self.in_flight_bytes -= used
+            self.batches.append((slot, [r.rid for r in batch]))
+        for r in batch:
+            r.done_at = now
+            r.batch_size = len(batch)
+            r.slot = slot
+            r.done.set()
+
+    def _run_batch(self, slot, batch, used, solo=False):
+        try:
+            self.ex.execute(slot, batch, solo)
+        except Exception as exc:  # a failed batch fails its requests, not the worker
+            self._fail(slot, batch, exc)
+        finally:
+            self._complete(slot, batch, used)
+
+    def _run_stepwise(self, slot, r, used):
+        """One large request round by round; the small requests queued between two
+        of its rounds run on this slot then, within what is left of its share."""
+        try:
+            job = self.ex.begin_solo(slot, r)
+            while not job.advance():
                 with self.cv:
-                    self.in_flight_bytes -= used
-                    self.batches.append((slot, [r.rid for r in batch]))
-                for r in batch:
-                    r.done_at = now
-                    r.batch_size = len(batch)
-                    r.slot = slot
-                    r.done.set()
+                    small, sused = self._take_small(self.share - used)
+                    if small:
+                        self.in_flight_bytes += sused
+                        self.peak_in_flight_bytes = max(self.peak_in_flight_bytes, self.in_flight_bytes)
+                    else:
+                        self.cv.wait(timeout=self.step_poll_s)
+                if small:
+                    self.interleaved.append((slot, r.rid, [x.rid for x in small]))
+                    self._run_batch(slot, small, sused)
+            job.finish()
+        except Exception as exc:
+            self._fail(slot, [r], exc)
+        finally:
+            self._complete(slot, [r], used)
 
 
 class PlainServer:

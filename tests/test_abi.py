@@ -239,3 +239,21 @@ def test_profile_read_rounds_host(lib):
         assert B.mst_profile_read_rounds() == {}
     finally:
         B.mst_profile_enable(was)
+
+
+def test_stepwise_host_checks(lib):
+    """mst_solve_begin / advance / end refuse bad arguments before any device
+    call and leave no handle behind."""
+    from paper_2005_06913_amd import binding as B
+    c = ctypes
+    dummy = c.c_void_p(16)
+    h = c.c_void_p(0)
+    assert lib.mst_solve_begin(-1, 0, None, None, None, None, None, None, c.byref(h)) == B.MSTX_ERR_INVALID_ARG
+    assert lib.mst_solve_begin(4, 1 << 32, dummy, dummy, dummy, dummy, dummy, None, c.byref(h)) == \
+        B.MSTX_ERR_TOO_LARGE
+    assert lib.mst_solve_begin(4, 3, dummy, dummy, dummy, None, dummy, None, c.byref(h)) == B.MSTX_ERR_INVALID_ARG
+    assert lib.mst_solve_begin(4, 3, dummy, dummy, dummy, dummy, dummy, None, None) == B.MSTX_ERR_INVALID_ARG
+    assert h.value is None
+    done = c.c_int32(0)
+    assert lib.mst_solve_advance(None, c.byref(done)) == B.MSTX_ERR_INVALID_ARG
+    assert lib.mst_solve_end(None) == B.MSTX_ERR_INVALID_ARG

@@ -62,3 +62,79 @@ def test_plain_server(dev):
         k = oracle.kruskal(r.n, r.src, r.dst, r.w)
         assert r.status == k.status and r.total == k.total
         assert np.array_equal(r.in_mst, k.in_mst)
+
+
+def test_stepwise_solve_with_work_between_rounds(dev):
+    """mst_solve_begin / advance / end: the same bytes, total and round
+    statistics as mst_solve, with a batched call run on the same stream
+    between two rounds (its results exact too); a second stepwise solve on the
+    same stream is refused while one is open."""
+    import paper_2005_06913_amd as P
+    from paper_2005_06913_amd import graphgen as G
+    g = G.tree_plus_extra(300_000, 2_400_001, seed=25, name="stepwise")
+    s, d, w = (torch.from_numpy(a).to(dev) for a in (g.src, g.dst, g.w))
+    stream = torch.cuda.current_stream()
+    want = P.solve(g.n, s, d, w)
+    want_stats = P.mst_last_round_stats()
+    in_mst = torch.full((g.m,), 9, dtype=torch.uint8, device=dev)
+    total = torch.zeros(1, dtype=torch.uint64, device=dev)
+    print(f"[case] stepwise n={g.n} m={g.m}", flush=True)
+    st, h = P.mst_solve_begin(g.n, s, d, w, in_mst, total, stream)
+    assert st == 0 and h is not None
+    st2, h2 = P.mst_solve_begin(g.n, s, d, w, in_mst, total, stream)
+    assert st2 == P.MSTX_ERR_INVALID_ARG and h2 is None
+    b = G.batch(6, seed=26, n_lo=100, n_hi=5000)
+    bs, bd, bw = (torch.from_numpy(a).to(dev) for a in (b.src, b.dst, b.w))
+    bm = torch.empty(int(b.edge_offsets[-1]), dtype=torch.uint8, device=dev)
+    bt = torch.empty(b.num_graphs, dtype=torch.uint64, device=dev)
+    bst = torch.empty(b.num_graphs, dtype=torch.int32, device=dev)
+    steps, batched = 0, False
+    while not P.mst_solve_advance(h):
+        steps += 1
+        if not batched:
+            assert P.mst_solve_batched(b.vertex_offsets, b.edge_offsets, bs, bd, bw, bm, bt, bst, stream) == 0
+            batched = True
+    assert P.mst_solve_end(h) == want.status == 0
+    torch.cuda.synchronize()
+    assert int(total.view(torch.int64).item()) == want.total
+    assert torch.equal(in_mst, want.in_mst)
+    assert np.array_equal(P.mst_last_round_stats(), want_stats)
+    flags, tots = bm.cpu().numpy(), bt.view(torch.int64).cpu().numpy()
+    for i in range(b.num_graphs):
+        x = b.graph(i)
+        k = oracle.kruskal(x.n, x.src, x.dst, x.w)
+        assert int(bst[i]) == k.status and int(tots[i]) == k.total
+        assert np.array_equal(flags[b.edge_offsets[i]:b.edge_offsets[i + 1]], k.in_mst)
+
+
+def test_round_granular_admission_gpu(dev):
+    """One slot: small requests that arrive while a large one is solved round by
+    round run between its rounds and finish before it; every result equals the
+    oracle's."""
+    import time
+
+    from paper_2005_06913_amd import graphgen as G
+    from paper_2005_06913_amd import serve
+    big_g = G.tree_plus_extra(1 << 20, 1 << 23, seed=27)
+    big = serve.Request(1000, big_g.n, big_g.src, big_g.dst, big_g.w)
+    b = G.batch(24, seed=28, n_lo=100, n_hi=4000)
+    small = [serve.Request(i, *(lambda x: (x.n, x.src, x.dst, x.w))(b.graph(i))) for i in range(b.num_graphs)]
+    ex = serve.GpuExecutor(slots=1, device=dev)
+    srv = serve.MstServer(ex, slots=1, hbm_budget_bytes=8 << 30).start()
+    print("[case] round-granular admission, 1 slot", flush=True)
+    srv.submit(big)
+    time.sleep(0.0005)
+    for r in small:
+        srv.submit(r)
+    for r in small + [big]:
+        r.done.wait()
+    srv.close()
+    for r in small + [big]:
+        k = oracle.kruskal(r.n, r.src, r.dst, r.w)
+        assert r.status == k.status == 0, (r.rid, r.status)
+        assert r.total == k.total and np.array_equal(r.in_mst, k.in_mst), r.rid
+    if srv.interleaved:  # the large solve was still running when the small ones came
+        assert all(big_id == 1000 for _, big_id, _ in srv.interleaved)
+        ran = {rid for _, _, ids in srv.interleaved for rid in ids}
+        assert all(next(x for x in small if x.rid == rid).done_at < big.done_at for rid in ran)
+    ex.release()

@@ -133,3 +133,53 @@ def test_failed_batch_releases_slot_and_requests():
             k = oracle.kruskal(r.n, r.src, r.dst, r.w)
             assert r.status == k.status == 0 and r.total == k.total
             assert np.array_equal(r.in_mst, k.in_mst)
+
+
+class StepFakeExecutor(FakeExecutor):
+    """FakeExecutor whose large requests run round by round: `rounds` rounds of
+    `round_s` seconds each, the result from the oracle at the end."""
+
+    def __init__(self, delay=0.002, rounds=8, round_s=0.01):
+        super().__init__(delay)
+        self.rounds, self.round_s = rounds, round_s
+
+    def begin_solo(self, slot, r):
+        ex = self
+
+        class Job:
+            def __init__(self):
+                self.t0 = time.perf_counter()
+
+            def advance(self):
+                return time.perf_counter() - self.t0 >= ex.rounds * ex.round_s
+
+            def finish(self):
+                k = oracle.kruskal(r.n, r.src, r.dst, r.w)
+                r.in_mst, r.total, r.status = k.in_mst, k.total, k.status
+
+        return Job()
+
+
+def test_round_granular_admission():
+    """With one slot busy on a large request, small requests that arrive during
+    it are solved between its rounds and finish before it does."""
+    ex = StepFakeExecutor(delay=0.002, rounds=10, round_s=0.01)
+    srv = serve.MstServer(ex, slots=1, hbm_budget_bytes=1 << 30, solo_edges=50_000).start()
+    big_g = G.tree_plus_extra(20_000, 60_000, seed=9)
+    big = serve.Request(1000, big_g.n, big_g.src, big_g.dst, big_g.w)
+    srv.submit(big)
+    time.sleep(0.02)
+    small = make_requests(12, seed=10, n_hi=500)
+    for r in small:
+        srv.submit(r)
+        time.sleep(0.003)
+    for r in small + [big]:
+        r.done.wait()
+    srv.close()
+    assert srv.interleaved and all(big_id == 1000 for _, big_id, _ in srv.interleaved)
+    assert max(r.done_at for r in small) < big.done_at
+    for r in small + [big]:
+        k = oracle.kruskal(r.n, r.src, r.dst, r.w)
+        assert r.status == k.status == 0 and r.total == k.total
+        assert np.array_equal(r.in_mst, k.in_mst)
+    assert srv.in_flight_bytes == 0
