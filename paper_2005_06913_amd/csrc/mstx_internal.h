@@ -254,10 +254,20 @@ struct ScanArgs {
 };
 
 // LDS-mode minima of more than kSlabMin components are flushed through a
-// per-workgroup slab and a column minimum (k_slab_min) instead of atomics.
+// per-workgroup slab and a column minimum (k_slab_min) instead of atomics --
+// unless the round's stream is short next to the rows: a record lowers at
+// most two minima, so a workgroup's atomics are at most twice its records,
+// while its row is all n_r entries (written, then read again).  With
+// `stream` records and nwg rows the atomics win below about nwg * n_r /
+// kSlabStreamRatio records (an atomic merge costs about twice the traffic
+// of a row entry).  Dense mode passes no stream (always the slab).
 static constexpr int32_t kSlabMin = 512;
-__host__ __device__ inline bool use_slab(const unsigned long long* slab, int64_t cap, int32_t nr, int nwg) {
-  return slab != nullptr && nr > kSlabMin && (int64_t)nwg * nr <= cap;
+static constexpr int64_t kSlabStreamRatio = 4;
+static constexpr int64_t kSlabAnyStream = (int64_t)1 << 60;
+__host__ __device__ inline bool use_slab(const unsigned long long* slab, int64_t cap, int32_t nr, int nwg,
+                                         int64_t stream) {
+  return slab != nullptr && nr > kSlabMin && (int64_t)nwg * nr <= cap &&
+         kSlabStreamRatio * stream >= (int64_t)nwg * nr;
 }
 
 // Batched solve: graphs with at most kSmallN vertices are solved by one

@@ -602,7 +602,7 @@ __global__ void __launch_bounds__(kScanBlock) k_scan(ScanArgs A) {
   if (kMode == kModeBucket && my_btot) atomicAdd(A.btot + threadIdx.x, my_btot);
   if (kMode == kModeDense) {
     __syncthreads();
-    if (use_slab(A.slab, A.slab_cap, npairs, gridDim.x)) {
+    if (use_slab(A.slab, A.slab_cap, npairs, gridDim.x, kSlabAnyStream)) {
       unsigned long long* row = A.slab + (int64_t)blockIdx.x * npairs;
       for (int32_t c = threadIdx.x; c < npairs; c += kScanBlock) row[c] = lbest[c];
     } else {
@@ -614,7 +614,7 @@ __global__ void __launch_bounds__(kScanBlock) k_scan(ScanArgs A) {
   }
   if (kMode == kModeLds) {
     __syncthreads();
-    if (use_slab(A.slab, A.slab_cap, nr, gridDim.x)) {
+    if (use_slab(A.slab, A.slab_cap, nr, gridDim.x, A.st->stream[A.round])) {
       // coalesced copy of this workgroup's minima; k_slab_min takes the column minima
       unsigned long long* row = A.slab + (int64_t)blockIdx.x * nr;
       for (int32_t c = threadIdx.x; c < nr; c += kScanBlock) row[c] = lbest[c];
@@ -645,12 +645,14 @@ __global__ void __launch_bounds__(kBlock) k_slab_min(int round, int launched, in
   if (round > 0 && st->err) return;
   // runs after the scan of `mode` (LDS or dense) and only if that scan ran
   if (pick_mode(nr, launched) != mode) return;
+  int64_t stream = st->stream[round];
   if (mode == kModeDense) {
     // columns are the component pairs, the target the pair minima
     nr = dense_pairs(nr);
     best = pbest;
+    stream = kSlabAnyStream;
   }
-  if (!use_slab(slab, slab_cap, nr, nwg)) return;
+  if (!use_slab(slab, slab_cap, nr, nwg, stream)) return;
   const int b0 = blockIdx.y * kSlabRowsPerBlock;
   const int b1 = min(nwg, b0 + kSlabRowsPerBlock);
   for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < nr; c += (int64_t)gridDim.x * kBlock) {
@@ -1270,7 +1272,8 @@ __global__ void __launch_bounds__(kBlock) k_compress(int round, int32_t* parent,
 // ---------------------------------------------------------------- finalize
 
 // The stream state round r leaves for round r + 1 (one thread; n_next
-// components enter round r + 1): the records it reads (`stream_next`), the
+// components enter round r + 1; `in` is the state as round r found it,
+// written to st): the records it reads (`stream_next`), the
 // map from the labels in the records to round r + 1's (round r's own label
 // map if round r rewrote the records, else that map composed with round r's,
 // which k_relabel / k_round_tail write), and what round r + 1 does with its
@@ -1278,27 +1281,40 @@ __global__ void __launch_bounds__(kBlock) k_compress(int round, int32_t* parent,
 // read dead there, are kept in place if every LDS or dense launch of round
 // r + 2 (bound n_next / 2) can stage the composed map it would then read,
 // else relabelled in place; otherwise the survivors are compacted.
-__device__ __forceinline__ void next_stream_state(DevState* st, int round, int32_t nr, int32_t n_next, int64_t live,
-                                                  int64_t stream_next) {
-  const int64_t read = st->stream[round];
-  st->stream[round + 1] = stream_next;
-  if (st->keep[round] == kKeepRecords) {
-    st->map_off[round + 1] = st->cmap_off + (int64_t)((round + 1) & 1) * kNarrowMax;
-    st->map_n[round + 1] = st->map_n[round];
-  } else {
-    st->map_off[round + 1] = st->lab_off[round];
-    st->map_n[round + 1] = nr;
-  }
+__device__ __forceinline__ int next_stream_state(const DevState& in, DevState* st, int round, int32_t nr,
+                                                 int32_t n_next, int64_t live, int64_t stream_next) {
+  const int64_t read = in.stream[round];
+  const bool kept = in.keep[round] == kKeepRecords;
+  const int64_t map_off = kept ? in.cmap_off + (int64_t)((round + 1) & 1) * kNarrowMax : in.lab_off[round];
+  const int32_t map_n = kept ? in.map_n[round] : nr;
   int what = kMoveRecords;
   if (round >= 1 && nr <= kNarrowMax && (int64_t)kKeepDeadDen * (read - live) < read) {
     const int64_t bound = n_next / 2;
-    const int modes = scan_modes(bound, false, 3, st->dense_limit, true, kBucketMaxComponents);
+    const int modes = scan_modes(bound, false, 3, in.dense_limit, true, kBucketMaxComponents);
     bool fits = true;
     for (int mode : {kModeLds, kModeDense})
-      if ((modes >> mode) & 1) fits = fits && map_fits_lds(mode, bound, st->dense_limit, st->map_n[round + 1]);
+      if ((modes >> mode) & 1) fits = fits && map_fits_lds(mode, bound, in.dense_limit, map_n);
     what = fits ? kKeepRecords : kRelabelRecords;
   }
+  st->stream[round + 1] = stream_next;
+  st->map_off[round + 1] = map_off;
+  st->map_n[round + 1] = map_n;
   st->keep[round + 1] = what;
+  return what;
+}
+
+// Stores the 16 prefixes of words g0 .. g0 + 15 (those below W).
+__device__ __forceinline__ void store_prefixes(int32_t* rootpre, int32_t g0, int32_t W, const int32_t (&pre)[16]) {
+  if (g0 + 15 < W) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      *reinterpret_cast<int4*>(rootpre + g0 + 4 * k) = make_int4(pre[4 * k], pre[4 * k + 1], pre[4 * k + 2],
+                                                                   pre[4 * k + 3]);
+  } else {
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+      if (g0 + k < W) rootpre[g0 + k] = pre[k];
+  }
 }
 
 // One workgroup of 1024 threads.  Exclusive scan of rootcnt[0..W) into
@@ -1307,9 +1323,13 @@ __device__ __forceinline__ void next_stream_state(DevState* st, int round, int32
 // (seg_cnt), and the per-block partials of the hook: edges added and their
 // weight (part_sel / part_w [0..nhook)); adds the weight to *total; writes
 // the round's record for the host (pinned host memory) and the stream state
-// of the next round.  The counts and partials are read first, several per
-// thread in flight; the root counts are scanned 16 consecutive words per
-// thread (four 16-byte loads) per pass.
+// of the next round.  The kernel is a chain of dependent memory round trips,
+// so every independent read is issued at entry: the device state (copied to
+// LDS, one word per thread), the running total, the counts and partials
+// (several per thread in flight); the root counts follow once n_r is known,
+// 16 consecutive words per thread (four 16-byte loads) per pass.  A barrier
+// waits for the workgroup's outstanding stores, so the stores come after the
+// last one (the prefixes of the last pass stay in registers until then).
 __global__ void __launch_bounds__(1024) k_finalize(int round, const int32_t* __restrict__ rootcnt,
                                                    int32_t* __restrict__ rootpre,
                                                    const uint32_t* __restrict__ seg_cnt,
@@ -1318,11 +1338,18 @@ __global__ void __launch_bounds__(1024) k_finalize(int round, const int32_t* __r
                                                    const unsigned long long* __restrict__ part_w,
                                                    int32_t nhook, DevState* st,
                                                    unsigned long long* total, HostRound* host) {
+  __shared__ DevState sst;  // the device state as this kernel found it
   __shared__ int64_t sh[16];
-  __shared__ unsigned long long shw[16];
-  __shared__ int64_t shs[16];
+  __shared__ int64_t sh_live[16], sh_recs[16], sh_sel[16];
+  __shared__ unsigned long long sh_w[16];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
+  {
+    constexpr int kWords = (int)(sizeof(DevState) / 4);
+    static_assert(sizeof(DevState) % 4 == 0 && kWords <= 1024, "one word of the state per thread");
+    if (tid < kWords) reinterpret_cast<uint32_t*>(&sst)[tid] = reinterpret_cast<const uint32_t*>(st)[tid];
+  }
+  const unsigned long long total0 = tid == 0 ? *total : 0ull;
   // counts and partials (nseg >= 1 and nhook >= 1: clamped reads stay inside)
   int64_t live = 0, recs = 0, sel = 0;
   unsigned long long ws = 0;
@@ -1362,13 +1389,24 @@ __global__ void __launch_bounds__(1024) k_finalize(int round, const int32_t* __r
       ws += x[q];
     }
   }
-  const int32_t nr = st->n[round];
-  if (st->dense_at == round) return;  // the dense finish wrote this round's record
+  live = wave_sum(live);
+  recs = wave_sum(recs);
+  sel = wave_sum(sel);
+  ws = wave_sum(ws);
+  if (lane == 0) {
+    sh_live[wv] = live;
+    sh_recs[wv] = recs;
+    sh_sel[wv] = sel;
+    sh_w[wv] = ws;
+  }
+  __syncthreads();  // the state's copy and the per-wave sums are complete
+  const int32_t nr = sst.n[round];
+  if (sst.dense_at == round) return;  // the dense finish wrote this round's record
   if (nr <= 1 && round > 0) {
     if (tid == 0) {
       st->n[round + 1] = 0;
-      st->lab_off[round + 1] = st->lab_off[round];
-      HostRound h{0, st->err, st->err_internal, 0, 0, 0, st->edges_added, 0, 0, 0, 0, 0};
+      st->lab_off[round + 1] = sst.lab_off[round];
+      HostRound h{0, sst.err, sst.err_internal, 0, 0, 0, sst.edges_added, 0, 0, 0, 0, 0};
       host[round] = h;
       __threadfence_system();
     }
@@ -1377,6 +1415,8 @@ __global__ void __launch_bounds__(1024) k_finalize(int round, const int32_t* __r
   // passes of 1024 x 16 words: exclusive scan with a carry
   const int32_t W = (nr + 63) >> 6;
   int64_t carry = 0;
+  int32_t pre[16];
+  int32_t g_last = W;  // first word of this thread's prefixes still to store (W: none)
   for (int32_t t0 = 0; t0 < W; t0 += 16 * 1024) {
     const int32_t g0 = t0 + 16 * tid;
     int32_t v[16];
@@ -1409,64 +1449,46 @@ __global__ void __launch_bounds__(1024) k_finalize(int round, const int32_t* __r
       tile_tot += sh[i];
     }
     int64_t e = carry + wave_base + x - mine;
-    int32_t pre[16];
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
       pre[k] = (int32_t)e;
       e += v[k];
     }
-    if (g0 + 15 < W) {
-#pragma unroll
-      for (int k = 0; k < 4; ++k)
-        *reinterpret_cast<int4*>(rootpre + g0 + 4 * k) = make_int4(pre[4 * k], pre[4 * k + 1], pre[4 * k + 2],
-                                                                     pre[4 * k + 3]);
-    } else {
-#pragma unroll
-      for (int k = 0; k < 16; ++k)
-        if (g0 + k < W) rootpre[g0 + k] = pre[k];
-    }
     carry += tile_tot;
-    __syncthreads();  // sh[] is rewritten by the next pass
+    g_last = g0;
+    if (t0 + 16 * 1024 < W) {
+      // another pass follows: store now (sh[] is rewritten by that pass)
+      store_prefixes(rootpre, g0, W, pre);
+      g_last = W;
+      __syncthreads();
+    }
   }
-  const int64_t total_roots = carry;
-  live = wave_sum(live);
-  recs = wave_sum(recs);
-  sel = wave_sum(sel);
-  ws = wave_sum(ws);
-  __syncthreads();
-  if (lane == 0) {
-    sh[wv] = live;
-    shw[wv] = ws;
-    shs[wv] = recs;
-  }
-  __syncthreads();
-  int64_t L = 0, Rn = 0;
-  unsigned long long S = 0;
-  for (int i = 0; i < 16; ++i) {
-    L += sh[i];
-    S += shw[i];
-    Rn += shs[i];
-  }
-  __syncthreads();
-  if (lane == 0) sh[wv] = sel;
-  __syncthreads();
   if (tid == 0) {
-    int64_t T = 0;
-    for (int i = 0; i < 16; ++i) T += sh[i];
+    int64_t L = 0, Rn = 0, T = 0;
+    unsigned long long S = 0;
+    for (int i = 0; i < 16; ++i) {
+      L += sh_live[i];
+      Rn += sh_recs[i];
+      T += sh_sel[i];
+      S += sh_w[i];
+    }
+    const int64_t total_roots = carry;
+    const int64_t added = sst.edges_added + T;
     st->live[round] = L;
     st->sel[round] = T;
-    st->edges_added += T;
+    st->edges_added = added;
     st->n[round + 1] = (int32_t)total_roots;
-    st->lab_off[round + 1] = st->lab_off[round] + nr;
-    *total += S;
+    st->lab_off[round + 1] = sst.lab_off[round] + nr;
+    *total = total0 + S;
     // round 0 leaves the stream untouched: round 1 reads the caller's edges
-    next_stream_state(st, round, nr, (int32_t)total_roots, L, round == 0 ? st->m : Rn);
-    HostRound h{(int32_t)total_roots, st->err,          st->err_internal, 0,
-                L,                    T,                st->edges_added,  st->stream[round],
-                st->map_n[round],     st->keep[round],  st->keep[round + 1], 0};
+    const int next = next_stream_state(sst, st, round, nr, (int32_t)total_roots, L, round == 0 ? sst.m : Rn);
+    HostRound h{(int32_t)total_roots, sst.err, sst.err_internal, 0,
+                L,                    T,       added,            sst.stream[round],
+                sst.map_n[round],     sst.keep[round], next,     0};
     host[round] = h;
     __threadfence_system();
   }
+  if (g_last < W) store_prefixes(rootpre, g_last, W, pre);
 }
 
 // ----------------------------------------------------------------- relabel
@@ -1519,12 +1541,16 @@ __global__ void __launch_bounds__(kBlock) k_relabel(int round, const int32_t* __
 // Hook, compress, finalize and relabel of one round in one workgroup, for a
 // round with n_r <= kTailMax components (the host launches it only when its
 // bound on n_r is that small).  The same steps as k_hook .. k_relabel, with
-// the parent forest in LDS: every component with a minimum edge names the
-// component at the far end; of a mutual pair only the smaller id acts; the
-// larger root is linked under the smaller by compare-and-swap (LDS), so every
-// root is its component's smallest id and the labels (rank among the kept
-// roots, -1 for an isolated component) equal the multi-kernel path's.
+// the parent forest in LDS: every component with a minimum edge takes the
+// component at the far end as its parent, except the smaller of a mutual
+// pair, which stays a root (the rule of k_hook, so the roots and labels --
+// rank among the kept roots, -1 for an isolated component -- equal the
+// multi-kernel path's).  The roots are then found by pointer jumping: every
+// pass replaces each parent by its parent's parent, so a chain of length L
+// is resolved in about log2 L passes (a walk along it would take L dependent
+// LDS reads, and the minimum edges of grid-like graphs form long chains).
 // LDS: parent [n_r] and target / root [n_r], int32 each.
+static constexpr int kTailJumpPasses = 40;  // > log2(kTailMax) + 2: more means a cycle, an internal error
 static constexpr int kTailThreads = 1024;
 static constexpr int kTailPer = (kTailMax + kTailThreads - 1) / kTailThreads;
 
@@ -1540,6 +1566,7 @@ __global__ void __launch_bounds__(kTailThreads) k_round_tail(int round, int32_t 
   __shared__ int64_t red_a[kTailThreads / 64];
   __shared__ int64_t red_b[kTailThreads / 64];
   __shared__ int64_t red_c[kTailThreads / 64];
+  __shared__ int64_t red_l[kTailThreads / 64];
   __shared__ unsigned long long red_w[kTailThreads / 64];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   // Every read that does not depend on another is issued here, before the
@@ -1678,40 +1705,65 @@ __global__ void __launch_bounds__(kTailThreads) k_round_tail(int round, int32_t 
       tgt[c] = d[q];
     }
   }
-  const bool any_bad = __syncthreads_or(bad);
-  // hook; of a mutual pair (each the other's far end, so the same edge) the
-  // smaller id acts
-  uint32_t sel = 0;
+  const bool any_bad0 = __syncthreads_or(bad);
+  // hook by successors; of a mutual pair (each the other's far end, so the
+  // same edge) the larger id hooks and owns the edge.  Global stores wait
+  // until after the last barrier (a barrier waits for them): the edges this
+  // thread adds are remembered in a bit mask.
+  uint32_t sel = 0, hooked = 0;
   unsigned long long wsum = 0;
 #pragma unroll
   for (int q = 0; q < kTailPer; ++q) {
     const int32_t c = tid + q * kTailThreads;
-    if (d[q] < 0 || (d[q] < c && tgt[d[q]] == c)) continue;
-    int32_t x = c, y = d[q];
-    while (true) {
-      const int32_t rx = walk_root(par, x);
-      const int32_t ry = walk_root(par, y);
-      if (rx == ry) break;
-      const int32_t hi = rx > ry ? rx : ry;
-      const int32_t lo = rx > ry ? ry : rx;
-      const int32_t old = atomicCAS(par + hi, hi, lo);
-      if (old == hi) {
-        in_mst[e[q]] = 1;
-        ++sel;
-        wsum += (uint32_t)(key[q] >> 32);  // the edge's weight
-        break;
-      }
-      if (hi == rx) x = old;
-      else y = old;
+    if (c >= nr) continue;
+    const bool hooks = d[q] >= 0 && !(d[q] > c && tgt[d[q]] == c);
+    par[c] = hooks ? d[q] : c;
+    if (hooks) {
+      hooked |= 1u << q;
+      ++sel;
+      wsum += (uint32_t)(key[q] >> 32);  // the edge's weight
     }
   }
+  // the round's sums, per wave (read by thread 0 after the last barrier)
+  live = wave_sum(live);
+  recs = wave_sum(recs);
+  const int64_t sel64 = wave_sum((int64_t)sel);
+  wsum = wave_sum(wsum);
+  if (lane == 0) {
+    red_b[wv] = sel64;
+    red_c[wv] = recs;
+    red_l[wv] = live;
+    red_w[wv] = wsum;
+  }
   __syncthreads();
+  // pointer jumping in place: a value read while another thread rewrites it
+  // is the old or the new parent, both ancestors, so every pass keeps each
+  // entry on its path to the root and the passes end when none changes
+  bool jumping = true;
+  int passes = 0;
+  while (jumping && passes < kTailJumpPasses) {
+    bool changed = false;
+#pragma unroll
+    for (int q = 0; q < kTailPer; ++q) {
+      const int32_t c = tid + q * kTailThreads;
+      if (c >= nr) continue;
+      const int32_t p = __hip_atomic_load(par + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      const int32_t pp = __hip_atomic_load(par + p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      if (pp != p) {
+        __hip_atomic_store(par + c, pp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        changed = true;
+      }
+    }
+    jumping = __syncthreads_or(changed);
+    ++passes;
+  }
+  const bool any_bad = any_bad0 || jumping;  // still moving: a cycle, never expected
   // roots: tgt[c] = root of c, -1 for an isolated component (no minimum
   // edge: nothing hooked onto it and it hooked onto nothing)
 #pragma unroll
   for (int q = 0; q < kTailPer; ++q) {
     const int32_t c = tid + q * kTailThreads;
-    if (c < nr) tgt[c] = d[q] < 0 && par[c] == c ? -1 : walk_root(par, c);
+    if (c < nr) tgt[c] = d[q] < 0 && par[c] == c ? -1 : par[c];
   }
   __syncthreads();
   // new labels: rank of each kept root (tgt[c] == c) in id order; thread t
@@ -1739,13 +1791,37 @@ __global__ void __launch_bounds__(kTailThreads) k_round_tail(int round, int32_t 
     const int32_t c = tid * kTailPer + q;
     if (c < nr && tgt[c] == c) par[c] = rank++;
   }
-  __syncthreads();
+  __syncthreads();  // the last barrier: global stores from here on
+  if (tid == 0) {
+    int64_t L = 0, T = 0, R = 0;
+    unsigned long long W = 0;
+    for (int i = 0; i < kTailThreads / 64; ++i) {
+      L += red_l[i];
+      T += red_b[i];
+      R += red_c[i];
+      W += red_w[i];
+    }
+    const int erri = any_bad ? 1 : erri0;
+    st->err_internal = erri;
+    st->live[round] = L;
+    st->sel[round] = T;
+    st->edges_added = added0 + T;
+    st->n[round + 1] = roots;
+    st->lab_off[round + 1] = off + nr;
+    *total = total0 + W;
+    const int next = next_stream_state(*st, st, round, nr, roots, L, round == 0 ? st->m : R);
+    HostRound h{roots, err0, erri, 0, L, T, added0 + T, st->stream[round], st->map_n[round], st->keep[round],
+                next, 0};
+    host[round] = h;
+    __threadfence_system();
+  }
 #pragma unroll
   for (int q = 0; q < kTailPer; ++q) {
     const int32_t c = tid + q * kTailThreads;
     if (c < nr) {
       const int32_t r = tgt[c];
       labpool[off + c] = r < 0 ? -1 : par[r];
+      if ((hooked >> q) & 1u) in_mst[e[q]] = 1;
     }
   }
   if (st->keep[round] == kKeepRecords) {
@@ -1776,42 +1852,6 @@ __global__ void __launch_bounds__(kTailThreads) k_round_tail(int round, int32_t 
   }
   if (btot)
     for (int32_t i = tid; i < kMaxBuckets; i += kTailThreads) btot[i] = 0;
-  // the round's record
-  live = wave_sum(live);
-  recs = wave_sum(recs);
-  int64_t sel64 = wave_sum((int64_t)sel);
-  wsum = wave_sum(wsum);
-  __syncthreads();  // red_a is rewritten
-  if (lane == 0) {
-    red_a[wv] = live;
-    red_b[wv] = sel64;
-    red_c[wv] = recs;
-    red_w[wv] = wsum;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    int64_t L = 0, T = 0, R = 0;
-    unsigned long long W = 0;
-    for (int i = 0; i < kTailThreads / 64; ++i) {
-      L += red_a[i];
-      T += red_b[i];
-      R += red_c[i];
-      W += red_w[i];
-    }
-    const int erri = any_bad ? 1 : erri0;
-    st->err_internal = erri;
-    st->live[round] = L;
-    st->sel[round] = T;
-    st->edges_added = added0 + T;
-    st->n[round + 1] = roots;
-    st->lab_off[round + 1] = off + nr;
-    *total = total0 + W;
-    next_stream_state(st, round, nr, roots, L, round == 0 ? st->m : R);
-    HostRound h{roots, err0, erri, 0, L, T, added0 + T, st->stream[round], st->map_n[round], st->keep[round],
-                st->keep[round + 1], 0};
-    host[round] = h;
-    __threadfence_system();
-  }
 }
 
 // ------------------------------------------------------------ launchers
