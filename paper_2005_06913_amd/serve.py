@@ -23,6 +23,12 @@ next free worker, or between the rounds of a large solve: batching is
 continuous, not a queue in front of a single solver, and the caps keep
 several workers busy at once.
 
+A request's arrays are host arrays (numpy; the executor copies them to the
+device on the slot's stream and the flags back) or device tensors already
+in HBM, e.g. written by an earlier GPU stage (then nothing crosses PCIe but
+the per-request total and status, and the flags stay on the device as a
+view of the batch's output).
+
 Every request's result is exactly the minimum spanning forest of its graph
 (a disjoint union of graphs has the union of their forests as its forest),
 so it is the same whether solved alone or in a mix; ``tests/test_serve.py``
@@ -71,6 +77,16 @@ class Request:
         return int(self.src.shape[0])
 
     @property
+    def resident(self) -> bool:
+        """The graph's arrays are device tensors (no host-to-device copy)."""
+        return bool(getattr(self.src, "is_cuda", False))
+
+    def flags(self) -> np.ndarray:
+        """in_mst as a host array (copied from the device for a resident request)."""
+        f = self.in_mst
+        return f.cpu().numpy() if hasattr(f, "cpu") else f
+
+    @property
     def latency(self) -> float:
         return self.done_at - self.arrival
 
@@ -114,33 +130,46 @@ class GpuExecutor:
         """Starts the round-by-round solve of one large request on the slot's stream."""
         return _SoloJob(self, slot, r)
 
+    def _tensor(self, a):
+        """A request array as a tensor: device tensors as they are, host arrays wrapped."""
+        return a if isinstance(a, self.torch.Tensor) else self.torch.from_numpy(a)
+
+    def _on_device(self, a):
+        """A request array on the device (host arrays copied on the current stream)."""
+        return a if isinstance(a, self.torch.Tensor) else self.torch.from_numpy(a).to(self.dev, non_blocking=True)
+
     def execute(self, slot: int, reqs, solo: bool = False) -> None:
         torch = self.torch
         stream = self.streams[slot]
         if solo:
             (r,) = reqs
             with torch.cuda.stream(stream):
-                src = torch.from_numpy(r.src).to(self.dev, non_blocking=True)
-                dst = torch.from_numpy(r.dst).to(self.dev, non_blocking=True)
-                w = torch.from_numpy(r.w).to(self.dev, non_blocking=True)
+                src, dst, w = (self._on_device(a) for a in (r.src, r.dst, r.w))
                 in_mst = torch.empty(r.m, dtype=torch.uint8, device=self.dev)
                 total = torch.empty(1, dtype=torch.uint64, device=self.dev)
                 r.status = self.B.mst_solve(r.n, src, dst, w, in_mst, total, stream)
-                r.in_mst = in_mst.cpu().numpy()
-                r.total = int(total.view(torch.int64).cpu().item())
+                r.total = int(total.view(torch.int64).cpu().item())  # waits for the solve
+                r.in_mst = in_mst if r.resident else in_mst.cpu().numpy()
             return
         vo, eo = batch_offsets(reqs)
         m = int(eo[-1])
         G = len(reqs)
         with torch.cuda.stream(stream):
-            src = torch.empty(m, dtype=torch.int32, device=self.dev)
-            dst = torch.empty(m, dtype=torch.int32, device=self.dev)
-            w = torch.empty(m, dtype=torch.uint32, device=self.dev)
-            for r, a in zip(reqs, eo[:-1]):
-                a = int(a)
-                src[a:a + r.m].copy_(torch.from_numpy(r.src), non_blocking=True)
-                dst[a:a + r.m].copy_(torch.from_numpy(r.dst), non_blocking=True)
-                w[a:a + r.m].copy_(torch.from_numpy(r.w), non_blocking=True)
+            if all(r.resident for r in reqs):
+                # one concatenation per array inside HBM (weights as int32 bits)
+                src = torch.cat([r.src for r in reqs])
+                dst = torch.cat([r.dst for r in reqs])
+                w = torch.cat([r.w.view(torch.int32) for r in reqs]).view(torch.uint32)
+            else:
+                src = torch.empty(m, dtype=torch.int32, device=self.dev)
+                dst = torch.empty(m, dtype=torch.int32, device=self.dev)
+                w = torch.empty(m, dtype=torch.uint32, device=self.dev)
+                for r, a in zip(reqs, eo[:-1]):
+                    a = int(a)
+                    # host arrays cross PCIe here; device arrays are copied inside HBM
+                    src[a:a + r.m].copy_(self._tensor(r.src), non_blocking=True)
+                    dst[a:a + r.m].copy_(self._tensor(r.dst), non_blocking=True)
+                    w[a:a + r.m].copy_(self._tensor(r.w), non_blocking=True)
             in_mst = torch.empty(m, dtype=torch.uint8, device=self.dev)
             total = torch.empty(G, dtype=torch.uint64, device=self.dev)
             status = torch.empty(G, dtype=torch.int32, device=self.dev)
@@ -149,11 +178,12 @@ class GpuExecutor:
                 for r in reqs:
                     r.status = rc
                 return
-            flags = in_mst.cpu().numpy()
-            tot = total.view(torch.int64).cpu().numpy()
+            tot = total.view(torch.int64).cpu().numpy()  # waits for the solve
             st = status.cpu().numpy()
+            host_flags = in_mst.cpu().numpy() if not all(r.resident for r in reqs) else None
         for i, r in enumerate(reqs):
-            r.in_mst = flags[eo[i]:eo[i + 1]]
+            a, b = int(eo[i]), int(eo[i + 1])
+            r.in_mst = in_mst[a:b] if r.resident else host_flags[a:b]
             r.total = int(tot[i])
             r.status = int(st[i])
 
@@ -169,9 +199,7 @@ class _SoloJob:
         torch = ex.torch
         self.ex, self.r, self.stream = ex, r, ex.streams[slot]
         with torch.cuda.stream(self.stream):
-            self.src = torch.from_numpy(r.src).to(ex.dev, non_blocking=True)
-            self.dst = torch.from_numpy(r.dst).to(ex.dev, non_blocking=True)
-            self.w = torch.from_numpy(r.w).to(ex.dev, non_blocking=True)
+            self.src, self.dst, self.w = (ex._on_device(a) for a in (r.src, r.dst, r.w))
             self.in_mst = torch.empty(r.m, dtype=torch.uint8, device=ex.dev)
             self.total = torch.empty(1, dtype=torch.uint64, device=ex.dev)
             st, self.h = ex.B.mst_solve_begin(r.n, self.src, self.dst, self.w, self.in_mst, self.total, self.stream)
@@ -190,8 +218,8 @@ class _SoloJob:
         else:
             r.status = 0
         with torch.cuda.stream(self.stream):
-            r.in_mst = self.in_mst.cpu().numpy()
-            r.total = int(self.total.view(torch.int64).cpu().item())
+            r.total = int(self.total.view(torch.int64).cpu().item())  # waits for the solve
+            r.in_mst = self.in_mst if r.resident else self.in_mst.cpu().numpy()
 
 
 class MstServer:
@@ -400,14 +428,13 @@ class PlainServer:
                     return
                 r = self.queue.popleft()
             with torch.cuda.stream(self.stream):
-                src = torch.from_numpy(r.src).to(self.dev, non_blocking=True)
-                dst = torch.from_numpy(r.dst).to(self.dev, non_blocking=True)
-                w = torch.from_numpy(r.w).to(self.dev, non_blocking=True)
+                src, dst, w = (a if isinstance(a, torch.Tensor) else torch.from_numpy(a).to(self.dev, non_blocking=True)
+                               for a in (r.src, r.dst, r.w))
                 in_mst = torch.empty(r.m, dtype=torch.uint8, device=self.dev)
                 total = torch.empty(1, dtype=torch.uint64, device=self.dev)
                 r.status = self.B.mst_solve(r.n, src, dst, w, in_mst, total, self.stream)
-                r.in_mst = in_mst.cpu().numpy()
-                r.total = int(total.view(torch.int64).cpu().item())
+                r.total = int(total.view(torch.int64).cpu().item())  # waits for the solve
+                r.in_mst = in_mst if r.resident else in_mst.cpu().numpy()
             r.done_at = time.perf_counter()
             r.batch_size = 1
             r.done.set()

@@ -138,3 +138,37 @@ def test_round_granular_admission_gpu(dev):
         ran = {rid for _, _, ids in srv.interleaved for rid in ids}
         assert all(next(x for x in small if x.rid == rid).done_at < big.done_at for rid in ran)
     ex.release()
+
+
+def test_resident_requests(dev):
+    """Requests whose graphs are already device tensors: small ones batched by
+    one concatenation inside HBM, a large one solved round by round; flags stay
+    on the device; every result equals the oracle's, and the plain server's."""
+    from paper_2005_06913_amd import graphgen as G
+    from paper_2005_06913_amd import serve
+    b = G.batch(20, seed=29, n_lo=100, n_hi=8000)
+    graphs = [b.graph(i) for i in range(b.num_graphs)] + [G.tree_plus_extra(200_000, 1_200_000, seed=30)]
+
+    def requests():
+        return [serve.Request(i, g.n, *(torch.from_numpy(a).to(dev) for a in (g.src, g.dst, g.w)))
+                for i, g in enumerate(graphs)]
+
+    reqs = requests()
+    assert all(r.resident for r in reqs)
+    ex = serve.GpuExecutor(slots=2, device=dev)
+    srv = serve.MstServer(ex, slots=2, hbm_budget_bytes=4 << 30).start()
+    print("[case] resident requests, 2 slots", flush=True)
+    serve.poisson_replay(srv, reqs, qps=5000.0, seed=31)
+    srv.close()
+    plain = requests()
+    psrv = serve.PlainServer(device=dev).start()
+    serve.poisson_replay(psrv, plain, qps=5000.0, seed=32)
+    psrv.close()
+    for r, p, g in zip(reqs, plain, graphs):
+        assert hasattr(r.in_mst, "is_cuda") and r.in_mst.is_cuda
+        k = oracle.kruskal(g.n, g.src, g.dst, g.w)
+        assert r.status == p.status == k.status == 0, r.rid
+        assert r.total == p.total == k.total, r.rid
+        assert np.array_equal(r.flags(), k.in_mst) and np.array_equal(p.flags(), k.in_mst), r.rid
+    assert any(len(ids) > 1 for _, ids in srv.batches)
+    ex.release()
