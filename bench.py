@@ -55,7 +55,9 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_random_n1M_d16.json")
+def traffic_file(workload: str) -> str:
+    """The counter summary of `workload` (bench.py --summarize-pmc)."""
+    return os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.json")
 
 
 def kernel_source_hash() -> str:
@@ -69,18 +71,46 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def _pmc_rows(d):
+def _pmc_dispatches(d):
+    """[(dispatch id, kernel name, counter value)] of one rocprofv3 --pmc run, in dispatch order."""
     import csv
     import glob
-    out = {}
+    rows = []
     for path in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
         for r in csv.DictReader(open(path)):
             name = r["Kernel_Name"].replace("void ", "").replace("mstx::", "").split("(")[0]
-            out.setdefault(name, []).append(float(r["Counter_Value"]))
+            rows.append((int(r["Dispatch_Id"]), name, float(r["Counter_Value"])))
+    rows.sort()
+    return rows
+
+
+def _pmc_rows(d):
+    out = {}
+    for _, name, v in _pmc_dispatches(d):
+        out.setdefault(name, []).append(v)
     return out
 
 
-def summarize_pmc(copy_fetch, copy_write, solve_fetch, solve_write, copy_mib, out_path):
+def _rounds_of_last_solve(dispatches):
+    """Per round of the last solve (from its k_init on): {kernel: bytes}.  A round
+    ends with its k_relabel or k_round_tail, or with the dense finish."""
+    starts = [i for i, (_, name, _) in enumerate(dispatches) if name == "k_init"]
+    if not starts:
+        return []
+    rounds, cur = [], {}
+    for _, name, v in dispatches[starts[-1] + 1:]:
+        if not name.startswith("k_"):
+            continue
+        cur[name] = cur.get(name, 0.0) + v
+        if name in ("k_relabel", "k_round_tail"):
+            rounds.append(cur)
+            cur = {}
+    if cur:
+        rounds.append(cur)
+    return rounds
+
+
+def summarize_pmc(copy_fetch, copy_write, solve_fetch, solve_write, copy_mib, workload, out_path=None):
     """Folds four rocprofv3 --pmc runs (FETCH_SIZE / WRITE_SIZE of a plain copy and of the
     solve) into HBM bytes per launch for every kernel, scaled by the copy calibration."""
     cf, cw = _pmc_rows(copy_fetch), _pmc_rows(copy_write)
@@ -99,33 +129,55 @@ def summarize_pmc(copy_fetch, copy_write, solve_fetch, solve_write, copy_mib, ou
                       "write_bytes_mean": sum(wb) / len(wb),
                       "traffic_bytes_mean": sum(fb) / len(fb) + sum(wb) / len(wb),
                       "traffic_bytes_max_launch": max(a + b for a, b in zip(fb, wb))}
-    doc = {"workload": "random_n1M_d16", "source_sha256": kernel_source_hash(),
+    # per round of the last solve: the two passes dispatch the same kernels in the same order
+    fr = _rounds_of_last_solve([(i, n, v * 1024.0 * fetch_factor) for i, n, v in _pmc_dispatches(solve_fetch)])
+    wr = _rounds_of_last_solve([(i, n, v * 1024.0 * write_factor) for i, n, v in _pmc_dispatches(solve_write)])
+    per_round = []
+    if len(fr) == len(wr):
+        for a, b in zip(fr, wr):
+            per_round.append({k: {"fetch_bytes": a[k], "write_bytes": b.get(k, 0.0),
+                                  "traffic_bytes": a[k] + b.get(k, 0.0)} for k in a})
+    wl = "" if workload == "random_n1M_d16" else f"--workload {workload} "
+    doc = {"workload": workload, "source_sha256": kernel_source_hash(),
            "copy_calibration": {"kernel": copy_name, "bytes_each_way": nbytes,
                                 "fetch_kib": max(cf[copy_name]), "write_kib": max(cw[copy_name]),
                                 "fetch_factor": fetch_factor, "write_factor": write_factor},
            "commands": [
                f"rocprofv3 --pmc FETCH_SIZE -f csv -d <dir> -o run -- python3 bench.py --calibrate-copy-mib {copy_mib}",
                f"rocprofv3 --pmc WRITE_SIZE -f csv -d <dir> -o run -- python3 bench.py --calibrate-copy-mib {copy_mib}",
-               "rocprofv3 --pmc FETCH_SIZE -f csv -d <dir> -o run -- python3 bench.py --steps 2 --warmup 1 "
+               f"rocprofv3 --pmc FETCH_SIZE -f csv -d <dir> -o run -- python3 bench.py {wl}--steps 2 --warmup 1 "
                "--no-cpu-baseline --cold-reps 0",
-               "rocprofv3 --pmc WRITE_SIZE -f csv -d <dir> -o run -- python3 bench.py --steps 2 --warmup 1 "
-               "--no-cpu-baseline --cold-reps 0"],
-           "kernels": kernels}
-    with open(out_path, "w") as f:
+               f"rocprofv3 --pmc WRITE_SIZE -f csv -d <dir> -o run -- python3 bench.py {wl}--steps 2 --warmup 1 "
+               "--no-cpu-baseline --cold-reps 0",
+               f"python3 bench.py {wl}--summarize-pmc <copy FETCH dir> <copy WRITE dir> <FETCH dir> <WRITE dir>"],
+           "kernels": kernels,
+           "per_round_last_solve": per_round}
+    with open(out_path or traffic_file(workload), "w") as f:
         json.dump(doc, f, indent=1)
     return doc
 
 
-def traffic_for(kernel: str):
-    """Counter-measured HBM bytes per launch of `kernel`, or None if absent or stale."""
+def traffic_for(kernel: str, workload: str):
+    """Counter-measured HBM bytes per launch of `kernel` on `workload`, or None if absent or stale."""
     try:
-        doc = json.load(open(TRAFFIC_FILE))
+        doc = json.load(open(traffic_file(workload)))
     except (OSError, ValueError):
         return None
     if doc.get("source_sha256") != kernel_source_hash():
         return None
     k = doc.get("kernels", {}).get(kernel)
     return None if k is None else k["traffic_bytes_mean"]
+
+
+def traffic_per_round(workload: str):
+    """Counter-measured HBM bytes per round and kernel of one solve, or None if absent or stale."""
+    try:
+        doc = json.load(open(traffic_file(workload)))
+    except (OSError, ValueError):
+        return None
+    if doc.get("source_sha256") != kernel_source_hash():
+        return None
+    return doc.get("per_round_last_solve") or None
 
 
 def host_info():
@@ -184,6 +236,35 @@ def cpu_baseline_batched(b, budget_s: float):
     return {"value": done / el, "unit": "solves/s", "cores": cores, "kind": "oracle",
             "sample": f"the first {done} of {b.num_graphs} graphs of the same batch, Kruskal per graph, "
                       f"{cores} host threads ({el:.1f} s)"}
+
+
+def per_graph_leg(b, src, dst, w, got, got_tot, got_st, stream, dev):
+    """The plain path on the same device arrays: one mst_solve per graph of the batch,
+    compared byte for byte with the batched call's results."""
+    import numpy as np
+    import torch
+
+    import paper_2005_06913_amd as P
+    log("[bench] per-graph path")
+    m = int(b.edge_offsets[-1])
+    Gn = b.num_graphs
+    one_mst = torch.empty(m, dtype=torch.uint8, device=dev)
+    one_tot = torch.empty(1, dtype=torch.uint64, device=dev)
+    tots = np.zeros(Gn, np.int64)
+    sts = np.zeros(Gn, np.int32)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for g in range(Gn):
+        a, c = int(b.edge_offsets[g]), int(b.edge_offsets[g + 1])
+        n = int(b.vertex_offsets[g + 1] - b.vertex_offsets[g])
+        sts[g] = P.mst_solve(n, src[a:c], dst[a:c], w[a:c], one_mst[a:c], one_tot, stream)
+        tots[g] = int(one_tot.view(torch.int64).item())
+    torch.cuda.synchronize()
+    per_graph_s = time.perf_counter() - t0
+    same = bool(np.array_equal(one_mst.cpu().numpy(), got) and np.array_equal(tots, got_tot)
+                and np.array_equal(sts, got_st))
+    return {"value": Gn / per_graph_s, "unit": "solves/s", "ms_per_batch": per_graph_s * 1e3,
+            "bit_exact_vs_batched": same}
 
 
 def bench_batched(args, dev):
@@ -245,23 +326,9 @@ def bench_batched(args, dev):
     got_st = status.cpu().numpy()
 
     tuned.__exit__(None, None, None)
-    # plain path: one mst_solve per graph, same device arrays
-    log("[bench] per-graph path")
-    one_mst = torch.empty(m, dtype=torch.uint8, device=dev)
-    one_tot = torch.empty(1, dtype=torch.uint64, device=dev)
-    tots = np.zeros(Gn, np.int64)
-    sts = np.zeros(Gn, np.int32)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for g in range(Gn):
-        a, c = int(b.edge_offsets[g]), int(b.edge_offsets[g + 1])
-        n = int(b.vertex_offsets[g + 1] - b.vertex_offsets[g])
-        sts[g] = P.mst_solve(n, src[a:c], dst[a:c], w[a:c], one_mst[a:c], one_tot, stream)
-        tots[g] = int(one_tot.view(torch.int64).item())
-    torch.cuda.synchronize()
-    per_graph_s = time.perf_counter() - t0
-    same = bool(np.array_equal(one_mst.cpu().numpy(), got) and np.array_equal(tots, got_tot)
-                and np.array_equal(sts, got_st))
+    per_graph = None
+    if not args.no_per_graph:
+        per_graph = per_graph_leg(b, src, dst, w, got, got_tot, got_st, stream, dev)
     out = {
         "metric": METRIC,
         "value": Gn / (ms_per_step * 1e-3),
@@ -280,14 +347,14 @@ def bench_batched(args, dev):
                    "knobs": knobs or "library defaults",
                    "edges_per_s": m / (ms_per_step * 1e-3)},
         "roofline": {"bound": "hbm", "achieved": batch_bytes / (dev_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": batch_bytes / (dev_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": batch_bytes / (dev_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "traffic": traffic_for("k_batch_solve", args.workload),
                      "kernel": "k_batch_solve", "device_ms_per_call": dev_ms,
                      "alg_bytes": batch_bytes,
                      "alg_bytes_model": "one pass over the batch: 12 B per edge read, 1 B per edge written, "
                                         "12 B per graph"},
-        "per_graph_path": {"value": Gn / per_graph_s, "unit": "solves/s", "ms_per_batch": per_graph_s * 1e3,
-                           "bit_exact_vs_batched": same},
-        "speedup_vs_per_graph": (per_graph_s * 1e3) / ms_per_step,
+        "per_graph_path": per_graph,
+        "speedup_vs_per_graph": per_graph["ms_per_batch"] / ms_per_step if per_graph else None,
         "status_counts": {int(k): int(v) for k, v in zip(*np.unique(got_st, return_counts=True))},
     }
     if not args.no_cpu_baseline:
@@ -495,6 +562,8 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="time budget of the CPU oracle leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cold-reps", type=int, default=5, help="extra solves after a 1 GiB cache flush")
+    ap.add_argument("--no-per-graph", action="store_true",
+                    help="batched workload: leave out the per-graph comparison leg (counter runs)")
     ap.add_argument("--requests", type=int, default=160, help="served workload: requests per replay")
     ap.add_argument("--slots", type=int, default=3, help="served workload: concurrent server slots")
     ap.add_argument("--hbm-budget-gib", type=int, default=96, help="served workload: device memory budget")
@@ -506,7 +575,7 @@ def main() -> int:
     args = ap.parse_args()
 
     if args.summarize_pmc:
-        doc = summarize_pmc(*args.summarize_pmc, copy_mib=256, out_path=TRAFFIC_FILE)
+        doc = summarize_pmc(*args.summarize_pmc, copy_mib=256, workload=args.workload)
         print(json.dumps({k: round(v["traffic_bytes_mean"] / 1e6, 2) for k, v in doc["kernels"].items()}))
         return 0
 
@@ -628,6 +697,7 @@ def main() -> int:
     # per round: every kernel's mean duration per step, its algorithmic bytes
     # and fraction of the HBM peak (launches that returned at once included)
     per_round = []
+    counted = traffic_per_round(args.workload)
     for r, row in sorted(prof_rounds.items()):
         entry = {"round": r}
         if r < len(stats):
@@ -638,7 +708,9 @@ def main() -> int:
             us = ms * 1e3 / args.steps
             ks[name] = {"us_per_step": us, "launches_per_step": n_launch / args.steps,
                         "alg_bytes": b / args.steps,
-                        "frac": (b / args.steps) / (us * 1e-6) / 1e9 / HBM_PEAK_GBS if b and us else None}
+                        "frac": (b / args.steps) / (us * 1e-6) / 1e9 / HBM_PEAK_GBS if b and us else None,
+                        "traffic": (counted[r].get(name, {}).get("traffic_bytes")
+                                    if counted and r < len(counted) else None)}
         entry["kernels"] = ks
         entry["us_per_step"] = sum(v["us_per_step"] for v in ks.values())
         per_round.append(entry)
@@ -673,7 +745,7 @@ def main() -> int:
                    "leg": "single graph", "rounds": int(len(stats)), "knobs": knobs or "library defaults",
                    "round_stats": stats.tolist()},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for(bound_kernel),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for(bound_kernel, args.workload),
                      "kernel": bound_kernel},
         "kernels": kernels,
         "scan_family": {"ms_per_step": scan_ms / args.steps, "alg_bytes_per_step": scan_bytes / args.steps,

@@ -325,17 +325,21 @@ struct LaunchTimer {
   }
   // After the stream is synchronised.  chosen[r] = mode that ran in round r,
   // bytes[r] = algorithmic bytes of round r's scan, bmin[r] those of its
-  // bucket minima; rounds >= nrounds were idle.
-  void commit(int nrounds, const int* chosen, const double* bytes, const double* bmin) {
+  // bucket minima, other[r][kind] those of the round's other kernels (the
+  // mode-bound ones count when their mode ran); rounds >= nrounds were idle.
+  void commit(int nrounds, const int* chosen, const double* bytes, const double* bmin,
+              const double (*other)[kKinds]) {
     if (!on) return;
     std::lock_guard<std::mutex> g(g_prof.mu);
     for (const auto& p : pending) {
       float ms = 0.f;
       if (hipEventElapsedTime(&ms, p.a, p.b) != hipSuccess) continue;
       double b = 0.0;
-      if (p.round < nrounds && p.mode == chosen[p.round]) {
-        if (p.kind < kScanKinds) b = bytes[p.round];
-        else if (p.kind == kBucketMin) b = bmin[p.round];
+      if (p.round >= 0 && p.round < nrounds) {
+        const bool moded = p.kind < kScanKinds || p.kind == kBucketMin || p.kind == kSlabMin_ || p.kind == kDenseFinish;
+        if (!moded) b = other[p.round][p.kind];
+        else if (p.mode == chosen[p.round])
+          b = p.kind < kScanKinds ? bytes[p.round] : (p.kind == kBucketMin ? bmin[p.round] : other[p.round][p.kind]);
       }
       g_prof.ms[p.kind] += ms;
       g_prof.launches[p.kind] += 1;
@@ -618,6 +622,35 @@ double round_scan_bytes(const HostRound* rec, const int32_t* nr_of, int r, int64
   return b;
 }
 
+// Algorithmic bytes of round r's kernels other than the scan and the bucket
+// minima (all bound by latency: random gathers, one-workgroup chains), per
+// component c of the n_r: the hook reads best[c], the record at its key (the
+// 4-byte end xor in round 0, a 12-byte narrow record with its edge index,
+// else 16 B) and best of the far end, and writes parent and in_mst of the
+// s_r components that hook; compress reads a parent and best[c] and writes
+// the root (16 B, bits aside); finalize reads and writes one word per 64
+// components and two counts per segment; relabel reads the root, its mask
+// word and prefix and writes the label (20 B), and resets the next round's
+// minimum and parent (12 B per component of round r + 1); the round tail
+// does hook, relabel and resets in one (best, record, label, in_mst, resets);
+// the dense finish reads its pair table once.  Walks longer than one step
+// and the composed label maps are not counted.
+void other_bytes(const HostRound* rec, const int32_t* nr_of, int r, int nseg, double (&out)[kKinds]) {
+  for (double& x : out) x = 0.0;
+  const HostRound& M = rec[r];
+  const double n = (double)nr_of[r], nn = (double)M.n_next, sel = (double)M.sel;
+  const double recb = r == 0 ? 4.0 : (nr_of[r] <= kNarrowMax ? 12.0 : 16.0);
+  if (M.dense) {
+    out[kDenseFinish] = 8.0 * (double)dense_pairs(nr_of[r]);
+    return;
+  }
+  out[kHook] = (16.0 + recb) * n + 5.0 * sel;
+  out[kCompress] = 16.0 * n;
+  out[kFinalize] = 8.0 * n / 64.0 + 8.0 * (double)nseg;
+  out[kRelabel] = 20.0 * n + 12.0 * nn;
+  out[kRoundTail] = (8.0 + recb + 4.0) * n + 5.0 * sel + 12.0 * nn + 8.0 * (double)nseg;
+}
+
 // What the host learns from the round records of one solve.
 struct RoundLoop {
   int32_t n = 0;
@@ -654,7 +687,9 @@ struct RoundLoop {
     T.rounds = rounds;
     int chosen[kMaxRounds + 1];
     double bytes[kMaxRounds + 1], bmin[kMaxRounds + 1];
+    double other[kMaxRounds + 1][kKinds];
     for (int r = 0; r < rounds; ++r) {
+      other_bytes(rec, nr_of, r, S.L.nseg, other[r]);
       T.v[3 * r + 0] = nr_of[r];
       T.v[3 * r + 1] = rec[r].live;
       T.v[3 * r + 2] = rec[r].sel;
@@ -663,7 +698,7 @@ struct RoundLoop {
       // bucket minima: two 8-byte offers per live edge read, one 8-byte minimum per component written
       bmin[r] = 16.0 * (double)rec[r].live + 8.0 * (double)nr_of[r];
     }
-    t_timer.commit(rounds, chosen, bytes, bmin);
+    t_timer.commit(rounds, chosen, bytes, bmin, other);
   }
 };
 
@@ -807,7 +842,7 @@ int solve_small_locked(DeviceCache* dc, int32_t n, int64_t m, const int32_t* src
   const int rows = (int)std::min<int64_t>(std::max<int64_t>(st[0], 0), kMaxRounds + 1);
   // algorithmic bytes: every round reads the 12-byte edges once, plus one
   // final round that finds nothing to add
-  T.commit(0, nullptr, nullptr, nullptr);
+  T.commit(0, nullptr, nullptr, nullptr, nullptr);
   if (T.on) {
     std::lock_guard<std::mutex> g(g_prof.mu);
     g_prof.bytes[kSmallSolve] += 12.0 * (double)m * (double)(rows + 1);
