@@ -93,9 +93,11 @@ def batch_class(num_graphs: int, sum_m: int) -> str:
 
 
 def device_key() -> str:
+    """The device's ISA and compute-unit count (the marketing name is not used:
+    the same card reports different names depending on the installed id tables)."""
     import torch
     p = torch.cuda.get_device_properties(torch.cuda.current_device())
-    return f"{p.name}/{getattr(p, 'gcnArchName', '')}"
+    return f"{getattr(p, 'gcnArchName', '')}/cu{p.multi_processor_count}"
 
 
 def load_cache(path: Optional[str] = None) -> dict:
