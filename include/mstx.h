@@ -320,9 +320,10 @@ int32_t mst_set_mid_limit(int32_t limit);
 /*
  * Late rounds (Section 2.2.2's union and find, one launch): when mst_solve's
  * bound on a round's component count is at most `limit`, the round's hook
- * (compare-and-swap of the larger root under the smaller), pointer jumping,
- * root count and relabel run in one workgroup with the parent forest in LDS,
- * instead of four grid-wide kernels.  The tree, the labels and the round
+ * (each component's parent is the component its lightest edge reaches; the
+ * smaller of a mutual pair stays a root), pointer jumping, root count and
+ * relabel run in one workgroup with the parent forest in LDS, instead of
+ * four grid-wide kernels.  The tree, the labels and the round
  * statistics are the same.  limit is clamped to [0, 10240] (0: off; the
  * default is 10240); limit < 0 only queries.  Returns the previous limit.
  * Process-wide; read at the start of each call (mst_solve_batched's large
