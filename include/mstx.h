@@ -357,6 +357,22 @@ int32_t mst_set_bucket_limit(int32_t limit);
  */
 int32_t mst_set_scan_occupancy(int32_t wg_per_cu);
 
+/*
+ * Sparse finish (the cycle property of Section 2.1's covered edges, applied
+ * to component pairs): in a round r >= 1 of mst_solve whose previous round
+ * had at most 16384 components, if at most `live_edges` live edges were left
+ * two rounds before, the lightest edge of every pair of components is
+ * collected and, when the pairs fit one workgroup (about 13,000 pairs at
+ * few components, fewer as the count grows), the remaining Boruvka rounds
+ * run on that small graph in one launch and the solve ends in that round.
+ * Otherwise the round goes on as usual.  The tree and total are the same;
+ * the round statistics then end with that round, whose edges added are the
+ * sum of the remaining rounds'.  0 = never; the default is 2^20; limit < 0
+ * only queries.  Returns the previous value.  Process-wide; read at the start
+ * of each call.
+ */
+int32_t mst_set_sparse_limit(int32_t live_edges);
+
 /* Static description of a status code. */
 const char* mst_status_string(int status);
 

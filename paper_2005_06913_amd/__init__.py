@@ -37,6 +37,8 @@ from .binding import (  # noqa: F401
     mst_set_dense_limit,
     mst_set_mid_limit,
     mst_set_scan_occupancy,
+    mst_set_sparse_limit,
+    sparse_limit,
     mst_set_small_limit,
     mst_set_tail_limit,
     mst_solve,

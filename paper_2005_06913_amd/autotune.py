@@ -15,8 +15,8 @@ bucket of graph shapes:
 
 Knobs (the C ABI setters of ``include/mstx.h``): the dense-finish limit, the
 round-tail limit, the one-workgroup limit for small single graphs, the
-bucket-mode limit, the LDS-mode scan occupancy, and for batches the mid-size
-limit.  The search is coordinate descent from the defaults: each knob in
+bucket-mode limit, the LDS-mode scan occupancy, the sparse-finish limit, and
+for batches the mid-size limit.  The search is coordinate descent from the defaults: each knob in
 turn takes the candidate value that is fastest with the others fixed, two
 passes.
 
@@ -50,6 +50,7 @@ SINGLE_KNOBS: Dict[str, Sequence[int]] = {
     "small_limit": (0, 8192),
     "bucket_limit": (0, 16760832),
     "scan_occupancy": (0, 1, 2, 4),
+    "sparse_limit": (0, 1 << 20),
 }
 BATCH_KNOBS: Dict[str, Sequence[int]] = {
     "mid_limit": (8192, 12288, 16280),
@@ -64,6 +65,7 @@ SETTERS: Dict[str, Callable[[int], int]] = {
     "bucket_limit": B.mst_set_bucket_limit,
     "scan_occupancy": B.mst_set_scan_occupancy,
     "mid_limit": B.mst_set_mid_limit,
+    "sparse_limit": B.mst_set_sparse_limit,
 }
 
 

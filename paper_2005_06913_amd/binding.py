@@ -30,7 +30,7 @@ EXPORTS = ("mst_solve", "mst_solve_batched", "mst_batched_workspace_bytes", "mst
            "mst_profile_read", "mst_profile_kernel_name", "mst_workspace_release", "mst_set_dense_limit", "mst_set_small_limit",
            "mst_set_tail_limit", "mst_set_mid_limit", "mst_set_bucket_limit", "mst_csr_to_edges",
            "mst_solve_noalloc", "mst_profile_read_rounds", "mst_set_scan_occupancy", "mst_solve_begin",
-           "mst_solve_advance", "mst_solve_end")
+           "mst_solve_advance", "mst_solve_end", "mst_set_sparse_limit")
 
 _lib = None
 
@@ -93,6 +93,8 @@ def load_library(path: str = LIB_PATH):
     lib.mst_set_scan_occupancy.restype = ctypes.c_int32
     lib.mst_set_bucket_limit.argtypes = [ctypes.c_int32]
     lib.mst_set_bucket_limit.restype = ctypes.c_int32
+    lib.mst_set_sparse_limit.argtypes = [ctypes.c_int32]
+    lib.mst_set_sparse_limit.restype = ctypes.c_int32
     lib.mst_profile_read_rounds.argtypes = [p, p, p, i32]
     lib.mst_profile_read_rounds.restype = ctypes.c_int
     lib.mst_profile_kernel_name.argtypes = [ctypes.c_int]
@@ -162,6 +164,27 @@ def mst_set_bucket_limit(limit: int) -> int:
     (0: never bucket mode; clamped to 16760832; negative: query).  Returns the
     previous limit."""
     return int(load_library().mst_set_bucket_limit(int(limit)))
+
+
+def mst_set_sparse_limit(live_edges: int) -> int:
+    """Set the live-edge bound under which a late round tries the sparse finish
+    (0: never; negative: query).  Returns the previous value."""
+    return int(load_library().mst_set_sparse_limit(int(live_edges)))
+
+
+class sparse_limit:
+    """Context manager: ``with sparse_limit(0): ...`` never tries the sparse finish."""
+
+    def __init__(self, limit: int):
+        self.limit = limit
+
+    def __enter__(self):
+        self.prev = mst_set_sparse_limit(self.limit)
+        return self
+
+    def __exit__(self, *exc):
+        mst_set_sparse_limit(self.prev)
+        return False
 
 
 def mst_set_scan_occupancy(wg_per_cu: int) -> int:

@@ -44,7 +44,7 @@ constexpr int kMaxGrid = 4096;  // capacity of the per-block partial arrays (hoo
 
 struct Layout {
   size_t best, parent, root_of, labpool, cmap, rootmask, rootcnt, rootpre, rec, seg_cnt, seg_live, part_sel,
-      part_w, state, pbest, btot, offers, offT, slab, bytes;
+      part_w, state, pbest, btot, sp_pid, sp_key, sp_state, offers, offT, slab, bytes;
   int64_t slab_cap;  // u64 entries of the LDS-mode slab (0: none)
   int32_t nseg;
   bool bucket;  // offer buffers present
@@ -84,6 +84,9 @@ Layout plan(int32_t n, int64_t m) {
   L.state = take(sizeof(DevState));
   L.pbest = take(8 * (size_t)kDensePairsMax);
   L.btot = take(4 * (size_t)kMaxBuckets);
+  L.sp_pid = take(4 * (size_t)kSparseHash);  // the sparse finish's pair table
+  L.sp_key = take(8 * (size_t)kSparseHash);
+  L.sp_state = take(16);
   L.slab_cap = n > kSlabMin ? (int64_t)kSlabRows * std::min<int32_t>(n, kLdsSlots) : 0;
   if (L.slab_cap) L.slab = take(8 * (size_t)L.slab_cap);
   if (L.bucket) {
@@ -140,6 +143,11 @@ std::atomic<int64_t> g_bucket_limit{kBucketMaxComponents};
 // most 4; else this many as far as 160 KB of LDS per CU holds them);
 // mst_set_scan_occupancy() changes it.
 std::atomic<int> g_scan_occupancy{0};
+// The sparse finish is tried in a round whose bound on the component count
+// is at most kSparseMaxK when at most this many live edges were left two
+// rounds before (0: never); mst_set_sparse_limit() changes it.
+constexpr int32_t kSparseLiveDefault = 1 << 20;
+std::atomic<int> g_sparse_limit{kSparseLiveDefault};
 std::map<std::pair<int, hipStream_t>, std::unique_ptr<DeviceCache>> g_caches;
 
 // Per-round statistics of the calling thread's last single-graph solve
@@ -244,7 +252,8 @@ int rounds_bound(int32_t n) {
 // round statistics).
 enum Kind {
   kScanFirst = 0,  // 4 stages x 4 minima modes: kind = kNumModes * stage + mode
-  kBucketMin = 16, kSlabMin_, kDenseFinish, kHook, kCompress, kFinalize, kRelabel, kSmallSolve, kRoundTail, kKinds
+  kBucketMin = 16, kSlabMin_, kDenseFinish, kHook, kCompress, kFinalize, kRelabel, kSmallSolve, kRoundTail,
+  kPairCollect, kSparseFinish, kKinds
 };
 constexpr int kScanKinds = 16;
 // Names as rocprofv3 reports the kernels (template arguments: minima mode
@@ -257,7 +266,7 @@ const char* const kKindNames[kKinds] = {
     "k_scan<0, 2>", "k_scan<1, 2>", "k_scan<2, 2>", "k_scan<3, 2>",
     "k_scan<0, 3>", "k_scan<1, 3>", "k_scan<2, 3>", "k_scan<3, 3>",
     "k_bucket_min", "k_slab_min", "k_dense_finish", "k_hook", "k_compress", "k_finalize", "k_relabel",
-    "k_small_solve", "k_round_tail"};
+    "k_small_solve", "k_round_tail", "k_pair_collect", "k_sparse_finish"};
 
 int scan_kind(int stage, int mode) { return kNumModes * stage + mode; }
 
@@ -394,7 +403,11 @@ struct Solve {
   unsigned long long* slab;
   unsigned long long* pbest;
   uint32_t* btot;
+  SparseTable sp;
   int dense_limit;            // 0: no dense finish
+  int64_t sparse_limit;       // live-edge bound below which the sparse finish is tried (0: never)
+  int64_t live_rec[kMaxRounds + 1];  // live edges of round r, from its record (taken before round r + 2 is enqueued)
+  bool sparse_tried[kMaxRounds + 1];
   int tail_limit;             // 0: every round takes the multi-workgroup hook .. relabel
   int64_t bucket_limit;       // largest bound that may take bucket mode (0: never)
   int launched[kMaxRounds + 1];  // per round
@@ -502,8 +515,30 @@ hipError_t enqueue_round(Solve& S, int r, int64_t bound, int64_t n_prev, bool ex
   S.dom[r] = r == 0 ? 0 : (S.keep[r - 1] == kKeepRecords ? S.dom[r - 1] : n_prev);
   S.launched[r] = enqueue_scan(S, r, stage, bound, exact, err, S.dom[r]);
   if (err != hipSuccess) return err;
+  // the live edges two rounds before (the input's before round 1) are known
+  // to every round loop when it enqueues round r, so every loop tries the
+  // same rounds (the kernels check the exact count and mode themselves)
+  const int64_t live_before = r >= 2 ? S.live_rec[r - 2] : S.m;
+  if (r >= 1 && bound <= kSparseMaxK && S.sparse_limit > 0 && live_before <= S.sparse_limit &&
+      (S.launched[r] & (1 << kModeLds))) {
+    // few live edges left: try to end the solve on the graph of component pairs
+    S.sparse_tried[r] = true;
+    int k = T.start(kPairCollect, r, -1);
+    err = launch_pair_collect(r, S.launched[r], S.rec, S.labpool, S.seg_cnt, S.L.nseg, S.sp, S.st,
+                              std::min(S.L.nseg, 4 * S.cus), S.s);
+    T.stop(k);
+    if (err != hipSuccess) return err;
+    k = T.start(kSparseFinish, r, -1);
+    err = launch_sparse_finish(r, S.launched[r], S.rec, S.sp, S.seg_live, S.L.nseg, S.in_mst, S.total, S.st,
+                               S.rounds, S.s);
+    T.stop(k);
+    if (err != hipSuccess) return err;
+  }
   const int gh = grid_for(std::max<int64_t>(bound, 1));
-  if (bound <= S.tail_limit) {
+  // a round that tried the sparse finish (bound <= kSparseMaxK <= kTailMax)
+  // closes in one workgroup: one launch that returns when the finish ended
+  // the solve, instead of four
+  if (bound <= S.tail_limit || S.sparse_tried[r]) {
     // few components: the rest of the round in one workgroup
     const int k = T.start(kRoundTail, r, -1);
     err = launch_round_tail(r, (int32_t)bound, S.rec, S.best, S.parent, S.labpool, S.seg_cnt, S.seg_live,
@@ -592,7 +627,11 @@ Solve make_solve(void* B, int cus, HostRound* rounds, hipEvent_t* events, const 
   S.slab = L.slab_cap ? at<unsigned long long>(B, L.slab) : nullptr;
   S.pbest = at<unsigned long long>(B, L.pbest);
   S.btot = at<uint32_t>(B, L.btot);
+  S.sp = SparseTable{at<uint32_t>(B, L.sp_pid), at<unsigned long long>(B, L.sp_key), at<uint32_t>(B, L.sp_state)};
   S.dense_limit = g_dense_limit.load();
+  S.sparse_limit = g_sparse_limit.load();
+  for (int64_t& x : S.live_rec) x = m;
+  for (bool& x : S.sparse_tried) x = false;
   S.tail_limit = g_tail_limit.load();
   S.bucket_limit = g_bucket_limit.load();
   for (int& x : S.launched) x = 0;
@@ -612,11 +651,12 @@ double round_scan_bytes(const HostRound* rec, const int32_t* nr_of, int r, int64
   const HostRound& M = rec[r];
   const double nrd = (double)nr_of[r];
   const bool narrow_in = r >= 2 && nr_of[r - 1] <= kNarrowMax;
-  const bool moves = r >= 1 && !M.dense && M.keep == kMoveRecords;
-  const bool relabels = !M.dense && M.keep == kRelabelRecords;
+  const bool dense = M.dense == 1;  // the dense finish's round (2: the sparse finish, an LDS round)
+  const bool moves = r >= 1 && !dense && M.keep == kMoveRecords;
+  const bool relabels = !dense && M.keep == kRelabelRecords;
   double b = r <= 1 ? 12.0 * (double)m : (narrow_in ? (moves ? 12.0 : 8.0) : 16.0) * (double)M.stream;
   b += 4.0 * (double)M.map_n;
-  b += M.dense ? 8.0 * (double)dense_pairs(nr_of[r]) : 16.0 * nrd;
+  b += dense ? 8.0 * (double)dense_pairs(nr_of[r]) : 16.0 * nrd;
   if (moves) b += (nr_of[r] <= kNarrowMax ? 12.0 : 16.0) * (double)M.live;
   if (relabels) b += 8.0 * (double)M.stream;
   return b;
@@ -635,15 +675,23 @@ double round_scan_bytes(const HostRound* rec, const int32_t* nr_of, int r, int64
 // does hook, relabel and resets in one (best, record, label, in_mst, resets);
 // the dense finish reads its pair table once.  Walks longer than one step
 // and the composed label maps are not counted.
-void other_bytes(const HostRound* rec, const int32_t* nr_of, int r, int nseg, double (&out)[kKinds]) {
+void other_bytes(const HostRound* rec, const int32_t* nr_of, int r, int nseg, bool sparse_tried,
+                 double (&out)[kKinds]) {
   for (double& x : out) x = 0.0;
   const HostRound& M = rec[r];
   const double n = (double)nr_of[r], nn = (double)M.n_next, sel = (double)M.sel;
   const double recb = r == 0 ? 4.0 : (nr_of[r] <= kNarrowMax ? 12.0 : 16.0);
-  if (M.dense) {
+  if (sparse_tried) {
+    // the pair collection reads every live record once (8 B) and lowers a
+    // 12-byte pair slot for it; the finish reads and empties the table
+    out[kPairCollect] = 20.0 * (double)M.live;
+    out[kSparseFinish] = 24.0 * (double)kSparseHash + 8.0 * (double)nseg;
+  }
+  if (M.dense == 1) {
     out[kDenseFinish] = 8.0 * (double)dense_pairs(nr_of[r]);
     return;
   }
+  if (M.dense == 2) return;  // the sparse finish ended the solve: no hook or relabel ran
   out[kHook] = (16.0 + recb) * n + 5.0 * sel;
   out[kCompress] = 16.0 * n;
   out[kFinalize] = 8.0 * n / 64.0 + 8.0 * (double)nseg;
@@ -689,7 +737,7 @@ struct RoundLoop {
     double bytes[kMaxRounds + 1], bmin[kMaxRounds + 1];
     double other[kMaxRounds + 1][kKinds];
     for (int r = 0; r < rounds; ++r) {
-      other_bytes(rec, nr_of, r, S.L.nseg, other[r]);
+      other_bytes(rec, nr_of, r, S.L.nseg, S.sparse_tried[r], other[r]);
       T.v[3 * r + 0] = nr_of[r];
       T.v[3 * r + 1] = rec[r].live;
       T.v[3 * r + 2] = rec[r].sel;
@@ -708,7 +756,7 @@ hipError_t start_solve(const Solve& S) {
   if (e == hipSuccess) e = hipMemsetAsync(S.total, 0, sizeof(uint64_t), S.s);
   if (e == hipSuccess)
     e = launch_init(S.n, S.m, (int64_t)((S.L.cmap - S.L.labpool) / 4), S.dense_limit, S.best, S.parent,
-                    S.dense_limit > 0 ? S.pbest : nullptr, S.btot, S.st, grid_for(S.n), S.s);
+                    S.dense_limit > 0 ? S.pbest : nullptr, S.btot, S.sp, S.st, grid_for(S.n), S.s);
   return e;
 }
 
@@ -756,17 +804,20 @@ struct RoundMachine {
         done = true;  // round-count watchdog: status stays MSTX_ERR_DEVICE
         break;
       }
+      if (r_enq < r) {
+        // round r - 1 tried the sparse finish and went on: round r was not
+        // enqueued ahead, and its count is known exactly now
+        HIP_OK(enqueue_round(S, r, n_known, R.nr_of[r - 1], true));
+        r_enq = r;
+      }
       // a round whose scan takes the dense finish (its count n_known is exact
-      // here) is the last one: nothing to enqueue after it
+      // here) is the last one: nothing to enqueue after it; a round that tries
+      // the sparse finish usually is, so the next one waits for its record
       const bool final_round = pick_mode(n_known, S.launched[r]) == kModeDense;
-      if (r_enq == r && r + 1 <= kMaxRounds - 1 && !final_round) {
+      if (r_enq == r && r + 1 <= kMaxRounds - 1 && !final_round && !S.sparse_tried[r]) {
         // n_known entered round r: the size of the label map round r + 1 reads
         HIP_OK(enqueue_round(S, r + 1, n_known / 2, n_known, false));
         r_enq = r + 1;
-      }
-      if (r_enq < r) {
-        done = true;  // never: the round before was final (status stays MSTX_ERR_DEVICE)
-        break;
       }
       if (block) {
         HIP_OK(hipEventSynchronize(ev[r]));
@@ -790,6 +841,7 @@ struct RoundMachine {
       }
       R.take(r, M);
       S.keep[r + 1] = M.keep_next;
+      S.live_rec[r] = M.live;
       if (R.done) {
         done = true;
         break;
@@ -978,6 +1030,7 @@ int solve_noalloc(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, 
       }
       R.take(r, h[r]);
       S.keep[r + 1] = h[r].keep_next;
+      S.live_rec[r] = h[r].live;
     }
     if (R.done) break;
     const int r = r_enq + 1;  // its component count is known exactly now
@@ -1418,7 +1471,7 @@ int select_min_edges(int32_t n, int64_t m, const int32_t* src, const int32_t* ds
   t_timer.begin(s);
   t_timer.on = false;
   HIP_OK(launch_init(n, m, (int64_t)((L.cmap - L.labpool) / 4), 0, S.best, at<int32_t>(B, L.parent), nullptr,
-                     S.btot, S.st, grid_for(n), s));
+                     S.btot, SparseTable{nullptr, nullptr, nullptr}, S.st, grid_for(n), s));
   if (m > 0) {
     hipError_t err = hipSuccess;
     enqueue_scan(S, 0, 0, n, true, err);
@@ -1613,6 +1666,11 @@ int32_t mst_set_tail_limit(int32_t limit) {
 int32_t mst_set_bucket_limit(int32_t limit) {
   if (limit < 0) return (int32_t)mstx::g_bucket_limit.load();
   return (int32_t)mstx::g_bucket_limit.exchange(std::min<int64_t>(limit, mstx::kBucketMaxComponents));
+}
+
+int32_t mst_set_sparse_limit(int32_t live_edges) {
+  if (live_edges < 0) return mstx::g_sparse_limit.load();
+  return mstx::g_sparse_limit.exchange(live_edges);
 }
 
 int32_t mst_set_scan_occupancy(int32_t wg_per_cu) {

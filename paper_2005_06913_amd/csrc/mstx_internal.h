@@ -97,6 +97,22 @@ static_assert(kDensePairsMax <= kLdsSlots && kDenseMax < 256, "dense limit");
 // in LDS, 8 bytes per component, and ten components' edges per thread in
 // registers).
 static constexpr int32_t kTailMax = 10240;
+// Sparse finish: a late round of at most kSparseMaxK components whose live
+// edges join few distinct component pairs collects the lightest edge of every
+// pair into a hash table of kSparseHash slots in the workspace (pair id,
+// key; k_pair_collect) and, when they fit one workgroup's LDS as a small
+// graph (sparse_pair_cap: 12 B per pair beside 18 B per component), finishes
+// the solve there (k_sparse_finish); otherwise the round goes on as usual.
+static constexpr int32_t kSparseMaxK = 8192;
+static constexpr int kSparseHashBits = 15;
+static constexpr int32_t kSparseHash = 1 << kSparseHashBits;
+static constexpr int kSparseProbes = 64;  // a longer probe sequence counts as overflow
+__host__ __device__ constexpr int32_t sparse_pair_cap(int32_t k) {
+  return (int64_t)kMaxDynLds - 18 * (int64_t)k - 64 <= 0 ? 0
+                                                          : (int32_t)(((int64_t)kMaxDynLds - 18 * (int64_t)k - 64) / 12);
+}
+static_assert(2 * sparse_pair_cap(0) <= kSparseHash, "hash load factor at most one half");
+static_assert(kSparseMaxK <= kTailMax, "a round that tries the sparse finish can close in one workgroup");
 // index of the unordered pair {a, b}, a < b < k, in row-major upper-triangle order
 __host__ __device__ inline int32_t pair_index(int32_t a, int32_t b, int32_t k) {
   return a * k - a * (a + 1) / 2 + (b - a - 1);
@@ -216,7 +232,7 @@ struct HostRound {
   int32_t n_next;
   int32_t err;
   int32_t err_internal;
-  int32_t dense;  // 1: the dense finish ended the solve in this round
+  int32_t dense;  // 1: the dense finish ended the solve in this round, 2: the sparse finish
   int64_t live;
   int64_t sel;
   int64_t edges_added;
@@ -374,9 +390,23 @@ hipError_t launch_graph_epilogue(const int32_t* glist, int ng, const int64_t* vo
                                  const uint32_t* gw, const int32_t* gbad, uint8_t* in_mst,
                                  unsigned long long* acc_w, uint32_t* acc_c, unsigned long long* total,
                                  int32_t* status, hipStream_t s);
+// The sparse finish's pair table in the workspace (all null: none).
+struct SparseTable {
+  uint32_t* pid;            // [kSparseHash] lo * n_r + hi of the pair held, kPairEmpty: free
+  unsigned long long* key;  // [kSparseHash] lightest key of that pair
+  uint32_t* state;          // [0] slots claimed, [1] overflow
+};
+static constexpr uint32_t kPairEmpty = 0xFFFFFFFFu;
+
 hipError_t launch_init(int32_t n, int64_t m, int64_t cmap_off, int dense_limit, unsigned long long* best,
-                       int32_t* parent, unsigned long long* pbest, uint32_t* btot, DevState* st, int grid,
-                       hipStream_t s);
+                       int32_t* parent, unsigned long long* pbest, uint32_t* btot, SparseTable sp, DevState* st,
+                       int grid, hipStream_t s);
+hipError_t launch_pair_collect(int round, int launched, const uint4* rec, const int32_t* labpool,
+                               const uint32_t* seg_cnt, int32_t nseg, SparseTable sp, const DevState* st, int grid,
+                               hipStream_t s);
+hipError_t launch_sparse_finish(int round, int launched, const uint4* rec, SparseTable sp, const uint32_t* seg_live,
+                                int32_t nseg, uint8_t* in_mst, unsigned long long* total, DevState* st,
+                                HostRound* host, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, int64_t count, unsigned long long v, int grid,
                            hipStream_t s);
 hipError_t launch_scan(int mode, int stage, const ScanArgs& a, int grid, size_t lds, hipStream_t s);

@@ -163,8 +163,16 @@ __device__ __forceinline__ void stage_map(LabT* dst, const int32_t* __restrict__
 // best[0..n) <- none, parent[c] <- c, state for round 0.
 __global__ void __launch_bounds__(kBlock) k_init(int32_t n, int64_t m, int64_t cmap_off, int dense_limit,
                                                  unsigned long long* best, int32_t* parent,
-                                                 unsigned long long* pbest, uint32_t* btot, DevState* st) {
+                                                 unsigned long long* pbest, uint32_t* btot, SparseTable sp,
+                                                 DevState* st) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  if (sp.pid) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < kSparseHash; i += stride) {
+      sp.pid[i] = kPairEmpty;
+      sp.key[i] = kKeyNone;
+    }
+    if (blockIdx.x == 0 && threadIdx.x < 2) sp.state[threadIdx.x] = 0;
+  }
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += stride) {
     best[c] = kKeyNone;
     parent[c] = (int32_t)c;
@@ -1133,6 +1141,402 @@ __global__ void __launch_bounds__(kDenseThreads) k_dense_finish(int round, int l
   }
 }
 
+// ------------------------------------------------------------ sparse finish
+
+// The cycle property of the dense finish, for a late round whose live edges
+// join few distinct pairs of components (a sparse graph, e.g. a grid, has a
+// few neighbours per component): only the lightest edge of every pair can
+// be in the tree, so when the pairs fit one workgroup's LDS, Boruvka on the
+// graph of components and pair-minimum edges ends the solve in one launch.
+//
+// k_pair_collect runs after an LDS-mode scan of round r >= 1 with n_r <=
+// kSparseMaxK: it reads the records that scan left (narrow, with this
+// round's labels, or kept with older ones, then mapped as the scan mapped
+// them), and for every live one lowers the key of its pair {lo, hi} in an
+// open-addressing table (slot claimed by compare-and-swap of the pair id,
+// key lowered by an atomic minimum).  The key is the one the scan built: the
+// weight and the record's position in the stream.  A probe sequence longer
+// than kSparseProbes sets the overflow word; the finish counts the pairs
+// against sparse_pair_cap(n_r).
+__device__ __forceinline__ uint32_t pair_hash(uint32_t pid) {
+  return (pid * 2654435761u) >> (32 - kSparseHashBits);
+}
+
+// Lowers the key of pair `pid` in the table: the slot is claimed (or found)
+// by one compare-and-swap per probe, the key lowered by an atomic minimum
+// whose result is not waited for.  True when no slot was found within
+// kSparseProbes probes (overflow).  The finish counts the pairs.
+__device__ __forceinline__ bool pair_insert(const SparseTable& sp, uint32_t pid, unsigned long long key) {
+  uint32_t slot = pair_hash(pid);
+  for (int probe = 0; probe < kSparseProbes; ++probe) {
+    const uint32_t cur = atomicCAS(sp.pid + slot, kPairEmpty, pid);
+    if (cur == kPairEmpty || cur == pid) {
+      atomicMin(sp.key + slot, key);
+      return false;
+    }
+    slot = (slot + 1) & (uint32_t)(kSparseHash - 1);
+  }
+  return true;
+}
+
+// Each workgroup first merges its segment's pairs in an LDS table of
+// kPairLds slots (a segment of a late round's stream holds few distinct
+// pairs: its edges are neighbours in the input order), lists the occupied
+// slots, and inserts every distinct pair once into the global table, one
+// list entry per thread at a time; a record that finds no LDS slot goes to
+// the global table directly.
+static constexpr int kPairLds = 2048;
+static constexpr int kPairLdsProbes = 16;
+
+__global__ void __launch_bounds__(kBlock) k_pair_collect(int round, int launched, const uint4* __restrict__ rec,
+                                                         const int32_t* __restrict__ labpool,
+                                                         const uint32_t* __restrict__ seg_cnt, int32_t nseg,
+                                                         SparseTable sp, const DevState* __restrict__ st) {
+  __shared__ uint32_t lpid[kPairLds];
+  __shared__ unsigned long long lkey[kPairLds];
+  __shared__ uint16_t list[kPairLds];
+  __shared__ uint32_t nlist;
+  if (round < 1) return;
+  const int32_t nr = st->n[round];
+  // tried where half the previous round's count is within kSparseMaxK: the
+  // bound every round loop had when it enqueued this round (so every loop
+  // tries the same rounds)
+  if (nr <= 1 || st->n[round - 1] / 2 > kSparseMaxK) return;
+  if (st->err || st->dense_at >= 0) return;
+  if (pick_mode(nr, launched) != kModeLds) return;
+  const bool kept = st->keep[round] == kKeepRecords;
+  const int32_t* map = labpool + st->map_off[round];
+  const unsigned long long* nrec = reinterpret_cast<const unsigned long long*>(rec);
+  bool over = false;
+  for (int32_t s = blockIdx.x; s < nseg; s += gridDim.x) {
+    for (int i = threadIdx.x; i < kPairLds; i += kBlock) {
+      lpid[i] = kPairEmpty;
+      lkey[i] = kKeyNone;
+    }
+    if (threadIdx.x == 0) nlist = 0;
+    __syncthreads();
+    const uint32_t cnt = seg_cnt[s];
+    const uint32_t base = (uint32_t)s * (uint32_t)kSegCap;
+    for (uint32_t j = threadIdx.x; j < cnt; j += kBlock) {
+      const unsigned long long x = nrec[narrow_rec_index(base + j)];
+      int32_t a = (int32_t)(x & 0xFFFFu), b = (int32_t)((x >> 16) & 0xFFFFu);
+      if (kept) {
+        a = map[a];
+        b = map[b];
+      }
+      if (a == b || (a | b) < 0 || a >= nr || b >= nr) continue;  // internal, isolated (or never: out of range)
+      const uint32_t lo = (uint32_t)(a < b ? a : b), hi = (uint32_t)(a < b ? b : a);
+      const uint32_t pid = lo * (uint32_t)nr + hi;
+      const unsigned long long key = (x & 0xFFFFFFFF00000000ull) | (unsigned long long)(base + j);
+      uint32_t slot = (pid * 2654435761u) >> (32 - 11);
+      bool placed = false;
+      for (int probe = 0; probe < kPairLdsProbes; ++probe) {
+        uint32_t cur = atomicCAS(lpid + slot, kPairEmpty, pid);
+        if (cur == kPairEmpty) list[atomicAdd(&nlist, 1u)] = (uint16_t)slot;
+        if (cur == kPairEmpty || cur == pid) {
+          lower_lds(lkey, (int32_t)slot, key);
+          placed = true;
+          break;
+        }
+        slot = (slot + 1) & (uint32_t)(kPairLds - 1);
+      }
+      if (!placed) over = pair_insert(sp, pid, key) || over;
+    }
+    __syncthreads();
+    const uint32_t nl = nlist;
+    for (uint32_t i = threadIdx.x; i < nl; i += kBlock) {
+      const uint32_t slot = list[i];
+      over = pair_insert(sp, lpid[slot], lkey[slot]) || over;
+    }
+    __syncthreads();  // the LDS table is reset for the next segment
+  }
+  if (over) atomicOr(sp.state + 1, 1u);
+}
+static_assert(kPairLds == 1 << 11, "LDS pair hash of 11 bits");
+
+// One workgroup after k_pair_collect: if the pairs fit (no overflow), they
+// are copied into LDS as a small graph -- the ends of every pair (2 + 2 B)
+// and its key (8 B), per component its current root (2 B), lightest key
+// (8 B), far end (2 B), parent (2 B) and the position of the key it added
+// (4 B) -- and Boruvka runs to the end there: every root takes the lightest
+// key over its pairs (LDS atomic minimum), the pair holding it names the far
+// end (the keys are distinct), every root with an edge takes the far end's
+// root as parent except the smaller of a mutual pair, pointer jumping
+// flattens, every component reads its new root.  The added keys' positions
+// give the edges (the narrow record at that position holds the edge index),
+// marked in in_mst at the end; the round's record says the solve ended here
+// (dense = 2).  Either way the table is emptied for a later round.
+static constexpr int kSparseThreads = 1024;
+static constexpr int kSparseJumpPasses = 40;
+
+__global__ void __launch_bounds__(kSparseThreads) k_sparse_finish(int round, int launched,
+                                                                 const uint4* __restrict__ rec, SparseTable sp,
+                                                                 const uint32_t* __restrict__ seg_live, int32_t nseg,
+                                                                 uint8_t* __restrict__ in_mst,
+                                                                 unsigned long long* total, DevState* st,
+                                                                 HostRound* host) {
+  extern __shared__ unsigned long long fsm[];
+  __shared__ uint32_t nsel_s;
+  __shared__ uint32_t scan_sh[kScanWaves];
+  __shared__ unsigned long long red_w[kSparseThreads / 64];
+  __shared__ int64_t red_n[kSparseThreads / 64];
+  __shared__ int64_t red_l[kSparseThreads / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  int64_t live = 0;
+  for (int32_t i0 = 0; i0 < nseg; i0 += 8 * kSparseThreads) {
+    uint32_t v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int32_t i = i0 + q * kSparseThreads + tid;
+      const uint32_t x = seg_live[i < nseg ? i : 0];  // nseg >= 1
+      v[q] = i < nseg ? x : 0u;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) live += v[q];
+  }
+  int64_t added0 = 0;
+  unsigned long long total0 = 0;
+  if (tid == 0) {
+    added0 = st->edges_added;
+    total0 = *total;
+  }
+  if (round < 1) return;
+  const int32_t k = st->n[round];
+  // the same conditions as k_pair_collect: the table was filled iff they hold
+  if (k <= 1 || st->n[round - 1] / 2 > kSparseMaxK) return;
+  if (st->err || st->dense_at >= 0) return;
+  if (pick_mode(k, launched) != kModeLds) return;
+  const uint32_t cap = (uint32_t)sparse_pair_cap(k);
+  const bool clean = sp.state[1] == 0;  // no probe sequence ran out
+  // LDS: pair keys [cap] u64, component keys [k] u64, added positions [k]
+  // u32, pair ends [cap] u16 x 2, root / far end / parent [k] u16 each
+  unsigned long long* pkey = fsm;
+  unsigned long long* ckey = pkey + cap;
+  uint32_t* selpos = reinterpret_cast<uint32_t*>(ckey + k);
+  uint16_t* pa = reinterpret_cast<uint16_t*>(selpos + k);
+  uint16_t* pb = pa + cap;
+  uint16_t* comp = pb + cap;
+  uint16_t* far = comp + k;
+  uint16_t* par = far + k;
+  if (tid == 0) nsel_s = 0;
+  // copy the occupied slots (as many as fit; all are counted) and empty the
+  // table: this thread's 32 pair ids loaded first, then the keys of the
+  // occupied ones; places in the pair list by a block-wide prefix sum of the
+  // per-thread counts (one LDS counter for every pair would serialise)
+  constexpr int kPer = kSparseHash / kSparseThreads;
+  static_assert(kSparseHash % kSparseThreads == 0 && kPer == 32, "32 slots per thread");
+  // every pair id of this thread's 32 slots loaded at once; the occupied
+  // slots' indices go to the pair list's places (a block-wide prefix sum of
+  // the per-thread counts, kept in pa[] for now), then the list is read
+  // back, four entries per thread at a time, and each entry's pair id and
+  // key loaded again (cache hits) into the list.  The occupied slots are
+  // remembered (one bit each) and emptied at the very end: a barrier waits
+  // for a workgroup's outstanding stores.
+  uint32_t occupied = 0;
+  {
+    uint32_t pid[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) pid[q] = sp.pid[q * kSparseThreads + tid];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) occupied |= (pid[q] != kPairEmpty ? 1u : 0u) << q;
+  }
+  uint32_t base = 0;
+  uint32_t at = block_excl_scan((uint32_t)__popc(occupied), scan_sh, &base);
+  if (clean && base <= cap) {
+#pragma unroll
+    for (int q = 0; q < kPer; ++q)
+      if ((occupied >> q) & 1u) pa[at++] = (uint16_t)(q * kSparseThreads + tid);
+  }
+  __syncthreads();
+  if (clean && base <= cap) {
+    for (uint32_t i0 = 0; i0 < base; i0 += 4 * kSparseThreads) {
+      uint32_t slot[4], pid[4];
+      unsigned long long key[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint32_t i = i0 + q * kSparseThreads + tid;
+        slot[q] = i < base ? pa[i] : 0u;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        pid[q] = sp.pid[slot[q]];
+        key[q] = sp.key[slot[q]];
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint32_t i = i0 + q * kSparseThreads + tid;
+        if (i < base) {
+          pkey[i] = key[q];
+          pa[i] = (uint16_t)(pid[q] / (uint32_t)k);
+          pb[i] = (uint16_t)(pid[q] % (uint32_t)k);
+        }
+      }
+    }
+  }
+  const uint32_t npairs = base;
+  const bool fits = clean && npairs <= cap;
+  auto empty_table = [&]() {
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      if ((occupied >> q) & 1u) {
+        sp.pid[q * kSparseThreads + tid] = kPairEmpty;
+        sp.key[q * kSparseThreads + tid] = kKeyNone;
+      }
+    }
+    if (tid < 2) sp.state[tid] = 0;
+  };
+  if (!fits) {
+    empty_table();
+    return;  // the round goes on with its one-workgroup close
+  }
+  for (int32_t v = tid; v < k; v += kSparseThreads) {
+    comp[v] = (uint16_t)v;
+    ckey[v] = kKeyNone;
+  }
+  __syncthreads();
+  const uint32_t np = npairs;
+  unsigned long long wsum = 0;
+  int64_t added = 0;
+  bool bad = false, finished = false;
+  for (int it = 0; it < 64; ++it) {  // each pass at least halves the roots with an edge: ends far sooner
+    // (the component keys are "none" here: set before the loop and at the
+    // end of every pass)
+    // four pairs per thread at a time, their loads issued together
+    for (uint32_t i0 = 0; i0 < np; i0 += 4 * kSparseThreads) {
+      int32_t a[4], b[4];
+      unsigned long long key[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint32_t i = i0 + q * kSparseThreads + tid;
+        const uint32_t ic = i < np ? i : 0u;
+        a[q] = comp[pa[ic]];
+        b[q] = comp[pb[ic]];
+        key[q] = i < np ? pkey[ic] : kKeyNone;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (key[q] != kKeyNone && a[q] != b[q]) {
+          lower_lds(ckey, a[q], key[q]);
+          lower_lds(ckey, b[q], key[q]);
+        }
+      }
+    }
+    __syncthreads();
+    for (uint32_t i0 = 0; i0 < np; i0 += 4 * kSparseThreads) {
+      int32_t a[4], b[4];
+      unsigned long long key[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint32_t i = i0 + q * kSparseThreads + tid;
+        const uint32_t ic = i < np ? i : 0u;
+        a[q] = comp[pa[ic]];
+        b[q] = comp[pb[ic]];
+        key[q] = i < np ? pkey[ic] : kKeyNone;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (key[q] != kKeyNone && a[q] != b[q]) {
+          if (ckey[a[q]] == key[q]) far[a[q]] = (uint16_t)b[q];
+          if (ckey[b[q]] == key[q]) far[b[q]] = (uint16_t)a[q];
+        }
+      }
+    }
+    __syncthreads();
+    // hook; the added keys' places by one LDS atomic per wave
+    bool any = false;
+    for (int32_t c0 = 0; c0 < k; c0 += kSparseThreads) {
+      const int32_t c = c0 + tid;
+      bool hooks = false;
+      unsigned long long key = kKeyNone;
+      int32_t d = 0;
+      if (c < k && comp[c] == c) {  // roots only
+        key = ckey[c];
+        par[c] = (uint16_t)c;
+        if (key != kKeyNone) {
+          d = far[c];
+          hooks = !(far[d] == c && ckey[d] == key && c < d);  // the smaller of a mutual pair stays
+        }
+      }
+      const uint64_t mask = __ballot(hooks);
+      uint32_t base = 0;
+      if (lane == 0 && mask) base = atomicAdd(&nsel_s, (uint32_t)__popcll(mask));
+      base = __shfl(base, 0, 64);
+      if (hooks) {
+        par[c] = (uint16_t)d;
+        selpos[base + (uint32_t)__popcll(mask & lanemask_lt())] = (uint32_t)key;
+        wsum += key >> 32;
+        ++added;
+        any = true;
+      }
+    }
+    if (!__syncthreads_or(any)) {
+      finished = true;
+      break;
+    }
+    bool jumping = true;
+    int passes = 0;
+    while (jumping && passes < kSparseJumpPasses) {
+      bool changed = false;
+      for (int32_t c = tid; c < k; c += kSparseThreads) {
+        if (comp[c] != c) continue;
+        const int32_t p = par[c], pp = par[p];
+        if (pp != p) {
+          par[c] = (uint16_t)pp;
+          changed = true;
+        }
+      }
+      jumping = __syncthreads_or(changed);
+      ++passes;
+    }
+    bad = bad || jumping;  // still moving: a cycle, never expected
+    for (int32_t v = tid; v < k; v += kSparseThreads) {
+      comp[v] = par[comp[v]];
+      ckey[v] = kKeyNone;  // for the next pass (read only by the hook, done)
+    }
+    __syncthreads();
+  }
+  bad = bad || !finished;
+  const bool any_bad = __syncthreads_or(bad);
+  for (int off = 32; off > 0; off >>= 1) {
+    wsum += __shfl_xor(wsum, off, 64);
+    added += __shfl_xor(added, off, 64);
+    live += __shfl_xor(live, off, 64);
+  }
+  if (lane == 0) {
+    red_w[wv] = wsum;
+    red_n[wv] = added;
+    red_l[wv] = live;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    unsigned long long W = 0;
+    int64_t A = 0, Lv = 0;
+    for (int i = 0; i < kSparseThreads / 64; ++i) {
+      W += red_w[i];
+      A += red_n[i];
+      Lv += red_l[i];
+    }
+    if (any_bad) st->err_internal = 1;
+    *total = total0 + W;
+    st->live[round] = Lv;
+    st->sel[round] = A;
+    st->edges_added = added0 + A;
+    st->n[round + 1] = 0;
+    st->lab_off[round + 1] = st->lab_off[round];
+    st->dense_at = round;
+    HostRound h{0, st->err, st->err_internal, 2, Lv, A, added0 + A, st->stream[round], st->map_n[round],
+                st->keep[round], 0, 0};
+    host[round] = h;
+    __threadfence_system();
+  }
+  // after the last barrier: the edges of the added keys (the narrow record at
+  // the position holds its index) and the emptied table
+  const uint32_t nadd = nsel_s;
+  const uint32_t* ne = reinterpret_cast<const uint32_t*>(rec);
+  for (uint32_t i = tid; i < nadd; i += kSparseThreads) in_mst[ne[narrow_e_index(selpos[i])]] = 1;
+  empty_table();
+}
+
 // -------------------------------------------------------------------- hook
 
 // Root of x by plain loads (values may be stale, but every value ever stored
@@ -1889,13 +2293,16 @@ hipError_t configure_kernels() {
   hipError_t r2 = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bucket_min),
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxDynLds);
   if (r2 != hipSuccess) e = r2;
+  hipError_t r5 = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sparse_finish),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxDynLds);
+  if (r5 != hipSuccess) e = r5;
   return e;
 }
 
 hipError_t launch_init(int32_t n, int64_t m, int64_t cmap_off, int dense_limit, unsigned long long* best,
-                       int32_t* parent, unsigned long long* pbest, uint32_t* btot, DevState* st, int grid,
-                       hipStream_t s) {
-  k_init<<<grid, kBlock, 0, s>>>(n, m, cmap_off, dense_limit, best, parent, pbest, btot, st);
+                       int32_t* parent, unsigned long long* pbest, uint32_t* btot, SparseTable sp, DevState* st,
+                       int grid, hipStream_t s) {
+  k_init<<<grid, kBlock, 0, s>>>(n, m, cmap_off, dense_limit, best, parent, pbest, btot, sp, st);
   MSTX_LAUNCH_CHECK();
   return hipSuccess;
 }
@@ -1948,6 +2355,23 @@ hipError_t launch_dense_finish(int round, int launched, const unsigned long long
   const int32_t kmax = launched_dense_limit(launched) < kDenseMax ? launched_dense_limit(launched) : kDenseMax;
   const size_t lds = dense_finish_lds(kmax);
   k_dense_finish<<<1, kDenseThreads, lds, s>>>(round, launched, pbest, seg_live, nseg, rec, in_mst, total, st, host);
+  MSTX_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+hipError_t launch_pair_collect(int round, int launched, const uint4* rec, const int32_t* labpool,
+                               const uint32_t* seg_cnt, int32_t nseg, SparseTable sp, const DevState* st, int grid,
+                               hipStream_t s) {
+  k_pair_collect<<<grid, kBlock, 0, s>>>(round, launched, rec, labpool, seg_cnt, nseg, sp, st);
+  MSTX_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+hipError_t launch_sparse_finish(int round, int launched, const uint4* rec, SparseTable sp, const uint32_t* seg_live,
+                                int32_t nseg, uint8_t* in_mst, unsigned long long* total, DevState* st,
+                                HostRound* host, hipStream_t s) {
+  k_sparse_finish<<<1, kSparseThreads, kMaxDynLds, s>>>(round, launched, rec, sp, seg_live, nseg, in_mst, total, st,
+                                                        host);
   MSTX_LAUNCH_CHECK();
   return hipSuccess;
 }

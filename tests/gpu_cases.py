@@ -32,17 +32,19 @@ MID_MAX = 16280  # largest vertex count of a batched graph solved by one workgro
 MID_MAX_EDGES = 1 << 21  # ... and its largest edge count
 PRE_MAX = 65536  # largest vertex count of a batched graph contracted by one workgroup first
 BUCKET_MAX = 1023 << 14  # largest component count whose minima bucket mode takes
+SPARSE_MAX = 8192  # largest component count at which the sparse finish may end the solve
+SPARSE_DEFAULT = 1 << 20  # the library's default live-edge bound for trying it
 
 
 def stats_consistent(gpu_stats, oracle_stats, limit=DENSE_MAX):
     """Whether per-round statistics (components, live edges, edges added) of a
-    solve that may end with the dense finish agree with the oracle's Boruvka
-    rounds.
+    solve that may end with the dense or the sparse finish agree with the
+    oracle's Boruvka rounds.
 
-    Without a dense finish the rows are equal.  A dense finish at round r ends
-    the rows at r: rows before r are equal, row r has the oracle's component
-    and live-edge counts (at most `limit` components), and its edges added are
-    the oracle's added edges of round r and every later round together.
+    Without a finish the rows are equal.  A finish at round r ends the rows at
+    r: rows before r are equal, row r has the oracle's component and live-edge
+    counts (at most `limit` components), and its edges added are the oracle's
+    added edges of round r and every later round together.
     """
     g = [tuple(int(x) for x in r) for r in gpu_stats]
     o = [tuple(int(x) for x in r) for r in oracle_stats]

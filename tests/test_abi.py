@@ -257,3 +257,16 @@ def test_stepwise_host_checks(lib):
     done = c.c_int32(0)
     assert lib.mst_solve_advance(None, c.byref(done)) == B.MSTX_ERR_INVALID_ARG
     assert lib.mst_solve_end(None) == B.MSTX_ERR_INVALID_ARG
+
+
+def test_sparse_limit_option(lib):
+    from paper_2005_06913_amd import binding as B
+    prev = B.mst_set_sparse_limit(-1)
+    try:
+        assert prev == gpu_cases.SPARSE_DEFAULT
+        assert B.mst_set_sparse_limit(0) == prev
+        with B.sparse_limit(123):
+            assert B.mst_set_sparse_limit(-1) == 123
+        assert B.mst_set_sparse_limit(-1) == 0
+    finally:
+        B.mst_set_sparse_limit(prev)

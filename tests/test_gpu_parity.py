@@ -7,9 +7,11 @@ connected the oracle's sequential Boruvka round counts are comparable one to
 one: both remove exactly the internal edges and add one tree edge per
 distinct selected minimum.  A solve that ends with the dense finish stops its
 rows at that round, whose added edges are those of the oracle's remaining
-rounds together (gpu_cases.stats_consistent); the small cases run with the
-dense finish off, at its default limit and at limits that make it start in
-earlier or later rounds.
+rounds together (gpu_cases.stats_consistent); so does a solve that ends with
+the sparse finish (the lightest edge of every component pair, finished in
+one workgroup).  The small cases run with the dense finish off, at its
+default limit and at limits that make it start in earlier or later rounds,
+with the sparse finish at its default and off.
 """
 
 import numpy as np
@@ -40,24 +42,31 @@ def to_dev(dev, src, dst, w):
 
 
 def gpu_solve(dev, n, src, dst, w, limit=gpu_cases.DENSE_MAX, small=gpu_cases.SMALL_MAX, tail=gpu_cases.TAIL_MAX,
-              bucket=gpu_cases.BUCKET_MAX):
+              bucket=gpu_cases.BUCKET_MAX, sparse=gpu_cases.SPARSE_DEFAULT):
     import paper_2005_06913_amd as P
     s, d, ww = to_dev(dev, src, dst, w)
     m = len(src)
     in_mst = torch.full((m,), 7, dtype=torch.uint8, device=dev)  # garbage: must be overwritten
     total = torch.full((1,), 12345, dtype=torch.int64, device=dev).view(torch.uint64)
-    with P.dense_limit(limit), P.small_limit(small), P.tail_limit(tail), P.bucket_limit(bucket):
+    with P.dense_limit(limit), P.small_limit(small), P.tail_limit(tail), P.bucket_limit(bucket), \
+            P.sparse_limit(sparse):
         st = P.mst_solve(n, s, d, ww, in_mst, total)
     torch.cuda.synchronize()
     stats = P.mst_last_round_stats()
     return st, in_mst.cpu().numpy(), int(total.view(torch.int64).cpu().item()), stats
 
 
+def finish_limit(limit, sparse):
+    """Largest component count at which a finish may end the solve."""
+    return max(limit, gpu_cases.SPARSE_MAX) if sparse else limit
+
+
 def check_against_oracle(dev, name, n, src, dst, w, stats=True, limit=gpu_cases.DENSE_MAX,
-                         small=gpu_cases.SMALL_MAX, tail=gpu_cases.TAIL_MAX, bucket=gpu_cases.BUCKET_MAX):
+                         small=gpu_cases.SMALL_MAX, tail=gpu_cases.TAIL_MAX, bucket=gpu_cases.BUCKET_MAX,
+                         sparse=gpu_cases.SPARSE_DEFAULT):
     print(f"[case] {name} n={n} m={len(src)} dense_limit={limit} small_limit={small} tail_limit={tail} "
-          f"bucket_limit={bucket}", flush=True)
-    st, in_mst, total, gstats = gpu_solve(dev, n, src, dst, w, limit, small, tail, bucket)
+          f"bucket_limit={bucket} sparse_limit={sparse}", flush=True)
+    st, in_mst, total, gstats = gpu_solve(dev, n, src, dst, w, limit, small, tail, bucket, sparse)
     k = oracle.kruskal(n, src, dst, w)
     assert st == k.status, f"{name}: status {st} != oracle {k.status}"
     assert total == k.total, f"{name}: total {total} != oracle {k.total}"
@@ -65,9 +74,9 @@ def check_against_oracle(dev, name, n, src, dst, w, stats=True, limit=gpu_cases.
     assert diff.size == 0, f"{name}: {diff.size} edges differ, first {diff[:8]}"
     if stats and k.status == 0 and n > 1:
         b = oracle.boruvka(n, src, dst, w)
-        assert gpu_cases.stats_consistent(gstats, b.stats, limit), \
+        assert gpu_cases.stats_consistent(gstats, b.stats, finish_limit(limit, sparse)), \
             f"{name}: round stats\n{gstats}\n!~\n{b.stats}"
-        if limit == 0:
+        if limit == 0 and sparse == 0:
             assert np.array_equal(gstats, b.stats)
     return gstats
 
@@ -118,23 +127,26 @@ def test_min_edge_keys_golden(dev):
 
 # ------------------------------------------------------------- full solve
 
-# (dense-finish limit, small-graph limit, round-tail limit): the defaults
-# (graphs of at most 8192 vertices take the one-workgroup path), and the
-# per-round kernel chain with the dense finish at its default, off, and
-# starting earlier or later, with late rounds closed in one workgroup or by
-# the grid-wide hook .. relabel kernels
-D, S, T = gpu_cases.DENSE_MAX, gpu_cases.SMALL_MAX, gpu_cases.TAIL_MAX
-PATHS = [(D, S, T), (D, 0, T), (D, 0, 0), (0, 0, T), (0, 0, 0), (2, 0, T), (9, 0, 0), (64, 0, T), (64, 0, 0)]
-PATH_IDS = [f"dense{a}-small{b}-tail{c}" for a, b, c in PATHS]
-FEW_PATHS = [(D, S, T), (D, 0, T), (0, 0, T), (0, 0, 0)]
-FEW_IDS = [f"dense{a}-small{b}-tail{c}" for a, b, c in FEW_PATHS]
+# (dense-finish limit, small-graph limit, round-tail limit, sparse-finish
+# limit): the defaults (graphs of at most 8192 vertices take the
+# one-workgroup path), and the per-round kernel chain with the dense finish at
+# its default, off, and starting earlier or later, with late rounds closed in
+# one workgroup or by the grid-wide hook .. relabel kernels, with the sparse
+# finish tried (the default) or not, and tried whatever the live edges
+D, S, T, SP = gpu_cases.DENSE_MAX, gpu_cases.SMALL_MAX, gpu_cases.TAIL_MAX, gpu_cases.SPARSE_DEFAULT
+ANY = (1 << 31) - 1
+PATHS = [(D, S, T, SP), (D, 0, T, SP), (D, 0, 0, SP), (0, 0, T, SP), (0, 0, 0, SP), (0, 0, T, 0), (0, 0, 0, 0),
+         (D, 0, T, 0), (2, 0, T, SP), (9, 0, 0, SP), (64, 0, T, SP), (64, 0, 0, SP), (0, 0, T, ANY), (D, 0, 0, ANY)]
+PATH_IDS = [f"dense{a}-small{b}-tail{c}-sparse{d}" for a, b, c, d in PATHS]
+FEW_PATHS = [(D, S, T, SP), (D, 0, T, SP), (0, 0, T, 0), (0, 0, 0, SP), (D, 0, T, ANY)]
+FEW_IDS = [f"dense{a}-small{b}-tail{c}-sparse{d}" for a, b, c, d in FEW_PATHS]
 
 
-@pytest.mark.parametrize("limit,small,tail", PATHS, ids=PATH_IDS)
+@pytest.mark.parametrize("limit,small,tail,sparse", PATHS, ids=PATH_IDS)
 @pytest.mark.parametrize("idx", range(len(gpu_cases.small_cases())))
-def test_solve_small(dev, idx, limit, small, tail):
+def test_solve_small(dev, idx, limit, small, tail, sparse):
     g = gpu_cases.small_cases()[idx]
-    check_against_oracle(dev, g.name, g.n, g.src, g.dst, g.w, limit=limit, small=small, tail=tail)
+    check_against_oracle(dev, g.name, g.n, g.src, g.dst, g.w, limit=limit, small=small, tail=tail, sparse=sparse)
 
 
 # GLOBAL minima mode (bucket mode off): every round above the LDS range takes
@@ -142,11 +154,12 @@ def test_solve_small(dev, idx, limit, small, tail):
 GLOBAL_CASES = [i for i, g in enumerate(gpu_cases.small_cases()) if g.n > gpu_cases.LDS_SLOTS]
 
 
-@pytest.mark.parametrize("limit,small,tail", FEW_PATHS[1:], ids=FEW_IDS[1:])
+@pytest.mark.parametrize("limit,small,tail,sparse", FEW_PATHS[1:], ids=FEW_IDS[1:])
 @pytest.mark.parametrize("idx", GLOBAL_CASES)
-def test_solve_global_mode(dev, idx, limit, small, tail):
+def test_solve_global_mode(dev, idx, limit, small, tail, sparse):
     g = gpu_cases.small_cases()[idx]
-    check_against_oracle(dev, g.name, g.n, g.src, g.dst, g.w, limit=limit, small=small, tail=tail, bucket=0)
+    check_against_oracle(dev, g.name, g.n, g.src, g.dst, g.w, limit=limit, small=small, tail=tail, bucket=0,
+                         sparse=sparse)
 
 
 def test_dense_finish_ends_early(dev):
@@ -163,6 +176,19 @@ def test_dense_finish_ends_early(dev):
     assert len(gstats) == 1 and gstats[0][2] == 63
 
 
+def test_sparse_finish_ends_early(dev):
+    """A grid's late rounds join few component pairs: the sparse finish ends the
+    solve before the oracle's last round (dense finish off), with the rows
+    consistent; with it off the rows equal the oracle's."""
+    g = next(x for x in gpu_cases.small_cases() if x.name == "grid_256x256")
+    b = oracle.boruvka(g.n, g.src, g.dst, g.w)
+    on = check_against_oracle(dev, g.name, g.n, g.src, g.dst, g.w, limit=0, small=0, tail=0)
+    assert len(on) < len(b.stats), (on, b.stats)
+    assert int(on[-1][0]) <= gpu_cases.SPARSE_MAX and len(on) >= 2
+    off = check_against_oracle(dev, g.name, g.n, g.src, g.dst, g.w, limit=0, small=0, tail=0, sparse=0)
+    assert np.array_equal(off, b.stats)
+
+
 def test_small_path_matches_chain(dev):
     """The one-workgroup path and the per-round chain give the same bytes and the
     oracle's round statistics exactly (the small path has no dense finish)."""
@@ -170,8 +196,8 @@ def test_small_path_matches_chain(dev):
         if g.n > gpu_cases.SMALL_MAX or len(g.src) > (1 << 17):
             continue
         a = gpu_solve(dev, g.n, g.src, g.dst, g.w, small=gpu_cases.SMALL_MAX)
-        c = gpu_solve(dev, g.n, g.src, g.dst, g.w, limit=0, small=0, tail=0)
-        t = gpu_solve(dev, g.n, g.src, g.dst, g.w, limit=0, small=0)
+        c = gpu_solve(dev, g.n, g.src, g.dst, g.w, limit=0, small=0, tail=0, sparse=0)
+        t = gpu_solve(dev, g.n, g.src, g.dst, g.w, limit=0, small=0, sparse=0)
         for x in (a, t):
             assert x[0] == c[0] and x[2] == c[2] and np.array_equal(x[1], c[1]), g.name
             assert np.array_equal(x[3], c[3]), g.name
@@ -179,24 +205,24 @@ def test_small_path_matches_chain(dev):
             assert np.array_equal(a[3], oracle.boruvka(g.n, g.src, g.dst, g.w).stats), g.name
 
 
-@pytest.mark.parametrize("limit,small,tail", FEW_PATHS, ids=FEW_IDS)
-def test_solve_golden(dev, limit, small, tail):
+@pytest.mark.parametrize("limit,small,tail,sparse", FEW_PATHS, ids=FEW_IDS)
+def test_solve_golden(dev, limit, small, tail, sparse):
     for fx in mst_pins.all_fixtures():
-        st, in_mst, total, stats = gpu_solve(dev, fx.n, fx.src, fx.dst, fx.w, limit, small, tail)
+        st, in_mst, total, stats = gpu_solve(dev, fx.n, fx.src, fx.dst, fx.w, limit, small, tail, sparse=sparse)
         assert st == fx.status, fx.name
         assert total == fx.total, fx.name
         assert np.array_equal(in_mst, fx.in_mst), fx.name
         if fx.status == 0:
-            assert gpu_cases.stats_consistent(stats, fx.rounds, limit), fx.name
-            if limit == 0:
+            assert gpu_cases.stats_consistent(stats, fx.rounds, finish_limit(limit, sparse)), fx.name
+            if limit == 0 and sparse == 0:
                 assert [tuple(r) for r in stats.tolist()] == fx.rounds, fx.name
 
 
-@pytest.mark.parametrize("limit,small,tail", FEW_PATHS, ids=FEW_IDS)
+@pytest.mark.parametrize("limit,small,tail,sparse", FEW_PATHS, ids=FEW_IDS)
 @pytest.mark.parametrize("case", gpu_cases.edge_cases(), ids=[c[0] for c in gpu_cases.edge_cases()])
-def test_solve_edge_cases(dev, case, limit, small, tail):
+def test_solve_edge_cases(dev, case, limit, small, tail, sparse):
     name, n, src, dst, w = case
-    check_against_oracle(dev, name, n, src, dst, w, stats=False, limit=limit, small=small, tail=tail)
+    check_against_oracle(dev, name, n, src, dst, w, stats=False, limit=limit, small=small, tail=tail, sparse=sparse)
 
 
 def test_vertex_range_error(dev):
