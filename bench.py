@@ -449,7 +449,13 @@ def bench_served(args, dev):
                    "requests_in": "HBM (device tensors); the pcie object repeats the legs with host arrays",
                    "latency_includes": "queueing and the solve; pcie: also the host-to-device copy of the "
                                        "request and the device-to-host copy of its flags"},
-        "roofline": None,
+        # the stream as one pass over every request's edges (12 B read, 1 B flag
+        # written) per wall second at saturation: how far serving is from the
+        # HBM bound (the per-request launches and waits set its rate)
+        "roofline": {"bound": "hbm", "achieved": 13.0 * m * sat["solves_per_s"] / args.requests / 1e9,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": 13.0 * m * sat["solves_per_s"] / args.requests / 1e9 / HBM_PEAK_GBS,
+                     "traffic": None, "kernel": "the resident served stream at saturation (one-pass model)"},
         **res,
         "pcie": pcie,
         "bit_exact_resident_vs_pcie": bool(same_modes),
