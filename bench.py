@@ -571,7 +571,7 @@ def main() -> int:
     ap.add_argument("--no-per-graph", action="store_true",
                     help="batched workload: leave out the per-graph comparison leg (counter runs)")
     ap.add_argument("--requests", type=int, default=160, help="served workload: requests per replay")
-    ap.add_argument("--slots", type=int, default=3, help="served workload: concurrent server slots")
+    ap.add_argument("--slots", type=int, default=6, help="served workload: concurrent server slots")
     ap.add_argument("--hbm-budget-gib", type=int, default=96, help="served workload: device memory budget")
     ap.add_argument("--summarize-pmc", nargs=4, metavar=("COPY_FETCH", "COPY_WRITE", "SOLVE_FETCH", "SOLVE_WRITE"),
                     help="fold four rocprofv3 --pmc output directories into the traffic summary and exit")
