@@ -132,6 +132,10 @@ typedef struct MstxSolve MstxSolve;
 int mst_solve_begin(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, const uint32_t* w,
                     uint8_t* out_in_mst, uint64_t* out_total_weight, void* stream, MstxSolve** out_handle);
 int mst_solve_advance(MstxSolve* handle, int32_t* out_done);
+/* The same as mst_solve_advance, but waits (on the host, on the round's
+ * event) until the next round's record is there, takes that one record and
+ * enqueues what follows it: one round per call, without polling. */
+int mst_solve_wait_round(MstxSolve* handle, int32_t* out_done);
 int mst_solve_end(MstxSolve* handle);
 
 /*

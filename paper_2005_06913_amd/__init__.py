@@ -38,6 +38,7 @@ from .binding import (  # noqa: F401
     mst_set_mid_limit,
     mst_set_scan_occupancy,
     mst_set_sparse_limit,
+    mst_solve_wait_round,
     sparse_limit,
     mst_set_small_limit,
     mst_set_tail_limit,

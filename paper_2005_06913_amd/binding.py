@@ -30,7 +30,7 @@ EXPORTS = ("mst_solve", "mst_solve_batched", "mst_batched_workspace_bytes", "mst
            "mst_profile_read", "mst_profile_kernel_name", "mst_workspace_release", "mst_set_dense_limit", "mst_set_small_limit",
            "mst_set_tail_limit", "mst_set_mid_limit", "mst_set_bucket_limit", "mst_csr_to_edges",
            "mst_solve_noalloc", "mst_profile_read_rounds", "mst_set_scan_occupancy", "mst_solve_begin",
-           "mst_solve_advance", "mst_solve_end", "mst_set_sparse_limit")
+           "mst_solve_advance", "mst_solve_end", "mst_set_sparse_limit", "mst_solve_wait_round")
 
 _lib = None
 
@@ -57,6 +57,8 @@ def load_library(path: str = LIB_PATH):
     lib.mst_solve_begin.restype = ctypes.c_int
     lib.mst_solve_advance.argtypes = [p, ctypes.POINTER(i32)]
     lib.mst_solve_advance.restype = ctypes.c_int
+    lib.mst_solve_wait_round.argtypes = [p, ctypes.POINTER(i32)]
+    lib.mst_solve_wait_round.restype = ctypes.c_int
     lib.mst_solve_end.argtypes = [p]
     lib.mst_solve_end.restype = ctypes.c_int
     lib.mst_solve_noalloc.argtypes = [i32, i64, p, p, p, p, p, p]
@@ -325,6 +327,16 @@ def mst_solve_advance(handle) -> bool:
     True once the solve has ended."""
     done = ctypes.c_int32(0)
     rc = load_library().mst_solve_advance(handle, ctypes.byref(done))
+    if rc < 0:
+        raise MstxError(rc)
+    return bool(done.value)
+
+
+def mst_solve_wait_round(handle) -> bool:
+    """C ``mst_solve_wait_round``: waits for the next round's record, takes it and
+    enqueues what follows; True once the solve has ended."""
+    done = ctypes.c_int32(0)
+    rc = load_library().mst_solve_wait_round(handle, ctypes.byref(done))
     if rc < 0:
         raise MstxError(rc)
     return bool(done.value)

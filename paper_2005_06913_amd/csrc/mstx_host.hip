@@ -798,7 +798,11 @@ struct RoundMachine {
     return MSTX_OK;
   }
 
-  int advance(bool block) {
+  // one_round: return once a record has been taken and the rounds after it
+  // are enqueued as far as the pipelining allows (a blocking call then waits
+  // for one round only)
+  int advance(bool block, bool one_round = false) {
+    bool took = false;
     while (!done) {
       if (r >= max_rounds) {
         done = true;  // round-count watchdog: status stays MSTX_ERR_DEVICE
@@ -819,6 +823,7 @@ struct RoundMachine {
         HIP_OK(enqueue_round(S, r + 1, n_known / 2, n_known, false));
         r_enq = r + 1;
       }
+      if (one_round && took) return MSTX_OK;
       if (block) {
         HIP_OK(hipEventSynchronize(ev[r]));
       } else {
@@ -840,6 +845,7 @@ struct RoundMachine {
         }
       }
       R.take(r, M);
+      took = true;
       S.keep[r + 1] = M.keep_next;
       S.live_rec[r] = M.live;
       if (R.done) {
@@ -1126,11 +1132,11 @@ int step_begin(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, con
   return MSTX_OK;
 }
 
-int step_advance(StepSolve* h, bool block) {
+int step_advance(StepSolve* h, bool block, bool one_round = false) {
   if (h->done) return MSTX_OK;
   t_timer.begin(h->s);
   t_timer.on = false;
-  const int rc = h->rm->advance(block);
+  const int rc = h->rm->advance(block, one_round);
   if (rc != MSTX_OK || h->rm->done) {
     h->done = true;
     h->status = rc != MSTX_OK ? rc : h->rm->R.status;
@@ -1630,6 +1636,14 @@ int mst_solve_advance(MstxSolve* handle, int32_t* out_done) {
   if (!handle || !out_done) return MSTX_ERR_INVALID_ARG;
   auto* h = reinterpret_cast<mstx::StepSolve*>(handle);
   mstx::step_advance(h, false);
+  *out_done = h->done ? 1 : 0;
+  return MSTX_OK;
+}
+
+int mst_solve_wait_round(MstxSolve* handle, int32_t* out_done) {
+  if (!handle || !out_done) return MSTX_ERR_INVALID_ARG;
+  auto* h = reinterpret_cast<mstx::StepSolve*>(handle);
+  mstx::step_advance(h, true, true);
   *out_done = h->done ? 1 : 0;
   return MSTX_OK;
 }

@@ -8,8 +8,9 @@ device-memory budget (admission by HBM budget):
 
 * a request with at least `solo_edges` edges already fills the GPU: it is
   solved alone, round by round (``mst_solve_begin`` / ``mst_solve_advance``
-  / ``mst_solve_end``), and between two of its Boruvka rounds the worker
-  admits the small requests queued by then: it solves them with one
+  / ``mst_solve_end``; with nothing to admit the worker sleeps in
+  ``mst_solve_wait_round``), and between two of its Boruvka rounds the
+  worker admits the small requests queued by then: it solves them with one
   ``mst_solve_batched`` call on the same stream, which the device runs
   after the rounds enqueued so far (round-granular admission: a small
   request waits for at most about two rounds of a large one, not for the
@@ -210,6 +211,11 @@ class _SoloJob:
         """True once the solve has ended (its next round is enqueued otherwise)."""
         return self.h is None or self.ex.B.mst_solve_advance(self.h)
 
+    def wait_round(self) -> bool:
+        """Waits for the next round to finish (the host thread sleeps in the
+        library, the interpreter lock released); True once the solve has ended."""
+        return self.h is None or self.ex.B.mst_solve_wait_round(self.h)
+
     def finish(self) -> None:
         r, torch = self.r, self.ex.torch
         if self.h is not None:
@@ -361,20 +367,28 @@ class MstServer:
 
     def _run_stepwise(self, slot, r, used):
         """One large request round by round; the small requests queued between two
-        of its rounds run on this slot then, within what is left of its share."""
+        of its rounds run on this slot then, within what is left of its share.
+        With nothing to admit the worker waits for the next round inside the
+        library (no polling), so a small request waits for at most about one
+        round of the large one."""
         try:
             job = self.ex.begin_solo(slot, r)
-            while not job.advance():
+            wait = getattr(job, "wait_round", None)
+            done = job.advance()
+            while not done:
                 with self.cv:
                     small, sused = self._take_small(self.share - used)
                     if small:
                         self.in_flight_bytes += sused
                         self.peak_in_flight_bytes = max(self.peak_in_flight_bytes, self.in_flight_bytes)
-                    else:
+                    elif wait is None:
                         self.cv.wait(timeout=self.step_poll_s)
                 if small:
                     self.interleaved.append((slot, r.rid, [x.rid for x in small]))
                     self._run_batch(slot, small, sused)
+                    done = job.advance()
+                else:
+                    done = wait() if wait is not None else job.advance()
             job.finish()
         except Exception as exc:
             self._fail(slot, [r], exc)

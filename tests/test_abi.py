@@ -256,6 +256,7 @@ def test_stepwise_host_checks(lib):
     assert h.value is None
     done = c.c_int32(0)
     assert lib.mst_solve_advance(None, c.byref(done)) == B.MSTX_ERR_INVALID_ARG
+    assert lib.mst_solve_wait_round(None, c.byref(done)) == B.MSTX_ERR_INVALID_ARG
     assert lib.mst_solve_end(None) == B.MSTX_ERR_INVALID_ARG
 
 

@@ -94,6 +94,8 @@ def test_stepwise_solve_with_work_between_rounds(dev):
         if not batched:
             assert P.mst_solve_batched(b.vertex_offsets, b.edge_offsets, bs, bd, bw, bm, bt, bst, stream) == 0
             batched = True
+        elif steps % 2 == 0 and P.mst_solve_wait_round(h):  # one round at a time, waiting
+            break
     assert P.mst_solve_end(h) == want.status == 0
     torch.cuda.synchronize()
     assert int(total.view(torch.int64).item()) == want.total

@@ -160,6 +160,44 @@ class StepFakeExecutor(FakeExecutor):
         return Job()
 
 
+class WaitingStepExecutor(StepFakeExecutor):
+    """StepFakeExecutor whose jobs also wait for their next round (no polling)."""
+
+    def begin_solo(self, slot, r):
+        job = super().begin_solo(slot, r)
+        ex = self
+
+        def wait_round():
+            time.sleep(ex.round_s / 2)
+            return job.advance()
+
+        job.wait_round = wait_round
+        return job
+
+
+def test_round_granular_admission_waiting():
+    """The same with the worker waiting for rounds instead of polling: small
+    requests still run between the large request's rounds."""
+    ex = WaitingStepExecutor(delay=0.002, rounds=10, round_s=0.01)
+    srv = serve.MstServer(ex, slots=1, hbm_budget_bytes=1 << 30, solo_edges=50_000).start()
+    big_g = G.tree_plus_extra(20_000, 60_000, seed=11)
+    big = serve.Request(1000, big_g.n, big_g.src, big_g.dst, big_g.w)
+    srv.submit(big)
+    time.sleep(0.02)
+    small = make_requests(8, seed=12, n_hi=500)
+    for r in small:
+        srv.submit(r)
+        time.sleep(0.003)
+    for r in small + [big]:
+        r.done.wait()
+    srv.close()
+    assert srv.interleaved and max(r.done_at for r in small) < big.done_at
+    for r in small + [big]:
+        k = oracle.kruskal(r.n, r.src, r.dst, r.w)
+        assert r.status == k.status == 0 and r.total == k.total
+        assert np.array_equal(r.in_mst, k.in_mst)
+
+
 def test_round_granular_admission():
     """With one slot busy on a large request, small requests that arrive during
     it are solved between its rounds and finish before it does."""
