@@ -31,18 +31,22 @@
 //   hook      every component with a minimum: its parent becomes the
 //             component at the far end of its lightest edge (the smaller of
 //             a mutual pair stays a root); it marks that edge.
-//   compress  pointer jumping: every component finds its root; a wave ballot
+//   compress  path halving: every component finds its root; a wave ballot
 //             records which roots still have an outgoing edge.
 //   finalize  one workgroup: exclusive scan of the root counts (dense new
 //             labels), per-round totals, a small record for the host.
 //   relabel   old label -> new label map; reset parent[] and the minima.
 //   (round tail: when the round has few components, hook .. relabel run in
-//   one workgroup with the parent forest in LDS, k_round_tail.)
+//   one workgroup with the parent forest in LDS, k_round_tail.  Sparse
+//   finish: a late round whose components have few neighbours collects the
+//   lightest edge of every component pair into a hash table and, when they
+//   fit, ends the solve in one workgroup, k_pair_collect / k_sparse_finish.)
 //
 // Layout: vertex state is structure-of-arrays in HBM.  The edge stream of
-// round 0 is the caller's src/dst/w arrays; from round 1 on it is a record
-// stream {a, b, w, e} (16 B, one dwordx4) cut into fixed segments of 4096
-// records, one segment per workgroup iteration, compacted in place.
+// rounds 0 and 1 is the caller's src/dst/w arrays; from round 2 on it is a
+// record stream cut into fixed segments of 4096 records, one segment per
+// workgroup iteration, compacted in place: {a, b, w, e} (16 B, one dwordx4),
+// or once the labels fit 16 bits a | b << 16 | w << 32 (8 B) with e apart.
 //
 // Device-scope 64-bit atomics on gfx950 execute at the memory side (~27
 // Gop/s whatever the table size) and same-address atomics serialise, so the

@@ -240,7 +240,7 @@ class MstServer:
     def __init__(self, executor, slots: int = 3, hbm_budget_bytes: int = 64 << 30, max_batch: int = 1024,
                  solo_edges: int = 1 << 19, batch_edges: int = 1 << 22, step_poll_s: float = 2e-4):
         self.ex = executor
-        self.step_poll_s = step_poll_s  # wait between two polls of a large solve's rounds
+        self.step_poll_s = step_poll_s  # poll interval for executors whose jobs cannot wait for a round
         self.slots = slots
         self.share = hbm_budget_bytes // slots
         self.max_batch = max_batch
