@@ -318,6 +318,26 @@ def bench_batched(args, dev):
         ev.append((e0, e1))
     torch.cuda.synchronize()
     dev_ms = sum(a.elapsed_time(c) for a, c in ev) / len(ev)
+    # the same batch planned once and captured as a HIP graph, replayed
+    replay = None
+    g_mst = torch.empty(m, dtype=torch.uint8, device=dev)
+    g_tot = torch.empty(Gn, dtype=torch.uint64, device=dev)
+    g_st = torch.empty(Gn, dtype=torch.int32, device=dev)
+    rc, plan = P.mst_batched_plan_create(b.vertex_offsets, b.edge_offsets, src, dst, w, g_mst, g_tot, g_st, stream)
+    if rc == 0:
+        for _ in range(args.warmup):
+            P.mst_batched_plan_run(plan, stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            P.mst_batched_plan_run(plan, stream)
+        torch.cuda.synchronize()
+        same = (torch.equal(g_mst, in_mst) and torch.equal(g_st, status)
+                and torch.equal(g_tot.view(torch.int64), total.view(torch.int64)))
+        replay = {"ms_per_step": (time.perf_counter() - t0) * 1e3 / args.steps, "bit_exact_vs_call": bool(same)}
+        P.mst_batched_plan_destroy(plan)
+    else:
+        replay = {"status": rc}
     # algorithmic bytes of a batch: every edge read once (12 B) and its flag
     # written (1 B), a total and a status per graph (12 B)
     batch_bytes = 13.0 * m + 12.0 * Gn
@@ -353,6 +373,7 @@ def bench_batched(args, dev):
                      "alg_bytes": batch_bytes,
                      "alg_bytes_model": "one pass over the batch: 12 B per edge read, 1 B per edge written, "
                                         "12 B per graph"},
+        "graph_replay": replay,
         "per_graph_path": per_graph,
         "speedup_vs_per_graph": per_graph["ms_per_batch"] / ms_per_step if per_graph else None,
         "status_counts": {int(k): int(v) for k, v in zip(*np.unique(got_st, return_counts=True))},

@@ -170,6 +170,32 @@ int mst_solve_batched(int32_t num_graphs, const int64_t* vertex_offsets, const i
                       const int32_t* src, const int32_t* dst, const uint32_t* w, uint8_t* out_in_mst,
                       uint64_t* out_total_weight, int32_t* out_status, void* stream);
 
+/*
+ * Repeated batched solves of one shape (Section 2.1 on each graph, as
+ * mst_solve_batched): the batch's offsets are planned once and the solve is
+ * captured as a HIP graph on the given device buffers; every
+ * mst_batched_plan_run replays it on `stream` (asynchronously: the results
+ * are there when the stream has reached that point).  Between runs the
+ * caller may change the contents of src / dst / w, not the pointers, the
+ * offsets or the library's limits (mst_set_mid_limit and the like are read
+ * at creation).  Only batches whose every graph is solved by one workgroup
+ * can be captured (under the default limits: at most 65536 vertices and 2^21
+ * edges per graph); others return MSTX_ERR_INVALID_ARG -- use
+ * mst_solve_batched for them.  Unlike mst_solve_batched, a run does not
+ * synchronise and reports no call status: out_status holds every graph's.
+ * The plan owns about mst_batched_workspace_bytes of device memory until
+ * mst_batched_plan_destroy, which the caller calls when no run is in flight.
+ * Creation allocates and captures (on an internal stream); runs allocate
+ * nothing.  Errors: MSTX_ERR_INVALID_ARG, MSTX_ERR_VERTEX_RANGE is reported
+ * per graph in out_status, MSTX_ERR_OUT_OF_MEMORY, MSTX_ERR_DEVICE.
+ */
+typedef struct MstxBatchPlan MstxBatchPlan;
+int mst_batched_plan_create(int32_t num_graphs, const int64_t* vertex_offsets, const int64_t* edge_offsets,
+                            const int32_t* src, const int32_t* dst, const uint32_t* w, uint8_t* out_in_mst,
+                            uint64_t* out_total_weight, int32_t* out_status, void* stream, MstxBatchPlan** out_plan);
+int mst_batched_plan_run(MstxBatchPlan* plan, void* stream);
+int mst_batched_plan_destroy(MstxBatchPlan* plan);
+
 /* Device workspace bytes of mst_solve_batched for these offsets (upper bound;
  * 0 for invalid offsets).  Pure host arithmetic. */
 size_t mst_batched_workspace_bytes(int32_t num_graphs, const int64_t* vertex_offsets,

@@ -39,6 +39,9 @@ from .binding import (  # noqa: F401
     mst_set_scan_occupancy,
     mst_set_sparse_limit,
     mst_solve_wait_round,
+    mst_batched_plan_create,
+    mst_batched_plan_run,
+    mst_batched_plan_destroy,
     sparse_limit,
     mst_set_small_limit,
     mst_set_tail_limit,

@@ -30,7 +30,8 @@ EXPORTS = ("mst_solve", "mst_solve_batched", "mst_batched_workspace_bytes", "mst
            "mst_profile_read", "mst_profile_kernel_name", "mst_workspace_release", "mst_set_dense_limit", "mst_set_small_limit",
            "mst_set_tail_limit", "mst_set_mid_limit", "mst_set_bucket_limit", "mst_csr_to_edges",
            "mst_solve_noalloc", "mst_profile_read_rounds", "mst_set_scan_occupancy", "mst_solve_begin",
-           "mst_solve_advance", "mst_solve_end", "mst_set_sparse_limit", "mst_solve_wait_round")
+           "mst_solve_advance", "mst_solve_end", "mst_set_sparse_limit", "mst_solve_wait_round",
+           "mst_batched_plan_create", "mst_batched_plan_run", "mst_batched_plan_destroy")
 
 _lib = None
 
@@ -65,6 +66,12 @@ def load_library(path: str = LIB_PATH):
     lib.mst_solve_noalloc.restype = ctypes.c_int
     lib.mst_solve_batched.argtypes = [i32, p, p, p, p, p, p, p, p, p]
     lib.mst_solve_batched.restype = ctypes.c_int
+    lib.mst_batched_plan_create.argtypes = [i32, p, p, p, p, p, p, p, p, p, ctypes.POINTER(p)]
+    lib.mst_batched_plan_create.restype = ctypes.c_int
+    lib.mst_batched_plan_run.argtypes = [p, p]
+    lib.mst_batched_plan_run.restype = ctypes.c_int
+    lib.mst_batched_plan_destroy.argtypes = [p]
+    lib.mst_batched_plan_destroy.restype = ctypes.c_int
     lib.mst_batched_workspace_bytes.argtypes = [i32, p, p]
     lib.mst_batched_workspace_bytes.restype = ctypes.c_size_t
     lib.mst_select_min_edges.argtypes = [i32, i64, p, p, p, p, p]
@@ -373,6 +380,39 @@ def mst_solve_batched(vertex_offsets, edge_offsets, src, dst, w, out_in_mst, out
     return int(load_library().mst_solve_batched(G, vo.ctypes.data_as(ctypes.c_void_p),
                                                  eo.ctypes.data_as(ctypes.c_void_p), *args,
                                                  _stream_handle(stream)))
+
+
+def mst_batched_plan_create(vertex_offsets, edge_offsets, src, dst, w, out_in_mst, out_total_weight, out_status,
+                            stream=None):
+    """C ``mst_batched_plan_create``: plans and captures the batched solve of this
+    shape on these tensors; returns (status, plan) with plan None on a negative
+    status.  The tensors must stay alive until ``mst_batched_plan_destroy``."""
+    import torch
+    vo = _host_offsets(vertex_offsets, "vertex_offsets")
+    eo = _host_offsets(edge_offsets, "edge_offsets")
+    G = vo.shape[0] - 1
+    if eo.shape[0] != G + 1:
+        raise ValueError("vertex_offsets and edge_offsets must have the same length")
+    m = int(eo[-1])
+    args = (_dev_ptr(src, torch.int32, "src", m), _dev_ptr(dst, torch.int32, "dst", m),
+            _dev_ptr(w, torch.uint32, "w", m), _dev_ptr(out_in_mst, torch.uint8, "out_in_mst", m),
+            _dev_ptr(out_total_weight, torch.uint64, "out_total_weight", G),
+            _dev_ptr(out_status, torch.int32, "out_status", G))
+    h = ctypes.c_void_p(0)
+    st = int(load_library().mst_batched_plan_create(G, vo.ctypes.data_as(ctypes.c_void_p),
+                                                     eo.ctypes.data_as(ctypes.c_void_p), *args,
+                                                     _stream_handle(stream), ctypes.byref(h)))
+    return st, (h if st >= 0 and h.value else None)
+
+
+def mst_batched_plan_run(plan, stream=None) -> int:
+    """C ``mst_batched_plan_run``: replays the captured solve on the stream (asynchronous)."""
+    return int(load_library().mst_batched_plan_run(plan, _stream_handle(stream)))
+
+
+def mst_batched_plan_destroy(plan) -> int:
+    """C ``mst_batched_plan_destroy``: frees the plan (no run may be in flight)."""
+    return int(load_library().mst_batched_plan_destroy(plan))
 
 
 def mst_batched_workspace_bytes(vertex_offsets, edge_offsets) -> int:

@@ -1310,6 +1310,40 @@ BatchLayout plan_batch(int32_t G, const BatchPlan& P) {
                     P.max_chunk_m, (int64_t)P.con.size(), P.con_n, P.con_m);
 }
 
+// Every graph of the batch that one workgroup solves, in one launch: the
+// contracted ones (their first rounds, then the mid-size solve on the at most
+// mid_limit components left), the mid-size ones, the small ones.  The class
+// lists and offsets are at their places in A (laid out by BL).
+hipError_t launch_one_workgroup_classes(const BatchPlan& P, const BatchLayout& BL, void* A, int32_t mid_limit,
+                                        const int32_t* src, const int32_t* dst, const uint32_t* w, uint8_t* in_mst,
+                                        uint64_t* total, int32_t* status, hipStream_t s) {
+  auto* d_voff = at<int64_t>(A, BL.voff);
+  auto* d_eoff = at<int64_t>(A, BL.eoff);
+  auto* d_small = at<int32_t>(A, BL.small);
+  auto* d_mid = at<int32_t>(A, BL.mid);
+  auto* d_con = at<int32_t>(A, BL.con);
+  auto* d_cpoff = at<int64_t>(A, BL.cpoff);
+  auto* d_csoff = at<int64_t>(A, BL.csoff);
+  auto* d_cnum = at<int32_t>(A, BL.cnum);
+  auto* d_pcnt = at<int32_t>(A, BL.pcnt);
+  auto* d_pbad = at<int32_t>(A, BL.pbad);
+  auto* d_pairs = at<uint32_t>(A, BL.pairs);
+  auto* tot = reinterpret_cast<unsigned long long*>(total);
+  const int32_t max_n = std::min<int32_t>(mid_limit, kMidN);
+  BatchSolveArgs B{};
+  B.pre = PreArgs{d_con,   d_voff,  d_eoff, src,    dst,    w,      d_csoff, at<unsigned long long>(A, BL.cscratch),
+                  d_pairs, d_cpoff, d_cnum, d_pcnt, d_pbad, in_mst, tot,     max_n};
+  B.con = MidArgs{d_con,  d_voff, d_eoff, nullptr, nullptr, w,   d_pairs, d_cpoff,
+                  d_cnum, d_pcnt, d_pbad, in_mst,  tot,     status, max_n};
+  B.mid = MidArgs{d_mid,   d_voff,  d_eoff,  src,    dst, w,      nullptr, nullptr,
+                  nullptr, nullptr, nullptr, in_mst, tot, status, P.mid_max_n};
+  B.small = MidArgs{d_small, d_voff,  d_eoff,  src,    dst, w,      nullptr, nullptr,
+                    nullptr, nullptr, nullptr, in_mst, tot, status, 0};
+  B.ncon = (int32_t)P.con.size();
+  B.nmid = (int32_t)P.mid.size();
+  return launch_batch_solve(B, (int)P.small.size(), s);
+}
+
 int solve_batched(int32_t G, const int64_t* voff, const int64_t* eoff, const int32_t* src, const int32_t* dst,
                   const uint32_t* w, uint8_t* in_mst, uint64_t* total, int32_t* status, hipStream_t s) {
   t_last_stats.clear();
@@ -1368,24 +1402,7 @@ int solve_batched(int32_t G, const int64_t* voff, const int64_t* eoff, const int
     HIP_OK(hipMemcpyAsync(d_csoff, P.csoff.data(), 8 * (size_t)ncon, hipMemcpyHostToDevice, s));
   }
   if (eoff[G] > 0) HIP_OK(hipMemsetAsync(in_mst, 0, (size_t)eoff[G], s));
-  {
-    // every graph one workgroup solves, in one launch: the contracted ones
-    // (their first rounds, then the mid-size solve on the at most mid_limit
-    // components left), the mid-size ones, the small ones
-    const int32_t max_n = std::min<int32_t>(mid_limit, kMidN);
-    BatchSolveArgs B{};
-    B.pre = PreArgs{d_con,   d_voff,  d_eoff, src,    dst,    w,      d_csoff, at<unsigned long long>(A, BL.cscratch),
-                    d_pairs, d_cpoff, d_cnum, d_pcnt, d_pbad, in_mst, tot,     max_n};
-    B.con = MidArgs{d_con,  d_voff, d_eoff, nullptr, nullptr, w,   d_pairs, d_cpoff,
-                    d_cnum, d_pcnt, d_pbad, in_mst,  tot,     status, max_n};
-    B.mid = MidArgs{d_mid,   d_voff,  d_eoff,  src,    dst, w,      nullptr, nullptr,
-                    nullptr, nullptr, nullptr, in_mst, tot, status, P.mid_max_n};
-    B.small = MidArgs{d_small, d_voff,  d_eoff,  src,    dst, w,      nullptr, nullptr,
-                      nullptr, nullptr, nullptr, in_mst, tot, status, 0};
-    B.ncon = (int32_t)ncon;
-    B.nmid = (int32_t)P.mid.size();
-    HIP_OK(launch_batch_solve(B, (int)P.small.size(), s));
-  }
+  HIP_OK(launch_one_workgroup_classes(P, BL, A, mid_limit, src, dst, w, in_mst, total, status, s));
 
   for (size_t c = 0; c + 1 < P.cfirst.size(); ++c) {
     const int32_t i0 = P.cfirst[c], ng = P.cfirst[c + 1] - i0;
@@ -1408,6 +1425,79 @@ int solve_batched(int32_t G, const int64_t* voff, const int64_t* eoff, const int
                                  at<uint32_t>(A, BL.acc_c), tot, status, s));
   }
   HIP_OK(hipStreamSynchronize(s));
+  return MSTX_OK;
+}
+
+// A batch of fixed shape on fixed buffers, planned once and captured as a
+// HIP graph: the flags cleared by a kernel (no memset node) and the
+// one-launch solve of every graph.  Replays run the graph on any stream of
+// the plan's device.
+struct BatchGraphPlan {
+  int device = 0;
+  void* mem = nullptr;  // class lists, offsets and the contraction scratch (BatchLayout)
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+void plan_free(BatchGraphPlan* h) {
+  if (h->exec) (void)hipGraphExecDestroy(h->exec);
+  if (h->graph) (void)hipGraphDestroy(h->graph);
+  if (h->mem) (void)hipFree(h->mem);
+  delete h;
+}
+
+int batch_plan_create(int32_t G, const int64_t* voff, const int64_t* eoff, const int32_t* src, const int32_t* dst,
+                      const uint32_t* w, uint8_t* in_mst, uint64_t* total, int32_t* status, hipStream_t s,
+                      BatchGraphPlan** out) {
+  *out = nullptr;
+  const int32_t mid_limit = g_mid_limit.load();
+  const BatchPlan P = plan_batch_graphs(G, voff, eoff, mid_limit);
+  // graphs that need the union chunks' host-driven rounds cannot be captured
+  if (!P.uni.empty()) return MSTX_ERR_INVALID_ARG;
+  const BatchLayout BL = plan_batch(G, P);
+  {
+    // the kernels' LDS limits are raised once per device (as for a solve)
+    DeviceCache* dc = nullptr;
+    std::unique_lock<std::mutex> lock;
+    const int rc = acquire(dc, lock, 0, s);
+    if (rc != MSTX_OK) return rc;
+  }
+  std::unique_ptr<BatchGraphPlan, void (*)(BatchGraphPlan*)> h(new BatchGraphPlan(), plan_free);
+  HIP_OK(hipGetDevice(&h->device));
+  if (hipMalloc(&h->mem, std::max<size_t>(BL.bytes, 256)) != hipSuccess) {
+    (void)hipGetLastError();
+    h->mem = nullptr;
+    return MSTX_ERR_OUT_OF_MEMORY;
+  }
+  void* A = h->mem;
+  auto put = [&](size_t at_, const void* p, size_t bytes) {
+    return bytes ? hipMemcpy(at<char>(A, at_), p, bytes, hipMemcpyHostToDevice) : hipSuccess;
+  };
+  HIP_OK(put(BL.voff, voff, 8 * ((size_t)G + 1)));
+  HIP_OK(put(BL.eoff, eoff, 8 * ((size_t)G + 1)));
+  HIP_OK(put(BL.small, P.small.data(), 4 * P.small.size()));
+  HIP_OK(put(BL.mid, P.mid.data(), 4 * P.mid.size()));
+  HIP_OK(put(BL.con, P.con.data(), 4 * P.con.size()));
+  HIP_OK(put(BL.cpoff, P.cpoff.data(), 8 * P.cpoff.size()));
+  HIP_OK(put(BL.csoff, P.csoff.data(), 8 * P.csoff.size()));
+  // capture on a stream of our own (default priority), so that nothing the
+  // caller enqueues meanwhile joins the graph
+  hipStream_t cs = nullptr;
+  HIP_OK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    hipError_t le = launch_fill_u8(in_mst, eoff[G], 0, cs);
+    if (le == hipSuccess) le = launch_one_workgroup_classes(P, BL, A, mid_limit, src, dst, w, in_mst, total, status, cs);
+    e = hipStreamEndCapture(cs, &h->graph);
+    if (e == hipSuccess) e = le;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&h->exec, h->graph, nullptr, nullptr, 0);
+  (void)hipStreamDestroy(cs);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return MSTX_ERR_DEVICE;
+  }
+  *out = h.release();
   return MSTX_OK;
 }
 
@@ -1655,6 +1745,37 @@ int mst_solve_end(MstxSolve* handle) {
   const int st = h->status;
   delete h;
   return st;
+}
+
+int mst_batched_plan_create(int32_t num_graphs, const int64_t* vertex_offsets, const int64_t* edge_offsets,
+                            const int32_t* src, const int32_t* dst, const uint32_t* w, uint8_t* out_in_mst,
+                            uint64_t* out_total_weight, int32_t* out_status, void* stream, MstxBatchPlan** out_plan) {
+  if (!out_plan) return MSTX_ERR_INVALID_ARG;
+  *out_plan = nullptr;
+  if (num_graphs <= 0) return MSTX_ERR_INVALID_ARG;
+  int rc = mstx::check_batch_args(num_graphs, vertex_offsets, edge_offsets, src, dst, w, out_in_mst, out_total_weight,
+                                  out_status);
+  if (rc != MSTX_OK) return rc;
+  mstx::BatchGraphPlan* h = nullptr;
+  rc = mstx::batch_plan_create(num_graphs, vertex_offsets, edge_offsets, src, dst, w, out_in_mst, out_total_weight,
+                               out_status, (hipStream_t)stream, &h);
+  if (rc != MSTX_OK) return rc;
+  *out_plan = reinterpret_cast<MstxBatchPlan*>(h);
+  return MSTX_OK;
+}
+
+int mst_batched_plan_run(MstxBatchPlan* plan, void* stream) {
+  if (!plan) return MSTX_ERR_INVALID_ARG;
+  auto* h = reinterpret_cast<mstx::BatchGraphPlan*>(plan);
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != h->device) return MSTX_ERR_INVALID_ARG;
+  return hipGraphLaunch(h->exec, (hipStream_t)stream) == hipSuccess ? MSTX_OK : MSTX_ERR_DEVICE;
+}
+
+int mst_batched_plan_destroy(MstxBatchPlan* plan) {
+  if (!plan) return MSTX_ERR_INVALID_ARG;
+  mstx::plan_free(reinterpret_cast<mstx::BatchGraphPlan*>(plan));
+  return MSTX_OK;
 }
 
 size_t mst_workspace_bytes(int32_t n, int64_t m) {

@@ -407,6 +407,7 @@ hipError_t launch_pair_collect(int round, int launched, const uint4* rec, const 
 hipError_t launch_sparse_finish(int round, int launched, const uint4* rec, SparseTable sp, const uint32_t* seg_live,
                                 int32_t nseg, uint8_t* in_mst, unsigned long long* total, DevState* st,
                                 HostRound* host, hipStream_t s);
+hipError_t launch_fill_u8(uint8_t* p, int64_t count, uint8_t v, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, int64_t count, unsigned long long v, int grid,
                            hipStream_t s);
 hipError_t launch_scan(int mode, int stage, const ScanArgs& a, int grid, size_t lds, hipStream_t s);

@@ -203,6 +203,13 @@ __global__ void __launch_bounds__(kBlock) k_init(int32_t n, int64_t m, int64_t c
   }
 }
 
+// p[0 .. count) = v, bytes (a kernel rather than a memset node, so that a
+// captured graph clears the flags with a kernel).
+__global__ void __launch_bounds__(kBlock) k_fill_u8(uint8_t* p, int64_t count, uint8_t v) {
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < count; i += stride) p[i] = v;
+}
+
 __global__ void __launch_bounds__(kBlock) k_fill_u64(unsigned long long* p, int64_t count, unsigned long long v) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = v;
@@ -2307,6 +2314,14 @@ hipError_t launch_init(int32_t n, int64_t m, int64_t cmap_off, int dense_limit, 
                        int32_t* parent, unsigned long long* pbest, uint32_t* btot, SparseTable sp, DevState* st,
                        int grid, hipStream_t s) {
   k_init<<<grid, kBlock, 0, s>>>(n, m, cmap_off, dense_limit, best, parent, pbest, btot, sp, st);
+  MSTX_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+hipError_t launch_fill_u8(uint8_t* p, int64_t count, uint8_t v, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  const int64_t blocks = (count + 16 * kBlock - 1) / (16 * kBlock);
+  k_fill_u8<<<(int)(blocks < 4096 ? blocks : 4096), kBlock, 0, s>>>(p, count, v);
   MSTX_LAUNCH_CHECK();
   return hipSuccess;
 }

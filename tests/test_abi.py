@@ -271,3 +271,23 @@ def test_sparse_limit_option(lib):
         assert B.mst_set_sparse_limit(-1) == 0
     finally:
         B.mst_set_sparse_limit(prev)
+
+
+def test_batched_plan_host_checks(lib):
+    """mst_batched_plan_create / run / destroy refuse bad arguments on the host."""
+    from paper_2005_06913_amd import binding as B
+    c = ctypes
+    h = c.c_void_p(0)
+    dummy = c.c_void_p(16)
+    vo = np.array([0, 3, 2], np.int64)  # decreasing offsets
+    eo = np.array([0, 1, 2], np.int64)
+    ptr = lambda a: a.ctypes.data_as(c.c_void_p)
+    assert lib.mst_batched_plan_create(2, ptr(vo), ptr(eo), dummy, dummy, dummy, dummy, dummy, dummy, None,
+                                       c.byref(h)) == B.MSTX_ERR_INVALID_ARG
+    assert lib.mst_batched_plan_create(0, None, None, None, None, None, None, None, None, None,
+                                       c.byref(h)) == B.MSTX_ERR_INVALID_ARG
+    assert lib.mst_batched_plan_create(1, ptr(vo), ptr(eo), dummy, dummy, dummy, dummy, dummy, dummy, None,
+                                       None) == B.MSTX_ERR_INVALID_ARG
+    assert h.value is None
+    assert lib.mst_batched_plan_run(None, None) == B.MSTX_ERR_INVALID_ARG
+    assert lib.mst_batched_plan_destroy(None) == B.MSTX_ERR_INVALID_ARG

@@ -258,3 +258,64 @@ def test_batched_empty_and_args(dev):
     import ctypes
     ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)
     assert lib.mst_solve_batched(2, ptr(bad), ptr(ok), None, None, None, None, None, None, None) == P.MSTX_ERR_INVALID_ARG
+
+
+def test_batched_plan_replays(dev):
+    """A batch planned once and captured as a HIP graph (mst_batched_plan_*):
+    three replays, with the weights rewritten and other solves run on the
+    stream between them; every replay equals mst_solve_batched on the same
+    inputs, and the oracle on every graph."""
+    import paper_2005_06913_amd as P
+    from paper_2005_06913_amd import graphgen as G
+    b = G.batch(40, seed=61, n_lo=64, n_hi=60_000)
+    vo, eo = b.vertex_offsets, b.edge_offsets
+    m, Gn = int(eo[-1]), b.num_graphs
+    src, dst = torch.from_numpy(b.src).to(dev), torch.from_numpy(b.dst).to(dev)
+    w = torch.from_numpy(b.w).to(dev)
+    flags = torch.full((m,), 7, dtype=torch.uint8, device=dev)
+    tot = torch.full((Gn,), 5, dtype=torch.int64, device=dev).view(torch.uint64)
+    st = torch.full((Gn,), 9, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+    print("[case] batched plan: 40 graphs, capture", flush=True)
+    rc, plan = P.mst_batched_plan_create(vo, eo, src, dst, w, flags, tot, st, stream)
+    assert rc == 0 and plan is not None
+    other = G.tree_plus_extra(50_000, 300_000, seed=63)
+    os_, od, ow = (torch.from_numpy(a).to(dev) for a in (other.src, other.dst, other.w))
+    rng = np.random.default_rng(64)
+    try:
+        for rep in range(3):
+            wn = b.w if rep == 0 else rng.permutation(b.w).astype(np.uint32)
+            w.copy_(torch.from_numpy(wn))
+            assert P.solve(other.n, os_, od, ow).status == 0  # eager work between replays
+            print(f"[case] batched plan: replay {rep}", flush=True)
+            assert P.mst_batched_plan_run(plan, stream) == 0
+            torch.cuda.synchronize()
+            got_f, got_t = flags.cpu().numpy(), tot.view(torch.int64).cpu().numpy()
+            got_s = st.cpu().numpy()
+            rc2, ref_f, ref_t, ref_s = run_batched(dev, vo, eo, b.src, b.dst, wn)
+            assert rc2 == 0
+            assert np.array_equal(got_f, ref_f) and np.array_equal(got_t, ref_t) and np.array_equal(got_s, ref_s)
+            for g in range(Gn):
+                a, c = int(eo[g]), int(eo[g + 1])
+                k = oracle.kruskal(int(vo[g + 1] - vo[g]), b.src[a:c], b.dst[a:c], wn[a:c])
+                assert got_s[g] == k.status and int(got_t[g]) == k.total, (rep, g)
+                assert np.array_equal(got_f[a:c], k.in_mst), (rep, g)
+    finally:
+        torch.cuda.synchronize()
+        assert P.mst_batched_plan_destroy(plan) == 0
+
+
+def test_batched_plan_refuses_union_graphs(dev):
+    """A batch with a graph that needs the union rounds cannot be captured."""
+    import paper_2005_06913_amd as P
+    from paper_2005_06913_amd import graphgen as G
+    big = G.tree_plus_extra(70_000, 200_000, seed=65)
+    small = G.tree_plus_extra(1000, 5000, seed=66)
+    vo, eo, s, d, w = concat([(big.n, big.src, big.dst, big.w), (small.n, small.src, small.dst, small.w)])
+    m = int(eo[-1])
+    args = [torch.from_numpy(a).to(dev) for a in (s, d, w)]
+    flags = torch.empty(m, dtype=torch.uint8, device=dev)
+    tot = torch.empty(2, dtype=torch.uint64, device=dev)
+    st = torch.empty(2, dtype=torch.int32, device=dev)
+    rc, plan = P.mst_batched_plan_create(vo, eo, *args, flags, tot, st)
+    assert rc == P.MSTX_ERR_INVALID_ARG and plan is None
