@@ -363,14 +363,6 @@ struct LaunchTimer {
 };
 thread_local LaunchTimer t_timer;
 
-// Mode that handles `bound` components when it is the exact count.
-int mode_for(int64_t nr, int dense_limit, int64_t bucket_limit) {
-  if (nr <= dense_limit) return kModeDense;
-  if (nr <= kLdsSlots) return kModeLds;
-  if (nr <= bucket_limit) return kModeBucket;
-  return kModeGlobal;
-}
-
 // Everything one solve needs to enqueue its rounds.
 struct Solve {
   int32_t n;
@@ -1379,10 +1371,6 @@ int solve_batched(int32_t G, const int64_t* voff, const int64_t* eoff, const int
   auto* d_con = at<int32_t>(A, BL.con);
   auto* d_cpoff = at<int64_t>(A, BL.cpoff);
   auto* d_csoff = at<int64_t>(A, BL.csoff);
-  auto* d_cnum = at<int32_t>(A, BL.cnum);
-  auto* d_pcnt = at<int32_t>(A, BL.pcnt);
-  auto* d_pbad = at<int32_t>(A, BL.pbad);
-  auto* d_pairs = at<uint32_t>(A, BL.pairs);
   auto* tot = reinterpret_cast<unsigned long long*>(total);
 
   HIP_OK(hipMemcpyAsync(d_voff, voff, 8 * ((size_t)G + 1), hipMemcpyHostToDevice, s));
