@@ -424,7 +424,7 @@ int enqueue_scan(Solve& S, int r, int stage, int64_t bound, bool exact, hipError
   launched |= S.dense_limit << 8;
   ScanArgs A{r,         launched,   S.src,    S.dst,  S.w,      (uint32_t)S.m, S.n,      S.labpool,
              S.rec,     S.seg_cnt,  S.seg_live, S.L.nseg, S.best, S.st,     S.offers,      S.offT,   S.slab,
-             S.L.slab_cap, S.pbest, 0,          S.btot};
+             S.L.slab_cap, S.pbest, 0,          S.btot,    S.in_mst};
   const int cus = S.cus;
   for (int mode : {kModeDense, kModeLds, kModeBucket, kModeGlobal}) {
     if (!(launched & (1 << mode))) continue;

@@ -267,6 +267,7 @@ struct ScanArgs {
   int32_t lds_bytes;            // dynamic LDS of the launch (LDS / DENSE mode: the table for n_r,
                                 // then the first entries of the label map that fit, rounds >= 2)
   uint32_t* btot;               // BUCKET mode: offers per bucket, summed over the scan [kMaxBuckets]
+  const uint8_t* in_mst;        // round 1: the edges round 0 added (dead now), or null
 };
 
 // LDS-mode minima of more than kSlabMin components are flushed through a
