@@ -72,6 +72,10 @@ class Request:
     batch_size: int = 0
     slot: int = -1
     done: threading.Event = field(default_factory=threading.Event)
+    # resident requests: an event recorded on the submitting thread's current
+    # stream at submit(); the solve's stream waits for it before reading the
+    # arrays, so they may still be being written by work enqueued before submit
+    ready: object = None
 
     @property
     def m(self) -> int:
@@ -79,8 +83,26 @@ class Request:
 
     @property
     def resident(self) -> bool:
-        """The graph's arrays are device tensors (no host-to-device copy)."""
+        """The graph's arrays are device tensors (no host-to-device copy).
+
+        A resident request's in_mst is a view of a tensor the server allocated
+        on one of its streams; a caller that uses it on another stream calls
+        ``record_stream`` on it, as for any tensor shared between streams."""
         return bool(getattr(self.src, "is_cuda", False))
+
+    def mark_submitted(self) -> None:
+        """Arrival time, and for a resident request the event its solve waits for."""
+        self.arrival = time.perf_counter()
+        if self.resident:
+            import torch
+
+            self.ready = torch.cuda.Event()
+            self.ready.record(torch.cuda.current_stream(self.src.device))
+
+    def wait_ready(self, stream) -> None:
+        """Orders `stream` after the work that wrote a resident request's arrays."""
+        if self.ready is not None:
+            stream.wait_event(self.ready)
 
     def flags(self) -> np.ndarray:
         """in_mst as a host array (copied from the device for a resident request)."""
@@ -145,6 +167,7 @@ class GpuExecutor:
         if solo:
             (r,) = reqs
             with torch.cuda.stream(stream):
+                r.wait_ready(stream)
                 src, dst, w = (self._on_device(a) for a in (r.src, r.dst, r.w))
                 in_mst = torch.empty(r.m, dtype=torch.uint8, device=self.dev)
                 total = torch.empty(1, dtype=torch.uint64, device=self.dev)
@@ -156,6 +179,8 @@ class GpuExecutor:
         m = int(eo[-1])
         G = len(reqs)
         with torch.cuda.stream(stream):
+            for r in reqs:
+                r.wait_ready(stream)
             if all(r.resident for r in reqs):
                 # one concatenation per array inside HBM (weights as int32 bits)
                 src = torch.cat([r.src for r in reqs])
@@ -200,6 +225,7 @@ class _SoloJob:
         torch = ex.torch
         self.ex, self.r, self.stream = ex, r, ex.streams[slot]
         with torch.cuda.stream(self.stream):
+            r.wait_ready(self.stream)
             self.src, self.dst, self.w = (ex._on_device(a) for a in (r.src, r.dst, r.w))
             self.in_mst = torch.empty(r.m, dtype=torch.uint8, device=ex.dev)
             self.total = torch.empty(1, dtype=torch.uint64, device=ex.dev)
@@ -264,7 +290,7 @@ class MstServer:
         return self
 
     def submit(self, req: Request) -> Request:
-        req.arrival = time.perf_counter()
+        req.mark_submitted()
         with self.cv:
             self.queue.append(req)
             self.cv.notify()
@@ -420,7 +446,7 @@ class PlainServer:
         return self
 
     def submit(self, req: Request) -> Request:
-        req.arrival = time.perf_counter()
+        req.mark_submitted()
         with self.cv:
             self.queue.append(req)
             self.cv.notify()
@@ -442,6 +468,7 @@ class PlainServer:
                     return
                 r = self.queue.popleft()
             with torch.cuda.stream(self.stream):
+                r.wait_ready(self.stream)
                 src, dst, w = (a if isinstance(a, torch.Tensor) else torch.from_numpy(a).to(self.dev, non_blocking=True)
                                for a in (r.src, r.dst, r.w))
                 in_mst = torch.empty(r.m, dtype=torch.uint8, device=self.dev)

@@ -174,3 +174,39 @@ def test_resident_requests(dev):
         assert np.array_equal(r.flags(), k.in_mst) and np.array_equal(p.flags(), k.in_mst), r.rid
     assert any(len(ids) > 1 for _, ids in srv.batches)
     ex.release()
+
+
+@pytest.mark.parametrize("server", ["batched", "solo", "plain"])
+def test_resident_request_waits_for_its_producer(dev, server):
+    """A resident request whose arrays are still being written on the
+    submitting thread's stream (behind a 20-ms spin) is solved only after
+    them: its result equals the oracle's.  Small requests go through the
+    batched call, large ones through the round-by-round solve."""
+    from paper_2005_06913_amd import graphgen as G
+    from paper_2005_06913_amd import serve
+    n, m = (20_000, 120_000) if server != "solo" else (300_000, 2_400_000)
+    g = G.tree_plus_extra(n, m, seed=34)
+    staged = [torch.from_numpy(a).to(dev) for a in (g.src, g.dst, g.w)]
+    arrays = [torch.zeros_like(t) for t in staged]
+    torch.cuda.synchronize()
+    if server == "plain":
+        srv = serve.PlainServer(device=dev).start()
+        ex = None
+    else:
+        ex = serve.GpuExecutor(slots=1, device=dev)
+        srv = serve.MstServer(ex, slots=1, hbm_budget_bytes=4 << 30).start()
+    producer = torch.cuda.Stream(device=dev)
+    print(f"[case] resident request behind its producer, {server}", flush=True)
+    with torch.cuda.stream(producer):
+        torch.cuda._sleep(50_000_000)  # a bounded spin, then the arrays are written
+        for a, t in zip(arrays, staged):
+            a.copy_(t)
+        r = srv.submit(serve.Request(0, g.n, *arrays))
+    r.done.wait()
+    srv.close()
+    k = oracle.kruskal(g.n, g.src, g.dst, g.w)
+    assert r.status == k.status == 0, r.status
+    assert r.total == k.total
+    assert np.array_equal(r.flags(), k.in_mst)
+    if ex is not None:
+        ex.release()
