@@ -288,8 +288,9 @@ def lookup(cls: str, path: Optional[str] = None) -> Optional[Dict[str, int]]:
     from `path` (default: the user cache), else from the shipped file."""
     dev = device_key()
     for p in ([path] if path else [cache_path(), SHIPPED]):
-        e = load_cache(p)["entries"].get(dev, {}).get(cls)
-        if e is not None:
+        per_dev = load_cache(p)["entries"].get(dev)
+        e = per_dev.get(cls) if isinstance(per_dev, dict) else None
+        if isinstance(e, dict) and isinstance(e.get("knobs"), dict):  # a malformed entry is skipped
             return {k: int(v) for k, v in e["knobs"].items() if k in SETTERS}
     return None
 

@@ -76,3 +76,14 @@ def test_search_spaces_only_known_knobs():
     for space in (A.SINGLE_KNOBS, A.BATCH_KNOBS):
         assert set(space) <= set(A.SETTERS)
         assert A.search_space_size(space) > 1
+
+
+def test_lookup_skips_malformed_entries(tmp_path, monkeypatch):
+    monkeypatch.setattr(A, "device_key", lambda: "dev")
+    p = str(tmp_path / "t.json")
+    cls = "single/n2^10/deg2^3"
+    for entry in ({cls: {"ms": 1.0}}, {cls: "x"}, "not a dict", {cls: {"knobs": [1]}}):
+        A.save_cache({"version": 1, "entries": {"dev": entry}}, p)
+        assert A.lookup(cls, p) is None
+    A.save_cache({"version": 1, "entries": {"dev": {cls: {"knobs": {"dense_limit": 64, "unknown": 1}}}}}, p)
+    assert A.lookup(cls, p) == {"dense_limit": 64}
