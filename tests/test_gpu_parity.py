@@ -14,6 +14,8 @@ default limit and at limits that make it start in earlier or later rounds,
 with the sparse finish at its default and off.
 """
 
+import functools
+
 import numpy as np
 import pytest
 
@@ -303,3 +305,33 @@ def test_solve_increasing_path_2_20(dev, tail):
     g = G.path_graph(1 << 20)
     gstats = check_against_oracle(dev, g.name, g.n, g.src, g.dst, g.w, tail=tail)
     assert len(gstats) == 1 and int(gstats[0][2]) == g.n - 1
+
+
+# ------------------------------------------- more than 256 offer buckets
+
+@functools.lru_cache(maxsize=1)
+def _five_million():
+    """n = 5,000,000 > 256 * 16384: round 0's bucket minima take 306 buckets of
+    the widest size, whose offer runs are not padded (the headline sizes use
+    at most 256 padded buckets)."""
+    from paper_2005_06913_amd import graphgen as G
+    return G.tree_plus_extra(5_000_000, 20_000_000, seed=41, name="tree_plus_extra_n5M_m20M")
+
+
+@pytest.mark.timeout(300)
+def test_min_edge_keys_more_than_256_buckets(dev):
+    import paper_2005_06913_amd as P
+    g = _five_million()
+    print(f"[case] min-edge {g.name}", flush=True)
+    s, d, w = to_dev(dev, g.src, g.dst, g.w)
+    out = torch.zeros(g.n, dtype=torch.int64, device=dev).view(torch.uint64)
+    assert P.mst_select_min_edges(g.n, s, d, w, out) == 0
+    st, want = oracle.min_edge_keys(g.n, g.src, g.dst, g.w)
+    assert st == 0
+    assert np.array_equal(out.view(torch.int64).cpu().numpy().view(np.uint64), want)
+
+
+@pytest.mark.timeout(300)
+def test_solve_more_than_256_buckets(dev):
+    g = _five_million()
+    check_against_oracle(dev, g.name, g.n, g.src, g.dst, g.w, stats=True)
