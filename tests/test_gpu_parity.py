@@ -335,3 +335,52 @@ def test_min_edge_keys_more_than_256_buckets(dev):
 def test_solve_more_than_256_buckets(dev):
     g = _five_million()
     check_against_oracle(dev, g.name, g.n, g.src, g.dst, g.w, stats=True)
+
+
+@pytest.mark.timeout(600)
+def test_solve_edge_positions_beyond_2_31(dev):
+    """m = 2^31 + 2^23 - 1 edges (about 100 GB of device memory with the
+    workspace), built on the device: 2^31 uniform extra edges first, weighing
+    n .. n + 2^31 - 1, then a random recursive tree on n = 2^23 vertices whose
+    edges weigh a permutation of 1 .. n - 1, at positions beyond 2^31.  Every
+    extra edge is the heaviest on the cycle it closes with the tree, so the
+    MST is the tree (closed form: total n(n - 1)/2, exactly the last n - 1
+    flags set)."""
+    import paper_2005_06913_amd as P
+    n, m_extra = 1 << 23, 1 << 31
+    m = m_extra + n - 1
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(51)
+    src = torch.empty(m, dtype=torch.int32, device=dev)
+    dst = torch.empty(m, dtype=torch.int32, device=dev)
+    w = torch.empty(m, dtype=torch.int32, device=dev)  # uint32 bits
+    chunk = 1 << 28
+    for off in range(0, m_extra, chunk):
+        u = torch.randint(0, n, (chunk,), generator=gen, device=dev, dtype=torch.int64)
+        v = (u + 1 + torch.randint(0, n - 1, (chunk,), generator=gen, device=dev, dtype=torch.int64)) % n
+        src[off:off + chunk] = u.to(torch.int32)
+        dst[off:off + chunk] = v.to(torch.int32)
+        w[off:off + chunk] = (n + off + torch.arange(chunk, device=dev, dtype=torch.int64)).to(torch.int32)
+        del u, v
+    i = torch.arange(1, n, device=dev, dtype=torch.int64)
+    parent = (torch.rand(n - 1, generator=gen, device=dev, dtype=torch.float64) * i).floor().to(torch.int64)
+    src[m_extra:] = i.to(torch.int32)
+    dst[m_extra:] = parent.to(torch.int32)
+    w[m_extra:] = (torch.randperm(n - 1, generator=gen, device=dev) + 1).to(torch.int32)
+    del i, parent
+    in_mst = torch.full((m,), 7, dtype=torch.uint8, device=dev)
+    total = torch.zeros(1, dtype=torch.uint64, device=dev)
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    print(f"[case] edge positions beyond 2^31: n={n} m={m}", flush=True)
+    st = P.mst_solve(n, src, dst, w.view(torch.uint32), in_mst, total, stream)
+    torch.cuda.synchronize()
+    try:
+        assert st == 0, st
+        assert int(total.view(torch.int64).item()) == n * (n - 1) // 2
+        assert not bool(torch.any(in_mst[:m_extra] != 0))
+        assert bool(torch.all(in_mst[m_extra:] == 1))
+    finally:
+        del src, dst, w, in_mst
+        P.mst_workspace_release(stream)
+        torch.cuda.empty_cache()
