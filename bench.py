@@ -46,6 +46,13 @@ WORKLOAD_TEXT["cpu_context"] = ("Table 1 shapes of the paper: n in {10K, 100K, 1
 PAPER_SPEEDUPS = {"parallel_lock": {"vs_sequential": 1.94, "vs_sequential_covered": 1.40},
                   "parallel_cas": {"vs_sequential": 2.03, "vs_sequential_covered": 1.403},
                   "host": "Intel Xeon E-2186G, 6 cores / 12 threads, 3.86 GHz; best at 4 threads"}
+# graphs built on the device (too large for the host generator and the oracle):
+# their parity is the closed form of the planted tree
+DEVICE_WORKLOADS = {"planted_n8M_m2G": dict(n=1 << 23, m_extra=1 << 31, seed=51)}
+WORKLOAD_TEXT["planted_n8M_m2G"] = ("n = 2^23, m = 2^31 + 2^23 - 1: 2^31 uniform extra pairs weighing n .. n + 2^31 - 1 "
+                                    "in order, then a random recursive tree whose edges weigh a permutation of "
+                                    "1 .. n - 1, at positions beyond 2^31; built on the device, seed 51; the MST "
+                                    "is the tree (closed form)")
 WORKLOAD_TEXT["served"] = ("Poisson request stream, each request one connected random graph: n log-uniform in "
                            "[1024, 1048576], average degree uniform in [4, 32], random spanning tree + uniform "
                            "extra pairs, weights a permutation of 1..m, seed 6")
@@ -655,14 +662,23 @@ def main() -> int:
     P.load_library()
     from paper_2005_06913_amd import autotune
     log(f"[bench] generating {args.workload}")
-    g = G.workload(args.workload)
+    spec = DEVICE_WORKLOADS.get(args.workload)
+    if spec:
+        src, dst, w = G.planted_on_device(spec["n"], spec["m_extra"], spec["seed"], dev)
+        w = w.view(torch.uint32)
+        g = G.Graph(spec["n"], np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0, np.uint32), args.workload)
+        g_m = int(src.numel())
+    else:
+        g = G.workload(args.workload)
+        g_m = g.m
     # the autotuner's settings for this graph class on this device, if any
-    tuned = autotune.tuned_single(g.n, g.m)
+    tuned = autotune.tuned_single(g.n, g_m)
     knobs = tuned.__enter__()
-    src = torch.from_numpy(g.src).to(dev)
-    dst = torch.from_numpy(g.dst).to(dev)
-    w = torch.from_numpy(g.w).to(dev)
-    in_mst = torch.empty(g.m, dtype=torch.uint8, device=dev)
+    if not spec:
+        src = torch.from_numpy(g.src).to(dev)
+        dst = torch.from_numpy(g.dst).to(dev)
+        w = torch.from_numpy(g.w).to(dev)
+    in_mst = torch.empty(g_m, dtype=torch.uint8, device=dev)
     total = torch.empty(1, dtype=torch.uint64, device=dev)
     stream = torch.cuda.current_stream()
 
@@ -762,7 +778,7 @@ def main() -> int:
         parts = [k for k, v in r0.items() if k.startswith("k_scan") and v["alg_bytes"]]
         parts += [k for k in ("k_bucket_min", "k_slab_min") if k in r0]
         us0 = sum(r0[k]["us_per_step"] for k in parts)
-        b0 = 12.0 * g.m + 16.0 * g.n
+        b0 = 12.0 * g_m + 16.0 * g.n
         bar = {"step": "round-0 edge scan and its minima (" + " + ".join(parts) + ")", "alg_bytes": b0,
                "us": us0, "achieved_GBs": b0 / (us0 * 1e-6) / 1e9 if us0 else None,
                "frac": b0 / (us0 * 1e-6) / 1e9 / HBM_PEAK_GBS if us0 else None,
@@ -770,7 +786,7 @@ def main() -> int:
 
     out = {
         "metric": METRIC,
-        "value": g.m / (ms_per_step * 1e-3),
+        "value": g_m / (ms_per_step * 1e-3),
         "unit": "edges/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -781,7 +797,7 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {WORKLOAD_TEXT[args.workload]}", "n": g.n, "m": g.m,
+        "config": {"workload": f"{args.workload}: {WORKLOAD_TEXT[args.workload]}", "n": g.n, "m": g_m,
                    "leg": "single graph", "rounds": int(len(stats)), "knobs": knobs or "library defaults",
                    "round_stats": stats.tolist()},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -795,7 +811,16 @@ def main() -> int:
         "cold_ms_per_step": {"median": statistics.median(cold) if cold else None, "all": cold},
         "total_weight": res_total,
     }
-    if not args.no_cpu_baseline:
+    if spec:
+        # the planted tree: exactly the last n - 1 flags, weight n(n - 1)/2
+        tree_at = g_m - (g.n - 1)
+        out["parity_vs_closed_form"] = bool(res_total == g.n * (g.n - 1) // 2
+                                            and not bool(torch.any(in_mst[:tree_at] != 0))
+                                            and bool(torch.all(in_mst[tree_at:] == 1)))
+        out["cpu_baseline"] = None
+        out["cpu_baseline_note"] = "no oracle leg: the graph exists on the device only"
+        out["workspace_bytes"] = int(P.mst_workspace_bytes(g.n, g_m))
+    elif not args.no_cpu_baseline:
         log(f"[bench] cpu oracle leg (~{args.cpu_seconds:.0f} s)")
         cb, ref = cpu_baseline(g, args.cpu_seconds)
         out["cpu_baseline"] = cb

@@ -729,6 +729,19 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* sh, ui
   return base + x - v;
 }
 
+// Sum of one 64-bit value per thread over a 1024-thread block, returned to
+// every thread.  `sh` holds kScanWaves words.
+__device__ __forceinline__ unsigned long long block_sum64(unsigned long long v, unsigned long long* sh) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if (lane_id() == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  unsigned long long tot = 0;
+#pragma unroll
+  for (int i = 0; i < kScanWaves; ++i) tot += sh[i];
+  __syncthreads();  // sh may be reused
+  return tot;
+}
+
 // The minimum offer of every component of a bucket, over the run
 // offT[p][s] (start, length) of the bucket in every segment s, taken in LDS.
 //
@@ -758,6 +771,7 @@ __global__ void __launch_bounds__(kScanBlock) k_bucket_min(int round, int launch
                                                            const DevState* __restrict__ st) {
   extern __shared__ unsigned long long table[];  // [B] minima, then the staging below
   __shared__ uint32_t sh[kScanWaves];
+  __shared__ unsigned long long sh64[kScanWaves];
   const int32_t nr = st->n[round];
   if (nr <= 1 && round > 0) return;
   if (round > 0 && st->err) return;  // the scan of this round did nothing either
@@ -770,13 +784,16 @@ __global__ void __launch_bounds__(kScanBlock) k_bucket_min(int round, int launch
   uint32_t* uprefix = iprefix + kChunkRuns + 1;              // [kMaxBuckets + 1]
   const int tid = threadIdx.x;
 
-  // work units of every bucket (nbk <= kScanBlock - 1: one bucket per thread)
-  uint32_t all;
-  const uint32_t tot_p = tid < nbk ? btot[tid] : 0u;
-  (void)block_excl_scan(tot_p, sh, &all);
+  // work units of every bucket (nbk <= kScanBlock - 1: one bucket per thread);
+  // their sum in 64 bits: a round of more than 2^31 live edges makes more
+  // than 2^32 offers.  (A single bucket's 32-bit count wraps only past 2^32
+  // offers into one bucket; its units are then fewer than they should be,
+  // never its segments.)
+  const unsigned long long tot_p = tid < nbk ? btot[tid] : 0ull;
+  const unsigned long long all = block_sum64(tot_p, sh64);
   // target >= twice the average, so the extra units number at most nbk / 2
   const uint64_t target = max((uint64_t)1, (2 * (uint64_t)all + (uint32_t)nbk - 1) / (uint32_t)nbk);
-  uint32_t units = tid < nbk ? 1u + (uint32_t)((uint64_t)tot_p / target) : 0u;
+  uint32_t units = tid < nbk ? 1u + (uint32_t)(tot_p / target) : 0u;
   uint32_t total_units;
   uint32_t ex = block_excl_scan(units, sh, &total_units);
   if (total_units > gridDim.x) {  // never with the host's grid; one unit per bucket then

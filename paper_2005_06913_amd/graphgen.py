@@ -43,6 +43,7 @@ __all__ = [
     "WORKLOADS",
     "Batch",
     "batch",
+    "planted_on_device",
 ]
 
 
@@ -302,6 +303,39 @@ def workload(name: str) -> Graph:
     if name not in WORKLOADS:
         raise KeyError(f"unknown workload {name!r}; known: {sorted(WORKLOADS)}")
     return WORKLOADS[name]()
+
+
+def planted_on_device(n: int, m_extra: int, seed: int, device, chunk: int = 1 << 28):
+    """A graph too large to build on the host, built on `device` (torch tensors
+    int32 src, dst and weights as int32 bits of uint32): m_extra uniform extra
+    pairs (u != v) first, weighing n .. n + m_extra - 1 in order, then a random
+    recursive tree on n vertices (vertex i joins a uniform earlier vertex)
+    whose edges weigh a random permutation of 1 .. n - 1.  Every extra edge is
+    heavier than every tree edge, so the minimum spanning tree is the tree:
+    its flags are exactly the last n - 1 and its weight n(n - 1)/2."""
+    import torch
+
+    assert 2 <= n <= 1 << 30 and 0 <= m_extra and n + m_extra <= 1 << 32
+    m = m_extra + n - 1
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    src = torch.empty(m, dtype=torch.int32, device=device)
+    dst = torch.empty(m, dtype=torch.int32, device=device)
+    w = torch.empty(m, dtype=torch.int32, device=device)
+    for off in range(0, m_extra, chunk):
+        k = min(chunk, m_extra - off)
+        u = torch.randint(0, n, (k,), generator=gen, device=device, dtype=torch.int64)
+        v = (u + 1 + torch.randint(0, n - 1, (k,), generator=gen, device=device, dtype=torch.int64)) % n
+        src[off:off + k] = u.to(torch.int32)
+        dst[off:off + k] = v.to(torch.int32)
+        w[off:off + k] = (n + off + torch.arange(k, device=device, dtype=torch.int64)).to(torch.int32)
+        del u, v
+    i = torch.arange(1, n, device=device, dtype=torch.int64)
+    parent = (torch.rand(n - 1, generator=gen, device=device, dtype=torch.float64) * i).floor().to(torch.int64)
+    src[m_extra:] = i.to(torch.int32)
+    dst[m_extra:] = parent.to(torch.int32)
+    w[m_extra:] = (torch.randperm(n - 1, generator=gen, device=device) + 1).to(torch.int32)
+    return src, dst, w
 
 
 

@@ -347,27 +347,10 @@ def test_solve_edge_positions_beyond_2_31(dev):
     MST is the tree (closed form: total n(n - 1)/2, exactly the last n - 1
     flags set)."""
     import paper_2005_06913_amd as P
+    from paper_2005_06913_amd import graphgen as G
     n, m_extra = 1 << 23, 1 << 31
     m = m_extra + n - 1
-    gen = torch.Generator(device=dev)
-    gen.manual_seed(51)
-    src = torch.empty(m, dtype=torch.int32, device=dev)
-    dst = torch.empty(m, dtype=torch.int32, device=dev)
-    w = torch.empty(m, dtype=torch.int32, device=dev)  # uint32 bits
-    chunk = 1 << 28
-    for off in range(0, m_extra, chunk):
-        u = torch.randint(0, n, (chunk,), generator=gen, device=dev, dtype=torch.int64)
-        v = (u + 1 + torch.randint(0, n - 1, (chunk,), generator=gen, device=dev, dtype=torch.int64)) % n
-        src[off:off + chunk] = u.to(torch.int32)
-        dst[off:off + chunk] = v.to(torch.int32)
-        w[off:off + chunk] = (n + off + torch.arange(chunk, device=dev, dtype=torch.int64)).to(torch.int32)
-        del u, v
-    i = torch.arange(1, n, device=dev, dtype=torch.int64)
-    parent = (torch.rand(n - 1, generator=gen, device=dev, dtype=torch.float64) * i).floor().to(torch.int64)
-    src[m_extra:] = i.to(torch.int32)
-    dst[m_extra:] = parent.to(torch.int32)
-    w[m_extra:] = (torch.randperm(n - 1, generator=gen, device=dev) + 1).to(torch.int32)
-    del i, parent
+    src, dst, w = G.planted_on_device(n, m_extra, seed=51, device=dev)
     in_mst = torch.full((m,), 7, dtype=torch.uint8, device=dev)
     total = torch.zeros(1, dtype=torch.uint64, device=dev)
     stream = torch.cuda.current_stream()
