@@ -1,7 +1,7 @@
 """The CPU oracle against what the paper and mathematics fix (no GPU).
 
 Each pin is described in ``tests/mst_pins.py``.  These tests establish that
-the oracle can be trusted before it is used to judge the GPU path.
+the oracle can be trusted before the GPU path is compared with it.
 """
 
 import numpy as np
