@@ -122,7 +122,7 @@ def test_round_granular_admission_gpu(dev):
     b = G.batch(24, seed=28, n_lo=100, n_hi=4000)
     small = [serve.Request(i, *(lambda x: (x.n, x.src, x.dst, x.w))(b.graph(i))) for i in range(b.num_graphs)]
     ex = serve.GpuExecutor(slots=1, device=dev)
-    srv = serve.MstServer(ex, slots=1, hbm_budget_bytes=8 << 30).start()
+    srv = serve.MstServer(ex, slots=1, hbm_budget_bytes=8 << 30, solo_edges=1 << 19).start()
     print("[case] round-granular admission, 1 slot", flush=True)
     srv.submit(big)
     time.sleep(0.0005)
@@ -158,7 +158,7 @@ def test_resident_requests(dev):
     reqs = requests()
     assert all(r.resident for r in reqs)
     ex = serve.GpuExecutor(slots=2, device=dev)
-    srv = serve.MstServer(ex, slots=2, hbm_budget_bytes=4 << 30).start()
+    srv = serve.MstServer(ex, slots=2, hbm_budget_bytes=4 << 30, solo_edges=1 << 19).start()
     print("[case] resident requests, 2 slots", flush=True)
     serve.poisson_replay(srv, reqs, qps=5000.0, seed=31)
     srv.close()
@@ -194,7 +194,7 @@ def test_resident_request_waits_for_its_producer(dev, server):
         ex = None
     else:
         ex = serve.GpuExecutor(slots=1, device=dev)
-        srv = serve.MstServer(ex, slots=1, hbm_budget_bytes=4 << 30).start()
+        srv = serve.MstServer(ex, slots=1, hbm_budget_bytes=4 << 30, solo_edges=1 << 19).start()
     producer = torch.cuda.Stream(device=dev)
     print(f"[case] resident request behind its producer, {server}", flush=True)
     with torch.cuda.stream(producer):
