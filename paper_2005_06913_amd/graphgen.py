@@ -315,7 +315,8 @@ def planted_on_device(n: int, m_extra: int, seed: int, device, chunk: int = 1 <<
     its flags are exactly the last n - 1 and its weight n(n - 1)/2."""
     import torch
 
-    assert 2 <= n <= 1 << 30 and 0 <= m_extra and n + m_extra <= 1 << 32
+    if not (2 <= n <= 1 << 30 and 0 <= m_extra and n + m_extra <= 1 << 32):
+        raise ValueError(f"planted_on_device: n = {n}, m_extra = {m_extra} out of range")
     m = m_extra + n - 1
     gen = torch.Generator(device=device)
     gen.manual_seed(seed)
