@@ -339,7 +339,7 @@ def test_solve_more_than_256_buckets(dev):
 
 @pytest.mark.timeout(600)
 def test_solve_edge_positions_beyond_2_31(dev):
-    """m = 2^31 + 2^23 - 1 edges (about 100 GB of device memory with the
+    """m = 2^31 + 2^23 - 1 edges (about 117 GB of device memory with the
     workspace), built on the device: 2^31 uniform extra edges first, weighing
     n .. n + 2^31 - 1, then a random recursive tree on n = 2^23 vertices whose
     edges weigh a permutation of 1 .. n - 1, at positions beyond 2^31.  Every
