@@ -221,3 +221,38 @@ def test_round_granular_admission():
         assert r.status == k.status == 0 and r.total == k.total
         assert np.array_equal(r.in_mst, k.in_mst)
     assert srv.in_flight_bytes == 0
+
+
+class RoutingExecutor:
+    """Records how each batch was run (alone or batched) and fills dummy results."""
+
+    def __init__(self):
+        self.runs = []  # (solo, [request ids])
+
+    def batch_bytes(self, reqs, solo=False):
+        return sum(r.data_bytes() for r in reqs)
+
+    def execute(self, slot, reqs, solo=False):
+        self.runs.append((solo, [r.rid for r in reqs]))
+        for r in reqs:
+            r.in_mst, r.total, r.status = None, 0, 0
+
+
+def test_default_thresholds_route_by_edge_count():
+    """With the default thresholds a request of fewer than 2^22 edges joins a
+    batched call (several of them up to 2^23 edges in one) and one of 2^22
+    edges or more is solved alone."""
+    def req(rid, m):
+        z = np.zeros(m, np.int32)
+        return serve.Request(rid, 2, z, z, z.view(np.uint32))
+    ex = RoutingExecutor()
+    srv = serve.MstServer(ex, slots=1, hbm_budget_bytes=1 << 34)
+    assert srv.solo_edges == 1 << 22 and srv.batch_edges == 1 << 23
+    reqs = [req(0, 3_000_000), req(1, 3_000_000), req(2, 1_000_000), req(3, 5_000_000), req(4, 100)]
+    for r in reqs:
+        srv.submit(r)  # queued before the worker starts, so the split is deterministic
+    srv.start()
+    for r in reqs:
+        r.done.wait()
+    srv.close()
+    assert ex.runs == [(False, [0, 1, 2]), (True, [3]), (False, [4])]
